@@ -1,0 +1,163 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle/axion_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests, the package smoke check and the
+CPU-baseline leg of the benchmark.  The GPU library never imports it.
+
+A run is described by a plain dict whose keys are the fields of
+``ora_config`` (see axion_oracle.h); missing keys take neutral defaults.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+EM_PERIODIC, EM_MUR = 0, 1
+AX_PERIODIC, AX_REFLECT, AX_OUTFLOW, AX_PML = 0, 1, 2, 3
+ENV_CW, ENV_GAUSS = 0, 1
+
+FIELD_IDS = {name: i for i, name in enumerate(
+    ["E0X", "E0Y", "E0Z", "B0X", "B0Y", "B0Z",
+     "E1X", "E1Y", "E1Z", "B1X", "B1Y", "B1Z", "PHI_OLD", "PHI_NEW"])}
+
+
+class OraConfig(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3), ("dt", ctypes.c_double),
+        ("em_bc", ctypes.c_int * 3), ("ax_bc", ctypes.c_int * 3),
+        ("pml_n", ctypes.c_int), ("pml_sigma_dt", ctypes.c_double),
+        ("m", ctypes.c_double), ("g", ctypes.c_double),
+        ("bext", ctypes.c_double * 3), ("slab_lo", ctypes.c_int), ("slab_hi", ctypes.c_int),
+        ("laser_on", ctypes.c_int), ("laser_pol", ctypes.c_int), ("laser_env", ctypes.c_int),
+        ("omega", ctypes.c_double), ("e_amp", ctypes.c_double), ("ramp_periods", ctypes.c_double),
+        ("fwhm", ctypes.c_double), ("t_center", ctypes.c_double), ("waist", ctypes.c_double),
+        ("x_focus", ctypes.c_double), ("y_c", ctypes.c_double), ("z_c", ctypes.c_double),
+        ("cep", ctypes.c_double),
+        ("packet_on", ctypes.c_int),
+        ("pk_amp", ctypes.c_double), ("pk_k", ctypes.c_double), ("pk_w", ctypes.c_double),
+        ("pk_x0", ctypes.c_double), ("pk_y0", ctypes.c_double), ("pk_z0", ctypes.c_double),
+        ("pk_dir", ctypes.c_int),
+    ]
+
+
+def build(force=False):
+    """Compile liboracle.so with gcc (plain -O2, no FP contraction)."""
+    src = os.path.join(HERE, "axion_oracle.c")
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(src):
+        return LIB_PATH
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           "-std=gnu99", "-Wall", "-o", LIB_PATH + ".tmp", src, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.ora_create.argtypes = [ctypes.POINTER(OraConfig), ctypes.POINTER(ctypes.c_void_p)]
+        L.ora_create.restype = ctypes.c_int
+        L.ora_destroy.argtypes = [ctypes.c_void_p]
+        L.ora_extents.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
+        L.ora_field.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.ora_field.restype = ctypes.POINTER(ctypes.c_double)
+        L.ora_axion_ghost.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.ora_axion_ghost.restype = ctypes.POINTER(ctypes.c_double)
+        L.ora_refresh_initial.argtypes = [ctypes.c_void_p]
+        L.ora_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+        L.ora_step_count.argtypes = [ctypes.c_void_p]
+        L.ora_step_count.restype = ctypes.c_long
+        L.ora_energies.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+        L.ora_incident.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_double] * 4
+        L.ora_incident.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def make_config(cfg):
+    c = OraConfig()
+    c.n[:] = [int(v) for v in cfg.get("n", [1, 1, 1])]
+    c.dx[:] = [float(v) for v in cfg.get("dx", [1.0, 1.0, 1.0])]
+    c.dt = float(cfg["dt"])
+    c.em_bc[:] = [int(v) for v in cfg.get("em_bc", [0, 0, 0])]
+    c.ax_bc[:] = [int(v) for v in cfg.get("ax_bc", [0, 0, 0])]
+    c.pml_n = int(cfg.get("pml_n", 20))
+    c.pml_sigma_dt = float(cfg.get("pml_sigma_dt", 0.2))
+    c.m = float(cfg.get("m", 0.0))
+    c.g = float(cfg.get("g", 0.0))
+    c.bext[:] = [float(v) for v in cfg.get("bext", [0.0, 0.0, 0.0])]
+    c.slab_lo = int(cfg.get("slab_lo", 0))
+    c.slab_hi = int(cfg.get("slab_hi", c.n[0]))
+    for key in ("laser_on", "laser_pol", "laser_env", "packet_on", "pk_dir"):
+        setattr(c, key, int(cfg.get(key, 0)))
+    for key in ("omega", "e_amp", "ramp_periods", "fwhm", "t_center", "waist", "x_focus",
+                "y_c", "z_c", "cep", "pk_amp", "pk_k", "pk_w", "pk_x0", "pk_y0", "pk_z0"):
+        setattr(c, key, float(cfg.get(key, 0.0)))
+    if c.laser_on and c.omega == 0.0:
+        raise ValueError("laser needs omega > 0")
+    return c
+
+
+class Oracle:
+    """One FP64 oracle run; arrays are numpy views on the oracle's memory."""
+
+    def __init__(self, cfg):
+        self._cfg = make_config(cfg)
+        h = ctypes.c_void_p()
+        if lib().ora_create(ctypes.byref(self._cfg), ctypes.byref(h)) != 0:
+            raise ValueError("oracle rejected the configuration")
+        self._h = h
+        nn = (ctypes.c_int * 3)()
+        lib().ora_extents(h, nn)
+        self.nn = tuple(nn)
+        self.n = tuple(self._cfg.n)
+
+    def close(self):
+        if self._h:
+            lib().ora_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def field(self, name):
+        """Array of field `name` with shape (nn_z, nn_y, nn_x): a live view."""
+        p = lib().ora_field(self._h, FIELD_IDS[name])
+        nz, ny, nx = self.nn[2], self.nn[1], self.nn[0]
+        return np.ctypeslib.as_array(p, shape=(nz * ny * nx,)).reshape(nz, ny, nx)
+
+    def axion_ghost(self, d, side, level):
+        p = lib().ora_axion_ghost(self._h, d, side, level)
+        if not p:
+            return None
+        a, b = [e for e in range(3) if e != d]
+        return np.ctypeslib.as_array(p, shape=(self.nn[a] * self.nn[b],)).reshape(self.nn[b], self.nn[a])
+
+    def refresh_initial(self):
+        lib().ora_refresh_initial(self._h)
+
+    def step(self, nsteps=1):
+        lib().ora_step(self._h, int(nsteps))
+
+    @property
+    def step_count(self):
+        return lib().ora_step_count(self._h)
+
+    def energies(self):
+        out = (ctypes.c_double * 3)()
+        lib().ora_energies(self._h, out)
+        return tuple(out)
+
+    def incident(self, comp, x, y, z, t):
+        return lib().ora_incident(self._h, comp, x, y, z, t)
