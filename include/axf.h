@@ -1,0 +1,223 @@
+/*
+ * axf.h -- C ABI of the MI355X axion-coupled Yee step (libaxf.so).
+ *
+ * The library advances, on one gfx950 GPU, the coupled system of
+ * An et al., "Modeling of axion and electromagnetic fields coupling in a
+ * particle-in-cell code" (arXiv 2406.16796), in natural units (c = 1):
+ *
+ *   Klein-Gordon axion      d_t^2 phi - lap phi + m^2 phi = g E0.B0     (Sec. II.A, eq. wave_axion)
+ *   first-order EM (FPS)    d_t E1 = curl B1 - g[(d_t phi) B0 - E0 x grad phi],
+ *                           d_t B1 = -curl E1                              (Sec. II.B, eq. curl-b1)
+ *   zero-order EM (laser)   vacuum Maxwell for E0, B0; a static B_ext is
+ *                           added to B0 wherever B0 enters a source term.
+ *
+ * on the staggered layout of Sec. II.C (phi at cell centres, E on faces, B on
+ * edges) with the time discretisation of Sec. II.C (axion at half-integer
+ * times, phi^n the mean of its neighbours), stored in the equivalent
+ * leapfrog form E^{n-1/2}, B^n, phi^{n-1/2}, phi^{n+1/2}.  Axion boundaries:
+ * periodic, reflect, outflow, PML (Sec. II.D).  EM boundaries: periodic, or
+ * first-order Mur on the tangential E half a cell outside the boundary node
+ * plane, with a laser entering through the x_min face.
+ *
+ * Conventions for every call:
+ *   - every function returns 0 (AXF_OK) or a negative AXF_E* code and never
+ *     throws or aborts; axf_last_error() gives a message for the calling thread;
+ *   - device memory passed in is owned by the caller and must outlive the
+ *     objects carved from it; the library never frees it;
+ *   - `stream` is a hipStream_t (NULL = default stream); all GPU work of a run
+ *     is enqueued on its stream and is asynchronous unless stated otherwise;
+ *   - arrays crossing the ABI are dense, x fastest, with the storage extents
+ *     of axf_extents() (n + 1 along Mur axes for nodal components, n otherwise).
+ */
+#ifndef AXF_H
+#define AXF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+enum {
+    AXF_OK = 0,
+    AXF_EINVAL = -1,     /* bad argument or configuration */
+    AXF_ENOMEM = -2,     /* caller buffer too small / budget exceeded */
+    AXF_EHIP = -3,       /* a HIP runtime call failed */
+    AXF_EUNSTABLE = -4,  /* time step beyond the Yee / Klein-Gordon limit */
+    AXF_EBUSY = -5,      /* server full, or object still in use */
+    AXF_ENOTFOUND = -6,  /* unknown request id or field */
+    AXF_ESTATE = -7      /* call not allowed in the current state */
+};
+
+enum { AXF_F32 = 0, AXF_F64 = 1 };                       /* field storage precision */
+enum { AXF_EM_PERIODIC = 0, AXF_EM_MUR = 1 };
+enum { AXF_AX_PERIODIC = 0, AXF_AX_REFLECT = 1, AXF_AX_OUTFLOW = 2, AXF_AX_PML = 3 };
+enum { AXF_ENV_CW = 0, AXF_ENV_GAUSS = 1 };
+enum { AXF_PATH_AUTO = 0, AXF_PATH_PLAIN = 1, AXF_PATH_FUSED = 2 };
+
+/* field ids for axf_read_field / axf_write_field */
+enum {
+    AXF_E0X = 0, AXF_E0Y, AXF_E0Z, AXF_B0X, AXF_B0Y, AXF_B0Z,
+    AXF_E1X, AXF_E1Y, AXF_E1Z, AXF_B1X, AXF_B1Y, AXF_B1Z,
+    AXF_PHI_OLD,   /* phi at t_n - dt/2 */
+    AXF_PHI_NEW,   /* phi at t_n + dt/2 */
+    AXF_NFIELDS
+};
+
+/* ---------------------------------------------------------------- config
+ * One run.  Axes 0..ndim-1 are active; n[d] = 1 for d >= ndim, and those
+ * axes are periodic.  Active components per ndim (others are identically zero
+ * for the allowed inputs and are not stored):
+ *   ndim 1: E0y E0z B0y B0z, E1y E1z B1y B1z   (requires bext[0] == 0)
+ *   ndim 2: E0x E0y B0z, all six E1/B1          (laser polarised along y)
+ *   ndim 3: all twelve.
+ */
+typedef struct {
+    int32_t ndim;            /* 1, 2 or 3 */
+    int32_t n[3];            /* cells per axis */
+    double  dx[3];           /* cell size per axis */
+    double  dt;              /* time step; must satisfy dt^2 (sum 1/dx^2 + m^2/4) < 1 */
+    int32_t precision;       /* AXF_F32 or AXF_F64 */
+    int32_t em_bc[3];        /* AXF_EM_* per axis (both faces) */
+    int32_t ax_bc[3];        /* AXF_AX_* per axis (both faces) */
+    int32_t pml_n;           /* PML thickness in cells (Sec. III.A: 20) */
+    double  pml_sigma_dt;    /* sigma_max * dt (Sec. III.A: 0.2) */
+    double  m;               /* axion mass */
+    double  g;               /* axion-photon coupling */
+    double  bext[3];         /* static external B */
+    int32_t slab_lo, slab_hi;/* B_ext present for cells slab_lo <= i < slab_hi along x */
+    /* laser through x_min, along +x */
+    int32_t laser_on;
+    int32_t laser_pol;       /* 1: E along y, 2: E along z */
+    int32_t laser_env;       /* AXF_ENV_CW (sin^2 ramp) or AXF_ENV_GAUSS */
+    double  omega;           /* angular frequency */
+    double  e_amp;           /* peak field */
+    double  ramp_periods;    /* CW ramp length in periods */
+    double  fwhm;            /* Gaussian intensity FWHM duration */
+    double  t_center;        /* time the Gaussian peak crosses x = 0 */
+    double  waist;           /* 1/e field radius at focus; 0 = plane wave */
+    double  x_focus, y_c, z_c;
+    double  cep;
+    /* initial axion packet A exp(-(eta^2 + r_perp^2)/w^2) sin(k eta), eta = x - x0 - dir t,
+       set at t = -dt/2 and +dt/2 (Sec. III.A) */
+    int32_t packet_on;
+    double  pk_amp, pk_k, pk_w, pk_x0, pk_y0, pk_z0;
+    int32_t pk_dir;          /* +1 or -1 */
+    /* execution */
+    int32_t diag_every;      /* record energies every k steps (0: only on request) */
+    int32_t path;            /* AXF_PATH_*: step kernels to use */
+} axf_config;
+
+/* one diagnostic record at integer time t = step * dt, all FP64, descaled
+   (Sec. III.B/C: P_gamma->phi = H_phi / H_gamma(E0,B0), P_phi->gamma = H_gamma(E1,B1) / H_phi) */
+typedef struct {
+    int64_t step;
+    double  t;
+    double  h_phi;           /* axion energy: sum over cells of ((D_t phi)^2 + |D+ phi|^2 + m^2 phi^2)/2 dV */
+    double  h_em0;           /* zero-order EM energy (laser only, B_ext excluded) */
+    double  h_em1;           /* first-order EM energy */
+    double  p_gen;           /* h_phi / h_em0 (0 if h_em0 == 0) */
+    double  p_conv;          /* h_em1 / h_phi (0 if h_phi == 0) */
+    int32_t finite;          /* 0 if any field was not finite */
+    int32_t pad;
+} axf_diag_record;
+
+typedef struct axf_run axf_run;
+typedef struct axf_batch axf_batch;
+typedef struct axf_server axf_server;
+
+/* thread-local text of the last error of this thread (never NULL) */
+const char *axf_last_error(void);
+/* library version string */
+const char *axf_version(void);
+
+/* ------------------------------------------------------------ single run */
+
+/* Device bytes a run needs (all state, ghosts and scratch).  Pure host call. */
+int axf_footprint(const axf_config *cfg, size_t *bytes);
+
+/* Storage extents of the arrays crossing the ABI for this configuration. */
+int axf_extents(const axf_config *cfg, int32_t nn[3]);
+
+/* Create a run carved from caller-owned device memory `dev_buf` of `bytes`
+   (>= axf_footprint), enqueue the analytic initial state on `stream`.
+   Errors: EINVAL (bad config), EUNSTABLE (dt), ENOMEM (buffer too small), EHIP. */
+int axf_create(const axf_config *cfg, void *dev_buf, size_t bytes, void *stream, axf_run **out);
+
+/* Overwrite field `field_id` of the initial state (only before the first step).
+   `src` holds the dense array in FP64 (true, unscaled values); host or device. */
+int axf_write_field(axf_run *run, int32_t field_id, const void *src, size_t src_bytes, int32_t src_is_device);
+
+/* Advance `nsteps` steps (asynchronous on the run's stream). */
+int axf_step(axf_run *run, int64_t nsteps);
+
+/* Read field `field_id` at the current integer time into `dst` as FP64 true
+   values (E fields co-timed at t_n; phi at t_n -+ dt/2).  Synchronises the stream. */
+int axf_read_field(axf_run *run, int32_t field_id, void *dst, size_t dst_bytes, int32_t dst_is_device);
+
+/* Compute a diagnostic record at the current time now (synchronises). */
+int axf_diag_now(axf_run *run, axf_diag_record *out);
+
+/* Copy up to `max` recorded diagnostics (oldest first) and clear them; *n = count. */
+int axf_read_diag(axf_run *run, axf_diag_record *out, int32_t max, int32_t *n);
+
+/* Checkpoint: raw state (fields, ghosts, counters) into / from a host buffer. */
+int axf_state_bytes(const axf_run *run, size_t *bytes);
+int axf_read_state(axf_run *run, void *buf, size_t bytes);
+int axf_write_state(axf_run *run, const void *buf, size_t bytes);
+
+int axf_sync(axf_run *run);
+int axf_steps_done(const axf_run *run, int64_t *steps);
+/* release library-side handles (not the caller's device memory) */
+int axf_destroy(axf_run *run);
+
+/* Per-launch GPU time of the last `axf_step` call measured with HIP events on
+   the run's stream: total ms over the steps and the number of step launches. */
+int axf_last_step_timing(const axf_run *run, double *ms, int64_t *launches);
+
+/* ------------------------------------------------------------ batches */
+
+/* Many independent runs carved from one device buffer; one launch per kernel
+   kind and dimensionality advances every active run by one step. */
+int axf_batch_footprint(const axf_config *cfgs, int32_t count, size_t *bytes);
+int axf_batch_create(const axf_config *cfgs, int32_t count, void *dev_buf, size_t bytes,
+                     void *stream, axf_batch **out);
+/* advance run i by nsteps[i] steps (runs finish at different times) */
+int axf_batch_step(axf_batch *b, const int64_t *nsteps);
+/* borrowed view of run i (do not destroy it) */
+int axf_batch_run(axf_batch *b, int32_t i, axf_run **view);
+int axf_batch_destroy(axf_batch *b);
+
+/* ------------------------------------------------------------ server */
+
+/* Result of one served request. Times are seconds on the server's clock. */
+typedef struct {
+    uint64_t id;
+    int32_t  status;         /* 0 ok, AXF_E* on failure, 1 cancelled */
+    int32_t  pad;
+    int64_t  steps;
+    int64_t  cells;
+    double   t_submit, t_admit, t_done;
+    axf_diag_record final;   /* record at the last step */
+} axf_result;
+
+/* Continuous-batching server on one GPU.  `pool` is caller device memory of
+   `pool_bytes` from which resident runs are carved (admission by footprint);
+   at most `max_slots` runs are resident; `macro_steps` steps are taken per
+   batched launch round.  A host thread drives the GPU until destroy. */
+int axf_server_create(void *pool, size_t pool_bytes, int32_t max_slots, int32_t macro_steps,
+                      void *stream, axf_server **out);
+int axf_server_submit(axf_server *s, const axf_config *cfg, int64_t nsteps, uint64_t *id);
+int axf_server_cancel(axf_server *s, uint64_t id);
+/* completed results (oldest first), up to max; *n = count; non-blocking */
+int axf_server_poll(axf_server *s, axf_result *out, int32_t max, int32_t *n);
+/* queue depth, resident runs, bytes in use */
+int axf_server_stats(axf_server *s, int32_t *queued, int32_t *resident, size_t *bytes_used);
+int axf_server_destroy(axf_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,19 @@
+// axf_fused.h -- launcher of the fused one-pass step kernel.
+#pragma once
+
+#include <type_traits>
+
+#include "axf_internal.h"
+
+namespace axf {
+
+// Fused step for 2D (march along y, tiles of TX cells in x) and 3D (march
+// along z, tiles of TX x TY cells in x, y); `chunk` planes per workgroup.
+template <int D, int TX, int TY, typename T>
+struct Fused {
+    static size_t lds_bytes();
+    static int threads();
+    static hipError_t launch(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st);
+};
+
+}  // namespace axf

@@ -1,0 +1,752 @@
+// axf_fused.hip -- the fused step: one launch advances every field of a run by
+// one full step, so each cell's state is read once and written once from HBM.
+//
+// A workgroup owns an in-plane tile (x for 2D; x,y for 3D) and marches along the
+// last axis M (y for 2D, z for 3D) over a chunk of planes.  Each plane of each
+// input is loaded once (prefetched one iteration ahead into registers) into an
+// LDS window of recent planes that covers the tile plus a halo of 3 cells on
+// each side.  The intermediate quantities of the step are computed plane by
+// plane, each in its own LDS window, lagging the newest loaded plane:
+//   S1  E0^{n+1/2} and E0^n at plane t-1        (+ Mur ghosts of E0)
+//   S2  axion current C^n at centres, plane t-2
+//   S3  B0^{n+1} at plane t-1
+//   S4  E1^{n+1/2} at plane t-2                 (+ Mur ghosts of E1)
+//   S5  B1^{n+1} at plane t-2
+//   S6  phi^{n+3/2} at plane t-2                (+ axion ghosts of the new level)
+// The point formulas are the ones of the unfused kernels, written in the same
+// operation order, so the two paths agree bit for bit.
+#include "axf_fused.h"
+#include "axf_stencil.h"
+
+namespace axf {
+
+__device__ __forceinline__ int pmod(int p, int w) { int r = p % w; return r < 0 ? r + w : r; }
+__device__ __forceinline__ int imod(int v, int n) { int r = v % n; return r < 0 ? r + n : r; }
+// periodic wrap of a coordinate at most one period outside [0, n)
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// dynamic LDS of the fused kernel (accessed through the symbol so that the
+// compiler keeps LDS addressing)
+extern __shared__ __align__(16) unsigned char axf_smem[];
+
+template <typename T>
+__device__ __forceinline__ T *lds() { return reinterpret_cast<T *>(axf_smem); }
+
+// state arrays live in global memory: address them as such, so that their
+// loads and stores do not share the LDS counters (generic pointers would)
+template <typename T>
+__device__ __forceinline__ T gld(const T *p, long i) { return ((const __attribute__((address_space(1))) T *)p)[i]; }
+template <typename T>
+__device__ __forceinline__ void gst(T *p, long i, T v) { ((__attribute__((address_space(1))) T *)p)[i] = v; }
+
+// Registers-resident view of a run for one step: the two base pointers of the
+// uniform layout, the geometry and the coefficients (loaded once per launch,
+// so that nothing in the march has to wait on a descriptor load)
+template <typename T>
+struct KV {
+    const char *sb, *fb;       // field arrays / boundary planes
+    long as, fs;               // their strides in bytes
+    int n[3], nn[3], mur[3], axbc[3];
+    long sx, sy;
+    T cdt[3], half, inv_dt, inv2dx[3], inv_dx2[3], dt2, m2, gax, cg1, out_r[3], bext[3], pml_sdt_max;
+    int slab_lo, slab_hi, pml_n;
+
+    __device__ __forceinline__ const T *arr(int q) const { return (const T *)(sb + q * as); }
+    __device__ __forceinline__ T *warr(int q) const { return (T *)(sb + q * as); }
+    __device__ __forceinline__ const T *face(int q) const { return (const T *)(fb + q * fs); }
+    __device__ __forceinline__ T *wface(int q) const { return (T *)(fb + q * fs); }
+};
+
+template <typename T>
+__device__ __forceinline__ KV<T> make_kv(const RunK<T> *__restrict__ rp)
+{
+    KV<T> v;
+    v.sb = rp->state_base;
+    v.fb = rp->face_base;
+    v.as = rp->arr_stride;
+    v.fs = rp->face_stride;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        v.n[d] = rp->n[d];
+        v.nn[d] = rp->nn[d];
+        v.mur[d] = rp->mur[d];
+        v.axbc[d] = rp->axbc[d];
+        v.cdt[d] = rp->cdt[d];
+        v.inv2dx[d] = rp->inv2dx[d];
+        v.inv_dx2[d] = rp->inv_dx2[d];
+        v.out_r[d] = rp->out_r[d];
+        v.bext[d] = rp->bext[d];
+    }
+    v.sx = rp->sx;
+    v.sy = rp->sy;
+    v.half = rp->half;
+    v.inv_dt = rp->inv_dt;
+    v.dt2 = rp->dt2;
+    v.m2 = rp->m2;
+    v.gax = rp->gax;
+    v.cg1 = rp->cg1;
+    v.pml_sdt_max = rp->pml_sdt_max;
+    v.slab_lo = rp->slab_lo;
+    v.slab_hi = rp->slab_hi;
+    v.pml_n = rp->pml_n;
+    return v;
+}
+
+template <int D, int TX, int TY, typename T>
+struct FK {
+    static constexpr int M = D - 1;
+    static constexpr int RX = TX + 6, RY = (D == 3 ? TY + 6 : 1), R = RX * RY;
+    static constexpr int NT = ((R + 63) / 64) * 64;
+    static constexpr int W_B0N = 3, W_PH = 3, W_B1N = 2, W2 = 2;
+    static constexpr int nE0 = D == 3 ? 3 : 2, nB0 = D == 3 ? 3 : 1;
+    __host__ __device__ static constexpr int iE0(int c) { return c; }                 // 2D: E0x, E0y
+    __host__ __device__ static constexpr int iB0(int c) { return D == 3 ? c : 0; }    // 2D: B0z only
+    static constexpr int oB0N = 0;
+    static constexpr int oPHA = oB0N + nB0 * W_B0N;
+    static constexpr int oPHB = oPHA + W_PH;
+    static constexpr int oB1N = oPHB + W_PH;
+    static constexpr int oE0H = oB1N + 3 * W_B1N;
+    static constexpr int oE0N = oE0H + nE0 * W2;
+    static constexpr int oC = oE0N + nE0 * W2;
+    static constexpr int oB0P = oC + 3 * W2;
+    static constexpr int oE1H = oB0P + nB0 * W2;
+    static constexpr int NPL = oE1H + 3 * W2;
+    static constexpr size_t LDS = (size_t)NPL * R * sizeof(T);
+    // in-plane region index shift of a unit step along axis a (a != M)
+    __device__ static constexpr int sh(int a) { return a == 0 ? 1 : RX; }
+};
+
+// one point's view of the LDS windows
+template <int D, int TX, int TY, typename T>
+struct Win {
+    using K = FK<D, TX, TY, T>;
+    int li;   // region index of the point
+    // value of window buffer `base` (W planes) at plane p + o[M], in-plane offset o
+    __device__ __forceinline__ T at(int base, int W, int p, int o0, int o1, int o2) const
+    {
+        const int o[3] = {o0, o1, o2};
+        int plane = p + o[K::M];
+        int idx = li;
+#pragma unroll
+        for (int a = 0; a < D; a++)
+            if (a != K::M) idx += o[a] * K::sh(a);
+        return lds<T>()[(base + pmod(plane, W)) * K::R + idx];
+    }
+    __device__ __forceinline__ T &ref(int base, int W, int p) const { return lds<T>()[(base + pmod(p, W)) * K::R + li]; }
+};
+
+// unit offset along axis a as an (o0, o1, o2) triple
+#define OFF(a, s) ((a) == 0 ? (s) : 0), ((a) == 1 ? (s) : 0), ((a) == 2 ? (s) : 0)
+
+template <int D, int TX, int TY, typename T>
+struct FusedStep {
+    using K = FK<D, TX, TY, T>;
+    using Wn = Win<D, TX, TY, T>;
+    static constexpr int M = K::M;
+
+    // buffers of the quantities (plane-buffer base of component c)
+    __device__ static int bB0N(int c) { return K::oB0N + K::iB0(c) * K::W_B0N; }
+    __device__ static int bB1N(int c) { return K::oB1N + c * K::W_B1N; }
+    __device__ static int bE0H(int c) { return K::oE0H + K::iE0(c) * K::W2; }
+    __device__ static int bE0N(int c) { return K::oE0N + K::iE0(c) * K::W2; }
+    __device__ static int bC(int c) { return K::oC + c * K::W2; }
+    __device__ static int bB0P(int c) { return K::oB0P + K::iB0(c) * K::W2; }
+    __device__ static int bE1H(int c) { return K::oE1H + c * K::W2; }
+
+    template <int O>
+    __device__ static T B_n(const Wn& w, int c, int p, int o0, int o1, int o2)
+    {
+        return O == 0 ? w.at(bB0N(c), K::W_B0N, p, o0, o1, o2) : w.at(bB1N(c), K::W_B1N, p, o0, o1, o2);
+    }
+
+    // dt (curl B)_c at the E_c point: same terms and order as curl_B of the unfused path
+    template <int O>
+    __device__ static T curlB(const KV<T>& r, const Wn& w, int c, int p)
+    {
+        T a = T(0), b = T(0);
+        if (c == 0) {
+            if (D >= 2 && actB<D, O>(2)) a = r.cdt[1] * (B_n<O>(w, 2, p, OFF(1, 1)) - B_n<O>(w, 2, p, 0, 0, 0));
+            if (D >= 3 && actB<D, O>(1)) b = r.cdt[2] * (B_n<O>(w, 1, p, OFF(2, 1)) - B_n<O>(w, 1, p, 0, 0, 0));
+        } else if (c == 1) {
+            if (D >= 3 && actB<D, O>(0)) a = r.cdt[2] * (B_n<O>(w, 0, p, OFF(2, 1)) - B_n<O>(w, 0, p, 0, 0, 0));
+            if (actB<D, O>(2)) b = r.cdt[0] * (B_n<O>(w, 2, p, OFF(0, 1)) - B_n<O>(w, 2, p, 0, 0, 0));
+        } else {
+            if (actB<D, O>(1)) a = r.cdt[0] * (B_n<O>(w, 1, p, OFF(0, 1)) - B_n<O>(w, 1, p, 0, 0, 0));
+            if (D >= 2 && actB<D, O>(0)) b = r.cdt[1] * (B_n<O>(w, 0, p, OFF(1, 1)) - B_n<O>(w, 0, p, 0, 0, 0));
+        }
+        return a - b;
+    }
+
+    template <int O>
+    __device__ static T E_h(const Wn& w, int c, int p, int o0, int o1, int o2)
+    {
+        if (!actE<D, O>(c)) return T(0);
+        return O == 0 ? w.at(bE0H(c), K::W2, p, o0, o1, o2) : w.at(bE1H(c), K::W2, p, o0, o1, o2);
+    }
+
+    // dt (curl E)_c at the B_c point from E^{n+1/2} (ghosts already in the windows)
+    template <int O>
+    __device__ static T curlE(const KV<T>& r, const Wn& w, int c, int p)
+    {
+        T a = T(0), b = T(0);
+        if (c == 0) {
+            if (D >= 2 && actE<D, O>(2)) a = r.cdt[1] * (E_h<O>(w, 2, p, 0, 0, 0) - E_h<O>(w, 2, p, OFF(1, -1)));
+            if (D >= 3 && actE<D, O>(1)) b = r.cdt[2] * (E_h<O>(w, 1, p, 0, 0, 0) - E_h<O>(w, 1, p, OFF(2, -1)));
+        } else if (c == 1) {
+            if (D >= 3 && actE<D, O>(0)) a = r.cdt[2] * (E_h<O>(w, 0, p, 0, 0, 0) - E_h<O>(w, 0, p, OFF(2, -1)));
+            if (actE<D, O>(2)) b = r.cdt[0] * (E_h<O>(w, 2, p, 0, 0, 0) - E_h<O>(w, 2, p, OFF(0, -1)));
+        } else {
+            if (actE<D, O>(1)) a = r.cdt[0] * (E_h<O>(w, 1, p, 0, 0, 0) - E_h<O>(w, 1, p, OFF(0, -1)));
+            if (D >= 2 && actE<D, O>(0)) b = r.cdt[1] * (E_h<O>(w, 0, p, 0, 0, 0) - E_h<O>(w, 0, p, OFF(1, -1)));
+        }
+        return a - b;
+    }
+
+    // 4-point centre average of a B window buffer (same order as centre_B)
+    template <int O>
+    __device__ static T centreB(const Wn& w, int base, int W, int c, int p)
+    {
+        if (!actB<D, O>(c)) return T(0);
+        const int a = c == 0 ? 1 : 0, b = c == 2 ? 1 : 2;
+        const bool ua = a < D, ub = b < D;
+        T p00 = w.at(base, W, p, 0, 0, 0);
+        if (!ua && !ub) return p00;
+        T pa = w.at(base, W, p, OFF(a, 1));
+        if (!ub) return T(0.5) * (p00 + pa);
+        T pb = w.at(base, W, p, OFF(b, 1));
+        T pab = w.at(base, W, p, (a == 0 || b == 0) ? 1 : 0, (a == 1 || b == 1) ? 1 : 0, (a == 2 || b == 2) ? 1 : 0);
+        return T(0.25) * ((p00 + pa) + (pb + pab));
+    }
+};
+
+// ------------------------------------------------------------------ loads
+
+// coordinate v along axis d of an EM array: wrapped on periodic axes, checked
+// against the nodal or centred extent on Mur axes
+template <typename R>
+__device__ __forceinline__ bool em_coord(const R& r, int d, int v, bool nodal, int& w)
+{
+    if (!r.mur[d]) { w = wrap1(v, r.n[d]); return true; }
+    w = v;
+    return v >= 0 && v < (nodal ? r.nn[d] : r.n[d]);
+}
+
+template <int D, typename R>
+__device__ __forceinline__ long lin3(const R& r, int x, int y, int z)
+{
+    return x + (D >= 2 ? (long)y * r.sx : 0) + (D >= 3 ? (long)z * r.sy : 0);
+}
+
+// B_c (nodal along the axes other than c) at global coordinates, 0 outside
+template <int D, typename T>
+__device__ __forceinline__ T load_B(const KV<T>& r, const T *a, int c, int x, int y, int z)
+{
+    int wx, wy = 0, wz = 0;
+    if (!em_coord(r, 0, x, c != 0, wx)) return T(0);
+    if (D >= 2 && !em_coord(r, 1, y, c != 1, wy)) return T(0);
+    if (D >= 3 && !em_coord(r, 2, z, c != 2, wz)) return T(0);
+    return gld(a, lin3<D>(r, wx, wy, wz));
+}
+
+// E_c (nodal along c) at global coordinates, 0 outside
+template <int D, typename T>
+__device__ __forceinline__ T load_E(const KV<T>& r, const T *a, int c, int x, int y, int z)
+{
+    int wx, wy = 0, wz = 0;
+    if (!em_coord(r, 0, x, c == 0, wx)) return T(0);
+    if (D >= 2 && !em_coord(r, 1, y, c == 1, wy)) return T(0);
+    if (D >= 3 && !em_coord(r, 2, z, c == 2, wz)) return T(0);
+    return gld(a, lin3<D>(r, wx, wy, wz));
+}
+
+// phi of axion slot L at centre coordinates; axion ghosts one cell outside
+// non-periodic faces; 0 elsewhere outside (each axis handled by a constant
+// index so that the view stays in registers)
+template <int D, typename T>
+__device__ __forceinline__ T load_phi(const KV<T>& r, int L, int x, int y, int z)
+{
+    int v0 = x, v1 = D >= 2 ? y : 0, v2 = D >= 3 ? z : 0;
+    int o0 = 0, o1 = 0, o2 = 0;   // -1 / +1: one cell outside the low / high face; 2: further out
+    auto chk = [&](int d, int& v, int& o) __attribute__((always_inline)) {
+        if (r.axbc[d] == AXF_AX_PERIODIC) {
+            v = wrap1(v, r.n[d]);
+        } else if (v < 0 || v >= r.n[d]) {
+            o = (v == -1) ? -1 : (v == r.n[d] ? 1 : 2);
+        }
+    };
+    chk(0, v0, o0);
+    if (D >= 2) chk(1, v1, o1);
+    if (D >= 3) chk(2, v2, o2);
+    const int nout = (o0 != 0) + (o1 != 0) + (o2 != 0);
+    if (nout > 1 || o0 == 2 || o1 == 2 || o2 == 2) return T(0);
+    if (o0) return gld(r.face(q_axg(0, o0 < 0 ? 0 : 1, L)), face_index(r, 0, v0, v1, v2));
+    if (D >= 2 && o1) return gld(r.face(q_axg(1, o1 < 0 ? 0 : 1, L)), face_index(r, 1, v0, v1, v2));
+    if (D >= 3 && o2) return gld(r.face(q_axg(2, o2 < 0 ? 0 : 1, L)), face_index(r, 2, v0, v1, v2));
+    return gld(r.arr(q_phi(L)), lin3<D>(r, v0, v1, v2));
+}
+
+// Address of a B / E / phi point for an unconditional load: the element
+// pointer (a valid location of the same array when the point is outside) and
+// whether the value is real.  Loading unconditionally and masking at use keeps
+// the prefetch loads in flight together instead of waiting on each branch.
+template <int D, typename T>
+__device__ __forceinline__ const T *addr_em(const KV<T>& r, const T *a, unsigned nodal, int x, int y, int z, bool& ok)
+{
+    int wx, wy = 0, wz = 0;
+    ok = em_coord(r, 0, x, nodal & 1u, wx);
+    if (D >= 2) ok = em_coord(r, 1, y, (nodal >> 1) & 1u, wy) && ok;
+    if (D >= 3) ok = em_coord(r, 2, z, (nodal >> 2) & 1u, wz) && ok;
+    return a + (ok ? lin3<D>(r, wx, wy, wz) : 0);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ const T *addr_phi(const KV<T>& r, int L, int x, int y, int z, bool& ok)
+{
+    int v0 = x, v1 = D >= 2 ? y : 0, v2 = D >= 3 ? z : 0;
+    int o0 = 0, o1 = 0, o2 = 0;
+    auto chk = [&](int d, int& v, int& o) __attribute__((always_inline)) {
+        if (r.axbc[d] == AXF_AX_PERIODIC) {
+            v = wrap1(v, r.n[d]);
+        } else if (v < 0 || v >= r.n[d]) {
+            o = (v == -1) ? -1 : (v == r.n[d] ? 1 : 2);
+        }
+    };
+    chk(0, v0, o0);
+    if (D >= 2) chk(1, v1, o1);
+    if (D >= 3) chk(2, v2, o2);
+    const int nout = (o0 != 0) + (o1 != 0) + (o2 != 0);
+    ok = !(nout > 1 || o0 == 2 || o1 == 2 || o2 == 2);
+    const T *base = r.arr(q_phi(L));
+    if (!ok) return base;
+    if (o0) return r.face(q_axg(0, o0 < 0 ? 0 : 1, L)) + face_index(r, 0, v0, v1, v2);
+    if (D >= 2 && o1) return r.face(q_axg(1, o1 < 0 ? 0 : 1, L)) + face_index(r, 1, v0, v1, v2);
+    if (D >= 3 && o2) return r.face(q_axg(2, o2 < 0 ? 0 : 1, L)) + face_index(r, 2, v0, v1, v2);
+    return base + lin3<D>(r, v0, v1, v2);
+}
+
+// First-order Mur update of one tangential E ghost (FP64), the same formula as
+// the unfused path: out of line, it runs on boundary points only
+template <typename T>
+__device__ __noinline__ T mur_update(const RunK<T> *__restrict__ rp, int O, int c, int d, int side, double e_old, double e_new,
+                                     double g_old, int a0, int a1, int a2, long step)
+{
+    const RunK<T>& rk = *rp;
+    double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
+    if (O == 0 && d == 0 && side == 0 && rk.las.on) {
+        double px = c == 0 ? a0 * rk.dx[0] : (a0 + 0.5) * rk.dx[0];
+        double py = c == 1 ? a1 * rk.dx[1] : (a1 + 0.5) * rk.dx[1];
+        double pz = c == 2 ? a2 * rk.dx[2] : (a2 + 0.5) * rk.dx[2];
+        double xg = -0.5 * rk.dx[0];
+        double t_o = (step - 0.5) * rk.dt, t_n = (step + 0.5) * rk.dt;
+        ia_o = incident(rk.las, c, px, py, pz, t_o);
+        ia_n = incident(rk.las, c, px, py, pz, t_n);
+        ig_o = incident(rk.las, c, xg, py, pz, t_o);
+        ig_n = incident(rk.las, c, xg, py, pz, t_n);
+    }
+    double sa_o = e_old - ia_o, sa_n = e_new - ia_n, sg_o = g_old - ig_o;
+    double sg_n = sa_o + rk.murc[d] * (sa_n - sg_o);
+    return (T)(sg_n + ig_n);
+}
+
+// ------------------------------------------------------------------ kernel
+
+template <int D, int TX, int TY, typename T>
+__global__ void __launch_bounds__((FK<D, TX, TY, T>::NT))
+k_fused(const RunK<T> *__restrict__ rp, long step, int ntx, int nty, int nch, int chunk)
+{
+    using K = FK<D, TX, TY, T>;
+    using S = FusedStep<D, TX, TY, T>;
+    using Wn = Win<D, TX, TY, T>;
+    constexpr int M = K::M;
+    KV<T> r = make_kv(rp);
+
+    // XCD-aware tile order: consecutive workgroups land on different XCDs, so
+    // hand each XCD a contiguous run of tiles (neighbours share its L2)
+    const int nb = ntx * nty * nch;
+    const int bid = blockIdx.x, xcd = bid & 7, kq = bid >> 3, q8 = nb >> 3, rem = nb & 7;
+    const int L = xcd * q8 + (xcd < rem ? xcd : rem) + kq;
+    const int tx = L % ntx, ty = (L / ntx) % nty, ch = L / (ntx * nty);
+
+    const int so = (int)(step & 1), sn = so ^ 1;
+    const int la = (int)(step % 3), lb = (int)((step + 1) % 3), ln = (int)((step + 2) % 3);
+
+    // in-plane tile and ownership ranges (the last tile also owns the nodal plane n)
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int own_x_hi = (tx == ntx - 1) ? r.nn[0] : x0 + TX;
+    const int own_y_hi = D == 3 ? ((ty == nty - 1) ? r.nn[1] : y0 + TY) : 1;
+    const int c0 = ch * chunk, c1 = (ch == nch - 1) ? r.nn[M] : c0 + chunk;
+
+    const int tid = threadIdx.x;
+    const bool live = tid < K::R;
+    const int lx = tid % K::RX, ly = tid / K::RX;
+    const int rx = lx - 3, ry = D == 3 ? ly - 3 : 0;       // offsets from the tile origin
+    const int gx = x0 + rx, gy = D == 3 ? y0 + ry : 0;     // global in-plane coordinates
+    const Wn w{live ? tid : 0};
+
+    auto in_rng = [&](int lo, int hi) __attribute__((always_inline)) {
+        bool ok = live && rx >= lo && rx < hi;
+        if (D == 3) ok = ok && ry >= lo && ry < hi;
+        return ok;
+    };
+    // stage regions (offsets from the tile origin, per in-plane axis)
+    const bool rS1 = in_rng(-2, TX + 2), rS2 = in_rng(-2, TX + 1), rS3 = in_rng(0, TX + 2);
+    const bool rS4 = in_rng(-1, TX + 1), rS56 = in_rng(0, TX + 1);
+    const bool own_inplane = live && gx >= x0 && gx < own_x_hi && (D == 2 || (gy >= y0 && gy < own_y_hi));
+
+    // global coordinates of this thread's point at plane p
+    auto X = [&](int p) __attribute__((always_inline)) { return gx; };
+    auto Y = [&](int p) __attribute__((always_inline)) { return D == 3 ? gy : p; };
+    auto Z = [&](int p) __attribute__((always_inline)) { return D == 3 ? p : 0; };
+    // is the point (at plane p) inside the extent of a component nodal along the
+    // axes in `nodal` (bit mask)?  periodic axes always are
+    auto valid = [&](int p, unsigned nodal) __attribute__((always_inline)) {
+        bool ok = true;
+        int v[3] = {X(p), Y(p), Z(p)};
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            if (!r.mur[d]) continue;
+            int ext = (nodal >> d & 1) ? r.nn[d] : r.n[d];
+            ok = ok && v[d] >= 0 && v[d] < ext;
+        }
+        return ok;
+    };
+    auto own_plane = [&](int p) __attribute__((always_inline)) { return p >= c0 && p < c1; };
+    auto gindex = [&](int p) __attribute__((always_inline)) {
+        int vx = X(p), vy = Y(p), vz = Z(p);
+        if (!r.mur[0]) vx = wrap1(vx, r.n[0]);
+        if (D >= 2 && !r.mur[1]) vy = wrap1(vy, r.n[1]);
+        if (D >= 3 && !r.mur[2]) vz = wrap1(vz, r.n[2]);
+        return lin3<D>(r, vx, vy, vz);
+    };
+
+    // ---- prefetch registers for one iteration: raw loads plus validity masks
+    T pf_b0[3], pf_b1[3], pf_pa, pf_pb, pf_e0m[3], pf_e1m[3];
+    unsigned pf_mask = 0;
+    T cur_e0m[3], cur_e1m[3];
+    auto prefetch = [&](int t) __attribute__((always_inline)) {
+        if (!live) return;
+        unsigned m = 0;
+        bool ok;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            if (!actB0<D>(c)) { pf_b0[c] = T(0); continue; }
+            const T *p = addr_em<D>(r, r.arr(q_em(1, so, c)), 7u & ~(1u << c), X(t), Y(t), Z(t), ok);
+            pf_b0[c] = gld(p, 0);
+            m |= ok ? 1u << c : 0u;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const T *p = addr_em<D>(r, r.arr(q_em(3, so, c)), 7u & ~(1u << c), X(t - 1), Y(t - 1), Z(t - 1), ok);
+            pf_b1[c] = gld(p, 0);
+            m |= ok ? 8u << c : 0u;
+        }
+        {
+            const T *p = addr_phi<D>(r, la, X(t - 1), Y(t - 1), Z(t - 1), ok);
+            pf_pa = gld(p, 0);
+            m |= ok ? 64u : 0u;
+            p = addr_phi<D>(r, lb, X(t - 1), Y(t - 1), Z(t - 1), ok);
+            pf_pb = gld(p, 0);
+            m |= ok ? 128u : 0u;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            if (!actE0<D>(c)) { pf_e0m[c] = T(0); continue; }
+            const T *p = addr_em<D>(r, r.arr(q_em(0, so, c)), 1u << c, X(t - 1), Y(t - 1), Z(t - 1), ok);
+            pf_e0m[c] = gld(p, 0);
+            m |= (ok && rS1) ? 256u << c : 0u;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const T *p = addr_em<D>(r, r.arr(q_em(2, so, c)), 1u << c, X(t - 2), Y(t - 2), Z(t - 2), ok);
+            pf_e1m[c] = gld(p, 0);
+            m |= (ok && rS4) ? 2048u << c : 0u;
+        }
+        pf_mask = m;
+    };
+    auto sel = [&](T v, unsigned bit) __attribute__((always_inline)) { return (pf_mask & bit) ? v : T(0); };
+
+    // Mur ghost of E_c of order O at this thread's point of plane pg, across axis
+    // d (side 0 at coordinate -1, side 1 at n): from the adjacent interior point
+    // (offset (o0,o1,o2), at plane pa in the window) and the old state in HBM
+    auto mur_ghost = [&](auto Oc, int c, int d, int side, int pg, int pa, int o0, int o1, int o2, bool write_hist) __attribute__((always_inline)) -> T {
+        constexpr int O = decltype(Oc)::value;
+        int a0 = X(pg) + o0, a1 = Y(pg) + o1, a2 = Z(pg) + o2;
+        if (!r.mur[0]) a0 = wrap1(a0, r.n[0]);
+        if (D >= 2 && !r.mur[1]) a1 = wrap1(a1, r.n[1]);
+        if (D >= 3 && !r.mur[2]) a2 = wrap1(a2, r.n[2]);
+        long fidx = face_index(r, d, a0, a1, a2);
+        double e_old = (double)gld(r.arr(q_em(O == 0 ? 0 : 2, so, c)), lin3<D>(r, a0, a1, a2));
+        const int i0 = M == 0 ? 0 : o0, i1 = M == 1 ? 0 : o1, i2 = M == 2 ? 0 : o2;
+        double e_new = (double)(O == 0 ? w.at(S::bE0H(c), K::W2, pa, i0, i1, i2) : w.at(S::bE1H(c), K::W2, pa, i0, i1, i2));
+        double g_old = (double)gld(r.face(q_mur(O, d, side, c, so)), fidx);
+        T val = mur_update<T>(rp, O, c, d, side, e_old, e_new, g_old, a0, a1, a2, step);
+        if (write_hist) gst(r.wface(q_mur(O, d, side, c, sn)), fidx, val);
+        return val;
+    };
+
+    // Mur ghosts of order O once E^{n+1/2} of plane p is in its window: ghosts
+    // across in-plane axes at plane p; on a Mur march axis the ghost plane -1
+    // (while plane 0 is done) and the ghost plane n (from plane n - 1)
+    auto ghost_fix = [&](auto Oc, int p) __attribute__((always_inline)) {
+        constexpr int O = decltype(Oc)::value;
+        if (!(O == 0 ? rS1 : rS4)) return;
+        const int v[3] = {X(p), Y(p), Z(p)};
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            if (!actE<D, O>(c)) continue;
+            const int base = O == 0 ? S::bE0H(c) : S::bE1H(c);
+#pragma unroll
+            for (int d = 0; d < D; d++) {
+                if (d == M || d == c || !r.mur[d]) continue;
+                int side = v[d] == -1 ? 0 : (v[d] == r.n[d] ? 1 : -1);
+                if (side < 0) continue;
+                bool ok = true;
+#pragma unroll
+                for (int e = 0; e < D; e++) {
+                    if (e == d || !r.mur[e]) continue;
+                    int ext = (e == c) ? r.nn[e] : r.n[e];
+                    ok = ok && v[e] >= 0 && v[e] < ext;
+                }
+                if (!ok) continue;
+                const int sg = side == 0 ? 1 : -1;
+                const int ax = d == 0 ? gx + sg : gx, ay = (D == 3 && d == 1) ? gy + sg : gy;
+                const bool owner = own_plane(p) && ax >= x0 && ax < own_x_hi && (D == 2 || (ay >= y0 && ay < own_y_hi));
+                T val = mur_ghost(Oc, c, d, side, p, p, d == 0 ? sg : 0, d == 1 ? sg : 0, d == 2 ? sg : 0, owner);
+                w.ref(base, K::W2, p) = val;
+            }
+            if (c != M && r.mur[M]) {
+                int side = -1, pg = 0, pad = 0;
+                if (p == 0) { side = 0; pg = -1; pad = 0; }
+                else if (p == r.n[M]) { side = 1; pg = p; pad = p - 1; }
+                if (side >= 0) {
+                    bool ok = true;
+#pragma unroll
+                    for (int e = 0; e < D; e++) {
+                        if (e == M || !r.mur[e]) continue;
+                        int ext = (e == c) ? r.nn[e] : r.n[e];
+                        ok = ok && v[e] >= 0 && v[e] < ext;
+                    }
+                    if (ok) {
+                        const bool owner = own_inplane && own_plane(pad);
+                        const int dm = pad - pg;
+                        T val = mur_ghost(Oc, c, M, side, pg, pad, M == 0 ? dm : 0, M == 1 ? dm : 0, M == 2 ? dm : 0, owner);
+                        w.ref(base, K::W2, pg) = val;
+                    }
+                }
+            }
+        }
+    };
+
+    // ---- the march
+    const int t_first = c0 - 2, t_last = c1 + 1;
+    prefetch(t_first);
+    for (int t = t_first; t <= t_last; t++) {
+        // keep the array strides opaque to loop-invariant code motion: array
+        // addresses are then formed per access from two scalar registers instead
+        // of being hoisted into dozens of live 64-bit values
+        asm volatile("" : "+s"(r.as), "+s"(r.fs));
+        __syncthreads();   // previous iteration done with the slots about to be reused
+        if (live) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                if (actB0<D>(c)) w.ref(S::bB0N(c), K::W_B0N, t) = sel(pf_b0[c], 1u << c);
+                w.ref(S::bB1N(c), K::W_B1N, t - 1) = sel(pf_b1[c], 8u << c);
+                cur_e0m[c] = sel(pf_e0m[c], 256u << c);
+                cur_e1m[c] = sel(pf_e1m[c], 2048u << c);
+            }
+            w.ref(K::oPHA, K::W_PH, t - 1) = sel(pf_pa, 64u);
+            w.ref(K::oPHB, K::W_PH, t - 1) = sel(pf_pb, 128u);
+        }
+        if (t < t_last) prefetch(t + 1);
+        __syncthreads();
+
+        // S1: E0^{n+1/2} and E0^n at plane p1 = t - 1
+        const int p1 = t - 1;
+        if (rS1) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                if (!actE0<D>(c)) continue;
+                T eh = T(0), en = T(0);
+                if (valid(p1, 1u << c)) {
+                    T rhs = S::template curlB<0>(r, w, c, p1);
+                    eh = cur_e0m[c] + T(1) * rhs;
+                    en = r.half * (cur_e0m[c] + eh);
+                    if (own_inplane && own_plane(p1)) gst(r.warr(q_em(0, sn, c)), gindex(p1), eh);
+                }
+                w.ref(S::bE0H(c), K::W2, p1) = eh;
+                w.ref(S::bE0N(c), K::W2, p1) = en;
+            }
+        }
+        __syncthreads();
+        ghost_fix(std::integral_constant<int, 0>{}, p1);
+        __syncthreads();
+
+        // S2: C^n at the centres of plane p2 = t - 2;  S3: B0^{n+1} at plane p1
+        const int p2 = t - 2;
+        if (rS2) {
+            T C0 = T(0), C1 = T(0), C2 = T(0);
+            if (valid(p2, 0u)) {
+                T e[3], bb[3], gp[3] = {T(0), T(0), T(0)};
+                const int cxg = wrap1(X(p2), r.n[0]);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    e[c] = T(0);
+                    if (actE0<D>(c)) {
+                        T lo = w.at(S::bE0N(c), K::W2, p2, 0, 0, 0);
+                        T hi = w.at(S::bE0N(c), K::W2, p2, OFF(c, 1));
+                        e[c] = c < D ? r.half * (lo + hi) : lo;
+                    }
+                    bb[c] = S::template centreB<0>(w, S::bB0N(c), K::W_B0N, c, p2) + bext_at(r, c, cxg);
+                }
+                T pa0 = w.at(K::oPHA, K::W_PH, p2, 0, 0, 0), pb0 = w.at(K::oPHB, K::W_PH, p2, 0, 0, 0);
+                T dtphi = (pb0 - pa0) * r.inv_dt;
+#pragma unroll
+                for (int d = 0; d < D; d++) {
+                    T up = r.half * (w.at(K::oPHA, K::W_PH, p2, OFF(d, 1)) + w.at(K::oPHB, K::W_PH, p2, OFF(d, 1)));
+                    T dn = r.half * (w.at(K::oPHA, K::W_PH, p2, OFF(d, -1)) + w.at(K::oPHB, K::W_PH, p2, OFF(d, -1)));
+                    gp[d] = (up - dn) * r.inv2dx[d];
+                }
+                C0 = dtphi * bb[0] - (e[1] * gp[2] - e[2] * gp[1]);
+                C1 = dtphi * bb[1] - (e[2] * gp[0] - e[0] * gp[2]);
+                C2 = dtphi * bb[2] - (e[0] * gp[1] - e[1] * gp[0]);
+            }
+            w.ref(S::bC(0), K::W2, p2) = C0;
+            w.ref(S::bC(1), K::W2, p2) = C1;
+            w.ref(S::bC(2), K::W2, p2) = C2;
+        }
+        if (rS3) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                if (!actB0<D>(c)) continue;
+                T v = T(0);
+                if (valid(p1, 7u & ~(1u << c))) {
+                    v = w.at(S::bB0N(c), K::W_B0N, p1, 0, 0, 0) - S::template curlE<0>(r, w, c, p1);
+                    if (own_inplane && own_plane(p1)) gst(r.warr(q_em(1, sn, c)), gindex(p1), v);
+                }
+                w.ref(S::bB0P(c), K::W2, p1) = v;
+            }
+        }
+        __syncthreads();
+
+        // S4: E1^{n+1/2} at plane p2
+        if (rS4) {
+            const int v[3] = {X(p2), Y(p2), Z(p2)};
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                T val = T(0);
+                if (valid(p2, 1u << c)) {
+                    T Sc;
+                    if (c >= D) {
+                        Sc = w.at(S::bC(c), K::W2, p2, 0, 0, 0);
+                    } else {
+                        int lo = -1, hi = 0;
+                        if (r.mur[c]) {
+                            if (v[c] - 1 < 0) lo = 0;
+                            if (v[c] > r.n[c] - 1) hi = -1;
+                        }
+                        Sc = r.half * (w.at(S::bC(c), K::W2, p2, OFF(c, lo)) + w.at(S::bC(c), K::W2, p2, OFF(c, hi)));
+                    }
+                    T rhs = S::template curlB<1>(r, w, c, p2) - r.cg1 * Sc;
+                    val = cur_e1m[c] + T(1) * rhs;
+                    if (own_inplane && own_plane(p2)) gst(r.warr(q_em(2, sn, c)), gindex(p2), val);
+                }
+                w.ref(S::bE1H(c), K::W2, p2) = val;
+            }
+        }
+        __syncthreads();
+        ghost_fix(std::integral_constant<int, 1>{}, p2);
+        __syncthreads();
+
+        // S5: B1^{n+1} and S6: phi^{n+3/2} at plane p2 (stored directly)
+        if (rS56 && own_inplane && own_plane(p2)) {
+            const long gi2 = gindex(p2);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                if (!valid(p2, 7u & ~(1u << c))) continue;
+                gst(r.warr(q_em(3, sn, c)), gi2, w.at(S::bB1N(c), K::W_B1N, p2, 0, 0, 0) - S::template curlE<1>(r, w, c, p2));
+            }
+            if (valid(p2, 0u)) {
+                const int gi = wrap1(X(p2), r.n[0]);
+                const int gj = D >= 2 ? wrap1(Y(p2), r.n[1]) : 0;
+                const int gk = D >= 3 ? wrap1(Z(p2), r.n[2]) : 0;
+                T e[3], bb[3];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    e[c] = T(0);
+                    if (actE0<D>(c)) {
+                        T q0 = w.at(S::bE0H(c), K::W2, p2, 0, 0, 0);
+                        e[c] = c < D ? r.half * (q0 + w.at(S::bE0H(c), K::W2, p2, OFF(c, 1))) : q0;
+                    }
+                    T bo = S::template centreB<0>(w, S::bB0N(c), K::W_B0N, c, p2);
+                    T bn = S::template centreB<0>(w, S::bB0P(c), K::W2, c, p2);
+                    bb[c] = r.half * (bo + bn) + bext_at(r, c, gi);
+                }
+                T sax = r.gax * (e[0] * bb[0] + e[1] * bb[1] + e[2] * bb[2]);
+                T pa = w.at(K::oPHA, K::W_PH, p2, 0, 0, 0), pb = w.at(K::oPHB, K::W_PH, p2, 0, 0, 0);
+                T lap = T(0);
+#pragma unroll
+                for (int d = 0; d < D; d++)
+                    lap += ((w.at(K::oPHB, K::W_PH, p2, OFF(d, 1)) - T(2) * pb) + w.at(K::oPHB, K::W_PH, p2, OFF(d, -1)))
+                           * r.inv_dx2[d];
+                T sdt = pml_sdt<D>(r, gi, gj, gk);
+                T x = r.dt2 * ((sax - r.m2 * pb) + lap) - sdt * sdt * pb;
+                T pn = (((x + sdt * pa) + T(2) * pb) - pa) / (T(1) + sdt);
+                gst(r.warr(q_phi(ln)), gi2, pn);
+                const int gv[3] = {gi, gj, gk};
+#pragma unroll
+                for (int d = 0; d < D; d++) {
+                    if (r.axbc[d] == AXF_AX_PERIODIC) continue;
+#pragma unroll
+                    for (int side = 0; side < 2; side++) {
+                        if (gv[d] != (side ? r.n[d] - 1 : 0)) continue;
+                        long f = face_index(r, d, gi, gj, gk);
+                        T gval;
+                        if (r.axbc[d] == AXF_AX_OUTFLOW) {
+                            T gbv = gld(r.face(q_axg(d, side, lb)), f), gav = gld(r.face(q_axg(d, side, la)), f), rr = r.out_r[d];
+                            T xx = (((T(-2) * gbv + T(2) * gav) - r.dt2 * (sax - r.m2 * gbv)) + rr * pb - rr * rr * (pb - T(2) * gbv))
+                                   / (rr + rr * rr);
+                            gval = gav + rr * (pb - xx);
+                        } else {
+                            gval = pn;
+                        }
+                        gst(r.wface(q_axg(d, side, ln)), f, gval);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int D, int TX, int TY, typename T>
+size_t Fused<D, TX, TY, T>::lds_bytes() { return FK<D, TX, TY, T>::LDS; }
+
+template <int D, int TX, int TY, typename T>
+int Fused<D, TX, TY, T>::threads() { return FK<D, TX, TY, T>::NT; }
+
+template <int D, int TX, int TY, typename T>
+hipError_t Fused<D, TX, TY, T>::launch(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st)
+{
+    using K = FK<D, TX, TY, T>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_fused<D, TX, TY, T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)K::LDS);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int M = D - 1;
+    int ntx = (h.n[0] + TX - 1) / TX;
+    int nty = D == 3 ? (h.n[1] + TY - 1) / TY : 1;
+    int nch = (h.nn[M] + chunk - 1) / chunk;
+    unsigned nb = (unsigned)(ntx * nty * nch);
+    hipLaunchKernelGGL((k_fused<D, TX, TY, T>), dim3(nb), dim3(K::NT), K::LDS, st, rk, step, ntx, nty, nch, chunk);
+    return hipGetLastError();
+}
+
+template struct Fused<2, 256, 1, float>;
+template struct Fused<2, 128, 1, double>;
+template struct Fused<3, 32, 6, float>;
+template struct Fused<3, 32, 8, float>;
+template struct Fused<3, 32, 4, double>;
+
+}  // namespace axf

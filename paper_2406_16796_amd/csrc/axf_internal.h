@@ -1,0 +1,83 @@
+// axf_internal.h -- device-side run descriptor and helpers shared by the
+// kernels and the host runtime of libaxf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/axf.h"
+
+namespace axf {
+
+// Laser injected through x_min (parameters in FP64).
+struct Laser {
+    int on, pol, env, q;          // q = number of transverse axes of the beam profile
+    double omega, e_amp, ramp_t, tau0, t_center, waist, x_focus, y_c, z_c, cep, zr;
+};
+
+struct Packet {
+    int on, dir;
+    double amp, k, w, x0, y0, z0;
+};
+
+// Active components per dimensionality (the others stay identically zero for
+// the accepted configurations): 1D keeps the transverse components of both
+// polarisations, 2D keeps the in-plane-polarised zero-order set (E0x E0y B0z)
+// and all first-order components, 3D keeps everything.
+template <int D> __host__ __device__ constexpr bool actE0(int c) { return D == 3 ? true : (D == 2 ? c != 2 : c != 0); }
+template <int D> __host__ __device__ constexpr bool actB0(int c) { return D == 3 ? true : (D == 2 ? c == 2 : c != 0); }
+template <int D> __host__ __device__ constexpr bool actE1(int c) { return D >= 2 ? true : c != 0; }
+template <int D> __host__ __device__ constexpr bool actB1(int c) { return D >= 2 ? true : c != 0; }
+
+// Uniform layout of a run's device buffer: 30 field arrays of equal size at
+// state_base + q * arr_stride, and 90 boundary planes of equal size at
+// face_base + q * face_stride (some unused for a given configuration).
+__host__ __device__ constexpr int q_em(int kind, int slot, int comp) { return (kind * 2 + slot) * 3 + comp; }  // kind 0 E0, 1 B0, 2 E1, 3 B1
+__host__ __device__ constexpr int q_phi(int slot) { return 24 + slot; }
+__host__ __device__ constexpr int q_c(int comp) { return 27 + comp; }
+constexpr int kNumArrays = 30;
+__host__ __device__ constexpr int q_axg(int d, int side, int slot) { return (d * 2 + side) * 3 + slot; }
+__host__ __device__ constexpr int q_mur(int o, int d, int side, int comp, int slot) { return 18 + (((o * 3 + d) * 2 + side) * 3 + comp) * 2 + slot; }
+constexpr int kNumFaces = 90;
+
+// Immutable per-run descriptor, stored in device memory once at creation.
+// Time-level slots rotate with the step counter: E/B buffers and Mur ghosts by
+// parity, the three axion levels (and their ghosts) modulo 3.
+template <typename T>
+struct RunK {
+    int D;
+    int n[3], nn[3];          // cells, storage extents (n + 1 on Mur axes)
+    int mur[3], axbc[3];
+    long sx, sy;              // element strides of j and k
+    long npts;                // nn0 * nn1 * nn2
+    // coefficients in storage precision
+    T cdt[3];                 // dt / dx
+    T inv_dt, inv2dx[3], inv_dx2[3], dt2, m2, gax, cg1, half;
+    T bext[3];
+    int slab_lo, slab_hi;
+    T pml_sdt_max;            // sigma_max * dt
+    int pml_n;
+    T out_r[3];               // dt / dx for the outflow ghost solve
+    // FP64 parameters
+    double dt, dx[3], murc[3], m2d;
+    double s_phi, s_1;
+    Laser las;
+    Packet pk;
+    // state (uniform layout, see q_em / q_axg; the pointers below point into it)
+    char *state_base, *face_base;
+    long arr_stride, face_stride;
+    T *E0[2][3], *B0[2][3], *E1[2][3], *B1[2][3];
+    T *phi[3];
+    T *C[3];                  // scratch: axion current at centres (plain path)
+    T *axg[3][2][3];          // axion ghosts [axis][side][slot]
+    T *murg[2][3][2][3][2];   // Mur ghosts [order][axis][side][component][slot]
+    // diagnostics
+    double *part;             // per-block partial sums, 4 per block
+    int diag_blocks;
+    axf_diag_record *rec;     // device ring of records (slot chosen by the host)
+    int rec_cap;
+};
+
+__host__ __device__ inline long round_up(long v, long m) { return (v + m - 1) / m * m; }
+
+}  // namespace axf

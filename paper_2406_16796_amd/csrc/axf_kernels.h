@@ -1,0 +1,23 @@
+// axf_kernels.h -- host-side launchers of the kernels of libaxf.
+#pragma once
+
+#include "axf_internal.h"
+
+namespace axf {
+
+// Unfused step: one launch per update phase (the correctness baseline).
+template <int D, typename T>
+struct Plain {
+    static void e0(const RunK<T> *rk, const RunK<T>& h, int s_in, int s_b, int s_out, T scale, hipStream_t st);
+    static void c(const RunK<T> *rk, const RunK<T>& h, int pa, int pb, int e_m, int e_p, int s_b, int cotimed, hipStream_t st);
+    static void e1(const RunK<T> *rk, const RunK<T>& h, int s_in, int s_b, int s_out, T scale, hipStream_t st);
+    static void mur(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
+    static void mur_init(const RunK<T> *rk, const RunK<T>& h, hipStream_t st);
+    static void b(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
+    static void phi(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
+    static void init_phi(const RunK<T> *rk, const RunK<T>& h, hipStream_t st);
+    static void copy_ghosts(const RunK<T> *rk, const RunK<T>& h, int s0, int s1, hipStream_t st);
+    static void diag(const RunK<T> *rk, const RunK<T>& h, long step, int slot, hipStream_t st);
+};
+
+}  // namespace axf

@@ -1,0 +1,552 @@
+// axf_plain.hip -- the unfused step: one kernel per update phase of the
+// leapfrog form (E0, axion current C, E1, Mur ghosts, B, axion), plus the
+// initial state, the co-timed -> leapfrog conversion and the diagnostics.
+// Every thread owns one storage index (i,j,k) and reads its neighbours from
+// global memory.  These kernels are the correctness baseline of the fused path.
+#include "axf_stencil.h"
+#include "axf_kernels.h"
+
+namespace axf {
+
+template <typename T>
+__device__ __forceinline__ bool decompose(const RunK<T>& r, long p, int& i, int& j, int& k)
+{
+    if (p >= r.npts) return false;
+    long q = p / r.nn[0];
+    i = (int)(p - q * r.nn[0]);
+    k = (int)(q / r.nn[1]);
+    j = (int)(q - (long)k * r.nn[1]);
+    return true;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ bool in_E(const RunK<T>& r, int c, int i, int j, int k)
+{
+    return i < (c == 0 ? r.nn[0] : r.n[0]) && j < (c == 1 ? r.nn[1] : r.n[1]) && k < (c == 2 ? r.nn[2] : r.n[2]);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ bool in_B(const RunK<T>& r, int c, int i, int j, int k)
+{
+    return i < (c != 0 ? r.nn[0] : r.n[0]) && j < (c != 1 ? r.nn[1] : r.n[1]) && k < (c != 2 ? r.nn[2] : r.n[2]);
+}
+
+template <typename T>
+__device__ __forceinline__ bool in_cell(const RunK<T>& r, int i, int j, int k)
+{
+    return i < r.n[0] && j < r.n[1] && k < r.n[2];
+}
+
+// E0_out = E0_in + scale * dt curl B0   (scale 1: step; -1/2: backward half step)
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_e0(const RunK<T> *__restrict__ rp, int s_in, int s_b, int s_out, T scale)
+{
+    const RunK<T>& r = *rp;
+    int i, j, k;
+    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    long id = lin(r, i, j, k);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (!actE0<D>(c) || !in_E<D>(r, c, i, j, k)) continue;
+        T rhs = curl_B<D, 0>(r, r.B0[s_b], c, i, j, k, id);
+        r.E0[s_out][c][id] = r.E0[s_in][c][id] + scale * rhs;
+    }
+}
+
+// C = (D_t phi) B0 - E0 x (D phi) at every centre for the integer time between
+// axion slots (a, b); E0 = mean of slots (e_m, e_p), or slot e_m alone if cotimed.
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_c(const RunK<T> *__restrict__ rp, int pa, int pb, int e_m, int e_p, int s_b, int cotimed)
+{
+    const RunK<T>& r = *rp;
+    int i, j, k;
+    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!in_cell(r, i, j, k)) return;
+    long id = lin(r, i, j, k);
+    T e[3], b[3], gp[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        e[c] = T(0);
+        if (actE0<D>(c)) {
+            const T *m = r.E0[e_m][c], *p = r.E0[e_p][c];
+            long o = c < D ? em_step(r, c, coord(c, i, j, k), 1) : 0;
+            T lo = cotimed ? m[id] : r.half * (m[id] + p[id]);
+            T hi = cotimed ? m[id + o] : r.half * (m[id + o] + p[id + o]);
+            e[c] = c < D ? r.half * (lo + hi) : lo;
+        }
+        b[c] = centre_B<D, 0>(r, r.B0[s_b], c, i, j, k, id) + bext_at(r, c, i);
+    }
+    const T *A = r.phi[pa], *Bp = r.phi[pb];
+    T dtphi = (Bp[id] - A[id]) * r.inv_dt;
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        T up = r.half * (phi_nb(r, A, pa, d, 1, i, j, k, id) + phi_nb(r, Bp, pb, d, 1, i, j, k, id));
+        T dn = r.half * (phi_nb(r, A, pa, d, -1, i, j, k, id) + phi_nb(r, Bp, pb, d, -1, i, j, k, id));
+        gp[d] = (up - dn) * r.inv2dx[d];
+    }
+    r.C[0][id] = dtphi * b[0] - (e[1] * gp[2] - e[2] * gp[1]);
+    r.C[1][id] = dtphi * b[1] - (e[2] * gp[0] - e[0] * gp[2]);
+    r.C[2][id] = dtphi * b[2] - (e[0] * gp[1] - e[1] * gp[0]);
+}
+
+// axion current on the E_c face: mean of C_c at the two adjacent centres (one
+// interior centre on a Mur face, wrap on a periodic axis)
+template <int D, typename T>
+__device__ __forceinline__ T face_S(const RunK<T>& r, int c, int i, int j, int k, long id)
+{
+    const T *C = r.C[c];
+    if (c >= D) return C[id];
+    int v = coord(c, i, j, k), lo = v - 1, hi = v;
+    if (r.mur[c]) {
+        lo = lo < 0 ? 0 : lo;
+        hi = hi > r.n[c] - 1 ? r.n[c] - 1 : hi;
+    } else {
+        lo = wrapi(lo, r.n[c]);
+    }
+    long st = stride_of(r, c);
+    return r.half * (C[id + (long)(lo - v) * st] + C[id + (long)(hi - v) * st]);
+}
+
+// E1_out = E1_in + scale * dt (curl B1 - g1 S)
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_e1(const RunK<T> *__restrict__ rp, int s_in, int s_b, int s_out, T scale)
+{
+    const RunK<T>& r = *rp;
+    int i, j, k;
+    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    long id = lin(r, i, j, k);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (!actE1<D>(c) || !in_E<D>(r, c, i, j, k)) continue;
+        T rhs = curl_B<D, 1>(r, r.B1[s_b], c, i, j, k, id) - r.cg1 * face_S<D>(r, c, i, j, k, id);
+        r.E1[s_out][c][id] = r.E1[s_in][c][id] + scale * rhs;
+    }
+}
+
+// First-order Mur for the tangential E ghost half a cell outside a Mur face, on
+// the scattered part E - E_inc (E_inc nonzero for E0 on the x_min face):
+// ghost^{n+1/2} = inc_g^{n+1/2} + s_a^{n-1/2} + c_M (s_a^{n+1/2} - s_g^{n-1/2}),
+// c_M = (dt - dx)/(dt + dx), s = scattered part, a = adjacent interior centre.
+template <int D, int O, typename T>
+__device__ __forceinline__ void mur_point(const RunK<T>& r, long step, int d, int side, int c, int ia, int ib)
+{
+    if (!actE<D, O>(c)) return;
+    const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+    int id3[3];
+    id3[d] = side ? r.n[d] - 1 : 0;
+    id3[a] = ia;
+    id3[b] = ib;
+    // E_c is nodal along c and centred along the other face axis
+    for (int e = 0; e < 3; e++) {
+        if (e == d) continue;
+        int ext = (e == c) ? r.nn[e] : r.n[e];
+        if (id3[e] >= ext) return;
+    }
+    const int s_old = (int)(step & 1), s_new = s_old ^ 1;
+    long id = lin(r, id3[0], id3[1], id3[2]);
+    long f = face_index(r, d, id3[0], id3[1], id3[2]);
+    T *const *Eo = O == 0 ? r.E0[s_old] : r.E1[s_old];
+    T *const *En = O == 0 ? r.E0[s_new] : r.E1[s_new];
+    double e_old = (double)Eo[c][id], e_new = (double)En[c][id];
+    double g_old = (double)r.murg[O][d][side][c][s_old][f];
+    double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
+    if (O == 0 && d == 0 && side == 0 && r.las.on) {
+        double pos[3];
+        for (int e = 0; e < 3; e++)
+            pos[e] = (e == c) ? id3[e] * r.dx[e] : (id3[e] + 0.5) * r.dx[e];
+        double xg = -0.5 * r.dx[0];
+        double t_o = (step - 0.5) * r.dt, t_n = (step + 0.5) * r.dt;
+        ia_o = incident(r.las, c, pos[0], pos[1], pos[2], t_o);
+        ia_n = incident(r.las, c, pos[0], pos[1], pos[2], t_n);
+        ig_o = incident(r.las, c, xg, pos[1], pos[2], t_o);
+        ig_n = incident(r.las, c, xg, pos[1], pos[2], t_n);
+    }
+    double sa_o = e_old - ia_o, sa_n = e_new - ia_n, sg_o = g_old - ig_o;
+    double sg_n = sa_o + r.murc[d] * (sa_n - sg_o);
+    r.murg[O][d][side][c][s_new][f] = (T)(sg_n + ig_n);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_mur(const RunK<T> *__restrict__ rp, long step)
+{
+    const RunK<T>& r = *rp;
+    const int d = blockIdx.y >> 1, side = blockIdx.y & 1;
+    if (d >= D || !r.mur[d]) return;
+    const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+    long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long na = r.nn[a], nb = r.nn[b];
+    if (p >= na * nb) return;
+    int ia = (int)(p % na), ib = (int)(p / na);
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        int c = q == 0 ? a : b;
+        mur_point<D, 0>(r, step, d, side, c, ia, ib);
+        mur_point<D, 1>(r, step, d, side, c, ia, ib);
+    }
+}
+
+// Mur ghost slot 0 at t = -dt/2: the incident field on the x_min face, zero elsewhere
+template <int D, typename T>
+__global__ void k_mur_init(const RunK<T> *__restrict__ rp)
+{
+    const RunK<T>& r = *rp;
+    const int d = blockIdx.y >> 1, side = blockIdx.y & 1;
+    if (d >= D || !r.mur[d]) return;
+    const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+    long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long na = r.nn[a], nb = r.nn[b];
+    if (p >= na * nb) return;
+    int ia = (int)(p % na), ib = (int)(p / na);
+    for (int q = 0; q < 2; q++) {
+        int c = q == 0 ? a : b;
+        for (int o = 0; o < 2; o++) {
+            T *g = r.murg[o][d][side][c][0];
+            if (!g) continue;
+            double v = 0.0;
+            if (o == 0 && d == 0 && side == 0 && r.las.on) {
+                int id3[3];
+                id3[0] = 0; id3[a] = ia; id3[b] = ib;
+                double y = (c == 1) ? id3[1] * r.dx[1] : (id3[1] + 0.5) * r.dx[1];
+                double z = (c == 2) ? id3[2] * r.dx[2] : (id3[2] + 0.5) * r.dx[2];
+                v = incident(r.las, c, -0.5 * r.dx[0], y, z, -0.5 * r.dt);
+            }
+            g[p] = (T)v;
+        }
+    }
+}
+
+// B^{n+1} = B^n - dt curl E^{n+1/2}, both orders, old slot -> new slot
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_b(const RunK<T> *__restrict__ rp, long step)
+{
+    const RunK<T>& r = *rp;
+    int i, j, k;
+    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    long id = lin(r, i, j, k);
+    const int so = (int)(step & 1), sn = so ^ 1;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (!in_B<D>(r, c, i, j, k)) continue;
+        if (actB0<D>(c))
+            r.B0[sn][c][id] = r.B0[so][c][id] - curl_E<D, 0>(r, sn, sn, c, i, j, k);
+        if (actB1<D>(c))
+            r.B1[sn][c][id] = r.B1[so][c][id] - curl_E<D, 1>(r, sn, sn, c, i, j, k);
+    }
+}
+
+// phi^{n+3/2}: leapfrog of the Klein-Gordon equation with source g E0.B0 at
+// t_{n+1/2} (Sec. II.C, eq. update_axion), in the damped form of the PML
+// layer (Sec. II.D) where sigma > 0, then the ghosts of the new level.
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_phi(const RunK<T> *__restrict__ rp, long step)
+{
+    const RunK<T>& r = *rp;
+    int i, j, k;
+    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!in_cell(r, i, j, k)) return;
+    long id = lin(r, i, j, k);
+    const int so = (int)(step & 1), sn = so ^ 1;
+    const int la = (int)(step % 3), lb = (int)((step + 1) % 3), ln = (int)((step + 2) % 3);
+    T e[3], b[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        e[c] = actE0<D>(c) ? centre_E<D>(r, r.E0[sn][c], c, i, j, k, id) : T(0);
+        T bo = centre_B<D, 0>(r, r.B0[so], c, i, j, k, id);
+        T bn = centre_B<D, 0>(r, r.B0[sn], c, i, j, k, id);
+        b[c] = r.half * (bo + bn) + bext_at(r, c, i);
+    }
+    T sax = r.gax * (e[0] * b[0] + e[1] * b[1] + e[2] * b[2]);
+    const T *A = r.phi[la], *Bp = r.phi[lb];
+    T pa = A[id], pb = Bp[id];
+    T lap = T(0);
+#pragma unroll
+    for (int d = 0; d < D; d++)
+        lap += ((phi_nb(r, Bp, lb, d, 1, i, j, k, id) - T(2) * pb) + phi_nb(r, Bp, lb, d, -1, i, j, k, id)) * r.inv_dx2[d];
+    T sdt = pml_sdt<D>(r, i, j, k);
+    T x = r.dt2 * ((sax - r.m2 * pb) + lap) - sdt * sdt * pb;
+    T pn = (((x + sdt * pa) + T(2) * pb) - pa) / (T(1) + sdt);
+    r.phi[ln][id] = pn;
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        if (r.axbc[d] == AXF_AX_PERIODIC) continue;
+        int v = coord(d, i, j, k);
+        for (int side = 0; side < 2; side++) {
+            if (v != (side ? r.n[d] - 1 : 0)) continue;
+            long f = face_index(r, d, i, j, k);
+            T g;
+            if (r.axbc[d] == AXF_AX_OUTFLOW) {
+                // one-way wave and Klein-Gordon at the ghost (Sec. II.D, outflow)
+                T gb = r.axg[d][side][lb][f], ga = r.axg[d][side][la][f], rr = r.out_r[d];
+                T xx = (((T(-2) * gb + T(2) * ga) - r.dt2 * (sax - r.m2 * gb)) + rr * pb - rr * rr * (pb - T(2) * gb))
+                       / (rr + rr * rr);
+                g = ga + rr * (pb - xx);
+            } else {
+                g = pn;
+            }
+            r.axg[d][side][ln][f] = g;
+        }
+    }
+}
+
+// initial axion levels at t = -dt/2 (slot 0) and +dt/2 (slot 1) from the packet,
+// with their ghosts (outflow: the packet at the ghost centre; others: copies)
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_init_phi(const RunK<T> *__restrict__ rp)
+{
+    const RunK<T>& r = *rp;
+    int i, j, k;
+    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!in_cell(r, i, j, k)) return;
+    long id = lin(r, i, j, k);
+    double x = (i + 0.5) * r.dx[0], y = (j + 0.5) * r.dx[1], z = (k + 0.5) * r.dx[2];
+    double inv = 1.0 / r.s_phi;
+    for (int L = 0; L < 2; L++) {
+        double t = (L == 0 ? -0.5 : 0.5) * r.dt;
+        r.phi[L][id] = (T)(packet_value(r.pk, D, x, y, z, t) * inv);
+    }
+    for (int d = 0; d < D; d++) {
+        if (r.axbc[d] != AXF_AX_OUTFLOW) continue;
+        int v = coord(d, i, j, k);
+        for (int side = 0; side < 2; side++) {
+            if (v != (side ? r.n[d] - 1 : 0)) continue;
+            double pos[3] = {x, y, z};
+            pos[d] = side ? (r.n[d] + 0.5) * r.dx[d] : -0.5 * r.dx[d];
+            long f = face_index(r, d, i, j, k);
+            for (int L = 0; L < 2; L++) {
+                double t = (L == 0 ? -0.5 : 0.5) * r.dt;
+                r.axg[d][side][L][f] = (T)(packet_value(r.pk, D, pos[0], pos[1], pos[2], t) * inv);
+            }
+        }
+    }
+}
+
+// reflect / PML ghosts of axion slots 0 and 1 copied from the interior
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_copy_ghosts(const RunK<T> *__restrict__ rp, int s0, int s1)
+{
+    const RunK<T>& r = *rp;
+    int i, j, k;
+    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!in_cell(r, i, j, k)) return;
+    long id = lin(r, i, j, k);
+    for (int d = 0; d < D; d++) {
+        if (r.axbc[d] != AXF_AX_REFLECT && r.axbc[d] != AXF_AX_PML) continue;
+        int v = coord(d, i, j, k);
+        for (int side = 0; side < 2; side++) {
+            if (v != (side ? r.n[d] - 1 : 0)) continue;
+            long f = face_index(r, d, i, j, k);
+            r.axg[d][side][s0][f] = r.phi[s0][id];
+            r.axg[d][side][s1][f] = r.phi[s1][id];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- diagnostics
+
+template <typename T>
+__device__ __forceinline__ bool finite_val(T v) { return v == v && v - v == T(0); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// block sums of 4 quantities in a fixed order (deterministic), written to part[blk*4 + q]
+__device__ __forceinline__ void block_sum4(double v[4], double *out)
+{
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        double s = wave_sum(v[q]);
+        if (lane == 0) red[w][q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        int q = threadIdx.x;
+        out[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+    }
+}
+
+// energies at t_n: E^n = mean of the two E slots, B^n = old slot, phi^n = mean
+// of the axion levels; H_phi = sum ((D_t phi)^2 + sum_d (D+_d phi)^2 + m^2 phi^2) / 2
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_diag(const RunK<T> *__restrict__ rp, long step)
+{
+    const RunK<T>& r = *rp;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    int i, j, k;
+    long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (decompose(r, p, i, j, k)) {
+        long id = lin(r, i, j, k);
+        const int so = (int)(step & 1), sn = so ^ 1;
+        const int la = (int)(step % 3), lb = (int)((step + 1) % 3);
+        bool fin = true;
+        if (in_cell(r, i, j, k)) {
+            const T *A = r.phi[la], *Bp = r.phi[lb];
+            double pa = A[id], pb = Bp[id];
+            double dtp = (pb - pa) / r.dt, pm = 0.5 * (pa + pb);
+            double e = dtp * dtp + r.m2d * pm * pm;
+            for (int d = 0; d < D; d++) {
+                int vv = coord(d, i, j, k);
+                if (r.axbc[d] != AXF_AX_PERIODIC && vv + 1 >= r.n[d]) continue;
+                int w = wrapi(vv + 1, r.n[d]);
+                long o = (long)(w - vv) * stride_of(r, d);
+                double pn = 0.5 * ((double)A[id + o] + (double)Bp[id + o]);
+                double gr = (pn - pm) / r.dx[d];
+                e += gr * gr;
+            }
+            v[0] = 0.5 * e;
+            fin = fin && finite_val(pa) && finite_val(pb);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            if (in_E<D>(r, c, i, j, k)) {
+                if (actE0<D>(c)) {
+                    double ev = 0.5 * ((double)r.E0[so][c][id] + (double)r.E0[sn][c][id]);
+                    v[1] += 0.5 * ev * ev;
+                    fin = fin && finite_val(ev);
+                }
+                if (actE1<D>(c)) {
+                    double ev = 0.5 * ((double)r.E1[so][c][id] + (double)r.E1[sn][c][id]);
+                    v[2] += 0.5 * ev * ev;
+                    fin = fin && finite_val(ev);
+                }
+            }
+            if (in_B<D>(r, c, i, j, k)) {
+                if (actB0<D>(c)) {
+                    double bv = r.B0[so][c][id];
+                    v[1] += 0.5 * bv * bv;
+                    fin = fin && finite_val(bv);
+                }
+                if (actB1<D>(c)) {
+                    double bv = r.B1[so][c][id];
+                    v[2] += 0.5 * bv * bv;
+                    fin = fin && finite_val(bv);
+                }
+            }
+        }
+        v[3] = fin ? 0.0 : 1.0;
+    }
+    block_sum4(v, r.part + blockIdx.x * 4);
+}
+
+// fixed-order sum of the block partials into record slot `slot`
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag_final(const RunK<T> *__restrict__ rp, long step, int slot)
+{
+    const RunK<T>& r = *rp;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int blk = threadIdx.x; blk < r.diag_blocks; blk += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 4; q++) v[q] += r.part[blk * 4 + q];
+    __shared__ double tot[4];
+    block_sum4(v, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double dv = 1.0;
+        for (int d = 0; d < r.D; d++) dv *= r.dx[d];
+        axf_diag_record rec;
+        rec.step = step;
+        rec.t = step * r.dt;
+        rec.h_phi = tot[0] * dv * r.s_phi * r.s_phi;
+        rec.h_em0 = tot[1] * dv;
+        rec.h_em1 = tot[2] * dv * r.s_1 * r.s_1;
+        rec.p_gen = rec.h_em0 > 0.0 ? rec.h_phi / rec.h_em0 : 0.0;
+        rec.p_conv = rec.h_phi > 0.0 ? rec.h_em1 / rec.h_phi : 0.0;
+        rec.finite = tot[3] == 0.0 ? 1 : 0;
+        rec.pad = 0;
+        r.rec[slot] = rec;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline unsigned nblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int D, typename T>
+void Plain<D, T>::e0(const RunK<T> *rk, const RunK<T>& h, int s_in, int s_b, int s_out, T scale, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_e0<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, s_in, s_b, s_out, scale);
+}
+
+template <int D, typename T>
+void Plain<D, T>::c(const RunK<T> *rk, const RunK<T>& h, int pa, int pb, int e_m, int e_p, int s_b, int cotimed, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_c<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, pa, pb, e_m, e_p, s_b, cotimed);
+}
+
+template <int D, typename T>
+void Plain<D, T>::e1(const RunK<T> *rk, const RunK<T>& h, int s_in, int s_b, int s_out, T scale, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_e1<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, s_in, s_b, s_out, scale);
+}
+
+template <int D, typename T>
+void Plain<D, T>::mur(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st)
+{
+    long face = 0;
+    for (int d = 0; d < D; d++) {
+        if (!h.mur[d]) continue;
+        int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+        long f = (long)h.nn[a] * h.nn[b];
+        face = f > face ? f : face;
+    }
+    if (face == 0) return;
+    hipLaunchKernelGGL((k_mur<D, T>), dim3(nblocks(face, 256), 2 * D), dim3(256), 0, st, rk, step);
+}
+
+template <int D, typename T>
+void Plain<D, T>::mur_init(const RunK<T> *rk, const RunK<T>& h, hipStream_t st)
+{
+    long face = 0;
+    for (int d = 0; d < D; d++) {
+        if (!h.mur[d]) continue;
+        int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+        long f = (long)h.nn[a] * h.nn[b];
+        face = f > face ? f : face;
+    }
+    if (face == 0) return;
+    hipLaunchKernelGGL((k_mur_init<D, T>), dim3(nblocks(face, 256), 2 * D), dim3(256), 0, st, rk);
+}
+
+template <int D, typename T>
+void Plain<D, T>::b(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_b<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
+}
+
+template <int D, typename T>
+void Plain<D, T>::phi(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_phi<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
+}
+
+template <int D, typename T>
+void Plain<D, T>::init_phi(const RunK<T> *rk, const RunK<T>& h, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_init_phi<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk);
+}
+
+template <int D, typename T>
+void Plain<D, T>::copy_ghosts(const RunK<T> *rk, const RunK<T>& h, int s0, int s1, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_copy_ghosts<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, s0, s1);
+}
+
+template <int D, typename T>
+void Plain<D, T>::diag(const RunK<T> *rk, const RunK<T>& h, long step, int slot, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_diag<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
+    hipLaunchKernelGGL((k_diag_final<T>), dim3(1), dim3(256), 0, st, rk, step, slot);
+}
+
+template struct Plain<1, float>;
+template struct Plain<2, float>;
+template struct Plain<3, float>;
+template struct Plain<1, double>;
+template struct Plain<2, double>;
+template struct Plain<3, double>;
+
+}  // namespace axf

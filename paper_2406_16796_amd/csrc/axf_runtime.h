@@ -1,0 +1,66 @@
+// axf_runtime.h -- host-side run object and memory layout of libaxf.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "axf_internal.h"
+
+namespace axf {
+
+// Byte offsets of every array of one run inside its device buffer (-1 = absent).
+struct Layout {
+    int n[3], nn[3];
+    long px;                     // padded row length (elements)
+    size_t arr_bytes;            // bytes of one field array
+    long npts;
+    size_t off_rk;               // device copy of the run descriptor
+    size_t off_state;            // start of the checkpointed region
+    size_t off_arrays, arr_stride, off_faces, face_stride;
+    long off_em[4][2][3];        // [E0,B0,E1,B1][slot][component]
+    long off_phi[3];
+    long off_c[3];
+    long off_axg[3][2][3];
+    long off_murg[2][3][2][3][2];
+    int diag_blocks;
+    size_t off_part;
+    int rec_cap;
+    size_t off_rec;
+    size_t total;
+};
+
+struct Run {
+    axf_config cfg;
+    Layout L;
+    char *base = nullptr;
+    hipStream_t stream = nullptr;
+    double s_phi = 1.0, s_1 = 1.0;
+    RunK<float> hf;
+    RunK<double> hd;
+    int64_t step = 0;
+    bool converted = false;
+    int64_t ephase_step = -1;
+    int64_t rec_written = 0;
+    int64_t launches = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int64_t timed_steps = 0, timed_launches = 0;
+    bool batch_owned = false;
+    bool use_fused = false;
+    int chunk = 0;                 // fused planes per workgroup (0: default)
+
+    template <typename T> const RunK<T>& hk() const;
+    template <typename T> const RunK<T> *rk() const { return (const RunK<T> *)(base + L.off_rk); }
+};
+
+template <> inline const RunK<float>& Run::hk<float>() const { return hf; }
+template <> inline const RunK<double>& Run::hk<double>() const { return hd; }
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int validate(const axf_config *c);
+Layout make_layout(const axf_config *c);
+int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStream_t stream);
+int run_step(Run *R, int64_t nsteps);
+bool fused_supported(const axf_config *c);
+
+}  // namespace axf

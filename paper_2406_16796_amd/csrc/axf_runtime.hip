@@ -1,0 +1,769 @@
+// axf_runtime.hip -- host side of libaxf: configuration checks, device
+// memory carving, the step driver, field/diagnostic/state I/O and the C ABI.
+#include <math.h>
+#include <stdlib.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "axf_internal.h"
+#include "axf_fused.h"
+#include "axf_kernels.h"
+#include "axf_runtime.h"
+
+namespace axf {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(AXF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(call)                                             \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);        \
+    } while (0)
+
+// ------------------------------------------------------------ validation
+
+// AUTO picks the fused kernel only where it beats the unfused sequence
+// (AXF_AUTO_FUSED=1 forces it wherever supported)
+static bool auto_fused_enabled(const axf_config *c)
+{
+    const char *e = getenv("AXF_AUTO_FUSED");
+    if (e) return e[0] == '1';
+    return false;
+}
+
+static double pow2_near(double v) { return ldexp(1.0, (int)lround(log2(v))); }
+
+int validate(const axf_config *c)
+{
+    if (!c) return fail(AXF_EINVAL, "null config");
+    const int D = c->ndim;
+    if (D < 1 || D > 3) return fail(AXF_EINVAL, "ndim must be 1, 2 or 3 (got %d)", D);
+    if (c->precision != AXF_F32 && c->precision != AXF_F64) return fail(AXF_EINVAL, "precision must be AXF_F32 or AXF_F64");
+    double inv2 = 0.0;
+    for (int d = 0; d < 3; d++) {
+        if (d >= D) {
+            if (c->n[d] != 1) return fail(AXF_EINVAL, "axis %d beyond ndim must have n = 1", d);
+            continue;
+        }
+        if (c->n[d] < 2) return fail(AXF_EINVAL, "axis %d needs at least 2 cells", d);
+        if (!(c->dx[d] > 0.0)) return fail(AXF_EINVAL, "dx[%d] must be positive", d);
+        if (c->em_bc[d] != AXF_EM_PERIODIC && c->em_bc[d] != AXF_EM_MUR) return fail(AXF_EINVAL, "bad em_bc[%d]", d);
+        if (c->ax_bc[d] < AXF_AX_PERIODIC || c->ax_bc[d] > AXF_AX_PML) return fail(AXF_EINVAL, "bad ax_bc[%d]", d);
+        if (c->ax_bc[d] == AXF_AX_PML && (c->pml_n < 1 || 2 * c->pml_n > c->n[d]))
+            return fail(AXF_EINVAL, "PML thickness %d does not fit axis %d", c->pml_n, d);
+        if (c->ax_bc[d] == AXF_AX_PML && !(c->pml_sigma_dt >= 0.0)) return fail(AXF_EINVAL, "pml_sigma_dt must be >= 0");
+        inv2 += 1.0 / (c->dx[d] * c->dx[d]);
+    }
+    if (!(c->dt > 0.0)) return fail(AXF_EINVAL, "dt must be positive");
+    if (!(c->m >= 0.0) || !isfinite(c->g)) return fail(AXF_EINVAL, "m must be >= 0 and g finite");
+    if (c->dt * c->dt * (inv2 + 0.25 * c->m * c->m) >= 1.0)
+        return fail(AXF_EUNSTABLE, "dt = %g beyond the Yee/Klein-Gordon stability limit", c->dt);
+    if (D == 1 && c->bext[0] != 0.0) return fail(AXF_EINVAL, "1D runs need bext[0] == 0 (longitudinal E1 not stored)");
+    if (c->slab_lo > c->slab_hi) return fail(AXF_EINVAL, "slab_lo > slab_hi");
+    if (c->laser_on) {
+        if (c->em_bc[0] != AXF_EM_MUR) return fail(AXF_EINVAL, "the laser enters through a Mur x_min face");
+        if (c->laser_pol != 1 && c->laser_pol != 2) return fail(AXF_EINVAL, "laser_pol must be 1 or 2");
+        if (D == 2 && c->laser_pol != 1) return fail(AXF_EINVAL, "2D runs carry the in-plane (y) polarisation");
+        if (!(c->omega > 0.0)) return fail(AXF_EINVAL, "laser omega must be positive");
+        if (c->laser_env == AXF_ENV_GAUSS && !(c->fwhm > 0.0)) return fail(AXF_EINVAL, "Gaussian laser needs fwhm > 0");
+        if (c->laser_env == AXF_ENV_CW && !(c->ramp_periods > 0.0)) return fail(AXF_EINVAL, "CW laser needs ramp_periods > 0");
+    }
+    if (c->packet_on && (!(c->pk_w > 0.0) || (c->pk_dir != 1 && c->pk_dir != -1)))
+        return fail(AXF_EINVAL, "packet needs w > 0 and dir = +-1");
+    if (c->diag_every < 0) return fail(AXF_EINVAL, "diag_every must be >= 0");
+    if (c->path < AXF_PATH_AUTO || c->path > AXF_PATH_FUSED) return fail(AXF_EINVAL, "bad path");
+    return AXF_OK;
+}
+
+// ------------------------------------------------------------------ layout
+
+static size_t elem_size(const axf_config *c) { return c->precision == AXF_F64 ? 8 : 4; }
+
+Layout make_layout(const axf_config *c)
+{
+    Layout L;
+    const int D = c->ndim;
+    const size_t es = elem_size(c);
+    for (int d = 0; d < 3; d++) {
+        L.n[d] = c->n[d];
+        L.nn[d] = (d < D && c->em_bc[d] == AXF_EM_MUR) ? c->n[d] + 1 : c->n[d];
+    }
+    L.px = round_up(L.nn[0], 64 / (long)es);
+    L.arr_bytes = (size_t)L.px * L.nn[1] * L.nn[2] * es;
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t o = off; off += (size_t)round_up((long)b, 256); return o; };
+    L.off_rk = take(c->precision == AXF_F64 ? sizeof(RunK<double>) : sizeof(RunK<float>));
+    L.off_state = off;
+    auto act = [&](int kind, int comp) -> bool {
+        switch (D) {
+        case 1: return kind == 0 ? actE0<1>(comp) : kind == 1 ? actB0<1>(comp) : kind == 2 ? actE1<1>(comp) : actB1<1>(comp);
+        case 2: return kind == 0 ? actE0<2>(comp) : kind == 1 ? actB0<2>(comp) : kind == 2 ? actE1<2>(comp) : actB1<2>(comp);
+        default: return true;
+        }
+    };
+    // every array and every boundary plane is reserved, used or not, so that
+    // the kernels address them as base + index * stride
+    L.arr_stride = (size_t)round_up((long)L.arr_bytes, 256);
+    L.off_arrays = off;
+    off += L.arr_stride * kNumArrays;
+    for (int kind = 0; kind < 4; kind++)
+        for (int s = 0; s < 2; s++)
+            for (int comp = 0; comp < 3; comp++)
+                L.off_em[kind][s][comp] = act(kind, comp) ? (long)(L.off_arrays + L.arr_stride * q_em(kind, s, comp)) : -1;
+    for (int s = 0; s < 3; s++) L.off_phi[s] = (long)(L.off_arrays + L.arr_stride * q_phi(s));
+    for (int comp = 0; comp < 3; comp++) L.off_c[comp] = (long)(L.off_arrays + L.arr_stride * q_c(comp));
+    size_t fmax = 0;
+    for (int d = 0; d < 3; d++) {
+        int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+        size_t fb = (size_t)L.nn[a] * L.nn[b] * es;
+        fmax = fb > fmax ? fb : fmax;
+    }
+    L.face_stride = (size_t)round_up((long)fmax, 256);
+    L.off_faces = off;
+    off += L.face_stride * kNumFaces;
+    for (int d = 0; d < 3; d++)
+        for (int side = 0; side < 2; side++) {
+            for (int s = 0; s < 3; s++)
+                L.off_axg[d][side][s] = (d < D && c->ax_bc[d] != AXF_AX_PERIODIC) ? (long)(L.off_faces + L.face_stride * q_axg(d, side, s)) : -1;
+            for (int o = 0; o < 2; o++)
+                for (int comp = 0; comp < 3; comp++)
+                    for (int s = 0; s < 2; s++) {
+                        bool on = d < D && c->em_bc[d] == AXF_EM_MUR && comp != d && act(o == 0 ? 0 : 2, comp);
+                        L.off_murg[o][d][side][comp][s] = on ? (long)(L.off_faces + L.face_stride * q_mur(o, d, side, comp, s)) : -1;
+                    }
+        }
+    L.npts = (long)L.nn[0] * L.nn[1] * L.nn[2];
+    L.diag_blocks = (int)((L.npts + 255) / 256);
+    L.off_part = take((size_t)L.diag_blocks * 4 * sizeof(double));
+    L.rec_cap = 4096;
+    L.off_rec = take((size_t)(L.rec_cap + 1) * sizeof(axf_diag_record));
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+static void fill_runk(RunK<T>& k, const axf_config *c, const Layout& L, char *base, double s_phi, double s_1)
+{
+    memset((void *)&k, 0, sizeof k);
+    const int D = c->ndim;
+    k.D = D;
+    for (int d = 0; d < 3; d++) {
+        k.n[d] = L.n[d];
+        k.nn[d] = L.nn[d];
+        k.mur[d] = d < D && c->em_bc[d] == AXF_EM_MUR;
+        k.axbc[d] = d < D ? c->ax_bc[d] : AXF_AX_PERIODIC;
+        double dx = d < D ? c->dx[d] : 1.0;
+        k.dx[d] = dx;
+        k.cdt[d] = d < D ? (T)(c->dt / dx) : T(0);
+        k.inv2dx[d] = (T)(0.5 / dx);
+        k.inv_dx2[d] = (T)(1.0 / (dx * dx));
+        k.out_r[d] = (T)(c->dt / dx);
+        k.murc[d] = (c->dt - dx) / (c->dt + dx);
+        k.bext[d] = (T)c->bext[d];
+    }
+    k.sx = L.px;
+    k.sy = L.px * L.nn[1];
+    k.npts = L.npts;
+    k.inv_dt = (T)(1.0 / c->dt);
+    k.dt2 = (T)(c->dt * c->dt);
+    k.m2 = (T)(c->m * c->m);
+    k.m2d = c->m * c->m;
+    k.gax = (T)(c->g / s_phi);
+    k.cg1 = (T)(c->dt * c->g * s_phi / s_1);
+    k.half = T(0.5);
+    k.slab_lo = c->slab_lo;
+    k.slab_hi = c->slab_hi;
+    k.pml_sdt_max = (T)c->pml_sigma_dt;
+    k.pml_n = c->pml_n > 0 ? c->pml_n : 1;
+    k.dt = c->dt;
+    k.s_phi = s_phi;
+    k.s_1 = s_1;
+    k.las.on = c->laser_on;
+    k.las.pol = c->laser_pol;
+    k.las.env = c->laser_env;
+    k.las.q = D - 1;
+    k.las.omega = c->omega;
+    k.las.e_amp = c->e_amp;
+    k.las.ramp_t = c->omega > 0 ? c->ramp_periods * 2.0 * M_PI / c->omega : 1.0;
+    k.las.tau0 = c->fwhm > 0 ? c->fwhm / sqrt(2.0 * log(2.0)) : 1.0;
+    k.las.t_center = c->t_center;
+    k.las.waist = c->waist;
+    k.las.x_focus = c->x_focus;
+    k.las.y_c = c->y_c;
+    k.las.z_c = c->z_c;
+    k.las.cep = c->cep;
+    k.las.zr = 0.5 * c->omega * c->waist * c->waist;
+    k.pk.on = c->packet_on;
+    k.pk.dir = c->pk_dir;
+    k.pk.amp = c->pk_amp;
+    k.pk.k = c->pk_k;
+    k.pk.w = c->pk_w;
+    k.pk.x0 = c->pk_x0;
+    k.pk.y0 = c->pk_y0;
+    k.pk.z0 = c->pk_z0;
+    auto P = [&](long off) -> T * { return off < 0 ? nullptr : (T *)(base + off); };
+    k.state_base = base + L.off_arrays;
+    k.face_base = base + L.off_faces;
+    k.arr_stride = (long)L.arr_stride;
+    k.face_stride = (long)L.face_stride;
+    for (int s = 0; s < 2; s++)
+        for (int comp = 0; comp < 3; comp++) {
+            k.E0[s][comp] = P(L.off_em[0][s][comp]);
+            k.B0[s][comp] = P(L.off_em[1][s][comp]);
+            k.E1[s][comp] = P(L.off_em[2][s][comp]);
+            k.B1[s][comp] = P(L.off_em[3][s][comp]);
+        }
+    for (int s = 0; s < 3; s++) k.phi[s] = P(L.off_phi[s]);
+    for (int comp = 0; comp < 3; comp++) k.C[comp] = P(L.off_c[comp]);
+    for (int d = 0; d < 3; d++)
+        for (int side = 0; side < 2; side++) {
+            for (int s = 0; s < 3; s++) k.axg[d][side][s] = P(L.off_axg[d][side][s]);
+            for (int o = 0; o < 2; o++)
+                for (int comp = 0; comp < 3; comp++)
+                    for (int s = 0; s < 2; s++) k.murg[o][d][side][comp][s] = P(L.off_murg[o][d][side][comp][s]);
+        }
+    k.part = (double *)(base + L.off_part);
+    k.diag_blocks = L.diag_blocks;
+    k.rec = (axf_diag_record *)(base + L.off_rec);
+    k.rec_cap = L.rec_cap;
+}
+
+// Power-of-two scales of the stored first-order quantities: phi / s_phi and
+// E1, B1 / s_1.  The chain E0 -> phi -> E1 is linear, so scaling by powers of two
+// is exact and keeps the stored values of order one whatever g is.
+static void choose_scales(const axf_config *c, double *s_phi, double *s_1)
+{
+    double g = fabs(c->g);
+    if (!(g > 0.0)) { *s_phi = 1.0; *s_1 = 1.0; return; }
+    double pg = pow2_near(g);
+    *s_phi = c->packet_on ? 1.0 : pg;
+    *s_1 = *s_phi * pg;
+}
+
+// ------------------------------------------------------------------ stepping
+
+template <int D, typename T>
+static void convert_to_leapfrog(Run *R)
+{
+    using P = Plain<D, T>;
+    const RunK<T>& h = R->hk<T>();
+    const RunK<T> *rk = R->rk<T>();
+    hipStream_t st = R->stream;
+    P::copy_ghosts(rk, h, 0, 1, st);
+    P::c(rk, h, 0, 1, 0, 0, 0, 1, st);
+    P::e1(rk, h, 0, 0, 0, T(-0.5), st);
+    P::e0(rk, h, 0, 0, 0, T(-0.5), st);
+    R->converted = true;
+}
+
+// E^{n+1/2} into the new slot without advancing (for reads and diagnostics)
+template <int D, typename T>
+static void e_phase(Run *R)
+{
+    using P = Plain<D, T>;
+    const RunK<T>& h = R->hk<T>();
+    const RunK<T> *rk = R->rk<T>();
+    long s = R->step;
+    int so = (int)(s & 1), sn = so ^ 1, la = (int)(s % 3), lb = (int)((s + 1) % 3);
+    P::e0(rk, h, so, so, sn, T(1), R->stream);
+    P::c(rk, h, la, lb, so, sn, so, 0, R->stream);
+    P::e1(rk, h, so, so, sn, T(1), R->stream);
+}
+
+template <int D, typename T>
+static void steps_plain(Run *R, int64_t nsteps)
+{
+    using P = Plain<D, T>;
+    const RunK<T>& h = R->hk<T>();
+    const RunK<T> *rk = R->rk<T>();
+    hipStream_t st = R->stream;
+    for (int64_t it = 0; it < nsteps; it++) {
+        long s = R->step;
+        int so = (int)(s & 1), sn = so ^ 1, la = (int)(s % 3), lb = (int)((s + 1) % 3);
+        P::e0(rk, h, so, so, sn, T(1), st);
+        P::c(rk, h, la, lb, so, sn, so, 0, st);
+        P::e1(rk, h, so, so, sn, T(1), st);
+        P::mur(rk, h, s, st);
+        P::b(rk, h, s, st);
+        P::phi(rk, h, s, st);
+        if (R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0) {
+            P::diag(rk, h, s, R->rec_written % h.rec_cap, st);
+            R->rec_written++;
+        }
+        R->step++;
+        R->launches += 6;
+    }
+}
+
+// fused tile shapes per dimensionality and precision
+template <int D, typename T> struct FusedShape;
+template <> struct FusedShape<2, float> { using F = Fused<2, 256, 1, float>; static constexpr int chunk = 64; };
+template <> struct FusedShape<2, double> { using F = Fused<2, 128, 1, double>; static constexpr int chunk = 64; };
+template <> struct FusedShape<3, float> { using F = Fused<3, 32, 6, float>; static constexpr int chunk = 128; };
+template <> struct FusedShape<3, double> { using F = Fused<3, 32, 4, double>; static constexpr int chunk = 128; };
+
+template <int D, typename T>
+static int steps_fused(Run *R, int64_t nsteps)
+{
+    if constexpr (D == 1) {
+        return fail(AXF_EINVAL, "no fused kernel for 1D");
+    } else {
+        using F = typename FusedShape<D, T>::F;
+        const RunK<T>& h = R->hk<T>();
+        const RunK<T> *rk = R->rk<T>();
+        int chunk = R->chunk > 0 ? R->chunk : FusedShape<D, T>::chunk;
+        for (int64_t it = 0; it < nsteps; it++) {
+            long s = R->step;
+            hipError_t e = F::launch(rk, h, s, chunk, R->stream);
+            if (e != hipSuccess) return hip_fail(e, "fused step launch");
+            if (R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0) {
+                Plain<D, T>::diag(rk, h, s, R->rec_written % h.rec_cap, R->stream);
+                R->rec_written++;
+            }
+            R->step++;
+            R->launches += 1;
+        }
+        return AXF_OK;
+    }
+}
+
+// the fused kernel needs the axion to be periodic wherever the EM field is
+bool fused_supported(const axf_config *c)
+{
+    if (c->ndim < 2) return false;
+    for (int d = 0; d < c->ndim; d++)
+        if (c->em_bc[d] == AXF_EM_PERIODIC && c->ax_bc[d] != AXF_AX_PERIODIC) return false;
+    return true;
+}
+
+template <int D, typename T>
+static int run_steps(Run *R, int64_t nsteps, int *rc)
+{
+    if (!R->converted) convert_to_leapfrog<D, T>(R);
+    R->ephase_step = -1;
+    if (R->use_fused) *rc = steps_fused<D, T>(R, nsteps);
+    else steps_plain<D, T>(R, nsteps);
+    return *rc;
+}
+
+template <int D, typename T>
+static void diag_now_impl(Run *R)
+{
+    if (!R->converted) convert_to_leapfrog<D, T>(R);
+    e_phase<D, T>(R);
+    Plain<D, T>::diag(R->rk<T>(), R->hk<T>(), R->step, R->hk<T>().rec_cap, R->stream);
+}
+
+#define AXF_DISPATCH(R, FN, ...)                                                                     \
+    do {                                                                                             \
+        if ((R)->cfg.precision == AXF_F32) {                                                         \
+            switch ((R)->cfg.ndim) {                                                                 \
+            case 1: FN<1, float>(__VA_ARGS__); break;                                                \
+            case 2: FN<2, float>(__VA_ARGS__); break;                                                \
+            default: FN<3, float>(__VA_ARGS__); break;                                               \
+            }                                                                                        \
+        } else {                                                                                     \
+            switch ((R)->cfg.ndim) {                                                                 \
+            case 1: FN<1, double>(__VA_ARGS__); break;                                               \
+            case 2: FN<2, double>(__VA_ARGS__); break;                                               \
+            default: FN<3, double>(__VA_ARGS__); break;                                              \
+            }                                                                                        \
+        }                                                                                            \
+    } while (0)
+
+template <int D, typename T>
+static void init_state(Run *R)
+{
+    Plain<D, T>::init_phi(R->rk<T>(), R->hk<T>(), R->stream);
+    Plain<D, T>::mur_init(R->rk<T>(), R->hk<T>(), R->stream);
+}
+
+int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStream_t stream)
+{
+    R->cfg = *cfg;
+    R->L = make_layout(cfg);
+    if (bytes < R->L.total)
+        return fail(AXF_ENOMEM, "device buffer of %zu bytes < footprint %zu", bytes, R->L.total);
+    if (((uintptr_t)dev_buf & 255) != 0) return fail(AXF_EINVAL, "device buffer must be 256-byte aligned");
+    R->base = (char *)dev_buf;
+    R->stream = stream;
+    if (cfg->path == AXF_PATH_FUSED && !fused_supported(cfg))
+        return fail(AXF_EINVAL, "the fused path needs ndim >= 2 and a periodic axion on every periodic EM axis");
+    if (const char *ch = getenv("AXF_FUSED_CHUNK")) R->chunk = atoi(ch);
+    R->use_fused = cfg->path == AXF_PATH_FUSED || (cfg->path == AXF_PATH_AUTO && fused_supported(cfg) && auto_fused_enabled(cfg));
+    choose_scales(cfg, &R->s_phi, &R->s_1);
+    if (cfg->precision == AXF_F32) {
+        fill_runk<float>(R->hf, cfg, R->L, R->base, R->s_phi, R->s_1);
+    } else {
+        fill_runk<double>(R->hd, cfg, R->L, R->base, R->s_phi, R->s_1);
+    }
+    HIPCHK(hipMemsetAsync(R->base + R->L.off_state, 0, R->L.total - R->L.off_state, stream));
+    if (cfg->precision == AXF_F32)
+        HIPCHK(hipMemcpyAsync(R->base + R->L.off_rk, &R->hf, sizeof(RunK<float>), hipMemcpyHostToDevice, stream));
+    else
+        HIPCHK(hipMemcpyAsync(R->base + R->L.off_rk, &R->hd, sizeof(RunK<double>), hipMemcpyHostToDevice, stream));
+    AXF_DISPATCH(R, init_state, R);
+    HIPCHK(hipGetLastError());
+    // the descriptor copy reads host memory owned by R: finish it before returning
+    HIPCHK(hipStreamSynchronize(stream));
+    return AXF_OK;
+}
+
+int run_step(Run *R, int64_t nsteps)
+{
+    if (nsteps < 0) return fail(AXF_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return AXF_OK;
+    if (!R->ev0) {
+        HIPCHK(hipEventCreate(&R->ev0));
+        HIPCHK(hipEventCreate(&R->ev1));
+    }
+    int64_t l0 = R->launches;
+    int rc = AXF_OK;
+    HIPCHK(hipEventRecord(R->ev0, R->stream));
+    AXF_DISPATCH(R, run_steps, R, nsteps, &rc);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(R->ev1, R->stream));
+    HIPCHK(hipGetLastError());
+    R->timed_steps = nsteps;
+    R->timed_launches = R->launches - l0;
+    return AXF_OK;
+}
+
+// ------------------------------------------------------------ field I/O
+
+static int field_info(const Run *R, int id, int *kind, int *comp, double *scale)
+{
+    if (id < 0 || id >= AXF_NFIELDS) return fail(AXF_ENOTFOUND, "unknown field id %d", id);
+    if (id <= AXF_B1Z) {
+        *kind = id / 3;   // 0 E0, 1 B0, 2 E1, 3 B1
+        *comp = id % 3;
+        *scale = *kind >= 2 ? R->s_1 : 1.0;
+    } else {
+        *kind = 4;
+        *comp = id - AXF_PHI_OLD;
+        *scale = R->s_phi;
+    }
+    return AXF_OK;
+}
+
+static size_t dense_count(const Run *R) { return (size_t)R->L.nn[0] * R->L.nn[1] * R->L.nn[2]; }
+
+// device array (padded rows) -> dense host doubles
+static int fetch(const Run *R, const char *dev, std::vector<double>& out)
+{
+    const size_t es = elem_size(&R->cfg), nx = R->L.nn[0], rows = (size_t)R->L.nn[1] * R->L.nn[2];
+    std::vector<char> tmp(nx * rows * es);
+    HIPCHK(hipMemcpy2D(tmp.data(), nx * es, dev, R->L.px * es, nx * es, rows, hipMemcpyDeviceToHost));
+    out.resize(nx * rows);
+    if (es == 4) {
+        const float *f = (const float *)tmp.data();
+        for (size_t q = 0; q < out.size(); q++) out[q] = f[q];
+    } else {
+        memcpy(out.data(), tmp.data(), out.size() * 8);
+    }
+    return AXF_OK;
+}
+
+static const char *array_ptr(const Run *R, int kind, int comp, int slot)
+{
+    long off;
+    if (kind == 4) off = R->L.off_phi[slot];
+    else off = R->L.off_em[kind][slot][comp];
+    return off < 0 ? nullptr : R->base + off;
+}
+
+int run_read_field(Run *R, int id, void *dst, size_t dst_bytes, int dst_is_device)
+{
+    int kind, comp;
+    double scale;
+    int rc = field_info(R, id, &kind, &comp, &scale);
+    if (rc) return rc;
+    size_t cnt = dense_count(R);
+    if (dst_bytes < cnt * sizeof(double)) return fail(AXF_ENOMEM, "destination holds %zu bytes, need %zu", dst_bytes, cnt * 8);
+    std::vector<double> out(cnt, 0.0), tmp;
+    long s = R->step;
+    if (kind == 4) {
+        int slot = (int)((s + comp) % 3);
+        HIPCHK(hipStreamSynchronize(R->stream));
+        if ((rc = fetch(R, array_ptr(R, 4, 0, slot), out))) return rc;
+    } else if (array_ptr(R, kind, comp, 0)) {
+        bool is_e = (kind == 0 || kind == 2);
+        int so = (int)(s & 1), sn = so ^ 1;
+        if (is_e && R->converted && R->ephase_step != s) {
+            AXF_DISPATCH(R, e_phase, R);
+            R->ephase_step = s;
+        }
+        HIPCHK(hipStreamSynchronize(R->stream));
+        if ((rc = fetch(R, array_ptr(R, kind, comp, so), out))) return rc;
+        if (is_e && R->converted) {
+            if ((rc = fetch(R, array_ptr(R, kind, comp, sn), tmp))) return rc;
+            for (size_t q = 0; q < cnt; q++) out[q] = 0.5 * (out[q] + tmp[q]);
+        }
+    }
+    for (size_t q = 0; q < cnt; q++) out[q] *= scale;
+    if (dst_is_device) HIPCHK(hipMemcpy(dst, out.data(), cnt * 8, hipMemcpyHostToDevice));
+    else memcpy(dst, out.data(), cnt * 8);
+    return AXF_OK;
+}
+
+int run_write_field(Run *R, int id, const void *src, size_t src_bytes, int src_is_device)
+{
+    if (R->step != 0 || R->converted) return fail(AXF_ESTATE, "fields can only be written before the first step");
+    int kind, comp;
+    double scale;
+    int rc = field_info(R, id, &kind, &comp, &scale);
+    if (rc) return rc;
+    size_t cnt = dense_count(R);
+    if (src_bytes < cnt * sizeof(double)) return fail(AXF_ENOMEM, "source holds %zu bytes, need %zu", src_bytes, cnt * 8);
+    const char *dev = kind == 4 ? array_ptr(R, 4, 0, comp) : array_ptr(R, kind, comp, 0);
+    if (!dev) return fail(AXF_EINVAL, "field %d is not stored for ndim %d", id, R->cfg.ndim);
+    std::vector<double> in(cnt);
+    if (src_is_device) HIPCHK(hipMemcpy(in.data(), src, cnt * 8, hipMemcpyDeviceToHost));
+    else memcpy(in.data(), src, cnt * 8);
+    const size_t es = elem_size(&R->cfg), nx = R->L.nn[0], rows = cnt / nx;
+    std::vector<char> tmp(cnt * es);
+    for (size_t q = 0; q < cnt; q++) {
+        double v = in[q] / scale;
+        if (es == 4) ((float *)tmp.data())[q] = (float)v;
+        else ((double *)tmp.data())[q] = v;
+    }
+    HIPCHK(hipStreamSynchronize(R->stream));
+    HIPCHK(hipMemcpy2D((void *)dev, R->L.px * es, tmp.data(), nx * es, nx * es, rows, hipMemcpyHostToDevice));
+    return AXF_OK;
+}
+
+int run_diag_now(Run *R, axf_diag_record *out)
+{
+    AXF_DISPATCH(R, diag_now_impl, R);
+    R->ephase_step = R->step;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, R->base + R->L.off_rec + (size_t)R->L.rec_cap * sizeof(axf_diag_record),
+                          sizeof(axf_diag_record), hipMemcpyDeviceToHost, R->stream));
+    HIPCHK(hipStreamSynchronize(R->stream));
+    return AXF_OK;
+}
+
+int run_read_diag(Run *R, axf_diag_record *out, int max, int *n)
+{
+    HIPCHK(hipStreamSynchronize(R->stream));
+    int cap = R->L.rec_cap;
+    int64_t have = R->rec_written;
+    int64_t first = have > cap ? have - cap : 0;
+    std::vector<axf_diag_record> ring(cap);
+    HIPCHK(hipMemcpy(ring.data(), R->base + R->L.off_rec, (size_t)cap * sizeof(axf_diag_record), hipMemcpyDeviceToHost));
+    int cnt = 0;
+    for (int64_t q = first; q < have && cnt < max; q++) out[cnt++] = ring[q % cap];
+    *n = cnt;
+    R->rec_written = 0;
+    return AXF_OK;
+}
+
+// checkpoint: header + the raw state region
+struct StateHeader {
+    uint64_t magic;
+    int64_t step;
+    int64_t rec_written;
+    int32_t converted;
+    int32_t pad;
+    uint64_t region;
+};
+
+static const uint64_t kMagic = 0x61786673746174ULL;
+
+int run_state_bytes(const Run *R, size_t *bytes)
+{
+    *bytes = sizeof(StateHeader) + (R->L.total - R->L.off_state);
+    return AXF_OK;
+}
+
+int run_read_state(Run *R, void *buf, size_t bytes)
+{
+    size_t need;
+    run_state_bytes(R, &need);
+    if (bytes < need) return fail(AXF_ENOMEM, "state buffer of %zu bytes < %zu", bytes, need);
+    HIPCHK(hipStreamSynchronize(R->stream));
+    StateHeader h = {kMagic, R->step, R->rec_written, R->converted ? 1 : 0, 0, R->L.total - R->L.off_state};
+    memcpy(buf, &h, sizeof h);
+    HIPCHK(hipMemcpy((char *)buf + sizeof h, R->base + R->L.off_state, h.region, hipMemcpyDeviceToHost));
+    return AXF_OK;
+}
+
+int run_write_state(Run *R, const void *buf, size_t bytes)
+{
+    size_t need;
+    run_state_bytes(R, &need);
+    if (bytes < need) return fail(AXF_ENOMEM, "state buffer of %zu bytes < %zu", bytes, need);
+    StateHeader h;
+    memcpy(&h, buf, sizeof h);
+    if (h.magic != kMagic || h.region != R->L.total - R->L.off_state)
+        return fail(AXF_EINVAL, "state does not belong to a run of this configuration");
+    HIPCHK(hipStreamSynchronize(R->stream));
+    HIPCHK(hipMemcpy(R->base + R->L.off_state, (const char *)buf + sizeof h, h.region, hipMemcpyHostToDevice));
+    R->step = h.step;
+    R->rec_written = h.rec_written;
+    R->converted = h.converted != 0;
+    R->ephase_step = -1;
+    return AXF_OK;
+}
+
+}  // namespace axf
+
+// =================================================================== C ABI
+
+using namespace axf;
+
+struct axf_run : public axf::Run {};
+
+extern "C" {
+
+const char *axf_last_error(void) { return g_err.c_str(); }
+
+const char *axf_version(void) { return "axf 0.1 (gfx950)"; }
+
+int axf_footprint(const axf_config *cfg, size_t *bytes)
+{
+    if (!bytes) return fail(AXF_EINVAL, "null output");
+    int rc = validate(cfg);
+    if (rc) return rc;
+    *bytes = make_layout(cfg).total;
+    return AXF_OK;
+}
+
+int axf_extents(const axf_config *cfg, int32_t nn[3])
+{
+    int rc = validate(cfg);
+    if (rc) return rc;
+    Layout L = make_layout(cfg);
+    for (int d = 0; d < 3; d++) nn[d] = L.nn[d];
+    return AXF_OK;
+}
+
+int axf_create(const axf_config *cfg, void *dev_buf, size_t bytes, void *stream, axf_run **out)
+{
+    if (!out) return fail(AXF_EINVAL, "null output");
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (!dev_buf) return fail(AXF_EINVAL, "null device buffer");
+    axf_run *R = new (std::nothrow) axf_run();
+    if (!R) return fail(AXF_ENOMEM, "host allocation failed");
+    rc = run_init(R, cfg, dev_buf, bytes, (hipStream_t)stream);
+    if (rc) {
+        delete R;
+        return rc;
+    }
+    *out = R;
+    return AXF_OK;
+}
+
+int axf_write_field(axf_run *run, int32_t field_id, const void *src, size_t src_bytes, int32_t src_is_device)
+{
+    if (!run || !src) return fail(AXF_EINVAL, "null argument");
+    return run_write_field(run, field_id, src, src_bytes, src_is_device);
+}
+
+int axf_step(axf_run *run, int64_t nsteps)
+{
+    if (!run) return fail(AXF_EINVAL, "null run");
+    if (run->batch_owned) return fail(AXF_ESTATE, "runs of a batch advance through axf_batch_step");
+    return run_step(run, nsteps);
+}
+
+int axf_read_field(axf_run *run, int32_t field_id, void *dst, size_t dst_bytes, int32_t dst_is_device)
+{
+    if (!run || !dst) return fail(AXF_EINVAL, "null argument");
+    return run_read_field(run, field_id, dst, dst_bytes, dst_is_device);
+}
+
+int axf_diag_now(axf_run *run, axf_diag_record *out)
+{
+    if (!run || !out) return fail(AXF_EINVAL, "null argument");
+    return run_diag_now(run, out);
+}
+
+int axf_read_diag(axf_run *run, axf_diag_record *out, int32_t max, int32_t *n)
+{
+    if (!run || !out || !n || max < 0) return fail(AXF_EINVAL, "bad argument");
+    return run_read_diag(run, out, max, n);
+}
+
+int axf_state_bytes(const axf_run *run, size_t *bytes)
+{
+    if (!run || !bytes) return fail(AXF_EINVAL, "null argument");
+    return run_state_bytes(run, bytes);
+}
+
+int axf_read_state(axf_run *run, void *buf, size_t bytes)
+{
+    if (!run || !buf) return fail(AXF_EINVAL, "null argument");
+    return run_read_state(run, buf, bytes);
+}
+
+int axf_write_state(axf_run *run, const void *buf, size_t bytes)
+{
+    if (!run || !buf) return fail(AXF_EINVAL, "null argument");
+    return run_write_state(run, buf, bytes);
+}
+
+int axf_sync(axf_run *run)
+{
+    if (!run) return fail(AXF_EINVAL, "null run");
+    HIPCHK(hipStreamSynchronize(run->stream));
+    return AXF_OK;
+}
+
+int axf_steps_done(const axf_run *run, int64_t *steps)
+{
+    if (!run || !steps) return fail(AXF_EINVAL, "null argument");
+    *steps = run->step;
+    return AXF_OK;
+}
+
+int axf_last_step_timing(const axf_run *run, double *ms, int64_t *launches)
+{
+    if (!run || !ms || !launches) return fail(AXF_EINVAL, "null argument");
+    if (!run->ev0 || run->timed_steps == 0) return fail(AXF_ESTATE, "no timed step yet");
+    HIPCHK(hipEventSynchronize(run->ev1));
+    float f = 0.f;
+    HIPCHK(hipEventElapsedTime(&f, run->ev0, run->ev1));
+    *ms = f;
+    *launches = run->timed_launches;
+    return AXF_OK;
+}
+
+int axf_destroy(axf_run *run)
+{
+    if (!run) return AXF_OK;
+    if (run->batch_owned) return fail(AXF_ESTATE, "runs of a batch are released with the batch");
+    if (run->ev0) hipEventDestroy(run->ev0);
+    if (run->ev1) hipEventDestroy(run->ev1);
+    delete run;
+    return AXF_OK;
+}
+
+}  // extern "C"

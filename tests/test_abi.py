@@ -1,0 +1,65 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function declared in include/axf.h, and its pure host calls (footprint,
+extents, configuration checks) behave as documented."""
+import os
+import re
+
+import pytest
+
+from paper_2406_16796_amd import axf
+from paper_2406_16796_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "axf.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(axf_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 25
+    L = axf.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(axf.EXPORTS)
+
+
+def test_footprint_and_extents_follow_the_layout():
+    cfg = W.focused_3d(n=64)
+    nn = axf.extents(cfg)
+    assert nn == (65, 65, 65)               # Mur axes carry the extra node plane
+    f32 = axf.footprint(cfg, precision=axf.F32)
+    f64 = axf.footprint(cfg, precision=axf.F64)
+    assert 1.7 < f64 / f32 < 2.05
+    # 12 EM arrays x 2 time slots + 3 axion levels + 3 scratch, padded rows of 80 floats
+    arr = 80 * 65 * 65 * 4
+    assert f32 >= 30 * arr
+    one_d = W.plane_wave_1d(nx=1000)
+    assert axf.extents(one_d) == (1001, 1, 1)
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda c: c.update(dt=10.0), axf.EUNSTABLE),
+    (lambda c: c.update(ndim=4), axf.EINVAL),
+    (lambda c: c.update(laser_pol=2), axf.EINVAL),          # 2D keeps the in-plane polarisation
+    (lambda c: c.update(em_bc=[0, 1, 0]), axf.EINVAL),      # laser needs a Mur x_min face
+    (lambda c: c.update(pml_n=3000), axf.EINVAL),
+    (lambda c: c.update(n=[4096, 4096, 2]), axf.EINVAL),    # ndim 2 needs n_z = 1
+])
+def test_invalid_configurations_are_rejected(mutate, code):
+    cfg = W.gaussian_2d(n=256)
+    cfg["ndim"] = 2
+    mutate(cfg)
+    with pytest.raises(axf.AxfError) as e:
+        axf.footprint(cfg)
+    assert e.value.code == code
+
+
+def test_one_d_rejects_longitudinal_bext():
+    cfg = W.plane_wave_1d(nx=512)
+    cfg["bext"] = [0.5, 1.0, 0.0]
+    with pytest.raises(axf.AxfError) as e:
+        axf.footprint(cfg)
+    assert e.value.code == axf.EINVAL
