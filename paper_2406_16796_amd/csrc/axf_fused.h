@@ -16,4 +16,8 @@ struct Fused {
     static hipError_t launch(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st);
 };
 
+// Fused 2D step on wavefront-owned x segments (no LDS, no barriers).
+template <typename T>
+hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st);
+
 }  // namespace axf

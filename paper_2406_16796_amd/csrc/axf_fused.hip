@@ -15,6 +15,8 @@
 //   S6  phi^{n+3/2} at plane t-2                (+ axion ghosts of the new level)
 // The point formulas are the ones of the unfused kernels, written in the same
 // operation order, so the two paths agree bit for bit.
+#include <stdlib.h>
+
 #include "axf_fused.h"
 #include "axf_stencil.h"
 
@@ -50,6 +52,10 @@ struct KV {
     long sx, sy;
     T cdt[3], half, inv_dt, inv2dx[3], inv_dx2[3], dt2, m2, gax, cg1, out_r[3], bext[3], pml_sdt_max;
     int slab_lo, slab_hi, pml_n;
+    const double *inc;          // laser table on the x_min face (see RunK::inc)
+    long inc_face;
+    int inc_k1, las_on, las_pol;
+    double murc[3];
 
     __device__ __forceinline__ const T *arr(int q) const { return (const T *)(sb + q * as); }
     __device__ __forceinline__ T *warr(int q) const { return (T *)(sb + q * as); }
@@ -89,6 +95,13 @@ __device__ __forceinline__ KV<T> make_kv(const RunK<T> *__restrict__ rp)
     v.slab_lo = rp->slab_lo;
     v.slab_hi = rp->slab_hi;
     v.pml_n = rp->pml_n;
+    v.inc = rp->inc;
+    v.inc_face = rp->inc_face;
+    v.inc_k1 = rp->inc_k1;
+    v.las_on = rp->las.on;
+    v.las_pol = rp->las.pol;
+#pragma unroll
+    for (int d = 0; d < 3; d++) v.murc[d] = rp->murc[d];
     return v;
 }
 
@@ -325,26 +338,21 @@ __device__ __forceinline__ const T *addr_phi(const KV<T>& r, int L, int x, int y
 }
 
 // First-order Mur update of one tangential E ghost (FP64), the same formula as
-// the unfused path: out of line, it runs on boundary points only
+// the unfused path, with the laser values from the per-level table
 template <typename T>
-__device__ __noinline__ T mur_update(const RunK<T> *__restrict__ rp, int O, int c, int d, int side, double e_old, double e_new,
-                                     double g_old, int a0, int a1, int a2, long step)
+__device__ __forceinline__ T mur_update(const KV<T>& r, int O, int c, int d, int side, double e_old, double e_new,
+                                        double g_old, long fidx, long step)
 {
-    const RunK<T>& rk = *rp;
     double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
-    if (O == 0 && d == 0 && side == 0 && rk.las.on) {
-        double px = c == 0 ? a0 * rk.dx[0] : (a0 + 0.5) * rk.dx[0];
-        double py = c == 1 ? a1 * rk.dx[1] : (a1 + 0.5) * rk.dx[1];
-        double pz = c == 2 ? a2 * rk.dx[2] : (a2 + 0.5) * rk.dx[2];
-        double xg = -0.5 * rk.dx[0];
-        double t_o = (step - 0.5) * rk.dt, t_n = (step + 0.5) * rk.dt;
-        ia_o = incident(rk.las, c, px, py, pz, t_o);
-        ia_n = incident(rk.las, c, px, py, pz, t_n);
-        ig_o = incident(rk.las, c, xg, py, pz, t_o);
-        ig_n = incident(rk.las, c, xg, py, pz, t_n);
+    if (O == 0 && d == 0 && side == 0 && r.las_on && c == r.las_pol) {
+        const long lo = (step % r.inc_k1) * 2 * r.inc_face, ln = ((step + 1) % r.inc_k1) * 2 * r.inc_face;
+        ia_o = r.inc[lo + fidx];
+        ig_o = r.inc[lo + r.inc_face + fidx];
+        ia_n = r.inc[ln + fidx];
+        ig_n = r.inc[ln + r.inc_face + fidx];
     }
     double sa_o = e_old - ia_o, sa_n = e_new - ia_n, sg_o = g_old - ig_o;
-    double sg_n = sa_o + rk.murc[d] * (sa_n - sg_o);
+    double sg_n = sa_o + r.murc[d] * (sa_n - sg_o);
     return (T)(sg_n + ig_n);
 }
 
@@ -479,7 +487,7 @@ k_fused(const RunK<T> *__restrict__ rp, long step, int ntx, int nty, int nch, in
         const int i0 = M == 0 ? 0 : o0, i1 = M == 1 ? 0 : o1, i2 = M == 2 ? 0 : o2;
         double e_new = (double)(O == 0 ? w.at(S::bE0H(c), K::W2, pa, i0, i1, i2) : w.at(S::bE1H(c), K::W2, pa, i0, i1, i2));
         double g_old = (double)gld(r.face(q_mur(O, d, side, c, so)), fidx);
-        T val = mur_update<T>(rp, O, c, d, side, e_old, e_new, g_old, a0, a1, a2, step);
+        T val = mur_update<T>(r, O, c, d, side, e_old, e_new, g_old, fidx, step);
         if (write_hist) gst(r.wface(q_mur(O, d, side, c, sn)), fidx, val);
         return val;
     };
@@ -716,6 +724,374 @@ k_fused(const RunK<T> *__restrict__ rp, long step, int ntx, int nty, int nch, in
         }
     }
 }
+
+// ====================================================================== 2D
+// Fused 2D step without LDS or barriers: one wavefront owns 64 consecutive x
+// columns (59 outputs: 3 halo columns on the low side, 2 on the high side) and
+// marches along y through a chunk of rows.  x neighbours come from the
+// neighbouring lane (DPP wavefront shifts), y history stays in registers of the
+// own lane, so every value of a row is computed once per wavefront.  The point
+// formulas and their operation order are those of the unfused kernels.
+
+__device__ __forceinline__ float lane_up(float v)    // value of lane + 1 (0 in the last lane)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_dn(float v)    // value of lane - 1 (0 in lane 0)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_up(double v)
+{
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x130, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_dn(double v)
+{
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x138, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+constexpr int kWaveOut = 59;   // output columns per wavefront
+
+template <typename T, int MINW>
+__global__ void __launch_bounds__(256, MINW) k_wave2d(const RunK<T> *__restrict__ rp, long step, int nseg, int nch, int chunk)
+{
+    KV<T> r = make_kv(rp);
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (gw >= nseg * nch) return;      // whole wavefronts only: no barriers in this kernel
+    const int seg = gw % nseg, ch = gw / nseg;
+    const int so = (int)(step & 1), sn = so ^ 1;
+    const int la = (int)(step % 3), lb = (int)((step + 1) % 3), ln = (int)((step + 2) % 3);
+
+    const int x0 = seg * kWaveOut, gx = x0 - 3 + lane;
+    const int own_x_hi = min(x0 + kWaveOut, r.nn[0]);
+    const bool own_x = lane >= 3 && lane < 3 + kWaveOut && gx < own_x_hi;
+    const int c0 = ch * chunk, c1 = (ch == nch - 1) ? r.nn[1] : c0 + chunk;
+    const int n0 = r.n[0], n1 = r.n[1];
+    const bool mx = r.mur[0], my = r.mur[1];
+    // x validity of nodal / centred components at this lane, y validity per plane
+    const bool vx_nod = !mx || (gx >= 0 && gx < r.nn[0]);
+    const bool vx_cen = !mx || (gx >= 0 && gx < n0);
+    auto vy_nod = [&](int p) __attribute__((always_inline)) { return !my || (p >= 0 && p < r.nn[1]); };
+    auto vy_cen = [&](int p) __attribute__((always_inline)) { return !my || (p >= 0 && p < n1); };
+    auto own_plane = [&](int p) __attribute__((always_inline)) { return p >= c0 && p < c1; };
+    const int wx = mx ? gx : wrap1(gx, n0);
+    auto gidx = [&](int p) __attribute__((always_inline)) { return (long)wx + (long)(my ? p : wrap1(p, n1)) * r.sx; };
+
+    // register windows along y (suffix = planes behind the newest loaded plane t)
+    T b0z_2 = 0, b0z_1 = 0, b0z_0 = 0;
+    T pa_3 = 0, pa_2 = 0, pa_1 = 0, pb_3 = 0, pb_2 = 0, pb_1 = 0;
+    T b1_2[3] = {0, 0, 0}, b1_1[3] = {0, 0, 0};
+    T e0h_2[2] = {0, 0}, e0h_1[2] = {0, 0}, e0n_2[2] = {0, 0}, e0n_1[2] = {0, 0};
+    T c_3[3] = {0, 0, 0}, c_2[3] = {0, 0, 0};
+    T b0p_2 = 0, b0p_1 = 0;
+    T e1h_3[3] = {0, 0, 0}, e1h_2[3] = {0, 0, 0};
+    // prefetch (raw values + mask), consumed one iteration later
+    T f_b0z, f_b1[3], f_pa, f_pb, f_e0m[2], f_e1m[3];
+    unsigned f_mask = 0;
+    auto prefetch = [&](int t) __attribute__((always_inline)) {
+        bool ok;
+        unsigned m = 0;
+        const T *q = addr_em<2>(r, r.arr(q_em(1, so, 2)), 3u, gx, t, 0, ok);
+        f_b0z = gld(q, 0);
+        m |= ok ? 1u : 0u;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            q = addr_em<2>(r, r.arr(q_em(3, so, c)), 7u & ~(1u << c), gx, t - 1, 0, ok);
+            f_b1[c] = gld(q, 0);
+            m |= ok ? 2u << c : 0u;
+        }
+        q = addr_phi<2>(r, la, gx, t - 1, 0, ok);
+        f_pa = gld(q, 0);
+        m |= ok ? 16u : 0u;
+        q = addr_phi<2>(r, lb, gx, t - 1, 0, ok);
+        f_pb = gld(q, 0);
+        m |= ok ? 32u : 0u;
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            q = addr_em<2>(r, r.arr(q_em(0, so, c)), 1u << c, gx, t - 1, 0, ok);
+            f_e0m[c] = gld(q, 0);
+            m |= ok ? 64u << c : 0u;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            q = addr_em<2>(r, r.arr(q_em(2, so, c)), 1u << c, gx, t - 2, 0, ok);
+            f_e1m[c] = gld(q, 0);
+            m |= ok ? 256u << c : 0u;
+        }
+        f_mask = m;
+    };
+    auto sel = [&](T v, unsigned bit) __attribute__((always_inline)) { return (f_mask & bit) ? v : T(0); };
+
+    // Mur ghost of E_c (order O) of this lane at plane pg from the adjacent
+    // interior point (x offset ox, plane pa) whose E^{n+1/2} is e_new
+    auto ghost = [&](int O, int c, int d, int side, int pg, int ox, int pa, T e_new, bool owner) __attribute__((always_inline)) -> T {
+        int a0 = gx + ox, a1 = pa;
+        if (!mx) a0 = wrap1(a0, n0);
+        if (!my) a1 = wrap1(a1, n1);
+        long fidx = face_index(r, d, a0, a1, 0);
+        double e_old = (double)gld(r.arr(q_em(O == 0 ? 0 : 2, so, c)), (long)a0 + (long)a1 * r.sx);
+        double g_old = (double)gld(r.face(q_mur(O, d, side, c, so)), fidx);
+        T val = mur_update<T>(r, O, c, d, side, e_old, (double)e_new, g_old, fidx, step);
+        if (owner) gst(r.wface(q_mur(O, d, side, c, sn)), fidx, val);
+        return val;
+    };
+
+    const int t_first = c0 - 2, t_last = c1 + 1;
+    prefetch(t_first);
+    for (int t = t_first; t <= t_last; t++) {
+        // rotate the windows and take in the prefetched planes
+        b0z_2 = b0z_1; b0z_1 = b0z_0; b0z_0 = sel(f_b0z, 1u);
+        pa_3 = pa_2; pa_2 = pa_1; pa_1 = sel(f_pa, 16u);
+        pb_3 = pb_2; pb_2 = pb_1; pb_1 = sel(f_pb, 32u);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            b1_2[c] = b1_1[c];
+            b1_1[c] = sel(f_b1[c], 2u << c);
+            c_3[c] = c_2[c];
+            e1h_3[c] = e1h_2[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            e0h_2[c] = e0h_1[c];
+            e0n_2[c] = e0n_1[c];
+        }
+        b0p_2 = b0p_1;
+        T e0m[2] = {sel(f_e0m[0], 64u), sel(f_e0m[1], 128u)};
+        T e1m[3] = {sel(f_e1m[0], 256u), sel(f_e1m[1], 512u), sel(f_e1m[2], 1024u)};
+        if (t < t_last) prefetch(t + 1);
+
+        const int p1 = t - 1, p2 = t - 2;
+        // ---- S1: E0^{n+1/2}, E0^n at plane p1 (E0x nodal in x, E0y nodal in y)
+        {
+            const T up_b0z = lane_up(b0z_1);
+            T eh[2] = {T(0), T(0)}, en[2] = {T(0), T(0)};
+            if (vx_nod && vy_cen(p1)) {
+                T a = r.cdt[1] * (b0z_0 - b0z_1), b = T(0);
+                T rhs = a - b;
+                eh[0] = e0m[0] + T(1) * rhs;
+                en[0] = r.half * (e0m[0] + eh[0]);
+            }
+            if (vx_cen && vy_nod(p1)) {
+                T a = T(0), b = r.cdt[0] * (up_b0z - b0z_1);
+                T rhs = a - b;
+                eh[1] = e0m[1] + T(1) * rhs;
+                en[1] = r.half * (e0m[1] + eh[1]);
+            }
+            e0h_1[0] = eh[0]; e0h_1[1] = eh[1];
+            e0n_1[0] = en[0]; e0n_1[1] = en[1];
+            const bool own = own_x && own_plane(p1);
+            if (own && vx_nod && vy_cen(p1)) gst(r.warr(q_em(0, sn, 0)), gidx(p1), eh[0]);
+            if (own && vx_cen && vy_nod(p1)) gst(r.warr(q_em(0, sn, 1)), gidx(p1), eh[1]);
+            // Mur ghosts of E0y across x (E0y centred in x)
+            const T up_e = lane_up(e0h_1[1]), dn_e = lane_dn(e0h_1[1]);
+            if (mx && (gx == -1 || gx == n0) && vy_nod(p1)) {
+                const int side = gx == -1 ? 0 : 1, ox = side ? -1 : 1;
+                const bool owner = own_plane(p1) && lane + ox >= 3 && lane + ox < 3 + kWaveOut && gx + ox < own_x_hi;
+                e0h_1[1] = ghost(0, 1, 0, side, p1, ox, p1, side ? dn_e : up_e, owner);
+            }
+            // Mur ghosts of E0x across y (E0x centred in y): plane -1 from plane 0, plane n1 from n1 - 1
+            if (my && vx_nod) {
+                if (p1 == 0) e0h_2[0] = ghost(0, 0, 1, 0, -1, 0, 0, e0h_1[0], own_x && own_plane(0));
+                else if (p1 == n1) e0h_1[0] = ghost(0, 0, 1, 1, n1, 0, n1 - 1, e0h_2[0], own_x && own_plane(n1 - 1));
+            }
+        }
+        // ---- S2: C^n at the centres of plane p2
+        {
+            T e[3], bb[3], gp[3];
+            const T up_en0 = lane_up(e0n_2[0]);
+            const T up_b2 = lane_up(b0z_2), up_b1 = lane_up(b0z_1);
+            const T up_pa = lane_up(pa_2), up_pb = lane_up(pb_2), dn_pa = lane_dn(pa_2), dn_pb = lane_dn(pb_2);
+            T C0 = T(0), C1 = T(0), C2 = T(0);
+            if (vx_cen && vy_cen(p2)) {
+                const int cxg = wrap1(gx, n0);
+                e[0] = r.half * (e0n_2[0] + up_en0);
+                e[1] = r.half * (e0n_2[1] + e0n_1[1]);
+                e[2] = T(0);
+                bb[0] = T(0) + bext_at(r, 0, cxg);
+                bb[1] = T(0) + bext_at(r, 1, cxg);
+                bb[2] = T(0.25) * ((b0z_2 + up_b2) + (b0z_1 + up_b1)) + bext_at(r, 2, cxg);
+                T dtphi = (pb_2 - pa_2) * r.inv_dt;
+                {
+                    T up = r.half * (up_pa + up_pb), dn = r.half * (dn_pa + dn_pb);
+                    gp[0] = (up - dn) * r.inv2dx[0];
+                }
+                {
+                    T up = r.half * (pa_1 + pb_1), dn = r.half * (pa_3 + pb_3);
+                    gp[1] = (up - dn) * r.inv2dx[1];
+                }
+                gp[2] = T(0);
+                C0 = dtphi * bb[0] - (e[1] * gp[2] - e[2] * gp[1]);
+                C1 = dtphi * bb[1] - (e[2] * gp[0] - e[0] * gp[2]);
+                C2 = dtphi * bb[2] - (e[0] * gp[1] - e[1] * gp[0]);
+            }
+            c_2[0] = C0; c_2[1] = C1; c_2[2] = C2;
+        }
+        // ---- S3: B0z^{n+1} at plane p1
+        {
+            const T dn_e0y = lane_dn(e0h_1[1]);
+            T v = T(0);
+            if (vx_nod && vy_nod(p1)) {
+                T a = r.cdt[0] * (e0h_1[1] - dn_e0y), b = r.cdt[1] * (e0h_1[0] - e0h_2[0]);
+                v = b0z_1 - (a - b);
+                if (own_x && own_plane(p1)) gst(r.warr(q_em(1, sn, 2)), gidx(p1), v);
+            }
+            b0p_1 = v;
+        }
+        // ---- S4: E1^{n+1/2} at plane p2
+        {
+            const T up_b1z = lane_up(b1_2[2]), up_b1y = lane_up(b1_2[1]);
+            const T dn_cx = lane_dn(c_2[0]);
+            T v[3] = {T(0), T(0), T(0)};
+            const bool own = own_x && own_plane(p2);
+            // E1x: nodal x, centred y
+            if (vx_nod && vy_cen(p2)) {
+                T lo = (mx && gx - 1 < 0) ? c_2[0] : dn_cx;
+                T hi = (mx && gx > n0 - 1) ? dn_cx : c_2[0];
+                T Sc = r.half * (lo + hi);
+                T a = r.cdt[1] * (b1_1[2] - b1_2[2]), b = T(0);
+                T rhs = (a - b) - r.cg1 * Sc;
+                v[0] = e1m[0] + T(1) * rhs;
+                if (own) gst(r.warr(q_em(2, sn, 0)), gidx(p2), v[0]);
+            }
+            // E1y: centred x, nodal y
+            if (vx_cen && vy_nod(p2)) {
+                T lo = (my && p2 - 1 < 0) ? c_2[1] : c_3[1];
+                T hi = (my && p2 > n1 - 1) ? c_3[1] : c_2[1];
+                T Sc = r.half * (lo + hi);
+                T a = T(0), b = r.cdt[0] * (up_b1z - b1_2[2]);
+                T rhs = (a - b) - r.cg1 * Sc;
+                v[1] = e1m[1] + T(1) * rhs;
+                if (own) gst(r.warr(q_em(2, sn, 1)), gidx(p2), v[1]);
+            }
+            // E1z: centred x, centred y
+            if (vx_cen && vy_cen(p2)) {
+                T Sc = c_2[2];
+                T a = r.cdt[0] * (up_b1y - b1_2[1]), b = r.cdt[1] * (b1_1[0] - b1_2[0]);
+                T rhs = (a - b) - r.cg1 * Sc;
+                v[2] = e1m[2] + T(1) * rhs;
+                if (own) gst(r.warr(q_em(2, sn, 2)), gidx(p2), v[2]);
+            }
+            e1h_2[0] = v[0]; e1h_2[1] = v[1]; e1h_2[2] = v[2];
+            // Mur ghosts of E1y, E1z across x; of E1x, E1z across y
+            const T up_y = lane_up(e1h_2[1]), dn_y = lane_dn(e1h_2[1]);
+            const T up_z = lane_up(e1h_2[2]), dn_z = lane_dn(e1h_2[2]);
+            if (mx && (gx == -1 || gx == n0)) {
+                const int side = gx == -1 ? 0 : 1, ox = side ? -1 : 1;
+                const bool owner = own_plane(p2) && lane + ox >= 3 && lane + ox < 3 + kWaveOut && gx + ox < own_x_hi;
+                if (vy_nod(p2)) e1h_2[1] = ghost(1, 1, 0, side, p2, ox, p2, side ? dn_y : up_y, owner);
+                if (vy_cen(p2)) e1h_2[2] = ghost(1, 2, 0, side, p2, ox, p2, side ? dn_z : up_z, owner);
+            }
+            if (my) {
+                if (p2 == 0) {
+                    if (vx_nod) e1h_3[0] = ghost(1, 0, 1, 0, -1, 0, 0, e1h_2[0], own_x && own_plane(0));
+                    if (vx_cen) e1h_3[2] = ghost(1, 2, 1, 0, -1, 0, 0, e1h_2[2], own_x && own_plane(0));
+                } else if (p2 == n1) {
+                    if (vx_nod) e1h_2[0] = ghost(1, 0, 1, 1, n1, 0, n1 - 1, e1h_3[0], own_x && own_plane(n1 - 1));
+                    if (vx_cen) e1h_2[2] = ghost(1, 2, 1, 1, n1, 0, n1 - 1, e1h_3[2], own_x && own_plane(n1 - 1));
+                }
+            }
+        }
+        // ---- S5: B1^{n+1} and S6: phi^{n+3/2} at plane p2
+        {
+            const T dn_e1z = lane_dn(e1h_2[2]), dn_e1y = lane_dn(e1h_2[1]);
+            const T up_e0x = lane_up(e0h_2[0]);
+            const T up_b2 = lane_up(b0z_2), up_b1 = lane_up(b0z_1);
+            const T up_p2 = lane_up(b0p_2), up_p1 = lane_up(b0p_1);
+            const T up_pb = lane_up(pb_2), dn_pb = lane_dn(pb_2);
+            if (own_x && own_plane(p2)) {
+                const long gi2 = gidx(p2);
+                // B1x: centred x, nodal y
+                if (vx_cen && vy_nod(p2)) {
+                    T a = r.cdt[1] * (e1h_2[2] - e1h_3[2]), b = T(0);
+                    gst(r.warr(q_em(3, sn, 0)), gi2, b1_2[0] - (a - b));
+                }
+                // B1y: nodal x, centred y
+                if (vx_nod && vy_cen(p2)) {
+                    T a = T(0), b = r.cdt[0] * (e1h_2[2] - dn_e1z);
+                    gst(r.warr(q_em(3, sn, 1)), gi2, b1_2[1] - (a - b));
+                }
+                // B1z: nodal x, nodal y
+                if (vx_nod && vy_nod(p2)) {
+                    T a = r.cdt[0] * (e1h_2[1] - dn_e1y), b = r.cdt[1] * (e1h_2[0] - e1h_3[0]);
+                    gst(r.warr(q_em(3, sn, 2)), gi2, b1_2[2] - (a - b));
+                }
+                if (vx_cen && vy_cen(p2)) {
+                    const int gi = wrap1(gx, n0), gj = my ? p2 : wrap1(p2, n1);
+                    T e[3], bb[3];
+                    e[0] = r.half * (e0h_2[0] + up_e0x);
+                    e[1] = r.half * (e0h_2[1] + e0h_1[1]);
+                    e[2] = T(0);
+                    T bo0 = T(0), bn0 = T(0), bo1 = T(0), bn1 = T(0);
+                    T bo2 = T(0.25) * ((b0z_2 + up_b2) + (b0z_1 + up_b1));
+                    T bn2 = T(0.25) * ((b0p_2 + up_p2) + (b0p_1 + up_p1));
+                    bb[0] = r.half * (bo0 + bn0) + bext_at(r, 0, gi);
+                    bb[1] = r.half * (bo1 + bn1) + bext_at(r, 1, gi);
+                    bb[2] = r.half * (bo2 + bn2) + bext_at(r, 2, gi);
+                    T sax = r.gax * (e[0] * bb[0] + e[1] * bb[1] + e[2] * bb[2]);
+                    T pa = pa_2, pb = pb_2;
+                    T lap = T(0);
+                    lap += ((up_pb - T(2) * pb) + dn_pb) * r.inv_dx2[0];
+                    lap += ((pb_1 - T(2) * pb) + pb_3) * r.inv_dx2[1];
+                    T sdt = pml_sdt<2>(r, gi, gj, 0);
+                    T x = r.dt2 * ((sax - r.m2 * pb) + lap) - sdt * sdt * pb;
+                    T pn = (((x + sdt * pa) + T(2) * pb) - pa) / (T(1) + sdt);
+                    gst(r.warr(q_phi(ln)), gi2, pn);
+                    const int gv[2] = {gi, gj};
+#pragma unroll
+                    for (int d = 0; d < 2; d++) {
+                        if (r.axbc[d] == AXF_AX_PERIODIC) continue;
+#pragma unroll
+                        for (int side = 0; side < 2; side++) {
+                            if (gv[d] != (side ? r.n[d] - 1 : 0)) continue;
+                            long f = face_index(r, d, gi, gj, 0);
+                            T gval;
+                            if (r.axbc[d] == AXF_AX_OUTFLOW) {
+                                T gbv = gld(r.face(q_axg(d, side, lb)), f), gav = gld(r.face(q_axg(d, side, la)), f), rr = r.out_r[d];
+                                T xx = (((T(-2) * gbv + T(2) * gav) - r.dt2 * (sax - r.m2 * gbv)) + rr * pb - rr * rr * (pb - T(2) * gbv))
+                                       / (rr + rr * rr);
+                                gval = gav + rr * (pb - xx);
+                            } else {
+                                gval = pn;
+                            }
+                            gst(r.wface(q_axg(d, side, ln)), f, gval);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st)
+{
+    int nseg = (h.nn[0] + kWaveOut - 1) / kWaveOut;
+    int nch = (h.nn[1] + chunk - 1) / chunk;
+    long waves = (long)nseg * nch;
+    unsigned nb = (unsigned)((waves + 3) / 4);
+    static int occ = -1;
+    if (occ < 0) {
+        const char *e = getenv("AXF_WAVE_OCC");
+        occ = e ? atoi(e) : 3;
+    }
+    if (occ >= 4)
+        hipLaunchKernelGGL((k_wave2d<T, 4>), dim3(nb), dim3(256), 0, st, rk, step, nseg, nch, chunk);
+    else if (occ == 2)
+        hipLaunchKernelGGL((k_wave2d<T, 2>), dim3(nb), dim3(256), 0, st, rk, step, nseg, nch, chunk);
+    else
+        hipLaunchKernelGGL((k_wave2d<T, 3>), dim3(nb), dim3(256), 0, st, rk, step, nseg, nch, chunk);
+    return hipGetLastError();
+}
+
+template hipError_t launch_wave2d<float>(const RunK<float> *, const RunK<float>&, long, int, hipStream_t);
+template hipError_t launch_wave2d<double>(const RunK<double> *, const RunK<double>&, long, int, hipStream_t);
 
 template <int D, int TX, int TY, typename T>
 size_t Fused<D, TX, TY, T>::lds_bytes() { return FK<D, TX, TY, T>::LDS; }

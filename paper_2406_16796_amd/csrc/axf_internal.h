@@ -39,6 +39,7 @@ constexpr int kNumArrays = 30;
 __host__ __device__ constexpr int q_axg(int d, int side, int slot) { return (d * 2 + side) * 3 + slot; }
 __host__ __device__ constexpr int q_mur(int o, int d, int side, int comp, int slot) { return 18 + (((o * 3 + d) * 2 + side) * 3 + comp) * 2 + slot; }
 constexpr int kNumFaces = 90;
+constexpr int kIncLevels = 17;   // time levels per laser table fill (16 steps)
 
 // Immutable per-run descriptor, stored in device memory once at creation.
 // Time-level slots rotate with the step counter: E/B buffers and Mur ghosts by
@@ -71,6 +72,11 @@ struct RunK {
     T *C[3];                  // scratch: axion current at centres (plain path)
     T *axg[3][2][3];          // axion ghosts [axis][side][slot]
     T *murg[2][3][2][3][2];   // Mur ghosts [order][axis][side][component][slot]
+    // incident laser field on the x_min face, tabulated per time level L
+    // (t = (L - 1/2) dt) in slot L mod inc_k1: [slot][0 adjacent centre, 1 ghost][face point]
+    double *inc;
+    int inc_k1;
+    long inc_face;
     // diagnostics
     double *part;             // per-block partial sums, 4 per block
     int diag_blocks;

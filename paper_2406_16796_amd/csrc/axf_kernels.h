@@ -13,6 +13,7 @@ struct Plain {
     static void e1(const RunK<T> *rk, const RunK<T>& h, int s_in, int s_b, int s_out, T scale, hipStream_t st);
     static void mur(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
     static void mur_init(const RunK<T> *rk, const RunK<T>& h, hipStream_t st);
+    static void inc_fill(const RunK<T> *rk, const RunK<T>& h, long L0, int nlev, hipStream_t st);
     static void b(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
     static void phi(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
     static void init_phi(const RunK<T> *rk, const RunK<T>& h, hipStream_t st);

@@ -150,16 +150,12 @@ __device__ __forceinline__ void mur_point(const RunK<T>& r, long step, int d, in
     double e_old = (double)Eo[c][id], e_new = (double)En[c][id];
     double g_old = (double)r.murg[O][d][side][c][s_old][f];
     double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
-    if (O == 0 && d == 0 && side == 0 && r.las.on) {
-        double pos[3];
-        for (int e = 0; e < 3; e++)
-            pos[e] = (e == c) ? id3[e] * r.dx[e] : (id3[e] + 0.5) * r.dx[e];
-        double xg = -0.5 * r.dx[0];
-        double t_o = (step - 0.5) * r.dt, t_n = (step + 0.5) * r.dt;
-        ia_o = incident(r.las, c, pos[0], pos[1], pos[2], t_o);
-        ia_n = incident(r.las, c, pos[0], pos[1], pos[2], t_n);
-        ig_o = incident(r.las, c, xg, pos[1], pos[2], t_o);
-        ig_n = incident(r.las, c, xg, pos[1], pos[2], t_n);
+    if (O == 0 && d == 0 && side == 0 && r.las.on && c == r.las.pol) {
+        const long lo = (step % r.inc_k1) * 2 * r.inc_face, ln = ((step + 1) % r.inc_k1) * 2 * r.inc_face;
+        ia_o = r.inc[lo + f];
+        ig_o = r.inc[lo + r.inc_face + f];
+        ia_n = r.inc[ln + f];
+        ig_n = r.inc[ln + r.inc_face + f];
     }
     double sa_o = e_old - ia_o, sa_n = e_new - ia_n, sg_o = g_old - ig_o;
     double sg_n = sa_o + r.murc[d] * (sa_n - sg_o);
@@ -182,6 +178,27 @@ __global__ void __launch_bounds__(256) k_mur(const RunK<T> *__restrict__ rp, lon
         int c = q == 0 ? a : b;
         mur_point<D, 0>(r, step, d, side, c, ia, ib);
         mur_point<D, 1>(r, step, d, side, c, ia, ib);
+    }
+}
+
+// laser field at the x_min face for time levels L0 .. L0 + nlev - 1 (t = (L - 1/2) dt),
+// at the first interior centre and at the ghost centre, into slot L mod inc_k1
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_inc_fill(const RunK<T> *__restrict__ rp, long L0, int nlev)
+{
+    const RunK<T>& r = *rp;
+    long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (p >= r.inc_face) return;
+    const int c = r.las.pol;
+    int j = (int)(p % r.nn[1]), k = (int)(p / r.nn[1]);
+    double y = (c == 1) ? j * r.dx[1] : (j + 0.5) * r.dx[1];
+    double z = (c == 2) ? k * r.dx[2] : (k + 0.5) * r.dx[2];
+    for (int q = 0; q < nlev; q++) {
+        long L = L0 + q;
+        double t = (L - 0.5) * r.dt;
+        long base = (L % r.inc_k1) * 2 * r.inc_face;
+        r.inc[base + p] = incident(r.las, c, 0.5 * r.dx[0], y, z, t);
+        r.inc[base + r.inc_face + p] = incident(r.las, c, -0.5 * r.dx[0], y, z, t);
     }
 }
 
@@ -509,6 +526,12 @@ void Plain<D, T>::mur_init(const RunK<T> *rk, const RunK<T>& h, hipStream_t st)
     }
     if (face == 0) return;
     hipLaunchKernelGGL((k_mur_init<D, T>), dim3(nblocks(face, 256), 2 * D), dim3(256), 0, st, rk);
+}
+
+template <int D, typename T>
+void Plain<D, T>::inc_fill(const RunK<T> *rk, const RunK<T>& h, long L0, int nlev, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_inc_fill<D, T>), dim3(nblocks(h.inc_face, 256)), dim3(256), 0, st, rk, L0, nlev);
 }
 
 template <int D, typename T>

@@ -26,6 +26,7 @@ struct Layout {
     size_t off_part;
     int rec_cap;
     size_t off_rec;
+    long inc_face, off_inc;
     size_t total;
 };
 
@@ -47,6 +48,8 @@ struct Run {
     bool batch_owned = false;
     bool use_fused = false;
     int chunk = 0;                 // fused planes per workgroup (0: default)
+    bool lds_march = false;
+    long inc_lo = -1;               // first time level held by the laser table        // 2D: use the LDS-marching kernel instead of the wavefront one
 
     template <typename T> const RunK<T>& hk() const;
     template <typename T> const RunK<T> *rk() const { return (const RunK<T> *)(base + L.off_rk); }

@@ -47,13 +47,14 @@ int hip_fail(hipError_t e, const char *what)
 
 // ------------------------------------------------------------ validation
 
-// AUTO picks the fused kernel only where it beats the unfused sequence
-// (AXF_AUTO_FUSED=1 forces it wherever supported)
+// AUTO picks the fused kernel only where it beats the unfused sequence: the
+// 2D wavefront kernel does; in 1D and 3D the unfused phases are faster.
+// AXF_AUTO_FUSED=1/0 forces the choice wherever the fused kernel is supported.
 static bool auto_fused_enabled(const axf_config *c)
 {
     const char *e = getenv("AXF_AUTO_FUSED");
     if (e) return e[0] == '1';
-    return false;
+    return c->ndim == 2;
 }
 
 static double pow2_near(double v) { return ldexp(1.0, (int)lround(log2(v))); }
@@ -162,6 +163,8 @@ Layout make_layout(const axf_config *c)
     L.off_part = take((size_t)L.diag_blocks * 4 * sizeof(double));
     L.rec_cap = 4096;
     L.off_rec = take((size_t)(L.rec_cap + 1) * sizeof(axf_diag_record));
+    L.inc_face = (long)L.nn[1] * L.nn[2];
+    L.off_inc = c->laser_on ? (long)take((size_t)kIncLevels * 2 * L.inc_face * sizeof(double)) : -1;
     L.total = off;
     return L;
 }
@@ -251,6 +254,9 @@ static void fill_runk(RunK<T>& k, const axf_config *c, const Layout& L, char *ba
     k.diag_blocks = L.diag_blocks;
     k.rec = (axf_diag_record *)(base + L.off_rec);
     k.rec_cap = L.rec_cap;
+    k.inc = L.off_inc < 0 ? nullptr : (double *)(base + L.off_inc);
+    k.inc_k1 = kIncLevels;
+    k.inc_face = L.inc_face;
 }
 
 // Power-of-two scales of the stored first-order quantities: phi / s_phi and
@@ -295,6 +301,16 @@ static void e_phase(Run *R)
     P::e1(rk, h, so, so, sn, T(1), R->stream);
 }
 
+// keep the laser table covering time levels s and s + 1 of step s
+template <int D, typename T>
+static void ensure_incident(Run *R, long s)
+{
+    if (!R->cfg.laser_on) return;
+    if (R->inc_lo >= 0 && s >= R->inc_lo && s + 1 < R->inc_lo + kIncLevels) return;
+    Plain<D, T>::inc_fill(R->rk<T>(), R->hk<T>(), s, kIncLevels, R->stream);
+    R->inc_lo = s;
+}
+
 template <int D, typename T>
 static void steps_plain(Run *R, int64_t nsteps)
 {
@@ -305,6 +321,7 @@ static void steps_plain(Run *R, int64_t nsteps)
     for (int64_t it = 0; it < nsteps; it++) {
         long s = R->step;
         int so = (int)(s & 1), sn = so ^ 1, la = (int)(s % 3), lb = (int)((s + 1) % 3);
+        ensure_incident<D, T>(R, s);
         P::e0(rk, h, so, so, sn, T(1), st);
         P::c(rk, h, la, lb, so, sn, so, 0, st);
         P::e1(rk, h, so, so, sn, T(1), st);
@@ -337,9 +354,12 @@ static int steps_fused(Run *R, int64_t nsteps)
         const RunK<T>& h = R->hk<T>();
         const RunK<T> *rk = R->rk<T>();
         int chunk = R->chunk > 0 ? R->chunk : FusedShape<D, T>::chunk;
+        const bool wave2d = D == 2 && !R->lds_march;
+        if (wave2d && R->chunk <= 0) chunk = 32;
         for (int64_t it = 0; it < nsteps; it++) {
             long s = R->step;
-            hipError_t e = F::launch(rk, h, s, chunk, R->stream);
+            ensure_incident<D, T>(R, s);
+            hipError_t e = wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->stream) : F::launch(rk, h, s, chunk, R->stream);
             if (e != hipSuccess) return hip_fail(e, "fused step launch");
             if (R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0) {
                 Plain<D, T>::diag(rk, h, s, R->rec_written % h.rec_cap, R->stream);
@@ -415,6 +435,7 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     if (cfg->path == AXF_PATH_FUSED && !fused_supported(cfg))
         return fail(AXF_EINVAL, "the fused path needs ndim >= 2 and a periodic axion on every periodic EM axis");
     if (const char *ch = getenv("AXF_FUSED_CHUNK")) R->chunk = atoi(ch);
+    if (const char *lm = getenv("AXF_LDS_MARCH")) R->lds_march = lm[0] == '1';
     R->use_fused = cfg->path == AXF_PATH_FUSED || (cfg->path == AXF_PATH_AUTO && fused_supported(cfg) && auto_fused_enabled(cfg));
     choose_scales(cfg, &R->s_phi, &R->s_1);
     if (cfg->precision == AXF_F32) {
