@@ -1,19 +1,33 @@
 """Benchmark of the axion-coupled Yee step on one MI355X.
 
-Default workload: the 3D focused-pulse + counter-propagating axion packet run
-(512^3 cells, lambda/12, FP32 fields, Mur EM and outflow axion boundaries),
-advanced by the fused one-pass kernel.  One step = one full leapfrog step of
-every field (E0/B0, axion, E1/B1, boundaries); diagnostics are recorded every
-100 steps inside the timed region.
+Default workload: the 2D Gaussian-pulse run (4096 x 4096 cells, lambda/16,
+dt = 0.95 dx / sqrt(2), Gaussian laser of waist 8 lambda and FWHM 10 lambda
+entering through the x_min Mur face, static B slab over cells 1024-3071, PML
+axion layers), FP32 fields, advanced by the fused wavefront kernel.  One step
+is one full leapfrog step of every active field (zero-order E/B, axion,
+first-order E/B, Mur and axion boundaries, laser injection); the energy and
+probability diagnostics are recorded every 100 steps inside the timed region.
 
-Printed: one JSON line with the throughput (Gcell-updates/s), the HBM roofline
-of the fused kernel (algorithmic bytes per launch / mean launch time from HIP
-events on the run's stream), the unfused path for comparison, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+Printed: one JSON line with the whole-path throughput (Gcell-updates/s), the
+HBM roofline of the dominant kernel (algorithmic bytes per launch over the mean
+launch time from HIP events on the run's stream; measured HBM traffic from the
+committed rocprofv3 counter summary when it matches the kernel source), the
+unfused path for comparison, a device copy for the achievable bandwidth, and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Other modes:
+  --profile-only          the device copy and the fused steps only (the command
+                          the rocprofv3 counter passes run)
+  --pmc-summary F W       turn the FETCH_SIZE and WRITE_SIZE counter CSVs of two
+                          rocprofv3 --pmc runs of --profile-only into the traffic
+                          summary under profiles/
+  --trace-summary S       turn the kernel_stats CSV of a rocprofv3 --kernel-trace
+                          --stats run of this script into the summary under profiles/
 """
 import argparse
+import csv
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -22,6 +36,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30
+KERNEL_SOURCES = ["paper_2406_16796_amd/csrc/axf_fused.hip", "paper_2406_16796_amd/csrc/axf_fused.h",
+                  "paper_2406_16796_amd/csrc/axf_stencil.h", "paper_2406_16796_amd/csrc/axf_internal.h",
+                  "paper_2406_16796_amd/build.py"]
+WORKLOADS = {
+    "2d": ("gaussian_2d", "k_wave2d"),
+    "3d": ("focused_3d", "k_e1"),
+    "1d": ("plane_wave_1d", "k_e1"),
+}
 
 
 def words_per_cell(ndim):
@@ -33,20 +56,62 @@ def words_per_cell(ndim):
 
 def workload(name):
     from paper_2406_16796_amd import workloads as W
-    if name == "3d":
-        cfg = W.focused_3d()
-    elif name == "2d":
-        cfg = W.gaussian_2d()
-    elif name == "1d":
-        cfg = W.plane_wave_1d()
-    else:
-        raise SystemExit("unknown workload " + name)
-    return cfg
+    return getattr(W, WORKLOADS[name][0])()
 
 
-def cells(cfg):
-    n = cfg["n"]
-    return int(n[0]) * int(n[1]) * int(n[2])
+def workload_tag(cfg, precision):
+    n = [int(v) for v in cfg["n"] if int(v) > 1]
+    return "%s_%s_%s" % (cfg["name"], "x".join(map(str, n)), precision)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_file(tag, kernel):
+    return os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.md" % (kernel, tag))
+
+
+def read_traffic(tag, kernel):
+    """HBM bytes per launch from the committed counter summary, or None when
+    it is missing or was taken on another version of the kernel source."""
+    path = traffic_file(tag, kernel)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- `") and "=" in line:
+                k, v = line[3:].split("`", 1)[0].split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def device_copy(torch):
+    """A plain device copy of COPY_BYTES: the calibration kernel of the
+    counter passes and the achievable HBM bandwidth on this GPU."""
+    n = COPY_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * COPY_BYTES / (ms * 1e-3) / 1e9
 
 
 def time_path(axf, torch, cfg, precision, path, steps, warmup, diag_every):
@@ -61,14 +126,15 @@ def time_path(axf, torch, cfg, precision, path, steps, warmup, diag_every):
     wall = time.perf_counter() - t0
     ev_ms, launches = run.last_step_timing()
     rec = run.diag_now()
+    fused = run.uses_fused()
     del run
     torch.cuda.empty_cache()
-    return wall, ev_ms, launches, rec
+    return wall, ev_ms, launches, rec, fused
 
 
 def cpu_baseline(cfg, target_s=15.0):
     """The FP64 oracle on a bounded sample: the same workload on a grid cut
-    down to a few 10^5-10^6 cells, timed over whole steps."""
+    down to a few 10^5 cells, timed over whole steps."""
     from oracle.oracle import Oracle
     sample = dict(cfg)
     ndim = sum(1 for v in cfg["n"] if v > 1)
@@ -86,26 +152,133 @@ def cpu_baseline(cfg, target_s=15.0):
         steps += 1
     dt = time.perf_counter() - t0
     nc = n[0] * n[1] * n[2]
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = o.threads()
     return {"value": nc * steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": "%s grid of the same workload, %d steps, FP64, %.1f s" % ("x".join(map(str, n)), steps, dt)}
+            "sample": "%s cells of the same workload (FP64, same boundaries and sources), %d whole steps in %.1f s"
+                      % ("x".join(map(str, n)), steps, dt)}
+
+
+def pmc_rows(path):
+    """(kernel name, counter value) per dispatch from a rocprofv3 counter CSV."""
+    out = []
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            out.append((row["Kernel_Name"], float(row["Counter_Value"])))
+    return out
+
+
+def pmc_summary(args):
+    """Scale the FETCH_SIZE / WRITE_SIZE readings of the step kernel by the
+    readings of the device copy of known size, write the summary file."""
+    cfg = workload(args.workload)
+    tag = workload_tag(cfg, args.precision)
+    kernel = WORKLOADS[args.workload][1]
+    res = {}
+    for counter, path in (("FETCH_SIZE", args.pmc_summary[0]), ("WRITE_SIZE", args.pmc_summary[1])):
+        rows = pmc_rows(path)
+        copy = [v for k, v in rows if "neg" in k.lower()]
+        step = [v for k, v in rows if kernel in k]
+        if not copy or not step:
+            raise SystemExit("no copy or %s dispatches in %s" % (kernel, path))
+        kib_copy = max(copy)
+        factor = COPY_BYTES / (kib_copy * 1024.0)
+        kib_step = sum(step) / len(step)
+        res[counter] = (kib_copy, factor, kib_step, len(step), kib_step * 1024.0 * factor)
+    ndim = sum(1 for v in cfg["n"] if v > 1)
+    esize = 4 if args.precision == "f32" else 8
+    nc = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
+    algo = words_per_cell(ndim) * esize * nc
+    traffic = res["FETCH_SIZE"][4] + res["WRITE_SIZE"][4]
+    lines = ["# HBM traffic of %s, workload %s" % (kernel, tag), "",
+             "Two rocprofv3 counter passes over `python bench.py --profile-only --workload %s --precision %s "
+             "--steps %d` (the device copy of %d bytes read and %d written, then the fused steps):"
+             % (args.workload, args.precision, args.steps, COPY_BYTES, COPY_BYTES), "",
+             "    cd /tmp && export TMPDIR=/tmp",
+             "    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d $OUT/fetch -o fetch --output-format csv -- "
+             "python3 $REPO/bench.py --profile-only --workload %s --precision %s --steps %d"
+             % (args.workload, args.precision, args.steps),
+             "    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d $OUT/write -o write --output-format csv -- "
+             "python3 $REPO/bench.py --profile-only --workload %s --precision %s --steps %d"
+             % (args.workload, args.precision, args.steps),
+             "    python3 $REPO/bench.py --workload %s --precision %s --steps %d --pmc-summary "
+             "<fetch counter_collection.csv> <write counter_collection.csv>"
+             % (args.workload, args.precision, args.steps), "",
+             "| counter | copy kernel KiB | scale (bytes per KiB read) | %s KiB per launch (mean of %d) | bytes per launch |"
+             % (kernel, res["FETCH_SIZE"][3]),
+             "|---|---|---|---|---|"]
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        kc, fac, ks, _, b = res[counter]
+        lines.append("| %s | %.0f | %.4f x 1024 | %.0f | %.4g |" % (counter, kc, fac, ks, b))
+    lines += ["",
+              "Algorithmic bytes per launch: %d words x %d B x %d cells = %.4g B; measured / algorithmic = %.3f."
+              % (words_per_cell(ndim), esize, nc, algo, traffic / algo), "",
+              "- `traffic_bytes_per_launch = %.6g`" % traffic,
+              "- `algorithmic_bytes_per_launch = %d`" % algo,
+              "- `kernel_source_sha256 = %s`" % kernel_source_hash(), ""]
+    path = traffic_file(tag, kernel)
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+    print(path)
+
+
+def trace_summary(args):
+    """Per-kernel call count and mean duration from a rocprofv3 kernel_stats CSV."""
+    cfg = workload(args.workload)
+    tag = workload_tag(cfg, args.precision)
+    kernel = WORKLOADS[args.workload][1]
+    rows = list(csv.DictReader(open(args.trace_summary)))
+    cmd = ("python3 $REPO/bench.py --workload %s --precision %s --steps %d --no-cpu-baseline"
+           % (args.workload, args.precision, args.steps))
+    lines = ["# Kernel trace of bench.py, workload %s" % tag, "",
+             "    cd /tmp && export TMPDIR=/tmp",
+             "    timeout -k 10 300 rocprofv3 --kernel-trace --stats -d $OUT/kt -o kt --output-format csv -- " + cmd,
+             "    python3 $REPO/bench.py --workload %s --precision %s --trace-summary $OUT/kt/kt_kernel_stats.csv"
+             % (args.workload, args.precision), "",
+             "The run times the fused path twice (with and without diagnostics) and the unfused phase "
+             "sequence once; the copy kernel is the bandwidth calibration.", "",
+             "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"]
+        short = name.split("(")[0].replace("void ", "")
+        if len(short) > 70:
+            short = short[:67] + "..."
+        lines.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f |" % (
+            short, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["Percentage"])))
+    dom = [r for r in rows if kernel in r["Name"]]
+    if dom:
+        lines += ["", "- `%s_mean_us = %.2f`" % (kernel, float(dom[0]["AverageNs"]) / 1e3),
+                  "- `kernel_source_sha256 = %s`" % kernel_source_hash()]
+    path = os.path.join(ROOT, "profiles", "%s_%s_kernel_trace.md" % (kernel, tag))
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(path)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="3d", choices=["3d", "2d", "1d"])
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="2d", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--diag-every", type=int, default=100)
-    ap.add_argument("--plain-steps", type=int, default=40)
+    ap.add_argument("--plain-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only (--gpus %d requested); multi-GPU sharding is "
-              "described in DESIGN.md but not built" % args.gpus, file=sys.stderr)
+        print("this build runs on one GPU only (--gpus %d requested): the step is a single-GPU kernel; "
+              "slab sharding across GPUs is a design, not code" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.pmc_summary:
+        pmc_summary(args)
+        return
+    if args.trace_summary:
+        trace_summary(args)
+        return
 
     import torch
     from paper_2406_16796_amd import axf
@@ -114,24 +287,32 @@ def main():
     prec = axf.F32 if args.precision == "f32" else axf.F64
     esize = 4 if prec == axf.F32 else 8
     ndim = sum(1 for v in cfg["n"] if v > 1)
-    nc = cells(cfg)
+    nc = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
+    tag = workload_tag(cfg, args.precision)
+    kernel = WORKLOADS[args.workload][1]
 
-    # whole hot path (fused step + diagnostics at the configured cadence)
-    wall, ev_ms, launches, rec = time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, args.warmup,
-                                           args.diag_every)
+    copy_gbs = device_copy(torch)
+    if args.profile_only:
+        time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, 2, 0)
+        print(json.dumps({"profile_only": tag, "steps": args.steps}), flush=True)
+        return
+
+    # whole hot path: step + diagnostics at the configured cadence
+    wall, _, _, rec, fused = time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, args.warmup,
+                                       args.diag_every)
     value = nc * args.steps / wall / 1e9
-    # the dominant kernel alone: fused launches only, HIP events on the run's stream
-    _, k_ms, k_launches, _ = time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, 2, 0)
+    # the dominant kernel alone: step launches only, HIP events on the run's stream
+    _, k_ms, k_launches, _, _ = time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, 2, 0)
     per_launch_s = k_ms / 1e3 / max(k_launches, 1)
     algo_bytes = words_per_cell(ndim) * esize * nc
     achieved = algo_bytes / per_launch_s / 1e9
-    traffic = None
-    # unfused path for comparison
-    p_wall, p_ms, p_launches, _ = time_path(axf, torch, cfg, prec, axf.PATH_PLAIN, args.plain_steps, 2, 0)
+    traffic = read_traffic(tag, kernel) if fused else None
+    # the unfused phase sequence for comparison
+    p_wall, _, p_launches, _, _ = time_path(axf, torch, cfg, prec, axf.PATH_PLAIN, args.plain_steps, 2, 0)
     plain_value = nc * args.plain_steps / p_wall / 1e9
 
     line = {
-        "metric": "Gcell-updates/s (fused step; % of HBM roofline)",
+        "metric": "Gcell-updates/s + % HBM roofline (fused vs plain)",
         "value": round(value, 3),
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
@@ -144,21 +325,23 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {
-            "workload": cfg.get("name"), "ndim": ndim, "n": cfg["n"], "dx": cfg["dx"][0], "dt": cfg["dt"],
+            "workload": tag, "ndim": ndim, "n": cfg["n"], "dx": cfg["dx"][0], "dt": cfg["dt"],
             "m": cfg["m"], "g": cfg["g"], "em_bc": "mur", "axion_bc": cfg["ax_bc"][0],
-            "diag_every": args.diag_every, "path": "fused",
+            "diag_every": args.diag_every, "path": "fused" if fused else "plain",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_fused", "bytes_per_launch": algo_bytes, "mean_launch_ms": round(per_launch_s * 1e3, 4),
-            "launches": k_launches,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic) if traffic is not None else None,
+            "kernel": kernel if fused else "plain phase sequence", "bytes_per_launch": algo_bytes,
+            "mean_launch_ms": round(per_launch_s * 1e3, 5), "launches": k_launches,
+            "copy_kernel_GBs": round(copy_gbs, 1),
         },
         "plain": {"value": round(plain_value, 3), "unit": "Gcell-updates/s",
                   "ms_per_step": round(p_wall / args.plain_steps * 1e3, 4),
                   "launches_per_step": round(p_launches / max(args.plain_steps, 1), 2),
-                  "speedup_fused": round(value / plain_value, 3) if plain_value > 0 else None},
-        "diag": {"p_gen": rec["p_gen"], "p_conv": rec["p_conv"], "finite": rec["finite"]},
+                  "fused_speedup": round(value / plain_value, 3) if plain_value > 0 else None},
+        "diag": {"step": rec["step"], "p_gen": rec["p_gen"], "p_conv": rec["p_conv"], "finite": rec["finite"]},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)

@@ -170,6 +170,8 @@ int axf_write_state(axf_run *run, const void *buf, size_t bytes);
 
 int axf_sync(axf_run *run);
 int axf_steps_done(const axf_run *run, int64_t *steps);
+/* the step path this run takes: AXF_PATH_PLAIN or AXF_PATH_FUSED (AUTO resolved) */
+int axf_path_in_use(const axf_run *run, int32_t *path);
 /* release library-side handles (not the caller's device memory) */
 int axf_destroy(axf_run *run);
 

@@ -42,6 +42,18 @@
 #include <string.h>
 #include <stdio.h>
 #include "axion_oracle.h"
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 struct ora_state {
     ora_config c;

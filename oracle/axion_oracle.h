@@ -96,6 +96,9 @@ long   ora_step_count(const ora_state *s);
 /* energies at the current integer time: out[0] = H_phi, out[1] = H_gamma(E0,B0), out[2] = H_gamma(E1,B1) */
 void   ora_energies(const ora_state *s, double out[3]);
 /* incident laser E component comp (1 = y, 2 = z) at (x, y, z, t); exposed for tests */
+/* OpenMP threads the step loops use (1 without OpenMP) */
+int    ora_threads(void);
+
 double ora_incident(const ora_state *s, int comp, double x, double y, double z, double t);
 
 #ifdef __cplusplus

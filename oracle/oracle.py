@@ -78,6 +78,7 @@ def lib():
         L.ora_energies.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
         L.ora_incident.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_double] * 4
         L.ora_incident.restype = ctypes.c_double
+        L.ora_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -158,6 +159,9 @@ class Oracle:
         out = (ctypes.c_double * 3)()
         lib().ora_energies(self._h, out)
         return tuple(out)
+
+    def threads(self):
+        return lib().ora_threads()
 
     def incident(self, comp, x, y, z, t):
         return lib().ora_incident(self._h, comp, x, y, z, t)

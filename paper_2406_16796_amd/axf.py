@@ -23,7 +23,7 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 EXPORTS = [
     "axf_last_error", "axf_version", "axf_footprint", "axf_extents", "axf_create", "axf_write_field",
     "axf_step", "axf_read_field", "axf_diag_now", "axf_read_diag", "axf_state_bytes", "axf_read_state",
-    "axf_write_state", "axf_sync", "axf_steps_done", "axf_destroy", "axf_last_step_timing",
+    "axf_write_state", "axf_sync", "axf_steps_done", "axf_path_in_use", "axf_destroy", "axf_last_step_timing",
     "axf_batch_footprint", "axf_batch_create", "axf_batch_step", "axf_batch_run", "axf_batch_destroy",
     "axf_server_create", "axf_server_submit", "axf_server_cancel", "axf_server_poll", "axf_server_stats",
     "axf_server_destroy",
@@ -104,6 +104,7 @@ def lib():
         "axf_write_state": ([vp, vp, sz], ctypes.c_int),
         "axf_sync": ([vp], ctypes.c_int),
         "axf_steps_done": ([vp, P(i64)], ctypes.c_int),
+        "axf_path_in_use": ([vp, P(i32)], ctypes.c_int),
         "axf_destroy": ([vp], ctypes.c_int),
         "axf_last_step_timing": ([vp, P(dp), P(i64)], ctypes.c_int),
         "axf_batch_footprint": ([P(Config), i32, P(sz)], ctypes.c_int),
@@ -234,6 +235,11 @@ class Run:
         v = ctypes.c_int64()
         check(lib().axf_steps_done(self._h, ctypes.byref(v)))
         return v.value
+
+    def uses_fused(self):
+        v = ctypes.c_int32()
+        check(lib().axf_path_in_use(self._h, ctypes.byref(v)))
+        return v.value == PATH_FUSED
 
     def read(self, name):
         """Field `name` at the current time as float64, shape (nn_z, nn_y, nn_x)."""

@@ -765,6 +765,13 @@ int axf_steps_done(const axf_run *run, int64_t *steps)
     return AXF_OK;
 }
 
+int axf_path_in_use(const axf_run *run, int32_t *path)
+{
+    if (!run || !path) return fail(AXF_EINVAL, "null argument");
+    *path = run->use_fused ? AXF_PATH_FUSED : AXF_PATH_PLAIN;
+    return AXF_OK;
+}
+
 int axf_last_step_timing(const axf_run *run, double *ms, int64_t *launches)
 {
     if (!run || !ms || !launches) return fail(AXF_EINVAL, "null argument");
