@@ -138,8 +138,9 @@ Layout make_layout(const axf_config *c)
                 L.off_em[kind][s][comp] = act(kind, comp) ? (long)(L.off_arrays + L.arr_stride * q_em(kind, s, comp)) : -1;
     for (int s = 0; s < 3; s++) L.off_phi[s] = (long)(L.off_arrays + L.arr_stride * q_phi(s));
     for (int comp = 0; comp < 3; comp++) L.off_c[comp] = (long)(L.off_arrays + L.arr_stride * q_c(comp));
+    // boundary planes exist only normal to the active axes
     size_t fmax = 0;
-    for (int d = 0; d < 3; d++) {
+    for (int d = 0; d < D; d++) {
         int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
         size_t fb = (size_t)L.nn[a] * L.nn[b] * es;
         fmax = fb > fmax ? fb : fmax;
