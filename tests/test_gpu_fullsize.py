@@ -1,0 +1,147 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times (AUTO path: the fused wavefront kernel in 2D, the unfused
+phases in 1D and 3D), and the FP32 accuracy budget on the conversion
+probabilities.
+
+- Full-size grids: the oracle advances the whole 4096^2 (and 512^3) grid for a
+  few steps; every field is compared element by element.  An axion packet
+  inside the B slab and a laser already at its peak on the entry face make
+  every component nonzero from the first step.
+- FP32 budget: the conversion probability P = H_phi / H_gamma0 of an FP32 run
+  is within 1e-5 relative of the FP64 result.  For the 1D CW run the FP64
+  result is the oracle's; for the full 2D runs (4096^2, 6000 steps, three
+  masses) it is the GPU's own FP64 run, which the tests above tie to the
+  oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2406_16796_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["E0X", "E0Y", "E0Z", "B0X", "B0Y", "B0Z", "E1X", "E1Y", "E1Z", "B1X", "B1Y", "B1Z",
+          "PHI_OLD", "PHI_NEW"]
+P_TOL_FP32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def axf():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_16796_amd import axf as A
+    A.lib()
+    return A
+
+
+def order_scales(ora):
+    s0 = max(np.abs(ora.field(n)).max() for n in FIELDS[:6])
+    s1 = max(np.abs(ora.field(n)).max() for n in FIELDS[6:12])
+    sp = max(np.abs(ora.field(n)).max() for n in FIELDS[12:])
+    return [s0] * 6 + [s1] * 6 + [sp] * 2
+
+
+def compare(run, ora, tol, label):
+    scales = order_scales(ora)
+    worst = {}
+    for name, scale in zip(FIELDS, scales):
+        g = run.read(name)
+        o = ora.field(name)
+        assert g.shape == o.shape, name
+        err = float(np.abs(g - o).max())
+        worst[name] = err / scale if scale > 0 else err
+    print(label, {k: "%.1e" % v for k, v in worst.items()}, flush=True)
+    for k, v in worst.items():
+        assert v <= tol, (label, k, v)
+
+
+def full_2d():
+    cfg = W.gaussian_2d()
+    dx = cfg["dx"][0]
+    n = cfg["n"][0]
+    cfg.update(t_center=0.0, packet_on=1, pk_amp=1e-3, pk_k=1.0, pk_w=5 * W.TWO_PI,
+               pk_x0=0.5 * n * dx, pk_y0=0.45 * n * dx, pk_dir=-1)
+    return cfg
+
+
+@pytest.fixture(scope="module")
+def oracle_2d():
+    cfg = full_2d()
+    ora = Oracle(cfg)
+    ora.step(6)
+    return cfg, ora
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_size_2d_fused_matches_oracle(axf, oracle_2d, prec):
+    cfg, ora = oracle_2d
+    p = axf.F64 if prec == "f64" else axf.F32
+    run = axf.Run(cfg, precision=p)
+    assert run.uses_fused()
+    run.step(6)
+    compare(run, ora, 1e-10 if prec == "f64" else 2e-5, "full 2d " + prec)
+
+
+def test_full_size_3d_matches_oracle(axf):
+    cfg = W.focused_3d()
+    cfg["t_center"] = 0.0
+    ora = Oracle(cfg)
+    ora.step(2)
+    run = axf.Run(cfg, precision=axf.F32)
+    run.step(2)
+    compare(run, ora, 2e-5, "full 3d f32")
+
+
+def p_rel(a, b):
+    return abs(a / b - 1.0)
+
+
+def test_fp32_conversion_probability_1d_cw(axf):
+    """The 4096-cell, 3000-step CW conversion run in FP32 against the FP64 oracle."""
+    cfg = W.plane_wave_1d()
+    ora = Oracle(cfg)
+    ora.step(cfg["steps"])
+    h = ora.energies()
+    run = axf.Run(cfg, precision=axf.F32)
+    run.step(cfg["steps"])
+    rec = run.diag_now()
+    print("1d cw fp32 P rel err %.2e, H_em0 rel err %.2e" % (p_rel(rec["p_gen"], h[0] / h[1]),
+                                                             p_rel(rec["h_em0"], h[1])), flush=True)
+    assert p_rel(rec["p_gen"], h[0] / h[1]) <= P_TOL_FP32
+
+
+def test_fp32_probabilities_2d_pulse_against_oracle(axf):
+    """A reduced 2D pulse crossing the slab (512^2, 700 steps), FP32 against
+    the FP64 oracle: generation probability at the end."""
+    cfg = W.gaussian_2d(n=512, steps=700, m=0.05, waist_lam=4.0, fwhm_lam=2.0, slab=(64, 448))
+    cfg["t_center"] = 8.0
+    ora = Oracle(cfg)
+    ora.step(cfg["steps"])
+    h = ora.energies()
+    run = axf.Run(cfg, precision=axf.F32)
+    run.step(cfg["steps"])
+    rec = run.diag_now()
+    assert h[0] > 0
+    print("2d pulse fp32 P rel err %.2e" % p_rel(rec["p_gen"], h[0] / h[1]), flush=True)
+    assert p_rel(rec["p_gen"], h[0] / h[1]) <= P_TOL_FP32
+
+
+@pytest.mark.parametrize("m", [0.0, 0.05, 0.2])
+def test_fp32_probability_full_2d_runs(axf, m):
+    """4096^2, 6000 steps (the pulse crosses the whole slab): FP32 against the
+    GPU's FP64 run, which matches the oracle element for element above."""
+    import torch
+    cfg = W.gaussian_2d(m=m)
+    recs = []
+    for p in (axf.F64, axf.F32):
+        run = axf.Run(cfg, precision=p)
+        run.step(cfg["steps"])
+        recs.append(run.diag_now())
+        run.close()
+        torch.cuda.empty_cache()
+    assert recs[0]["p_gen"] > 0
+    err = p_rel(recs[1]["p_gen"], recs[0]["p_gen"])
+    print("full 2d m=%g P=%.4e fp32 rel err %.2e" % (m, recs[0]["p_gen"], err), flush=True)
+    assert err <= P_TOL_FP32
