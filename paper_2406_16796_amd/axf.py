@@ -279,3 +279,110 @@ class Run:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         check(lib().axf_last_step_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def _configs(cfgs, precision, diag_every, path):
+    arr = (Config * len(cfgs))()
+    for i, c in enumerate(cfgs):
+        arr[i] = make_config(c, precision=precision, diag_every=diag_every, path=path)
+    return arr
+
+
+def batch_footprint(cfgs, precision=F32, diag_every=0, path=PATH_AUTO):
+    arr = _configs(cfgs, precision, diag_every, path)
+    b = ctypes.c_size_t()
+    check(lib().axf_batch_footprint(arr, len(cfgs), ctypes.byref(b)))
+    return b.value
+
+
+class Batch:
+    """Independent runs in one device buffer, advanced by batched launches.
+    `runs[i]` are borrowed views with the Run read/diag/state methods."""
+
+    def __init__(self, cfgs, precision=F32, diag_every=0, path=PATH_AUTO, stream=None):
+        self.count = len(cfgs)
+        self._cfgs = _configs(cfgs, precision, diag_every, path)
+        self.nbytes = batch_footprint(cfgs, precision, diag_every, path)
+        self.buffer = device_buffer(self.nbytes)
+        self.stream = stream if stream is not None else current_stream()
+        h = ctypes.c_void_p()
+        check(lib().axf_batch_create(self._cfgs, self.count, ctypes.c_void_p(self.buffer.data_ptr()),
+                                     self.buffer.numel(), self.stream, ctypes.byref(h)))
+        self._h = h
+        self.runs = []
+        for i, c in enumerate(cfgs):
+            v = ctypes.c_void_p()
+            check(lib().axf_batch_run(self._h, i, ctypes.byref(v)))
+            nn = extents(c, precision=precision, diag_every=diag_every, path=path)
+            self.runs.append(Run._view(v, self._cfgs[i], nn))
+
+    def step(self, nsteps):
+        """Advance run i by nsteps[i] (an int applies to every run)."""
+        if np.isscalar(nsteps):
+            nsteps = [int(nsteps)] * self.count
+        arr = (ctypes.c_int64 * self.count)(*[int(v) for v in nsteps])
+        check(lib().axf_batch_step(self._h, arr))
+
+    def sync(self):
+        _torch().cuda.synchronize()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().axf_batch_destroy(self._h)
+        self._h = None
+        self.runs = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over a device pool of `pool_bytes`."""
+
+    def __init__(self, pool_bytes, max_slots=64, macro_steps=100, stream=None):
+        self.pool = device_buffer(pool_bytes)
+        self.stream = stream if stream is not None else current_stream()
+        h = ctypes.c_void_p()
+        check(lib().axf_server_create(ctypes.c_void_p(self.pool.data_ptr()), self.pool.numel(), int(max_slots),
+                                      int(macro_steps), self.stream, ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, cfg, nsteps, precision=F32, diag_every=0, path=PATH_AUTO):
+        c = make_config(cfg, precision=precision, diag_every=diag_every, path=path)
+        rid = ctypes.c_uint64()
+        check(lib().axf_server_submit(self._h, ctypes.byref(c), int(nsteps), ctypes.byref(rid)))
+        return rid.value
+
+    def cancel(self, rid):
+        check(lib().axf_server_cancel(self._h, ctypes.c_uint64(rid)))
+
+    def poll(self, max_results=256):
+        buf = (Result * max_results)()
+        n = ctypes.c_int32()
+        check(lib().axf_server_poll(self._h, buf, max_results, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            r = buf[i]
+            out.append({"id": r.id, "status": r.status, "steps": r.steps, "cells": r.cells,
+                        "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done,
+                        "final": r.final.as_dict()})
+        return out
+
+    def stats(self):
+        q, r, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        check(lib().axf_server_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b)))
+        return {"queued": q.value, "resident": r.value, "bytes_used": b.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().axf_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,20 +1,637 @@
-// axf_batch.hip -- batches of runs and the continuous-batching server.
+// axf_batch.hip -- batches of independent runs and the continuous-batching
+// server.
+//
+// Both sit on one stepping engine.  The engine groups runs by the kernels they
+// share: dimensionality, precision, and the 2D wavefront kernel vs the unfused
+// phase sequence.  Each group's runs are sorted by remaining steps, so the runs
+// still active at a step are a prefix of the group's table.  One step is then
+// one launch per kernel kind and group, whatever the number of runs: the
+// wavefront kernel, or the six unfused phases; the laser-table fill every
+// 16 steps; the diagnostics at the runs' cadence.  Every block of a batched
+// launch executes its run's own single-run body with the run's own step
+// counter, so a run's result is bit-identical alone and in any mix.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <set>
+#include <thread>
+#include <vector>
+
+#include "axf_fused.h"
+#include "axf_kernels.h"
 #include "axf_runtime.h"
+
+namespace axf {
+
+#define BCHK(call)                                               \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);        \
+    } while (0)
+
+static long cdiv(long a, long b) { return (a + b - 1) / b; }
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// blocks of each launch kind for one run (the single-run launchers' grids)
+static void run_blocks(const Run *R, bool wave, long blk[kNumKinds])
+{
+    const Layout& L = R->L;
+    blk[kVolume] = cdiv(L.npts, 256);
+    long face = 0;
+    for (int d = 0; d < R->cfg.ndim; d++) {
+        if (R->cfg.em_bc[d] != AXF_EM_MUR) continue;
+        int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+        face = std::max(face, (long)L.nn[a] * L.nn[b]);
+    }
+    blk[kFace] = cdiv(face, 256);
+    blk[kLaser] = R->cfg.laser_on ? cdiv(L.inc_face, 256) : 0;
+    blk[kWave] = wave ? wave2d_blocks(L.nn[0], L.nn[1], run_wave_chunk(R)) : 0;
+}
+
+// ------------------------------------------------------------------ engine
+
+struct Group {
+    int D = 0;
+    bool f64 = false, wave = false, any_diag = false;
+    std::vector<int> idx;       // runs, sorted by steps this call (descending)
+    size_t off = 0;             // first table entry
+    int nact = 0;
+};
+
+class Engine {
+public:
+    ~Engine() { if (host_) hipHostFree(host_); }
+
+    // `dev` holds `cap` table entries of device memory owned by the caller
+    int init(BItem *dev, size_t cap)
+    {
+        dev_ = dev;
+        cap_ = cap;
+        BCHK(hipHostMalloc((void **)&host_, cap * sizeof(BItem), hipHostMallocDefault));
+        return AXF_OK;
+    }
+
+    static size_t entries_for(size_t runs) { return runs + 16; }
+
+    int step(Run *const *runs, const int64_t *ns, int count, hipStream_t st);
+
+private:
+    template <int D, typename T>
+    int group_step(Group& g, long s, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st);
+
+    BItem *dev_ = nullptr, *host_ = nullptr;
+    size_t cap_ = 0;
+};
+
+template <int D, typename T>
+int Engine::group_step(Group& g, long s, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st)
+{
+    const BItem *dt = dev_ + g.off, *ht = host_ + g.off;
+    const int n = g.nact;
+    if (s % (kIncLevels - 1) == 0) Plain<D, T>::batch_inc_fill(dt, ht, n, s, kIncLevels, st);
+    bool launched = false;
+    if constexpr (D == 2) {
+        if (g.wave) {
+            hipError_t e = launch_wave2d_batch<T>(dt, ht, n, s, st);
+            if (e != hipSuccess) return hip_fail(e, "batched wavefront step");
+            launched = true;
+        }
+    }
+    if (!launched) Plain<D, T>::batch_step(dt, ht, n, s, st);
+    if (!g.any_diag) return AXF_OK;
+    // diagnostics of the runs whose cadence hits this step
+    int hits = 0;
+    bool same = true;
+    for (int k = 0; k < n; k++) {
+        const Run *R = runs[g.idx[k]];
+        const int64_t de = R->cfg.diag_every;
+        if (de > 0 && (R->step + s) % de == 0) hits++;
+        same = same && nrec[g.idx[k]] == nrec[g.idx[0]];
+    }
+    if (hits == 0) return AXF_OK;
+    if (hits == n && same) {
+        Plain<D, T>::batch_diag(dt, ht, n, s, nrec[g.idx[0]], st);
+        for (int k = 0; k < n; k++) nrec[g.idx[k]]++;
+        return AXF_OK;
+    }
+    for (int k = 0; k < n; k++) {
+        Run *R = runs[g.idx[k]];
+        const int64_t de = R->cfg.diag_every;
+        if (de <= 0 || (R->step + s) % de != 0) continue;
+        const int64_t slot = (R->rec_written + nrec[g.idx[k]]) % R->hk<T>().rec_cap;
+        Plain<D, T>::diag(R->rk<T>(), R->hk<T>(), R->step + s, (int)slot, st);
+        nrec[g.idx[k]]++;
+    }
+    return AXF_OK;
+}
+
+int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
+{
+    std::vector<Group> groups;
+    int64_t smax = 0;
+    for (int i = 0; i < count; i++) {
+        if (ns[i] < 0) return fail(AXF_EINVAL, "negative step count for run %d", i);
+        if (ns[i] == 0) continue;
+        Run *R = runs[i];
+        int rc = run_prepare(R);
+        if (rc) return rc;
+        const int D = R->cfg.ndim;
+        const bool f64 = R->cfg.precision == AXF_F64, wave = run_wave2d(R);
+        Group *g = nullptr;
+        for (auto& q : groups)
+            if (q.D == D && q.f64 == f64 && q.wave == wave) g = &q;
+        if (!g) {
+            groups.emplace_back();
+            g = &groups.back();
+            g->D = D;
+            g->f64 = f64;
+            g->wave = wave;
+        }
+        g->idx.push_back(i);
+        g->any_diag = g->any_diag || R->cfg.diag_every > 0;
+        smax = std::max(smax, ns[i]);
+    }
+    if (smax == 0) return AXF_OK;
+    size_t off = 0;
+    for (auto& g : groups) off += g.idx.size() + 1;
+    if (off > cap_) return fail(AXF_ENOMEM, "batch table of %zu entries exceeds its %zu", off, cap_);
+    off = 0;
+    for (auto& g : groups) {
+        std::stable_sort(g.idx.begin(), g.idx.end(), [&](int a, int b) { return ns[a] > ns[b]; });
+        g.off = off;
+        g.nact = (int)g.idx.size();
+        long acc[kNumKinds] = {0, 0, 0, 0};
+        for (size_t k = 0; k <= g.idx.size(); k++) {
+            BItem& b = host_[off + k];
+            b = BItem{};
+            for (int q = 0; q < kNumKinds; q++) b.blk[q] = acc[q];
+            if (k == g.idx.size()) break;
+            const Run *R = runs[g.idx[k]];
+            b.rk = R->base + R->L.off_rk;
+            b.step0 = R->step;
+            b.rec0 = R->rec_written;
+            b.chunk = run_wave_chunk(R);
+            long nb[kNumKinds];
+            run_blocks(R, g.wave, nb);
+            for (int q = 0; q < kNumKinds; q++) acc[q] += nb[q];
+        }
+        off += g.idx.size() + 1;
+    }
+    BCHK(hipMemcpyAsync(dev_, host_, off * sizeof(BItem), hipMemcpyHostToDevice, st));
+    // the staging buffer is rewritten by the next call: finish the copy now
+    BCHK(hipStreamSynchronize(st));
+
+    std::vector<int64_t> nrec(count, 0);
+    for (int64_t s = 0; s < smax; s++) {
+        for (auto& g : groups) {
+            while (g.nact > 0 && ns[g.idx[g.nact - 1]] <= s) g.nact--;
+            if (g.nact == 0) continue;
+            int rc;
+            switch (g.D * 2 + (g.f64 ? 1 : 0)) {
+            case 2: rc = group_step<1, float>(g, s, nrec, runs, st); break;
+            case 3: rc = group_step<1, double>(g, s, nrec, runs, st); break;
+            case 4: rc = group_step<2, float>(g, s, nrec, runs, st); break;
+            case 5: rc = group_step<2, double>(g, s, nrec, runs, st); break;
+            case 6: rc = group_step<3, float>(g, s, nrec, runs, st); break;
+            default: rc = group_step<3, double>(g, s, nrec, runs, st); break;
+            }
+            if (rc) return rc;
+        }
+    }
+    BCHK(hipGetLastError());
+    for (int i = 0; i < count; i++) {
+        if (ns[i] == 0) continue;
+        Run *R = runs[i];
+        if (R->cfg.laser_on) R->inc_lo = R->step + (ns[i] - 1) / (kIncLevels - 1) * (kIncLevels - 1);
+        R->step += ns[i];
+        R->rec_written += nrec[i];
+    }
+    return AXF_OK;
+}
+
+}  // namespace axf
 
 using namespace axf;
 
+// ------------------------------------------------------------------ batches
+
+struct axf_batch {
+    std::vector<axf_run *> runs;
+    Engine eng;
+    hipStream_t stream = nullptr;
+};
+
+static int batch_layout(const axf_config *cfgs, int32_t count, std::vector<size_t> *offs, size_t *total)
+{
+    if (!cfgs || count <= 0) return fail(AXF_EINVAL, "a batch needs at least one configuration");
+    size_t off = align256(Engine::entries_for(count) * sizeof(BItem));
+    for (int32_t i = 0; i < count; i++) {
+        int rc = validate(&cfgs[i]);
+        if (rc) return fail(rc, "run %d: %s", i, axf_last_error());
+        if (offs) offs->push_back(off);
+        off += align256(make_layout(&cfgs[i]).total);
+    }
+    *total = off;
+    return AXF_OK;
+}
+
 extern "C" {
 
-int axf_batch_footprint(const axf_config *, int32_t, size_t *) { return fail(AXF_EINVAL, "batches not built yet"); }
-int axf_batch_create(const axf_config *, int32_t, void *, size_t, void *, axf_batch **) { return fail(AXF_EINVAL, "batches not built yet"); }
-int axf_batch_step(axf_batch *, const int64_t *) { return fail(AXF_EINVAL, "batches not built yet"); }
-int axf_batch_run(axf_batch *, int32_t, axf_run **) { return fail(AXF_EINVAL, "batches not built yet"); }
-int axf_batch_destroy(axf_batch *) { return AXF_OK; }
-int axf_server_create(void *, size_t, int32_t, int32_t, void *, axf_server **) { return fail(AXF_EINVAL, "server not built yet"); }
-int axf_server_submit(axf_server *, const axf_config *, int64_t, uint64_t *) { return fail(AXF_EINVAL, "server not built yet"); }
-int axf_server_cancel(axf_server *, uint64_t) { return fail(AXF_EINVAL, "server not built yet"); }
-int axf_server_poll(axf_server *, axf_result *, int32_t, int32_t *) { return fail(AXF_EINVAL, "server not built yet"); }
-int axf_server_stats(axf_server *, int32_t *, int32_t *, size_t *) { return fail(AXF_EINVAL, "server not built yet"); }
-int axf_server_destroy(axf_server *) { return AXF_OK; }
-
+int axf_batch_footprint(const axf_config *cfgs, int32_t count, size_t *bytes)
+{
+    if (!bytes) return fail(AXF_EINVAL, "null output");
+    return batch_layout(cfgs, count, nullptr, bytes);
 }
+
+int axf_batch_create(const axf_config *cfgs, int32_t count, void *dev_buf, size_t bytes, void *stream,
+                     axf_batch **out)
+{
+    if (!out) return fail(AXF_EINVAL, "null output");
+    *out = nullptr;
+    std::vector<size_t> offs;
+    size_t total = 0;
+    int rc = batch_layout(cfgs, count, &offs, &total);
+    if (rc) return rc;
+    if (!dev_buf) return fail(AXF_EINVAL, "null device buffer");
+    if (((uintptr_t)dev_buf & 255) != 0) return fail(AXF_EINVAL, "device buffer must be 256-byte aligned");
+    if (bytes < total) return fail(AXF_ENOMEM, "device buffer of %zu bytes < batch footprint %zu", bytes, total);
+    axf_batch *B = new (std::nothrow) axf_batch();
+    if (!B) return fail(AXF_ENOMEM, "host allocation failed");
+    B->stream = (hipStream_t)stream;
+    char *base = (char *)dev_buf;
+    rc = B->eng.init((BItem *)base, Engine::entries_for(count));
+    for (int32_t i = 0; i < count && rc == AXF_OK; i++) {
+        axf_run *R = new (std::nothrow) axf_run();
+        if (!R) {
+            rc = fail(AXF_ENOMEM, "host allocation failed");
+            break;
+        }
+        R->batch_owned = true;
+        B->runs.push_back(R);
+        rc = run_init(R, &cfgs[i], base + offs[i], make_layout(&cfgs[i]).total, B->stream);
+    }
+    if (rc) {
+        for (auto *R : B->runs) delete R;
+        delete B;
+        return rc;
+    }
+    *out = B;
+    return AXF_OK;
+}
+
+int axf_batch_step(axf_batch *b, const int64_t *nsteps)
+{
+    if (!b || !nsteps) return fail(AXF_EINVAL, "null argument");
+    std::vector<Run *> runs(b->runs.begin(), b->runs.end());
+    return b->eng.step(runs.data(), nsteps, (int)runs.size(), b->stream);
+}
+
+int axf_batch_run(axf_batch *b, int32_t i, axf_run **view)
+{
+    if (!b || !view) return fail(AXF_EINVAL, "null argument");
+    if (i < 0 || i >= (int32_t)b->runs.size()) return fail(AXF_ENOTFOUND, "run %d not in the batch of %zu", i, b->runs.size());
+    *view = b->runs[i];
+    return AXF_OK;
+}
+
+int axf_batch_destroy(axf_batch *b)
+{
+    if (!b) return AXF_OK;
+    hipStreamSynchronize(b->stream);
+    for (auto *R : b->runs) {
+        if (R->ev0) hipEventDestroy(R->ev0);
+        if (R->ev1) hipEventDestroy(R->ev1);
+        delete R;
+    }
+    delete b;
+    return AXF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ server
+//
+// A host thread owns the GPU work.  Each round it admits queued requests that
+// fit (a free slot and a first-fit range of the pool), initialises them, and
+// advances every resident run by up to `macro_steps` steps through the engine,
+// so newly admitted runs join the batched launches of the runs already on the
+// device.  Runs that reach their step count (or are cancelled) are retired:
+// their final diagnostic record becomes the result and their memory returns to
+// the pool.  A request passed over for more than kStarveRounds rounds stops
+// later requests from overtaking it.
+
+namespace {
+
+constexpr int kStarveRounds = 4;
+
+struct Request {
+    uint64_t id;
+    axf_config cfg;
+    int64_t nsteps;
+    size_t bytes;
+    double t_submit;
+    int skipped = 0;
+};
+
+struct Resident {
+    uint64_t id;
+    axf_run *R;
+    int64_t nsteps, done;
+    size_t off, bytes;
+    double t_submit, t_admit;
+    bool cancel;
+};
+
+// first-fit allocator over [0, size) in 256-byte units
+class Pool {
+public:
+    void reset(size_t size) { free_.clear(); free_[0] = size; }
+    bool take(size_t bytes, size_t *off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            size_t rest = it->second - bytes, at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void give(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+};
+
+}  // namespace
+
+struct axf_server {
+    char *pool = nullptr;        // run memory (after the engine table)
+    size_t pool_bytes = 0;
+    int max_slots = 0;
+    int64_t macro = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Engine eng;
+    Pool alloc;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request> queue;
+    std::vector<Resident> res;
+    std::deque<axf_result> done;
+    std::set<uint64_t> cancels;
+    size_t used = 0;
+    uint64_t next_id = 1;
+    bool stop = false;
+    std::thread th;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+
+    void finish(Resident& r, int status, double t)
+    {
+        axf_result out{};
+        out.id = r.id;
+        out.status = status;
+        out.steps = r.done;
+        out.cells = (int64_t)r.R->cfg.n[0] * r.R->cfg.n[1] * r.R->cfg.n[2];
+        out.t_submit = r.t_submit;
+        out.t_admit = r.t_admit;
+        if (status == AXF_OK) {
+            int rc = run_diag_now(r.R, &out.final);
+            if (rc) out.status = rc;
+        }
+        out.t_done = t;
+        delete r.R;
+        std::lock_guard<std::mutex> lk(mu);
+        alloc.give(r.off, r.bytes);
+        used -= r.bytes;
+        done.push_back(out);
+    }
+
+    // a request that could not be started (no host memory): report and release
+    void fail_request(const Request& q, size_t off, int status, double t)
+    {
+        axf_result out{};
+        out.id = q.id;
+        out.status = status;
+        out.cells = (int64_t)q.cfg.n[0] * q.cfg.n[1] * q.cfg.n[2];
+        out.t_submit = q.t_submit;
+        out.t_admit = out.t_done = t;
+        std::lock_guard<std::mutex> lk(mu);
+        alloc.give(off, q.bytes);
+        used -= q.bytes;
+        done.push_back(out);
+    }
+
+    void loop()
+    {
+        hipSetDevice(device);
+        for (;;) {
+            std::vector<Request> admit;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stop || !queue.empty() || !res.empty(); });
+                if (stop) break;
+                for (auto& r : res)
+                    if (cancels.erase(r.id)) r.cancel = true;
+                int slots = max_slots - (int)res.size();
+                bool blocked = false;
+                for (auto it = queue.begin(); it != queue.end() && slots > 0;) {
+                    size_t off;
+                    if (!blocked && alloc.take(it->bytes, &off)) {
+                        used += it->bytes;
+                        admit.push_back(*it);
+                        pending_off.push_back(off);
+                        it = queue.erase(it);
+                        slots--;
+                    } else {
+                        if (++it->skipped > kStarveRounds) blocked = true;
+                        ++it;
+                    }
+                }
+            }
+            const double ta = now();
+            for (size_t k = 0; k < admit.size(); k++) {
+                Request& q = admit[k];
+                const size_t off = pending_off[k];
+                axf_run *R = new (std::nothrow) axf_run();
+                if (!R) {
+                    fail_request(q, off, AXF_ENOMEM, ta);
+                    continue;
+                }
+                R->batch_owned = true;
+                int rc = run_init(R, &q.cfg, pool + off, q.bytes, stream);
+                Resident r{q.id, R, q.nsteps, 0, off, q.bytes, q.t_submit, ta, false};
+                if (rc) {
+                    finish(r, rc, now());
+                    continue;
+                }
+                std::lock_guard<std::mutex> lk(mu);
+                res.push_back(r);
+            }
+            pending_off.clear();
+            if (res.empty()) continue;
+            std::vector<Run *> runs;
+            std::vector<int64_t> ns;
+            for (auto& r : res) {
+                runs.push_back(r.R);
+                ns.push_back(r.cancel ? 0 : std::min(macro, r.nsteps - r.done));
+            }
+            int rc = eng.step(runs.data(), ns.data(), (int)runs.size(), stream);
+            if (rc == AXF_OK && hipStreamSynchronize(stream) != hipSuccess) rc = AXF_EHIP;
+            const double t = now();
+            std::vector<Resident> keep;
+            for (size_t k = 0; k < res.size(); k++) {
+                Resident& r = res[k];
+                if (rc == AXF_OK) r.done += ns[k];
+                if (rc != AXF_OK) finish(r, rc, t);
+                else if (r.cancel) finish(r, 1, t);
+                else if (r.done >= r.nsteps) finish(r, AXF_OK, t);
+                else keep.push_back(r);
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            res.swap(keep);
+        }
+        // shut down: resident runs end as cancelled
+        for (auto& r : res) finish(r, 1, now());
+        res.clear();
+    }
+
+    std::vector<size_t> pending_off;
+};
+
+extern "C" {
+
+int axf_server_create(void *pool, size_t pool_bytes, int32_t max_slots, int32_t macro_steps, void *stream,
+                      axf_server **out)
+{
+    if (!out) return fail(AXF_EINVAL, "null output");
+    *out = nullptr;
+    if (!pool) return fail(AXF_EINVAL, "null pool");
+    if (((uintptr_t)pool & 255) != 0) return fail(AXF_EINVAL, "pool must be 256-byte aligned");
+    if (max_slots <= 0 || macro_steps <= 0) return fail(AXF_EINVAL, "max_slots and macro_steps must be positive");
+    const size_t table = align256(Engine::entries_for((size_t)max_slots) * sizeof(BItem));
+    if (pool_bytes <= table) return fail(AXF_ENOMEM, "pool of %zu bytes leaves no room for runs", pool_bytes);
+    hipPointerAttribute_t attr;
+    int device = 0;
+    if (hipPointerGetAttributes(&attr, pool) == hipSuccess) device = attr.device;
+    else hipGetDevice(&device);
+    axf_server *S = new (std::nothrow) axf_server();
+    if (!S) return fail(AXF_ENOMEM, "host allocation failed");
+    S->pool = (char *)pool + table;
+    S->pool_bytes = pool_bytes - table;
+    S->max_slots = max_slots;
+    S->macro = macro_steps;
+    S->stream = (hipStream_t)stream;
+    S->device = device;
+    S->alloc.reset(S->pool_bytes);
+    int rc = S->eng.init((BItem *)pool, Engine::entries_for((size_t)max_slots));
+    if (rc) {
+        delete S;
+        return rc;
+    }
+    S->th = std::thread([S] { S->loop(); });
+    *out = S;
+    return AXF_OK;
+}
+
+int axf_server_submit(axf_server *s, const axf_config *cfg, int64_t nsteps, uint64_t *id)
+{
+    if (!s || !cfg || !id) return fail(AXF_EINVAL, "null argument");
+    if (nsteps <= 0) return fail(AXF_EINVAL, "nsteps must be positive");
+    int rc = validate(cfg);
+    if (rc) return rc;
+    const size_t bytes = align256(make_layout(cfg).total);
+    if (bytes > s->pool_bytes) return fail(AXF_ENOMEM, "request of %zu bytes exceeds the pool of %zu", bytes, s->pool_bytes);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return fail(AXF_ESTATE, "server is shutting down");
+    Request q{s->next_id++, *cfg, nsteps, bytes, s->now()};
+    s->queue.push_back(q);
+    *id = q.id;
+    s->cv.notify_one();
+    return AXF_OK;
+}
+
+int axf_server_cancel(axf_server *s, uint64_t id)
+{
+    if (!s) return fail(AXF_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+        if (it->id != id) continue;
+        axf_result out{};
+        out.id = id;
+        out.status = 1;
+        out.cells = (int64_t)it->cfg.n[0] * it->cfg.n[1] * it->cfg.n[2];
+        out.t_submit = it->t_submit;
+        out.t_admit = out.t_done = s->now();
+        s->done.push_back(out);
+        s->queue.erase(it);
+        return AXF_OK;
+    }
+    for (auto& r : s->res)
+        if (r.id == id) {
+            s->cancels.insert(id);
+            return AXF_OK;
+        }
+    return fail(AXF_ENOTFOUND, "request %llu is neither queued nor resident", (unsigned long long)id);
+}
+
+int axf_server_poll(axf_server *s, axf_result *out, int32_t max, int32_t *n)
+{
+    if (!s || !n || (max > 0 && !out)) return fail(AXF_EINVAL, "bad argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    int32_t k = 0;
+    while (k < max && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n = k;
+    return AXF_OK;
+}
+
+int axf_server_stats(axf_server *s, int32_t *queued, int32_t *resident, size_t *bytes_used)
+{
+    if (!s) return fail(AXF_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (queued) *queued = (int32_t)s->queue.size();
+    if (resident) *resident = (int32_t)s->res.size();
+    if (bytes_used) *bytes_used = s->used;
+    return AXF_OK;
+}
+
+int axf_server_destroy(axf_server *s)
+{
+    if (!s) return AXF_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    if (s->th.joinable()) s->th.join();
+    hipStreamSynchronize(s->stream);
+    delete s;
+    return AXF_OK;
+}
+
+}  // extern "C"

@@ -19,5 +19,10 @@ struct Fused {
 // Fused 2D step on wavefront-owned x segments (no LDS, no barriers).
 template <typename T>
 hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st);
+// the same over the first n runs of a batch table at step s of the call
+template <typename T>
+hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st);
+// workgroups (4 wavefronts each) of one run's wavefront launch
+int wave2d_blocks(int nn0, int nn1, int chunk);
 
 }  // namespace axf

@@ -15,8 +15,6 @@
 //   S6  phi^{n+3/2} at plane t-2                (+ axion ghosts of the new level)
 // The point formulas are the ones of the unfused kernels, written in the same
 // operation order, so the two paths agree bit for bit.
-#include <stdlib.h>
-
 #include "axf_fused.h"
 #include "axf_stencil.h"
 
@@ -758,12 +756,12 @@ __device__ __forceinline__ double lane_dn(double v)
 
 constexpr int kWaveOut = 59;   // output columns per wavefront
 
-template <typename T, int MINW>
-__global__ void __launch_bounds__(256, MINW) k_wave2d(const RunK<T> *__restrict__ rp, long step, int nseg, int nch, int chunk)
+// wavefront gw (of nseg x nch) of one run's step
+template <typename T>
+__device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long step, int gw, int nseg, int nch, int chunk)
 {
     KV<T> r = make_kv(rp);
     const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (gw >= nseg * nch) return;      // whole wavefronts only: no barriers in this kernel
     const int seg = gw % nseg, ch = gw / nseg;
     const int so = (int)(step & 1), sn = so ^ 1;
@@ -1070,28 +1068,53 @@ __global__ void __launch_bounds__(256, MINW) k_wave2d(const RunK<T> *__restrict_
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256, 3) k_wave2d(const RunK<T> *__restrict__ rp, long step, int nseg, int nch, int chunk)
+{
+    wave2d_body<T>(rp, step, blockIdx.x * 4 + (threadIdx.x >> 6), nseg, nch, chunk);
+}
+
+// batched: every active run of the table, each with its own step and chunk
+template <typename T>
+__global__ void __launch_bounds__(256, 3) kb_wave2d(const BItem *__restrict__ it, int n, long s)
+{
+    const int i = find_item<kWave>(it, n, blockIdx.x);
+    const RunK<T> *rp = (const RunK<T> *)it[i].rk;
+    const int chunk = it[i].chunk;
+    const int nseg = (rp->nn[0] + kWaveOut - 1) / kWaveOut, nch = (rp->nn[1] + chunk - 1) / chunk;
+    const int gw = (int)(blockIdx.x - it[i].blk[kWave]) * 4 + (threadIdx.x >> 6);
+    wave2d_body<T>(rp, it[i].step0 + s, gw, nseg, nch, chunk);
+}
+
+int wave2d_blocks(int nn0, int nn1, int chunk)
+{
+    const long waves = (long)((nn0 + kWaveOut - 1) / kWaveOut) * ((nn1 + chunk - 1) / chunk);
+    return (int)((waves + 3) / 4);
+}
+
+template <typename T>
+hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st)
+{
+    const unsigned nb = (unsigned)host[n].blk[kWave];
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL((kb_wave2d<T>), dim3(nb), dim3(256), 0, st, it, n, s);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st)
 {
     int nseg = (h.nn[0] + kWaveOut - 1) / kWaveOut;
     int nch = (h.nn[1] + chunk - 1) / chunk;
     long waves = (long)nseg * nch;
     unsigned nb = (unsigned)((waves + 3) / 4);
-    static int occ = -1;
-    if (occ < 0) {
-        const char *e = getenv("AXF_WAVE_OCC");
-        occ = e ? atoi(e) : 3;
-    }
-    if (occ >= 4)
-        hipLaunchKernelGGL((k_wave2d<T, 4>), dim3(nb), dim3(256), 0, st, rk, step, nseg, nch, chunk);
-    else if (occ == 2)
-        hipLaunchKernelGGL((k_wave2d<T, 2>), dim3(nb), dim3(256), 0, st, rk, step, nseg, nch, chunk);
-    else
-        hipLaunchKernelGGL((k_wave2d<T, 3>), dim3(nb), dim3(256), 0, st, rk, step, nseg, nch, chunk);
+    hipLaunchKernelGGL((k_wave2d<T>), dim3(nb), dim3(256), 0, st, rk, step, nseg, nch, chunk);
     return hipGetLastError();
 }
 
 template hipError_t launch_wave2d<float>(const RunK<float> *, const RunK<float>&, long, int, hipStream_t);
 template hipError_t launch_wave2d<double>(const RunK<double> *, const RunK<double>&, long, int, hipStream_t);
+template hipError_t launch_wave2d_batch<float>(const BItem *, const BItem *, int, long, hipStream_t);
+template hipError_t launch_wave2d_batch<double>(const BItem *, const BItem *, int, long, hipStream_t);
 
 template <int D, int TX, int TY, typename T>
 size_t Fused<D, TX, TY, T>::lds_bytes() { return FK<D, TX, TY, T>::LDS; }

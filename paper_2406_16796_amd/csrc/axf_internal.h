@@ -86,4 +86,31 @@ struct RunK {
 
 __host__ __device__ inline long round_up(long v, long m) { return (v + m - 1) / m * m; }
 
+// One run of a batched launch.  A batched launch covers the first `n` runs of a
+// table sorted by remaining steps; blk[K] is the first block of the run in
+// launches of kind K, and entry n holds the totals.  Every run computes exactly
+// what its own single-run launch would.
+enum BlockKind { kVolume = 0, kFace = 1, kLaser = 2, kWave = 3, kNumKinds = 4 };
+struct BItem {
+    const void *rk;     // the run's RunK<T> (device)
+    long step0;         // the run's step counter at the first step of the call
+    long rec0;          // diagnostic records written before the call
+    long blk[kNumKinds];
+    int chunk;          // rows per wavefront march (fused 2D)
+    int pad;
+};
+
+// index of the run owning block b of a launch of kind K (largest i with blk[K] <= b)
+template <int K>
+__device__ __forceinline__ int find_item(const BItem *it, int n, long b)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (it[mid].blk[K] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 }  // namespace axf

@@ -19,6 +19,11 @@ struct Plain {
     static void init_phi(const RunK<T> *rk, const RunK<T>& h, hipStream_t st);
     static void copy_ghosts(const RunK<T> *rk, const RunK<T>& h, int s0, int s1, hipStream_t st);
     static void diag(const RunK<T> *rk, const RunK<T>& h, long step, int slot, hipStream_t st);
+    // batched launches over the first n runs of a sorted table (device `it`,
+    // host copy `host` for the grid sizes) at step s of the call
+    static void batch_step(const BItem *it, const BItem *host, int n, long s, hipStream_t st);
+    static void batch_inc_fill(const BItem *it, const BItem *host, int n, long s, int nlev, hipStream_t st);
+    static void batch_diag(const BItem *it, const BItem *host, int n, long s, long ev, hipStream_t st);
 };
 
 }  // namespace axf

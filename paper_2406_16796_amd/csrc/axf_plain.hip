@@ -39,11 +39,10 @@ __device__ __forceinline__ bool in_cell(const RunK<T>& r, int i, int j, int k)
 
 // E0_out = E0_in + scale * dt curl B0   (scale 1: step; -1/2: backward half step)
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_e0(const RunK<T> *__restrict__ rp, int s_in, int s_b, int s_out, T scale)
+__device__ __forceinline__ void e0_body(const RunK<T>& r, long bx, int s_in, int s_b, int s_out, T scale)
 {
-    const RunK<T>& r = *rp;
     int i, j, k;
-    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
     long id = lin(r, i, j, k);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -56,11 +55,10 @@ __global__ void __launch_bounds__(256) k_e0(const RunK<T> *__restrict__ rp, int 
 // C = (D_t phi) B0 - E0 x (D phi) at every centre for the integer time between
 // axion slots (a, b); E0 = mean of slots (e_m, e_p), or slot e_m alone if cotimed.
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_c(const RunK<T> *__restrict__ rp, int pa, int pb, int e_m, int e_p, int s_b, int cotimed)
+__device__ __forceinline__ void c_body(const RunK<T>& r, long bx, int pa, int pb, int e_m, int e_p, int s_b, int cotimed)
 {
-    const RunK<T>& r = *rp;
     int i, j, k;
-    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
     if (!in_cell(r, i, j, k)) return;
     long id = lin(r, i, j, k);
     T e[3], b[3], gp[3] = {T(0), T(0), T(0)};
@@ -109,11 +107,10 @@ __device__ __forceinline__ T face_S(const RunK<T>& r, int c, int i, int j, int k
 
 // E1_out = E1_in + scale * dt (curl B1 - g1 S)
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_e1(const RunK<T> *__restrict__ rp, int s_in, int s_b, int s_out, T scale)
+__device__ __forceinline__ void e1_body(const RunK<T>& r, long bx, int s_in, int s_b, int s_out, T scale)
 {
-    const RunK<T>& r = *rp;
     int i, j, k;
-    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
     long id = lin(r, i, j, k);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -163,13 +160,12 @@ __device__ __forceinline__ void mur_point(const RunK<T>& r, long step, int d, in
 }
 
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_mur(const RunK<T> *__restrict__ rp, long step)
+__device__ __forceinline__ void mur_body(const RunK<T>& r, long bx, long step)
 {
-    const RunK<T>& r = *rp;
     const int d = blockIdx.y >> 1, side = blockIdx.y & 1;
     if (d >= D || !r.mur[d]) return;
     const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
-    long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long p = bx * 256 + threadIdx.x;
     long na = r.nn[a], nb = r.nn[b];
     if (p >= na * nb) return;
     int ia = (int)(p % na), ib = (int)(p / na);
@@ -184,10 +180,9 @@ __global__ void __launch_bounds__(256) k_mur(const RunK<T> *__restrict__ rp, lon
 // laser field at the x_min face for time levels L0 .. L0 + nlev - 1 (t = (L - 1/2) dt),
 // at the first interior centre and at the ghost centre, into slot L mod inc_k1
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_inc_fill(const RunK<T> *__restrict__ rp, long L0, int nlev)
+__device__ __forceinline__ void inc_fill_body(const RunK<T>& r, long bx, long L0, int nlev)
 {
-    const RunK<T>& r = *rp;
-    long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long p = bx * 256 + threadIdx.x;
     if (p >= r.inc_face) return;
     const int c = r.las.pol;
     int j = (int)(p % r.nn[1]), k = (int)(p / r.nn[1]);
@@ -234,11 +229,10 @@ __global__ void k_mur_init(const RunK<T> *__restrict__ rp)
 
 // B^{n+1} = B^n - dt curl E^{n+1/2}, both orders, old slot -> new slot
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_b(const RunK<T> *__restrict__ rp, long step)
+__device__ __forceinline__ void b_body(const RunK<T>& r, long bx, long step)
 {
-    const RunK<T>& r = *rp;
     int i, j, k;
-    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
     long id = lin(r, i, j, k);
     const int so = (int)(step & 1), sn = so ^ 1;
 #pragma unroll
@@ -255,11 +249,10 @@ __global__ void __launch_bounds__(256) k_b(const RunK<T> *__restrict__ rp, long 
 // t_{n+1/2} (Sec. II.C, eq. update_axion), in the damped form of the PML
 // layer (Sec. II.D) where sigma > 0, then the ghosts of the new level.
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_phi(const RunK<T> *__restrict__ rp, long step)
+__device__ __forceinline__ void phi_body(const RunK<T>& r, long bx, long step)
 {
-    const RunK<T>& r = *rp;
     int i, j, k;
-    if (!decompose(r, blockIdx.x * (long)blockDim.x + threadIdx.x, i, j, k)) return;
+    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
     if (!in_cell(r, i, j, k)) return;
     long id = lin(r, i, j, k);
     const int so = (int)(step & 1), sn = so ^ 1;
@@ -389,12 +382,11 @@ __device__ __forceinline__ void block_sum4(double v[4], double *out)
 // energies at t_n: E^n = mean of the two E slots, B^n = old slot, phi^n = mean
 // of the axion levels; H_phi = sum ((D_t phi)^2 + sum_d (D+_d phi)^2 + m^2 phi^2) / 2
 template <int D, typename T>
-__global__ void __launch_bounds__(256) k_diag(const RunK<T> *__restrict__ rp, long step)
+__device__ __forceinline__ void diag_body(const RunK<T>& r, long bx, long step)
 {
-    const RunK<T>& r = *rp;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     int i, j, k;
-    long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long p = bx * 256 + threadIdx.x;
     if (decompose(r, p, i, j, k)) {
         long id = lin(r, i, j, k);
         const int so = (int)(step & 1), sn = so ^ 1;
@@ -446,14 +438,13 @@ __global__ void __launch_bounds__(256) k_diag(const RunK<T> *__restrict__ rp, lo
         }
         v[3] = fin ? 0.0 : 1.0;
     }
-    block_sum4(v, r.part + blockIdx.x * 4);
+    block_sum4(v, r.part + bx * 4);
 }
 
 // fixed-order sum of the block partials into record slot `slot`
 template <typename T>
-__global__ void __launch_bounds__(256) k_diag_final(const RunK<T> *__restrict__ rp, long step, int slot)
+__device__ __forceinline__ void diag_final_body(const RunK<T>& r, long step, int slot)
 {
-    const RunK<T>& r = *rp;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int blk = threadIdx.x; blk < r.diag_blocks; blk += blockDim.x)
 #pragma unroll
@@ -476,6 +467,110 @@ __global__ void __launch_bounds__(256) k_diag_final(const RunK<T> *__restrict__ 
         rec.pad = 0;
         r.rec[slot] = rec;
     }
+}
+
+// ------------------------------------------------------ single-run kernels
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_e0(const RunK<T> *__restrict__ rp, int s_in, int s_b, int s_out, T scale)
+{
+    e0_body<D, T>(*rp, blockIdx.x, s_in, s_b, s_out, scale);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_c(const RunK<T> *__restrict__ rp, int pa, int pb, int e_m, int e_p, int s_b, int cotimed)
+{
+    c_body<D, T>(*rp, blockIdx.x, pa, pb, e_m, e_p, s_b, cotimed);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_e1(const RunK<T> *__restrict__ rp, int s_in, int s_b, int s_out, T scale)
+{
+    e1_body<D, T>(*rp, blockIdx.x, s_in, s_b, s_out, scale);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_mur(const RunK<T> *__restrict__ rp, long step)
+{
+    mur_body<D, T>(*rp, blockIdx.x, step);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_inc_fill(const RunK<T> *__restrict__ rp, long L0, int nlev)
+{
+    inc_fill_body<D, T>(*rp, blockIdx.x, L0, nlev);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_b(const RunK<T> *__restrict__ rp, long step)
+{
+    b_body<D, T>(*rp, blockIdx.x, step);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_phi(const RunK<T> *__restrict__ rp, long step)
+{
+    phi_body<D, T>(*rp, blockIdx.x, step);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_diag(const RunK<T> *__restrict__ rp, long step)
+{
+    diag_body<D, T>(*rp, blockIdx.x, step);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag_final(const RunK<T> *__restrict__ rp, long step, int slot)
+{
+    diag_final_body<T>(*rp, step, slot);
+}
+
+// ---------------------------------------------------------- batched kernels
+//
+// One launch advances one phase of every active run of a batch group; block b
+// belongs to the run found by find_item and runs that run's own body with the
+// run's own step counter (step0 + s), so each run's arithmetic and block
+// partition are those of its single-run launch.
+
+enum BatchPhase { kPhE0 = 0, kPhC, kPhE1, kPhB, kPhPhi, kPhDiag };
+
+template <int D, typename T, int PH>
+__global__ void __launch_bounds__(256) kb_volume(const BItem *__restrict__ it, int n, long s)
+{
+    const int i = find_item<kVolume>(it, n, blockIdx.x);
+    const RunK<T>& r = *(const RunK<T> *)it[i].rk;
+    const long bx = blockIdx.x - it[i].blk[kVolume];
+    const long step = it[i].step0 + s;
+    const int so = (int)(step & 1), sn = so ^ 1, la = (int)(step % 3), lb = (int)((step + 1) % 3);
+    if (PH == kPhE0) e0_body<D, T>(r, bx, so, so, sn, T(1));
+    else if (PH == kPhC) c_body<D, T>(r, bx, la, lb, so, sn, so, 0);
+    else if (PH == kPhE1) e1_body<D, T>(r, bx, so, so, sn, T(1));
+    else if (PH == kPhB) b_body<D, T>(r, bx, step);
+    else if (PH == kPhPhi) phi_body<D, T>(r, bx, step);
+    else diag_body<D, T>(r, bx, step);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) kb_mur(const BItem *__restrict__ it, int n, long s)
+{
+    const int i = find_item<kFace>(it, n, blockIdx.x);
+    mur_body<D, T>(*(const RunK<T> *)it[i].rk, blockIdx.x - it[i].blk[kFace], it[i].step0 + s);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) kb_inc_fill(const BItem *__restrict__ it, int n, long s, int nlev)
+{
+    const int i = find_item<kLaser>(it, n, blockIdx.x);
+    inc_fill_body<D, T>(*(const RunK<T> *)it[i].rk, blockIdx.x - it[i].blk[kLaser], it[i].step0 + s, nlev);
+}
+
+// one block per run: record `ev` of this call goes to slot (rec0 + ev) mod rec_cap
+template <typename T>
+__global__ void __launch_bounds__(256) kb_diag_final(const BItem *__restrict__ it, long s, long ev)
+{
+    const BItem& b = it[blockIdx.x];
+    const RunK<T>& r = *(const RunK<T> *)b.rk;
+    diag_final_body<T>(r, b.step0 + s, (int)((b.rec0 + ev) % r.rec_cap));
 }
 
 // ------------------------------------------------------------------ launchers
@@ -563,6 +658,35 @@ void Plain<D, T>::diag(const RunK<T> *rk, const RunK<T>& h, long step, int slot,
 {
     hipLaunchKernelGGL((k_diag<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
     hipLaunchKernelGGL((k_diag_final<T>), dim3(1), dim3(256), 0, st, rk, step, slot);
+}
+
+template <int D, typename T>
+void Plain<D, T>::batch_step(const BItem *it, const BItem *host, int n, long s, hipStream_t st)
+{
+    const unsigned nv = (unsigned)host[n].blk[kVolume], nf = (unsigned)host[n].blk[kFace];
+    if (nv == 0) return;
+    hipLaunchKernelGGL((kb_volume<D, T, kPhE0>), dim3(nv), dim3(256), 0, st, it, n, s);
+    hipLaunchKernelGGL((kb_volume<D, T, kPhC>), dim3(nv), dim3(256), 0, st, it, n, s);
+    hipLaunchKernelGGL((kb_volume<D, T, kPhE1>), dim3(nv), dim3(256), 0, st, it, n, s);
+    if (nf > 0) hipLaunchKernelGGL((kb_mur<D, T>), dim3(nf, 2 * D), dim3(256), 0, st, it, n, s);
+    hipLaunchKernelGGL((kb_volume<D, T, kPhB>), dim3(nv), dim3(256), 0, st, it, n, s);
+    hipLaunchKernelGGL((kb_volume<D, T, kPhPhi>), dim3(nv), dim3(256), 0, st, it, n, s);
+}
+
+template <int D, typename T>
+void Plain<D, T>::batch_inc_fill(const BItem *it, const BItem *host, int n, long s, int nlev, hipStream_t st)
+{
+    const unsigned nl = (unsigned)host[n].blk[kLaser];
+    if (nl > 0) hipLaunchKernelGGL((kb_inc_fill<D, T>), dim3(nl), dim3(256), 0, st, it, n, s, nlev);
+}
+
+template <int D, typename T>
+void Plain<D, T>::batch_diag(const BItem *it, const BItem *host, int n, long s, long ev, hipStream_t st)
+{
+    const unsigned nv = (unsigned)host[n].blk[kVolume];
+    if (nv == 0) return;
+    hipLaunchKernelGGL((kb_volume<D, T, kPhDiag>), dim3(nv), dim3(256), 0, st, it, n, s);
+    hipLaunchKernelGGL((kb_diag_final<T>), dim3(n), dim3(256), 0, st, it, s, ev);
 }
 
 template struct Plain<1, float>;

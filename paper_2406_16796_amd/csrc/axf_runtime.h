@@ -48,8 +48,8 @@ struct Run {
     bool batch_owned = false;
     bool use_fused = false;
     int chunk = 0;                 // fused planes per workgroup (0: default)
-    bool lds_march = false;
-    long inc_lo = -1;               // first time level held by the laser table        // 2D: use the LDS-marching kernel instead of the wavefront one
+    bool lds_march = false;          // 2D fused: the LDS-marching kernel instead of the wavefront one
+    long inc_lo = -1;               // first time level held by the laser table
 
     template <typename T> const RunK<T>& hk() const;
     template <typename T> const RunK<T> *rk() const { return (const RunK<T> *)(base + L.off_rk); }
@@ -64,6 +64,15 @@ int validate(const axf_config *c);
 Layout make_layout(const axf_config *c);
 int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStream_t stream);
 int run_step(Run *R, int64_t nsteps);
+// leapfrog conversion before the first step (idempotent)
+int run_prepare(Run *R);
+// the run steps with the 2D wavefront kernel; its rows per march
+bool run_wave2d(const Run *R);
+int run_wave_chunk(const Run *R);
+int run_diag_now(Run *R, axf_diag_record *out);
 bool fused_supported(const axf_config *c);
 
 }  // namespace axf
+
+// the opaque handle of the C ABI is the run object itself
+struct axf_run : public axf::Run {};

@@ -355,8 +355,8 @@ static int steps_fused(Run *R, int64_t nsteps)
         const RunK<T>& h = R->hk<T>();
         const RunK<T> *rk = R->rk<T>();
         int chunk = R->chunk > 0 ? R->chunk : FusedShape<D, T>::chunk;
-        const bool wave2d = D == 2 && !R->lds_march;
-        if (wave2d && R->chunk <= 0) chunk = 32;
+        const bool wave2d = run_wave2d(R);
+        if (wave2d) chunk = run_wave_chunk(R);
         for (int64_t it = 0; it < nsteps; it++) {
             long s = R->step;
             ensure_incident<D, T>(R, s);
@@ -455,6 +455,24 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     HIPCHK(hipStreamSynchronize(stream));
     return AXF_OK;
 }
+
+template <int D, typename T>
+static void prepare_impl(Run *R)
+{
+    if (!R->converted) convert_to_leapfrog<D, T>(R);
+    R->ephase_step = -1;
+}
+
+int run_prepare(Run *R)
+{
+    AXF_DISPATCH(R, prepare_impl, R);
+    HIPCHK(hipGetLastError());
+    return AXF_OK;
+}
+
+bool run_wave2d(const Run *R) { return R->use_fused && R->cfg.ndim == 2 && !R->lds_march; }
+
+int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 32; }
 
 int run_step(Run *R, int64_t nsteps)
 {
@@ -659,7 +677,6 @@ int run_write_state(Run *R, const void *buf, size_t bytes)
 
 using namespace axf;
 
-struct axf_run : public axf::Run {};
 
 extern "C" {
 

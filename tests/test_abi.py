@@ -63,3 +63,15 @@ def test_one_d_rejects_longitudinal_bext():
     with pytest.raises(axf.AxfError) as e:
         axf.footprint(cfg)
     assert e.value.code == axf.EINVAL
+
+
+def test_batch_footprint_is_the_sum_of_run_footprints():
+    """Host-only: the batch carves each run at a 256-byte boundary after the
+    launch table, so its footprint is the sum of the runs' plus the table."""
+    cfgs = [W.plane_wave_1d(nx=1000), W.gaussian_2d(n=64), W.plane_wave_1d(nx=3000)]
+    total = axf.batch_footprint(cfgs, precision=axf.F32)
+    runs = sum((axf.footprint(c, precision=axf.F32) + 255) // 256 * 256 for c in cfgs)
+    assert runs < total <= runs + 64 * 1024
+    bad = dict(cfgs[1], dt=10.0)
+    with pytest.raises(axf.AxfError):
+        axf.batch_footprint([cfgs[0], bad], precision=axf.F32)

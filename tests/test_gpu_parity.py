@@ -110,7 +110,7 @@ def test_1d_fp64_matches_oracle(axf, ax_bc):
     check_energies(run.diag_now(), ora, 1e-10)
 
 
-@pytest.mark.parametrize("ax_bc", [W.AX_OUTFLOW, W.AX_PML])
+@pytest.mark.parametrize("ax_bc", [W.AX_OUTFLOW, W.AX_PML, W.AX_REFLECT])
 def test_2d_fp64_matches_oracle(axf, ax_bc):
     cfg = small_2d(ax_bc)
     run, ora = run_both(axf, cfg, axf.F64, cfg["steps"])
@@ -167,13 +167,14 @@ def test_fp32_tracks_oracle(axf, kind):
     assert abs(rec["h_em1"] / h[2] - 1) < 1e-3
 
 
-@pytest.mark.parametrize("kind", ["2d_out", "2d_pml", "3d"])
+@pytest.mark.parametrize("kind", ["2d_out", "2d_pml", "2d_ref", "3d"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_fused_equals_plain_bitwise(axf, kind, prec):
     """The fused one-pass kernel evaluates the same point formulas in the same
     order as the unfused kernels (no FP contraction), so the states agree bit
     for bit, boundaries included."""
-    cfg = {"2d_out": small_2d(W.AX_OUTFLOW), "2d_pml": small_2d(W.AX_PML), "3d": small_3d()}[kind]
+    cfg = {"2d_out": small_2d(W.AX_OUTFLOW), "2d_pml": small_2d(W.AX_PML), "2d_ref": small_2d(W.AX_REFLECT),
+           "3d": small_3d()}[kind]
     p = axf.F32 if prec == "f32" else axf.F64
     runs = []
     for path in (axf.PATH_PLAIN, axf.PATH_FUSED):
