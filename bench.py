@@ -40,10 +40,12 @@ COPY_BYTES = 1 << 30
 KERNEL_SOURCES = ["paper_2406_16796_amd/csrc/axf_fused.hip", "paper_2406_16796_amd/csrc/axf_fused.h",
                   "paper_2406_16796_amd/csrc/axf_stencil.h", "paper_2406_16796_amd/csrc/axf_internal.h",
                   "paper_2406_16796_amd/build.py"]
+# workload -> (generator, file tag of the step kernels, kernel-name patterns of
+# one step's launches)
 WORKLOADS = {
-    "2d": ("gaussian_2d", "k_wave2d"),
-    "3d": ("focused_3d", "k_e1"),
-    "1d": ("plane_wave_1d", "k_e1"),
+    "2d": ("gaussian_2d", "k_wave2d", ["k_wave2d_int<", "k_wave2d<"]),
+    "3d": ("focused_3d", "plain_step", ["k_e0<", "k_c<", "k_e1<", "k_mur<", "k_b<", "k_phi<"]),
+    "1d": ("plane_wave_1d", "plain_step", ["k_e0<", "k_c<", "k_e1<", "k_mur<", "k_b<", "k_phi<"]),
 }
 
 
@@ -158,6 +160,118 @@ def cpu_baseline(cfg, target_s=15.0):
                       % ("x".join(map(str, n)), steps, dt)}
 
 
+def scan_leg(axf, torch, steps_scale, count=512):
+    """Batched parameter scan (512 runs: 1D 1k-64k cells, 2D 256^2-1024^2, step
+    counts scaled by steps_scale) against the same runs launched one by one."""
+    from paper_2406_16796_amd import workloads as W
+    cfgs = W.scan_runs(count=count)
+    steps = [max(1, int(round(c["steps"] * steps_scale))) for c in cfgs]
+    work = sum(W.active_cells(c) * n for c, n in zip(cfgs, steps))
+    batch = axf.Batch(cfgs, precision=axf.F32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    probe = list(range(0, count, max(1, count // 8)))
+    p_batch = {i: batch.runs[i].diag_now()["p_gen"] for i in probe}
+    batch.close()
+    del batch
+    torch.cuda.empty_cache()
+    # one run at a time, each with its own launches
+    t_alone = 0.0
+    p_alone = {}
+    for i, (c, n) in enumerate(zip(cfgs, steps)):
+        run = axf.Run(c, precision=axf.F32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.step(n)
+        run.sync()
+        t_alone += time.perf_counter() - t0
+        if i in probe:
+            p_alone[i] = run.diag_now()["p_gen"]
+        run.close()
+        del run
+    torch.cuda.empty_cache()
+    return {"runs": count, "steps_scale": steps_scale, "cell_updates": work,
+            "batched": round(work / t_batch / 1e9, 3), "per_run": round(work / t_alone / 1e9, 3),
+            "unit": "Gcell-updates/s", "speedup": round(t_alone / t_batch, 3),
+            "batched_s": round(t_batch, 3), "per_run_s": round(t_alone, 3),
+            "p_bitwise_equal": all(p_batch[i] == p_alone[i] for i in probe)}
+
+
+def percentile(v, q):
+    v = sorted(v)
+    if not v:
+        return None
+    k = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
+    return v[k]
+
+
+def serve_leg(axf, torch, rates, count, steps_scale, pool_gb, max_slots=64, macro=16):
+    """Poisson arrivals of conversion requests (90% like the scan, 10% 3D
+    128^3-256^3), served by the continuous-batching server and, for the same
+    trace, one request at a time in arrival order (per-request launches).
+    Latency = completion - arrival, reported for all requests and for the
+    1D/2D ("small") and 3D requests apart."""
+    from paper_2406_16796_amd import workloads as W
+
+    def stats(lat, kinds, span, work):
+        small = [v for v, k in zip(lat, kinds) if k < 3]
+        big = [v for v, k in zip(lat, kinds) if k == 3]
+        r4 = lambda v: None if v is None else round(v, 4)
+        return {"Gcell_s": round(work / span / 1e9, 3), "req_s": round(len(lat) / span, 2),
+                "p50_s": r4(percentile(lat, 50)), "p99_s": r4(percentile(lat, 99)),
+                "small_p50_s": r4(percentile(small, 50)), "small_p99_s": r4(percentile(small, 99)),
+                "3d_p50_s": r4(percentile(big, 50)), "3d_p99_s": r4(percentile(big, 99))}
+
+    out = []
+    for rate in rates:
+        trace = W.serving_requests(count=count, rate=rate)
+        reqs = [(t, c, max(1, int(round(c["steps"] * steps_scale)))) for t, c in trace]
+        ndim = [sum(1 for v in c["n"] if v > 1) for _, c, _ in reqs]
+        work = sum(W.active_cells(c) * n for _, c, n in reqs)
+        srv = axf.Server(int(pool_gb * (1 << 30)), max_slots=max_slots, macro_steps=macro)
+        lat, kinds, ids = [], [], {}
+        t0 = time.perf_counter()
+        i = 0
+        while len(lat) < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i][0] <= now:
+                ids[srv.submit(reqs[i][1], reqs[i][2])] = i
+                i += 1
+            for r in srv.poll():
+                if r["status"] != 0:
+                    raise SystemExit("served request failed with status %d" % r["status"])
+                lat.append(r["t_done"] - r["t_submit"])
+                kinds.append(ndim[ids[r["id"]]])
+            time.sleep(0.0005)
+        span = time.perf_counter() - t0
+        srv.close()
+        del srv
+        torch.cuda.empty_cache()
+        # the same trace, one request at a time in arrival order
+        fifo = []
+        t0 = time.perf_counter()
+        for t_arr, c, n in reqs:
+            now = time.perf_counter() - t0
+            if now < t_arr:
+                time.sleep(t_arr - now)
+            run = axf.Run(c, precision=axf.F32)
+            run.step(n)
+            run.diag_now()
+            fifo.append(time.perf_counter() - t0 - t_arr)
+            run.close()
+            del run
+        fifo_span = time.perf_counter() - t0
+        torch.cuda.empty_cache()
+        out.append({"offered_req_s": rate, "requests": len(reqs), "cell_updates": work,
+                    "server": stats(lat, kinds, span, work),
+                    "fifo_per_request": stats(fifo, ndim, fifo_span, work)})
+    return {"steps_scale": steps_scale, "pool_GB": pool_gb, "max_slots": max_slots,
+            "slice_cell_updates": macro * (1 << 20), "points": out}
+
+
 def pmc_rows(path):
     """(kernel name, counter value) per dispatch from a rocprofv3 counter CSV."""
     out = []
@@ -172,18 +286,24 @@ def pmc_summary(args):
     readings of the device copy of known size, write the summary file."""
     cfg = workload(args.workload)
     tag = workload_tag(cfg, args.precision)
-    kernel = WORKLOADS[args.workload][1]
+    kernel, pats = WORKLOADS[args.workload][1], WORKLOADS[args.workload][2]
     res = {}
     for counter, path in (("FETCH_SIZE", args.pmc_summary[0]), ("WRITE_SIZE", args.pmc_summary[1])):
         rows = pmc_rows(path)
         copy = [v for k, v in rows if "neg" in k.lower()]
-        step = [v for k, v in rows if kernel in k]
-        if not copy or not step:
-            raise SystemExit("no copy or %s dispatches in %s" % (kernel, path))
+        if not copy:
+            raise SystemExit("no copy dispatches in %s" % path)
         kib_copy = max(copy)
         factor = COPY_BYTES / (kib_copy * 1024.0)
-        kib_step = sum(step) / len(step)
-        res[counter] = (kib_copy, factor, kib_step, len(step), kib_step * 1024.0 * factor)
+        # one step = one dispatch of each pattern: sum of the per-kernel means
+        kib_step, ndisp = 0.0, 0
+        for pat in pats:
+            vals = [v for k, v in rows if pat in k.replace(" ", "")]
+            if not vals:
+                raise SystemExit("no %s dispatches in %s" % (pat, path))
+            kib_step += sum(vals) / len(vals)
+            ndisp = max(ndisp, len(vals))
+        res[counter] = (kib_copy, factor, kib_step, ndisp, kib_step * 1024.0 * factor)
     ndim = sum(1 for v in cfg["n"] if v > 1)
     esize = 4 if args.precision == "f32" else 8
     nc = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
@@ -203,14 +323,14 @@ def pmc_summary(args):
              "    python3 $REPO/bench.py --workload %s --precision %s --steps %d --pmc-summary "
              "<fetch counter_collection.csv> <write counter_collection.csv>"
              % (args.workload, args.precision, args.steps), "",
-             "| counter | copy kernel KiB | scale (bytes per KiB read) | %s KiB per launch (mean of %d) | bytes per launch |"
-             % (kernel, res["FETCH_SIZE"][3]),
+             "| counter | copy kernel KiB | scale (bytes per KiB read) | %s KiB per step (mean of %d) | bytes per step |"
+             % (" + ".join(p.rstrip("<") for p in pats), res["FETCH_SIZE"][3]),
              "|---|---|---|---|---|"]
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
         kc, fac, ks, _, b = res[counter]
         lines.append("| %s | %.0f | %.4f x 1024 | %.0f | %.4g |" % (counter, kc, fac, ks, b))
     lines += ["",
-              "Algorithmic bytes per launch: %d words x %d B x %d cells = %.4g B; measured / algorithmic = %.3f."
+              "Algorithmic bytes per step: %d words x %d B x %d cells = %.4g B; measured / algorithmic = %.3f."
               % (words_per_cell(ndim), esize, nc, algo, traffic / algo), "",
               "- `traffic_bytes_per_launch = %.6g`" % traffic,
               "- `algorithmic_bytes_per_launch = %d`" % algo,
@@ -225,7 +345,7 @@ def trace_summary(args):
     """Per-kernel call count and mean duration from a rocprofv3 kernel_stats CSV."""
     cfg = workload(args.workload)
     tag = workload_tag(cfg, args.precision)
-    kernel = WORKLOADS[args.workload][1]
+    kernel, pats = WORKLOADS[args.workload][1], WORKLOADS[args.workload][2]
     rows = list(csv.DictReader(open(args.trace_summary)))
     cmd = ("python3 $REPO/bench.py --workload %s --precision %s --steps %d --no-cpu-baseline"
            % (args.workload, args.precision, args.steps))
@@ -245,10 +365,12 @@ def trace_summary(args):
         lines.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f |" % (
             short, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
             float(r["Percentage"])))
-    dom = [r for r in rows if kernel in r["Name"]]
-    if dom:
-        lines += ["", "- `%s_mean_us = %.2f`" % (kernel, float(dom[0]["AverageNs"]) / 1e3),
-                  "- `kernel_source_sha256 = %s`" % kernel_source_hash()]
+    lines.append("")
+    for pat in pats:
+        dom = [r for r in rows if pat in r["Name"].replace(" ", "")]
+        if dom:
+            lines.append("- `%s_mean_us = %.2f`" % (pat.rstrip("<"), float(dom[0]["AverageNs"]) / 1e3))
+    lines.append("- `kernel_source_sha256 = %s`" % kernel_source_hash())
     path = os.path.join(ROOT, "profiles", "%s_%s_kernel_trace.md" % (kernel, tag))
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -268,6 +390,14 @@ def main():
     ap.add_argument("--profile-only", action="store_true")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV")
+    ap.add_argument("--no-scan", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--steps-scale", type=float, default=0.1,
+                    help="step counts of the scan and serving legs relative to the workload's 1000-5000")
+    ap.add_argument("--serve-rates", default="8,16,32")
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-slice", type=int, default=256,
+                    help="server work slice per run and round, in units of 2^20 cell-updates")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only (--gpus %d requested): the step is a single-GPU kernel; "
@@ -289,7 +419,7 @@ def main():
     ndim = sum(1 for v in cfg["n"] if v > 1)
     nc = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
     tag = workload_tag(cfg, args.precision)
-    kernel = WORKLOADS[args.workload][1]
+    kernel, pats = WORKLOADS[args.workload][1], WORKLOADS[args.workload][2]
 
     copy_gbs = device_copy(torch)
     if args.profile_only:
@@ -301,9 +431,11 @@ def main():
     wall, _, _, rec, fused = time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, args.warmup,
                                        args.diag_every)
     value = nc * args.steps / wall / 1e9
-    # the dominant kernel alone: step launches only, HIP events on the run's stream
+    # the step kernels alone (no diagnostics): HIP events on the run's stream
+    # around the timed steps; one fused 2D step is the interior launch plus the
+    # boundary-frame launch running beside it on a second stream
     _, k_ms, k_launches, _, _ = time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, 2, 0)
-    per_launch_s = k_ms / 1e3 / max(k_launches, 1)
+    per_launch_s = k_ms / 1e3 / args.steps
     algo_bytes = words_per_cell(ndim) * esize * nc
     achieved = algo_bytes / per_launch_s / 1e9
     traffic = read_traffic(tag, kernel) if fused else None
@@ -312,7 +444,7 @@ def main():
     plain_value = nc * args.plain_steps / p_wall / 1e9
 
     line = {
-        "metric": "Gcell-updates/s + % HBM roofline (fused vs plain)",
+        "metric": "Gcell-updates/s + % HBM roofline (fused vs plain); p50/p99 latency of served scans",
         "value": round(value, 3),
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
@@ -333,8 +465,9 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": round(traffic) if traffic is not None else None,
-            "kernel": kernel if fused else "plain phase sequence", "bytes_per_launch": algo_bytes,
-            "mean_launch_ms": round(per_launch_s * 1e3, 5), "launches": k_launches,
+            "kernel": " + ".join(p.rstrip("<") for p in pats) if fused else "plain phase sequence",
+            "unit_of_work": "one fused step of the whole grid", "bytes_per_step": algo_bytes,
+            "mean_step_ms": round(per_launch_s * 1e3, 5), "steps_timed": args.steps,
             "copy_kernel_GBs": round(copy_gbs, 1),
         },
         "plain": {"value": round(plain_value, 3), "unit": "Gcell-updates/s",
@@ -343,6 +476,12 @@ def main():
                   "fused_speedup": round(value / plain_value, 3) if plain_value > 0 else None},
         "diag": {"step": rec["step"], "p_gen": rec["p_gen"], "p_conv": rec["p_conv"], "finite": rec["finite"]},
     }
+    if not args.no_scan:
+        line["scan"] = scan_leg(axf, torch, args.steps_scale)
+    if not args.no_serve:
+        rates = [float(v) for v in args.serve_rates.split(",") if v]
+        line["serving"] = serve_leg(axf, torch, rates, args.serve_requests, args.steps_scale, pool_gb=64,
+                                    macro=args.serve_slice)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

@@ -49,7 +49,11 @@ static void run_blocks(const Run *R, bool wave, long blk[kNumKinds])
     }
     blk[kFace] = cdiv(face, 256);
     blk[kLaser] = R->cfg.laser_on ? cdiv(L.inc_face, 256) : 0;
-    blk[kWave] = wave ? wave2d_blocks(L.nn[0], L.nn[1], run_wave_chunk(R)) : 0;
+    blk[kWave] = blk[kWaveI] = 0;
+    if (wave) {
+        if (R->cfg.precision == AXF_F64) wave2d_blocks(R->hk<double>(), run_wave_chunk(R), &blk[kWave], &blk[kWaveI]);
+        else wave2d_blocks(R->hk<float>(), run_wave_chunk(R), &blk[kWave], &blk[kWaveI]);
+    }
 }
 
 // ------------------------------------------------------------------ engine
@@ -64,7 +68,16 @@ struct Group {
 
 class Engine {
 public:
-    ~Engine() { if (host_) hipHostFree(host_); }
+    ~Engine()
+    {
+        if (host_) hipHostFree(host_);
+        if (ws_.side) {
+            hipStreamSynchronize(ws_.side);
+            hipEventDestroy(ws_.fork);
+            hipEventDestroy(ws_.join);
+            hipStreamDestroy(ws_.side);
+        }
+    }
 
     // `dev` holds `cap` table entries of device memory owned by the caller
     int init(BItem *dev, size_t cap)
@@ -72,6 +85,9 @@ public:
         dev_ = dev;
         cap_ = cap;
         BCHK(hipHostMalloc((void **)&host_, cap * sizeof(BItem), hipHostMallocDefault));
+        BCHK(hipStreamCreateWithFlags(&ws_.side, hipStreamNonBlocking));
+        BCHK(hipEventCreateWithFlags(&ws_.fork, hipEventDisableTiming));
+        BCHK(hipEventCreateWithFlags(&ws_.join, hipEventDisableTiming));
         return AXF_OK;
     }
 
@@ -85,6 +101,7 @@ private:
 
     BItem *dev_ = nullptr, *host_ = nullptr;
     size_t cap_ = 0;
+    WaveStreams ws_{nullptr, nullptr, nullptr};   // side stream of the 2D frame launches
 };
 
 template <int D, typename T>
@@ -96,7 +113,7 @@ int Engine::group_step(Group& g, long s, std::vector<int64_t>& nrec, Run *const 
     bool launched = false;
     if constexpr (D == 2) {
         if (g.wave) {
-            hipError_t e = launch_wave2d_batch<T>(dt, ht, n, s, st);
+            hipError_t e = launch_wave2d_batch<T>(dt, ht, n, s, st, &ws_);
             if (e != hipSuccess) return hip_fail(e, "batched wavefront step");
             launched = true;
         }
@@ -164,7 +181,7 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
         std::stable_sort(g.idx.begin(), g.idx.end(), [&](int a, int b) { return ns[a] > ns[b]; });
         g.off = off;
         g.nact = (int)g.idx.size();
-        long acc[kNumKinds] = {0, 0, 0, 0};
+        long acc[kNumKinds] = {};
         for (size_t k = 0; k <= g.idx.size(); k++) {
             BItem& b = host_[off + k];
             b = BItem{};
@@ -303,8 +320,7 @@ int axf_batch_destroy(axf_batch *b)
     if (!b) return AXF_OK;
     hipStreamSynchronize(b->stream);
     for (auto *R : b->runs) {
-        if (R->ev0) hipEventDestroy(R->ev0);
-        if (R->ev1) hipEventDestroy(R->ev1);
+        run_release(R);
         delete R;
     }
     delete b;
@@ -317,9 +333,10 @@ int axf_batch_destroy(axf_batch *b)
 //
 // A host thread owns the GPU work.  Each round it admits queued requests that
 // fit (a free slot and a first-fit range of the pool), initialises them, and
-// advances every resident run by up to `macro_steps` steps through the engine,
-// so newly admitted runs join the batched launches of the runs already on the
-// device.  Runs that reach their step count (or are cancelled) are retired:
+// advances every resident run through the engine by a work slice of about
+// macro_steps x 2^20 cell-updates (at least one step), so newly admitted runs
+// join the batched launches of the runs already on the device and small runs
+// are not held behind large ones.  Runs that reach their step count (or are cancelled) are retired:
 // their final diagnostic record becomes the result and their memory returns to
 // the pool.  A request passed over for more than kStarveRounds rounds stops
 // later requests from overtaking it.
@@ -422,6 +439,7 @@ struct axf_server {
             if (rc) out.status = rc;
         }
         out.t_done = t;
+        run_release(r.R);
         delete r.R;
         std::lock_guard<std::mutex> lk(mu);
         alloc.give(r.off, r.bytes);
@@ -442,6 +460,17 @@ struct axf_server {
         alloc.give(off, q.bytes);
         used -= q.bytes;
         done.push_back(out);
+    }
+
+    // steps of one round: a work budget of macro x 2^20 cell-updates per run,
+    // at least one step, at most what remains (small runs finish in a round,
+    // large runs share the GPU in slices)
+    int64_t round_steps(const Resident& r) const
+    {
+        const double cells = (double)r.R->cfg.n[0] * r.R->cfg.n[1] * r.R->cfg.n[2];
+        const double budget = (double)macro * 1048576.0;
+        const int64_t want = std::max<int64_t>(1, (int64_t)(budget / cells));
+        return std::min(want, r.nsteps - r.done);
     }
 
     void loop()
@@ -496,7 +525,7 @@ struct axf_server {
             std::vector<int64_t> ns;
             for (auto& r : res) {
                 runs.push_back(r.R);
-                ns.push_back(r.cancel ? 0 : std::min(macro, r.nsteps - r.done));
+                ns.push_back(r.cancel ? 0 : round_steps(r));
             }
             int rc = eng.step(runs.data(), ns.data(), (int)runs.size(), stream);
             if (rc == AXF_OK && hipStreamSynchronize(stream) != hipSuccess) rc = AXF_EHIP;

@@ -7,6 +7,13 @@
 
 namespace axf {
 
+// A second stream for the boundary-frame launch of the 2D step and the events
+// that fork it from and join it back to the run's stream.
+struct WaveStreams {
+    hipStream_t side;
+    hipEvent_t fork, join;
+};
+
 // Fused step for 2D (march along y, tiles of TX cells in x) and 3D (march
 // along z, tiles of TX x TY cells in x, y); `chunk` planes per workgroup.
 template <int D, int TX, int TY, typename T>
@@ -16,13 +23,18 @@ struct Fused {
     static hipError_t launch(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st);
 };
 
-// Fused 2D step on wavefront-owned x segments (no LDS, no barriers).
+// Fused 2D step on wavefront-owned x segments (no LDS, no barriers): the
+// interior launch on `st`, the boundary-frame launch on ws->side when given.
 template <typename T>
-hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st);
+hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st,
+                         const WaveStreams *ws);
 // the same over the first n runs of a batch table at step s of the call
 template <typename T>
-hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st);
-// workgroups (4 wavefronts each) of one run's wavefront launch
-int wave2d_blocks(int nn0, int nn1, int chunk);
+hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st,
+                               const WaveStreams *ws);
+// workgroups (4 wavefronts each) of one run's two wavefront launches: the
+// frame next to the domain boundary and the interior
+template <typename T>
+void wave2d_blocks(const RunK<T>& h, int chunk, long *edge_blocks, long *interior_blocks);
 
 }  // namespace axf

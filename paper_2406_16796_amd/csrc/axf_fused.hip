@@ -15,6 +15,8 @@
 //   S6  phi^{n+3/2} at plane t-2                (+ axion ghosts of the new level)
 // The point formulas are the ones of the unfused kernels, written in the same
 // operation order, so the two paths agree bit for bit.
+#include <stdlib.h>
+
 #include "axf_fused.h"
 #include "axf_stencil.h"
 
@@ -354,6 +356,24 @@ __device__ __forceinline__ T mur_update(const KV<T>& r, int O, int c, int d, int
     return (T)(sg_n + ig_n);
 }
 
+// the same reading the laser table and Mur coefficient from the run descriptor
+template <typename T>
+__device__ __forceinline__ T mur_update_rk(const RunK<T>& r, int O, int c, int d, int side, double e_old, double e_new,
+                                           double g_old, long fidx, long step)
+{
+    double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
+    if (O == 0 && d == 0 && side == 0 && r.las.on && c == r.las.pol) {
+        const long lo = (step % r.inc_k1) * 2 * r.inc_face, ln = ((step + 1) % r.inc_k1) * 2 * r.inc_face;
+        ia_o = r.inc[lo + fidx];
+        ig_o = r.inc[lo + r.inc_face + fidx];
+        ia_n = r.inc[ln + fidx];
+        ig_n = r.inc[ln + r.inc_face + fidx];
+    }
+    double sa_o = e_old - ia_o, sa_n = e_new - ia_n, sg_o = g_old - ig_o;
+    double sg_n = sa_o + r.murc[d] * (sa_n - sg_o);
+    return (T)(sg_n + ig_n);
+}
+
 // ------------------------------------------------------------------ kernel
 
 template <int D, int TX, int TY, typename T>
@@ -533,7 +553,9 @@ k_fused(const RunK<T> *__restrict__ rp, long step, int ntx, int nty, int nch, in
                         ok = ok && v[e] >= 0 && v[e] < ext;
                     }
                     if (ok) {
-                        const bool owner = own_inplane && own_plane(pad);
+                        // the top ghost is owned by the chunk owning the nodal plane n[M]:
+                        // only the last chunk marches the first-order plane that far
+                        const bool owner = own_inplane && own_plane(side == 1 ? p : pad);
                         const int dm = pad - pg;
                         T val = mur_ghost(Oc, c, M, side, pg, pad, M == 0 ? dm : 0, M == 1 ? dm : 0, M == 2 ? dm : 0, owner);
                         w.ref(base, K::W2, pg) = val;
@@ -696,7 +718,9 @@ k_fused(const RunK<T> *__restrict__ rp, long step, int ntx, int nty, int nch, in
                            * r.inv_dx2[d];
                 T sdt = pml_sdt<D>(r, gi, gj, gk);
                 T x = r.dt2 * ((sax - r.m2 * pb) + lap) - sdt * sdt * pb;
-                T pn = (((x + sdt * pa) + T(2) * pb) - pa) / (T(1) + sdt);
+                // outside the damping layer the divisor is exactly 1: skip the division
+    T pn = ((x + sdt * pa) + T(2) * pb) - pa;
+    if (sdt != T(0)) pn = pn / (T(1) + sdt);
                 gst(r.warr(q_phi(ln)), gi2, pn);
                 const int gv[3] = {gi, gj, gk};
 #pragma unroll
@@ -755,15 +779,79 @@ __device__ __forceinline__ double lane_dn(double v)
 }
 
 constexpr int kWaveOut = 59;   // output columns per wavefront
+// prefetch distance (rows ahead) of the interior march, by precision (measured)
+template <typename T> struct WavePD { static constexpr int value = 2; };
 
-// wavefront gw (of nseg x nch) of one run's step
+// global load / store at a 32-bit byte offset from a wave-uniform base (every
+// array of a run has the same layout, so one offset per row serves them all)
 template <typename T>
-__device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long step, int gw, int nseg, int nch, int chunk)
+__device__ __forceinline__ T ldo(const T *base, unsigned boff)
 {
-    KV<T> r = make_kv(rp);
+    return *(const __attribute__((address_space(1))) T *)((const __attribute__((address_space(1))) char *)base + boff);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T *base, unsigned boff, T v)
+{
+    *(__attribute__((address_space(1))) T *)((__attribute__((address_space(1))) char *)base + boff) = v;
+}
+
+// What the interior of the 2D march needs in registers: the field base and
+// stride, the grid and the coefficients.  Everything used only at the domain
+// boundary (ghost planes, Mur, laser, PML, outflow) is read from the run
+// descriptor where it is needed, so that it does not occupy scalar registers
+// for the whole march.
+template <typename T>
+struct KW {
+    const char *sb;
+    unsigned as;            // array stride in bytes (27 arrays span < 4 GiB: checked on the host)
+    int n[2], nn[2], mur[2], axbc[2];
+    int sx;
+    T cdt[2], half, inv_dt, inv2dx[2], inv_dx2[2], dt2, m2, gax, cg1;
+
+    __device__ __forceinline__ const T *arr(int q) const { return (const T *)(sb + (size_t)q * as); }
+    __device__ __forceinline__ T *warr(int q) const { return (T *)(sb + (size_t)q * as); }
+};
+
+template <typename T>
+__device__ __forceinline__ KW<T> make_kw(const RunK<T> *__restrict__ rp)
+{
+    KW<T> v;
+    v.sb = rp->state_base;
+    v.as = (unsigned)rp->arr_stride;
+#pragma unroll
+    for (int d = 0; d < 2; d++) {
+        v.n[d] = rp->n[d];
+        v.nn[d] = rp->nn[d];
+        v.mur[d] = rp->mur[d];
+        v.axbc[d] = rp->axbc[d];
+        v.cdt[d] = rp->cdt[d];
+        v.inv2dx[d] = rp->inv2dx[d];
+        v.inv_dx2[d] = rp->inv_dx2[d];
+    }
+    v.sx = (int)rp->sx;
+    v.half = rp->half;
+    v.inv_dt = rp->inv_dt;
+    v.dt2 = rp->dt2;
+    v.m2 = rp->m2;
+    v.gax = rp->gax;
+    v.cg1 = rp->cg1;
+    return v;
+}
+
+// boundary planes of a run (read from the descriptor at the boundary only)
+template <typename T>
+__device__ __forceinline__ T *face_of(const RunK<T> *rp, int q) { return (T *)(rp->face_base + q * rp->face_stride); }
+
+// The wavefront of x segment `seg` and row chunk `ch` of one run's step.
+// INTERIOR: the wavefront's columns and rows (its halo included) keep clear of
+// every face, ghost ring and damping layer, so every point is valid, nothing
+// wraps and there are no ghosts to read or write; the point formulas are the
+// same, so both variants produce the same bits.
+template <typename T, bool INTERIOR, int PD>
+__device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long step, int seg, int ch, int nch, int chunk)
+{
+    KW<T> r = make_kw(rp);
     const int lane = threadIdx.x & 63;
-    if (gw >= nseg * nch) return;      // whole wavefronts only: no barriers in this kernel
-    const int seg = gw % nseg, ch = gw / nseg;
     const int so = (int)(step & 1), sn = so ^ 1;
     const int la = (int)(step % 3), lb = (int)((step + 1) % 3), ln = (int)((step + 2) % 3);
 
@@ -771,16 +859,37 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
     const int own_x_hi = min(x0 + kWaveOut, r.nn[0]);
     const bool own_x = lane >= 3 && lane < 3 + kWaveOut && gx < own_x_hi;
     const int c0 = ch * chunk, c1 = (ch == nch - 1) ? r.nn[1] : c0 + chunk;
-    const int n0 = r.n[0], n1 = r.n[1];
-    const bool mx = r.mur[0], my = r.mur[1];
-    // x validity of nodal / centred components at this lane, y validity per plane
-    const bool vx_nod = !mx || (gx >= 0 && gx < r.nn[0]);
-    const bool vx_cen = !mx || (gx >= 0 && gx < n0);
-    auto vy_nod = [&](int p) __attribute__((always_inline)) { return !my || (p >= 0 && p < r.nn[1]); };
+    const int n0 = r.n[0], n1 = r.n[1], nn0 = r.nn[0], nn1 = r.nn[1];
+    const bool mx = INTERIOR ? false : r.mur[0], my = INTERIOR ? false : r.mur[1];
+    const unsigned es = sizeof(T), sxb = (unsigned)r.sx * es;   // element and row pitch in bytes
+    // this lane's column: x validity of nodal / centred EM points (fixed for the
+    // march) and the storage column read for them (any valid one when masked)
+    const bool inx_n = gx >= 0 && gx < nn0, inx_c = gx >= 0 && gx < n0;
+    const bool vx_nod = !mx || inx_n;
+    const bool vx_cen = !mx || inx_c;
+    const unsigned bx = (unsigned)(mx ? (inx_n ? gx : 0) : wrap1(gx, n0)) * es;
+    // the same for phi: wrapped on a periodic axion axis, else the interior or
+    // the ghost column one cell outside either face
+    const bool axpx = INTERIOR || r.axbc[0] == AXF_AX_PERIODIC, axpy = INTERIOR || r.axbc[1] == AXF_AX_PERIODIC;
+    const int xgs = axpx ? -1 : (gx == -1 ? 0 : (gx == n0 ? 1 : -1));
+    const bool vpx = axpx || inx_c || xgs >= 0;          // phi exists at this column
+    const bool vpx_in = axpx || inx_c;                   // ... and is not a ghost
+    const unsigned bxp = (unsigned)(axpx ? wrap1(gx, n0) : (inx_c ? gx : 0)) * es;
+    // plane p (wave-uniform): y validity and storage row
+    auto vy_nod = [&](int p) __attribute__((always_inline)) { return !my || (p >= 0 && p < nn1); };
     auto vy_cen = [&](int p) __attribute__((always_inline)) { return !my || (p >= 0 && p < n1); };
     auto own_plane = [&](int p) __attribute__((always_inline)) { return p >= c0 && p < c1; };
-    const int wx = mx ? gx : wrap1(gx, n0);
-    auto gidx = [&](int p) __attribute__((always_inline)) { return (long)wx + (long)(my ? p : wrap1(p, n1)) * r.sx; };
+    // every field array is addressed from the one state base with a 32-bit
+    // byte offset q * as + (row, column); the stride is re-read each iteration
+    // (opaque to the compiler) so that the per-array products stay in the loop
+    // instead of occupying 22 scalar register pairs for the whole march
+    unsigned as_l = r.as;
+    auto ldq = [&](int q, unsigned o) __attribute__((always_inline)) -> T { return ldo((const T *)r.sb, (unsigned)q * as_l + o); };
+    auto stq = [&](int q, unsigned o, T v) __attribute__((always_inline)) { sto((T *)r.sb, (unsigned)q * as_l + o, v); };
+    auto off = [&](int p) __attribute__((always_inline)) -> unsigned {
+        const int row = my ? ((p >= 0 && p < nn1) ? p : 0) : wrap1(p, n1);
+        return bx + (unsigned)row * sxb;
+    };
 
     // register windows along y (suffix = planes behind the newest loaded plane t)
     T b0z_2 = 0, b0z_1 = 0, b0z_0 = 0;
@@ -790,42 +899,41 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
     T c_3[3] = {0, 0, 0}, c_2[3] = {0, 0, 0};
     T b0p_2 = 0, b0p_1 = 0;
     T e1h_3[3] = {0, 0, 0}, e1h_2[3] = {0, 0, 0};
-    // prefetch (raw values + mask), consumed one iteration later
-    T f_b0z, f_b1[3], f_pa, f_pb, f_e0m[2], f_e1m[3];
-    unsigned f_mask = 0;
-    auto prefetch = [&](int t) __attribute__((always_inline)) {
-        bool ok;
-        unsigned m = 0;
-        const T *q = addr_em<2>(r, r.arr(q_em(1, so, 2)), 3u, gx, t, 0, ok);
-        f_b0z = gld(q, 0);
-        m |= ok ? 1u : 0u;
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            q = addr_em<2>(r, r.arr(q_em(3, so, c)), 7u & ~(1u << c), gx, t - 1, 0, ok);
-            f_b1[c] = gld(q, 0);
-            m |= ok ? 2u << c : 0u;
-        }
-        q = addr_phi<2>(r, la, gx, t - 1, 0, ok);
-        f_pa = gld(q, 0);
-        m |= ok ? 16u : 0u;
-        q = addr_phi<2>(r, lb, gx, t - 1, 0, ok);
-        f_pb = gld(q, 0);
-        m |= ok ? 32u : 0u;
-#pragma unroll
-        for (int c = 0; c < 2; c++) {
-            q = addr_em<2>(r, r.arr(q_em(0, so, c)), 1u << c, gx, t - 1, 0, ok);
-            f_e0m[c] = gld(q, 0);
-            m |= ok ? 64u << c : 0u;
-        }
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            q = addr_em<2>(r, r.arr(q_em(2, so, c)), 1u << c, gx, t - 2, 0, ok);
-            f_e1m[c] = gld(q, 0);
-            m |= ok ? 256u << c : 0u;
-        }
-        f_mask = m;
+    // prefetched raw values of plane t (and t-1, t-2) and the wave-uniform y
+    // validity they were loaded with, PD iterations ahead of their use; the
+    // lane masks are applied at use, so that the loads stay in flight together
+    struct Pref {
+        T b0z, b1[3], pa, pb, e0m[2], e1m[3];
+        bool yn0, yn1, yc1, yn2, yc2, pin, pgh;
     };
-    auto sel = [&](T v, unsigned bit) __attribute__((always_inline)) { return (f_mask & bit) ? v : T(0); };
+    Pref buf[PD];
+    auto load_phi = [&](int L, int p) __attribute__((always_inline)) -> T {
+        const int ys = axpy ? -1 : (p == -1 ? 0 : (p == n1 ? 1 : -1));
+        if (ys >= 0) return ldo((const T *)face_of(rp, q_axg(1, ys, L)), bxp);   // the y ghost row (uniform)
+        const int row = axpy ? wrap1(p, n1) : ((p >= 0 && p < n1) ? p : 0);
+        if (xgs >= 0) return ldo((const T *)face_of(rp, q_axg(0, xgs, L)), (unsigned)row * es);   // x ghost lanes
+        return ldq(q_phi(L), bxp + (unsigned)row * sxb);
+    };
+    auto prefetch = [&](int t, Pref& P) __attribute__((always_inline)) {
+        const unsigned o0 = off(t), o1 = off(t - 1), o2 = off(t - 2);
+        P.b0z = ldq(q_em(1, so, 2), o0);
+#pragma unroll
+        for (int c = 0; c < 3; c++) P.b1[c] = ldq(q_em(3, so, c), o1);
+        P.pa = load_phi(la, t - 1);
+        P.pb = load_phi(lb, t - 1);
+#pragma unroll
+        for (int c = 0; c < 2; c++) P.e0m[c] = ldq(q_em(0, so, c), o1);
+#pragma unroll
+        for (int c = 0; c < 3; c++) P.e1m[c] = ldq(q_em(2, so, c), o2);
+        P.yn0 = vy_nod(t);
+        P.yn1 = vy_nod(t - 1);
+        P.yc1 = vy_cen(t - 1);
+        P.yn2 = vy_nod(t - 2);
+        P.yc2 = vy_cen(t - 2);
+        const int p = t - 1;
+        P.pgh = !axpy && (p == -1 || p == n1);
+        P.pin = axpy || (p >= 0 && p < n1);
+    };
 
     // Mur ghost of E_c (order O) of this lane at plane pg from the adjacent
     // interior point (x offset ox, plane pa) whose E^{n+1/2} is e_new
@@ -835,37 +943,54 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
         if (!my) a1 = wrap1(a1, n1);
         long fidx = face_index(r, d, a0, a1, 0);
         double e_old = (double)gld(r.arr(q_em(O == 0 ? 0 : 2, so, c)), (long)a0 + (long)a1 * r.sx);
-        double g_old = (double)gld(r.face(q_mur(O, d, side, c, so)), fidx);
-        T val = mur_update<T>(r, O, c, d, side, e_old, (double)e_new, g_old, fidx, step);
-        if (owner) gst(r.wface(q_mur(O, d, side, c, sn)), fidx, val);
+        double g_old = (double)gld((const T *)face_of(rp, q_mur(O, d, side, c, so)), fidx);
+        T val = mur_update_rk<T>(*rp, O, c, d, side, e_old, (double)e_new, g_old, fidx, step);
+        if (owner) gst(face_of(rp, q_mur(O, d, side, c, sn)), fidx, val);
         return val;
     };
 
+    const T bext0 = bext_at(*rp, 0, wrap1(gx, n0)), bext1 = bext_at(*rp, 1, wrap1(gx, n0));
+    const T bext2 = bext_at(*rp, 2, wrap1(gx, n0));
     const int t_first = c0 - 2, t_last = c1 + 1;
-    prefetch(t_first);
-    for (int t = t_first; t <= t_last; t++) {
+#pragma unroll
+    for (int k = 0; k < PD; k++)
+        if (t_first + k <= t_last) prefetch(t_first + k, buf[k]);
+    // the march, unrolled by the prefetch distance so that every buffer has a
+    // fixed register home
+    for (int t0 = t_first; t0 <= t_last; t0 += PD)
+#pragma unroll
+    for (int k = 0; k < PD; k++) {
+        const int t = t0 + k;
+        if (t > t_last) break;
+        Pref& P = buf[k];
+        asm volatile("" : "+s"(as_l));
         // rotate the windows and take in the prefetched planes
-        b0z_2 = b0z_1; b0z_1 = b0z_0; b0z_0 = sel(f_b0z, 1u);
-        pa_3 = pa_2; pa_2 = pa_1; pa_1 = sel(f_pa, 16u);
-        pb_3 = pb_2; pb_2 = pb_1; pb_1 = sel(f_pb, 32u);
+        b0z_2 = b0z_1; b0z_1 = b0z_0; b0z_0 = (vx_nod && P.yn0) ? P.b0z : T(0);
+        const bool pok = P.pgh ? vpx_in : (vpx && P.pin);
+        pa_3 = pa_2; pa_2 = pa_1; pa_1 = pok ? P.pa : T(0);
+        pb_3 = pb_2; pb_2 = pb_1; pb_1 = pok ? P.pb : T(0);
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             b1_2[c] = b1_1[c];
-            b1_1[c] = sel(f_b1[c], 2u << c);
             c_3[c] = c_2[c];
             e1h_3[c] = e1h_2[c];
         }
+        b1_1[0] = (vx_cen && P.yn1) ? P.b1[0] : T(0);   // B1x: centred x, nodal y
+        b1_1[1] = (vx_nod && P.yc1) ? P.b1[1] : T(0);   // B1y: nodal x, centred y
+        b1_1[2] = (vx_nod && P.yn1) ? P.b1[2] : T(0);   // B1z: nodal x, nodal y
 #pragma unroll
         for (int c = 0; c < 2; c++) {
             e0h_2[c] = e0h_1[c];
             e0n_2[c] = e0n_1[c];
         }
         b0p_2 = b0p_1;
-        T e0m[2] = {sel(f_e0m[0], 64u), sel(f_e0m[1], 128u)};
-        T e1m[3] = {sel(f_e1m[0], 256u), sel(f_e1m[1], 512u), sel(f_e1m[2], 1024u)};
-        if (t < t_last) prefetch(t + 1);
+        const T e0m[2] = {(vx_nod && P.yc1) ? P.e0m[0] : T(0), (vx_cen && P.yn1) ? P.e0m[1] : T(0)};
+        const T e1m[3] = {(vx_nod && P.yc2) ? P.e1m[0] : T(0), (vx_cen && P.yn2) ? P.e1m[1] : T(0),
+                          (vx_cen && P.yc2) ? P.e1m[2] : T(0)};
+        if (t + PD <= t_last) prefetch(t + PD, P);
 
         const int p1 = t - 1, p2 = t - 2;
+        const unsigned o1 = off(p1), o2 = off(p2);
         // ---- S1: E0^{n+1/2}, E0^n at plane p1 (E0x nodal in x, E0y nodal in y)
         {
             const T up_b0z = lane_up(b0z_1);
@@ -885,8 +1010,8 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
             e0h_1[0] = eh[0]; e0h_1[1] = eh[1];
             e0n_1[0] = en[0]; e0n_1[1] = en[1];
             const bool own = own_x && own_plane(p1);
-            if (own && vx_nod && vy_cen(p1)) gst(r.warr(q_em(0, sn, 0)), gidx(p1), eh[0]);
-            if (own && vx_cen && vy_nod(p1)) gst(r.warr(q_em(0, sn, 1)), gidx(p1), eh[1]);
+            if (own && vx_nod && vy_cen(p1)) stq(q_em(0, sn, 0), o1, eh[0]);
+            if (own && vx_cen && vy_nod(p1)) stq(q_em(0, sn, 1), o1, eh[1]);
             // Mur ghosts of E0y across x (E0y centred in x)
             const T up_e = lane_up(e0h_1[1]), dn_e = lane_dn(e0h_1[1]);
             if (mx && (gx == -1 || gx == n0) && vy_nod(p1)) {
@@ -908,13 +1033,12 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
             const T up_pa = lane_up(pa_2), up_pb = lane_up(pb_2), dn_pa = lane_dn(pa_2), dn_pb = lane_dn(pb_2);
             T C0 = T(0), C1 = T(0), C2 = T(0);
             if (vx_cen && vy_cen(p2)) {
-                const int cxg = wrap1(gx, n0);
                 e[0] = r.half * (e0n_2[0] + up_en0);
                 e[1] = r.half * (e0n_2[1] + e0n_1[1]);
                 e[2] = T(0);
-                bb[0] = T(0) + bext_at(r, 0, cxg);
-                bb[1] = T(0) + bext_at(r, 1, cxg);
-                bb[2] = T(0.25) * ((b0z_2 + up_b2) + (b0z_1 + up_b1)) + bext_at(r, 2, cxg);
+                bb[0] = T(0) + bext0;
+                bb[1] = T(0) + bext1;
+                bb[2] = T(0.25) * ((b0z_2 + up_b2) + (b0z_1 + up_b1)) + bext2;
                 T dtphi = (pb_2 - pa_2) * r.inv_dt;
                 {
                     T up = r.half * (up_pa + up_pb), dn = r.half * (dn_pa + dn_pb);
@@ -938,7 +1062,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
             if (vx_nod && vy_nod(p1)) {
                 T a = r.cdt[0] * (e0h_1[1] - dn_e0y), b = r.cdt[1] * (e0h_1[0] - e0h_2[0]);
                 v = b0z_1 - (a - b);
-                if (own_x && own_plane(p1)) gst(r.warr(q_em(1, sn, 2)), gidx(p1), v);
+                if (own_x && own_plane(p1)) stq(q_em(1, sn, 2), o1, v);
             }
             b0p_1 = v;
         }
@@ -956,7 +1080,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                 T a = r.cdt[1] * (b1_1[2] - b1_2[2]), b = T(0);
                 T rhs = (a - b) - r.cg1 * Sc;
                 v[0] = e1m[0] + T(1) * rhs;
-                if (own) gst(r.warr(q_em(2, sn, 0)), gidx(p2), v[0]);
+                if (own) stq(q_em(2, sn, 0), o2, v[0]);
             }
             // E1y: centred x, nodal y
             if (vx_cen && vy_nod(p2)) {
@@ -966,7 +1090,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                 T a = T(0), b = r.cdt[0] * (up_b1z - b1_2[2]);
                 T rhs = (a - b) - r.cg1 * Sc;
                 v[1] = e1m[1] + T(1) * rhs;
-                if (own) gst(r.warr(q_em(2, sn, 1)), gidx(p2), v[1]);
+                if (own) stq(q_em(2, sn, 1), o2, v[1]);
             }
             // E1z: centred x, centred y
             if (vx_cen && vy_cen(p2)) {
@@ -974,7 +1098,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                 T a = r.cdt[0] * (up_b1y - b1_2[1]), b = r.cdt[1] * (b1_1[0] - b1_2[0]);
                 T rhs = (a - b) - r.cg1 * Sc;
                 v[2] = e1m[2] + T(1) * rhs;
-                if (own) gst(r.warr(q_em(2, sn, 2)), gidx(p2), v[2]);
+                if (own) stq(q_em(2, sn, 2), o2, v[2]);
             }
             e1h_2[0] = v[0]; e1h_2[1] = v[1]; e1h_2[2] = v[2];
             // Mur ghosts of E1y, E1z across x; of E1x, E1z across y
@@ -991,8 +1115,9 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                     if (vx_nod) e1h_3[0] = ghost(1, 0, 1, 0, -1, 0, 0, e1h_2[0], own_x && own_plane(0));
                     if (vx_cen) e1h_3[2] = ghost(1, 2, 1, 0, -1, 0, 0, e1h_2[2], own_x && own_plane(0));
                 } else if (p2 == n1) {
-                    if (vx_nod) e1h_2[0] = ghost(1, 0, 1, 1, n1, 0, n1 - 1, e1h_3[0], own_x && own_plane(n1 - 1));
-                    if (vx_cen) e1h_2[2] = ghost(1, 2, 1, 1, n1, 0, n1 - 1, e1h_3[2], own_x && own_plane(n1 - 1));
+                    // only the last chunk (which owns the nodal row n1) marches p2 up to n1
+                    if (vx_nod) e1h_2[0] = ghost(1, 0, 1, 1, n1, 0, n1 - 1, e1h_3[0], own_x && own_plane(n1));
+                    if (vx_cen) e1h_2[2] = ghost(1, 2, 1, 1, n1, 0, n1 - 1, e1h_3[2], own_x && own_plane(n1));
                 }
             }
         }
@@ -1004,21 +1129,20 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
             const T up_p2 = lane_up(b0p_2), up_p1 = lane_up(b0p_1);
             const T up_pb = lane_up(pb_2), dn_pb = lane_dn(pb_2);
             if (own_x && own_plane(p2)) {
-                const long gi2 = gidx(p2);
                 // B1x: centred x, nodal y
                 if (vx_cen && vy_nod(p2)) {
                     T a = r.cdt[1] * (e1h_2[2] - e1h_3[2]), b = T(0);
-                    gst(r.warr(q_em(3, sn, 0)), gi2, b1_2[0] - (a - b));
+                    stq(q_em(3, sn, 0), o2, b1_2[0] - (a - b));
                 }
                 // B1y: nodal x, centred y
                 if (vx_nod && vy_cen(p2)) {
                     T a = T(0), b = r.cdt[0] * (e1h_2[2] - dn_e1z);
-                    gst(r.warr(q_em(3, sn, 1)), gi2, b1_2[1] - (a - b));
+                    stq(q_em(3, sn, 1), o2, b1_2[1] - (a - b));
                 }
                 // B1z: nodal x, nodal y
                 if (vx_nod && vy_nod(p2)) {
                     T a = r.cdt[0] * (e1h_2[1] - dn_e1y), b = r.cdt[1] * (e1h_2[0] - e1h_3[0]);
-                    gst(r.warr(q_em(3, sn, 2)), gi2, b1_2[2] - (a - b));
+                    stq(q_em(3, sn, 2), o2, b1_2[2] - (a - b));
                 }
                 if (vx_cen && vy_cen(p2)) {
                     const int gi = wrap1(gx, n0), gj = my ? p2 : wrap1(p2, n1);
@@ -1029,36 +1153,39 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                     T bo0 = T(0), bn0 = T(0), bo1 = T(0), bn1 = T(0);
                     T bo2 = T(0.25) * ((b0z_2 + up_b2) + (b0z_1 + up_b1));
                     T bn2 = T(0.25) * ((b0p_2 + up_p2) + (b0p_1 + up_p1));
-                    bb[0] = r.half * (bo0 + bn0) + bext_at(r, 0, gi);
-                    bb[1] = r.half * (bo1 + bn1) + bext_at(r, 1, gi);
-                    bb[2] = r.half * (bo2 + bn2) + bext_at(r, 2, gi);
+                    bb[0] = r.half * (bo0 + bn0) + bext0;
+                    bb[1] = r.half * (bo1 + bn1) + bext1;
+                    bb[2] = r.half * (bo2 + bn2) + bext2;
                     T sax = r.gax * (e[0] * bb[0] + e[1] * bb[1] + e[2] * bb[2]);
                     T pa = pa_2, pb = pb_2;
                     T lap = T(0);
                     lap += ((up_pb - T(2) * pb) + dn_pb) * r.inv_dx2[0];
                     lap += ((pb_1 - T(2) * pb) + pb_3) * r.inv_dx2[1];
-                    T sdt = pml_sdt<2>(r, gi, gj, 0);
+                    T sdt = (!INTERIOR && (r.axbc[0] == AXF_AX_PML || r.axbc[1] == AXF_AX_PML)) ? pml_sdt<2>(*rp, gi, gj, 0) : T(0);
                     T x = r.dt2 * ((sax - r.m2 * pb) + lap) - sdt * sdt * pb;
-                    T pn = (((x + sdt * pa) + T(2) * pb) - pa) / (T(1) + sdt);
-                    gst(r.warr(q_phi(ln)), gi2, pn);
+                    T num = ((x + sdt * pa) + T(2) * pb) - pa;
+                    T pn = num;
+                    if (sdt != T(0)) pn = num / (T(1) + sdt);
+                    stq(q_phi(ln), o2, pn);
                     const int gv[2] = {gi, gj};
 #pragma unroll
                     for (int d = 0; d < 2; d++) {
-                        if (r.axbc[d] == AXF_AX_PERIODIC) continue;
+                        if (INTERIOR || r.axbc[d] == AXF_AX_PERIODIC) continue;
 #pragma unroll
                         for (int side = 0; side < 2; side++) {
                             if (gv[d] != (side ? r.n[d] - 1 : 0)) continue;
                             long f = face_index(r, d, gi, gj, 0);
                             T gval;
                             if (r.axbc[d] == AXF_AX_OUTFLOW) {
-                                T gbv = gld(r.face(q_axg(d, side, lb)), f), gav = gld(r.face(q_axg(d, side, la)), f), rr = r.out_r[d];
+                                T gbv = gld((const T *)face_of(rp, q_axg(d, side, lb)), f);
+                                T gav = gld((const T *)face_of(rp, q_axg(d, side, la)), f), rr = rp->out_r[d];
                                 T xx = (((T(-2) * gbv + T(2) * gav) - r.dt2 * (sax - r.m2 * gbv)) + rr * pb - rr * rr * (pb - T(2) * gbv))
                                        / (rr + rr * rr);
                                 gval = gav + rr * (pb - xx);
                             } else {
                                 gval = pn;
                             }
-                            gst(r.wface(q_axg(d, side, ln)), f, gval);
+                            gst(face_of(rp, q_axg(d, side, ln)), f, gval);
                         }
                     }
                 }
@@ -1067,54 +1194,168 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256, 3) k_wave2d(const RunK<T> *__restrict__ rp, long step, int nseg, int nch, int chunk)
+// Interior rectangle of the wavefront grid: segments [sx0, sx1) and chunks
+// [cy0, cy1) whose columns x0-3 .. x0+60 and rows c0-4 .. c1+1 stay at least
+// `margin` cells inside the grid (margin = 1, or the damping-layer thickness on
+// a PML axis).
+// index of this wavefront in its workgroup, as a wave-uniform value (the
+// compiler cannot tell that threadIdx.x / 64 is uniform; everything derived from
+// it -- segment, chunk, rows -- then stays in scalar registers and branches)
+__device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+struct WaveSplit {
+    int nseg, nch, sx0, sx1, cy0, cy1;
+    __host__ __device__ long interior() const { return (long)(sx1 - sx0) * (cy1 - cy0); }
+    __host__ __device__ long edge() const { return (long)nseg * nch - interior(); }
+};
+
+template <typename R>
+__host__ __device__ inline WaveSplit wave2d_split(const R& h, int chunk)
 {
-    wave2d_body<T>(rp, step, blockIdx.x * 4 + (threadIdx.x >> 6), nseg, nch, chunk);
+    WaveSplit w;
+    w.nseg = (h.nn[0] + kWaveOut - 1) / kWaveOut;
+    w.nch = (h.nn[1] + chunk - 1) / chunk;
+    const int mxg = 1 + (h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
+    const int myg = 1 + (h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
+    // x0 = seg * kWaveOut: need x0 - 3 >= mxg and x0 + 60 <= n0 - 1 - mxg
+    w.sx0 = (mxg + 3 + kWaveOut - 1) / kWaveOut;
+    w.sx1 = (h.n[0] - 1 - mxg - 60) >= 0 ? (h.n[0] - 1 - mxg - 60) / kWaveOut + 1 : 0;
+    // c0 = ch * chunk: need c0 - 4 >= myg and c0 + chunk + 1 <= n1 - 1 - myg; the
+    // last chunk (which runs to the storage end) is never interior
+    w.cy0 = (myg + 4 + chunk - 1) / chunk;
+    w.cy1 = (h.n[1] - 2 - myg - chunk) >= 0 ? (h.n[1] - 2 - myg - chunk) / chunk + 1 : 0;
+    w.cy1 = w.cy1 < w.nch - 1 ? w.cy1 : w.nch - 1;
+    if (w.sx1 <= w.sx0 || w.cy1 <= w.cy0) w.sx0 = w.sx1 = w.cy0 = w.cy1 = 0;
+    return w;
+}
+
+// segment and chunk of the e-th wavefront of the frame around the interior
+__device__ __forceinline__ void wave2d_edge_item(const WaveSplit& w, long e, int& seg, int& ch)
+{
+    const long below = (long)w.cy0 * w.nseg;                 // chunks under the interior, all segments
+    const int ni = w.sx1 - w.sx0, nside = w.nseg - ni;      // segments beside the interior
+    const long beside = (long)(w.cy1 - w.cy0) * nside;
+    if (e < below) {
+        seg = (int)(e % w.nseg);
+        ch = (int)(e / w.nseg);
+    } else if (e < below + beside) {
+        const long q = e - below;
+        const int k = (int)(q % nside);
+        ch = w.cy0 + (int)(q / nside);
+        seg = k < w.sx0 ? k : k + ni;
+    } else {
+        const long q = e - below - beside;
+        seg = (int)(q % w.nseg);
+        ch = w.cy1 + (int)(q / w.nseg);
+    }
+}
+
+template <typename T, int PD>
+__global__ void __launch_bounds__(256) k_wave2d_int(const RunK<T> *__restrict__ rp, long step, WaveSplit w, int chunk)
+{
+    const long gw = blockIdx.x * 4L + wave_in_block();
+    if (gw >= w.interior()) return;       // whole wavefronts only: no barriers in this kernel
+    const int ni = w.sx1 - w.sx0;
+    wave2d_body<T, true, PD>(rp, step, w.sx0 + (int)(gw % ni), w.cy0 + (int)(gw / ni), w.nch, chunk);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256, 3) k_wave2d(const RunK<T> *__restrict__ rp, long step, WaveSplit w, int chunk)
+{
+    const long gw = blockIdx.x * 4L + wave_in_block();
+    if (gw >= w.edge()) return;
+    int seg, ch;
+    wave2d_edge_item(w, gw, seg, ch);
+    wave2d_body<T, false, 1>(rp, step, seg, ch, w.nch, chunk);
 }
 
 // batched: every active run of the table, each with its own step and chunk
-template <typename T>
-__global__ void __launch_bounds__(256, 3) kb_wave2d(const BItem *__restrict__ it, int n, long s)
+template <typename T, bool INTERIOR>
+__global__ void __launch_bounds__(256, INTERIOR ? 1 : 3) kb_wave2d(const BItem *__restrict__ it, int n, long s)
 {
-    const int i = find_item<kWave>(it, n, blockIdx.x);
-    const RunK<T> *rp = (const RunK<T> *)it[i].rk;
+    constexpr int K = INTERIOR ? kWaveI : kWave;
+    const int i = find_item<K>(it, n, blockIdx.x);
+    const RunK<T> *rp = uniform_desc<RunK<T>>(it[i].rk);
     const int chunk = it[i].chunk;
-    const int nseg = (rp->nn[0] + kWaveOut - 1) / kWaveOut, nch = (rp->nn[1] + chunk - 1) / chunk;
-    const int gw = (int)(blockIdx.x - it[i].blk[kWave]) * 4 + (threadIdx.x >> 6);
-    wave2d_body<T>(rp, it[i].step0 + s, gw, nseg, nch, chunk);
-}
-
-int wave2d_blocks(int nn0, int nn1, int chunk)
-{
-    const long waves = (long)((nn0 + kWaveOut - 1) / kWaveOut) * ((nn1 + chunk - 1) / chunk);
-    return (int)((waves + 3) / 4);
+    const WaveSplit w = wave2d_split(*rp, chunk);
+    const long gw = (blockIdx.x - it[i].blk[K]) * 4L + wave_in_block();
+    if (INTERIOR) {
+        if (gw >= w.interior()) return;
+        const int ni = w.sx1 - w.sx0;
+        wave2d_body<T, true, WavePD<T>::value>(rp, it[i].step0 + s, w.sx0 + (int)(gw % ni), w.cy0 + (int)(gw / ni), w.nch, chunk);
+    } else {
+        if (gw >= w.edge()) return;
+        int seg, ch;
+        wave2d_edge_item(w, gw, seg, ch);
+        wave2d_body<T, false, 1>(rp, it[i].step0 + s, seg, ch, w.nch, chunk);
+    }
 }
 
 template <typename T>
-hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st)
+void wave2d_blocks(const RunK<T>& h, int chunk, long *edge_blocks, long *interior_blocks)
 {
-    const unsigned nb = (unsigned)host[n].blk[kWave];
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL((kb_wave2d<T>), dim3(nb), dim3(256), 0, st, it, n, s);
+    const WaveSplit w = wave2d_split(h, chunk);
+    *edge_blocks = (w.edge() + 3) / 4;
+    *interior_blocks = (w.interior() + 3) / 4;
+}
+template void wave2d_blocks<float>(const RunK<float>&, int, long *, long *);
+template void wave2d_blocks<double>(const RunK<double>&, int, long *, long *);
+
+template <typename T>
+hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st,
+                               const WaveStreams *ws)
+{
+    const unsigned ni = (unsigned)host[n].blk[kWaveI], ne = (unsigned)host[n].blk[kWave];
+    const bool fork = ws && ws->side && ne > 0 && ni > 0;
+    hipStream_t se = st;
+    if (fork) {
+        hipEventRecord(ws->fork, st);
+        hipStreamWaitEvent(ws->side, ws->fork, 0);
+        se = ws->side;
+    }
+    if (ne > 0) hipLaunchKernelGGL((kb_wave2d<T, false>), dim3(ne), dim3(256), 0, se, it, n, s);
+    if (ni > 0) hipLaunchKernelGGL((kb_wave2d<T, true>), dim3(ni), dim3(256), 0, st, it, n, s);
+    if (fork) {
+        hipEventRecord(ws->join, ws->side);
+        hipStreamWaitEvent(st, ws->join, 0);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st)
+hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st,
+                         const WaveStreams *ws)
 {
-    int nseg = (h.nn[0] + kWaveOut - 1) / kWaveOut;
-    int nch = (h.nn[1] + chunk - 1) / chunk;
-    long waves = (long)nseg * nch;
-    unsigned nb = (unsigned)((waves + 3) / 4);
-    hipLaunchKernelGGL((k_wave2d<T>), dim3(nb), dim3(256), 0, st, rk, step, nseg, nch, chunk);
+    const WaveSplit w = wave2d_split(h, chunk);
+    const unsigned ni = (unsigned)((w.interior() + 3) / 4), ne = (unsigned)((w.edge() + 3) / 4);
+    const char *pde = getenv("AXF_WAVE_PD");
+    const int pd = pde ? atoi(pde) : WavePD<T>::value;
+    // the frame runs beside the interior on the side stream when there is one
+    // (the two launches touch disjoint outputs and read only the old slots)
+    const bool fork = ws && ws->side && ne > 0 && ni > 0;
+    hipStream_t se = st;
+    if (fork) {
+        hipEventRecord(ws->fork, st);
+        hipStreamWaitEvent(ws->side, ws->fork, 0);
+        se = ws->side;
+    }
+    if (ne > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(ne), dim3(256), 0, se, rk, step, w, chunk);
+    if (ni > 0) {
+        if (pd <= 1) hipLaunchKernelGGL((k_wave2d_int<T, 1>), dim3(ni), dim3(256), 0, st, rk, step, w, chunk);
+        else if (pd == 2) hipLaunchKernelGGL((k_wave2d_int<T, 2>), dim3(ni), dim3(256), 0, st, rk, step, w, chunk);
+        else hipLaunchKernelGGL((k_wave2d_int<T, 3>), dim3(ni), dim3(256), 0, st, rk, step, w, chunk);
+    }
+    if (fork) {
+        hipEventRecord(ws->join, ws->side);
+        hipStreamWaitEvent(st, ws->join, 0);
+    }
     return hipGetLastError();
 }
 
-template hipError_t launch_wave2d<float>(const RunK<float> *, const RunK<float>&, long, int, hipStream_t);
-template hipError_t launch_wave2d<double>(const RunK<double> *, const RunK<double>&, long, int, hipStream_t);
-template hipError_t launch_wave2d_batch<float>(const BItem *, const BItem *, int, long, hipStream_t);
-template hipError_t launch_wave2d_batch<double>(const BItem *, const BItem *, int, long, hipStream_t);
+template hipError_t launch_wave2d<float>(const RunK<float> *, const RunK<float>&, long, int, hipStream_t, const WaveStreams *);
+template hipError_t launch_wave2d<double>(const RunK<double> *, const RunK<double>&, long, int, hipStream_t, const WaveStreams *);
+template hipError_t launch_wave2d_batch<float>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);
+template hipError_t launch_wave2d_batch<double>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);
 
 template <int D, int TX, int TY, typename T>
 size_t Fused<D, TX, TY, T>::lds_bytes() { return FK<D, TX, TY, T>::LDS; }

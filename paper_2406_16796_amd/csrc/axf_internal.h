@@ -90,7 +90,7 @@ __host__ __device__ inline long round_up(long v, long m) { return (v + m - 1) / 
 // table sorted by remaining steps; blk[K] is the first block of the run in
 // launches of kind K, and entry n holds the totals.  Every run computes exactly
 // what its own single-run launch would.
-enum BlockKind { kVolume = 0, kFace = 1, kLaser = 2, kWave = 3, kNumKinds = 4 };
+enum BlockKind { kVolume = 0, kFace = 1, kLaser = 2, kWave = 3, kWaveI = 4, kNumKinds = 5 };
 struct BItem {
     const void *rk;     // the run's RunK<T> (device)
     long step0;         // the run's step counter at the first step of the call
@@ -99,6 +99,18 @@ struct BItem {
     int chunk;          // rows per wavefront march (fused 2D)
     int pad;
 };
+
+// the run descriptor of a table entry as a wave-uniform pointer into global
+// memory, so that the compiler reads its fields with scalar loads as it does
+// for a descriptor passed as a kernel argument
+template <typename R>
+__device__ __forceinline__ const R *uniform_desc(const void *p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (const R *)(const __attribute__((address_space(1))) R *)(((unsigned long long)hi << 32) | lo);
+}
 
 // index of the run owning block b of a launch of kind K (largest i with blk[K] <= b)
 template <int K>

@@ -274,7 +274,9 @@ __device__ __forceinline__ void phi_body(const RunK<T>& r, long bx, long step)
         lap += ((phi_nb(r, Bp, lb, d, 1, i, j, k, id) - T(2) * pb) + phi_nb(r, Bp, lb, d, -1, i, j, k, id)) * r.inv_dx2[d];
     T sdt = pml_sdt<D>(r, i, j, k);
     T x = r.dt2 * ((sax - r.m2 * pb) + lap) - sdt * sdt * pb;
-    T pn = (((x + sdt * pa) + T(2) * pb) - pa) / (T(1) + sdt);
+    // outside the damping layer the divisor is exactly 1: skip the division
+    T pn = ((x + sdt * pa) + T(2) * pb) - pa;
+    if (sdt != T(0)) pn = pn / (T(1) + sdt);
     r.phi[ln][id] = pn;
 #pragma unroll
     for (int d = 0; d < D; d++) {
@@ -535,12 +537,9 @@ __global__ void __launch_bounds__(256) k_diag_final(const RunK<T> *__restrict__ 
 enum BatchPhase { kPhE0 = 0, kPhC, kPhE1, kPhB, kPhPhi, kPhDiag };
 
 template <int D, typename T, int PH>
-__global__ void __launch_bounds__(256) kb_volume(const BItem *__restrict__ it, int n, long s)
+__device__ __forceinline__ void kb_volume_run(const RunK<T> *__restrict__ rp, long bx, long step)
 {
-    const int i = find_item<kVolume>(it, n, blockIdx.x);
-    const RunK<T>& r = *(const RunK<T> *)it[i].rk;
-    const long bx = blockIdx.x - it[i].blk[kVolume];
-    const long step = it[i].step0 + s;
+    const RunK<T>& r = *rp;
     const int so = (int)(step & 1), sn = so ^ 1, la = (int)(step % 3), lb = (int)((step + 1) % 3);
     if (PH == kPhE0) e0_body<D, T>(r, bx, so, so, sn, T(1));
     else if (PH == kPhC) c_body<D, T>(r, bx, la, lb, so, sn, so, 0);
@@ -550,18 +549,37 @@ __global__ void __launch_bounds__(256) kb_volume(const BItem *__restrict__ it, i
     else diag_body<D, T>(r, bx, step);
 }
 
+template <int D, typename T, int PH>
+__global__ void __launch_bounds__(256) kb_volume(const BItem *__restrict__ it, int n, long s)
+{
+    const int i = find_item<kVolume>(it, n, blockIdx.x);
+    kb_volume_run<D, T, PH>(uniform_desc<RunK<T>>(it[i].rk), blockIdx.x - it[i].blk[kVolume], it[i].step0 + s);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void kb_mur_run(const RunK<T> *__restrict__ rp, long bx, long step)
+{
+    mur_body<D, T>(*rp, bx, step);
+}
+
 template <int D, typename T>
 __global__ void __launch_bounds__(256) kb_mur(const BItem *__restrict__ it, int n, long s)
 {
     const int i = find_item<kFace>(it, n, blockIdx.x);
-    mur_body<D, T>(*(const RunK<T> *)it[i].rk, blockIdx.x - it[i].blk[kFace], it[i].step0 + s);
+    kb_mur_run<D, T>(uniform_desc<RunK<T>>(it[i].rk), blockIdx.x - it[i].blk[kFace], it[i].step0 + s);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void kb_inc_run(const RunK<T> *__restrict__ rp, long bx, long L0, int nlev)
+{
+    inc_fill_body<D, T>(*rp, bx, L0, nlev);
 }
 
 template <int D, typename T>
 __global__ void __launch_bounds__(256) kb_inc_fill(const BItem *__restrict__ it, int n, long s, int nlev)
 {
     const int i = find_item<kLaser>(it, n, blockIdx.x);
-    inc_fill_body<D, T>(*(const RunK<T> *)it[i].rk, blockIdx.x - it[i].blk[kLaser], it[i].step0 + s, nlev);
+    kb_inc_run<D, T>(uniform_desc<RunK<T>>(it[i].rk), blockIdx.x - it[i].blk[kLaser], it[i].step0 + s, nlev);
 }
 
 // one block per run: record `ev` of this call goes to slot (rec0 + ev) mod rec_cap

@@ -49,6 +49,8 @@ struct Run {
     bool use_fused = false;
     int chunk = 0;                 // fused planes per workgroup (0: default)
     bool lds_march = false;          // 2D fused: the LDS-marching kernel instead of the wavefront one
+    hipStream_t side = nullptr;      // 2D fused: stream of the boundary-frame launch (created on use)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     long inc_lo = -1;               // first time level held by the laser table
 
     template <typename T> const RunK<T>& hk() const;
@@ -70,6 +72,7 @@ int run_prepare(Run *R);
 bool run_wave2d(const Run *R);
 int run_wave_chunk(const Run *R);
 int run_diag_now(Run *R, axf_diag_record *out);
+void run_release(Run *R);
 bool fused_supported(const axf_config *c);
 
 }  // namespace axf

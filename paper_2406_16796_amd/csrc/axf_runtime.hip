@@ -357,10 +357,21 @@ static int steps_fused(Run *R, int64_t nsteps)
         int chunk = R->chunk > 0 ? R->chunk : FusedShape<D, T>::chunk;
         const bool wave2d = run_wave2d(R);
         if (wave2d) chunk = run_wave_chunk(R);
+        WaveStreams ws{nullptr, nullptr, nullptr};
+        const char *sidee = getenv("AXF_WAVE_SIDE");      // 0: frame launch on the run's stream
+        if (wave2d && !(sidee && sidee[0] == '0')) {
+            if (!R->side) {
+                HIPCHK(hipStreamCreateWithFlags(&R->side, hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&R->ev_fork, hipEventDisableTiming));
+                HIPCHK(hipEventCreateWithFlags(&R->ev_join, hipEventDisableTiming));
+            }
+            ws = WaveStreams{R->side, R->ev_fork, R->ev_join};
+        }
         for (int64_t it = 0; it < nsteps; it++) {
             long s = R->step;
             ensure_incident<D, T>(R, s);
-            hipError_t e = wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->stream) : F::launch(rk, h, s, chunk, R->stream);
+            hipError_t e = wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->stream, ws.side ? &ws : nullptr)
+                                  : F::launch(rk, h, s, chunk, R->stream);
             if (e != hipSuccess) return hip_fail(e, "fused step launch");
             if (R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0) {
                 Plain<D, T>::diag(rk, h, s, R->rec_written % h.rec_cap, R->stream);
@@ -470,9 +481,14 @@ int run_prepare(Run *R)
     return AXF_OK;
 }
 
-bool run_wave2d(const Run *R) { return R->use_fused && R->cfg.ndim == 2 && !R->lds_march; }
+// the wavefront kernel addresses the 27 field arrays it touches with 32-bit
+// byte offsets from one base (the LDS-marching kernel covers larger grids)
+bool run_wave2d(const Run *R)
+{
+    return R->use_fused && R->cfg.ndim == 2 && !R->lds_march && (uint64_t)R->L.arr_stride * 27 <= (1ull << 32);
+}
 
-int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 32; }
+int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 8; }
 
 int run_step(Run *R, int64_t nsteps)
 {
@@ -671,6 +687,19 @@ int run_write_state(Run *R, const void *buf, size_t bytes)
     return AXF_OK;
 }
 
+// library-side handles of a run (events, the side stream)
+void run_release(Run *R)
+{
+    if (R->side) hipStreamSynchronize(R->side);
+    if (R->ev0) hipEventDestroy(R->ev0);
+    if (R->ev1) hipEventDestroy(R->ev1);
+    if (R->ev_fork) hipEventDestroy(R->ev_fork);
+    if (R->ev_join) hipEventDestroy(R->ev_join);
+    if (R->side) hipStreamDestroy(R->side);
+    R->ev0 = R->ev1 = R->ev_fork = R->ev_join = nullptr;
+    R->side = nullptr;
+}
+
 }  // namespace axf
 
 // =================================================================== C ABI
@@ -806,8 +835,7 @@ int axf_destroy(axf_run *run)
 {
     if (!run) return AXF_OK;
     if (run->batch_owned) return fail(AXF_ESTATE, "runs of a batch are released with the batch");
-    if (run->ev0) hipEventDestroy(run->ev0);
-    if (run->ev1) hipEventDestroy(run->ev1);
+    run_release(run);
     delete run;
     return AXF_OK;
 }

@@ -155,6 +155,7 @@ def serving_requests(count=2000, rate=100.0, seed=0, frac_3d=0.1, n3d=(128, 256)
     Returns a list of (arrival_time_s, cfg)."""
     rng = np.random.default_rng(BASE_SEED + 4 + 1000 * seed)
     scan = scan_runs(count=count, seed=seed + 17)
+    order = rng.permutation(count)     # the scan lists its 1D runs first
     out, t = [], 0.0
     for r in range(count):
         t += float(rng.exponential(1.0 / rate))
@@ -163,7 +164,7 @@ def serving_requests(count=2000, rate=100.0, seed=0, frac_3d=0.1, n3d=(128, 256)
             cfg = focused_3d(n=side, steps=int(rng.integers(1000, 5001)), seed=100 + r)
             cfg["name"] = "req3d_%04d" % r
         else:
-            cfg = dict(scan[r])
+            cfg = dict(scan[int(order[r])])
             cfg["name"] = "req_%04d" % r
         out.append((t, cfg))
     return out

@@ -37,7 +37,7 @@ def mixed_runs():
         c = W.plane_wave_1d(nx=n, m=0.3, g=0.02, a0=0.5, ax_bc=bc, omega=1.3)
         c.update(packet_on=1, pk_amp=0.2, pk_k=1.0, pk_w=6.0, pk_x0=0.5 * n * c["dx"][0], pml_n=12)
         out.append(c)
-    for (nx, ny), bc in (((40, 30), W.AX_OUTFLOW), ((90, 70), W.AX_PML), ((130, 61), W.AX_REFLECT)):
+    for (nx, ny), bc in (((40, 30), W.AX_OUTFLOW), ((290, 160), W.AX_PML), ((130, 61), W.AX_REFLECT)):
         c = W.gaussian_2d(n=nx, m=0.25, g=0.03, a0=0.5, waist_lam=1.2, fwhm_lam=1.5,
                           slab=(5, nx - 5), ax_bc=bc, seed=nx)
         dx = c["dx"][0]

@@ -118,6 +118,25 @@ def test_2d_fp64_matches_oracle(axf, ax_bc):
     check_energies(run.diag_now(), ora, 1e-10)
 
 
+@pytest.mark.parametrize("ny", [64, 96])
+def test_2d_fused_rows_multiple_of_chunk_match_oracle(axf, ny):
+    """n_y a multiple of the fused kernel's row chunk: the last chunk holds only
+    the nodal top row, and it alone reaches the top Mur ghost of E1."""
+    cfg = small_2d(W.AX_PML, n=(130, ny))
+    cfg["path"] = axf.PATH_FUSED
+    run, ora = run_both(axf, cfg, axf.F64, 300)
+    check_fields(run, ora, 1e-10, "2d fused ny=%d" % ny)
+
+
+def test_3d_fused_planes_multiple_of_chunk_match_oracle(axf):
+    """The same for the 3D marching kernel along z (n_z = 128, one chunk of 128
+    and a last chunk of the nodal top plane)."""
+    cfg = small_3d(n=(14, 12, 128))
+    cfg.update(path=axf.PATH_FUSED, z_c=64 * cfg["dx"][0], pk_z0=100 * cfg["dx"][0])
+    run, ora = run_both(axf, cfg, axf.F64, 90)
+    check_fields(run, ora, 1e-10, "3d fused nz=128")
+
+
 def test_3d_fp64_matches_oracle(axf):
     cfg = small_3d()
     run, ora = run_both(axf, cfg, axf.F64, cfg["steps"])
@@ -167,14 +186,22 @@ def test_fp32_tracks_oracle(axf, kind):
     assert abs(rec["h_em1"] / h[2] - 1) < 1e-3
 
 
-@pytest.mark.parametrize("kind", ["2d_out", "2d_pml", "2d_ref", "3d"])
+def wide_2d(ax_bc, n=(300, 170)):
+    """Large enough for interior wavefronts (clear of every face and PML layer)."""
+    cfg = small_2d(ax_bc, n=n)
+    cfg["pml_n"] = 10
+    return cfg
+
+
+@pytest.mark.parametrize("kind", ["2d_out", "2d_pml", "2d_ref", "2d_wide_pml", "2d_wide_out", "3d"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_fused_equals_plain_bitwise(axf, kind, prec):
-    """The fused one-pass kernel evaluates the same point formulas in the same
+    """The fused one-pass kernels evaluate the same point formulas in the same
     order as the unfused kernels (no FP contraction), so the states agree bit
-    for bit, boundaries included."""
+    for bit, boundaries included; the wide grids run both the interior and the
+    boundary-frame wavefront kernels."""
     cfg = {"2d_out": small_2d(W.AX_OUTFLOW), "2d_pml": small_2d(W.AX_PML), "2d_ref": small_2d(W.AX_REFLECT),
-           "3d": small_3d()}[kind]
+           "2d_wide_pml": wide_2d(W.AX_PML), "2d_wide_out": wide_2d(W.AX_OUTFLOW), "3d": small_3d()}[kind]
     p = axf.F32 if prec == "f32" else axf.F64
     runs = []
     for path in (axf.PATH_PLAIN, axf.PATH_FUSED):
