@@ -780,7 +780,7 @@ __device__ __forceinline__ double lane_dn(double v)
 
 constexpr int kWaveOut = 59;   // output columns per wavefront
 // prefetch distance (rows ahead) of the interior march, by precision (measured)
-template <typename T> struct WavePD { static constexpr int value = 2; };
+template <typename T> struct WavePD { static constexpr int value = sizeof(T) == 8 ? 2 : 3; };
 
 // global load / store at a 32-bit byte offset from a wave-uniform base (every
 // array of a run has the same layout, so one offset per row serves them all)
@@ -955,14 +955,16 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
 #pragma unroll
     for (int k = 0; k < PD; k++)
         if (t_first + k <= t_last) prefetch(t_first + k, buf[k]);
-    // the march, unrolled by the prefetch distance so that every buffer has a
-    // fixed register home
-    for (int t0 = t_first; t0 <= t_last; t0 += PD)
+    // the march, unrolled by a multiple of the prefetch distance and of the
+    // window lengths (2 and 3) so that every buffer and window has a fixed
+    // register home across the unrolled block
+    constexpr int U = PD == 1 ? 1 : 6;
+    for (int t0 = t_first; t0 <= t_last; t0 += U)
 #pragma unroll
-    for (int k = 0; k < PD; k++) {
+    for (int k = 0; k < U; k++) {
         const int t = t0 + k;
         if (t > t_last) break;
-        Pref& P = buf[k];
+        Pref& P = buf[k % PD];
         asm volatile("" : "+s"(as_l));
         // rotate the windows and take in the prefetched planes
         b0z_2 = b0z_1; b0z_1 = b0z_0; b0z_0 = (vx_nod && P.yn0) ? P.b0z : T(0);
