@@ -6,9 +6,14 @@
   P = (g B0 l / 2)^2 sinc^2(kappa l / 2), against the oracle's local
   energy-density ratio on the 4096-cell CW run, both in its continuum form
   and with the discrete dispersion of the scheme put in;
-- Mur + plane-wave injection (not in the paper): transmitted amplitude.
+- Mur + plane-wave injection (not in the paper): transmitted amplitude;
+- exact phase matching at m = 0 (the two discrete dispersion relations
+  coincide along an axis: P grows as l^2);
+- reciprocity P(photon -> axion) = P(axion -> photon) over a B slab.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -17,6 +22,8 @@ from oracle.oracle import Oracle
 from paper_2406_16796_amd import workloads as W
 
 pytestmark = pytest.mark.slow
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")))
 
 
 @pytest.mark.parametrize("bc,name", [(W.AX_OUTFLOW, "outflow"), (W.AX_PML, "pml")])
@@ -32,7 +39,7 @@ def test_absorbing_axion_boundary_reflectivity(bc, name):
     h0 = o.energies()[0]
     o.step(int(round(L / cfg["dt"])))
     r_energy = o.energies()[0] / h0
-    assert r_energy < 1e-2, (name, r_energy)
+    assert r_energy < GOLDEN["boundary_reflectivity"][name], (name, r_energy)
     assert math.sqrt(r_energy) < 5e-2, (name, r_energy)
 
 
@@ -98,3 +105,85 @@ def test_mur_injection_transmits_the_plane_wave(cw_run):
     # time-averaged energy density of a travelling wave: a0^2 (1 + cos^2(w dt/2)) / 4
     dens = h_em[sel] / h_em[sel].mean()
     assert np.abs(dens - 1.0).max() < 1e-2
+
+
+def test_massless_conversion_is_exactly_phase_matched():
+    """m = 0: the Klein-Gordon and Yee dispersion relations coincide along an
+    axis, so the scheme's axion and photon wave numbers are equal and P grows
+    as l^2 with no sinc factor (Sec. III.B with kappa = 0).  The discrete
+    limit of the two-wave solution above gives P = (g B0 l / 2)^2 / (1 - (dx
+    Omega / 2)^2), Omega = (2/dt) sin(dt/2)."""
+    cfg = W.plane_wave_1d(m=0.0)
+    o = Oracle(cfg)
+    dt, dx = cfg["dt"], cfg["dx"][0]
+    nx, win = cfg["n"][0], 420
+    o.step(cfg["steps"] - win)
+    h_phi = np.zeros(nx)
+    h_em = np.zeros(nx)
+    for s in range(win):
+        w = math.sin(math.pi * (s + 0.5) / win) ** 2
+        pa, pb = o.field("PHI_OLD")[0, 0, :nx], o.field("PHI_NEW")[0, 0, :nx]
+        pm = 0.5 * (pa + pb)
+        gr = (np.roll(pm, -1) - pm) / dx
+        h_phi += w * 0.5 * (((pb - pa) / dt) ** 2 + gr ** 2)
+        h_em += w * 0.5 * (o.field("E0Y")[0, 0, :nx] ** 2 + o.field("B0Z")[0, 0, :nx] ** 2)
+        o.step(1)
+    x = (np.arange(nx) + 0.5) * dx
+    sel = (x > 50.0) & (x < 700.0)
+    p_sim = h_phi[sel] / h_em[sel]
+    om = 2.0 / dt * math.sin(dt / 2.0)
+    p_disc = (0.5 * cfg["g"] * cfg["bext"][1] * x[sel]) ** 2 / (1.0 - (dx * om / 2.0) ** 2)
+    assert np.abs(p_sim / p_disc - 1.0).max() < 0.015
+    # l^2 growth: no coherence length (the massive run above falls below it)
+    ratio = p_sim / x[sel] ** 2
+    assert ratio.max() / ratio.min() < 1.03
+
+
+def _slab_run(kind, m, l_lam=64.0, g=1e-3, b0=1.0, ppw=20):
+    """1D: B0 = b0 along y in a slab of length l between vacuum margins; a
+    pulse (laser) or an axion packet of the same Gaussian envelope crosses it;
+    returns the conversion probability once it has left the slab."""
+    lam = 2.0 * math.pi
+    dx = lam / ppw
+    w = 6.0 * lam                              # 1/e amplitude half-width of the envelope
+    n_margin = int(round(5 * w / dx))
+    n_slab = int(round(l_lam * lam / dx))
+    nx = 2 * n_margin + n_slab + int(round(3 * w / dx))
+    cfg = W.plane_wave_1d(nx=nx, m=m, g=g, a0=1e-3, b0=b0, ppw=ppw, ax_bc=W.AX_OUTFLOW)
+    cfg.update(slab_lo=n_margin, slab_hi=n_margin + n_slab)
+    x_end = (n_margin + n_slab) * dx
+    if kind == "photon":
+        # Gaussian envelope exp(-u^2), u = (t - x - t_c) / tau0 with tau0 = w
+        fwhm = 2.0 * w * math.sqrt(math.log(2.0) / 2.0)
+        cfg.update(laser_env=W.ENV_GAUSS, fwhm=fwhm, t_center=2.5 * w)
+        t_end = x_end + 2.5 * w + 3.0 * w
+    else:
+        k = math.sqrt(1.0 - m * m)             # same frequency as the laser
+        cfg.update(laser_on=0, e_amp=0.0, packet_on=1, pk_amp=1e-3, pk_k=k, pk_w=w,
+                   pk_x0=n_margin * dx - 2.5 * w, pk_dir=1)
+        t_end = (x_end - cfg["pk_x0"]) / (k / math.sqrt(k * k + m * m)) + 3.0 * w
+    o = Oracle(cfg)
+    o.step(int(math.ceil(t_end / cfg["dt"])))
+    h_phi, h_em0, h_em1 = o.energies()
+    l = n_slab * dx
+    return (h_phi / h_em0 if kind == "photon" else h_em1 / h_phi), l
+
+
+@pytest.mark.parametrize("m", [0.0, 0.1])
+def test_reciprocity_photon_axion(m):
+    """P(photon -> axion) = P(axion -> photon) for the same frequency, mass,
+    coupling, field and length (Sec. III.B), both close to the closed form
+    (g B0 l / 2)^2 sinc^2(kappa l / 2) for a narrow-band pulse."""
+    p_ga, l = _slab_run("photon", m)
+    p_ag, _ = _slab_run("axion", m)
+    kappa = math.sqrt(1.0 - m * m) - 1.0
+    p_cf = 0.25 * (1e-3 * 1.0 * l) ** 2 * np.sinc(kappa * l / (2 * math.pi)) ** 2
+    # the scheme's factor of the massless limit (see the test above); the rest
+    # of the difference at m > 0 is the 1.6% error of its discrete kappa
+    dx = 2.0 * math.pi / 20
+    dt = 0.95 * dx
+    om = 2.0 / dt * math.sin(dt / 2.0)
+    p_disc = p_cf / (1.0 - (dx * om / 2.0) ** 2)
+    print("m=%g P_ga=%.5e P_ag=%.5e closed=%.5e" % (m, p_ga, p_ag, p_disc))
+    assert abs(p_ga / p_ag - 1.0) < 5e-3
+    assert abs(p_ga / p_disc - 1.0) < (1e-3 if m == 0.0 else 0.015)
