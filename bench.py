@@ -28,6 +28,7 @@ import argparse
 import csv
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -36,6 +37,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# built-in (rows per march, prefetch distance) of the 2D wavefront step
+DEFAULT_WAVE_SHAPE = {"f32": (8, 3), "f64": (8, 2)}
 COPY_BYTES = 1 << 30
 KERNEL_SOURCES = ["paper_2406_16796_amd/csrc/axf_fused.hip", "paper_2406_16796_amd/csrc/axf_fused.h",
                   "paper_2406_16796_amd/csrc/axf_stencil.h", "paper_2406_16796_amd/csrc/axf_internal.h",
@@ -160,13 +163,23 @@ def cpu_baseline(cfg, target_s=15.0):
                       % ("x".join(map(str, n)), steps, dt)}
 
 
-def scan_leg(axf, torch, steps_scale, count=512):
+def scan_leg(axf, torch, steps_scale, count=512, tune=True):
     """Batched parameter scan (512 runs: 1D 1k-64k cells, 2D 256^2-1024^2, step
     counts scaled by steps_scale) against the same runs launched one by one."""
     from paper_2406_16796_amd import workloads as W
     cfgs = W.scan_runs(count=count)
     steps = [max(1, int(round(c["steps"] * steps_scale))) for c in cfgs]
     work = sum(W.active_cells(c) * n for c, n in zip(cfgs, steps))
+    # tile shapes: one tuning run per power-of-two size class of the 2D runs
+    classes = {}
+    for c in cfgs:
+        if int(c["n"][1]) > 1:
+            classes.setdefault(tuple(int(math.ceil(math.log2(int(v)))) for v in c["n"][:2]), c)
+    tuned = {}
+    if tune:
+        for key, c in sorted(classes.items()):
+            t = axf.tune(c, precision=axf.F32, steps=10)
+            tuned["%dx%d" % (1 << key[0], 1 << key[1])] = [t["chunk"], t["prefetch"]]
     batch = axf.Batch(cfgs, precision=axf.F32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -197,7 +210,8 @@ def scan_leg(axf, torch, steps_scale, count=512):
             "batched": round(work / t_batch / 1e9, 3), "per_run": round(work / t_alone / 1e9, 3),
             "unit": "Gcell-updates/s", "speedup": round(t_alone / t_batch, 3),
             "batched_s": round(t_batch, 3), "per_run_s": round(t_alone, 3),
-            "p_bitwise_equal": all(p_batch[i] == p_alone[i] for i in probe)}
+            "p_bitwise_equal": all(p_batch[i] == p_alone[i] for i in probe),
+            "tuned_chunk_prefetch": tuned}
 
 
 def percentile(v, q):
@@ -391,6 +405,7 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV")
     ap.add_argument("--no-scan", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shapes")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--steps-scale", type=float, default=0.1,
                     help="step counts of the scan and serving legs relative to the workload's 1000-5000")
@@ -422,6 +437,10 @@ def main():
     kernel, pats = WORKLOADS[args.workload][1], WORKLOADS[args.workload][2]
 
     copy_gbs = device_copy(torch)
+    tuned = None
+    if not args.no_tune and not args.profile_only:
+        axf.tune_reset()
+        tuned = axf.tune(cfg, precision=prec, steps=12)
     if args.profile_only:
         time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, 2, 0)
         print(json.dumps({"profile_only": tag, "steps": args.steps}), flush=True)
@@ -438,7 +457,10 @@ def main():
     per_launch_s = k_ms / 1e3 / args.steps
     algo_bytes = words_per_cell(ndim) * esize * nc
     achieved = algo_bytes / per_launch_s / 1e9
-    traffic = read_traffic(tag, kernel) if fused else None
+    # the counter summary was taken with the built-in launch shape
+    default_shape = DEFAULT_WAVE_SHAPE[args.precision]
+    same_shape = tuned is None or (tuned["chunk"], tuned["prefetch"]) == default_shape
+    traffic = read_traffic(tag, kernel) if fused and same_shape else None
     # the unfused phase sequence for comparison
     p_wall, _, p_launches, _, _ = time_path(axf, torch, cfg, prec, axf.PATH_PLAIN, args.plain_steps, 2, 0)
     plain_value = nc * args.plain_steps / p_wall / 1e9
@@ -469,6 +491,10 @@ def main():
             "unit_of_work": "one fused step of the whole grid", "bytes_per_step": algo_bytes,
             "mean_step_ms": round(per_launch_s * 1e3, 5), "steps_timed": args.steps,
             "copy_kernel_GBs": round(copy_gbs, 1),
+            "tuned": None if tuned is None else {"chunk": tuned["chunk"], "prefetch": tuned["prefetch"],
+                                                 "candidates": tuned["candidates"],
+                                                 "best_ms": round(tuned["ms_per_step"], 4),
+                                                 "default_ms": round(tuned["default_ms_per_step"], 4)},
         },
         "plain": {"value": round(plain_value, 3), "unit": "Gcell-updates/s",
                   "ms_per_step": round(p_wall / args.plain_steps * 1e3, 4),
@@ -477,7 +503,7 @@ def main():
         "diag": {"step": rec["step"], "p_gen": rec["p_gen"], "p_conv": rec["p_conv"], "finite": rec["finite"]},
     }
     if not args.no_scan:
-        line["scan"] = scan_leg(axf, torch, args.steps_scale)
+        line["scan"] = scan_leg(axf, torch, args.steps_scale, tune=not args.no_tune)
     if not args.no_serve:
         rates = [float(v) for v in args.serve_rates.split(",") if v]
         line["serving"] = serve_leg(axf, torch, rates, args.serve_requests, args.steps_scale, pool_gb=64,

@@ -179,44 +179,97 @@ int axf_destroy(axf_run *run);
    the run's stream: total ms over the steps and the number of step launches. */
 int axf_last_step_timing(const axf_run *run, double *ms, int64_t *launches);
 
-/* ------------------------------------------------------------ batches */
+/* ------------------------------------------------------------ tuning
+ * Launch shape of the fused 2D step (rows per wavefront march and prefetch
+ * distance), chosen by timing every candidate on a scratch run.  The choice
+ * is kept in a process-wide table keyed by dimensionality, precision,
+ * boundary kinds and the power-of-two size class of the grid; runs and
+ * batches created afterwards with a matching key use it.  Configurations
+ * without a fused 2D path report AXF_PATH_PLAIN and keep their launches.
+ */
+typedef struct {
+    int32_t path;                /* AXF_PATH_FUSED or AXF_PATH_PLAIN */
+    int32_t chunk;               /* rows per wavefront march (fused 2D) */
+    int32_t prefetch;            /* rows prefetched ahead (fused 2D) */
+    int32_t candidates;          /* shapes timed */
+    double  ms_per_step;         /* best */
+    double  default_ms_per_step; /* the built-in default shape */
+} axf_tuning;
 
-/* Many independent runs carved from one device buffer; one launch per kernel
-   kind and dimensionality advances every active run by one step. */
+/* Time the candidates for `steps` steps each on a run carved from `scratch`
+   (caller device memory of >= axf_footprint bytes; its contents are
+   overwritten), record the best.  Synchronises `stream`. */
+int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, int32_t steps, axf_tuning *out);
+/* Forget every recorded choice (pure host call). */
+int axf_tune_reset(void);
+
+/* ------------------------------------------------------------ batches
+ * Many independent runs (parameter scans over m, g, B0, omega and grid size)
+ * carved from one caller device buffer.  Runs are grouped by dimensionality,
+ * precision and step path; one batched launch per kernel kind and group
+ * advances every active run of the group by one step, each run with its own
+ * step counter.  Every run's result is bit-identical to the same run created
+ * with axf_create and stepped alone.
+ */
+
+/* Device bytes of a batch: a launch table plus each run's footprint, each
+   256-byte aligned.  Pure host call; EINVAL names the first bad configuration. */
 int axf_batch_footprint(const axf_config *cfgs, int32_t count, size_t *bytes);
+/* Create `count` runs in `dev_buf` (256-byte aligned, >= the batch footprint),
+   all on `stream`.  Errors as axf_create, for the first run that fails. */
 int axf_batch_create(const axf_config *cfgs, int32_t count, void *dev_buf, size_t bytes,
                      void *stream, axf_batch **out);
-/* advance run i by nsteps[i] steps (runs finish at different times) */
+/* Advance run i by nsteps[i] >= 0 steps (array of `count`); runs with fewer
+   steps drop out of the launches when done.  Asynchronous on the stream. */
 int axf_batch_step(axf_batch *b, const int64_t *nsteps);
-/* borrowed view of run i (do not destroy it) */
+/* Borrowed view of run i for the single-run read, diagnostic and state
+   calls; axf_step and axf_destroy on a view fail with AXF_ESTATE. */
 int axf_batch_run(axf_batch *b, int32_t i, axf_run **view);
+/* Synchronise the stream and release the batch (not the caller's memory). */
 int axf_batch_destroy(axf_batch *b);
 
-/* ------------------------------------------------------------ server */
+/* ------------------------------------------------------------ server
+ * Continuous batching of conversion requests on one GPU.  A host thread
+ * drives the GPU: each round it admits queued requests that fit (a free slot
+ * and a first-fit range of the pool; a request passed over for more than a
+ * few rounds blocks later ones from overtaking it), creates them in the pool,
+ * and advances every resident run by a work slice of about
+ * macro_steps x 2^20 cell-updates (at least one step, at most what remains)
+ * through the batched launches.  Finished or cancelled runs are retired and
+ * their memory returns to the pool.  A result's final record is bit-identical
+ * to the same run stepped alone.
+ */
 
-/* Result of one served request. Times are seconds on the server's clock. */
+/* Result of one served request.  Times are seconds on the server's clock. */
 typedef struct {
     uint64_t id;
     int32_t  status;         /* 0 ok, AXF_E* on failure, 1 cancelled */
     int32_t  pad;
-    int64_t  steps;
-    int64_t  cells;
+    int64_t  steps;          /* steps taken */
+    int64_t  cells;          /* n[0] n[1] n[2] */
     double   t_submit, t_admit, t_done;
-    axf_diag_record final;   /* record at the last step */
+    axf_diag_record final;   /* record at the last step (status 0 only) */
 } axf_result;
 
-/* Continuous-batching server on one GPU.  `pool` is caller device memory of
-   `pool_bytes` from which resident runs are carved (admission by footprint);
-   at most `max_slots` runs are resident; `macro_steps` steps are taken per
-   batched launch round.  A host thread drives the GPU until destroy. */
+/* `pool` is caller device memory (256-byte aligned) of `pool_bytes`; the
+   server keeps a small launch table at its start and carves resident runs
+   from the rest.  At most `max_slots` runs are resident.  The server's thread
+   enqueues all GPU work on `stream`. */
 int axf_server_create(void *pool, size_t pool_bytes, int32_t max_slots, int32_t macro_steps,
                       void *stream, axf_server **out);
+/* Queue a request of `nsteps` steps; *id identifies its result.  ENOMEM if
+   the run can never fit the pool, EINVAL/EUNSTABLE for a bad configuration. */
 int axf_server_submit(axf_server *s, const axf_config *cfg, int64_t nsteps, uint64_t *id);
+/* Cancel a queued or resident request; its result has status 1.  ENOTFOUND
+   if the request is neither queued nor resident. */
 int axf_server_cancel(axf_server *s, uint64_t id);
-/* completed results (oldest first), up to max; *n = count; non-blocking */
+/* Move up to `max` completed results (oldest first) to `out`; *n = count.
+   Never blocks. */
 int axf_server_poll(axf_server *s, axf_result *out, int32_t max, int32_t *n);
-/* queue depth, resident runs, bytes in use */
+/* Queue depth, resident runs and pool bytes in use (any argument may be NULL). */
 int axf_server_stats(axf_server *s, int32_t *queued, int32_t *resident, size_t *bytes_used);
+/* Stop after the current round (resident runs end as cancelled, queued ones
+   are dropped), join the thread, release the server. */
 int axf_server_destroy(axf_server *s);
 
 #ifdef __cplusplus

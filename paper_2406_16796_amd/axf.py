@@ -24,7 +24,7 @@ EXPORTS = [
     "axf_last_error", "axf_version", "axf_footprint", "axf_extents", "axf_create", "axf_write_field",
     "axf_step", "axf_read_field", "axf_diag_now", "axf_read_diag", "axf_state_bytes", "axf_read_state",
     "axf_write_state", "axf_sync", "axf_steps_done", "axf_path_in_use", "axf_destroy", "axf_last_step_timing",
-    "axf_batch_footprint", "axf_batch_create", "axf_batch_step", "axf_batch_run", "axf_batch_destroy",
+    "axf_tune", "axf_tune_reset", "axf_batch_footprint", "axf_batch_create", "axf_batch_step", "axf_batch_run", "axf_batch_destroy",
     "axf_server_create", "axf_server_submit", "axf_server_cancel", "axf_server_poll", "axf_server_stats",
     "axf_server_destroy",
 ]
@@ -64,6 +64,12 @@ class DiagRecord(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("chunk", ctypes.c_int32), ("prefetch", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("ms_per_step", ctypes.c_double),
+                ("default_ms_per_step", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -107,6 +113,8 @@ def lib():
         "axf_path_in_use": ([vp, P(i32)], ctypes.c_int),
         "axf_destroy": ([vp], ctypes.c_int),
         "axf_last_step_timing": ([vp, P(dp), P(i64)], ctypes.c_int),
+        "axf_tune": ([P(Config), vp, sz, vp, i32, P(Tuning)], ctypes.c_int),
+        "axf_tune_reset": ([], ctypes.c_int),
         "axf_batch_footprint": ([P(Config), i32, P(sz)], ctypes.c_int),
         "axf_batch_create": ([P(Config), i32, vp, sz, vp, P(vp)], ctypes.c_int),
         "axf_batch_step": ([vp, P(i64)], ctypes.c_int),
@@ -187,6 +195,23 @@ def device_buffer(nbytes, device="cuda:0"):
 
 def current_stream():
     return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def tune(cfg, precision=F32, steps=20, stream=None):
+    """Time the fused 2D launch shapes on a scratch run of this configuration
+    and record the best for runs of its size class; returns the choice."""
+    c = make_config(cfg, precision=precision)
+    nbytes = footprint(cfg, precision=precision)
+    scratch = device_buffer(nbytes)
+    out = Tuning()
+    check(lib().axf_tune(ctypes.byref(c), ctypes.c_void_p(scratch.data_ptr()), scratch.numel(),
+                         stream if stream is not None else current_stream(), int(steps), ctypes.byref(out)))
+    del scratch
+    return {k: getattr(out, k) for k, _ in out._fields_}
+
+
+def tune_reset():
+    check(lib().axf_tune_reset())
 
 
 class Run:

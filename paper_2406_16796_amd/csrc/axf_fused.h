@@ -26,7 +26,7 @@ struct Fused {
 // Fused 2D step on wavefront-owned x segments (no LDS, no barriers): the
 // interior launch on `st`, the boundary-frame launch on ws->side when given.
 template <typename T>
-hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st,
+hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, int pd, hipStream_t st,
                          const WaveStreams *ws);
 // the same over the first n runs of a batch table at step s of the call
 template <typename T>

@@ -1325,13 +1325,12 @@ hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s
 }
 
 template <typename T>
-hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, hipStream_t st,
+hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chunk, int pd, hipStream_t st,
                          const WaveStreams *ws)
 {
     const WaveSplit w = wave2d_split(h, chunk);
     const unsigned ni = (unsigned)((w.interior() + 3) / 4), ne = (unsigned)((w.edge() + 3) / 4);
-    const char *pde = getenv("AXF_WAVE_PD");
-    const int pd = pde ? atoi(pde) : WavePD<T>::value;
+    if (pd <= 0) pd = WavePD<T>::value;
     // the frame runs beside the interior on the side stream when there is one
     // (the two launches touch disjoint outputs and read only the old slots)
     const bool fork = ws && ws->side && ne > 0 && ni > 0;
@@ -1354,8 +1353,8 @@ hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chu
     return hipGetLastError();
 }
 
-template hipError_t launch_wave2d<float>(const RunK<float> *, const RunK<float>&, long, int, hipStream_t, const WaveStreams *);
-template hipError_t launch_wave2d<double>(const RunK<double> *, const RunK<double>&, long, int, hipStream_t, const WaveStreams *);
+template hipError_t launch_wave2d<float>(const RunK<float> *, const RunK<float>&, long, int, int, hipStream_t, const WaveStreams *);
+template hipError_t launch_wave2d<double>(const RunK<double> *, const RunK<double>&, long, int, int, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d_batch<float>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d_batch<double>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);
 

@@ -48,6 +48,7 @@ struct Run {
     bool batch_owned = false;
     bool use_fused = false;
     int chunk = 0;                 // fused planes per workgroup (0: default)
+    int pd = 0;                    // 2D wavefront prefetch distance (0: default)
     bool lds_march = false;          // 2D fused: the LDS-marching kernel instead of the wavefront one
     hipStream_t side = nullptr;      // 2D fused: stream of the boundary-frame launch (created on use)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -71,6 +72,8 @@ int run_prepare(Run *R);
 // the run steps with the 2D wavefront kernel; its rows per march
 bool run_wave2d(const Run *R);
 int run_wave_chunk(const Run *R);
+// tuned 2D wavefront shape for a configuration, if one was recorded
+bool tuned_shape(const axf_config *c, int *chunk, int *pd);
 int run_diag_now(Run *R, axf_diag_record *out);
 void run_release(Run *R);
 bool fused_supported(const axf_config *c);

@@ -15,6 +15,9 @@
 #include "axf_internal.h"
 #include "axf_fused.h"
 #include "axf_kernels.h"
+#include <map>
+#include <mutex>
+
 #include "axf_runtime.h"
 
 namespace axf {
@@ -370,7 +373,7 @@ static int steps_fused(Run *R, int64_t nsteps)
         for (int64_t it = 0; it < nsteps; it++) {
             long s = R->step;
             ensure_incident<D, T>(R, s);
-            hipError_t e = wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->stream, ws.side ? &ws : nullptr)
+            hipError_t e = wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->pd, R->stream, ws.side ? &ws : nullptr)
                                   : F::launch(rk, h, s, chunk, R->stream);
             if (e != hipSuccess) return hip_fail(e, "fused step launch");
             if (R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0) {
@@ -446,7 +449,9 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     R->stream = stream;
     if (cfg->path == AXF_PATH_FUSED && !fused_supported(cfg))
         return fail(AXF_EINVAL, "the fused path needs ndim >= 2 and a periodic axion on every periodic EM axis");
+    tuned_shape(cfg, &R->chunk, &R->pd);
     if (const char *ch = getenv("AXF_FUSED_CHUNK")) R->chunk = atoi(ch);
+    if (const char *pd = getenv("AXF_WAVE_PD")) R->pd = atoi(pd);
     if (const char *lm = getenv("AXF_LDS_MARCH")) R->lds_march = lm[0] == '1';
     R->use_fused = cfg->path == AXF_PATH_FUSED || (cfg->path == AXF_PATH_AUTO && fused_supported(cfg) && auto_fused_enabled(cfg));
     choose_scales(cfg, &R->s_phi, &R->s_1);
@@ -687,6 +692,45 @@ int run_write_state(Run *R, const void *buf, size_t bytes)
     return AXF_OK;
 }
 
+// ------------------------------------------------------------ tuning table
+
+struct TuneKey {
+    int ndim, prec, em[3], ax[3], pml, c0, c1, c2;
+    bool operator<(const TuneKey& o) const { return memcmp(this, &o, sizeof *this) < 0; }
+};
+
+static int size_class(int n) { int c = 0; while ((1 << c) < n) c++; return c; }
+
+static TuneKey tune_key(const axf_config *c)
+{
+    TuneKey k;
+    memset(&k, 0, sizeof k);
+    k.ndim = c->ndim;
+    k.prec = c->precision;
+    for (int d = 0; d < 3; d++) {
+        k.em[d] = c->em_bc[d];
+        k.ax[d] = c->ax_bc[d];
+    }
+    k.pml = c->pml_n;
+    k.c0 = size_class(c->n[0]);
+    k.c1 = size_class(c->n[1]);
+    k.c2 = size_class(c->n[2]);
+    return k;
+}
+
+static std::mutex g_tune_mu;
+static std::map<TuneKey, std::pair<int, int>> g_tune;
+
+bool tuned_shape(const axf_config *c, int *chunk, int *pd)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(c));
+    if (it == g_tune.end()) return false;
+    *chunk = it->second.first;
+    *pd = it->second.second;
+    return true;
+}
+
 // library-side handles of a run (events, the side stream)
 void run_release(Run *R)
 {
@@ -712,6 +756,73 @@ extern "C" {
 const char *axf_last_error(void) { return g_err.c_str(); }
 
 const char *axf_version(void) { return "axf 0.1 (gfx950)"; }
+
+int axf_tune_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return AXF_OK;
+}
+
+int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, int32_t steps, axf_tuning *out)
+{
+    if (!out) return fail(AXF_EINVAL, "null output");
+    if (steps <= 0) return fail(AXF_EINVAL, "steps must be positive");
+    memset(out, 0, sizeof *out);
+    int rc = validate(cfg);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    axf_config c = *cfg;
+    c.diag_every = 0;
+    const int shapes[][2] = {{8, 1}, {8, 2}, {8, 3}, {12, 3}, {16, 2}, {16, 3}, {24, 3}, {32, 3}};
+    double best = 1e300;
+    int best_chunk = 0, best_pd = 0;
+    auto time_shape = [&](int chunk, int pd, double *ms) -> int {
+        axf_run R;
+        int e = run_init(&R, &c, scratch, bytes, st);
+        if (e) return e;
+        R.chunk = chunk;
+        R.pd = pd;
+        e = run_step(&R, 2);
+        if (!e) e = run_step(&R, steps);
+        if (!e && hipEventSynchronize(R.ev1) != hipSuccess) e = fail(AXF_EHIP, "tuning run failed");
+        float f = 0.f;
+        if (!e) hipEventElapsedTime(&f, R.ev0, R.ev1);
+        *ms = f / steps;
+        const bool wave = run_wave2d(&R);
+        run_release(&R);
+        if (!e && !wave) return 1;    // no wavefront path for this configuration
+        return e;
+    };
+    double dflt = 0.0;
+    rc = time_shape(0, 0, &dflt);
+    if (rc < 0) return rc;
+    out->default_ms_per_step = dflt;
+    if (rc == 1) {
+        out->path = AXF_PATH_PLAIN;
+        out->ms_per_step = dflt;
+        out->candidates = 1;
+        return AXF_OK;
+    }
+    for (auto& sh : shapes) {
+        double ms = 0.0;
+        rc = time_shape(sh[0], sh[1], &ms);
+        if (rc < 0) return rc;
+        out->candidates++;
+        if (ms < best) {
+            best = ms;
+            best_chunk = sh[0];
+            best_pd = sh[1];
+        }
+    }
+    out->path = AXF_PATH_FUSED;
+    out->chunk = best_chunk;
+    out->prefetch = best_pd;
+    out->ms_per_step = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(cfg)] = {best_chunk, best_pd};
+    return AXF_OK;
+}
 
 int axf_footprint(const axf_config *cfg, size_t *bytes)
 {

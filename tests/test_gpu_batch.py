@@ -171,3 +171,23 @@ def test_server_cancel_and_oversized(axf):
     st = srv.stats()
     assert st["resident"] == 0 and st["queued"] == 0 and st["bytes_used"] == 0
     srv.close()
+
+
+def test_tuned_shape_is_used_and_results_unchanged(axf):
+    """The tuner picks a launch shape for the size class; runs created after it
+    use that shape, and their results are the same bits as with the default."""
+    cfg = mixed_runs()[4]
+    ref = axf.Run(cfg, precision=axf.F32)
+    ref.step(60)
+    axf.tune_reset()
+    choice = axf.tune(cfg, precision=axf.F32, steps=8)
+    assert choice["path"] == axf.PATH_FUSED and choice["candidates"] >= 8
+    assert choice["chunk"] > 0 and choice["prefetch"] > 0
+    assert choice["ms_per_step"] <= choice["default_ms_per_step"] * 1.5
+    run = axf.Run(cfg, precision=axf.F32)
+    run.step(60)
+    axf.tune_reset()
+    for nm in FIELDS:
+        assert np.array_equal(run.read(nm), ref.read(nm)), nm
+    plain = axf.tune(mixed_runs()[0], precision=axf.F32, steps=4)
+    assert plain["path"] == axf.PATH_PLAIN
