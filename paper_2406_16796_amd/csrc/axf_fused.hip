@@ -914,17 +914,21 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
         if (xgs >= 0) return ldo((const T *)face_of(rp, q_axg(0, xgs, L)), (unsigned)row * es);   // x ghost lanes
         return ldq(q_phi(L), bxp + (unsigned)row * sxb);
     };
+    // Rows below the chunk feed the owned rows only through: B0z from row c0-2,
+    // phi from c0-3, E0 from c0-2, B1 from c0-1, E1 from c0-1 (the first owned
+    // row c0 needs E1 and B1 one row down, C two rows down, E0^n and B0 along
+    // with C, phi one row below that).  Older rows of a field are not loaded.
     auto prefetch = [&](int t, Pref& P) __attribute__((always_inline)) {
         const unsigned o0 = off(t), o1 = off(t - 1), o2 = off(t - 2);
         P.b0z = ldq(q_em(1, so, 2), o0);
 #pragma unroll
-        for (int c = 0; c < 3; c++) P.b1[c] = ldq(q_em(3, so, c), o1);
+        for (int c = 0; c < 3; c++) P.b1[c] = t - 1 >= c0 - 1 ? ldq(q_em(3, so, c), o1) : T(0);
         P.pa = load_phi(la, t - 1);
         P.pb = load_phi(lb, t - 1);
 #pragma unroll
-        for (int c = 0; c < 2; c++) P.e0m[c] = ldq(q_em(0, so, c), o1);
+        for (int c = 0; c < 2; c++) P.e0m[c] = t - 1 >= c0 - 2 ? ldq(q_em(0, so, c), o1) : T(0);
 #pragma unroll
-        for (int c = 0; c < 3; c++) P.e1m[c] = ldq(q_em(2, so, c), o2);
+        for (int c = 0; c < 3; c++) P.e1m[c] = t - 2 >= c0 - 1 ? ldq(q_em(2, so, c), o2) : T(0);
         P.yn0 = vy_nod(t);
         P.yn1 = vy_nod(t - 1);
         P.yc1 = vy_cen(t - 1);

@@ -19,6 +19,9 @@ struct Plain {
     static void init_phi(const RunK<T> *rk, const RunK<T>& h, hipStream_t st);
     static void copy_ghosts(const RunK<T> *rk, const RunK<T>& h, int s0, int s1, hipStream_t st);
     static void diag(const RunK<T> *rk, const RunK<T>& h, long step, int slot, hipStream_t st);
+    // semi-fused step: E0 with the axion current, B with the axion update
+    static void e0c(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
+    static void bphi(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
     // batched launches over the first n runs of a sorted table (device `it`,
     // host copy `host` for the grid sizes) at step s of the call
     static void batch_step(const BItem *it, const BItem *host, int n, long s, hipStream_t st);

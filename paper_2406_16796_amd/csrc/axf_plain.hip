@@ -87,6 +87,54 @@ __device__ __forceinline__ void c_body(const RunK<T>& r, long bx, int pa, int pb
     r.C[2][id] = dtphi * b[2] - (e[0] * gp[1] - e[1] * gp[0]);
 }
 
+// E0 update and the axion current C in one launch: the E0^{n+1/2} values the
+// C formula needs at the next face along each axis are recomputed, not read
+template <int D, typename T>
+__device__ __forceinline__ void e0c_body(const RunK<T>& r, long bx, long step)
+{
+    int i, j, k;
+    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
+    const long id = lin(r, i, j, k);
+    const int so = (int)(step & 1), sn = so ^ 1, la = (int)(step % 3), lb = (int)((step + 1) % 3);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (!actE0<D>(c) || !in_E<D>(r, c, i, j, k)) continue;
+        r.E0[sn][c][id] = e0new_at<D, T>(r, so, c, i, j, k);
+    }
+    if (!in_cell(r, i, j, k)) return;
+    T e[3], b[3], gp[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        e[c] = T(0);
+        if (actE0<D>(c)) {
+            const T *m = r.E0[so][c];
+            const long o = c < D ? em_step(r, c, coord(c, i, j, k), 1) : 0;
+            const T p0 = e0new_at<D, T>(r, so, c, i, j, k);
+            T p1 = p0;
+            if (c < D) {
+                int i1 = i, j1 = j, k1 = k;
+                coord_up(r, c, i1, j1, k1);
+                p1 = e0new_at<D, T>(r, so, c, i1, j1, k1);
+            }
+            T lo = r.half * (m[id] + p0);
+            T hi = r.half * (m[id + o] + p1);
+            e[c] = c < D ? r.half * (lo + hi) : lo;
+        }
+        b[c] = centre_B<D, 0>(r, r.B0[so], c, i, j, k, id) + bext_at(r, c, i);
+    }
+    const T *A = r.phi[la], *Bp = r.phi[lb];
+    T dtphi = (Bp[id] - A[id]) * r.inv_dt;
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        T up = r.half * (phi_nb(r, A, la, d, 1, i, j, k, id) + phi_nb(r, Bp, lb, d, 1, i, j, k, id));
+        T dn = r.half * (phi_nb(r, A, la, d, -1, i, j, k, id) + phi_nb(r, Bp, lb, d, -1, i, j, k, id));
+        gp[d] = (up - dn) * r.inv2dx[d];
+    }
+    r.C[0][id] = dtphi * b[0] - (e[1] * gp[2] - e[2] * gp[1]);
+    r.C[1][id] = dtphi * b[1] - (e[2] * gp[0] - e[0] * gp[2]);
+    r.C[2][id] = dtphi * b[2] - (e[0] * gp[1] - e[1] * gp[0]);
+}
+
 // axion current on the E_c face: mean of C_c at the two adjacent centres (one
 // interior centre on a Mur face, wrap on a periodic axis)
 template <int D, typename T>
@@ -248,7 +296,54 @@ __device__ __forceinline__ void b_body(const RunK<T>& r, long bx, long step)
 // phi^{n+3/2}: leapfrog of the Klein-Gordon equation with source g E0.B0 at
 // t_{n+1/2} (Sec. II.C, eq. update_axion), in the damped form of the PML
 // layer (Sec. II.D) where sigma > 0, then the ghosts of the new level.
+// coordinates one step up along axis d (wrapped on a periodic axis)
+template <typename T>
+__device__ __forceinline__ void coord_up(const RunK<T>& r, int d, int& i, int& j, int& k)
+{
+    int& v = d == 0 ? i : (d == 1 ? j : k);
+    v += 1;
+    if (!r.mur[d]) v = wrapi(v, r.n[d]);
+}
+
+// E0^{n+1/2} at face point (i,j,k): the expression the E0 update stores
 template <int D, typename T>
+__device__ __forceinline__ T e0new_at(const RunK<T>& r, int so, int c, int i, int j, int k)
+{
+    const long id = lin(r, i, j, k);
+    return r.E0[so][c][id] + T(1) * curl_B<D, 0>(r, r.B0[so], c, i, j, k, id);
+}
+
+// B0^{n+1} at edge point (i,j,k): the expression the B update stores
+template <int D, typename T>
+__device__ __forceinline__ T b0new_at(const RunK<T>& r, int so, int sn, int c, int i, int j, int k)
+{
+    return r.B0[so][c][lin(r, i, j, k)] - curl_E<D, 0>(r, sn, sn, c, i, j, k);
+}
+
+// centre_B of B0^{n+1} from recomputed edge values (same points, same order)
+template <int D, typename T>
+__device__ __forceinline__ T centre_B0new(const RunK<T>& r, int so, int sn, int c, int i, int j, int k)
+{
+    if (!actB<D, 0>(c)) return T(0);
+    const int a = c == 0 ? 1 : 0, b = c == 2 ? 1 : 2;
+    const bool ua = a < D, ub = b < D;
+    const T p00 = b0new_at<D, T>(r, so, sn, c, i, j, k);
+    if (!ua && !ub) return p00;
+    int ia = i, ja = j, ka = k;
+    coord_up(r, a, ia, ja, ka);
+    const T pa = b0new_at<D, T>(r, so, sn, c, ia, ja, ka);
+    if (!ub) return r.half * (p00 + pa);
+    int ib = i, jb = j, kb = k;
+    coord_up(r, b, ib, jb, kb);
+    int iab = ia, jab = ja, kab = ka;
+    coord_up(r, b, iab, jab, kab);
+    const T pb = b0new_at<D, T>(r, so, sn, c, ib, jb, kb), pab = b0new_at<D, T>(r, so, sn, c, iab, jab, kab);
+    return T(0.25) * ((p00 + pa) + (pb + pab));
+}
+
+// RECOMPUTE: B0^{n+1} at the four edges around the centre is recomputed
+// instead of read (the axion update then runs in the same launch as B)
+template <int D, typename T, bool RECOMPUTE = false>
 __device__ __forceinline__ void phi_body(const RunK<T>& r, long bx, long step)
 {
     int i, j, k;
@@ -262,7 +357,7 @@ __device__ __forceinline__ void phi_body(const RunK<T>& r, long bx, long step)
     for (int c = 0; c < 3; c++) {
         e[c] = actE0<D>(c) ? centre_E<D>(r, r.E0[sn][c], c, i, j, k, id) : T(0);
         T bo = centre_B<D, 0>(r, r.B0[so], c, i, j, k, id);
-        T bn = centre_B<D, 0>(r, r.B0[sn], c, i, j, k, id);
+        T bn = RECOMPUTE ? centre_B0new<D, T>(r, so, sn, c, i, j, k) : centre_B<D, 0>(r, r.B0[sn], c, i, j, k, id);
         b[c] = r.half * (bo + bn) + bext_at(r, c, i);
     }
     T sax = r.gax * (e[0] * b[0] + e[1] * b[1] + e[2] * b[2]);
@@ -527,6 +622,20 @@ __global__ void __launch_bounds__(256) k_diag_final(const RunK<T> *__restrict__ 
     diag_final_body<T>(*rp, step, slot);
 }
 
+// merged phases of the semi-fused step (E0 with C; B with the axion)
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_e0c(const RunK<T> *__restrict__ rp, long step)
+{
+    e0c_body<D, T>(*rp, blockIdx.x, step);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_bphi(const RunK<T> *__restrict__ rp, long step)
+{
+    b_body<D, T>(*rp, blockIdx.x, step);
+    phi_body<D, T, true>(*rp, blockIdx.x, step);
+}
+
 // ---------------------------------------------------------- batched kernels
 //
 // One launch advances one phase of every active run of a batch group; block b
@@ -676,6 +785,18 @@ void Plain<D, T>::diag(const RunK<T> *rk, const RunK<T>& h, long step, int slot,
 {
     hipLaunchKernelGGL((k_diag<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
     hipLaunchKernelGGL((k_diag_final<T>), dim3(1), dim3(256), 0, st, rk, step, slot);
+}
+
+template <int D, typename T>
+void Plain<D, T>::e0c(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_e0c<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
+}
+
+template <int D, typename T>
+void Plain<D, T>::bphi(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_bphi<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
 }
 
 template <int D, typename T>

@@ -128,19 +128,21 @@ def test_2d_fused_rows_multiple_of_chunk_match_oracle(axf, ny):
     check_fields(run, ora, 1e-10, "2d fused ny=%d" % ny)
 
 
-def test_3d_fused_planes_multiple_of_chunk_match_oracle(axf):
-    """The same for the 3D marching kernel along z (n_z = 128, one chunk of 128
-    and a last chunk of the nodal top plane)."""
+def test_3d_fused_planes_multiple_of_chunk_match_oracle(axf, monkeypatch):
+    """The same for the 3D LDS-marching kernel along z (n_z = 128, one chunk of
+    128 and a last chunk of the nodal top plane)."""
+    monkeypatch.setenv("AXF_LDS_MARCH", "1")
     cfg = small_3d(n=(14, 12, 128))
     cfg.update(path=axf.PATH_FUSED, z_c=64 * cfg["dx"][0], pk_z0=100 * cfg["dx"][0])
     run, ora = run_both(axf, cfg, axf.F64, 90)
     check_fields(run, ora, 1e-10, "3d fused nz=128")
 
 
-def test_3d_fp64_matches_oracle(axf):
-    cfg = small_3d()
+@pytest.mark.parametrize("path", ["plain", "fused"])
+def test_3d_fp64_matches_oracle(axf, path):
+    cfg = dict(small_3d(), path=axf.PATH_PLAIN if path == "plain" else axf.PATH_FUSED)
     run, ora = run_both(axf, cfg, axf.F64, cfg["steps"])
-    check_fields(run, ora, 1e-10, "3d")
+    check_fields(run, ora, 1e-10, "3d " + path)
     check_energies(run.diag_now(), ora, 1e-10)
 
 
@@ -193,15 +195,20 @@ def wide_2d(ax_bc, n=(300, 170)):
     return cfg
 
 
-@pytest.mark.parametrize("kind", ["2d_out", "2d_pml", "2d_ref", "2d_wide_pml", "2d_wide_out", "3d"])
+@pytest.mark.parametrize("kind", ["2d_out", "2d_pml", "2d_ref", "2d_wide_pml", "2d_wide_out", "2d_lds", "3d",
+                                  "3d_lds"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_fused_equals_plain_bitwise(axf, kind, prec):
-    """The fused one-pass kernels evaluate the same point formulas in the same
-    order as the unfused kernels (no FP contraction), so the states agree bit
-    for bit, boundaries included; the wide grids run both the interior and the
-    boundary-frame wavefront kernels."""
+def test_fused_equals_plain_bitwise(axf, kind, prec, monkeypatch):
+    """The fused paths evaluate the same point formulas in the same order as
+    the unfused kernels (no FP contraction), so the states agree bit for bit,
+    boundaries included: the 2D wavefront kernels (the wide grids run both the
+    interior and the boundary-frame kernels), the 3D semi-fused launches, and
+    the LDS-marching kernels (2d_lds, 3d_lds)."""
+    if kind.endswith("_lds"):
+        monkeypatch.setenv("AXF_LDS_MARCH", "1")
     cfg = {"2d_out": small_2d(W.AX_OUTFLOW), "2d_pml": small_2d(W.AX_PML), "2d_ref": small_2d(W.AX_REFLECT),
-           "2d_wide_pml": wide_2d(W.AX_PML), "2d_wide_out": wide_2d(W.AX_OUTFLOW), "3d": small_3d()}[kind]
+           "2d_wide_pml": wide_2d(W.AX_PML), "2d_wide_out": wide_2d(W.AX_OUTFLOW), "2d_lds": small_2d(W.AX_PML),
+           "3d": small_3d(), "3d_lds": small_3d()}[kind]
     p = axf.F32 if prec == "f32" else axf.F64
     runs = []
     for path in (axf.PATH_PLAIN, axf.PATH_FUSED):
