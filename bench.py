@@ -47,7 +47,7 @@ KERNEL_SOURCES = ["paper_2406_16796_amd/csrc/axf_fused.hip", "paper_2406_16796_a
 # one step's launches)
 WORKLOADS = {
     "2d": ("gaussian_2d", "k_wave2d", ["k_wave2d_int<", "k_wave2d<"]),
-    "3d": ("focused_3d", "plain_step", ["k_e0<", "k_c<", "k_e1<", "k_mur<", "k_b<", "k_phi<"]),
+    "3d": ("focused_3d", "semi_step", ["k_e0c<", "k_e1<", "k_mur<", "k_b<", "k_phi<"]),
     "1d": ("plane_wave_1d", "plain_step", ["k_e0<", "k_c<", "k_e1<", "k_mur<", "k_b<", "k_phi<"]),
 }
 
@@ -161,6 +161,24 @@ def cpu_baseline(cfg, target_s=15.0):
     return {"value": nc * steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
             "sample": "%s cells of the same workload (FP64, same boundaries and sources), %d whole steps in %.1f s"
                       % ("x".join(map(str, n)), steps, dt)}
+
+
+def leg_3d(axf, torch, steps=10):
+    """The 512^3 focused-pulse run (FP32): the fused path (E0 and the axion
+    current merged, then E1, Mur, B, axion) against the unfused phases, with
+    its HBM roofline (27 words per cell-update)."""
+    cfg = workload("3d")
+    nc = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
+    out = {"workload": workload_tag(cfg, "f32")}
+    for name, path in (("fused", axf.PATH_AUTO), ("plain", axf.PATH_PLAIN)):
+        _, ms, _, _, fused = time_path(axf, torch, cfg, axf.F32, path, steps, 2, 0)
+        step_s = ms / 1e3 / steps
+        out[name] = {"Gcell_s": round(nc / step_s / 1e9, 3), "ms_per_step": round(step_s * 1e3, 4)}
+        if name == "fused":
+            achieved = words_per_cell(3) * 4 * nc / step_s / 1e9
+            out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(achieved / HBM_PEAK_GBS, 4), "path_fused": fused}
+    return out
 
 
 def scan_leg(axf, torch, steps_scale, count=512, tune=True):
@@ -405,6 +423,7 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV")
     ap.add_argument("--no-scan", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shapes")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--steps-scale", type=float, default=0.1,
@@ -502,6 +521,8 @@ def main():
                   "fused_speedup": round(value / plain_value, 3) if plain_value > 0 else None},
         "diag": {"step": rec["step"], "p_gen": rec["p_gen"], "p_conv": rec["p_conv"], "finite": rec["finite"]},
     }
+    if not args.no_3d and args.workload != "3d":
+        line["3d"] = leg_3d(axf, torch)
     if not args.no_scan:
         line["scan"] = scan_leg(axf, torch, args.steps_scale, tune=not args.no_tune)
     if not args.no_serve:
