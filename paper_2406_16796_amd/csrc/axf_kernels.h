@@ -22,6 +22,9 @@ struct Plain {
     // semi-fused step: E0 with the axion current, B with the axion update
     static void e0c(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
     static void bphi(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
+    // the semi-fused step's launches (E0+C, E1, Mur, B, axion) on 3D tile walks
+    // of tz planes per workgroup (0: default)
+    static void tiled_step(const RunK<T> *rk, const RunK<T>& h, long step, int tz, hipStream_t st);
     // batched launches over the first n runs of a sorted table (device `it`,
     // host copy `host` for the grid sizes) at step s of the call
     static void batch_step(const BItem *it, const BItem *host, int n, long s, hipStream_t st);

@@ -39,10 +39,8 @@ __device__ __forceinline__ bool in_cell(const RunK<T>& r, int i, int j, int k)
 
 // E0_out = E0_in + scale * dt curl B0   (scale 1: step; -1/2: backward half step)
 template <int D, typename T>
-__device__ __forceinline__ void e0_body(const RunK<T>& r, long bx, int s_in, int s_b, int s_out, T scale)
+__device__ __forceinline__ void e0_at(const RunK<T>& r, int i, int j, int k, int s_in, int s_b, int s_out, T scale)
 {
-    int i, j, k;
-    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
     long id = lin(r, i, j, k);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -52,13 +50,19 @@ __device__ __forceinline__ void e0_body(const RunK<T>& r, long bx, int s_in, int
     }
 }
 
-// C = (D_t phi) B0 - E0 x (D phi) at every centre for the integer time between
-// axion slots (a, b); E0 = mean of slots (e_m, e_p), or slot e_m alone if cotimed.
 template <int D, typename T>
-__device__ __forceinline__ void c_body(const RunK<T>& r, long bx, int pa, int pb, int e_m, int e_p, int s_b, int cotimed)
+__device__ __forceinline__ void e0_body(const RunK<T>& r, long bx, int s_in, int s_b, int s_out, T scale)
 {
     int i, j, k;
     if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
+    e0_at<D, T>(r, i, j, k, s_in, s_b, s_out, scale);
+}
+
+// C = (D_t phi) B0 - E0 x (D phi) at every centre for the integer time between
+// axion slots (a, b); E0 = mean of slots (e_m, e_p), or slot e_m alone if cotimed.
+template <int D, typename T>
+__device__ __forceinline__ void c_at(const RunK<T>& r, int i, int j, int k, int pa, int pb, int e_m, int e_p, int s_b, int cotimed)
+{
     if (!in_cell(r, i, j, k)) return;
     long id = lin(r, i, j, k);
     T e[3], b[3], gp[3] = {T(0), T(0), T(0)};
@@ -87,13 +91,19 @@ __device__ __forceinline__ void c_body(const RunK<T>& r, long bx, int pa, int pb
     r.C[2][id] = dtphi * b[2] - (e[0] * gp[1] - e[1] * gp[0]);
 }
 
-// E0 update and the axion current C in one launch: the E0^{n+1/2} values the
-// C formula needs at the next face along each axis are recomputed, not read
 template <int D, typename T>
-__device__ __forceinline__ void e0c_body(const RunK<T>& r, long bx, long step)
+__device__ __forceinline__ void c_body(const RunK<T>& r, long bx, int pa, int pb, int e_m, int e_p, int s_b, int cotimed)
 {
     int i, j, k;
     if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
+    c_at<D, T>(r, i, j, k, pa, pb, e_m, e_p, s_b, cotimed);
+}
+
+// E0 update and the axion current C in one launch: the E0^{n+1/2} values the
+// C formula needs at the next face along each axis are recomputed, not read
+template <int D, typename T>
+__device__ __forceinline__ void e0c_at(const RunK<T>& r, int i, int j, int k, long step)
+{
     const long id = lin(r, i, j, k);
     const int so = (int)(step & 1), sn = so ^ 1, la = (int)(step % 3), lb = (int)((step + 1) % 3);
 #pragma unroll
@@ -135,6 +145,14 @@ __device__ __forceinline__ void e0c_body(const RunK<T>& r, long bx, long step)
     r.C[2][id] = dtphi * b[2] - (e[0] * gp[1] - e[1] * gp[0]);
 }
 
+template <int D, typename T>
+__device__ __forceinline__ void e0c_body(const RunK<T>& r, long bx, long step)
+{
+    int i, j, k;
+    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
+    e0c_at<D, T>(r, i, j, k, step);
+}
+
 // axion current on the E_c face: mean of C_c at the two adjacent centres (one
 // interior centre on a Mur face, wrap on a periodic axis)
 template <int D, typename T>
@@ -155,10 +173,8 @@ __device__ __forceinline__ T face_S(const RunK<T>& r, int c, int i, int j, int k
 
 // E1_out = E1_in + scale * dt (curl B1 - g1 S)
 template <int D, typename T>
-__device__ __forceinline__ void e1_body(const RunK<T>& r, long bx, int s_in, int s_b, int s_out, T scale)
+__device__ __forceinline__ void e1_at(const RunK<T>& r, int i, int j, int k, int s_in, int s_b, int s_out, T scale)
 {
-    int i, j, k;
-    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
     long id = lin(r, i, j, k);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -166,6 +182,14 @@ __device__ __forceinline__ void e1_body(const RunK<T>& r, long bx, int s_in, int
         T rhs = curl_B<D, 1>(r, r.B1[s_b], c, i, j, k, id) - r.cg1 * face_S<D>(r, c, i, j, k, id);
         r.E1[s_out][c][id] = r.E1[s_in][c][id] + scale * rhs;
     }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void e1_body(const RunK<T>& r, long bx, int s_in, int s_b, int s_out, T scale)
+{
+    int i, j, k;
+    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
+    e1_at<D, T>(r, i, j, k, s_in, s_b, s_out, scale);
 }
 
 // First-order Mur for the tangential E ghost half a cell outside a Mur face, on
@@ -277,10 +301,8 @@ __global__ void k_mur_init(const RunK<T> *__restrict__ rp)
 
 // B^{n+1} = B^n - dt curl E^{n+1/2}, both orders, old slot -> new slot
 template <int D, typename T>
-__device__ __forceinline__ void b_body(const RunK<T>& r, long bx, long step)
+__device__ __forceinline__ void b_at(const RunK<T>& r, int i, int j, int k, long step)
 {
-    int i, j, k;
-    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
     long id = lin(r, i, j, k);
     const int so = (int)(step & 1), sn = so ^ 1;
 #pragma unroll
@@ -291,6 +313,14 @@ __device__ __forceinline__ void b_body(const RunK<T>& r, long bx, long step)
         if (actB1<D>(c))
             r.B1[sn][c][id] = r.B1[so][c][id] - curl_E<D, 1>(r, sn, sn, c, i, j, k);
     }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void b_body(const RunK<T>& r, long bx, long step)
+{
+    int i, j, k;
+    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
+    b_at<D, T>(r, i, j, k, step);
 }
 
 // phi^{n+3/2}: leapfrog of the Klein-Gordon equation with source g E0.B0 at
@@ -344,10 +374,8 @@ __device__ __forceinline__ T centre_B0new(const RunK<T>& r, int so, int sn, int 
 // RECOMPUTE: B0^{n+1} at the four edges around the centre is recomputed
 // instead of read (the axion update then runs in the same launch as B)
 template <int D, typename T, bool RECOMPUTE = false>
-__device__ __forceinline__ void phi_body(const RunK<T>& r, long bx, long step)
+__device__ __forceinline__ void phi_at(const RunK<T>& r, int i, int j, int k, long step)
 {
-    int i, j, k;
-    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
     if (!in_cell(r, i, j, k)) return;
     long id = lin(r, i, j, k);
     const int so = (int)(step & 1), sn = so ^ 1;
@@ -393,6 +421,14 @@ __device__ __forceinline__ void phi_body(const RunK<T>& r, long bx, long step)
             r.axg[d][side][ln][f] = g;
         }
     }
+}
+
+template <int D, typename T, bool RECOMPUTE = false>
+__device__ __forceinline__ void phi_body(const RunK<T>& r, long bx, long step)
+{
+    int i, j, k;
+    if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
+    phi_at<D, T, RECOMPUTE>(r, i, j, k, step);
 }
 
 // initial axion levels at t = -dt/2 (slot 0) and +dt/2 (slot 1) from the packet,
@@ -636,6 +672,33 @@ __global__ void __launch_bounds__(256) k_bphi(const RunK<T> *__restrict__ rp, lo
     phi_body<D, T, true>(*rp, blockIdx.x, step);
 }
 
+// ------------------------------------------------------ 3D tiled launches
+//
+// The same point formulas on a tile walk: a workgroup of 64 x 4 threads owns a
+// 64 x 4 column tile and walks kTZ consecutive z planes, so the y and z
+// neighbours a point reads were just read by its own workgroup (cache hits)
+// instead of by a workgroup far away in the launch order.
+
+constexpr int kTX = 64, kTY = 4, kTZ = 4;
+enum TilePhase { kTE0C = 0, kTE1, kTB, kTPhi };
+
+template <int D, typename T, int PH>
+__global__ void __launch_bounds__(256) k3_tile(const RunK<T> *__restrict__ rp, long step, int tz)
+{
+    const RunK<T>& r = *rp;
+    const int i = blockIdx.x * kTX + (threadIdx.x & (kTX - 1));
+    const int j = blockIdx.y * kTY + (threadIdx.x / kTX);
+    if (i >= r.nn[0] || j >= r.nn[1]) return;
+    const int so = (int)(step & 1), sn = so ^ 1;
+    const int k0 = blockIdx.z * tz, k1 = min(k0 + tz, r.nn[2]);
+    for (int k = k0; k < k1; k++) {
+        if (PH == kTE0C) e0c_at<D, T>(r, i, j, k, step);
+        else if (PH == kTE1) e1_at<D, T>(r, i, j, k, so, so, sn, T(1));
+        else if (PH == kTB) b_at<D, T>(r, i, j, k, step);
+        else phi_at<D, T>(r, i, j, k, step);
+    }
+}
+
 // ---------------------------------------------------------- batched kernels
 //
 // One launch advances one phase of every active run of a batch group; block b
@@ -797,6 +860,19 @@ template <int D, typename T>
 void Plain<D, T>::bphi(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st)
 {
     hipLaunchKernelGGL((k_bphi<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
+}
+
+template <int D, typename T>
+void Plain<D, T>::tiled_step(const RunK<T> *rk, const RunK<T>& h, long step, int tz, hipStream_t st)
+{
+    if (tz <= 0) tz = kTZ;
+    const dim3 grid((unsigned)((h.nn[0] + kTX - 1) / kTX), (unsigned)((h.nn[1] + kTY - 1) / kTY),
+                    (unsigned)((h.nn[2] + tz - 1) / tz));
+    hipLaunchKernelGGL((k3_tile<D, T, kTE0C>), grid, dim3(256), 0, st, rk, step, tz);
+    hipLaunchKernelGGL((k3_tile<D, T, kTE1>), grid, dim3(256), 0, st, rk, step, tz);
+    mur(rk, h, step, st);
+    hipLaunchKernelGGL((k3_tile<D, T, kTB>), grid, dim3(256), 0, st, rk, step, tz);
+    hipLaunchKernelGGL((k3_tile<D, T, kTPhi>), grid, dim3(256), 0, st, rk, step, tz);
 }
 
 template <int D, typename T>

@@ -353,15 +353,21 @@ static void steps_semi(Run *R, int64_t nsteps)
     const RunK<T>& h = R->hk<T>();
     const RunK<T> *rk = R->rk<T>();
     hipStream_t st = R->stream;
+    const char *te = getenv("AXF_TILED");         // 0: one thread per point instead of tile walks
+    const bool tiled = D == 3 && !(te && te[0] == '0');
     for (int64_t it = 0; it < nsteps; it++) {
         long s = R->step;
         int so = (int)(s & 1), sn = so ^ 1;
         ensure_incident<D, T>(R, s);
-        P::e0c(rk, h, s, st);
-        P::e1(rk, h, so, so, sn, T(1), st);
-        P::mur(rk, h, s, st);
-        P::b(rk, h, s, st);
-        P::phi(rk, h, s, st);
+        if (tiled) {
+            P::tiled_step(rk, h, s, R->chunk, st);
+        } else {
+            P::e0c(rk, h, s, st);
+            P::e1(rk, h, so, so, sn, T(1), st);
+            P::mur(rk, h, s, st);
+            P::b(rk, h, s, st);
+            P::phi(rk, h, s, st);
+        }
         if (R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0) {
             P::diag(rk, h, s, R->rec_written % h.rec_cap, st);
             R->rec_written++;
