@@ -40,16 +40,31 @@ HBM_PEAK_GBS = 8000.0
 # built-in (rows per march, prefetch distance) of the 2D wavefront step
 DEFAULT_WAVE_SHAPE = {"f32": (8, 3), "f64": (8, 2)}
 COPY_BYTES = 1 << 30
-KERNEL_SOURCES = ["paper_2406_16796_amd/csrc/axf_fused.hip", "paper_2406_16796_amd/csrc/axf_fused.h",
-                  "paper_2406_16796_amd/csrc/axf_stencil.h", "paper_2406_16796_amd/csrc/axf_internal.h",
-                  "paper_2406_16796_amd/build.py"]
+CSRC = "paper_2406_16796_amd/csrc/"
+COMMON_SOURCES = [CSRC + "axf_stencil.h", CSRC + "axf_internal.h", "paper_2406_16796_amd/build.py"]
 # workload -> (generator, file tag of the step kernels, kernel-name patterns of
-# one step's launches)
+# one step's launches ({T} = float or double), sources those kernels are built
+# from)
 WORKLOADS = {
-    "2d": ("gaussian_2d", "k_wave2d", ["k_wave2d_int<", "k_wave2d<"]),
-    "3d": ("focused_3d", "semi_step", ["k_e0c<", "k_e1<", "k_mur<", "k_b<", "k_phi<"]),
-    "1d": ("plane_wave_1d", "plain_step", ["k_e0<", "k_c<", "k_e1<", "k_mur<", "k_b<", "k_phi<"]),
+    "2d": ("gaussian_2d", "k_wave2d", ["k_wave2d_int<{T}", "k_wave2d<{T}"],
+           [CSRC + "axf_fused.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
+    "3d": ("focused_3d", "k3_tile", ["k3_tile<3,{T},0>", "k3_tile<3,{T},1>", "k_mur<3,{T}>",
+                                     "k3_tile<3,{T},2>", "k3_tile<3,{T},3>"],
+           [CSRC + "axf_plain.hip", CSRC + "axf_kernels.h"] + COMMON_SOURCES),
+    "1d": ("plane_wave_1d", "plain_step", ["k_e0<1,{T}>", "k_c<1,{T}>", "k_e1<1,{T}>", "k_mur<1,{T}>",
+                                           "k_b<1,{T}>", "k_phi<1,{T}>"],
+           [CSRC + "axf_plain.hip", CSRC + "axf_kernels.h"] + COMMON_SOURCES),
 }
+
+
+def pattern_label(p):
+    return p if p.endswith(">") else p + ",...>"
+
+
+def step_patterns(name, precision):
+    """Kernel-name patterns (spaces removed) of one step's launches."""
+    t = "float" if precision == "f32" else "double"
+    return [p.replace("{T}", t) for p in WORKLOADS[name][2]]
 
 
 def words_per_cell(ndim):
@@ -69,9 +84,9 @@ def workload_tag(cfg, precision):
     return "%s_%s_%s" % (cfg["name"], "x".join(map(str, n)), precision)
 
 
-def kernel_source_hash():
+def kernel_source_hash(name):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in WORKLOADS[name][3]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -81,7 +96,7 @@ def traffic_file(tag, kernel):
     return os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.md" % (kernel, tag))
 
 
-def read_traffic(tag, kernel):
+def read_traffic(name, tag, kernel):
     """HBM bytes per launch from the committed counter summary, or None when
     it is missing or was taken on another version of the kernel source."""
     path = traffic_file(tag, kernel)
@@ -93,7 +108,7 @@ def read_traffic(tag, kernel):
             if line.startswith("- `") and "=" in line:
                 k, v = line[3:].split("`", 1)[0].split("=", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
+    if vals.get("kernel_source_sha256") != kernel_source_hash(name):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -318,7 +333,7 @@ def pmc_summary(args):
     readings of the device copy of known size, write the summary file."""
     cfg = workload(args.workload)
     tag = workload_tag(cfg, args.precision)
-    kernel, pats = WORKLOADS[args.workload][1], WORKLOADS[args.workload][2]
+    kernel, pats = WORKLOADS[args.workload][1], step_patterns(args.workload, args.precision)
     res = {}
     for counter, path in (("FETCH_SIZE", args.pmc_summary[0]), ("WRITE_SIZE", args.pmc_summary[1])):
         rows = pmc_rows(path)
@@ -356,7 +371,7 @@ def pmc_summary(args):
              "<fetch counter_collection.csv> <write counter_collection.csv>"
              % (args.workload, args.precision, args.steps), "",
              "| counter | copy kernel KiB | scale (bytes per KiB read) | %s KiB per step (mean of %d) | bytes per step |"
-             % (" + ".join(p.rstrip("<") for p in pats), res["FETCH_SIZE"][3]),
+             % (" + ".join(pattern_label(p) for p in pats), res["FETCH_SIZE"][3]),
              "|---|---|---|---|---|"]
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
         kc, fac, ks, _, b = res[counter]
@@ -366,7 +381,7 @@ def pmc_summary(args):
               % (words_per_cell(ndim), esize, nc, algo, traffic / algo), "",
               "- `traffic_bytes_per_launch = %.6g`" % traffic,
               "- `algorithmic_bytes_per_launch = %d`" % algo,
-              "- `kernel_source_sha256 = %s`" % kernel_source_hash(), ""]
+              "- `kernel_source_sha256 = %s`" % kernel_source_hash(args.workload), ""]
     path = traffic_file(tag, kernel)
     with open(path, "w") as f:
         f.write("\n".join(lines))
@@ -377,15 +392,17 @@ def trace_summary(args):
     """Per-kernel call count and mean duration from a rocprofv3 kernel_stats CSV."""
     cfg = workload(args.workload)
     tag = workload_tag(cfg, args.precision)
-    kernel, pats = WORKLOADS[args.workload][1], WORKLOADS[args.workload][2]
+    kernel, pats = WORKLOADS[args.workload][1], step_patterns(args.workload, args.precision)
     rows = list(csv.DictReader(open(args.trace_summary)))
-    cmd = ("python3 $REPO/bench.py --workload %s --precision %s --steps %d --no-cpu-baseline"
-           % (args.workload, args.precision, args.steps))
+    cmd = ("python3 $REPO/bench.py --workload %s --precision %s --steps %d --warmup %d --plain-steps %d "
+           "--no-cpu-baseline --no-scan --no-serve --no-3d --no-tune"
+           % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps))
     lines = ["# Kernel trace of bench.py, workload %s" % tag, "",
              "    cd /tmp && export TMPDIR=/tmp",
              "    timeout -k 10 300 rocprofv3 --kernel-trace --stats -d $OUT/kt -o kt --output-format csv -- " + cmd,
-             "    python3 $REPO/bench.py --workload %s --precision %s --trace-summary $OUT/kt/kt_kernel_stats.csv"
-             % (args.workload, args.precision), "",
+             "    python3 $REPO/bench.py --workload %s --precision %s --steps %d --warmup %d --plain-steps %d "
+             "--trace-summary $OUT/kt/kt_kernel_stats.csv"
+             % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps), "",
              "The run times the fused path twice (with and without diagnostics) and the unfused phase "
              "sequence once; the copy kernel is the bandwidth calibration.", "",
              "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
@@ -401,8 +418,8 @@ def trace_summary(args):
     for pat in pats:
         dom = [r for r in rows if pat in r["Name"].replace(" ", "")]
         if dom:
-            lines.append("- `%s_mean_us = %.2f`" % (pat.rstrip("<"), float(dom[0]["AverageNs"]) / 1e3))
-    lines.append("- `kernel_source_sha256 = %s`" % kernel_source_hash())
+            lines.append("- `%s_mean_us = %.2f`" % (pattern_label(pat), float(dom[0]["AverageNs"]) / 1e3))
+    lines.append("- `kernel_source_sha256 = %s`" % kernel_source_hash(args.workload))
     path = os.path.join(ROOT, "profiles", "%s_%s_kernel_trace.md" % (kernel, tag))
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -453,7 +470,7 @@ def main():
     ndim = sum(1 for v in cfg["n"] if v > 1)
     nc = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
     tag = workload_tag(cfg, args.precision)
-    kernel, pats = WORKLOADS[args.workload][1], WORKLOADS[args.workload][2]
+    kernel, pats = WORKLOADS[args.workload][1], step_patterns(args.workload, args.precision)
 
     copy_gbs = device_copy(torch)
     tuned = None
@@ -479,7 +496,7 @@ def main():
     # the counter summary was taken with the built-in launch shape
     default_shape = DEFAULT_WAVE_SHAPE[args.precision]
     same_shape = tuned is None or (tuned["chunk"], tuned["prefetch"]) == default_shape
-    traffic = read_traffic(tag, kernel) if fused and same_shape else None
+    traffic = read_traffic(args.workload, tag, kernel) if fused and same_shape else None
     # the unfused phase sequence for comparison
     p_wall, _, p_launches, _, _ = time_path(axf, torch, cfg, prec, axf.PATH_PLAIN, args.plain_steps, 2, 0)
     plain_value = nc * args.plain_steps / p_wall / 1e9
@@ -506,7 +523,7 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": round(traffic) if traffic is not None else None,
-            "kernel": " + ".join(p.rstrip("<") for p in pats) if fused else "plain phase sequence",
+            "kernel": " + ".join(pattern_label(p) for p in pats) if fused else "plain phase sequence",
             "unit_of_work": "one fused step of the whole grid", "bytes_per_step": algo_bytes,
             "mean_step_ms": round(per_launch_s * 1e3, 5), "steps_timed": args.steps,
             "copy_kernel_GBs": round(copy_gbs, 1),

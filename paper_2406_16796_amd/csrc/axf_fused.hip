@@ -388,9 +388,7 @@ k_fused(const RunK<T> *__restrict__ rp, long step, int ntx, int nty, int nch, in
 
     // XCD-aware tile order: consecutive workgroups land on different XCDs, so
     // hand each XCD a contiguous run of tiles (neighbours share its L2)
-    const int nb = ntx * nty * nch;
-    const int bid = blockIdx.x, xcd = bid & 7, kq = bid >> 3, q8 = nb >> 3, rem = nb & 7;
-    const int L = xcd * q8 + (xcd < rem ? xcd : rem) + kq;
+    const int L = (int)xcd_band(blockIdx.x, (long)ntx * nty * nch);
     const int tx = L % ntx, ty = (L / ntx) % nty, ch = L / (ntx * nty);
 
     const int so = (int)(step & 1), sn = so ^ 1;
@@ -1259,7 +1257,7 @@ __device__ __forceinline__ void wave2d_edge_item(const WaveSplit& w, long e, int
 template <typename T, int PD>
 __global__ void __launch_bounds__(256) k_wave2d_int(const RunK<T> *__restrict__ rp, long step, WaveSplit w, int chunk)
 {
-    const long gw = blockIdx.x * 4L + wave_in_block();
+    const long gw = xcd_band(blockIdx.x, gridDim.x) * 4L + wave_in_block();
     if (gw >= w.interior()) return;       // whole wavefronts only: no barriers in this kernel
     const int ni = w.sx1 - w.sx0;
     wave2d_body<T, true, PD>(rp, step, w.sx0 + (int)(gw % ni), w.cy0 + (int)(gw / ni), w.nch, chunk);
@@ -1280,11 +1278,12 @@ template <typename T, bool INTERIOR>
 __global__ void __launch_bounds__(256, INTERIOR ? 1 : 3) kb_wave2d(const BItem *__restrict__ it, int n, long s)
 {
     constexpr int K = INTERIOR ? kWaveI : kWave;
-    const int i = find_item<K>(it, n, blockIdx.x);
+    const long b = INTERIOR ? xcd_band(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+    const int i = find_item<K>(it, n, b);
     const RunK<T> *rp = uniform_desc<RunK<T>>(it[i].rk);
     const int chunk = it[i].chunk;
     const WaveSplit w = wave2d_split(*rp, chunk);
-    const long gw = (blockIdx.x - it[i].blk[K]) * 4L + wave_in_block();
+    const long gw = (b - it[i].blk[K]) * 4L + wave_in_block();
     if (INTERIOR) {
         if (gw >= w.interior()) return;
         const int ni = w.sx1 - w.sx0;

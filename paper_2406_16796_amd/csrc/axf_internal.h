@@ -112,6 +112,17 @@ __device__ __forceinline__ const R *uniform_desc(const void *p)
     return (const R *)(const __attribute__((address_space(1))) R *)(((unsigned long long)hi << 32) | lo);
 }
 
+// Workgroups of a launch are dealt to the 8 XCDs in turn, each XCD with its
+// own L2.  xcd_band renumbers block b of nb so that each XCD takes one
+// contiguous band of the launch order: tiles that share rows or planes with
+// their neighbours then meet in the same L2.  A bijection on [0, nb).
+__device__ __forceinline__ long xcd_band(long b, long nb)
+{
+    const long per = (nb + 7) / 8, full = nb % 8 == 0 ? 8 : nb % 8;
+    const long x = b % 8, q = b / 8;
+    return x < full ? x * per + q : full * per + (x - full) * (per - 1) + q;
+}
+
 // index of the run owning block b of a launch of kind K (largest i with blk[K] <= b)
 template <int K>
 __device__ __forceinline__ int find_item(const BItem *it, int n, long b)
