@@ -391,8 +391,8 @@ k_fused(const RunK<T> *__restrict__ rp, long step, int ntx, int nty, int nch, in
     const int L = (int)xcd_band(blockIdx.x, (long)ntx * nty * nch);
     const int tx = L % ntx, ty = (L / ntx) % nty, ch = L / (ntx * nty);
 
-    const int so = (int)(step & 1), sn = so ^ 1;
-    const int la = (int)(step % 3), lb = (int)((step + 1) % 3), ln = (int)((step + 2) % 3);
+    const int so = em_slot(step), sn = em_slot(step + 1);
+    const int la = phi_slot(step), lb = phi_slot(step + 1), ln = phi_slot(step + 2);
 
     // in-plane tile and ownership ranges (the last tile also owns the nodal plane n)
     const int x0 = tx * TX, y0 = ty * TY;
@@ -801,7 +801,7 @@ __device__ __forceinline__ void sto(T *base, unsigned boff, T v)
 template <typename T>
 struct KW {
     const char *sb;
-    unsigned as;            // array stride in bytes (27 arrays span < 4 GiB: checked on the host)
+    unsigned as;            // array stride in bytes (12 arrays span < 4 GiB: checked on the host)
     int n[2], nn[2], mur[2], axbc[2];
     int sx;
     T cdt[2], half, inv_dt, inv2dx[2], inv_dx2[2], dt2, m2, gax, cg1;
@@ -850,8 +850,8 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
 {
     KW<T> r = make_kw(rp);
     const int lane = threadIdx.x & 63;
-    const int so = (int)(step & 1), sn = so ^ 1;
-    const int la = (int)(step % 3), lb = (int)((step + 1) % 3), ln = (int)((step + 2) % 3);
+    const int so = em_slot(step), sn = em_slot(step + 1);
+    const int la = phi_slot(step), lb = phi_slot(step + 1), ln = phi_slot(step + 2);
 
     const int x0 = seg * kWaveOut, gx = x0 - 3 + lane;
     const int own_x_hi = min(x0 + kWaveOut, r.nn[0]);
@@ -877,13 +877,23 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
     auto vy_nod = [&](int p) __attribute__((always_inline)) { return !my || (p >= 0 && p < nn1); };
     auto vy_cen = [&](int p) __attribute__((always_inline)) { return !my || (p >= 0 && p < n1); };
     auto own_plane = [&](int p) __attribute__((always_inline)) { return p >= c0 && p < c1; };
-    // every field array is addressed from the one state base with a 32-bit
-    // byte offset q * as + (row, column); the stride is re-read each iteration
+    // every field array is addressed from one of three wave-uniform bases (the
+    // EM slot read, the EM slot written, the axion levels) with a 32-bit byte
+    // offset index * as + (row, column); the stride is re-read each iteration
     // (opaque to the compiler) so that the per-array products stay in the loop
     // instead of occupying 22 scalar register pairs for the whole march
     unsigned as_l = r.as;
-    auto ldq = [&](int q, unsigned o) __attribute__((always_inline)) -> T { return ldo((const T *)r.sb, (unsigned)q * as_l + o); };
-    auto stq = [&](int q, unsigned o, T v) __attribute__((always_inline)) { sto((T *)r.sb, (unsigned)q * as_l + o, v); };
+    const char *const b_rd = r.sb + (size_t)q_em(0, so, 0) * r.as;
+    const char *const b_wr = r.sb + (size_t)q_em(0, sn, 0) * r.as;
+    const char *const b_ph = r.sb + (size_t)q_phi(0) * r.as;
+    auto lde = [&](int kind, int c, unsigned o) __attribute__((always_inline)) -> T {
+        return ldo((const T *)b_rd, (unsigned)(kind * 3 + c) * as_l + o);
+    };
+    auto ste = [&](int kind, int c, unsigned o, T v) __attribute__((always_inline)) {
+        sto((T *)b_wr, (unsigned)(kind * 3 + c) * as_l + o, v);
+    };
+    auto ldp = [&](int L, unsigned o) __attribute__((always_inline)) -> T { return ldo((const T *)b_ph, (unsigned)L * as_l + o); };
+    auto stp = [&](int L, unsigned o, T v) __attribute__((always_inline)) { sto((T *)b_ph, (unsigned)L * as_l + o, v); };
     auto off = [&](int p) __attribute__((always_inline)) -> unsigned {
         const int row = my ? ((p >= 0 && p < nn1) ? p : 0) : wrap1(p, n1);
         return bx + (unsigned)row * sxb;
@@ -910,7 +920,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
         if (ys >= 0) return ldo((const T *)face_of(rp, q_axg(1, ys, L)), bxp);   // the y ghost row (uniform)
         const int row = axpy ? wrap1(p, n1) : ((p >= 0 && p < n1) ? p : 0);
         if (xgs >= 0) return ldo((const T *)face_of(rp, q_axg(0, xgs, L)), (unsigned)row * es);   // x ghost lanes
-        return ldq(q_phi(L), bxp + (unsigned)row * sxb);
+        return ldp(L, bxp + (unsigned)row * sxb);
     };
     // Rows below the chunk feed the owned rows only through: B0z from row c0-2,
     // phi from c0-3, E0 from c0-2, B1 from c0-1, E1 from c0-1 (the first owned
@@ -918,15 +928,15 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
     // with C, phi one row below that).  Older rows of a field are not loaded.
     auto prefetch = [&](int t, Pref& P) __attribute__((always_inline)) {
         const unsigned o0 = off(t), o1 = off(t - 1), o2 = off(t - 2);
-        P.b0z = ldq(q_em(1, so, 2), o0);
+        P.b0z = lde(1, 2, o0);
 #pragma unroll
-        for (int c = 0; c < 3; c++) P.b1[c] = t - 1 >= c0 - 1 ? ldq(q_em(3, so, c), o1) : T(0);
+        for (int c = 0; c < 3; c++) P.b1[c] = t - 1 >= c0 - 1 ? lde(3, c, o1) : T(0);
         P.pa = load_phi(la, t - 1);
         P.pb = load_phi(lb, t - 1);
 #pragma unroll
-        for (int c = 0; c < 2; c++) P.e0m[c] = t - 1 >= c0 - 2 ? ldq(q_em(0, so, c), o1) : T(0);
+        for (int c = 0; c < 2; c++) P.e0m[c] = t - 1 >= c0 - 2 ? lde(0, c, o1) : T(0);
 #pragma unroll
-        for (int c = 0; c < 3; c++) P.e1m[c] = t - 2 >= c0 - 1 ? ldq(q_em(2, so, c), o2) : T(0);
+        for (int c = 0; c < 3; c++) P.e1m[c] = t - 2 >= c0 - 1 ? lde(2, c, o2) : T(0);
         P.yn0 = vy_nod(t);
         P.yn1 = vy_nod(t - 1);
         P.yc1 = vy_cen(t - 1);
@@ -1014,8 +1024,8 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
             e0h_1[0] = eh[0]; e0h_1[1] = eh[1];
             e0n_1[0] = en[0]; e0n_1[1] = en[1];
             const bool own = own_x && own_plane(p1);
-            if (own && vx_nod && vy_cen(p1)) stq(q_em(0, sn, 0), o1, eh[0]);
-            if (own && vx_cen && vy_nod(p1)) stq(q_em(0, sn, 1), o1, eh[1]);
+            if (own && vx_nod && vy_cen(p1)) ste(0, 0, o1, eh[0]);
+            if (own && vx_cen && vy_nod(p1)) ste(0, 1, o1, eh[1]);
             // Mur ghosts of E0y across x (E0y centred in x)
             const T up_e = lane_up(e0h_1[1]), dn_e = lane_dn(e0h_1[1]);
             if (mx && (gx == -1 || gx == n0) && vy_nod(p1)) {
@@ -1066,7 +1076,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
             if (vx_nod && vy_nod(p1)) {
                 T a = r.cdt[0] * (e0h_1[1] - dn_e0y), b = r.cdt[1] * (e0h_1[0] - e0h_2[0]);
                 v = b0z_1 - (a - b);
-                if (own_x && own_plane(p1)) stq(q_em(1, sn, 2), o1, v);
+                if (own_x && own_plane(p1)) ste(1, 2, o1, v);
             }
             b0p_1 = v;
         }
@@ -1084,7 +1094,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                 T a = r.cdt[1] * (b1_1[2] - b1_2[2]), b = T(0);
                 T rhs = (a - b) - r.cg1 * Sc;
                 v[0] = e1m[0] + T(1) * rhs;
-                if (own) stq(q_em(2, sn, 0), o2, v[0]);
+                if (own) ste(2, 0, o2, v[0]);
             }
             // E1y: centred x, nodal y
             if (vx_cen && vy_nod(p2)) {
@@ -1094,7 +1104,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                 T a = T(0), b = r.cdt[0] * (up_b1z - b1_2[2]);
                 T rhs = (a - b) - r.cg1 * Sc;
                 v[1] = e1m[1] + T(1) * rhs;
-                if (own) stq(q_em(2, sn, 1), o2, v[1]);
+                if (own) ste(2, 1, o2, v[1]);
             }
             // E1z: centred x, centred y
             if (vx_cen && vy_cen(p2)) {
@@ -1102,7 +1112,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                 T a = r.cdt[0] * (up_b1y - b1_2[1]), b = r.cdt[1] * (b1_1[0] - b1_2[0]);
                 T rhs = (a - b) - r.cg1 * Sc;
                 v[2] = e1m[2] + T(1) * rhs;
-                if (own) stq(q_em(2, sn, 2), o2, v[2]);
+                if (own) ste(2, 2, o2, v[2]);
             }
             e1h_2[0] = v[0]; e1h_2[1] = v[1]; e1h_2[2] = v[2];
             // Mur ghosts of E1y, E1z across x; of E1x, E1z across y
@@ -1136,17 +1146,17 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                 // B1x: centred x, nodal y
                 if (vx_cen && vy_nod(p2)) {
                     T a = r.cdt[1] * (e1h_2[2] - e1h_3[2]), b = T(0);
-                    stq(q_em(3, sn, 0), o2, b1_2[0] - (a - b));
+                    ste(3, 0, o2, b1_2[0] - (a - b));
                 }
                 // B1y: nodal x, centred y
                 if (vx_nod && vy_cen(p2)) {
                     T a = T(0), b = r.cdt[0] * (e1h_2[2] - dn_e1z);
-                    stq(q_em(3, sn, 1), o2, b1_2[1] - (a - b));
+                    ste(3, 1, o2, b1_2[1] - (a - b));
                 }
                 // B1z: nodal x, nodal y
                 if (vx_nod && vy_nod(p2)) {
                     T a = r.cdt[0] * (e1h_2[1] - dn_e1y), b = r.cdt[1] * (e1h_2[0] - e1h_3[0]);
-                    stq(q_em(3, sn, 2), o2, b1_2[2] - (a - b));
+                    ste(3, 2, o2, b1_2[2] - (a - b));
                 }
                 if (vx_cen && vy_cen(p2)) {
                     const int gi = wrap1(gx, n0), gj = my ? p2 : wrap1(p2, n1);
@@ -1170,7 +1180,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                     T num = ((x + sdt * pa) + T(2) * pb) - pa;
                     T pn = num;
                     if (sdt != T(0)) pn = num / (T(1) + sdt);
-                    stq(q_phi(ln), o2, pn);
+                    stp(ln, o2, pn);
                     const int gv[2] = {gi, gj};
 #pragma unroll
                     for (int d = 0; d < 2; d++) {

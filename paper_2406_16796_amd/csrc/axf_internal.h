@@ -29,21 +29,34 @@ template <int D> __host__ __device__ constexpr bool actB0(int c) { return D == 3
 template <int D> __host__ __device__ constexpr bool actE1(int c) { return D >= 2 ? true : c != 0; }
 template <int D> __host__ __device__ constexpr bool actB1(int c) { return D >= 2 ? true : c != 0; }
 
-// Uniform layout of a run's device buffer: 30 field arrays of equal size at
-// state_base + q * arr_stride, and 90 boundary planes of equal size at
-// face_base + q * face_stride (some unused for a given configuration).
-__host__ __device__ constexpr int q_em(int kind, int slot, int comp) { return (kind * 2 + slot) * 3 + comp; }  // kind 0 E0, 1 B0, 2 E1, 3 B1
-__host__ __device__ constexpr int q_phi(int slot) { return 24 + slot; }
-__host__ __device__ constexpr int q_c(int comp) { return 27 + comp; }
-constexpr int kNumArrays = 30;
-__host__ __device__ constexpr int q_axg(int d, int side, int slot) { return (d * 2 + side) * 3 + slot; }
-__host__ __device__ constexpr int q_mur(int o, int d, int side, int comp, int slot) { return 18 + (((o * 3 + d) * 2 + side) * 3 + comp) * 2 + slot; }
-constexpr int kNumFaces = 90;
+// Time levels rotate through slots: the E/B buffers and the Mur ghosts through
+// three (step n reads slot n mod 3, writes slot (n + 1) mod 3), the axion levels
+// and their ghosts through four (level L, the field at t = (L - 1/2) dt, in slot
+// L mod 4).  One slot more than a single step needs, so that a launch advancing
+// two steps reads its inputs while it writes both later levels elsewhere.
+constexpr int kEmSlots = 3, kPhiSlots = 4;
+__host__ __device__ constexpr int em_slot(long step) { return (int)(step % kEmSlots); }
+__host__ __device__ constexpr int phi_slot(long level) { return (int)(level % kPhiSlots); }
+
+// Uniform layout of a run's device buffer: 43 field arrays of equal size at
+// state_base + q * arr_stride (the 12 EM components of one slot together, then
+// the axion levels and the current scratch), and 132 boundary planes of equal
+// size at face_base + q * face_stride (some unused for a given configuration).
+constexpr int kEmPerSlot = 12;
+__host__ __device__ constexpr int q_em(int kind, int slot, int comp) { return slot * kEmPerSlot + kind * 3 + comp; }  // kind 0 E0, 1 B0, 2 E1, 3 B1
+__host__ __device__ constexpr int q_phi(int slot) { return kEmSlots * kEmPerSlot + slot; }
+__host__ __device__ constexpr int q_c(int comp) { return q_phi(kPhiSlots) + comp; }
+constexpr int kNumArrays = q_c(3);
+__host__ __device__ constexpr int q_axg(int d, int side, int slot) { return (d * 2 + side) * kPhiSlots + slot; }
+__host__ __device__ constexpr int q_mur(int o, int d, int side, int comp, int slot)
+{
+    return 6 * kPhiSlots + (((o * 3 + d) * 2 + side) * 3 + comp) * kEmSlots + slot;
+}
+constexpr int kNumFaces = 6 * kPhiSlots + 36 * kEmSlots;
 constexpr int kIncLevels = 17;   // time levels per laser table fill (16 steps)
 
 // Immutable per-run descriptor, stored in device memory once at creation.
-// Time-level slots rotate with the step counter: E/B buffers and Mur ghosts by
-// parity, the three axion levels (and their ghosts) modulo 3.
+// Time-level slots rotate with the step counter (em_slot, phi_slot).
 template <typename T>
 struct RunK {
     int D;
@@ -67,11 +80,11 @@ struct RunK {
     // state (uniform layout, see q_em / q_axg; the pointers below point into it)
     char *state_base, *face_base;
     long arr_stride, face_stride;
-    T *E0[2][3], *B0[2][3], *E1[2][3], *B1[2][3];
-    T *phi[3];
+    T *E0[kEmSlots][3], *B0[kEmSlots][3], *E1[kEmSlots][3], *B1[kEmSlots][3];
+    T *phi[kPhiSlots];
     T *C[3];                  // scratch: axion current at centres (plain path)
-    T *axg[3][2][3];          // axion ghosts [axis][side][slot]
-    T *murg[2][3][2][3][2];   // Mur ghosts [order][axis][side][component][slot]
+    T *axg[3][2][kPhiSlots];          // axion ghosts [axis][side][slot]
+    T *murg[2][3][2][3][kEmSlots];    // Mur ghosts [order][axis][side][component][slot]
     // incident laser field on the x_min face, tabulated per time level L
     // (t = (L - 1/2) dt) in slot L mod inc_k1: [slot][0 adjacent centre, 1 ghost][face point]
     double *inc;

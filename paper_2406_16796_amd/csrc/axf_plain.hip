@@ -105,7 +105,7 @@ template <int D, typename T>
 __device__ __forceinline__ void e0c_at(const RunK<T>& r, int i, int j, int k, long step)
 {
     const long id = lin(r, i, j, k);
-    const int so = (int)(step & 1), sn = so ^ 1, la = (int)(step % 3), lb = (int)((step + 1) % 3);
+    const int so = em_slot(step), sn = em_slot(step + 1), la = phi_slot(step), lb = phi_slot(step + 1);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         if (!actE0<D>(c) || !in_E<D>(r, c, i, j, k)) continue;
@@ -211,7 +211,7 @@ __device__ __forceinline__ void mur_point(const RunK<T>& r, long step, int d, in
         int ext = (e == c) ? r.nn[e] : r.n[e];
         if (id3[e] >= ext) return;
     }
-    const int s_old = (int)(step & 1), s_new = s_old ^ 1;
+    const int s_old = em_slot(step), s_new = em_slot(step + 1);
     long id = lin(r, id3[0], id3[1], id3[2]);
     long f = face_index(r, d, id3[0], id3[1], id3[2]);
     T *const *Eo = O == 0 ? r.E0[s_old] : r.E1[s_old];
@@ -304,7 +304,7 @@ template <int D, typename T>
 __device__ __forceinline__ void b_at(const RunK<T>& r, int i, int j, int k, long step)
 {
     long id = lin(r, i, j, k);
-    const int so = (int)(step & 1), sn = so ^ 1;
+    const int so = em_slot(step), sn = em_slot(step + 1);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         if (!in_B<D>(r, c, i, j, k)) continue;
@@ -378,8 +378,8 @@ __device__ __forceinline__ void phi_at(const RunK<T>& r, int i, int j, int k, lo
 {
     if (!in_cell(r, i, j, k)) return;
     long id = lin(r, i, j, k);
-    const int so = (int)(step & 1), sn = so ^ 1;
-    const int la = (int)(step % 3), lb = (int)((step + 1) % 3), ln = (int)((step + 2) % 3);
+    const int so = em_slot(step), sn = em_slot(step + 1);
+    const int la = phi_slot(step), lb = phi_slot(step + 1), ln = phi_slot(step + 2);
     T e[3], b[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -522,8 +522,8 @@ __device__ __forceinline__ void diag_body(const RunK<T>& r, long bx, long step)
     long p = bx * 256 + threadIdx.x;
     if (decompose(r, p, i, j, k)) {
         long id = lin(r, i, j, k);
-        const int so = (int)(step & 1), sn = so ^ 1;
-        const int la = (int)(step % 3), lb = (int)((step + 1) % 3);
+        const int so = em_slot(step), sn = em_slot(step + 1);
+        const int la = phi_slot(step), lb = phi_slot(step + 1);
         bool fin = true;
         if (in_cell(r, i, j, k)) {
             const T *A = r.phi[la], *Bp = r.phi[lb];
@@ -689,7 +689,7 @@ __global__ void __launch_bounds__(256) k3_tile(const RunK<T> *__restrict__ rp, l
     const int i = blockIdx.x * kTX + (threadIdx.x & (kTX - 1));
     const int j = blockIdx.y * kTY + (threadIdx.x / kTX);
     if (i >= r.nn[0] || j >= r.nn[1]) return;
-    const int so = (int)(step & 1), sn = so ^ 1;
+    const int so = em_slot(step), sn = em_slot(step + 1);
     const int k0 = blockIdx.z * tz, k1 = min(k0 + tz, r.nn[2]);
     for (int k = k0; k < k1; k++) {
         if (PH == kTE0C) e0c_at<D, T>(r, i, j, k, step);
@@ -712,7 +712,7 @@ template <int D, typename T, int PH>
 __device__ __forceinline__ void kb_volume_run(const RunK<T> *__restrict__ rp, long bx, long step)
 {
     const RunK<T>& r = *rp;
-    const int so = (int)(step & 1), sn = so ^ 1, la = (int)(step % 3), lb = (int)((step + 1) % 3);
+    const int so = em_slot(step), sn = em_slot(step + 1), la = phi_slot(step), lb = phi_slot(step + 1);
     if (PH == kPhE0) e0_body<D, T>(r, bx, so, so, sn, T(1));
     else if (PH == kPhC) c_body<D, T>(r, bx, la, lb, so, sn, so, 0);
     else if (PH == kPhE1) e1_body<D, T>(r, bx, so, so, sn, T(1));

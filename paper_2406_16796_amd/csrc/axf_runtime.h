@@ -17,11 +17,11 @@ struct Layout {
     size_t off_rk;               // device copy of the run descriptor
     size_t off_state;            // start of the checkpointed region
     size_t off_arrays, arr_stride, off_faces, face_stride;
-    long off_em[4][2][3];        // [E0,B0,E1,B1][slot][component]
-    long off_phi[3];
+    long off_em[4][kEmSlots][3];        // [E0,B0,E1,B1][slot][component]
+    long off_phi[kPhiSlots];
     long off_c[3];
-    long off_axg[3][2][3];
-    long off_murg[2][3][2][3][2];
+    long off_axg[3][2][kPhiSlots];
+    long off_murg[2][3][2][3][kEmSlots];
     int diag_blocks;
     size_t off_part;
     int rec_cap;

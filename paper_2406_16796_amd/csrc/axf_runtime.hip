@@ -136,10 +136,10 @@ Layout make_layout(const axf_config *c)
     L.off_arrays = off;
     off += L.arr_stride * kNumArrays;
     for (int kind = 0; kind < 4; kind++)
-        for (int s = 0; s < 2; s++)
+        for (int s = 0; s < kEmSlots; s++)
             for (int comp = 0; comp < 3; comp++)
                 L.off_em[kind][s][comp] = act(kind, comp) ? (long)(L.off_arrays + L.arr_stride * q_em(kind, s, comp)) : -1;
-    for (int s = 0; s < 3; s++) L.off_phi[s] = (long)(L.off_arrays + L.arr_stride * q_phi(s));
+    for (int s = 0; s < kPhiSlots; s++) L.off_phi[s] = (long)(L.off_arrays + L.arr_stride * q_phi(s));
     for (int comp = 0; comp < 3; comp++) L.off_c[comp] = (long)(L.off_arrays + L.arr_stride * q_c(comp));
     // boundary planes exist only normal to the active axes
     size_t fmax = 0;
@@ -153,11 +153,11 @@ Layout make_layout(const axf_config *c)
     off += L.face_stride * kNumFaces;
     for (int d = 0; d < 3; d++)
         for (int side = 0; side < 2; side++) {
-            for (int s = 0; s < 3; s++)
+            for (int s = 0; s < kPhiSlots; s++)
                 L.off_axg[d][side][s] = (d < D && c->ax_bc[d] != AXF_AX_PERIODIC) ? (long)(L.off_faces + L.face_stride * q_axg(d, side, s)) : -1;
             for (int o = 0; o < 2; o++)
                 for (int comp = 0; comp < 3; comp++)
-                    for (int s = 0; s < 2; s++) {
+                    for (int s = 0; s < kEmSlots; s++) {
                         bool on = d < D && c->em_bc[d] == AXF_EM_MUR && comp != d && act(o == 0 ? 0 : 2, comp);
                         L.off_murg[o][d][side][comp][s] = on ? (long)(L.off_faces + L.face_stride * q_mur(o, d, side, comp, s)) : -1;
                     }
@@ -238,21 +238,21 @@ static void fill_runk(RunK<T>& k, const axf_config *c, const Layout& L, char *ba
     k.face_base = base + L.off_faces;
     k.arr_stride = (long)L.arr_stride;
     k.face_stride = (long)L.face_stride;
-    for (int s = 0; s < 2; s++)
+    for (int s = 0; s < kEmSlots; s++)
         for (int comp = 0; comp < 3; comp++) {
             k.E0[s][comp] = P(L.off_em[0][s][comp]);
             k.B0[s][comp] = P(L.off_em[1][s][comp]);
             k.E1[s][comp] = P(L.off_em[2][s][comp]);
             k.B1[s][comp] = P(L.off_em[3][s][comp]);
         }
-    for (int s = 0; s < 3; s++) k.phi[s] = P(L.off_phi[s]);
+    for (int s = 0; s < kPhiSlots; s++) k.phi[s] = P(L.off_phi[s]);
     for (int comp = 0; comp < 3; comp++) k.C[comp] = P(L.off_c[comp]);
     for (int d = 0; d < 3; d++)
         for (int side = 0; side < 2; side++) {
-            for (int s = 0; s < 3; s++) k.axg[d][side][s] = P(L.off_axg[d][side][s]);
+            for (int s = 0; s < kPhiSlots; s++) k.axg[d][side][s] = P(L.off_axg[d][side][s]);
             for (int o = 0; o < 2; o++)
                 for (int comp = 0; comp < 3; comp++)
-                    for (int s = 0; s < 2; s++) k.murg[o][d][side][comp][s] = P(L.off_murg[o][d][side][comp][s]);
+                    for (int s = 0; s < kEmSlots; s++) k.murg[o][d][side][comp][s] = P(L.off_murg[o][d][side][comp][s]);
         }
     k.part = (double *)(base + L.off_part);
     k.diag_blocks = L.diag_blocks;
@@ -299,7 +299,7 @@ static void e_phase(Run *R)
     const RunK<T>& h = R->hk<T>();
     const RunK<T> *rk = R->rk<T>();
     long s = R->step;
-    int so = (int)(s & 1), sn = so ^ 1, la = (int)(s % 3), lb = (int)((s + 1) % 3);
+    int so = em_slot(s), sn = em_slot(s + 1), la = phi_slot(s), lb = phi_slot(s + 1);
     P::e0(rk, h, so, so, sn, T(1), R->stream);
     P::c(rk, h, la, lb, so, sn, so, 0, R->stream);
     P::e1(rk, h, so, so, sn, T(1), R->stream);
@@ -324,7 +324,7 @@ static void steps_plain(Run *R, int64_t nsteps)
     hipStream_t st = R->stream;
     for (int64_t it = 0; it < nsteps; it++) {
         long s = R->step;
-        int so = (int)(s & 1), sn = so ^ 1, la = (int)(s % 3), lb = (int)((s + 1) % 3);
+        int so = em_slot(s), sn = em_slot(s + 1), la = phi_slot(s), lb = phi_slot(s + 1);
         ensure_incident<D, T>(R, s);
         P::e0(rk, h, so, so, sn, T(1), st);
         P::c(rk, h, la, lb, so, sn, so, 0, st);
@@ -357,7 +357,7 @@ static void steps_semi(Run *R, int64_t nsteps)
     const bool tiled = D == 3 && !(te && te[0] == '0');
     for (int64_t it = 0; it < nsteps; it++) {
         long s = R->step;
-        int so = (int)(s & 1), sn = so ^ 1;
+        int so = em_slot(s), sn = em_slot(s + 1);
         ensure_incident<D, T>(R, s);
         if (tiled) {
             P::tiled_step(rk, h, s, R->chunk, st);
@@ -523,11 +523,12 @@ int run_prepare(Run *R)
     return AXF_OK;
 }
 
-// the wavefront kernel addresses the 27 field arrays it touches with 32-bit
-// byte offsets from one base (the LDS-marching kernel covers larger grids)
+// the wavefront kernel addresses the arrays of one EM slot (12) and the axion
+// levels with 32-bit byte offsets from a base per group (the LDS-marching
+// kernel covers larger grids)
 bool run_wave2d(const Run *R)
 {
-    return R->use_fused && R->cfg.ndim == 2 && !R->lds_march && (uint64_t)R->L.arr_stride * 27 <= (1ull << 32);
+    return R->use_fused && R->cfg.ndim == 2 && !R->lds_march && (uint64_t)R->L.arr_stride * kEmPerSlot <= (1ull << 32);
 }
 
 int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 8; }
@@ -606,12 +607,12 @@ int run_read_field(Run *R, int id, void *dst, size_t dst_bytes, int dst_is_devic
     std::vector<double> out(cnt, 0.0), tmp;
     long s = R->step;
     if (kind == 4) {
-        int slot = (int)((s + comp) % 3);
+        int slot = phi_slot(s + comp);
         HIPCHK(hipStreamSynchronize(R->stream));
         if ((rc = fetch(R, array_ptr(R, 4, 0, slot), out))) return rc;
     } else if (array_ptr(R, kind, comp, 0)) {
         bool is_e = (kind == 0 || kind == 2);
-        int so = (int)(s & 1), sn = so ^ 1;
+        int so = em_slot(s), sn = em_slot(s + 1);
         if (is_e && R->converted && R->ephase_step != s) {
             AXF_DISPATCH(R, e_phase, R);
             R->ephase_step = s;
