@@ -32,6 +32,15 @@ hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chu
 template <typename T>
 hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st,
                                const WaveStreams *ws);
+// Two steps n, n + 1 in one pass over the interior (temporal blocking, ci rows
+// per wavefront) with the two one-step frame launches around it (cf rows per
+// wavefront, ci a multiple of cf); available when the grid has an interior
+// for the pass.
+template <typename T>
+bool wave2d_pair_available(const RunK<T>& h, int ci, int cf);
+template <typename T>
+hipError_t launch_wave2d_pair(const RunK<T> *rk, const RunK<T>& h, long step, int ci, int cf, int pd, hipStream_t st,
+                              const WaveStreams *ws);
 // workgroups (4 wavefronts each) of one run's two wavefront launches: the
 // frame next to the domain boundary and the interior
 template <typename T>

@@ -776,7 +776,8 @@ __device__ __forceinline__ double lane_dn(double v)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-constexpr int kWaveOut = 59;   // output columns per wavefront
+constexpr int kWaveOut = 59;   // output columns per wavefront (one step)
+constexpr int kWaveOut2 = 58;  // ... of the two-step march (lanes 3 .. 60)
 // prefetch distance (rows ahead) of the interior march, by precision (measured)
 template <typename T> struct WavePD { static constexpr int value = sizeof(T) == 8 ? 2 : 3; };
 
@@ -846,16 +847,17 @@ __device__ __forceinline__ T *face_of(const RunK<T> *rp, int q) { return (T *)(r
 // wraps and there are no ghosts to read or write; the point formulas are the
 // same, so both variants produce the same bits.
 template <typename T, bool INTERIOR, int PD>
-__device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long step, int seg, int ch, int nch, int chunk)
+__device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long step, int seg, int ch, int nch, int chunk,
+                                            int wid = kWaveOut)
 {
     KW<T> r = make_kw(rp);
     const int lane = threadIdx.x & 63;
     const int so = em_slot(step), sn = em_slot(step + 1);
     const int la = phi_slot(step), lb = phi_slot(step + 1), ln = phi_slot(step + 2);
 
-    const int x0 = seg * kWaveOut, gx = x0 - 3 + lane;
-    const int own_x_hi = min(x0 + kWaveOut, r.nn[0]);
-    const bool own_x = lane >= 3 && lane < 3 + kWaveOut && gx < own_x_hi;
+    const int x0 = seg * wid, gx = x0 - 3 + lane;
+    const int own_x_hi = min(x0 + wid, r.nn[0]);
+    const bool own_x = lane >= 3 && lane < 3 + wid && gx < own_x_hi;
     const int c0 = ch * chunk, c1 = (ch == nch - 1) ? r.nn[1] : c0 + chunk;
     const int n0 = r.n[0], n1 = r.n[1], nn0 = r.nn[0], nn1 = r.nn[1];
     const bool mx = INTERIOR ? false : r.mur[0], my = INTERIOR ? false : r.mur[1];
@@ -1030,7 +1032,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
             const T up_e = lane_up(e0h_1[1]), dn_e = lane_dn(e0h_1[1]);
             if (mx && (gx == -1 || gx == n0) && vy_nod(p1)) {
                 const int side = gx == -1 ? 0 : 1, ox = side ? -1 : 1;
-                const bool owner = own_plane(p1) && lane + ox >= 3 && lane + ox < 3 + kWaveOut && gx + ox < own_x_hi;
+                const bool owner = own_plane(p1) && lane + ox >= 3 && lane + ox < 3 + wid && gx + ox < own_x_hi;
                 e0h_1[1] = ghost(0, 1, 0, side, p1, ox, p1, side ? dn_e : up_e, owner);
             }
             // Mur ghosts of E0x across y (E0x centred in y): plane -1 from plane 0, plane n1 from n1 - 1
@@ -1120,7 +1122,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
             const T up_z = lane_up(e1h_2[2]), dn_z = lane_dn(e1h_2[2]);
             if (mx && (gx == -1 || gx == n0)) {
                 const int side = gx == -1 ? 0 : 1, ox = side ? -1 : 1;
-                const bool owner = own_plane(p2) && lane + ox >= 3 && lane + ox < 3 + kWaveOut && gx + ox < own_x_hi;
+                const bool owner = own_plane(p2) && lane + ox >= 3 && lane + ox < 3 + wid && gx + ox < own_x_hi;
                 if (vy_nod(p2)) e1h_2[1] = ghost(1, 1, 0, side, p2, ox, p2, side ? dn_y : up_y, owner);
                 if (vy_cen(p2)) e1h_2[2] = ghost(1, 2, 0, side, p2, ox, p2, side ? dn_z : up_z, owner);
             }
@@ -1208,6 +1210,183 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
     }
 }
 
+// ---------------------------------------------------------------- two steps
+//
+// Temporal blocking of the interior march: a wavefront advances its rows two
+// time steps per pass.  Stage 1 is the one-step pipeline on the loaded planes;
+// stage 2 is the same pipeline one row behind, fed from stage 1's registers
+// (its E, B and axion level of step n+1) instead of from memory, so each row
+// of the state is read once and written once per two steps.  Both stages use
+// the point formulas of the one-step interior march in the same order, so the
+// results are the same bits.  Stage 1 is valid on lanes 1 .. 62 and stage 2 on
+// lanes 3 .. 60: the pass owns 58 columns per wavefront.
+
+// register windows of one stage along y (suffix = rows behind the newest row t
+// of the stage); the outputs of an advance are at rows t - 1 (E0^{n+1/2},
+// B0^{n+1}) and t - 2 (E1^{n+1/2}, B1^{n+1}, phi^{n+3/2})
+template <typename T>
+struct Stage {
+    T b0z_2, b0z_1, b0z_0;
+    T pa_3, pa_2, pa_1, pb_3, pb_2, pb_1;
+    T b1_2[3], b1_1[3];
+    T e0h_2[2], e0h_1[2], e0n_2[2], e0n_1[2];
+    T c_3[3], c_2[3];
+    T b0p_2, b0p_1;
+    T e1h_3[3], e1h_2[3];
+    T b1n[3], pn;                          // B1^{n+1} and phi^{n+3/2} at row t - 2
+
+    __device__ __forceinline__ void clear()
+    {
+        b0z_2 = b0z_1 = b0z_0 = T(0);
+        pa_3 = pa_2 = pa_1 = pb_3 = pb_2 = pb_1 = T(0);
+        b0p_2 = b0p_1 = pn = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; c++) b1_2[c] = b1_1[c] = c_3[c] = c_2[c] = e1h_3[c] = e1h_2[c] = b1n[c] = T(0);
+#pragma unroll
+        for (int c = 0; c < 2; c++) e0h_2[c] = e0h_1[c] = e0n_2[c] = e0n_1[c] = T(0);
+    }
+
+    // one row of the interior one-step march: take in B0z at row t, B1, the
+    // two axion levels and E0 at row t - 1, E1 at row t - 2; S5 and S6 (B1 and
+    // phi at t - 2) only when full
+    template <typename K>
+    __device__ __forceinline__ void advance(const K& r, T bext0, T bext1, T bext2, T in_b0z, const T in_b1[3], T in_pa,
+                                            T in_pb, const T e0m[2], const T e1m[3], bool full)
+    {
+        b0z_2 = b0z_1; b0z_1 = b0z_0; b0z_0 = in_b0z;
+        pa_3 = pa_2; pa_2 = pa_1; pa_1 = in_pa;
+        pb_3 = pb_2; pb_2 = pb_1; pb_1 = in_pb;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            b1_2[c] = b1_1[c];
+            c_3[c] = c_2[c];
+            e1h_3[c] = e1h_2[c];
+            b1_1[c] = in_b1[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            e0h_2[c] = e0h_1[c];
+            e0n_2[c] = e0n_1[c];
+        }
+        b0p_2 = b0p_1;
+        // S1: E0^{n+1/2}, E0^n at row t - 1
+        {
+            const T up_b0z = lane_up(b0z_1);
+            T eh[2], en[2];
+            {
+                T a = r.cdt[1] * (b0z_0 - b0z_1), b = T(0);
+                T rhs = a - b;
+                eh[0] = e0m[0] + T(1) * rhs;
+                en[0] = r.half * (e0m[0] + eh[0]);
+            }
+            {
+                T a = T(0), b = r.cdt[0] * (up_b0z - b0z_1);
+                T rhs = a - b;
+                eh[1] = e0m[1] + T(1) * rhs;
+                en[1] = r.half * (e0m[1] + eh[1]);
+            }
+            e0h_1[0] = eh[0]; e0h_1[1] = eh[1];
+            e0n_1[0] = en[0]; e0n_1[1] = en[1];
+        }
+        // S2: C^n at the centres of row t - 2
+        {
+            T e[3], bb[3], gp[3];
+            const T up_en0 = lane_up(e0n_2[0]);
+            const T up_b2 = lane_up(b0z_2), up_b1 = lane_up(b0z_1);
+            const T up_pa = lane_up(pa_2), up_pb = lane_up(pb_2), dn_pa = lane_dn(pa_2), dn_pb = lane_dn(pb_2);
+            e[0] = r.half * (e0n_2[0] + up_en0);
+            e[1] = r.half * (e0n_2[1] + e0n_1[1]);
+            e[2] = T(0);
+            bb[0] = T(0) + bext0;
+            bb[1] = T(0) + bext1;
+            bb[2] = T(0.25) * ((b0z_2 + up_b2) + (b0z_1 + up_b1)) + bext2;
+            T dtphi = (pb_2 - pa_2) * r.inv_dt;
+            {
+                T up = r.half * (up_pa + up_pb), dn = r.half * (dn_pa + dn_pb);
+                gp[0] = (up - dn) * r.inv2dx[0];
+            }
+            {
+                T up = r.half * (pa_1 + pb_1), dn = r.half * (pa_3 + pb_3);
+                gp[1] = (up - dn) * r.inv2dx[1];
+            }
+            gp[2] = T(0);
+            c_2[0] = dtphi * bb[0] - (e[1] * gp[2] - e[2] * gp[1]);
+            c_2[1] = dtphi * bb[1] - (e[2] * gp[0] - e[0] * gp[2]);
+            c_2[2] = dtphi * bb[2] - (e[0] * gp[1] - e[1] * gp[0]);
+        }
+        // S3: B0z^{n+1} at row t - 1
+        {
+            const T dn_e0y = lane_dn(e0h_1[1]);
+            T a = r.cdt[0] * (e0h_1[1] - dn_e0y), b = r.cdt[1] * (e0h_1[0] - e0h_2[0]);
+            b0p_1 = b0z_1 - (a - b);
+        }
+        // S4: E1^{n+1/2} at row t - 2
+        {
+            const T up_b1z = lane_up(b1_2[2]), up_b1y = lane_up(b1_2[1]);
+            const T dn_cx = lane_dn(c_2[0]);
+            {
+                T Sc = r.half * (dn_cx + c_2[0]);
+                T a = r.cdt[1] * (b1_1[2] - b1_2[2]), b = T(0);
+                T rhs = (a - b) - r.cg1 * Sc;
+                e1h_2[0] = e1m[0] + T(1) * rhs;
+            }
+            {
+                T Sc = r.half * (c_3[1] + c_2[1]);
+                T a = T(0), b = r.cdt[0] * (up_b1z - b1_2[2]);
+                T rhs = (a - b) - r.cg1 * Sc;
+                e1h_2[1] = e1m[1] + T(1) * rhs;
+            }
+            {
+                T Sc = c_2[2];
+                T a = r.cdt[0] * (up_b1y - b1_2[1]), b = r.cdt[1] * (b1_1[0] - b1_2[0]);
+                T rhs = (a - b) - r.cg1 * Sc;
+                e1h_2[2] = e1m[2] + T(1) * rhs;
+            }
+        }
+        if (!full) return;
+        // S5: B1^{n+1} and S6: phi^{n+3/2} at row t - 2
+        {
+            const T dn_e1z = lane_dn(e1h_2[2]), dn_e1y = lane_dn(e1h_2[1]);
+            {
+                T a = r.cdt[1] * (e1h_2[2] - e1h_3[2]), b = T(0);
+                b1n[0] = b1_2[0] - (a - b);
+            }
+            {
+                T a = T(0), b = r.cdt[0] * (e1h_2[2] - dn_e1z);
+                b1n[1] = b1_2[1] - (a - b);
+            }
+            {
+                T a = r.cdt[0] * (e1h_2[1] - dn_e1y), b = r.cdt[1] * (e1h_2[0] - e1h_3[0]);
+                b1n[2] = b1_2[2] - (a - b);
+            }
+        }
+        {
+            const T up_e0x = lane_up(e0h_2[0]);
+            const T up_b2 = lane_up(b0z_2), up_b1 = lane_up(b0z_1);
+            const T up_p2 = lane_up(b0p_2), up_p1 = lane_up(b0p_1);
+            const T up_pb = lane_up(pb_2), dn_pb = lane_dn(pb_2);
+            T e[3], bb[3];
+            e[0] = r.half * (e0h_2[0] + up_e0x);
+            e[1] = r.half * (e0h_2[1] + e0h_1[1]);
+            e[2] = T(0);
+            T bo0 = T(0), bn0 = T(0), bo1 = T(0), bn1 = T(0);
+            T bo2 = T(0.25) * ((b0z_2 + up_b2) + (b0z_1 + up_b1));
+            T bn2 = T(0.25) * ((b0p_2 + up_p2) + (b0p_1 + up_p1));
+            bb[0] = r.half * (bo0 + bn0) + bext0;
+            bb[1] = r.half * (bo1 + bn1) + bext1;
+            bb[2] = r.half * (bo2 + bn2) + bext2;
+            T sax = r.gax * (e[0] * bb[0] + e[1] * bb[1] + e[2] * bb[2]);
+            T pa = pa_2, pb = pb_2;
+            T lap = T(0);
+            lap += ((up_pb - T(2) * pb) + dn_pb) * r.inv_dx2[0];
+            lap += ((pb_1 - T(2) * pb) + pb_3) * r.inv_dx2[1];
+            T sdt = T(0);
+            T x = r.dt2 * ((sax - r.m2 * pb) + lap) - sdt * sdt * pb;
+            pn = ((x + sdt * pa) + T(2) * pb) - pa;
+        }
+    }
+};
+
 // Interior rectangle of the wavefront grid: segments [sx0, sx1) and chunks
 // [cy0, cy1) whose columns x0-3 .. x0+60 and rows c0-4 .. c1+1 stay at least
 // `margin` cells inside the grid (margin = 1, or the damping-layer thickness on
@@ -1219,6 +1398,7 @@ __device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfir
 
 struct WaveSplit {
     int nseg, nch, sx0, sx1, cy0, cy1;
+    int wid;                              // output columns per segment
     __host__ __device__ long interior() const { return (long)(sx1 - sx0) * (cy1 - cy0); }
     __host__ __device__ long edge() const { return (long)nseg * nch - interior(); }
 };
@@ -1227,6 +1407,7 @@ template <typename R>
 __host__ __device__ inline WaveSplit wave2d_split(const R& h, int chunk)
 {
     WaveSplit w;
+    w.wid = kWaveOut;
     w.nseg = (h.nn[0] + kWaveOut - 1) / kWaveOut;
     w.nch = (h.nn[1] + chunk - 1) / chunk;
     const int mxg = 1 + (h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
@@ -1264,6 +1445,155 @@ __device__ __forceinline__ void wave2d_edge_item(const WaveSplit& w, long e, int
     }
 }
 
+// The interior of a two-step pass in units of 58-column segments and `ci`-row
+// chunks, and the two one-step frame launches around it (cf-row chunks, ci a
+// multiple of cf): frame A advances step n on everything but the core of the
+// interior (the interior without its outermost segment and frame chunk on each
+// side), frame B advances step n + 1 on everything but the interior.
+struct WavePair {
+    WaveSplit in, fa, fb;
+    int ci;
+    int ring_y0, ring_y1;                 // rows of the core; the core's phi^{n+3/2}
+                                          // comes from the interior, the rest from frame A
+};
+
+template <typename R>
+__host__ __device__ inline WavePair wave2d_split_pair(const R& h, int ci, int cf)
+{
+    WavePair p;
+    p.ci = ci;
+    WaveSplit& w = p.in;
+    w.wid = kWaveOut2;
+    w.nseg = (h.nn[0] + kWaveOut2 - 1) / kWaveOut2;
+    w.nch = (h.nn[1] + ci - 1) / ci;
+    const int mxg = 1 + (h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
+    const int myg = 1 + (h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
+    // columns x0 - 3 .. x0 + 60 and rows c0 - 7 .. c0 + ci + 2 (everything the
+    // pass loads or computes) stay at least the margin inside the grid
+    w.sx0 = (mxg + 3 + kWaveOut2 - 1) / kWaveOut2;
+    w.sx1 = (h.n[0] - 1 - mxg - 60) >= 0 ? (h.n[0] - 1 - mxg - 60) / kWaveOut2 + 1 : 0;
+    w.cy0 = (myg + 7 + ci - 1) / ci;
+    w.cy1 = (h.n[1] - 3 - myg - ci) >= 0 ? (h.n[1] - 3 - myg - ci) / ci + 1 : 0;
+    const int nchf = (h.nn[1] + cf - 1) / cf, k = ci / cf;
+    // the last frame chunk (which runs to the storage end) is never interior
+    if (w.cy1 * k > nchf - 1) w.cy1 = (nchf - 1) / k;
+    // a pass needs a core: at least one segment and one frame chunk inside the ring
+    if (w.sx1 - w.sx0 < 3 || (w.cy1 - w.cy0) * k < 3) w.sx0 = w.sx1 = w.cy0 = w.cy1 = 0;
+    p.fb = WaveSplit{w.nseg, nchf, w.sx0, w.sx1, w.cy0 * k, w.cy1 * k, kWaveOut2};
+    p.fa = p.fb;
+    if (w.sx1 > w.sx0) {
+        p.fa.sx0 += 1; p.fa.sx1 -= 1;
+        p.fa.cy0 += 1; p.fa.cy1 -= 1;
+    }
+    p.ring_y0 = p.fa.cy0 * cf;
+    p.ring_y1 = p.fa.cy1 * cf;
+    return p;
+}
+
+// The wavefront of segment `seg` and chunk `ch` of the interior of a two-step
+// pass: reads E/B of step n and the axion levels n, n + 1; writes E/B of step
+// n + 2, phi^{n+5/2} and, in the core, phi^{n+3/2}.
+template <typename T, int PD>
+__device__ __forceinline__ void wave2d_pair_body(const RunK<T> *__restrict__ rp, long step, const WavePair& wp, int seg,
+                                                 int ch)
+{
+    KW<T> r = make_kw(rp);
+    const int lane = threadIdx.x & 63;
+    const int e_rd = em_slot(step), e_wr = em_slot(step + 2);
+    const int la = phi_slot(step), lb = phi_slot(step + 1), l2 = phi_slot(step + 2), l3 = phi_slot(step + 3);
+    const int ci = wp.ci;
+    const int x0 = seg * kWaveOut2, gx = x0 - 3 + lane;
+    const bool own_x = lane >= 3 && lane < 3 + kWaveOut2;
+    const bool core_x = seg >= wp.fa.sx0 && seg < wp.fa.sx1;
+    const int c0 = ch * ci, c1 = c0 + ci, cs = c0 - 3;      // stage 1 starts as if its chunk began at cs
+    const int n0 = r.n[0];
+    const unsigned es = sizeof(T), sxb = (unsigned)r.sx * es;
+    const unsigned bx = (unsigned)gx * es;
+    unsigned as_l = r.as;
+    const char *const b_rd = r.sb + (size_t)q_em(0, e_rd, 0) * r.as;
+    const char *const b_wr = r.sb + (size_t)q_em(0, e_wr, 0) * r.as;
+    const char *const b_ph = r.sb + (size_t)q_phi(0) * r.as;
+    auto lde = [&](int kind, int c, unsigned o) __attribute__((always_inline)) -> T {
+        return ldo((const T *)b_rd, (unsigned)(kind * 3 + c) * as_l + o);
+    };
+    auto ste = [&](int kind, int c, unsigned o, T v) __attribute__((always_inline)) {
+        sto((T *)b_wr, (unsigned)(kind * 3 + c) * as_l + o, v);
+    };
+    auto ldp = [&](int L, unsigned o) __attribute__((always_inline)) -> T { return ldo((const T *)b_ph, (unsigned)L * as_l + o); };
+    auto stp = [&](int L, unsigned o, T v) __attribute__((always_inline)) { sto((T *)b_ph, (unsigned)L * as_l + o, v); };
+    auto off = [&](int p) __attribute__((always_inline)) -> unsigned { return bx + (unsigned)p * sxb; };
+
+    struct Pref {
+        T b0z, b1[3], pa, pb, e0m[2], e1m[3];
+    };
+    Pref buf[PD];
+    auto prefetch = [&](int t, Pref& P) __attribute__((always_inline)) {
+        const unsigned o0 = off(t), o1 = off(t - 1), o2 = off(t - 2);
+        P.b0z = lde(1, 2, o0);
+#pragma unroll
+        for (int c = 0; c < 3; c++) P.b1[c] = t - 1 >= cs - 1 ? lde(3, c, o1) : T(0);
+        P.pa = ldp(la, o1);
+        P.pb = ldp(lb, o1);
+#pragma unroll
+        for (int c = 0; c < 2; c++) P.e0m[c] = t - 1 >= cs - 2 ? lde(0, c, o1) : T(0);
+#pragma unroll
+        for (int c = 0; c < 3; c++) P.e1m[c] = t - 2 >= cs - 1 ? lde(2, c, o2) : T(0);
+    };
+
+    const T bext0 = bext_at(*rp, 0, gx), bext1 = bext_at(*rp, 1, gx), bext2 = bext_at(*rp, 2, gx);
+    (void)n0;
+    Stage<T> s1, s2;
+    s1.clear();
+    s2.clear();
+    const int t_first = cs - 2, t_last = c1 + 2;
+#pragma unroll
+    for (int k = 0; k < PD; k++)
+        if (t_first + k <= t_last) prefetch(t_first + k, buf[k]);
+    constexpr int U = PD == 1 ? 1 : 6;
+    for (int t0 = t_first; t0 <= t_last; t0 += U)
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+        const int t = t0 + k;
+        if (t > t_last) break;
+        Pref& P = buf[k % PD];
+        asm volatile("" : "+s"(as_l));
+        const T b0z = P.b0z, pa = P.pa, pb = P.pb;
+        const T b1[3] = {P.b1[0], P.b1[1], P.b1[2]};
+        const T e0m[2] = {P.e0m[0], P.e0m[1]};
+        const T e1m[3] = {P.e1m[0], P.e1m[1], P.e1m[2]};
+        if (t + PD <= t_last) prefetch(t + PD, P);
+        // stage 1: step n, rows t - 1 (E0, B0z) and t - 2 (E1, B1, phi)
+        s1.advance(r, bext0, bext1, bext2, b0z, b1, pa, pb, e0m, e1m, true);
+        const int q2 = t - 2;
+        if (q2 >= c0 && q2 < c1 && q2 >= wp.ring_y0 && q2 < wp.ring_y1 && core_x && own_x)
+            stp(l2, off(q2), s1.pn);
+        // stage 2: step n + 1 one row behind, from stage 1's registers
+        {
+            const T e1in[3] = {s1.e1h_3[0], s1.e1h_3[1], s1.e1h_3[2]};
+            const T e0in[2] = {s1.e0h_2[0], s1.e0h_2[1]};
+            const int q3 = t - 3;
+            const bool full = q3 >= c0 && q3 < c1;
+            s2.advance(r, bext0, bext1, bext2, s1.b0p_1, s1.b1n, s1.pb_2, s1.pn, e0in, e1in, full);
+            if (own_x) {
+                if (q2 >= c0 && q2 < c1) {
+                    const unsigned o = off(q2);
+                    ste(0, 0, o, s2.e0h_1[0]);
+                    ste(0, 1, o, s2.e0h_1[1]);
+                    ste(1, 2, o, s2.b0p_1);
+                }
+                if (full) {
+                    const unsigned o = off(q3);
+#pragma unroll
+                    for (int c = 0; c < 3; c++) ste(2, c, o, s2.e1h_2[c]);
+#pragma unroll
+                    for (int c = 0; c < 3; c++) ste(3, c, o, s2.b1n[c]);
+                    stp(l3, o, s2.pn);
+                }
+            }
+        }
+    }
+}
+
 template <typename T, int PD>
 __global__ void __launch_bounds__(256) k_wave2d_int(const RunK<T> *__restrict__ rp, long step, WaveSplit w, int chunk)
 {
@@ -1280,7 +1610,16 @@ __global__ void __launch_bounds__(256, 3) k_wave2d(const RunK<T> *__restrict__ r
     if (gw >= w.edge()) return;
     int seg, ch;
     wave2d_edge_item(w, gw, seg, ch);
-    wave2d_body<T, false, 1>(rp, step, seg, ch, w.nch, chunk);
+    wave2d_body<T, false, 1>(rp, step, seg, ch, w.nch, chunk, w.wid);
+}
+
+template <typename T, int PD>
+__global__ void __launch_bounds__(256) k_wave2d_pair(const RunK<T> *__restrict__ rp, long step, WavePair wp)
+{
+    const long gw = xcd_band(blockIdx.x, gridDim.x) * 4L + wave_in_block();
+    if (gw >= wp.in.interior()) return;
+    const int ni = wp.in.sx1 - wp.in.sx0;
+    wave2d_pair_body<T, PD>(rp, step, wp, wp.in.sx0 + (int)(gw % ni), wp.in.cy0 + (int)(gw / ni));
 }
 
 // batched: every active run of the table, each with its own step and chunk
@@ -1366,6 +1705,47 @@ hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chu
     return hipGetLastError();
 }
 
+template <typename T>
+bool wave2d_pair_available(const RunK<T>& h, int ci, int cf)
+{
+    return ci > 0 && cf > 0 && ci % cf == 0 && wave2d_split_pair(h, ci, cf).in.interior() > 0;
+}
+
+template <typename T>
+hipError_t launch_wave2d_pair(const RunK<T> *rk, const RunK<T>& h, long step, int ci, int cf, int pd, hipStream_t st,
+                              const WaveStreams *ws)
+{
+    const WavePair wp = wave2d_split_pair(h, ci, cf);
+    const unsigned ni = (unsigned)((wp.in.interior() + 3) / 4);
+    const unsigned na = (unsigned)((wp.fa.edge() + 3) / 4), nb = (unsigned)((wp.fb.edge() + 3) / 4);
+    if (ni == 0) return hipErrorInvalidValue;
+    if (pd <= 0) pd = 2;
+    // frame A (step n) and frame B (step n + 1) in order on the side stream,
+    // beside the interior: the three launches write disjoint outputs, and the
+    // interior reads only slots that neither frame writes
+    const bool fork = ws && ws->side;
+    hipStream_t se = st;
+    if (fork) {
+        hipEventRecord(ws->fork, st);
+        hipStreamWaitEvent(ws->side, ws->fork, 0);
+        se = ws->side;
+    }
+    if (na > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(na), dim3(256), 0, se, rk, step, wp.fa, cf);
+    if (pd <= 1) hipLaunchKernelGGL((k_wave2d_pair<T, 1>), dim3(ni), dim3(256), 0, st, rk, step, wp);
+    else if (pd == 2) hipLaunchKernelGGL((k_wave2d_pair<T, 2>), dim3(ni), dim3(256), 0, st, rk, step, wp);
+    else hipLaunchKernelGGL((k_wave2d_pair<T, 3>), dim3(ni), dim3(256), 0, st, rk, step, wp);
+    if (nb > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(nb), dim3(256), 0, se, rk, step + 1, wp.fb, cf);
+    if (fork) {
+        hipEventRecord(ws->join, ws->side);
+        hipStreamWaitEvent(st, ws->join, 0);
+    }
+    return hipGetLastError();
+}
+
+template bool wave2d_pair_available<float>(const RunK<float>&, int, int);
+template bool wave2d_pair_available<double>(const RunK<double>&, int, int);
+template hipError_t launch_wave2d_pair<float>(const RunK<float> *, const RunK<float>&, long, int, int, int, hipStream_t, const WaveStreams *);
+template hipError_t launch_wave2d_pair<double>(const RunK<double> *, const RunK<double>&, long, int, int, int, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d<float>(const RunK<float> *, const RunK<float>&, long, int, int, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d<double>(const RunK<double> *, const RunK<double>&, long, int, int, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d_batch<float>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);

@@ -305,12 +305,12 @@ static void e_phase(Run *R)
     P::e1(rk, h, so, so, sn, T(1), R->stream);
 }
 
-// keep the laser table covering time levels s and s + 1 of step s
+// keep the laser table covering time levels s .. s + nst of steps s .. s + nst - 1
 template <int D, typename T>
-static void ensure_incident(Run *R, long s)
+static void ensure_incident(Run *R, long s, int nst = 1)
 {
     if (!R->cfg.laser_on) return;
-    if (R->inc_lo >= 0 && s >= R->inc_lo && s + 1 < R->inc_lo + kIncLevels) return;
+    if (R->inc_lo >= 0 && s >= R->inc_lo && s + nst < R->inc_lo + kIncLevels) return;
     Plain<D, T>::inc_fill(R->rk<T>(), R->hk<T>(), s, kIncLevels, R->stream);
     R->inc_lo = s;
 }
@@ -406,17 +406,27 @@ static int steps_fused(Run *R, int64_t nsteps)
             }
             ws = WaveStreams{R->side, R->ev_fork, R->ev_join};
         }
-        for (int64_t it = 0; it < nsteps; it++) {
+        // two steps per pass (2D) unless a diagnostic record falls on the first
+        // of them or between them: the pass stores no complete state of step n + 1
+        int ci = 0, cf = 0;
+        run_pair_shape(R, &ci, &cf);
+        const bool pairs = wave2d && R->pair && wave2d_pair_available<T>(h, ci, cf);
+        auto due = [&](long s) { return R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0; };
+        for (int64_t it = 0; it < nsteps;) {
             long s = R->step;
-            ensure_incident<D, T>(R, s);
-            hipError_t e = wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->pd, R->stream, ws.side ? &ws : nullptr)
+            const bool two = pairs && nsteps - it >= 2 && !due(s) && !due(s + 1);
+            ensure_incident<D, T>(R, s, two ? 2 : 1);
+            const WaveStreams *wsp = ws.side ? &ws : nullptr;
+            hipError_t e = two ? launch_wave2d_pair<T>(rk, h, s, ci, cf, R->pair_pd, R->stream, wsp)
+                         : wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->pd, R->stream, wsp)
                                   : F::launch(rk, h, s, chunk, R->stream);
             if (e != hipSuccess) return hip_fail(e, "fused step launch");
-            if (R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0) {
+            if (!two && due(s)) {
                 Plain<D, T>::diag(rk, h, s, R->rec_written % h.rec_cap, R->stream);
                 R->rec_written++;
             }
-            R->step++;
+            R->step += two ? 2 : 1;
+            it += two ? 2 : 1;
             R->launches += 1;
         }
         return AXF_OK;
@@ -490,6 +500,10 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     if (const char *ch = getenv("AXF_FUSED_CHUNK")) R->chunk = atoi(ch);
     if (const char *pd = getenv("AXF_WAVE_PD")) R->pd = atoi(pd);
     if (const char *lm = getenv("AXF_LDS_MARCH")) R->lds_march = lm[0] == '1';
+    if (const char *pe = getenv("AXF_WAVE_PAIR")) R->pair = pe[0] != '0';
+    if (const char *pc = getenv("AXF_PAIR_CHUNK")) R->pair_ci = atoi(pc);
+    if (const char *pf = getenv("AXF_PAIR_FRAME")) R->pair_cf = atoi(pf);
+    if (const char *pp = getenv("AXF_PAIR_PD")) R->pair_pd = atoi(pp);
     R->use_fused = cfg->path == AXF_PATH_FUSED || (cfg->path == AXF_PATH_AUTO && fused_supported(cfg) && auto_fused_enabled(cfg));
     choose_scales(cfg, &R->s_phi, &R->s_1);
     if (cfg->precision == AXF_F32) {
@@ -532,6 +546,12 @@ bool run_wave2d(const Run *R)
 }
 
 int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 8; }
+
+void run_pair_shape(const Run *R, int *ci, int *cf)
+{
+    *cf = R->pair_cf > 0 ? R->pair_cf : 8;
+    *ci = R->pair_ci > 0 ? R->pair_ci : 16;
+}
 
 int run_step(Run *R, int64_t nsteps)
 {
