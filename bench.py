@@ -37,8 +37,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# built-in (rows per march, prefetch distance) of the 2D wavefront step
-DEFAULT_WAVE_SHAPE = {"f32": (8, 3), "f64": (8, 2)}
+# built-in shape of the 2D wavefront step: (steps per pass, rows per interior
+# wavefront, prefetch distance, rows per frame wavefront)
+DEFAULT_WAVE_SHAPE = {"f32": (2, 8, 2, 8), "f64": (2, 8, 3, 8)}
 COPY_BYTES = 1 << 30
 CSRC = "paper_2406_16796_amd/csrc/"
 COMMON_SOURCES = [CSRC + "axf_stencil.h", CSRC + "axf_internal.h", "paper_2406_16796_amd/build.py"]
@@ -46,7 +47,7 @@ COMMON_SOURCES = [CSRC + "axf_stencil.h", CSRC + "axf_internal.h", "paper_2406_1
 # one step's launches ({T} = float or double), sources those kernels are built
 # from)
 WORKLOADS = {
-    "2d": ("gaussian_2d", "k_wave2d", ["k_wave2d_int<{T}", "k_wave2d<{T}"],
+    "2d": ("gaussian_2d", "k_wave2d", ["k_wave2d_pair<{T}", "k_wave2d_int<{T}", "k_wave2d<{T}"],
            [CSRC + "axf_fused.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
     "3d": ("focused_3d", "k3_tile", ["k3_tile<3,{T},0>", "k3_tile<3,{T},1>", "k_mur<3,{T}>",
                                      "k3_tile<3,{T},2>", "k3_tile<3,{T},3>"],
@@ -212,7 +213,8 @@ def scan_leg(axf, torch, steps_scale, count=512, tune=True):
     if tune:
         for key, c in sorted(classes.items()):
             t = axf.tune(c, precision=axf.F32, steps=10)
-            tuned["%dx%d" % (1 << key[0], 1 << key[1])] = [t["chunk"], t["prefetch"]]
+            tuned["%dx%d" % (1 << key[0], 1 << key[1])] = [t["steps_per_pass"], t["chunk"], t["prefetch"],
+                                                            t["frame_chunk"]]
     batch = axf.Batch(cfgs, precision=axf.F32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -244,7 +246,7 @@ def scan_leg(axf, torch, steps_scale, count=512, tune=True):
             "unit": "Gcell-updates/s", "speedup": round(t_alone / t_batch, 3),
             "batched_s": round(t_batch, 3), "per_run_s": round(t_alone, 3),
             "p_bitwise_equal": all(p_batch[i] == p_alone[i] for i in probe),
-            "tuned_chunk_prefetch": tuned}
+            "tuned_steps_chunk_prefetch_frame": tuned}
 
 
 def percentile(v, q):
@@ -328,12 +330,16 @@ def pmc_rows(path):
     return out
 
 
+PROFILE_WARMUP = 2     # steps of the profile-only run before the timed ones
+
+
 def pmc_summary(args):
-    """Scale the FETCH_SIZE / WRITE_SIZE readings of the step kernel by the
+    """Scale the FETCH_SIZE / WRITE_SIZE readings of the step kernels by the
     readings of the device copy of known size, write the summary file."""
     cfg = workload(args.workload)
     tag = workload_tag(cfg, args.precision)
     kernel, pats = WORKLOADS[args.workload][1], step_patterns(args.workload, args.precision)
+    nsteps = args.steps + PROFILE_WARMUP
     res = {}
     for counter, path in (("FETCH_SIZE", args.pmc_summary[0]), ("WRITE_SIZE", args.pmc_summary[1])):
         rows = pmc_rows(path)
@@ -342,36 +348,35 @@ def pmc_summary(args):
             raise SystemExit("no copy dispatches in %s" % path)
         kib_copy = max(copy)
         factor = COPY_BYTES / (kib_copy * 1024.0)
-        # one step = one dispatch of each pattern: sum of the per-kernel means
-        kib_step, ndisp = 0.0, 0
+        # every dispatch of a step kernel over the whole run, per step
+        per = {}
         for pat in pats:
             vals = [v for k, v in rows if pat in k.replace(" ", "")]
-            if not vals:
-                raise SystemExit("no %s dispatches in %s" % (pat, path))
-            kib_step += sum(vals) / len(vals)
-            ndisp = max(ndisp, len(vals))
-        res[counter] = (kib_copy, factor, kib_step, ndisp, kib_step * 1024.0 * factor)
+            per[pat] = (len(vals), sum(vals))
+        if not any(n for n, _ in per.values()):
+            raise SystemExit("no step-kernel dispatches in %s" % path)
+        kib_step = sum(t for _, t in per.values()) / nsteps
+        res[counter] = (kib_copy, factor, kib_step, per, kib_step * 1024.0 * factor)
     ndim = sum(1 for v in cfg["n"] if v > 1)
     esize = 4 if args.precision == "f32" else 8
     nc = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
     algo = words_per_cell(ndim) * esize * nc
     traffic = res["FETCH_SIZE"][4] + res["WRITE_SIZE"][4]
+    cmd = "python3 $REPO/bench.py --profile-only --workload %s --precision %s --steps %d" % (
+        args.workload, args.precision, args.steps)
+    disp = ", ".join("%s x%d" % (pattern_label(p), n) for p, (n, _) in res["FETCH_SIZE"][3].items() if n)
     lines = ["# HBM traffic of %s, workload %s" % (kernel, tag), "",
-             "Two rocprofv3 counter passes over `python bench.py --profile-only --workload %s --precision %s "
-             "--steps %d` (the device copy of %d bytes read and %d written, then the fused steps):"
-             % (args.workload, args.precision, args.steps, COPY_BYTES, COPY_BYTES), "",
+             "Two rocprofv3 counter passes over `%s` (the device copy of %d bytes read and %d written, then "
+             "%d steps of the default path: %s):" % (cmd.replace("$REPO/", ""), COPY_BYTES, COPY_BYTES, nsteps, disp),
+             "",
              "    cd /tmp && export TMPDIR=/tmp",
-             "    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d $OUT/fetch -o fetch --output-format csv -- "
-             "python3 $REPO/bench.py --profile-only --workload %s --precision %s --steps %d"
-             % (args.workload, args.precision, args.steps),
-             "    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d $OUT/write -o write --output-format csv -- "
-             "python3 $REPO/bench.py --profile-only --workload %s --precision %s --steps %d"
-             % (args.workload, args.precision, args.steps),
+             "    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d $OUT/fetch -o fetch --output-format csv -- " + cmd,
+             "    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d $OUT/write -o write --output-format csv -- " + cmd,
              "    python3 $REPO/bench.py --workload %s --precision %s --steps %d --pmc-summary "
              "<fetch counter_collection.csv> <write counter_collection.csv>"
              % (args.workload, args.precision, args.steps), "",
-             "| counter | copy kernel KiB | scale (bytes per KiB read) | %s KiB per step (mean of %d) | bytes per step |"
-             % (" + ".join(pattern_label(p) for p in pats), res["FETCH_SIZE"][3]),
+             "| counter | copy kernel KiB | scale (bytes per KiB read) | step kernels KiB per step (all dispatches / %d steps) | bytes per step |"
+             % nsteps,
              "|---|---|---|---|---|"]
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
         kc, fac, ks, _, b = res[counter]
@@ -404,7 +409,8 @@ def trace_summary(args):
              "--trace-summary $OUT/kt/kt_kernel_stats.csv"
              % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps), "",
              "The run times the fused path twice (with and without diagnostics) and the unfused phase "
-             "sequence once; the copy kernel is the bandwidth calibration.", "",
+             "sequence once; the copy kernel is the bandwidth calibration.  In 2D a two-step pass is one "
+             "`k_wave2d_pair` launch with two `k_wave2d` frame launches beside it on a second stream.", "",
              "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in rows:
         name = r["Name"]
@@ -419,6 +425,9 @@ def trace_summary(args):
         dom = [r for r in rows if pat in r["Name"].replace(" ", "")]
         if dom:
             lines.append("- `%s_mean_us = %.2f`" % (pattern_label(pat), float(dom[0]["AverageNs"]) / 1e3))
+            if "pair" in pat:
+                lines.append("- `%s_mean_us_per_step = %.2f` (a launch advances two steps)"
+                             % (pattern_label(pat), float(dom[0]["AverageNs"]) / 2e3))
     lines.append("- `kernel_source_sha256 = %s`" % kernel_source_hash(args.workload))
     path = os.path.join(ROOT, "profiles", "%s_%s_kernel_trace.md" % (kernel, tag))
     with open(path, "w") as f:
@@ -478,7 +487,7 @@ def main():
         axf.tune_reset()
         tuned = axf.tune(cfg, precision=prec, steps=12)
     if args.profile_only:
-        time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, 2, 0)
+        time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, PROFILE_WARMUP, 0)
         print(json.dumps({"profile_only": tag, "steps": args.steps}), flush=True)
         return
 
@@ -495,7 +504,8 @@ def main():
     achieved = algo_bytes / per_launch_s / 1e9
     # the counter summary was taken with the built-in launch shape
     default_shape = DEFAULT_WAVE_SHAPE[args.precision]
-    same_shape = tuned is None or (tuned["chunk"], tuned["prefetch"]) == default_shape
+    same_shape = tuned is None or (tuned["steps_per_pass"], tuned["chunk"], tuned["prefetch"],
+                                   tuned["frame_chunk"]) == default_shape
     traffic = read_traffic(args.workload, tag, kernel) if fused and same_shape else None
     # the unfused phase sequence for comparison
     p_wall, _, p_launches, _, _ = time_path(axf, torch, cfg, prec, axf.PATH_PLAIN, args.plain_steps, 2, 0)
@@ -527,7 +537,9 @@ def main():
             "unit_of_work": "one fused step of the whole grid", "bytes_per_step": algo_bytes,
             "mean_step_ms": round(per_launch_s * 1e3, 5), "steps_timed": args.steps,
             "copy_kernel_GBs": round(copy_gbs, 1),
-            "tuned": None if tuned is None else {"chunk": tuned["chunk"], "prefetch": tuned["prefetch"],
+            "tuned": None if tuned is None else {"steps_per_pass": tuned["steps_per_pass"],
+                                                 "chunk": tuned["chunk"], "prefetch": tuned["prefetch"],
+                                                 "frame_chunk": tuned["frame_chunk"],
                                                  "candidates": tuned["candidates"],
                                                  "best_ms": round(tuned["ms_per_step"], 4),
                                                  "default_ms": round(tuned["default_ms_per_step"], 4)},

@@ -180,18 +180,24 @@ int axf_destroy(axf_run *run);
 int axf_last_step_timing(const axf_run *run, double *ms, int64_t *launches);
 
 /* ------------------------------------------------------------ tuning
- * Launch shape of the fused 2D step (rows per wavefront march and prefetch
- * distance), chosen by timing every candidate on a scratch run.  The choice
- * is kept in a process-wide table keyed by dimensionality, precision,
- * boundary kinds and the power-of-two size class of the grid; runs and
- * batches created afterwards with a matching key use it.  Configurations
- * without a fused 2D path report AXF_PATH_PLAIN and keep their launches.
+ * Launch shape of the fused 2D step, chosen by timing every candidate on a
+ * scratch run: one step per pass (rows per wavefront march, prefetch
+ * distance) or two steps per pass (rows per interior wavefront, rows per
+ * frame wavefront, prefetch distance).  The best shape of each kind is kept
+ * in a process-wide table keyed by dimensionality, precision, boundary kinds
+ * and the power-of-two size class of the grid, with the faster kind; runs
+ * created afterwards with a matching key use it (batches use the one-step
+ * shape).  Configurations without a fused 2D path report AXF_PATH_PLAIN and
+ * keep their launches.
  */
 typedef struct {
     int32_t path;                /* AXF_PATH_FUSED or AXF_PATH_PLAIN */
-    int32_t chunk;               /* rows per wavefront march (fused 2D) */
+    int32_t chunk;               /* rows per wavefront march (fused 2D; the
+                                    interior of a two-step pass) */
     int32_t prefetch;            /* rows prefetched ahead (fused 2D) */
     int32_t candidates;          /* shapes timed */
+    int32_t steps_per_pass;      /* 2: two-step passes are faster, 1: one step per pass */
+    int32_t frame_chunk;         /* rows per frame wavefront of a two-step pass (0 if 1) */
     double  ms_per_step;         /* best */
     double  default_ms_per_step; /* the built-in default shape */
 } axf_tuning;

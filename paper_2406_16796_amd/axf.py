@@ -68,8 +68,8 @@ class DiagRecord(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("chunk", ctypes.c_int32), ("prefetch", ctypes.c_int32),
-                ("candidates", ctypes.c_int32), ("ms_per_step", ctypes.c_double),
-                ("default_ms_per_step", ctypes.c_double)]
+                ("candidates", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32), ("frame_chunk", ctypes.c_int32),
+                ("ms_per_step", ctypes.c_double), ("default_ms_per_step", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):

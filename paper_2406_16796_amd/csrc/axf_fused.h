@@ -38,6 +38,8 @@ hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s
 // for the pass.
 template <typename T>
 bool wave2d_pair_available(const RunK<T>& h, int ci, int cf);
+// built-in prefetch distance of the interior march (one or two steps per pass)
+int wave2d_default_pd(bool f64, bool pair);
 template <typename T>
 hipError_t launch_wave2d_pair(const RunK<T> *rk, const RunK<T>& h, long step, int ci, int cf, int pd, hipStream_t st,
                               const WaveStreams *ws);

@@ -77,8 +77,14 @@ bool run_wave2d(const Run *R);
 int run_wave_chunk(const Run *R);
 // rows per interior and frame wavefront of the two-step pass
 void run_pair_shape(const Run *R, int *ci, int *cf);
-// tuned 2D wavefront shape for a configuration, if one was recorded
-bool tuned_shape(const axf_config *c, int *chunk, int *pd);
+// tuned 2D wavefront shapes for a configuration, if recorded: the best one-step
+// shape, the best two-step shape and whether two-step passes are faster
+struct TunedShape {
+    int chunk = 0, pd = 0;
+    bool pair = true;
+    int pair_ci = 0, pair_cf = 0, pair_pd = 0;
+};
+bool tuned_shape(const axf_config *c, TunedShape *out);
 int run_diag_now(Run *R, axf_diag_record *out);
 void run_release(Run *R);
 bool fused_supported(const axf_config *c);

@@ -496,7 +496,15 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     R->stream = stream;
     if (cfg->path == AXF_PATH_FUSED && !fused_supported(cfg))
         return fail(AXF_EINVAL, "the fused path needs ndim >= 2 and a periodic axion on every periodic EM axis");
-    tuned_shape(cfg, &R->chunk, &R->pd);
+    TunedShape ts;
+    if (tuned_shape(cfg, &ts)) {
+        R->chunk = ts.chunk;
+        R->pd = ts.pd;
+        R->pair = ts.pair;
+        R->pair_ci = ts.pair_ci;
+        R->pair_cf = ts.pair_cf;
+        R->pair_pd = ts.pair_pd;
+    }
     if (const char *ch = getenv("AXF_FUSED_CHUNK")) R->chunk = atoi(ch);
     if (const char *pd = getenv("AXF_WAVE_PD")) R->pd = atoi(pd);
     if (const char *lm = getenv("AXF_LDS_MARCH")) R->lds_march = lm[0] == '1';
@@ -550,7 +558,7 @@ int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 8; }
 void run_pair_shape(const Run *R, int *ci, int *cf)
 {
     *cf = R->pair_cf > 0 ? R->pair_cf : 8;
-    *ci = R->pair_ci > 0 ? R->pair_ci : 16;
+    *ci = R->pair_ci > 0 ? R->pair_ci : 8;
 }
 
 int run_step(Run *R, int64_t nsteps)
@@ -777,15 +785,14 @@ static TuneKey tune_key(const axf_config *c)
 }
 
 static std::mutex g_tune_mu;
-static std::map<TuneKey, std::pair<int, int>> g_tune;
+static std::map<TuneKey, TunedShape> g_tune;
 
-bool tuned_shape(const axf_config *c, int *chunk, int *pd)
+bool tuned_shape(const axf_config *c, TunedShape *out)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(c));
     if (it == g_tune.end()) return false;
-    *chunk = it->second.first;
-    *pd = it->second.second;
+    *out = it->second;
     return true;
 }
 
@@ -832,15 +839,26 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
     hipStream_t st = (hipStream_t)stream;
     axf_config c = *cfg;
     c.diag_every = 0;
-    const int shapes[][2] = {{8, 1}, {8, 2}, {8, 3}, {12, 3}, {16, 2}, {16, 3}, {24, 3}, {32, 3}};
-    double best = 1e300;
-    int best_chunk = 0, best_pd = 0;
-    auto time_shape = [&](int chunk, int pd, double *ms) -> int {
+    // one step per pass: rows per march, prefetch distance
+    const int singles[][2] = {{8, 1}, {8, 2}, {8, 3}, {12, 3}, {16, 2}, {16, 3}, {24, 3}, {32, 3}};
+    // two steps per pass: rows per interior wavefront, per frame wavefront, prefetch distance
+    const int pairs[][3] = {{6, 6, 2}, {8, 8, 2}, {8, 8, 3}, {8, 4, 2}, {12, 6, 2}, {16, 8, 2}, {16, 8, 3}, {24, 8, 2}};
+    // shape < 0: the built-in default (pairs where available)
+    auto time_shape = [&](const TunedShape& sh, bool dflt, double *ms, bool *paired) -> int {
         axf_run R;
         int e = run_init(&R, &c, scratch, bytes, st);
         if (e) return e;
-        R.chunk = chunk;
-        R.pd = pd;
+        if (!dflt) {
+            R.chunk = sh.chunk;
+            R.pd = sh.pd;
+            R.pair = sh.pair;
+            R.pair_ci = sh.pair_ci;
+            R.pair_cf = sh.pair_cf;
+            R.pair_pd = sh.pair_pd;
+        } else {
+            R.chunk = R.pd = R.pair_ci = R.pair_cf = R.pair_pd = 0;
+            R.pair = true;
+        }
         e = run_step(&R, 2);
         if (!e) e = run_step(&R, steps);
         if (!e && hipEventSynchronize(R.ev1) != hipSuccess) e = fail(AXF_EHIP, "tuning run failed");
@@ -848,12 +866,17 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
         if (!e) hipEventElapsedTime(&f, R.ev0, R.ev1);
         *ms = f / steps;
         const bool wave = run_wave2d(&R);
+        int ci = 0, cf = 0;
+        run_pair_shape(&R, &ci, &cf);
+        *paired = wave && R.pair && (c.precision == AXF_F64 ? wave2d_pair_available<double>(R.hd, ci, cf)
+                                                             : wave2d_pair_available<float>(R.hf, ci, cf));
         run_release(&R);
         if (!e && !wave) return 1;    // no wavefront path for this configuration
         return e;
     };
     double dflt = 0.0;
-    rc = time_shape(0, 0, &dflt);
+    bool paired = false, dflt_paired = false;
+    rc = time_shape(TunedShape{}, true, &dflt, &dflt_paired);
     if (rc < 0) return rc;
     out->default_ms_per_step = dflt;
     if (rc == 1) {
@@ -862,23 +885,60 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
         out->candidates = 1;
         return AXF_OK;
     }
-    for (auto& sh : shapes) {
+    TunedShape best{};
+    double best_single = 1e300, best_pair = 1e300;
+    for (auto& sh : singles) {
+        TunedShape t{};
+        t.chunk = sh[0];
+        t.pd = sh[1];
+        t.pair = false;
         double ms = 0.0;
-        rc = time_shape(sh[0], sh[1], &ms);
-        if (rc < 0) return rc;
+        if ((rc = time_shape(t, false, &ms, &paired)) < 0) return rc;
         out->candidates++;
-        if (ms < best) {
-            best = ms;
-            best_chunk = sh[0];
-            best_pd = sh[1];
+        if (ms < best_single) {
+            best_single = ms;
+            best.chunk = t.chunk;
+            best.pd = t.pd;
         }
     }
+    for (auto& sh : pairs) {
+        TunedShape t = best;
+        t.pair = true;
+        t.pair_ci = sh[0];
+        t.pair_cf = sh[1];
+        t.pair_pd = sh[2];
+        double ms = 0.0;
+        if ((rc = time_shape(t, false, &ms, &paired)) < 0) return rc;
+        if (!paired) break;                 // the grid has no interior for a two-step pass
+        out->candidates++;
+        if (ms < best_pair) {
+            best_pair = ms;
+            best.pair_ci = t.pair_ci;
+            best.pair_cf = t.pair_cf;
+            best.pair_pd = t.pair_pd;
+        }
+    }
+    best.pair = best_pair < best_single;
+    // keep the built-in shape unless a candidate beats it clearly (timings of
+    // near-equal shapes differ by noise from one tuning to the next)
+    if ((best.pair ? best_pair : best_single) > 0.98 * dflt) {
+        const bool f64 = c.precision == AXF_F64;
+        best = TunedShape{};
+        best.chunk = 8;
+        best.pd = wave2d_default_pd(f64, false);
+        best.pair = dflt_paired;
+        best.pair_ci = best.pair_cf = 8;
+        best.pair_pd = wave2d_default_pd(f64, true);
+        best_pair = best_single = dflt;
+    }
     out->path = AXF_PATH_FUSED;
-    out->chunk = best_chunk;
-    out->prefetch = best_pd;
-    out->ms_per_step = best;
+    out->steps_per_pass = best.pair ? 2 : 1;
+    out->chunk = best.pair ? best.pair_ci : best.chunk;
+    out->prefetch = best.pair ? best.pair_pd : best.pd;
+    out->frame_chunk = best.pair ? best.pair_cf : 0;
+    out->ms_per_step = best.pair ? best_pair : best_single;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(cfg)] = {best_chunk, best_pd};
+    g_tune[tune_key(cfg)] = best;
     return AXF_OK;
 }
 
