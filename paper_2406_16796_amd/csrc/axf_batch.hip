@@ -36,8 +36,19 @@ namespace axf {
 static long cdiv(long a, long b) { return (a + b - 1) / b; }
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
+// the run takes two-step passes in batched launches (2D wavefront path with
+// an interior for the pass)
+static bool run_pairs(const Run *R)
+{
+    if (!run_wave2d(R) || !R->pair) return false;
+    int ci = 0, cf = 0;
+    run_pair_shape(R, &ci, &cf);
+    return R->cfg.precision == AXF_F64 ? wave2d_pair_available(R->hk<double>(), ci, cf)
+                                       : wave2d_pair_available(R->hk<float>(), ci, cf);
+}
+
 // blocks of each launch kind for one run (the single-run launchers' grids)
-static void run_blocks(const Run *R, bool wave, long blk[kNumKinds])
+static void run_blocks(const Run *R, bool wave, bool pair, long blk[kNumKinds])
 {
     const Layout& L = R->L;
     blk[kVolume] = cdiv(L.npts, 256);
@@ -54,16 +65,24 @@ static void run_blocks(const Run *R, bool wave, long blk[kNumKinds])
         if (R->cfg.precision == AXF_F64) wave2d_blocks(R->hk<double>(), run_wave_chunk(R), &blk[kWave], &blk[kWaveI]);
         else wave2d_blocks(R->hk<float>(), run_wave_chunk(R), &blk[kWave], &blk[kWaveI]);
     }
+    blk[kPair] = blk[kFrameA] = blk[kFrameB] = 0;
+    if (pair) {
+        int ci = 0, cf = 0;
+        run_pair_shape(R, &ci, &cf);
+        if (R->cfg.precision == AXF_F64) wave2d_pair_blocks(R->hk<double>(), ci, cf, &blk[kPair], &blk[kFrameA], &blk[kFrameB]);
+        else wave2d_pair_blocks(R->hk<float>(), ci, cf, &blk[kPair], &blk[kFrameA], &blk[kFrameB]);
+    }
 }
 
 // ------------------------------------------------------------------ engine
 
 struct Group {
     int D = 0;
-    bool f64 = false, wave = false, any_diag = false;
+    bool f64 = false, wave = false, pair = false, any_diag = false;
     std::vector<int> idx;       // runs, sorted by steps this call (descending)
     size_t off = 0;             // first table entry
     int nact = 0;
+    int64_t s = 0;              // steps of this call done
 };
 
 class Engine {
@@ -97,15 +116,18 @@ public:
 
 private:
     template <int D, typename T>
-    int group_step(Group& g, long s, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st);
+    int group_step(Group& g, long s, bool two, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st);
 
     BItem *dev_ = nullptr, *host_ = nullptr;
     size_t cap_ = 0;
     WaveStreams ws_{nullptr, nullptr, nullptr};   // side stream of the 2D frame launches
 };
 
+// one step s of the call, or steps s and s + 1 when two (a two-step pass; the
+// caller takes one only where no diagnostic record and no laser-table fill
+// falls on s + 1)
 template <int D, typename T>
-int Engine::group_step(Group& g, long s, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st)
+int Engine::group_step(Group& g, long s, bool two, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st)
 {
     const BItem *dt = dev_ + g.off, *ht = host_ + g.off;
     const int n = g.nact;
@@ -113,13 +135,14 @@ int Engine::group_step(Group& g, long s, std::vector<int64_t>& nrec, Run *const 
     bool launched = false;
     if constexpr (D == 2) {
         if (g.wave) {
-            hipError_t e = launch_wave2d_batch<T>(dt, ht, n, s, st, &ws_);
+            hipError_t e = two ? launch_wave2d_pair_batch<T>(dt, ht, n, s, st, &ws_)
+                               : launch_wave2d_batch<T>(dt, ht, n, s, st, &ws_);
             if (e != hipSuccess) return hip_fail(e, "batched wavefront step");
             launched = true;
         }
     }
     if (!launched) Plain<D, T>::batch_step(dt, ht, n, s, st);
-    if (!g.any_diag) return AXF_OK;
+    if (two || !g.any_diag) return AXF_OK;
     // diagnostics of the runs whose cadence hits this step
     int hits = 0;
     bool same = true;
@@ -157,16 +180,17 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
         int rc = run_prepare(R);
         if (rc) return rc;
         const int D = R->cfg.ndim;
-        const bool f64 = R->cfg.precision == AXF_F64, wave = run_wave2d(R);
+        const bool f64 = R->cfg.precision == AXF_F64, wave = run_wave2d(R), pair = run_pairs(R);
         Group *g = nullptr;
         for (auto& q : groups)
-            if (q.D == D && q.f64 == f64 && q.wave == wave) g = &q;
+            if (q.D == D && q.f64 == f64 && q.wave == wave && q.pair == pair) g = &q;
         if (!g) {
             groups.emplace_back();
             g = &groups.back();
             g->D = D;
             g->f64 = f64;
             g->wave = wave;
+            g->pair = pair;
         }
         g->idx.push_back(i);
         g->any_diag = g->any_diag || R->cfg.diag_every > 0;
@@ -192,8 +216,9 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
             b.step0 = R->step;
             b.rec0 = R->rec_written;
             b.chunk = run_wave_chunk(R);
+            run_pair_shape(R, &b.pair_ci, &b.pair_cf);
             long nb[kNumKinds];
-            run_blocks(R, g.wave, nb);
+            run_blocks(R, g.wave, g.pair, nb);
             for (int q = 0; q < kNumKinds; q++) acc[q] += nb[q];
         }
         off += g.idx.size() + 1;
@@ -203,20 +228,37 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
     BCHK(hipStreamSynchronize(st));
 
     std::vector<int64_t> nrec(count, 0);
-    for (int64_t s = 0; s < smax; s++) {
+    // a diagnostic record of some active run of the group falls on step s
+    auto diag_at = [&](const Group& g, int64_t s) {
+        if (!g.any_diag) return false;
+        for (int k = 0; k < g.nact; k++) {
+            const Run *R = runs[g.idx[k]];
+            if (R->cfg.diag_every > 0 && (R->step + s) % R->cfg.diag_every == 0) return true;
+        }
+        return false;
+    };
+    for (bool busy = true; busy;) {
+        busy = false;
         for (auto& g : groups) {
+            const int64_t s = g.s;
             while (g.nact > 0 && ns[g.idx[g.nact - 1]] <= s) g.nact--;
             if (g.nact == 0) continue;
+            busy = true;
+            // two steps when every active run takes both, and neither a record
+            // nor a table fill falls on the second
+            const bool two = g.pair && ns[g.idx[g.nact - 1]] > s + 1 && (s + 1) % (kIncLevels - 1) != 0 &&
+                             !diag_at(g, s) && !diag_at(g, s + 1);
             int rc;
             switch (g.D * 2 + (g.f64 ? 1 : 0)) {
-            case 2: rc = group_step<1, float>(g, s, nrec, runs, st); break;
-            case 3: rc = group_step<1, double>(g, s, nrec, runs, st); break;
-            case 4: rc = group_step<2, float>(g, s, nrec, runs, st); break;
-            case 5: rc = group_step<2, double>(g, s, nrec, runs, st); break;
-            case 6: rc = group_step<3, float>(g, s, nrec, runs, st); break;
-            default: rc = group_step<3, double>(g, s, nrec, runs, st); break;
+            case 2: rc = group_step<1, float>(g, s, false, nrec, runs, st); break;
+            case 3: rc = group_step<1, double>(g, s, false, nrec, runs, st); break;
+            case 4: rc = group_step<2, float>(g, s, two, nrec, runs, st); break;
+            case 5: rc = group_step<2, double>(g, s, two, nrec, runs, st); break;
+            case 6: rc = group_step<3, float>(g, s, false, nrec, runs, st); break;
+            default: rc = group_step<3, double>(g, s, false, nrec, runs, st); break;
             }
             if (rc) return rc;
+            g.s += (g.D == 2 && two) ? 2 : 1;
         }
     }
     BCHK(hipGetLastError());

@@ -43,6 +43,14 @@ int wave2d_default_pd(bool f64, bool pair);
 template <typename T>
 hipError_t launch_wave2d_pair(const RunK<T> *rk, const RunK<T>& h, long step, int ci, int cf, int pd, hipStream_t st,
                               const WaveStreams *ws);
+// the two-step pass over the first n runs of a batch table: steps s and
+// s + 1 of the call for every run (each run with a pass interior)
+template <typename T>
+hipError_t launch_wave2d_pair_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st,
+                                    const WaveStreams *ws);
+// workgroups of one run's three launches of a two-step pass
+template <typename T>
+void wave2d_pair_blocks(const RunK<T>& h, int ci, int cf, long *interior, long *frame_a, long *frame_b);
 // workgroups (4 wavefronts each) of one run's two wavefront launches: the
 // frame next to the domain boundary and the interior
 template <typename T>

@@ -1645,6 +1645,68 @@ __global__ void __launch_bounds__(256, INTERIOR ? 1 : 3) kb_wave2d(const BItem *
     }
 }
 
+// batched two-step pass: every active run of the table advances steps s and
+// s + 1 of the call, each with its own pass shape; KIND selects the interior
+// (kPair) or one of the two frame launches (kFrameA: step s, kFrameB: s + 1)
+template <typename T, int KIND>
+__global__ void __launch_bounds__(256, KIND == kPair ? 1 : 3) kb_wave2d_pair(const BItem *__restrict__ it, int n, long s)
+{
+    const long b = KIND == kPair ? xcd_band(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+    const int i = find_item<KIND>(it, n, b);
+    const RunK<T> *rp = uniform_desc<RunK<T>>(it[i].rk);
+    const int cf = it[i].pair_cf;
+    const WavePair wp = wave2d_split_pair(*rp, it[i].pair_ci, cf);
+    const long gw = (b - it[i].blk[KIND]) * 4L + wave_in_block();
+    const long step = it[i].step0 + s;
+    if (KIND == kPair) {
+        if (gw >= wp.in.interior()) return;
+        const int ni = wp.in.sx1 - wp.in.sx0;
+        wave2d_pair_body<T, sizeof(T) == 8 ? 3 : 2>(rp, step, wp, wp.in.sx0 + (int)(gw % ni), wp.in.cy0 + (int)(gw / ni));
+    } else {
+        const WaveSplit& w = KIND == kFrameA ? wp.fa : wp.fb;
+        if (gw >= w.edge()) return;
+        int seg, ch;
+        wave2d_edge_item(w, gw, seg, ch);
+        wave2d_body<T, false, 1>(rp, step + (KIND == kFrameB ? 1 : 0), seg, ch, w.nch, cf, w.wid);
+    }
+}
+
+template <typename T>
+void wave2d_pair_blocks(const RunK<T>& h, int ci, int cf, long *interior, long *frame_a, long *frame_b)
+{
+    const WavePair wp = wave2d_split_pair(h, ci, cf);
+    *interior = (wp.in.interior() + 3) / 4;
+    *frame_a = (wp.fa.edge() + 3) / 4;
+    *frame_b = (wp.fb.edge() + 3) / 4;
+}
+template void wave2d_pair_blocks<float>(const RunK<float>&, int, int, long *, long *, long *);
+template void wave2d_pair_blocks<double>(const RunK<double>&, int, int, long *, long *, long *);
+
+template <typename T>
+hipError_t launch_wave2d_pair_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st,
+                                    const WaveStreams *ws)
+{
+    const unsigned ni = (unsigned)host[n].blk[kPair], na = (unsigned)host[n].blk[kFrameA];
+    const unsigned nb = (unsigned)host[n].blk[kFrameB];
+    const bool fork = ws && ws->side;
+    hipStream_t se = st;
+    if (fork) {
+        hipEventRecord(ws->fork, st);
+        hipStreamWaitEvent(ws->side, ws->fork, 0);
+        se = ws->side;
+    }
+    if (na > 0) hipLaunchKernelGGL((kb_wave2d_pair<T, kFrameA>), dim3(na), dim3(256), 0, se, it, n, s);
+    if (ni > 0) hipLaunchKernelGGL((kb_wave2d_pair<T, kPair>), dim3(ni), dim3(256), 0, st, it, n, s);
+    if (nb > 0) hipLaunchKernelGGL((kb_wave2d_pair<T, kFrameB>), dim3(nb), dim3(256), 0, se, it, n, s);
+    if (fork) {
+        hipEventRecord(ws->join, ws->side);
+        hipStreamWaitEvent(st, ws->join, 0);
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_wave2d_pair_batch<float>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);
+template hipError_t launch_wave2d_pair_batch<double>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);
+
 template <typename T>
 void wave2d_blocks(const RunK<T>& h, int chunk, long *edge_blocks, long *interior_blocks)
 {

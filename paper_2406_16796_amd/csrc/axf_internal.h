@@ -103,13 +103,19 @@ __host__ __device__ inline long round_up(long v, long m) { return (v + m - 1) / 
 // table sorted by remaining steps; blk[K] is the first block of the run in
 // launches of kind K, and entry n holds the totals.  Every run computes exactly
 // what its own single-run launch would.
-enum BlockKind { kVolume = 0, kFace = 1, kLaser = 2, kWave = 3, kWaveI = 4, kNumKinds = 5 };
+enum BlockKind {
+    kVolume = 0, kFace, kLaser, kWave, kWaveI,
+    kPair, kFrameA, kFrameB,           // two-step pass: interior, frames of steps n and n + 1
+    kNumKinds
+};
 struct BItem {
     const void *rk;     // the run's RunK<T> (device)
     long step0;         // the run's step counter at the first step of the call
     long rec0;          // diagnostic records written before the call
     long blk[kNumKinds];
-    int chunk;          // rows per wavefront march (fused 2D)
+    int chunk;          // rows per wavefront march (fused 2D, one step per pass)
+    int pair_ci;        // rows per interior / frame wavefront of a two-step pass
+    int pair_cf;
     int pad;
 };
 

@@ -109,3 +109,25 @@ def test_pair_matches_oracle(axf, monkeypatch):
         scale = s0 if k < 6 else (s1 if k < 12 else sp)
         err = float(np.abs(run.read(nm) - ora.field(nm)).max())
         assert err <= 1e-10 * scale, (nm, err, scale)
+
+
+def test_batched_pairs_equal_alone(axf, monkeypatch):
+    """A batch of grids with a pass interior (different sizes, boundaries and
+    diagnostic cadences, uneven step counts) takes two-step passes in its
+    batched launches; every run ends bit-identical to the same run alone."""
+    cfgs = [grid_2d(301, 213, W.AX_PML, seed=1), grid_2d(420, 331, W.AX_OUTFLOW, seed=2),
+            grid_2d(260, 300, W.AX_PERIODIC, seed=3), grid_2d(333, 257, W.AX_REFLECT, seed=4)]
+    for c, de in zip(cfgs, (0, 7, 10, 0)):
+        c["diag_every"] = de
+    counts = [[33, 40, 17, 0], [1, 28, 44, 51]]
+    batch = axf.Batch(cfgs, precision=axf.F32)
+    for c in counts:
+        batch.step(c)
+    for i, cfg in enumerate(cfgs):
+        run = axf.Run(cfg, precision=axf.F32)
+        for c in counts:
+            if c[i]:
+                run.step(c[i])
+        assert batch.runs[i].steps_done == run.steps_done
+        assert_same(batch.runs[i], run, "batched run %d" % i)
+    batch.close()
