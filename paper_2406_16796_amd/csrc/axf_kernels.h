@@ -21,7 +21,6 @@ struct Plain {
     static void diag(const RunK<T> *rk, const RunK<T>& h, long step, int slot, hipStream_t st);
     // semi-fused step: E0 with the axion current, B with the axion update
     static void e0c(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
-    static void bphi(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
     // the semi-fused step's launches (E0+C, E1, Mur, B, axion) on 3D tile walks
     // of tz planes per workgroup (0: default)
     static void tiled_step(const RunK<T> *rk, const RunK<T>& h, long step, int tz, hipStream_t st);

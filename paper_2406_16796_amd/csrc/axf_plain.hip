@@ -323,9 +323,6 @@ __device__ __forceinline__ void b_body(const RunK<T>& r, long bx, long step)
     b_at<D, T>(r, i, j, k, step);
 }
 
-// phi^{n+3/2}: leapfrog of the Klein-Gordon equation with source g E0.B0 at
-// t_{n+1/2} (Sec. II.C, eq. update_axion), in the damped form of the PML
-// layer (Sec. II.D) where sigma > 0, then the ghosts of the new level.
 // coordinates one step up along axis d (wrapped on a periodic axis)
 template <typename T>
 __device__ __forceinline__ void coord_up(const RunK<T>& r, int d, int& i, int& j, int& k)
@@ -343,37 +340,10 @@ __device__ __forceinline__ T e0new_at(const RunK<T>& r, int so, int c, int i, in
     return r.E0[so][c][id] + T(1) * curl_B<D, 0>(r, r.B0[so], c, i, j, k, id);
 }
 
-// B0^{n+1} at edge point (i,j,k): the expression the B update stores
+// phi^{n+3/2}: leapfrog of the Klein-Gordon equation with source g E0.B0 at
+// t_{n+1/2} (Sec. II.C, eq. update_axion), in the damped form of the PML
+// layer (Sec. II.D) where sigma > 0, then the ghosts of the new level.
 template <int D, typename T>
-__device__ __forceinline__ T b0new_at(const RunK<T>& r, int so, int sn, int c, int i, int j, int k)
-{
-    return r.B0[so][c][lin(r, i, j, k)] - curl_E<D, 0>(r, sn, sn, c, i, j, k);
-}
-
-// centre_B of B0^{n+1} from recomputed edge values (same points, same order)
-template <int D, typename T>
-__device__ __forceinline__ T centre_B0new(const RunK<T>& r, int so, int sn, int c, int i, int j, int k)
-{
-    if (!actB<D, 0>(c)) return T(0);
-    const int a = c == 0 ? 1 : 0, b = c == 2 ? 1 : 2;
-    const bool ua = a < D, ub = b < D;
-    const T p00 = b0new_at<D, T>(r, so, sn, c, i, j, k);
-    if (!ua && !ub) return p00;
-    int ia = i, ja = j, ka = k;
-    coord_up(r, a, ia, ja, ka);
-    const T pa = b0new_at<D, T>(r, so, sn, c, ia, ja, ka);
-    if (!ub) return r.half * (p00 + pa);
-    int ib = i, jb = j, kb = k;
-    coord_up(r, b, ib, jb, kb);
-    int iab = ia, jab = ja, kab = ka;
-    coord_up(r, b, iab, jab, kab);
-    const T pb = b0new_at<D, T>(r, so, sn, c, ib, jb, kb), pab = b0new_at<D, T>(r, so, sn, c, iab, jab, kab);
-    return T(0.25) * ((p00 + pa) + (pb + pab));
-}
-
-// RECOMPUTE: B0^{n+1} at the four edges around the centre is recomputed
-// instead of read (the axion update then runs in the same launch as B)
-template <int D, typename T, bool RECOMPUTE = false>
 __device__ __forceinline__ void phi_at(const RunK<T>& r, int i, int j, int k, long step)
 {
     if (!in_cell(r, i, j, k)) return;
@@ -385,7 +355,7 @@ __device__ __forceinline__ void phi_at(const RunK<T>& r, int i, int j, int k, lo
     for (int c = 0; c < 3; c++) {
         e[c] = actE0<D>(c) ? centre_E<D>(r, r.E0[sn][c], c, i, j, k, id) : T(0);
         T bo = centre_B<D, 0>(r, r.B0[so], c, i, j, k, id);
-        T bn = RECOMPUTE ? centre_B0new<D, T>(r, so, sn, c, i, j, k) : centre_B<D, 0>(r, r.B0[sn], c, i, j, k, id);
+        T bn = centre_B<D, 0>(r, r.B0[sn], c, i, j, k, id);
         b[c] = r.half * (bo + bn) + bext_at(r, c, i);
     }
     T sax = r.gax * (e[0] * b[0] + e[1] * b[1] + e[2] * b[2]);
@@ -423,12 +393,12 @@ __device__ __forceinline__ void phi_at(const RunK<T>& r, int i, int j, int k, lo
     }
 }
 
-template <int D, typename T, bool RECOMPUTE = false>
+template <int D, typename T>
 __device__ __forceinline__ void phi_body(const RunK<T>& r, long bx, long step)
 {
     int i, j, k;
     if (!decompose(r, bx * 256 + threadIdx.x, i, j, k)) return;
-    phi_at<D, T, RECOMPUTE>(r, i, j, k, step);
+    phi_at<D, T>(r, i, j, k, step);
 }
 
 // initial axion levels at t = -dt/2 (slot 0) and +dt/2 (slot 1) from the packet,
@@ -658,18 +628,11 @@ __global__ void __launch_bounds__(256) k_diag_final(const RunK<T> *__restrict__ 
     diag_final_body<T>(*rp, step, slot);
 }
 
-// merged phases of the semi-fused step (E0 with C; B with the axion)
+// merged phase of the semi-fused step: E0 with the axion current
 template <int D, typename T>
 __global__ void __launch_bounds__(256) k_e0c(const RunK<T> *__restrict__ rp, long step)
 {
     e0c_body<D, T>(*rp, blockIdx.x, step);
-}
-
-template <int D, typename T>
-__global__ void __launch_bounds__(256) k_bphi(const RunK<T> *__restrict__ rp, long step)
-{
-    b_body<D, T>(*rp, blockIdx.x, step);
-    phi_body<D, T, true>(*rp, blockIdx.x, step);
 }
 
 // ------------------------------------------------------ 3D tiled launches
@@ -854,12 +817,6 @@ template <int D, typename T>
 void Plain<D, T>::e0c(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st)
 {
     hipLaunchKernelGGL((k_e0c<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
-}
-
-template <int D, typename T>
-void Plain<D, T>::bphi(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_bphi<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
 }
 
 template <int D, typename T>
