@@ -2,12 +2,13 @@
 // server.
 //
 // Both sit on one stepping engine.  The engine groups runs by the kernels they
-// share: dimensionality, precision, and the 2D wavefront kernel vs the unfused
-// phase sequence.  Each group's runs are sorted by remaining steps, so the runs
-// still active at a step are a prefix of the group's table.  One step is then
-// one launch per kernel kind and group, whatever the number of runs: the
-// wavefront kernel, or the six unfused phases; the laser-table fill every
-// 16 steps; the diagnostics at the runs' cadence.  Every block of a batched
+// share: dimensionality, precision, the 2D wavefront kernels (and whether the
+// grid has an interior for the two-step pass) vs the phase sequence.  Each
+// group's runs are sorted by remaining steps, so the runs still active at a
+// step are a prefix of the group's table.  One step (or two-step pass) is then
+// one launch per kernel kind and group, whatever the number of runs: the 2D
+// wavefront launches, or the six unfused phases (1D, 3D); the laser-table fill
+// every 16 steps; the diagnostics at the runs' cadence.  Every block of a batched
 // launch executes its run's own single-run body with the run's own step
 // counter, so a run's result is bit-identical alone and in any mix.
 #include <algorithm>
