@@ -353,8 +353,15 @@ static void steps_semi(Run *R, int64_t nsteps)
     const RunK<T>& h = R->hk<T>();
     const RunK<T> *rk = R->rk<T>();
     hipStream_t st = R->stream;
-    const char *te = getenv("AXF_TILED");         // 0: one thread per point instead of tile walks
-    const bool tiled = D == 3 && !(te && te[0] == '0');
+    // tile walks (64-column tiles) unless the last tile column is mostly empty:
+    // on a Mur x axis (n + 1 node columns) small grids waste up to a third of
+    // the tiles, and one thread per point is faster there (measured: 128^3
+    // and 192^3 12.6 / 12.9 Gcell/s untiled against 10.4 / 10.2 tiled; from
+    // 256^3 on the tiles win).  AXF_TILED=0/1 forces the choice.
+    const char *te = getenv("AXF_TILED");
+    const long tiles_x = (h.nn[0] + 63) / 64 * 64;
+    const bool waste_ok = (tiles_x - h.nn[0]) * 5 <= tiles_x;
+    const bool tiled = D == 3 && (te ? te[0] == '1' : waste_ok);
     for (int64_t it = 0; it < nsteps; it++) {
         long s = R->step;
         int so = em_slot(s), sn = em_slot(s + 1);

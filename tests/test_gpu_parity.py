@@ -196,19 +196,24 @@ def wide_2d(ax_bc, n=(300, 170)):
 
 
 @pytest.mark.parametrize("kind", ["2d_out", "2d_pml", "2d_ref", "2d_wide_pml", "2d_wide_out", "2d_lds", "3d",
-                                  "3d_lds"])
+                                  "3d_tiled", "3d_lds"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_fused_equals_plain_bitwise(axf, kind, prec, monkeypatch):
     """The fused paths evaluate the same point formulas in the same order as
     the unfused kernels (no FP contraction), so the states agree bit for bit,
     boundaries included: the 2D wavefront kernels (the wide grids run both the
     interior and the boundary-frame kernels), the 3D semi-fused launches, and
-    the LDS-marching kernels (2d_lds, 3d_lds)."""
+    the LDS-marching kernels (2d_lds, 3d_lds).  The small 3D grid takes one
+    thread per point by default; 3d_tiled forces the tile walks."""
     if kind.endswith("_lds"):
         monkeypatch.setenv("AXF_LDS_MARCH", "1")
+    if kind == "3d_tiled":
+        monkeypatch.setenv("AXF_TILED", "1")
+    else:
+        monkeypatch.delenv("AXF_TILED", raising=False)
     cfg = {"2d_out": small_2d(W.AX_OUTFLOW), "2d_pml": small_2d(W.AX_PML), "2d_ref": small_2d(W.AX_REFLECT),
            "2d_wide_pml": wide_2d(W.AX_PML), "2d_wide_out": wide_2d(W.AX_OUTFLOW), "2d_lds": small_2d(W.AX_PML),
-           "3d": small_3d(), "3d_lds": small_3d()}[kind]
+           "3d": small_3d(), "3d_tiled": small_3d(), "3d_lds": small_3d()}[kind]
     p = axf.F32 if prec == "f32" else axf.F64
     runs = []
     for path in (axf.PATH_PLAIN, axf.PATH_FUSED):
