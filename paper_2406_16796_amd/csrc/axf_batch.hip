@@ -7,8 +7,9 @@
 // group's runs are sorted by remaining steps, so the runs still active at a
 // step are a prefix of the group's table.  One step (or two-step pass) is then
 // one launch per kernel kind and group, whatever the number of runs: the 2D
-// wavefront launches, or the six unfused phases (1D, 3D); the laser-table fill
-// every 16 steps; the diagnostics at the runs' cadence.  Every block of a batched
+// wavefront launches, the six unfused phases (1D) or five with E0 and the
+// axion current merged (3D); the laser-table fill every 16 steps; the
+// diagnostics at the runs' cadence.  Every block of a batched
 // launch executes its run's own single-run body with the run's own step
 // counter, so a run's result is bit-identical alone and in any mix.
 #include <algorithm>

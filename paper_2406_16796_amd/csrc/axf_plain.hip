@@ -669,7 +669,7 @@ __global__ void __launch_bounds__(256) k3_tile(const RunK<T> *__restrict__ rp, l
 // run's own step counter (step0 + s), so each run's arithmetic and block
 // partition are those of its single-run launch.
 
-enum BatchPhase { kPhE0 = 0, kPhC, kPhE1, kPhB, kPhPhi, kPhDiag };
+enum BatchPhase { kPhE0 = 0, kPhC, kPhE0C, kPhE1, kPhB, kPhPhi, kPhDiag };
 
 template <int D, typename T, int PH>
 __device__ __forceinline__ void kb_volume_run(const RunK<T> *__restrict__ rp, long bx, long step)
@@ -678,6 +678,7 @@ __device__ __forceinline__ void kb_volume_run(const RunK<T> *__restrict__ rp, lo
     const int so = em_slot(step), sn = em_slot(step + 1), la = phi_slot(step), lb = phi_slot(step + 1);
     if (PH == kPhE0) e0_body<D, T>(r, bx, so, so, sn, T(1));
     else if (PH == kPhC) c_body<D, T>(r, bx, la, lb, so, sn, so, 0);
+    else if (PH == kPhE0C) e0c_body<D, T>(r, bx, step);
     else if (PH == kPhE1) e1_body<D, T>(r, bx, so, so, sn, T(1));
     else if (PH == kPhB) b_body<D, T>(r, bx, step);
     else if (PH == kPhPhi) phi_body<D, T>(r, bx, step);
@@ -837,8 +838,13 @@ void Plain<D, T>::batch_step(const BItem *it, const BItem *host, int n, long s, 
 {
     const unsigned nv = (unsigned)host[n].blk[kVolume], nf = (unsigned)host[n].blk[kFace];
     if (nv == 0) return;
-    hipLaunchKernelGGL((kb_volume<D, T, kPhE0>), dim3(nv), dim3(256), 0, st, it, n, s);
-    hipLaunchKernelGGL((kb_volume<D, T, kPhC>), dim3(nv), dim3(256), 0, st, it, n, s);
+    if (D == 3) {
+        // E0 with the axion current in one launch, as in a single 3D run
+        hipLaunchKernelGGL((kb_volume<D, T, kPhE0C>), dim3(nv), dim3(256), 0, st, it, n, s);
+    } else {
+        hipLaunchKernelGGL((kb_volume<D, T, kPhE0>), dim3(nv), dim3(256), 0, st, it, n, s);
+        hipLaunchKernelGGL((kb_volume<D, T, kPhC>), dim3(nv), dim3(256), 0, st, it, n, s);
+    }
     hipLaunchKernelGGL((kb_volume<D, T, kPhE1>), dim3(nv), dim3(256), 0, st, it, n, s);
     if (nf > 0) hipLaunchKernelGGL((kb_mur<D, T>), dim3(nf, 2 * D), dim3(256), 0, st, it, n, s);
     hipLaunchKernelGGL((kb_volume<D, T, kPhB>), dim3(nv), dim3(256), 0, st, it, n, s);
