@@ -197,6 +197,23 @@ def leg_3d(axf, torch, steps=10):
     return out
 
 
+def leg_other_precision(axf, torch, name, precision, steps=200):
+    """The same 2D workload in the other storage precision (the FP32 vs FP64
+    comparison of the 4096^2 configuration): the fused step alone."""
+    cfg = workload(name)
+    prec = axf.F64 if precision == "f64" else axf.F32
+    esize = 8 if precision == "f64" else 4
+    nc = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
+    ndim = sum(1 for v in cfg["n"] if v > 1)
+    _, ms, _, _, fused = time_path(axf, torch, cfg, prec, axf.PATH_AUTO, steps, 2, 0)
+    step_s = ms / 1e3 / steps
+    achieved = words_per_cell(ndim) * esize * nc / step_s / 1e9
+    return {"workload": workload_tag(cfg, precision), "Gcell_s": round(nc / step_s / 1e9, 3),
+            "ms_per_step": round(step_s * 1e3, 4),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "path_fused": fused}}
+
+
 def scan_leg(axf, torch, steps_scale, count=512, tune=True):
     """Batched parameter scan (512 runs: 1D 1k-64k cells, 2D 256^2-1024^2, step
     counts scaled by steps_scale) against the same runs launched one by one."""
@@ -550,6 +567,9 @@ def main():
                   "fused_speedup": round(value / plain_value, 3) if plain_value > 0 else None},
         "diag": {"step": rec["step"], "p_gen": rec["p_gen"], "p_conv": rec["p_conv"], "finite": rec["finite"]},
     }
+    if args.workload == "2d":
+        other = "f64" if args.precision == "f32" else "f32"
+        line[other] = leg_other_precision(axf, torch, "2d", other)
     if not args.no_3d and args.workload != "3d":
         line["3d"] = leg_3d(axf, torch)
     if not args.no_scan:

@@ -131,3 +131,14 @@ def test_batched_pairs_equal_alone(axf, monkeypatch):
         assert batch.runs[i].steps_done == run.steps_done
         assert_same(batch.runs[i], run, "batched run %d" % i)
     batch.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(236, 36), (237, 43), (295, 37)])
+def test_pair_smallest_interiors_bitwise(axf, monkeypatch, nx, ny):
+    """Grids at the edge of having an interior for the pass (a one-segment,
+    one-chunk core) and rows that leave a partial last chunk."""
+    cfg = grid_2d(nx, ny, W.AX_OUTFLOW, seed=nx)
+    two, n2 = run_steps(axf, monkeypatch, cfg, axf.F32, [24], True)
+    one, _ = run_steps(axf, monkeypatch, cfg, axf.F32, [24], False)
+    assert n2 == 12, n2
+    assert_same(two, one, "%dx%d" % (nx, ny))
