@@ -30,6 +30,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -39,7 +40,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # built-in shape of the 2D wavefront step: (steps per pass, rows per interior
 # wavefront, prefetch distance, rows per frame wavefront)
-DEFAULT_WAVE_SHAPE = {"f32": (2, 8, 2, 8), "f64": (2, 8, 3, 8)}
+DEFAULT_WAVE_SHAPE = {"f32": (3, 12, 2, 6), "f64": (3, 12, 1, 6)}
 COPY_BYTES = 1 << 30
 CSRC = "paper_2406_16796_amd/csrc/"
 COMMON_SOURCES = [CSRC + "axf_stencil.h", CSRC + "axf_internal.h", "paper_2406_16796_amd/build.py"]
@@ -47,7 +48,7 @@ COMMON_SOURCES = [CSRC + "axf_stencil.h", CSRC + "axf_internal.h", "paper_2406_1
 # one step's launches ({T} = float or double), sources those kernels are built
 # from)
 WORKLOADS = {
-    "2d": ("gaussian_2d", "k_wave2d", ["k_wave2d_pair<{T}", "k_wave2d_int<{T}", "k_wave2d<{T}"],
+    "2d": ("gaussian_2d", "k_wave2d", ["k_wave2d_pass<{T}", "k_wave2d_int<{T}", "k_wave2d<{T}"],
            [CSRC + "axf_fused.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
     "3d": ("focused_3d", "k3_tile", ["k3_tile<3,{T},0>", "k3_tile<3,{T},1>", "k_mur<3,{T}>",
                                      "k3_tile<3,{T},2>", "k3_tile<3,{T},3>"],
@@ -426,8 +427,9 @@ def trace_summary(args):
              "--trace-summary $OUT/kt/kt_kernel_stats.csv"
              % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps), "",
              "The run times the fused path twice (with and without diagnostics) and the unfused phase "
-             "sequence once; the copy kernel is the bandwidth calibration.  In 2D a two-step pass is one "
-             "`k_wave2d_pair` launch with two `k_wave2d` frame launches beside it on a second stream.", "",
+             "sequence once; the copy kernel is the bandwidth calibration.  In 2D a pass of NS steps is one "
+             "`k_wave2d_pass<T, PD, NS>` launch with NS `k_wave2d` frame launches beside it on a second "
+             "stream.", "",
              "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in rows:
         name = r["Name"]
@@ -442,9 +444,11 @@ def trace_summary(args):
         dom = [r for r in rows if pat in r["Name"].replace(" ", "")]
         if dom:
             lines.append("- `%s_mean_us = %.2f`" % (pattern_label(pat), float(dom[0]["AverageNs"]) / 1e3))
-            if "pair" in pat:
-                lines.append("- `%s_mean_us_per_step = %.2f` (a launch advances two steps)"
-                             % (pattern_label(pat), float(dom[0]["AverageNs"]) / 2e3))
+            m = re.search(r"k_wave2d_pass<\w+,\d+,(\d+)>", dom[0]["Name"].replace(" ", ""))
+            if m:
+                ns = int(m.group(1))
+                lines.append("- `%s_mean_us_per_step = %.2f` (a launch advances %d steps)"
+                             % (pattern_label(pat), float(dom[0]["AverageNs"]) / 1e3 / ns, ns))
     lines.append("- `kernel_source_sha256 = %s`" % kernel_source_hash(args.workload))
     path = os.path.join(ROOT, "profiles", "%s_%s_kernel_trace.md" % (kernel, tag))
     with open(path, "w") as f:

@@ -45,8 +45,8 @@ static bool run_pairs(const Run *R)
     if (!run_wave2d(R) || !R->pair) return false;
     int ci = 0, cf = 0;
     run_pair_shape(R, &ci, &cf);
-    return R->cfg.precision == AXF_F64 ? wave2d_pair_available(R->hk<double>(), ci, cf)
-                                       : wave2d_pair_available(R->hk<float>(), ci, cf);
+    return R->cfg.precision == AXF_F64 ? wave2d_pass_available(R->hk<double>(), 2, ci, cf)
+                                       : wave2d_pass_available(R->hk<float>(), 2, ci, cf);
 }
 
 // blocks of each launch kind for one run (the single-run launchers' grids)

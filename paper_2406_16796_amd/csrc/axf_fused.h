@@ -32,17 +32,15 @@ hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chu
 template <typename T>
 hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st,
                                const WaveStreams *ws);
-// Two steps n, n + 1 in one pass over the interior (temporal blocking, ci rows
-// per wavefront) with the two one-step frame launches around it (cf rows per
-// wavefront, ci a multiple of cf); available when the grid has an interior
-// for the pass.
+// NS steps per pass (NS = 2 or 3): the interior advanced NS steps in one
+// launch, the frame in NS one-step launches beside it
 template <typename T>
-bool wave2d_pair_available(const RunK<T>& h, int ci, int cf);
-// built-in prefetch distance of the interior march (one or two steps per pass)
-int wave2d_default_pd(bool f64, bool pair);
+bool wave2d_pass_available(const RunK<T>& h, int ns, int ci, int cf);
 template <typename T>
-hipError_t launch_wave2d_pair(const RunK<T> *rk, const RunK<T>& h, long step, int ci, int cf, int pd, hipStream_t st,
-                              const WaveStreams *ws);
+hipError_t launch_wave2d_pass(const RunK<T> *rk, const RunK<T>& h, long step, int ns, int ci, int cf, int pd,
+                              hipStream_t st, const WaveStreams *ws);
+// built-in prefetch distance of the interior march for ns steps per pass
+int wave2d_default_pd(bool f64, int ns);
 // the two-step pass over the first n runs of a batch table: steps s and
 // s + 1 of the call for every run (each run with a pass interior)
 template <typename T>

@@ -776,8 +776,7 @@ __device__ __forceinline__ double lane_dn(double v)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-constexpr int kWaveOut = 59;   // output columns per wavefront (one step)
-constexpr int kWaveOut2 = 58;  // ... of the two-step march (lanes 3 .. 60)
+constexpr int kWaveOut = 59;   // output columns per wavefront (one step per pass)
 // prefetch distance (rows ahead) of the interior march, by precision (measured)
 template <typename T> struct WavePD { static constexpr int value = sizeof(T) == 8 ? 2 : 3; };
 
@@ -1210,16 +1209,15 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
     }
 }
 
-// ---------------------------------------------------------------- two steps
+// ------------------------------------------------------ several steps per pass
 //
-// Temporal blocking of the interior march: a wavefront advances its rows two
-// time steps per pass.  Stage 1 is the one-step pipeline on the loaded planes;
-// stage 2 is the same pipeline one row behind, fed from stage 1's registers
-// (its E, B and axion level of step n+1) instead of from memory, so each row
-// of the state is read once and written once per two steps.  Both stages use
-// the point formulas of the one-step interior march in the same order, so the
-// results are the same bits.  Stage 1 is valid on lanes 1 .. 62 and stage 2 on
-// lanes 3 .. 60: the pass owns 58 columns per wavefront.
+// Temporal blocking of the interior march: a wavefront advances its rows NS
+// (2 or 3) time steps per pass.  Stage 0 is the one-step pipeline on the
+// loaded rows; stage k is the same pipeline one row behind stage k - 1, fed
+// from its registers (E, B and the axion level of step n + k) instead of from
+// memory, so each row of the state is read once and written once per NS
+// steps.  Every stage uses the point formulas of the one-step interior march
+// in the same order, so the results are the same bits.
 
 // register windows of one stage along y (suffix = rows behind the newest row t
 // of the stage); the outputs of an advance are at rows t - 1 (E0^{n+1/2},
@@ -1445,68 +1443,92 @@ __device__ __forceinline__ void wave2d_edge_item(const WaveSplit& w, long e, int
     }
 }
 
-// The interior of a two-step pass in units of 58-column segments and `ci`-row
-// chunks, and the two one-step frame launches around it (cf-row chunks, ci a
-// multiple of cf): frame A advances step n on everything but the core of the
-// interior (the interior without its outermost segment and frame chunk on each
-// side), frame B advances step n + 1 on everything but the interior.
-struct WavePair {
-    WaveSplit in, fa, fb;
+template <typename T, int PD>
+__global__ void __launch_bounds__(256) k_wave2d_int(const RunK<T> *__restrict__ rp, long step, WaveSplit w, int chunk)
+{
+    const long gw = xcd_band(blockIdx.x, gridDim.x) * 4L + wave_in_block();
+    if (gw >= w.interior()) return;       // whole wavefronts only: no barriers in this kernel
+    const int ni = w.sx1 - w.sx0;
+    wave2d_body<T, true, PD>(rp, step, w.sx0 + (int)(gw % ni), w.cy0 + (int)(gw / ni), w.nch, chunk);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256, 3) k_wave2d(const RunK<T> *__restrict__ rp, long step, WaveSplit w, int chunk)
+{
+    const long gw = blockIdx.x * 4L + wave_in_block();
+    if (gw >= w.edge()) return;
+    int seg, ch;
+    wave2d_edge_item(w, gw, seg, ch);
+    wave2d_body<T, false, 1>(rp, step, seg, ch, w.nch, chunk, w.wid);
+}
+
+
+// The pass.  Stage k is valid on lanes 2k + 1 .. 62 - 2k (each stage's
+// stencils lose a lane on either side twice), so the pass owns lanes
+// 2 NS - 1 .. 64 - 2 NS: 58 columns per wavefront for two steps, 54 for three.
+// The boundary frame is NS one-step launches in order on the side stream:
+// frame k advances step n + k everywhere but core k, the interior shrunk by
+// NS - 1 - k rings (a ring is one segment and one frame chunk), so frame k + 1
+// finds step n + k + 1 written next to its region; frame NS - 1 leaves out the
+// interior.
+
+__host__ __device__ constexpr int pass_lane0(int ns) { return 2 * ns - 1; }
+__host__ __device__ constexpr int pass_width(int ns) { return 66 - 4 * ns; }
+
+template <int NS>
+struct WavePass {
+    WaveSplit in;                 // the interior, in pass_width columns and ci-row chunks
+    WaveSplit fr[NS];             // frame k (cf-row chunks); its rectangle is core k
     int ci;
-    int ring_y0, ring_y1;                 // rows of the core; the core's phi^{n+3/2}
-                                          // comes from the interior, the rest from frame A
 };
 
-template <typename R>
-__host__ __device__ inline WavePair wave2d_split_pair(const R& h, int ci, int cf)
+template <int NS, typename R>
+__host__ __device__ inline WavePass<NS> wave2d_split_pass(const R& h, int ci, int cf)
 {
-    WavePair p;
+    WavePass<NS> p;
     p.ci = ci;
     WaveSplit& w = p.in;
-    w.wid = kWaveOut2;
-    w.nseg = (h.nn[0] + kWaveOut2 - 1) / kWaveOut2;
+    const int W = pass_width(NS), lo = pass_lane0(NS);
+    w.wid = W;
+    w.nseg = (h.nn[0] + W - 1) / W;
     w.nch = (h.nn[1] + ci - 1) / ci;
     const int mxg = 1 + (h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
     const int myg = 1 + (h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
-    // columns x0 - 3 .. x0 + 60 and rows c0 - 7 .. c0 + ci + 2 (everything the
-    // pass loads or computes) stay at least the margin inside the grid
-    w.sx0 = (mxg + 3 + kWaveOut2 - 1) / kWaveOut2;
-    w.sx1 = (h.n[0] - 1 - mxg - 60) >= 0 ? (h.n[0] - 1 - mxg - 60) / kWaveOut2 + 1 : 0;
-    w.cy0 = (myg + 7 + ci - 1) / ci;
-    w.cy1 = (h.n[1] - 3 - myg - ci) >= 0 ? (h.n[1] - 3 - myg - ci) / ci + 1 : 0;
+    // columns x0 - lo .. x0 - lo + 63 and rows c0 - 3 NS - 1 .. c0 + ci + NS
+    // (everything the pass loads or computes) stay at least the margin inside
+    w.sx0 = (mxg + lo + W - 1) / W;
+    w.sx1 = (h.n[0] - 1 - mxg - (63 - lo)) >= 0 ? (h.n[0] - 1 - mxg - (63 - lo)) / W + 1 : 0;
+    w.cy0 = (myg + 3 * NS + 1 + ci - 1) / ci;
+    w.cy1 = (h.n[1] - 1 - myg - NS - ci) >= 0 ? (h.n[1] - 1 - myg - NS - ci) / ci + 1 : 0;
     const int nchf = (h.nn[1] + cf - 1) / cf, k = ci / cf;
     // the last frame chunk (which runs to the storage end) is never interior
     if (w.cy1 * k > nchf - 1) w.cy1 = (nchf - 1) / k;
-    // a pass needs a core: at least one segment and one frame chunk inside the ring
-    if (w.sx1 - w.sx0 < 3 || (w.cy1 - w.cy0) * k < 3) w.sx0 = w.sx1 = w.cy0 = w.cy1 = 0;
-    p.fb = WaveSplit{w.nseg, nchf, w.sx0, w.sx1, w.cy0 * k, w.cy1 * k, kWaveOut2};
-    p.fa = p.fb;
-    if (w.sx1 > w.sx0) {
-        p.fa.sx0 += 1; p.fa.sx1 -= 1;
-        p.fa.cy0 += 1; p.fa.cy1 -= 1;
+    // the innermost core needs at least one segment and one frame chunk
+    const int need = 2 * (NS - 1) + 1;
+    if (w.sx1 - w.sx0 < need || (w.cy1 - w.cy0) * k < need) w.sx0 = w.sx1 = w.cy0 = w.cy1 = 0;
+    for (int f = 0; f < NS; f++) {
+        const int d = w.sx1 > w.sx0 ? NS - 1 - f : 0;
+        p.fr[f] = WaveSplit{w.nseg, nchf, w.sx0 + d, w.sx1 - d, w.cy0 * k + d, w.cy1 * k - d, W};
     }
-    p.ring_y0 = p.fa.cy0 * cf;
-    p.ring_y1 = p.fa.cy1 * cf;
     return p;
 }
 
-// The wavefront of segment `seg` and chunk `ch` of the interior of a two-step
+// The wavefront of segment `seg` and chunk `ch` of the interior of an NS-step
 // pass: reads E/B of step n and the axion levels n, n + 1; writes E/B of step
-// n + 2, phi^{n+5/2} and, in the core, phi^{n+3/2}.
-template <typename T, int PD>
-__device__ __forceinline__ void wave2d_pair_body(const RunK<T> *__restrict__ rp, long step, const WavePair& wp, int seg,
-                                                 int ch)
+// n + NS, the axion level n + NS + 1 and, in core k, the level n + 2 + k.
+template <typename T, int PD, int NS>
+__device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp, long step, const WavePass<NS>& wp,
+                                                 int seg, int ch, int cf)
 {
     KW<T> r = make_kw(rp);
+    constexpr int lo = pass_lane0(NS), W = pass_width(NS);
     const int lane = threadIdx.x & 63;
-    const int e_rd = em_slot(step), e_wr = em_slot(step + 2);
-    const int la = phi_slot(step), lb = phi_slot(step + 1), l2 = phi_slot(step + 2), l3 = phi_slot(step + 3);
+    const int e_rd = em_slot(step), e_wr = em_slot(step + NS);
+    const int la = phi_slot(step), lb = phi_slot(step + 1);
     const int ci = wp.ci;
-    const int x0 = seg * kWaveOut2, gx = x0 - 3 + lane;
-    const bool own_x = lane >= 3 && lane < 3 + kWaveOut2;
-    const bool core_x = seg >= wp.fa.sx0 && seg < wp.fa.sx1;
-    const int c0 = ch * ci, c1 = c0 + ci, cs = c0 - 3;      // stage 1 starts as if its chunk began at cs
-    const int n0 = r.n[0];
+    const int x0 = seg * W, gx = x0 - lo + lane;
+    const bool own_x = lane >= lo && lane < lo + W;
+    const int c0 = ch * ci, c1 = c0 + ci, cs = c0 - 3 * (NS - 1);   // stage 0 starts as if its chunk began at cs
     const unsigned es = sizeof(T), sxb = (unsigned)r.sx * es;
     const unsigned bx = (unsigned)gx * es;
     unsigned as_l = r.as;
@@ -1541,85 +1563,84 @@ __device__ __forceinline__ void wave2d_pair_body(const RunK<T> *__restrict__ rp,
     };
 
     const T bext0 = bext_at(*rp, 0, gx), bext1 = bext_at(*rp, 1, gx), bext2 = bext_at(*rp, 2, gx);
-    (void)n0;
-    Stage<T> s1, s2;
-    s1.clear();
-    s2.clear();
-    const int t_first = cs - 2, t_last = c1 + 2;
+    // core k of an intermediate level: segments and rows of frame k's rectangle
+    bool core_x[NS];
+    int core_y0[NS], core_y1[NS];
+#pragma unroll
+    for (int k = 0; k < NS; k++) {
+        core_x[k] = seg >= wp.fr[k].sx0 && seg < wp.fr[k].sx1;
+        core_y0[k] = wp.fr[k].cy0 * cf;
+        core_y1[k] = wp.fr[k].cy1 * cf;
+    }
+    Stage<T> sg[NS];
+#pragma unroll
+    for (int k = 0; k < NS; k++) sg[k].clear();
+    const int t_first = cs - 2, t_last = c1 + NS;
 #pragma unroll
     for (int k = 0; k < PD; k++)
         if (t_first + k <= t_last) prefetch(t_first + k, buf[k]);
     constexpr int U = PD == 1 ? 1 : 6;
     for (int t0 = t_first; t0 <= t_last; t0 += U)
 #pragma unroll
-    for (int k = 0; k < U; k++) {
-        const int t = t0 + k;
+    for (int u = 0; u < U; u++) {
+        const int t = t0 + u;
         if (t > t_last) break;
-        Pref& P = buf[k % PD];
+        Pref& P = buf[u % PD];
         asm volatile("" : "+s"(as_l));
         const T b0z = P.b0z, pa = P.pa, pb = P.pb;
         const T b1[3] = {P.b1[0], P.b1[1], P.b1[2]};
         const T e0m[2] = {P.e0m[0], P.e0m[1]};
         const T e1m[3] = {P.e1m[0], P.e1m[1], P.e1m[2]};
         if (t + PD <= t_last) prefetch(t + PD, P);
-        // stage 1: step n, rows t - 1 (E0, B0z) and t - 2 (E1, B1, phi)
-        s1.advance(r, bext0, bext1, bext2, b0z, b1, pa, pb, e0m, e1m, true);
-        const int q2 = t - 2;
-        if (q2 >= c0 && q2 < c1 && q2 >= wp.ring_y0 && q2 < wp.ring_y1 && core_x && own_x)
-            stp(l2, off(q2), s1.pn);
-        // stage 2: step n + 1 one row behind, from stage 1's registers
-        {
-            const T e1in[3] = {s1.e1h_3[0], s1.e1h_3[1], s1.e1h_3[2]};
-            const T e0in[2] = {s1.e0h_2[0], s1.e0h_2[1]};
-            const int q3 = t - 3;
-            const bool full = q3 >= c0 && q3 < c1;
-            s2.advance(r, bext0, bext1, bext2, s1.b0p_1, s1.b1n, s1.pb_2, s1.pn, e0in, e1in, full);
-            if (own_x) {
-                if (q2 >= c0 && q2 < c1) {
-                    const unsigned o = off(q2);
-                    ste(0, 0, o, s2.e0h_1[0]);
-                    ste(0, 1, o, s2.e0h_1[1]);
-                    ste(1, 2, o, s2.b0p_1);
-                }
-                if (full) {
-                    const unsigned o = off(q3);
+        // stage 0: step n on the loaded rows
+        sg[0].advance(r, bext0, bext1, bext2, b0z, b1, pa, pb, e0m, e1m, true);
+        // stage k: step n + k, one row behind stage k - 1, from its registers
+        const int qf = t - NS - 1;              // the last stage's E1, B1, phi row
+        const bool full = qf >= c0 && qf < c1;
 #pragma unroll
-                    for (int c = 0; c < 3; c++) ste(2, c, o, s2.e1h_2[c]);
+        for (int k = 1; k < NS; k++) {
+            const Stage<T>& pv = sg[k - 1];
+            const T e1in[3] = {pv.e1h_3[0], pv.e1h_3[1], pv.e1h_3[2]};
+            const T e0in[2] = {pv.e0h_2[0], pv.e0h_2[1]};
+            sg[k].advance(r, bext0, bext1, bext2, pv.b0p_1, pv.b1n, pv.pb_2, pv.pn, e0in, e1in, k < NS - 1 || full);
+        }
+        if (own_x) {
+            // intermediate axion levels n + 2 + k (k < NS - 1) in core k
 #pragma unroll
-                    for (int c = 0; c < 3; c++) ste(3, c, o, s2.b1n[c]);
-                    stp(l3, o, s2.pn);
-                }
+            for (int k = 0; k < NS - 1; k++) {
+                const int q = t - 2 - k;
+                if (q >= c0 && q < c1 && q >= core_y0[k] && q < core_y1[k] && core_x[k])
+                    stp(phi_slot(step + 2 + k), off(q), sg[k].pn);
+            }
+            // the last stage: E0, B0z of step n + NS at row t - NS; E1, B1 and
+            // the axion level n + NS + 1 at row t - NS - 1
+            const Stage<T>& sl = sg[NS - 1];
+            const int qe = t - NS;
+            if (qe >= c0 && qe < c1) {
+                const unsigned o = off(qe);
+                ste(0, 0, o, sl.e0h_1[0]);
+                ste(0, 1, o, sl.e0h_1[1]);
+                ste(1, 2, o, sl.b0p_1);
+            }
+            if (full) {
+                const unsigned o = off(qf);
+#pragma unroll
+                for (int c = 0; c < 3; c++) ste(2, c, o, sl.e1h_2[c]);
+#pragma unroll
+                for (int c = 0; c < 3; c++) ste(3, c, o, sl.b1n[c]);
+                stp(phi_slot(step + NS + 1), o, sl.pn);
             }
         }
     }
 }
 
-template <typename T, int PD>
-__global__ void __launch_bounds__(256) k_wave2d_int(const RunK<T> *__restrict__ rp, long step, WaveSplit w, int chunk)
-{
-    const long gw = xcd_band(blockIdx.x, gridDim.x) * 4L + wave_in_block();
-    if (gw >= w.interior()) return;       // whole wavefronts only: no barriers in this kernel
-    const int ni = w.sx1 - w.sx0;
-    wave2d_body<T, true, PD>(rp, step, w.sx0 + (int)(gw % ni), w.cy0 + (int)(gw / ni), w.nch, chunk);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256, 3) k_wave2d(const RunK<T> *__restrict__ rp, long step, WaveSplit w, int chunk)
-{
-    const long gw = blockIdx.x * 4L + wave_in_block();
-    if (gw >= w.edge()) return;
-    int seg, ch;
-    wave2d_edge_item(w, gw, seg, ch);
-    wave2d_body<T, false, 1>(rp, step, seg, ch, w.nch, chunk, w.wid);
-}
-
-template <typename T, int PD>
-__global__ void __launch_bounds__(256) k_wave2d_pair(const RunK<T> *__restrict__ rp, long step, WavePair wp)
+template <typename T, int PD, int NS>
+__global__ void __launch_bounds__(256) k_wave2d_pass(const RunK<T> *__restrict__ rp, long step, WavePass<NS> wp, int cf)
 {
     const long gw = xcd_band(blockIdx.x, gridDim.x) * 4L + wave_in_block();
     if (gw >= wp.in.interior()) return;
     const int ni = wp.in.sx1 - wp.in.sx0;
-    wave2d_pair_body<T, PD>(rp, step, wp, wp.in.sx0 + (int)(gw % ni), wp.in.cy0 + (int)(gw / ni));
+    wave2d_pass_body<T, PD, NS>(rp, step, wp, wp.in.sx0 + (int)(gw % ni), wp.in.cy0 + (int)(gw / ni), cf);
 }
 
 // batched: every active run of the table, each with its own step and chunk
@@ -1655,15 +1676,16 @@ __global__ void __launch_bounds__(256, KIND == kPair ? 1 : 3) kb_wave2d_pair(con
     const int i = find_item<KIND>(it, n, b);
     const RunK<T> *rp = uniform_desc<RunK<T>>(it[i].rk);
     const int cf = it[i].pair_cf;
-    const WavePair wp = wave2d_split_pair(*rp, it[i].pair_ci, cf);
+    const WavePass<2> wp = wave2d_split_pass<2>(*rp, it[i].pair_ci, cf);
     const long gw = (b - it[i].blk[KIND]) * 4L + wave_in_block();
     const long step = it[i].step0 + s;
     if (KIND == kPair) {
         if (gw >= wp.in.interior()) return;
         const int ni = wp.in.sx1 - wp.in.sx0;
-        wave2d_pair_body<T, sizeof(T) == 8 ? 3 : 2>(rp, step, wp, wp.in.sx0 + (int)(gw % ni), wp.in.cy0 + (int)(gw / ni));
+        wave2d_pass_body<T, sizeof(T) == 8 ? 3 : 2, 2>(rp, step, wp, wp.in.sx0 + (int)(gw % ni),
+                                                       wp.in.cy0 + (int)(gw / ni), cf);
     } else {
-        const WaveSplit& w = KIND == kFrameA ? wp.fa : wp.fb;
+        const WaveSplit& w = wp.fr[KIND == kFrameA ? 0 : 1];
         if (gw >= w.edge()) return;
         int seg, ch;
         wave2d_edge_item(w, gw, seg, ch);
@@ -1674,10 +1696,10 @@ __global__ void __launch_bounds__(256, KIND == kPair ? 1 : 3) kb_wave2d_pair(con
 template <typename T>
 void wave2d_pair_blocks(const RunK<T>& h, int ci, int cf, long *interior, long *frame_a, long *frame_b)
 {
-    const WavePair wp = wave2d_split_pair(h, ci, cf);
+    const WavePass<2> wp = wave2d_split_pass<2>(h, ci, cf);
     *interior = (wp.in.interior() + 3) / 4;
-    *frame_a = (wp.fa.edge() + 3) / 4;
-    *frame_b = (wp.fb.edge() + 3) / 4;
+    *frame_a = (wp.fr[0].edge() + 3) / 4;
+    *frame_b = (wp.fr[1].edge() + 3) / 4;
 }
 template void wave2d_pair_blocks<float>(const RunK<float>&, int, int, long *, long *, long *);
 template void wave2d_pair_blocks<double>(const RunK<double>&, int, int, long *, long *, long *);
@@ -1744,7 +1766,7 @@ hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chu
 {
     const WaveSplit w = wave2d_split(h, chunk);
     const unsigned ni = (unsigned)((w.interior() + 3) / 4), ne = (unsigned)((w.edge() + 3) / 4);
-    if (pd <= 0) pd = wave2d_default_pd(sizeof(T) == 8, false);
+    if (pd <= 0) pd = wave2d_default_pd(sizeof(T) == 8, 1);
     // the frame runs beside the interior on the side stream when there is one
     // (the two launches touch disjoint outputs and read only the old slots)
     const bool fork = ws && ws->side && ne > 0 && ni > 0;
@@ -1767,30 +1789,23 @@ hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chu
     return hipGetLastError();
 }
 
-int wave2d_default_pd(bool f64, bool pair)
+int wave2d_default_pd(bool f64, int ns)
 {
-    // measured on 4096^2: one step FP32 3, FP64 2; two steps FP32 2, FP64 3
-    return pair ? (f64 ? 3 : 2) : (f64 ? 2 : 3);
+    // measured on 4096^2: one step per pass FP32 3, FP64 2; two steps FP32 2,
+    // FP64 3; three steps FP32 2, FP64 1
+    if (ns <= 1) return f64 ? 2 : 3;
+    if (ns == 2) return f64 ? 3 : 2;
+    return f64 ? 1 : 2;
 }
 
-template <typename T>
-bool wave2d_pair_available(const RunK<T>& h, int ci, int cf)
+template <typename T, int NS>
+static hipError_t launch_pass_ns(const RunK<T> *rk, const RunK<T>& h, long step, int ci, int cf, int pd, hipStream_t st,
+                                 const WaveStreams *ws)
 {
-    return ci > 0 && cf > 0 && ci % cf == 0 && wave2d_split_pair(h, ci, cf).in.interior() > 0;
-}
-
-template <typename T>
-hipError_t launch_wave2d_pair(const RunK<T> *rk, const RunK<T>& h, long step, int ci, int cf, int pd, hipStream_t st,
-                              const WaveStreams *ws)
-{
-    const WavePair wp = wave2d_split_pair(h, ci, cf);
+    const WavePass<NS> wp = wave2d_split_pass<NS>(h, ci, cf);
     const unsigned ni = (unsigned)((wp.in.interior() + 3) / 4);
-    const unsigned na = (unsigned)((wp.fa.edge() + 3) / 4), nb = (unsigned)((wp.fb.edge() + 3) / 4);
     if (ni == 0) return hipErrorInvalidValue;
-    if (pd <= 0) pd = wave2d_default_pd(sizeof(T) == 8, true);
-    // frame A (step n) and frame B (step n + 1) in order on the side stream,
-    // beside the interior: the three launches write disjoint outputs, and the
-    // interior reads only slots that neither frame writes
+    if (pd <= 0) pd = wave2d_default_pd(sizeof(T) == 8, NS);
     const bool fork = ws && ws->side;
     hipStream_t se = st;
     if (fork) {
@@ -1798,11 +1813,16 @@ hipError_t launch_wave2d_pair(const RunK<T> *rk, const RunK<T>& h, long step, in
         hipStreamWaitEvent(ws->side, ws->fork, 0);
         se = ws->side;
     }
-    if (na > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(na), dim3(256), 0, se, rk, step, wp.fa, cf);
-    if (pd <= 1) hipLaunchKernelGGL((k_wave2d_pair<T, 1>), dim3(ni), dim3(256), 0, st, rk, step, wp);
-    else if (pd == 2) hipLaunchKernelGGL((k_wave2d_pair<T, 2>), dim3(ni), dim3(256), 0, st, rk, step, wp);
-    else hipLaunchKernelGGL((k_wave2d_pair<T, 3>), dim3(ni), dim3(256), 0, st, rk, step, wp);
-    if (nb > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(nb), dim3(256), 0, se, rk, step + 1, wp.fb, cf);
+    // frame 0 before the interior is queued, the later frames after it
+    const unsigned nf0 = (unsigned)((wp.fr[0].edge() + 3) / 4);
+    if (nf0 > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(nf0), dim3(256), 0, se, rk, step, wp.fr[0], cf);
+    if (pd <= 1) hipLaunchKernelGGL((k_wave2d_pass<T, 1, NS>), dim3(ni), dim3(256), 0, st, rk, step, wp, cf);
+    else if (pd == 2) hipLaunchKernelGGL((k_wave2d_pass<T, 2, NS>), dim3(ni), dim3(256), 0, st, rk, step, wp, cf);
+    else hipLaunchKernelGGL((k_wave2d_pass<T, 3, NS>), dim3(ni), dim3(256), 0, st, rk, step, wp, cf);
+    for (int f = 1; f < NS; f++) {
+        const unsigned nf = (unsigned)((wp.fr[f].edge() + 3) / 4);
+        if (nf > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(nf), dim3(256), 0, se, rk, step + f, wp.fr[f], cf);
+    }
     if (fork) {
         hipEventRecord(ws->join, ws->side);
         hipStreamWaitEvent(st, ws->join, 0);
@@ -1810,10 +1830,28 @@ hipError_t launch_wave2d_pair(const RunK<T> *rk, const RunK<T>& h, long step, in
     return hipGetLastError();
 }
 
-template bool wave2d_pair_available<float>(const RunK<float>&, int, int);
-template bool wave2d_pair_available<double>(const RunK<double>&, int, int);
-template hipError_t launch_wave2d_pair<float>(const RunK<float> *, const RunK<float>&, long, int, int, int, hipStream_t, const WaveStreams *);
-template hipError_t launch_wave2d_pair<double>(const RunK<double> *, const RunK<double>&, long, int, int, int, hipStream_t, const WaveStreams *);
+template <typename T>
+bool wave2d_pass_available(const RunK<T>& h, int ns, int ci, int cf)
+{
+    if (ci <= 0 || cf <= 0 || ci % cf != 0) return false;
+    if (ns == 2) return wave2d_split_pass<2>(h, ci, cf).in.interior() > 0;
+    if (ns == 3) return wave2d_split_pass<3>(h, ci, cf).in.interior() > 0;
+    return false;
+}
+
+template <typename T>
+hipError_t launch_wave2d_pass(const RunK<T> *rk, const RunK<T>& h, long step, int ns, int ci, int cf, int pd,
+                              hipStream_t st, const WaveStreams *ws)
+{
+    if (ns == 2) return launch_pass_ns<T, 2>(rk, h, step, ci, cf, pd, st, ws);
+    if (ns == 3) return launch_pass_ns<T, 3>(rk, h, step, ci, cf, pd, st, ws);
+    return hipErrorInvalidValue;
+}
+
+template bool wave2d_pass_available<float>(const RunK<float>&, int, int, int);
+template bool wave2d_pass_available<double>(const RunK<double>&, int, int, int);
+template hipError_t launch_wave2d_pass<float>(const RunK<float> *, const RunK<float>&, long, int, int, int, int, hipStream_t, const WaveStreams *);
+template hipError_t launch_wave2d_pass<double>(const RunK<double> *, const RunK<double>&, long, int, int, int, int, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d<float>(const RunK<float> *, const RunK<float>&, long, int, int, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d<double>(const RunK<double> *, const RunK<double>&, long, int, int, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d_batch<float>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);

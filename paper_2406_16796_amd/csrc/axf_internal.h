@@ -34,7 +34,7 @@ template <int D> __host__ __device__ constexpr bool actB1(int c) { return D >= 2
 // and their ghosts through four (level L, the field at t = (L - 1/2) dt, in slot
 // L mod 4).  One slot more than a single step needs, so that a launch advancing
 // two steps reads its inputs while it writes both later levels elsewhere.
-constexpr int kEmSlots = 3, kPhiSlots = 4;
+constexpr int kEmSlots = 4, kPhiSlots = 5;
 __host__ __device__ constexpr int em_slot(long step) { return (int)(step % kEmSlots); }
 __host__ __device__ constexpr int phi_slot(long level) { return (int)(level % kPhiSlots); }
 

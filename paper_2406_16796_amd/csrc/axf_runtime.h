@@ -50,9 +50,10 @@ struct Run {
     int chunk = 0;                 // fused planes per workgroup (0: default)
     int pd = 0;                    // 2D wavefront prefetch distance (0: default)
     bool lds_march = false;          // 2D fused: the LDS-marching kernel instead of the wavefront one
-    bool pair = true;                // 2D fused: advance two steps per pass where possible
+    bool pair = true;                // 2D fused: advance several steps per pass where possible
     int pair_ci = 0, pair_cf = 0;    // ... rows per interior / frame wavefront (0: default)
     int pair_pd = 0;                 // ... prefetch distance of the interior (0: default)
+    int pass_steps = 0;              // ... most steps per pass (2 or 3; 0: default)
     hipStream_t side = nullptr;      // 2D fused: stream of the boundary-frame launch (created on use)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     long inc_lo = -1;               // first time level held by the laser table
@@ -75,14 +76,16 @@ int run_prepare(Run *R);
 // the run steps with the 2D wavefront kernel; its rows per march
 bool run_wave2d(const Run *R);
 int run_wave_chunk(const Run *R);
-// rows per interior and frame wavefront of the two-step pass
+// rows per interior and frame wavefront of a pass of several steps, and the
+// most steps per pass
 void run_pair_shape(const Run *R, int *ci, int *cf);
+int run_pass_steps(const Run *R);
 // tuned 2D wavefront shapes for a configuration, if recorded: the best one-step
 // shape, the best two-step shape and whether two-step passes are faster
 struct TunedShape {
     int chunk = 0, pd = 0;
     bool pair = true;
-    int pair_ci = 0, pair_cf = 0, pair_pd = 0;
+    int pass_steps = 0, pair_ci = 0, pair_cf = 0, pair_pd = 0;
 };
 bool tuned_shape(const axf_config *c, TunedShape *out);
 int run_diag_now(Run *R, axf_diag_record *out);

@@ -413,27 +413,38 @@ static int steps_fused(Run *R, int64_t nsteps)
             }
             ws = WaveStreams{R->side, R->ev_fork, R->ev_join};
         }
-        // two steps per pass (2D) unless a diagnostic record falls on the first
-        // of them or between them: the pass stores no complete state of step n + 1
+        // several steps per pass (2D) unless a diagnostic record falls on one of
+        // them but the last: a pass stores no complete state of the steps inside it
+        // (three, else two, else one)
         int ci = 0, cf = 0;
         run_pair_shape(R, &ci, &cf);
-        const bool pairs = wave2d && R->pair && wave2d_pair_available<T>(h, ci, cf);
+        const int nmax = run_pass_steps(R);
+        bool avail[4] = {false, false, false, false};
+        for (int k = 2; k <= nmax; k++) avail[k] = wave2d && R->pair && wave2d_pass_available<T>(h, k, ci, cf);
         auto due = [&](long s) { return R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0; };
+        auto clear = [&](long s, int k) {
+            for (int q = 0; q < k; q++)
+                if (due(s + q)) return false;
+            return true;
+        };
         for (int64_t it = 0; it < nsteps;) {
             long s = R->step;
-            const bool two = pairs && nsteps - it >= 2 && !due(s) && !due(s + 1);
-            ensure_incident<D, T>(R, s, two ? 2 : 1);
+            int ns = 1;
+            for (int k = nmax; k >= 2 && ns == 1; k--)
+                if (avail[k] && nsteps - it >= k && clear(s, k)) ns = k;
+            const bool multi = ns > 1;
+            ensure_incident<D, T>(R, s, ns);
             const WaveStreams *wsp = ws.side ? &ws : nullptr;
-            hipError_t e = two ? launch_wave2d_pair<T>(rk, h, s, ci, cf, R->pair_pd, R->stream, wsp)
-                         : wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->pd, R->stream, wsp)
-                                  : F::launch(rk, h, s, chunk, R->stream);
+            hipError_t e = multi ? launch_wave2d_pass<T>(rk, h, s, ns, ci, cf, R->pair_pd, R->stream, wsp)
+                           : wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->pd, R->stream, wsp)
+                                    : F::launch(rk, h, s, chunk, R->stream);
             if (e != hipSuccess) return hip_fail(e, "fused step launch");
-            if (!two && due(s)) {
+            if (!multi && due(s)) {
                 Plain<D, T>::diag(rk, h, s, R->rec_written % h.rec_cap, R->stream);
                 R->rec_written++;
             }
-            R->step += two ? 2 : 1;
-            it += two ? 2 : 1;
+            R->step += ns;
+            it += ns;
             R->launches += 1;
         }
         return AXF_OK;
@@ -508,6 +519,7 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
         R->chunk = ts.chunk;
         R->pd = ts.pd;
         R->pair = ts.pair;
+        R->pass_steps = ts.pass_steps;
         R->pair_ci = ts.pair_ci;
         R->pair_cf = ts.pair_cf;
         R->pair_pd = ts.pair_pd;
@@ -519,6 +531,7 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     if (const char *pc = getenv("AXF_PAIR_CHUNK")) R->pair_ci = atoi(pc);
     if (const char *pf = getenv("AXF_PAIR_FRAME")) R->pair_cf = atoi(pf);
     if (const char *pp = getenv("AXF_PAIR_PD")) R->pair_pd = atoi(pp);
+    if (const char *ps = getenv("AXF_PASS_STEPS")) R->pass_steps = atoi(ps) >= 3 ? 3 : 2;
     R->use_fused = cfg->path == AXF_PATH_FUSED || (cfg->path == AXF_PATH_AUTO && fused_supported(cfg) && auto_fused_enabled(cfg));
     choose_scales(cfg, &R->s_phi, &R->s_1);
     if (cfg->precision == AXF_F32) {
@@ -562,10 +575,17 @@ bool run_wave2d(const Run *R)
 
 int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 8; }
 
+int run_pass_steps(const Run *R)
+{
+    // measured on 4096^2 (Gcell/s, two / three steps per pass at the best
+    // shapes): FP32 72.0 / 86.3, FP64 41.7 / 50.8
+    return R->pass_steps > 0 ? R->pass_steps : 3;
+}
+
 void run_pair_shape(const Run *R, int *ci, int *cf)
 {
-    *cf = R->pair_cf > 0 ? R->pair_cf : 8;
-    *ci = R->pair_ci > 0 ? R->pair_ci : 8;
+    *cf = R->pair_cf > 0 ? R->pair_cf : 6;
+    *ci = R->pair_ci > 0 ? R->pair_ci : 12;
 }
 
 int run_step(Run *R, int64_t nsteps)
@@ -848,8 +868,11 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
     c.diag_every = 0;
     // one step per pass: rows per march, prefetch distance
     const int singles[][2] = {{8, 1}, {8, 2}, {8, 3}, {12, 3}, {16, 2}, {16, 3}, {24, 3}, {32, 3}};
-    // two steps per pass: rows per interior wavefront, per frame wavefront, prefetch distance
-    const int pairs[][3] = {{6, 6, 2}, {8, 8, 2}, {8, 8, 3}, {8, 4, 2}, {12, 6, 2}, {16, 8, 2}, {16, 8, 3}, {24, 8, 2}};
+    // several steps per pass: steps, rows per interior wavefront, per frame
+    // wavefront, prefetch distance
+    // (prefetch 0: the built-in one for the precision and steps)
+    const int pairs[][4] = {{2, 8, 8, 0}, {2, 12, 6, 0}, {3, 12, 6, 0}, {3, 12, 6, 1},
+                            {3, 12, 6, 2}, {3, 8, 8, 0}, {3, 14, 7, 0}, {3, 16, 8, 0}};
     // shape < 0: the built-in default (pairs where available)
     auto time_shape = [&](const TunedShape& sh, bool dflt, double *ms, bool *paired) -> int {
         axf_run R;
@@ -859,11 +882,12 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
             R.chunk = sh.chunk;
             R.pd = sh.pd;
             R.pair = sh.pair;
+            R.pass_steps = sh.pass_steps;
             R.pair_ci = sh.pair_ci;
             R.pair_cf = sh.pair_cf;
             R.pair_pd = sh.pair_pd;
         } else {
-            R.chunk = R.pd = R.pair_ci = R.pair_cf = R.pair_pd = 0;
+            R.chunk = R.pd = R.pair_ci = R.pair_cf = R.pair_pd = R.pass_steps = 0;
             R.pair = true;
         }
         e = run_step(&R, 2);
@@ -875,8 +899,9 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
         const bool wave = run_wave2d(&R);
         int ci = 0, cf = 0;
         run_pair_shape(&R, &ci, &cf);
-        *paired = wave && R.pair && (c.precision == AXF_F64 ? wave2d_pair_available<double>(R.hd, ci, cf)
-                                                             : wave2d_pair_available<float>(R.hf, ci, cf));
+        const int ns = run_pass_steps(&R);
+        *paired = wave && R.pair && (c.precision == AXF_F64 ? wave2d_pass_available<double>(R.hd, ns, ci, cf)
+                                                             : wave2d_pass_available<float>(R.hf, ns, ci, cf));
         run_release(&R);
         if (!e && !wave) return 1;    // no wavefront path for this configuration
         return e;
@@ -911,15 +936,17 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
     for (auto& sh : pairs) {
         TunedShape t = best;
         t.pair = true;
-        t.pair_ci = sh[0];
-        t.pair_cf = sh[1];
-        t.pair_pd = sh[2];
+        t.pass_steps = sh[0];
+        t.pair_ci = sh[1];
+        t.pair_cf = sh[2];
+        t.pair_pd = sh[3];
         double ms = 0.0;
         if ((rc = time_shape(t, false, &ms, &paired)) < 0) return rc;
-        if (!paired) break;                 // the grid has no interior for a two-step pass
+        if (!paired) continue;              // the grid has no interior for a pass of that many steps
         out->candidates++;
         if (ms < best_pair) {
             best_pair = ms;
+            best.pass_steps = t.pass_steps;
             best.pair_ci = t.pair_ci;
             best.pair_cf = t.pair_cf;
             best.pair_pd = t.pair_pd;
@@ -932,16 +959,19 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
         const bool f64 = c.precision == AXF_F64;
         best = TunedShape{};
         best.chunk = 8;
-        best.pd = wave2d_default_pd(f64, false);
+        best.pd = wave2d_default_pd(f64, 1);
         best.pair = dflt_paired;
-        best.pair_ci = best.pair_cf = 8;
-        best.pair_pd = wave2d_default_pd(f64, true);
+        best.pass_steps = 3;
+        best.pair_ci = 12;
+        best.pair_cf = 6;
+        best.pair_pd = 0;
         best_pair = best_single = dflt;
     }
     out->path = AXF_PATH_FUSED;
-    out->steps_per_pass = best.pair ? 2 : 1;
+    out->steps_per_pass = best.pair ? best.pass_steps : 1;
     out->chunk = best.pair ? best.pair_ci : best.chunk;
-    out->prefetch = best.pair ? best.pair_pd : best.pd;
+    out->prefetch = best.pair ? (best.pair_pd > 0 ? best.pair_pd : wave2d_default_pd(c.precision == AXF_F64, best.pass_steps))
+                              : best.pd;
     out->frame_chunk = best.pair ? best.pair_cf : 0;
     out->ms_per_step = best.pair ? best_pair : best_single;
     std::lock_guard<std::mutex> lk(g_tune_mu);

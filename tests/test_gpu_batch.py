@@ -181,10 +181,12 @@ def test_tuned_shape_is_used_and_results_unchanged(axf):
     ref.step(60)
     axf.tune_reset()
     choice = axf.tune(cfg, precision=axf.F32, steps=8)
-    assert choice["path"] == axf.PATH_FUSED and choice["candidates"] >= 16   # one- and two-step shapes
+    # one-step shapes and the multi-step shapes this grid has an interior for
+    # (two steps: 290 columns are too few for three)
+    assert choice["path"] == axf.PATH_FUSED and choice["candidates"] >= 10
     assert choice["chunk"] > 0 and choice["prefetch"] > 0
     assert choice["steps_per_pass"] in (1, 2)
-    assert (choice["frame_chunk"] > 0) == (choice["steps_per_pass"] == 2)
+    assert (choice["frame_chunk"] > 0) == (choice["steps_per_pass"] > 1)
     assert choice["ms_per_step"] <= choice["default_ms_per_step"] * 1.5
     run = axf.Run(cfg, precision=axf.F32)
     run.step(60)

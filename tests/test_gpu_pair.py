@@ -1,11 +1,16 @@
-"""The two-step pass of the 2D wavefront step (temporal blocking) against the
-one-step pass, through the C ABI.
+"""Passes of several steps of the 2D wavefront step (temporal blocking) against
+the one-step pass, through the C ABI.
 
-A pass advances the interior two steps with the same point formulas in the
-same order as two one-step passes, and the boundary frame with two one-step
+A pass advances the interior two or three steps with the same point formulas
+in the same order as one-step passes, and the boundary frame with one-step
 launches, so fields, diagnostic records and probabilities must be the same
 bits.  The one-step pass is itself tied to the oracle by the parity tests; one
-two-step run is also compared with the oracle directly.
+run of each pass length is also compared with the oracle directly.
+
+The number of launches a call makes is checked against a model of the
+runtime's choice: at each step the longest pass (up to the run's limit) that
+the grid has an interior for, that fits the steps left, and that no
+diagnostic record falls inside (on any of its steps).
 """
 import numpy as np
 import pytest
@@ -40,18 +45,69 @@ def grid_2d(nx, ny, ax_bc, pml_n=8, seed=5):
     return cfg
 
 
-def run_steps(axf, monkeypatch, cfg, prec, counts, pair, diag_every=0, ci=None):
-    monkeypatch.setenv("AXF_WAVE_PAIR", "1" if pair else "0")
-    if ci:
-        monkeypatch.setenv("AXF_PAIR_CHUNK", str(ci))
-    else:
-        monkeypatch.delenv("AXF_PAIR_CHUNK", raising=False)
+CI, CF = 12, 6          # the built-in rows per interior / frame wavefront
+
+
+def pass_available(cfg, ns, ci=CI, cf=CF):
+    """Whether the grid (Mur EM on x and y) has an interior for an ns-step pass:
+    columns x0 - lo .. x0 - lo + 63 and rows c0 - 3 ns - 1 .. c0 + ci + ns clear
+    of the margin, and a core of one segment and one frame chunk inside
+    ns - 1 rings."""
+    n0, n1 = int(cfg["n"][0]), int(cfg["n"][1])
+    nn1 = n1 + 1
+    pml = int(cfg.get("pml_n", 20))
+    mxg = 1 + (pml if cfg["ax_bc"][0] == W.AX_PML else 0)
+    myg = 1 + (pml if cfg["ax_bc"][1] == W.AX_PML else 0)
+    wid, lo = 66 - 4 * ns, 2 * ns - 1
+    sx0 = -(-(mxg + lo) // wid)
+    r = n0 - 1 - mxg - (63 - lo)
+    sx1 = r // wid + 1 if r >= 0 else 0
+    cy0 = -(-(myg + 3 * ns + 1) // ci)
+    r = n1 - 1 - myg - ns - ci
+    cy1 = r // ci + 1 if r >= 0 else 0
+    if ci % cf:
+        return False
+    nchf, k = -(-nn1 // cf), ci // cf
+    if cy1 * k > nchf - 1:
+        cy1 = (nchf - 1) // k
+    need = 2 * (ns - 1) + 1
+    return sx1 - sx0 >= need and (cy1 - cy0) * k >= need
+
+
+def model_launches(cfg, counts, nmax, diag_every, ci=CI, cf=CF):
+    avail = {k: pass_available(cfg, k, ci=ci, cf=cf) for k in range(2, nmax + 1)}
+    due = lambda s: diag_every > 0 and s % diag_every == 0
+    step, launches = 0, 0
+    for n in counts:
+        it = 0
+        while it < n:
+            ns = 1
+            for k in range(nmax, 1, -1):
+                if avail[k] and n - it >= k and not any(due(step + q) for q in range(k)):
+                    ns = k
+                    break
+            step += ns
+            it += ns
+            launches += 1
+    return launches
+
+
+def run_steps(axf, monkeypatch, cfg, prec, counts, ns, diag_every=0, ci=None, cf=None):
+    """ns = 1: one step per pass; 2 or 3: passes of up to ns steps."""
+    monkeypatch.setenv("AXF_WAVE_PAIR", "1" if ns > 1 else "0")
+    monkeypatch.setenv("AXF_PASS_STEPS", str(max(ns, 2)))
+    for name, v in (("AXF_PAIR_CHUNK", ci), ("AXF_PAIR_FRAME", cf)):
+        if v:
+            monkeypatch.setenv(name, str(v))
+        else:
+            monkeypatch.delenv(name, raising=False)
     run = axf.Run(dict(cfg, diag_every=diag_every), precision=prec, path=axf.PATH_FUSED)
     launches = 0
     for n in counts:
         run.step(n)
         launches += run.last_step_timing()[1]
     monkeypatch.delenv("AXF_WAVE_PAIR")
+    monkeypatch.delenv("AXF_PASS_STEPS")
     return run, launches
 
 
@@ -63,42 +119,50 @@ def assert_same(a, b, label):
     assert a.diag_now() == b.diag_now(), label
 
 
+@pytest.mark.parametrize("ns", [2, 3])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("bc", ["periodic", "outflow", "pml", "reflect"])
-def test_pair_equals_single_bitwise(axf, monkeypatch, prec, bc):
+def test_pass_equals_single_bitwise(axf, monkeypatch, ns, prec, bc):
     code = {"periodic": W.AX_PERIODIC, "outflow": W.AX_OUTFLOW, "pml": W.AX_PML, "reflect": W.AX_REFLECT}[bc]
     p = axf.F32 if prec == "f32" else axf.F64
-    cfg = grid_2d(301, 213, code)
-    counts = [1, 44, 17, 2]          # odd starts, diagnostics every 10 steps break pairs
-    two, n2 = run_steps(axf, monkeypatch, cfg, p, counts, True, diag_every=10)
-    one, n1 = run_steps(axf, monkeypatch, cfg, p, counts, False, diag_every=10)
+    cfg = grid_2d(420, 331, code)
+    assert pass_available(cfg, ns)
+    counts = [1, 44, 17, 2]          # odd starts; diagnostics every 10 steps break passes
+    multi, nm = run_steps(axf, monkeypatch, cfg, p, counts, ns, diag_every=10)
+    one, n1 = run_steps(axf, monkeypatch, cfg, p, counts, 1, diag_every=10)
     assert n1 == sum(counts)
-    assert n2 < 0.75 * sum(counts), n2            # most steps went two at a time
-    assert_same(two, one, "%s %s" % (prec, bc))
+    assert nm == model_launches(cfg, counts, ns, 10), nm
+    assert nm < (0.75 if ns == 2 else 0.6) * sum(counts), nm
+    assert_same(multi, one, "%d steps %s %s" % (ns, prec, bc))
 
 
-@pytest.mark.parametrize("ci", [8, 24, 32])
-def test_pair_interior_chunks_bitwise(axf, monkeypatch, ci):
+@pytest.mark.parametrize("ns", [2, 3])
+@pytest.mark.parametrize("ci,cf", [(8, 8), (24, 8), (36, 6), (16, 4)])
+def test_pass_interior_chunks_bitwise(axf, monkeypatch, ns, ci, cf):
     cfg = grid_2d(420, 331, W.AX_PML, pml_n=20, seed=11)
-    two, n2 = run_steps(axf, monkeypatch, cfg, axf.F32, [60], True, ci=ci)
-    one, _ = run_steps(axf, monkeypatch, cfg, axf.F32, [60], False)
-    assert n2 == 30
-    assert_same(two, one, "ci %d" % ci)
+    multi, nm = run_steps(axf, monkeypatch, cfg, axf.F32, [60], ns, ci=ci, cf=cf)
+    one, _ = run_steps(axf, monkeypatch, cfg, axf.F32, [60], 1)
+    assert nm == model_launches(cfg, [60], ns, 0, ci=ci, cf=cf), nm
+    assert nm < 60
+    assert_same(multi, one, "%d steps ci %d cf %d" % (ns, ci, cf))
 
 
-def test_pair_small_grid_falls_back(axf, monkeypatch):
-    """A grid with no interior for the pass steps one at a time, same bits."""
-    cfg = grid_2d(120, 90, W.AX_OUTFLOW)
-    two, n2 = run_steps(axf, monkeypatch, cfg, axf.F32, [31], True)
-    one, _ = run_steps(axf, monkeypatch, cfg, axf.F32, [31], False)
-    assert n2 == 31
-    assert_same(two, one, "small")
+def test_pass_small_grid_falls_back(axf, monkeypatch):
+    """A grid with no interior for any pass steps one at a time; one with an
+    interior for two steps but not three takes two-step passes; same bits."""
+    for nx, ny, want in ((120, 90, 31), (301, 213, 16)):
+        cfg = grid_2d(nx, ny, W.AX_OUTFLOW)
+        multi, nm = run_steps(axf, monkeypatch, cfg, axf.F32, [31], 3)
+        one, _ = run_steps(axf, monkeypatch, cfg, axf.F32, [31], 1)
+        assert nm == want == model_launches(cfg, [31], 3, 0), (nx, ny, nm)
+        assert_same(multi, one, "small %dx%d" % (nx, ny))
 
 
-def test_pair_matches_oracle(axf, monkeypatch):
-    cfg = grid_2d(301, 213, W.AX_PML)
-    run, n = run_steps(axf, monkeypatch, cfg, axf.F64, [120], True)
-    assert n == 60
+@pytest.mark.parametrize("ns", [2, 3])
+def test_pass_matches_oracle(axf, monkeypatch, ns):
+    cfg = grid_2d(420, 331, W.AX_PML)
+    run, n = run_steps(axf, monkeypatch, cfg, axf.F64, [120], ns)
+    assert n == 120 // ns
     ora = Oracle(cfg)
     ora.step(120)
     s0 = max(np.abs(ora.field(nm)).max() for nm in FIELDS[:6])
@@ -114,7 +178,8 @@ def test_pair_matches_oracle(axf, monkeypatch):
 def test_batched_pairs_equal_alone(axf, monkeypatch):
     """A batch of grids with a pass interior (different sizes, boundaries and
     diagnostic cadences, uneven step counts) takes two-step passes in its
-    batched launches; every run ends bit-identical to the same run alone."""
+    batched launches; every run ends bit-identical to the same run alone
+    (which takes three-step passes where it can)."""
     cfgs = [grid_2d(301, 213, W.AX_PML, seed=1), grid_2d(420, 331, W.AX_OUTFLOW, seed=2),
             grid_2d(260, 300, W.AX_PERIODIC, seed=3), grid_2d(333, 257, W.AX_REFLECT, seed=4)]
     for c, de in zip(cfgs, (0, 7, 10, 0)):
@@ -133,12 +198,28 @@ def test_batched_pairs_equal_alone(axf, monkeypatch):
     batch.close()
 
 
-@pytest.mark.parametrize("nx,ny", [(236, 36), (237, 43), (295, 37)])
-def test_pair_smallest_interiors_bitwise(axf, monkeypatch, nx, ny):
-    """Grids at the edge of having an interior for the pass (a one-segment,
-    one-chunk core) and rows that leave a partial last chunk."""
+def smallest_grid(ns):
+    """The narrowest and then the shortest grid with an interior for an
+    ns-step pass (the innermost core one segment and one chunk)."""
+    nx = next(x for x in range(64, 1000) if pass_available(grid_2d(x, 400, W.AX_OUTFLOW), ns))
+    ny = next(y for y in range(8, 1000) if pass_available(grid_2d(nx, y, W.AX_OUTFLOW), ns))
+    return nx, ny
+
+
+@pytest.mark.parametrize("ns", [2, 3])
+@pytest.mark.parametrize("dx,dy", [(0, 0), (1, 7), (59, 1)])
+def test_pass_smallest_interiors_bitwise(axf, monkeypatch, ns, dx, dy):
+    """Grids at the edge of having an interior for the pass (one column or
+    row fewer has none) and a little beyond, with rows that leave a partial
+    last chunk."""
+    nx0, ny0 = smallest_grid(ns)
+    nx, ny = nx0 + dx, ny0 + dy
     cfg = grid_2d(nx, ny, W.AX_OUTFLOW, seed=nx)
-    two, n2 = run_steps(axf, monkeypatch, cfg, axf.F32, [24], True)
-    one, _ = run_steps(axf, monkeypatch, cfg, axf.F32, [24], False)
-    assert n2 == 12, n2
-    assert_same(two, one, "%dx%d" % (nx, ny))
+    assert pass_available(cfg, ns)
+    assert not pass_available(grid_2d(nx0 - 1, ny0, W.AX_OUTFLOW), ns)
+    assert not pass_available(grid_2d(nx0, ny0 - 1, W.AX_OUTFLOW), ns)
+    steps = 6 * ns
+    multi, nm = run_steps(axf, monkeypatch, cfg, axf.F32, [steps], ns)
+    one, _ = run_steps(axf, monkeypatch, cfg, axf.F32, [steps], 1)
+    assert nm == steps // ns == model_launches(cfg, [steps], ns, 0), nm
+    assert_same(multi, one, "%d steps %dx%d" % (ns, nx, ny))
