@@ -182,22 +182,24 @@ int axf_last_step_timing(const axf_run *run, double *ms, int64_t *launches);
 /* ------------------------------------------------------------ tuning
  * Launch shape of the fused 2D step, chosen by timing every candidate on a
  * scratch run: one step per pass (rows per wavefront march, prefetch
- * distance) or two steps per pass (rows per interior wavefront, rows per
- * frame wavefront, prefetch distance).  The best shape of each kind is kept
- * in a process-wide table keyed by dimensionality, precision, boundary kinds
- * and the power-of-two size class of the grid, with the faster kind; runs
- * created afterwards with a matching key use it (batches use the one-step
- * shape).  Configurations without a fused 2D path report AXF_PATH_PLAIN and
- * keep their launches.
+ * distance) or passes of two or three steps (temporal blocking: steps per
+ * pass, rows per interior wavefront, rows per frame wavefront, prefetch
+ * distance).  The best shape of each kind is kept in a process-wide table
+ * keyed by dimensionality, precision, boundary kinds, PML width and the
+ * power-of-two size class of the grid, with the faster kind; runs created
+ * afterwards with a matching key use it (batches use the one-step shape, and
+ * two-step passes with the multi-step rows).  The built-in shape stays unless
+ * a candidate beats it by more than 2%.  Configurations without a fused 2D
+ * path report AXF_PATH_PLAIN and keep their launches.
  */
 typedef struct {
     int32_t path;                /* AXF_PATH_FUSED or AXF_PATH_PLAIN */
     int32_t chunk;               /* rows per wavefront march (fused 2D; the
-                                    interior of a two-step pass) */
+                                    interior of a pass of several steps) */
     int32_t prefetch;            /* rows prefetched ahead (fused 2D) */
     int32_t candidates;          /* shapes timed */
-    int32_t steps_per_pass;      /* 2: two-step passes are faster, 1: one step per pass */
-    int32_t frame_chunk;         /* rows per frame wavefront of a two-step pass (0 if 1) */
+    int32_t steps_per_pass;      /* most steps per pass (2 or 3), or 1 */
+    int32_t frame_chunk;         /* rows per frame wavefront of a pass of several steps (0 if 1) */
     double  ms_per_step;         /* best */
     double  default_ms_per_step; /* the built-in default shape */
 } axf_tuning;

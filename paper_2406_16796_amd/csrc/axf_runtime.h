@@ -81,7 +81,8 @@ int run_wave_chunk(const Run *R);
 void run_pair_shape(const Run *R, int *ci, int *cf);
 int run_pass_steps(const Run *R);
 // tuned 2D wavefront shapes for a configuration, if recorded: the best one-step
-// shape, the best two-step shape and whether two-step passes are faster
+// shape, the best shape of passes of several steps (with their number) and
+// whether those passes are faster
 struct TunedShape {
     int chunk = 0, pd = 0;
     bool pair = true;
