@@ -348,7 +348,7 @@ def pmc_rows(path):
     return out
 
 
-PROFILE_WARMUP = 2     # steps of the profile-only run before the timed ones
+PROFILE_WARMUP = 3     # steps of the profile-only run before the timed ones (one three-step pass)
 
 
 def pmc_summary(args):

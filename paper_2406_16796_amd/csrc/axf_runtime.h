@@ -80,6 +80,8 @@ int run_wave_chunk(const Run *R);
 // most steps per pass
 void run_pair_shape(const Run *R, int *ci, int *cf);
 int run_pass_steps(const Run *R);
+// the most steps per pass this run's grid and shape give (1: one step per pass)
+int run_pass_steps_taken(const Run *R);
 // tuned 2D wavefront shapes for a configuration, if recorded: the best one-step
 // shape, the best shape of passes of several steps (with their number) and
 // whether those passes are faster

@@ -575,6 +575,19 @@ bool run_wave2d(const Run *R)
 
 int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 8; }
 
+int run_pass_steps_taken(const Run *R)
+{
+    if (!run_wave2d(R) || !R->pair) return 1;
+    int ci = 0, cf = 0;
+    run_pair_shape(R, &ci, &cf);
+    for (int k = run_pass_steps(R); k >= 2; k--) {
+        const bool ok = R->cfg.precision == AXF_F64 ? wave2d_pass_available<double>(R->hd, k, ci, cf)
+                                                    : wave2d_pass_available<float>(R->hf, k, ci, cf);
+        if (ok) return k;
+    }
+    return 1;
+}
+
 int run_pass_steps(const Run *R)
 {
     // measured on 4096^2 (Gcell/s, two / three steps per pass at the best
@@ -874,7 +887,8 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
     const int pairs[][4] = {{2, 8, 8, 0}, {2, 12, 6, 0}, {3, 12, 6, 0}, {3, 12, 6, 1},
                             {3, 12, 6, 2}, {3, 8, 8, 0}, {3, 14, 7, 0}, {3, 16, 8, 0}};
     // shape < 0: the built-in default (pairs where available)
-    auto time_shape = [&](const TunedShape& sh, bool dflt, double *ms, bool *paired) -> int {
+    // *taken: the most steps per pass the shape gives on this grid (1: none)
+    auto time_shape = [&](const TunedShape& sh, bool dflt, double *ms, int *taken) -> int {
         axf_run R;
         int e = run_init(&R, &c, scratch, bytes, st);
         if (e) return e;
@@ -897,18 +911,14 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
         if (!e) hipEventElapsedTime(&f, R.ev0, R.ev1);
         *ms = f / steps;
         const bool wave = run_wave2d(&R);
-        int ci = 0, cf = 0;
-        run_pair_shape(&R, &ci, &cf);
-        const int ns = run_pass_steps(&R);
-        *paired = wave && R.pair && (c.precision == AXF_F64 ? wave2d_pass_available<double>(R.hd, ns, ci, cf)
-                                                             : wave2d_pass_available<float>(R.hf, ns, ci, cf));
+        *taken = run_pass_steps_taken(&R);
         run_release(&R);
         if (!e && !wave) return 1;    // no wavefront path for this configuration
         return e;
     };
     double dflt = 0.0;
-    bool paired = false, dflt_paired = false;
-    rc = time_shape(TunedShape{}, true, &dflt, &dflt_paired);
+    int taken = 1, dflt_taken = 1;
+    rc = time_shape(TunedShape{}, true, &dflt, &dflt_taken);
     if (rc < 0) return rc;
     out->default_ms_per_step = dflt;
     if (rc == 1) {
@@ -919,13 +929,14 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
     }
     TunedShape best{};
     double best_single = 1e300, best_pair = 1e300;
+    int best_taken = 1;
     for (auto& sh : singles) {
         TunedShape t{};
         t.chunk = sh[0];
         t.pd = sh[1];
         t.pair = false;
         double ms = 0.0;
-        if ((rc = time_shape(t, false, &ms, &paired)) < 0) return rc;
+        if ((rc = time_shape(t, false, &ms, &taken)) < 0) return rc;
         out->candidates++;
         if (ms < best_single) {
             best_single = ms;
@@ -941,11 +952,12 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
         t.pair_cf = sh[2];
         t.pair_pd = sh[3];
         double ms = 0.0;
-        if ((rc = time_shape(t, false, &ms, &paired)) < 0) return rc;
-        if (!paired) continue;              // the grid has no interior for a pass of that many steps
+        if ((rc = time_shape(t, false, &ms, &taken)) < 0) return rc;
+        if (taken != sh[0]) continue;       // the grid has no interior for a pass of that many steps
         out->candidates++;
         if (ms < best_pair) {
             best_pair = ms;
+            best_taken = taken;
             best.pass_steps = t.pass_steps;
             best.pair_ci = t.pair_ci;
             best.pair_cf = t.pair_cf;
@@ -960,17 +972,18 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
         best = TunedShape{};
         best.chunk = 8;
         best.pd = wave2d_default_pd(f64, 1);
-        best.pair = dflt_paired;
+        best.pair = dflt_taken > 1;
         best.pass_steps = 3;
         best.pair_ci = 12;
         best.pair_cf = 6;
         best.pair_pd = 0;
         best_pair = best_single = dflt;
+        best_taken = dflt_taken;
     }
     out->path = AXF_PATH_FUSED;
-    out->steps_per_pass = best.pair ? best.pass_steps : 1;
+    out->steps_per_pass = best.pair ? best_taken : 1;
     out->chunk = best.pair ? best.pair_ci : best.chunk;
-    out->prefetch = best.pair ? (best.pair_pd > 0 ? best.pair_pd : wave2d_default_pd(c.precision == AXF_F64, best.pass_steps))
+    out->prefetch = best.pair ? (best.pair_pd > 0 ? best.pair_pd : wave2d_default_pd(c.precision == AXF_F64, best_taken))
                               : best.pd;
     out->frame_chunk = best.pair ? best.pair_cf : 0;
     out->ms_per_step = best.pair ? best_pair : best_single;
