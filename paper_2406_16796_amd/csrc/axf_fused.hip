@@ -1675,8 +1675,8 @@ __global__ void __launch_bounds__(256, KIND == kPair ? 1 : 3) kb_wave2d_pair(con
     const long b = KIND == kPair ? xcd_band(blockIdx.x, gridDim.x) : (long)blockIdx.x;
     const int i = find_item<KIND>(it, n, b);
     const RunK<T> *rp = uniform_desc<RunK<T>>(it[i].rk);
-    const int cf = it[i].pair_cf;
-    const WavePass<2> wp = wave2d_split_pass<2>(*rp, it[i].pair_ci, cf);
+    const int cf = it[i].pass_cf;
+    const WavePass<2> wp = wave2d_split_pass<2>(*rp, it[i].pass_ci, cf);
     const long gw = (b - it[i].blk[KIND]) * 4L + wave_in_block();
     const long step = it[i].step0 + s;
     if (KIND == kPair) {

@@ -114,8 +114,8 @@ struct BItem {
     long rec0;          // diagnostic records written before the call
     long blk[kNumKinds];
     int chunk;          // rows per wavefront march (fused 2D, one step per pass)
-    int pair_ci;        // rows per interior / frame wavefront of a two-step pass
-    int pair_cf;
+    int pass_ci;        // rows per interior / frame wavefront of a two-step pass
+    int pass_cf;
     int pad;
 };
 

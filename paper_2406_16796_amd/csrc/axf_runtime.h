@@ -50,9 +50,9 @@ struct Run {
     int chunk = 0;                 // fused planes per workgroup (0: default)
     int pd = 0;                    // 2D wavefront prefetch distance (0: default)
     bool lds_march = false;          // 2D fused: the LDS-marching kernel instead of the wavefront one
-    bool pair = true;                // 2D fused: advance several steps per pass where possible
-    int pair_ci = 0, pair_cf = 0;    // ... rows per interior / frame wavefront (0: default)
-    int pair_pd = 0;                 // ... prefetch distance of the interior (0: default)
+    bool multi = true;               // 2D fused: advance several steps per pass where possible
+    int pass_ci = 0, pass_cf = 0;    // ... rows per interior / frame wavefront (0: default)
+    int pass_pd = 0;                 // ... prefetch distance of the interior (0: default)
     int pass_steps = 0;              // ... most steps per pass (2 or 3; 0: default)
     hipStream_t side = nullptr;      // 2D fused: stream of the boundary-frame launch (created on use)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -78,7 +78,7 @@ bool run_wave2d(const Run *R);
 int run_wave_chunk(const Run *R);
 // rows per interior and frame wavefront of a pass of several steps, and the
 // most steps per pass
-void run_pair_shape(const Run *R, int *ci, int *cf);
+void run_pass_shape(const Run *R, int *ci, int *cf);
 int run_pass_steps(const Run *R);
 // the most steps per pass this run's grid and shape give (1: one step per pass)
 int run_pass_steps_taken(const Run *R);
@@ -87,8 +87,8 @@ int run_pass_steps_taken(const Run *R);
 // whether those passes are faster
 struct TunedShape {
     int chunk = 0, pd = 0;
-    bool pair = true;
-    int pass_steps = 0, pair_ci = 0, pair_cf = 0, pair_pd = 0;
+    bool multi = true;
+    int pass_steps = 0, pass_ci = 0, pass_cf = 0, pass_pd = 0;
 };
 bool tuned_shape(const axf_config *c, TunedShape *out);
 int run_diag_now(Run *R, axf_diag_record *out);

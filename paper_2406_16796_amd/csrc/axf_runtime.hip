@@ -417,10 +417,10 @@ static int steps_fused(Run *R, int64_t nsteps)
         // them but the last: a pass stores no complete state of the steps inside it
         // (three, else two, else one)
         int ci = 0, cf = 0;
-        run_pair_shape(R, &ci, &cf);
+        run_pass_shape(R, &ci, &cf);
         const int nmax = run_pass_steps(R);
         bool avail[4] = {false, false, false, false};
-        for (int k = 2; k <= nmax; k++) avail[k] = wave2d && R->pair && wave2d_pass_available<T>(h, k, ci, cf);
+        for (int k = 2; k <= nmax; k++) avail[k] = wave2d && R->multi && wave2d_pass_available<T>(h, k, ci, cf);
         auto due = [&](long s) { return R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0; };
         auto clear = [&](long s, int k) {
             for (int q = 0; q < k; q++)
@@ -435,7 +435,7 @@ static int steps_fused(Run *R, int64_t nsteps)
             const bool multi = ns > 1;
             ensure_incident<D, T>(R, s, ns);
             const WaveStreams *wsp = ws.side ? &ws : nullptr;
-            hipError_t e = multi ? launch_wave2d_pass<T>(rk, h, s, ns, ci, cf, R->pair_pd, R->stream, wsp)
+            hipError_t e = multi ? launch_wave2d_pass<T>(rk, h, s, ns, ci, cf, R->pass_pd, R->stream, wsp)
                            : wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->pd, R->stream, wsp)
                                     : F::launch(rk, h, s, chunk, R->stream);
             if (e != hipSuccess) return hip_fail(e, "fused step launch");
@@ -518,19 +518,19 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     if (tuned_shape(cfg, &ts)) {
         R->chunk = ts.chunk;
         R->pd = ts.pd;
-        R->pair = ts.pair;
+        R->multi = ts.multi;
         R->pass_steps = ts.pass_steps;
-        R->pair_ci = ts.pair_ci;
-        R->pair_cf = ts.pair_cf;
-        R->pair_pd = ts.pair_pd;
+        R->pass_ci = ts.pass_ci;
+        R->pass_cf = ts.pass_cf;
+        R->pass_pd = ts.pass_pd;
     }
     if (const char *ch = getenv("AXF_FUSED_CHUNK")) R->chunk = atoi(ch);
     if (const char *pd = getenv("AXF_WAVE_PD")) R->pd = atoi(pd);
     if (const char *lm = getenv("AXF_LDS_MARCH")) R->lds_march = lm[0] == '1';
-    if (const char *pe = getenv("AXF_WAVE_PAIR")) R->pair = pe[0] != '0';
-    if (const char *pc = getenv("AXF_PAIR_CHUNK")) R->pair_ci = atoi(pc);
-    if (const char *pf = getenv("AXF_PAIR_FRAME")) R->pair_cf = atoi(pf);
-    if (const char *pp = getenv("AXF_PAIR_PD")) R->pair_pd = atoi(pp);
+    if (const char *pe = getenv("AXF_WAVE_PASS")) R->multi = pe[0] != '0';
+    if (const char *pc = getenv("AXF_PASS_CHUNK")) R->pass_ci = atoi(pc);
+    if (const char *pf = getenv("AXF_PASS_FRAME")) R->pass_cf = atoi(pf);
+    if (const char *pp = getenv("AXF_PASS_PD")) R->pass_pd = atoi(pp);
     if (const char *ps = getenv("AXF_PASS_STEPS")) R->pass_steps = atoi(ps) >= 3 ? 3 : 2;
     R->use_fused = cfg->path == AXF_PATH_FUSED || (cfg->path == AXF_PATH_AUTO && fused_supported(cfg) && auto_fused_enabled(cfg));
     choose_scales(cfg, &R->s_phi, &R->s_1);
@@ -577,9 +577,9 @@ int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 8; }
 
 int run_pass_steps_taken(const Run *R)
 {
-    if (!run_wave2d(R) || !R->pair) return 1;
+    if (!run_wave2d(R) || !R->multi) return 1;
     int ci = 0, cf = 0;
-    run_pair_shape(R, &ci, &cf);
+    run_pass_shape(R, &ci, &cf);
     for (int k = run_pass_steps(R); k >= 2; k--) {
         const bool ok = R->cfg.precision == AXF_F64 ? wave2d_pass_available<double>(R->hd, k, ci, cf)
                                                     : wave2d_pass_available<float>(R->hf, k, ci, cf);
@@ -595,10 +595,10 @@ int run_pass_steps(const Run *R)
     return R->pass_steps > 0 ? R->pass_steps : 3;
 }
 
-void run_pair_shape(const Run *R, int *ci, int *cf)
+void run_pass_shape(const Run *R, int *ci, int *cf)
 {
-    *cf = R->pair_cf > 0 ? R->pair_cf : 6;
-    *ci = R->pair_ci > 0 ? R->pair_ci : 12;
+    *cf = R->pass_cf > 0 ? R->pass_cf : 6;
+    *ci = R->pass_ci > 0 ? R->pass_ci : 12;
 }
 
 int run_step(Run *R, int64_t nsteps)
@@ -884,10 +884,10 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
     // several steps per pass: steps, rows per interior wavefront, per frame
     // wavefront, prefetch distance
     // (prefetch 0: the built-in one for the precision and steps)
-    const int pairs[][4] = {{2, 8, 8, 0}, {2, 12, 6, 0}, {3, 12, 6, 0}, {3, 12, 6, 1},
+    const int passes[][4] = {{2, 8, 8, 0}, {2, 12, 6, 0}, {3, 12, 6, 0}, {3, 12, 6, 1},
                             {3, 12, 6, 2}, {3, 8, 8, 0}, {3, 14, 7, 0}, {3, 16, 8, 0}};
-    // shape < 0: the built-in default (pairs where available)
-    // *taken: the most steps per pass the shape gives on this grid (1: none)
+    // dflt: the built-in shape; *taken: the most steps per pass the shape
+    // gives on this grid (1: one step per pass)
     auto time_shape = [&](const TunedShape& sh, bool dflt, double *ms, int *taken) -> int {
         axf_run R;
         int e = run_init(&R, &c, scratch, bytes, st);
@@ -895,14 +895,14 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
         if (!dflt) {
             R.chunk = sh.chunk;
             R.pd = sh.pd;
-            R.pair = sh.pair;
+            R.multi = sh.multi;
             R.pass_steps = sh.pass_steps;
-            R.pair_ci = sh.pair_ci;
-            R.pair_cf = sh.pair_cf;
-            R.pair_pd = sh.pair_pd;
+            R.pass_ci = sh.pass_ci;
+            R.pass_cf = sh.pass_cf;
+            R.pass_pd = sh.pass_pd;
         } else {
-            R.chunk = R.pd = R.pair_ci = R.pair_cf = R.pair_pd = R.pass_steps = 0;
-            R.pair = true;
+            R.chunk = R.pd = R.pass_ci = R.pass_cf = R.pass_pd = R.pass_steps = 0;
+            R.multi = true;
         }
         e = run_step(&R, 2);
         if (!e) e = run_step(&R, steps);
@@ -928,13 +928,13 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
         return AXF_OK;
     }
     TunedShape best{};
-    double best_single = 1e300, best_pair = 1e300;
+    double best_single = 1e300, best_multi = 1e300;
     int best_taken = 1;
     for (auto& sh : singles) {
         TunedShape t{};
         t.chunk = sh[0];
         t.pd = sh[1];
-        t.pair = false;
+        t.multi = false;
         double ms = 0.0;
         if ((rc = time_shape(t, false, &ms, &taken)) < 0) return rc;
         out->candidates++;
@@ -944,49 +944,49 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
             best.pd = t.pd;
         }
     }
-    for (auto& sh : pairs) {
+    for (auto& sh : passes) {
         TunedShape t = best;
-        t.pair = true;
+        t.multi = true;
         t.pass_steps = sh[0];
-        t.pair_ci = sh[1];
-        t.pair_cf = sh[2];
-        t.pair_pd = sh[3];
+        t.pass_ci = sh[1];
+        t.pass_cf = sh[2];
+        t.pass_pd = sh[3];
         double ms = 0.0;
         if ((rc = time_shape(t, false, &ms, &taken)) < 0) return rc;
         if (taken != sh[0]) continue;       // the grid has no interior for a pass of that many steps
         out->candidates++;
-        if (ms < best_pair) {
-            best_pair = ms;
+        if (ms < best_multi) {
+            best_multi = ms;
             best_taken = taken;
             best.pass_steps = t.pass_steps;
-            best.pair_ci = t.pair_ci;
-            best.pair_cf = t.pair_cf;
-            best.pair_pd = t.pair_pd;
+            best.pass_ci = t.pass_ci;
+            best.pass_cf = t.pass_cf;
+            best.pass_pd = t.pass_pd;
         }
     }
-    best.pair = best_pair < best_single;
+    best.multi = best_multi < best_single;
     // keep the built-in shape unless a candidate beats it clearly (timings of
     // near-equal shapes differ by noise from one tuning to the next)
-    if ((best.pair ? best_pair : best_single) > 0.98 * dflt) {
+    if ((best.multi ? best_multi : best_single) > 0.98 * dflt) {
         const bool f64 = c.precision == AXF_F64;
         best = TunedShape{};
         best.chunk = 8;
         best.pd = wave2d_default_pd(f64, 1);
-        best.pair = dflt_taken > 1;
+        best.multi = dflt_taken > 1;
         best.pass_steps = 3;
-        best.pair_ci = 12;
-        best.pair_cf = 6;
-        best.pair_pd = 0;
-        best_pair = best_single = dflt;
+        best.pass_ci = 12;
+        best.pass_cf = 6;
+        best.pass_pd = 0;
+        best_multi = best_single = dflt;
         best_taken = dflt_taken;
     }
     out->path = AXF_PATH_FUSED;
-    out->steps_per_pass = best.pair ? best_taken : 1;
-    out->chunk = best.pair ? best.pair_ci : best.chunk;
-    out->prefetch = best.pair ? (best.pair_pd > 0 ? best.pair_pd : wave2d_default_pd(c.precision == AXF_F64, best_taken))
+    out->steps_per_pass = best.multi ? best_taken : 1;
+    out->chunk = best.multi ? best.pass_ci : best.chunk;
+    out->prefetch = best.multi ? (best.pass_pd > 0 ? best.pass_pd : wave2d_default_pd(c.precision == AXF_F64, best_taken))
                               : best.pd;
-    out->frame_chunk = best.pair ? best.pair_cf : 0;
-    out->ms_per_step = best.pair ? best_pair : best_single;
+    out->frame_chunk = best.multi ? best.pass_cf : 0;
+    out->ms_per_step = best.multi ? best_multi : best_single;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[tune_key(cfg)] = best;
     return AXF_OK;

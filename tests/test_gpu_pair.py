@@ -94,9 +94,9 @@ def model_launches(cfg, counts, nmax, diag_every, ci=CI, cf=CF):
 
 def run_steps(axf, monkeypatch, cfg, prec, counts, ns, diag_every=0, ci=None, cf=None):
     """ns = 1: one step per pass; 2 or 3: passes of up to ns steps."""
-    monkeypatch.setenv("AXF_WAVE_PAIR", "1" if ns > 1 else "0")
+    monkeypatch.setenv("AXF_WAVE_PASS", "1" if ns > 1 else "0")
     monkeypatch.setenv("AXF_PASS_STEPS", str(max(ns, 2)))
-    for name, v in (("AXF_PAIR_CHUNK", ci), ("AXF_PAIR_FRAME", cf)):
+    for name, v in (("AXF_PASS_CHUNK", ci), ("AXF_PASS_FRAME", cf)):
         if v:
             monkeypatch.setenv(name, str(v))
         else:
@@ -106,7 +106,7 @@ def run_steps(axf, monkeypatch, cfg, prec, counts, ns, diag_every=0, ci=None, cf
     for n in counts:
         run.step(n)
         launches += run.last_step_timing()[1]
-    monkeypatch.delenv("AXF_WAVE_PAIR")
+    monkeypatch.delenv("AXF_WAVE_PASS")
     monkeypatch.delenv("AXF_PASS_STEPS")
     return run, launches
 
