@@ -1513,10 +1513,17 @@ __host__ __device__ inline WavePass<NS> wave2d_split_pass(const R& h, int ci, in
     return p;
 }
 
+// What a wavefront of the interior stores besides E/B of step n + NS and the
+// axion level n + NS + 1:
+//   kCores: the level n + 2 + k in core k (the frames recompute the rest);
+//   kCore:  the level n + NS (the older level of the state after the pass);
+//   kRing:  every intermediate step n + k + 1 (E/B and the level n + k + 2),
+//           so the frame launches of the later steps find it next to them.
+enum PassMode { kCores = 0, kCore = 1, kRing = 2 };
+
 // The wavefront of segment `seg` and chunk `ch` of the interior of an NS-step
-// pass: reads E/B of step n and the axion levels n, n + 1; writes E/B of step
-// n + NS, the axion level n + NS + 1 and, in core k, the level n + 2 + k.
-template <typename T, int PD, int NS>
+// pass: reads E/B of step n and the axion levels n, n + 1.
+template <typename T, int PD, int NS, int MODE>
 __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp, long step, const WavePass<NS>& wp,
                                                  int seg, int ch, int cf)
 {
@@ -1544,6 +1551,11 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
     auto ldp = [&](int L, unsigned o) __attribute__((always_inline)) -> T { return ldo((const T *)b_ph, (unsigned)L * as_l + o); };
     auto stp = [&](int L, unsigned o, T v) __attribute__((always_inline)) { sto((T *)b_ph, (unsigned)L * as_l + o, v); };
     auto off = [&](int p) __attribute__((always_inline)) -> unsigned { return bx + (unsigned)p * sxb; };
+    // E/B of the intermediate steps n + 1 .. n + NS - 1 (ring wavefronts)
+    auto stm = [&](int k, int kind, int c, unsigned o, T v) __attribute__((always_inline)) {
+        const char *b = r.sb + (size_t)q_em(0, em_slot(step + k + 1), 0) * r.as;
+        sto((T *)b, (unsigned)(kind * 3 + c) * as_l + o, v);
+    };
 
     struct Pref {
         T b0z, b1[3], pa, pb, e0m[2], e1m[3];
@@ -1605,12 +1617,33 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
             sg[k].advance(r, bext0, bext1, bext2, pv.b0p_1, pv.b1n, pv.pb_2, pv.pn, e0in, e1in, k < NS - 1 || full);
         }
         if (own_x) {
-            // intermediate axion levels n + 2 + k (k < NS - 1) in core k
+            // intermediate steps n + k + 1 (k < NS - 1): E0, B0z at row
+            // t - 1 - k; E1, B1 and the axion level n + k + 2 at row t - 2 - k
 #pragma unroll
             for (int k = 0; k < NS - 1; k++) {
                 const int q = t - 2 - k;
-                if (q >= c0 && q < c1 && q >= core_y0[k] && q < core_y1[k] && core_x[k])
+                const bool rows = q >= c0 && q < c1;
+                if (MODE == kCores && rows && q >= core_y0[k] && q < core_y1[k] && core_x[k])
                     stp(phi_slot(step + 2 + k), off(q), sg[k].pn);
+                if (MODE == kCore && k == NS - 2 && rows)
+                    stp(phi_slot(step + 2 + k), off(q), sg[k].pn);
+                if (MODE == kRing) {
+                    const int qe = t - 1 - k;
+                    if (qe >= c0 && qe < c1) {
+                        const unsigned o = off(qe);
+                        stm(k, 0, 0, o, sg[k].e0h_1[0]);
+                        stm(k, 0, 1, o, sg[k].e0h_1[1]);
+                        stm(k, 1, 2, o, sg[k].b0p_1);
+                    }
+                    if (rows) {
+                        const unsigned o = off(q);
+#pragma unroll
+                        for (int c = 0; c < 3; c++) stm(k, 2, c, o, sg[k].e1h_2[c]);
+#pragma unroll
+                        for (int c = 0; c < 3; c++) stm(k, 3, c, o, sg[k].b1n[c]);
+                        stp(phi_slot(step + 2 + k), o, sg[k].pn);
+                    }
+                }
             }
             // the last stage: E0, B0z of step n + NS at row t - NS; E1, B1 and
             // the axion level n + NS + 1 at row t - NS - 1
@@ -1634,13 +1667,32 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
     }
 }
 
-template <typename T, int PD, int NS>
-__global__ void __launch_bounds__(256) k_wave2d_pass(const RunK<T> *__restrict__ rp, long step, WavePass<NS> wp, int cf)
+// the interior in one launch (kCores), or its core (kCore) or its ring
+// (kRing): `rc` splits the interior's segments and chunks into the ring, its
+// outermost segment and chunk on each side, and the core inside
+template <typename T, int PD, int NS, int MODE>
+__global__ void __launch_bounds__(256) k_wave2d_pass(const RunK<T> *__restrict__ rp, long step, WavePass<NS> wp, int cf,
+                                                     WaveSplit rc)
 {
     const long gw = xcd_band(blockIdx.x, gridDim.x) * 4L + wave_in_block();
-    if (gw >= wp.in.interior()) return;
-    const int ni = wp.in.sx1 - wp.in.sx0;
-    wave2d_pass_body<T, PD, NS>(rp, step, wp, wp.in.sx0 + (int)(gw % ni), wp.in.cy0 + (int)(gw / ni), cf);
+    int seg, ch;
+    if (MODE == kCores) {
+        if (gw >= wp.in.interior()) return;
+        const int ni = wp.in.sx1 - wp.in.sx0;
+        seg = wp.in.sx0 + (int)(gw % ni);
+        ch = wp.in.cy0 + (int)(gw / ni);
+    } else if (MODE == kCore) {
+        if (gw >= rc.interior()) return;
+        const int ni = rc.sx1 - rc.sx0;
+        seg = wp.in.sx0 + rc.sx0 + (int)(gw % ni);
+        ch = wp.in.cy0 + rc.cy0 + (int)(gw / ni);
+    } else {
+        if (gw >= rc.edge()) return;
+        wave2d_edge_item(rc, gw, seg, ch);
+        seg += wp.in.sx0;
+        ch += wp.in.cy0;
+    }
+    wave2d_pass_body<T, PD, NS, MODE>(rp, step, wp, seg, ch, cf);
 }
 
 // batched: every active run of the table, each with its own step and chunk
@@ -1682,8 +1734,8 @@ __global__ void __launch_bounds__(256, KIND == kPair ? 1 : 3) kb_wave2d_pair(con
     if (KIND == kPair) {
         if (gw >= wp.in.interior()) return;
         const int ni = wp.in.sx1 - wp.in.sx0;
-        wave2d_pass_body<T, sizeof(T) == 8 ? 3 : 2, 2>(rp, step, wp, wp.in.sx0 + (int)(gw % ni),
-                                                       wp.in.cy0 + (int)(gw / ni), cf);
+        wave2d_pass_body<T, sizeof(T) == 8 ? 3 : 2, 2, kCores>(rp, step, wp, wp.in.sx0 + (int)(gw % ni),
+                                                               wp.in.cy0 + (int)(gw / ni), cf);
     } else {
         const WaveSplit& w = wp.fr[KIND == kFrameA ? 0 : 1];
         if (gw >= w.edge()) return;
@@ -1789,6 +1841,12 @@ hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chu
     return hipGetLastError();
 }
 
+bool ring_split_enabled()
+{
+    static const bool on = !(getenv("AXF_PASS_RING") && getenv("AXF_PASS_RING")[0] == '0');
+    return on;
+}
+
 int wave2d_default_pd(bool f64, int ns)
 {
     // measured on 4096^2: one step per pass FP32 3, FP64 2; two steps FP32 2,
@@ -1798,35 +1856,68 @@ int wave2d_default_pd(bool f64, int ns)
     return f64 ? 1 : 2;
 }
 
+template <typename T, int NS, int MODE>
+static void launch_interior(const RunK<T> *rk, long step, const WavePass<NS>& wp, int cf, const WaveSplit& rc,
+                            unsigned nb, int pd, hipStream_t st)
+{
+    if (pd <= 1) hipLaunchKernelGGL((k_wave2d_pass<T, 1, NS, MODE>), dim3(nb), dim3(256), 0, st, rk, step, wp, cf, rc);
+    else if (pd == 2) hipLaunchKernelGGL((k_wave2d_pass<T, 2, NS, MODE>), dim3(nb), dim3(256), 0, st, rk, step, wp, cf, rc);
+    else hipLaunchKernelGGL((k_wave2d_pass<T, 3, NS, MODE>), dim3(nb), dim3(256), 0, st, rk, step, wp, cf, rc);
+}
+
 template <typename T, int NS>
 static hipError_t launch_pass_ns(const RunK<T> *rk, const RunK<T>& h, long step, int ci, int cf, int pd, hipStream_t st,
                                  const WaveStreams *ws)
 {
     const WavePass<NS> wp = wave2d_split_pass<NS>(h, ci, cf);
-    const unsigned ni = (unsigned)((wp.in.interior() + 3) / 4);
-    if (ni == 0) return hipErrorInvalidValue;
+    if (wp.in.interior() == 0) return hipErrorInvalidValue;
     if (pd <= 0) pd = wave2d_default_pd(sizeof(T) == 8, NS);
-    const bool fork = ws && ws->side;
-    hipStream_t se = st;
-    if (fork) {
-        hipEventRecord(ws->fork, st);
-        hipStreamWaitEvent(ws->side, ws->fork, 0);
-        se = ws->side;
+    // ring and core of the interior (the core empty when the interior is
+    // less than three segments or chunks across)
+    const int nis = wp.in.sx1 - wp.in.sx0, nic = wp.in.cy1 - wp.in.cy0;
+    WaveSplit rc{nis, nic, 1, nis - 1, 1, nic - 1, wp.in.wid};
+    if (nis < 3 || nic < 3) rc.sx0 = rc.sx1 = rc.cy0 = rc.cy1 = 0;
+    const bool split = ws && ws->side && ws->ring && ring_split_enabled();
+    if (!split) {
+        // one interior launch; frame k leaves out core k
+        const bool fork = ws && ws->side;
+        hipStream_t se = st;
+        if (fork) {
+            hipEventRecord(ws->fork, st);
+            hipStreamWaitEvent(ws->side, ws->fork, 0);
+            se = ws->side;
+        }
+        const unsigned nf0 = (unsigned)((wp.fr[0].edge() + 3) / 4);
+        if (nf0 > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(nf0), dim3(256), 0, se, rk, step, wp.fr[0], cf);
+        launch_interior<T, NS, kCores>(rk, step, wp, cf, rc, (unsigned)((wp.in.interior() + 3) / 4), pd, st);
+        for (int f = 1; f < NS; f++) {
+            const unsigned nf = (unsigned)((wp.fr[f].edge() + 3) / 4);
+            if (nf > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(nf), dim3(256), 0, se, rk, step + f, wp.fr[f], cf);
+        }
+        if (fork) {
+            hipEventRecord(ws->join, ws->side);
+            hipStreamWaitEvent(st, ws->join, 0);
+        }
+        return hipGetLastError();
     }
-    // frame 0 before the interior is queued, the later frames after it
-    const unsigned nf0 = (unsigned)((wp.fr[0].edge() + 3) / 4);
-    if (nf0 > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(nf0), dim3(256), 0, se, rk, step, wp.fr[0], cf);
-    if (pd <= 1) hipLaunchKernelGGL((k_wave2d_pass<T, 1, NS>), dim3(ni), dim3(256), 0, st, rk, step, wp, cf);
-    else if (pd == 2) hipLaunchKernelGGL((k_wave2d_pass<T, 2, NS>), dim3(ni), dim3(256), 0, st, rk, step, wp, cf);
-    else hipLaunchKernelGGL((k_wave2d_pass<T, 3, NS>), dim3(ni), dim3(256), 0, st, rk, step, wp, cf);
-    for (int f = 1; f < NS; f++) {
-        const unsigned nf = (unsigned)((wp.fr[f].edge() + 3) / 4);
-        if (nf > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(nf), dim3(256), 0, se, rk, step + f, wp.fr[f], cf);
-    }
-    if (fork) {
-        hipEventRecord(ws->join, ws->side);
-        hipStreamWaitEvent(st, ws->join, 0);
-    }
+    // three streams: the core on `st`; the ring on ws->ring; the frame, every
+    // launch leaving out just the interior, on ws->side, its steps n + 1 ..
+    // after the ring has stored them
+    const WaveSplit& fr = wp.fr[NS - 1];
+    const unsigned nfr = (unsigned)((fr.edge() + 3) / 4);
+    hipEventRecord(ws->fork, st);
+    hipStreamWaitEvent(ws->side, ws->fork, 0);
+    hipStreamWaitEvent(ws->ring, ws->fork, 0);
+    launch_interior<T, NS, kRing>(rk, step, wp, cf, rc, (unsigned)((rc.edge() + 3) / 4), pd, ws->ring);
+    hipEventRecord(ws->ring_done, ws->ring);
+    if (nfr > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(nfr), dim3(256), 0, ws->side, rk, step, fr, cf);
+    if (rc.interior() > 0)
+        launch_interior<T, NS, kCore>(rk, step, wp, cf, rc, (unsigned)((rc.interior() + 3) / 4), pd, st);
+    hipStreamWaitEvent(ws->side, ws->ring_done, 0);
+    for (int f = 1; f < NS; f++)
+        if (nfr > 0) hipLaunchKernelGGL((k_wave2d<T>), dim3(nfr), dim3(256), 0, ws->side, rk, step + f, fr, cf);
+    hipEventRecord(ws->join, ws->side);
+    hipStreamWaitEvent(st, ws->join, 0);
     return hipGetLastError();
 }
 

@@ -56,6 +56,8 @@ struct Run {
     int pass_steps = 0;              // ... most steps per pass (2 or 3; 0: default)
     hipStream_t side = nullptr;      // 2D fused: stream of the boundary-frame launch (created on use)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t ring = nullptr;      // 2D fused: stream of the interior's ring (passes of several steps)
+    hipEvent_t ev_ring = nullptr;
     long inc_lo = -1;               // first time level held by the laser table
 
     template <typename T> const RunK<T>& hk() const;

@@ -408,10 +408,12 @@ static int steps_fused(Run *R, int64_t nsteps)
         if (wave2d && !(sidee && sidee[0] == '0')) {
             if (!R->side) {
                 HIPCHK(hipStreamCreateWithFlags(&R->side, hipStreamNonBlocking));
+                HIPCHK(hipStreamCreateWithFlags(&R->ring, hipStreamNonBlocking));
                 HIPCHK(hipEventCreateWithFlags(&R->ev_fork, hipEventDisableTiming));
                 HIPCHK(hipEventCreateWithFlags(&R->ev_join, hipEventDisableTiming));
+                HIPCHK(hipEventCreateWithFlags(&R->ev_ring, hipEventDisableTiming));
             }
-            ws = WaveStreams{R->side, R->ev_fork, R->ev_join};
+            ws = WaveStreams{R->side, R->ev_fork, R->ev_join, R->ring, R->ev_ring};
         }
         // several steps per pass (2D) unless a diagnostic record falls on one of
         // them but the last: a pass stores no complete state of the steps inside it
@@ -840,13 +842,16 @@ bool tuned_shape(const axf_config *c, TunedShape *out)
 void run_release(Run *R)
 {
     if (R->side) hipStreamSynchronize(R->side);
+    if (R->ring) hipStreamSynchronize(R->ring);
     if (R->ev0) hipEventDestroy(R->ev0);
     if (R->ev1) hipEventDestroy(R->ev1);
     if (R->ev_fork) hipEventDestroy(R->ev_fork);
     if (R->ev_join) hipEventDestroy(R->ev_join);
+    if (R->ev_ring) hipEventDestroy(R->ev_ring);
     if (R->side) hipStreamDestroy(R->side);
-    R->ev0 = R->ev1 = R->ev_fork = R->ev_join = nullptr;
-    R->side = nullptr;
+    if (R->ring) hipStreamDestroy(R->ring);
+    R->ev0 = R->ev1 = R->ev_fork = R->ev_join = R->ev_ring = nullptr;
+    R->side = R->ring = nullptr;
 }
 
 }  // namespace axf
