@@ -427,9 +427,11 @@ def trace_summary(args):
              "--trace-summary $OUT/kt/kt_kernel_stats.csv"
              % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps), "",
              "The run times the fused path twice (with and without diagnostics) and the unfused phase "
-             "sequence once; the copy kernel is the bandwidth calibration.  In 2D a pass of NS steps is one "
-             "`k_wave2d_pass<T, PD, NS>` launch with NS `k_wave2d` frame launches beside it on a second "
-             "stream.", "",
+             "sequence once; the copy kernel is the bandwidth calibration.  In 2D a pass of NS steps is "
+             "`k_wave2d_pass<T, PD, NS, MODE>` over the interior with NS `k_wave2d` launches over the "
+             "boundary frame beside it on a second stream.  A three-step pass splits its interior into a "
+             "core launch (MODE 1) and a ring launch (MODE 2, on a third stream, storing the intermediate "
+             "steps the frame launches read); a two-step pass is one launch (MODE 0).", "",
              "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in rows:
         name = r["Name"]
@@ -440,15 +442,18 @@ def trace_summary(args):
             short, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
             float(r["Percentage"])))
     lines.append("")
+    modes = {"0": "", "1": " core", "2": " ring"}
     for pat in pats:
         dom = [r for r in rows if pat in r["Name"].replace(" ", "")]
         if dom:
             lines.append("- `%s_mean_us = %.2f`" % (pattern_label(pat), float(dom[0]["AverageNs"]) / 1e3))
-            m = re.search(r"k_wave2d_pass<\w+,\d+,(\d+)>", dom[0]["Name"].replace(" ", ""))
+        for r in dom:
+            m = re.search(r"k_wave2d_pass<\w+,\d+,(\d+),(\d+)>", r["Name"].replace(" ", ""))
             if m:
                 ns = int(m.group(1))
-                lines.append("- `%s_mean_us_per_step = %.2f` (a launch advances %d steps)"
-                             % (pattern_label(pat), float(dom[0]["AverageNs"]) / 1e3 / ns, ns))
+                lines.append("- `%s_mean_us_per_step = %.2f` (%s calls, a launch of the%s interior advances "
+                             "%d steps)" % (pattern_label(pat), float(r["AverageNs"]) / 1e3 / ns, r["Calls"],
+                                            modes.get(m.group(2), ""), ns))
     lines.append("- `kernel_source_sha256 = %s`" % kernel_source_hash(args.workload))
     path = os.path.join(ROOT, "profiles", "%s_%s_kernel_trace.md" % (kernel, tag))
     with open(path, "w") as f:

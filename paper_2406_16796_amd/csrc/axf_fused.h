@@ -12,7 +12,9 @@ namespace axf {
 struct WaveStreams {
     hipStream_t side;
     hipEvent_t fork, join;
-    hipStream_t ring = nullptr;      // passes of several steps: the interior's ring
+    // three-step passes: the stream of the interior's ring launch (null: the
+    // interior in one launch, the frame launches covering the ring instead)
+    hipStream_t ring = nullptr;
     hipEvent_t ring_done = nullptr;
 };
 
@@ -41,9 +43,6 @@ bool wave2d_pass_available(const RunK<T>& h, int ns, int ci, int cf);
 template <typename T>
 hipError_t launch_wave2d_pass(const RunK<T> *rk, const RunK<T>& h, long step, int ns, int ci, int cf, int pd,
                               hipStream_t st, const WaveStreams *ws);
-// passes of several steps split the interior into ring and core launches
-// (AXF_PASS_RING=0: one interior launch, frames recompute the ring)
-bool ring_split_enabled();
 // built-in prefetch distance of the interior march for ns steps per pass
 int wave2d_default_pd(bool f64, int ns);
 // the two-step pass over the first n runs of a batch table: steps s and

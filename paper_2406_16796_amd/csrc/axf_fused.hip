@@ -1841,12 +1841,6 @@ hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chu
     return hipGetLastError();
 }
 
-bool ring_split_enabled()
-{
-    static const bool on = !(getenv("AXF_PASS_RING") && getenv("AXF_PASS_RING")[0] == '0');
-    return on;
-}
-
 int wave2d_default_pd(bool f64, int ns)
 {
     // measured on 4096^2: one step per pass FP32 3, FP64 2; two steps FP32 2,
@@ -1879,7 +1873,7 @@ static hipError_t launch_pass_ns(const RunK<T> *rk, const RunK<T>& h, long step,
     if (nis < 3 || nic < 3) rc.sx0 = rc.sx1 = rc.cy0 = rc.cy1 = 0;
     // (measured on 4096^2 FP32: three steps 93.6 Gcell/s split against 86.1;
     // two steps 70.0 against 72.0, where the frames were cheap already)
-    const bool split = NS >= 3 && ws && ws->side && ws->ring && ring_split_enabled();
+    const bool split = NS >= 3 && ws && ws->side && ws->ring;
     if (!split) {
         // one interior launch; frame k leaves out core k
         const bool fork = ws && ws->side;

@@ -413,7 +413,7 @@ static int steps_fused(Run *R, int64_t nsteps)
                 HIPCHK(hipEventCreateWithFlags(&R->ev_join, hipEventDisableTiming));
                 HIPCHK(hipEventCreateWithFlags(&R->ev_ring, hipEventDisableTiming));
             }
-            ws = WaveStreams{R->side, R->ev_fork, R->ev_join, R->ring, R->ev_ring};
+            ws = WaveStreams{R->side, R->ev_fork, R->ev_join, R->pass_ring ? R->ring : nullptr, R->ev_ring};
         }
         // several steps per pass (2D) unless a diagnostic record falls on one of
         // them but the last: a pass stores no complete state of the steps inside it
@@ -534,6 +534,7 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     if (const char *pf = getenv("AXF_PASS_FRAME")) R->pass_cf = atoi(pf);
     if (const char *pp = getenv("AXF_PASS_PD")) R->pass_pd = atoi(pp);
     if (const char *ps = getenv("AXF_PASS_STEPS")) R->pass_steps = atoi(ps) >= 3 ? 3 : 2;
+    if (const char *pr = getenv("AXF_PASS_RING")) R->pass_ring = pr[0] != '0';
     R->use_fused = cfg->path == AXF_PATH_FUSED || (cfg->path == AXF_PATH_AUTO && fused_supported(cfg) && auto_fused_enabled(cfg));
     choose_scales(cfg, &R->s_phi, &R->s_1);
     if (cfg->precision == AXF_F32) {

@@ -223,3 +223,22 @@ def test_pass_smallest_interiors_bitwise(axf, monkeypatch, ns, dx, dy):
     one, _ = run_steps(axf, monkeypatch, cfg, axf.F32, [steps], 1)
     assert nm == steps // ns == model_launches(cfg, [steps], ns, 0), nm
     assert_same(multi, one, "%d steps %dx%d" % (ns, nx, ny))
+
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_pass_one_interior_launch_bitwise(axf, monkeypatch, prec):
+    """Three-step passes with the interior in one launch (AXF_PASS_RING=0,
+    frame k leaving out core k) instead of core and ring launches: the same
+    bits as one-step passes and as the split passes."""
+    p = axf.F32 if prec == "f32" else axf.F64
+    cfg = grid_2d(420, 331, W.AX_PML, seed=17)
+    counts = [2, 37]
+    split, ns = run_steps(axf, monkeypatch, cfg, p, counts, 3)
+    monkeypatch.setenv("AXF_PASS_RING", "0")
+    whole, nw = run_steps(axf, monkeypatch, cfg, p, counts, 3)
+    monkeypatch.delenv("AXF_PASS_RING")
+    one, _ = run_steps(axf, monkeypatch, cfg, p, counts, 1)
+    assert nw == ns == model_launches(cfg, counts, 3, 0), (nw, ns)
+    assert_same(whole, one, "three steps, one interior launch")
+    assert_same(split, one, "three steps, core and ring")
