@@ -117,7 +117,11 @@ Layout make_layout(const axf_config *c)
         L.n[d] = c->n[d];
         L.nn[d] = (d < D && c->em_bc[d] == AXF_EM_MUR) ? c->n[d] + 1 : c->n[d];
     }
-    L.px = round_up(L.nn[0], 64 / (long)es);
+    // rows padded to whole 64-byte segments; in 3D to whole 128-byte cache
+    // lines, so that the 64-column rows of the tile walks start on a line
+    // (measured on 512^3 FP32: 15.8 against 15.0 Gcell/s; on 4096^2 the 2D
+    // march, whose segments start anywhere, was 2% slower with 128)
+    L.px = round_up(L.nn[0], (D == 3 ? 128 : 64) / (long)es);
     L.arr_bytes = (size_t)L.px * L.nn[1] * L.nn[2] * es;
     size_t off = 0;
     auto take = [&](size_t b) { size_t o = off; off += (size_t)round_up((long)b, 256); return o; };
