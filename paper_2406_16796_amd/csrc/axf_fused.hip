@@ -17,6 +17,9 @@
 // operation order, so the two paths agree bit for bit.
 #include <stdlib.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "axf_fused.h"
 #include "axf_stencil.h"
 
@@ -1249,7 +1252,7 @@ struct Stage {
     // phi at t - 2) only when full
     template <typename K>
     __device__ __forceinline__ void advance(const K& r, T bext0, T bext1, T bext2, T in_b0z, const T in_b1[3], T in_pa,
-                                            T in_pb, const T e0m[2], const T e1m[3], bool full)
+                                            T in_pb, const T e0m[2], const T e1m[3], bool full, bool compute = true)
     {
         b0z_2 = b0z_1; b0z_1 = b0z_0; b0z_0 = in_b0z;
         pa_3 = pa_2; pa_2 = pa_1; pa_1 = in_pa;
@@ -1267,6 +1270,8 @@ struct Stage {
             e0n_2[c] = e0n_1[c];
         }
         b0p_2 = b0p_1;
+        // (a warm-up row no stored value needs: take the inputs only)
+        if (!compute) return;
         // S1: E0^{n+1/2}, E0^n at row t - 1
         {
             const T up_b0z = lane_up(b0z_1);
@@ -1472,6 +1477,18 @@ __global__ void __launch_bounds__(256, 3) k_wave2d(const RunK<T> *__restrict__ r
 // finds step n + k + 1 written next to its region; frame NS - 1 leaves out the
 // interior.
 
+// f(integral_constant<int, 0>) .. f(integral_constant<int, N - 1>), in order
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 __host__ __device__ constexpr int pass_lane0(int ns) { return 2 * ns - 1; }
 __host__ __device__ constexpr int pass_width(int ns) { return 66 - 4 * ns; }
 
@@ -1587,17 +1604,22 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
     Stage<T> sg[NS];
 #pragma unroll
     for (int k = 0; k < NS; k++) sg[k].clear();
-    const int t_first = cs - 2, t_last = c1 + NS;
+    // Warm-up: the first iteration whose loads a stored value needs, and the
+    // first whose arithmetic of stage k does (a backward liveness of the stage
+    // formulas over the rows, relative to c0); before those, the stage only
+    // takes its inputs.  Peeled at compile time, so the main loop has no
+    // per-row branch.
+    constexpr int kLoad0 = NS == 3 ? -5 : -4;
+    constexpr int kFirst0 = NS == 3 ? -4 : -3, kFirst1 = NS == 3 ? -2 : 0, kFirst2 = 1;
+    constexpr int kHead = (NS == 3 ? kFirst2 : kFirst1) - kLoad0;
+    const int t_first = c0 + kLoad0, t_last = c1 + NS;
+    (void)cs;
 #pragma unroll
     for (int k = 0; k < PD; k++)
         if (t_first + k <= t_last) prefetch(t_first + k, buf[k]);
-    constexpr int U = PD == 1 ? 1 : 6;
-    for (int t0 = t_first; t0 <= t_last; t0 += U)
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-        const int t = t0 + u;
-        if (t > t_last) break;
-        Pref& P = buf[u % PD];
+    // one iteration; stage k computes when bit k of ACT is set
+    auto iter = [&](auto act_c, const int t, Pref& P) __attribute__((always_inline)) {
+        constexpr int ACT = decltype(act_c)::value;
         asm volatile("" : "+s"(as_l));
         const T b0z = P.b0z, pa = P.pa, pb = P.pb;
         const T b1[3] = {P.b1[0], P.b1[1], P.b1[2]};
@@ -1605,7 +1627,7 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
         const T e1m[3] = {P.e1m[0], P.e1m[1], P.e1m[2]};
         if (t + PD <= t_last) prefetch(t + PD, P);
         // stage 0: step n on the loaded rows
-        sg[0].advance(r, bext0, bext1, bext2, b0z, b1, pa, pb, e0m, e1m, true);
+        sg[0].advance(r, bext0, bext1, bext2, b0z, b1, pa, pb, e0m, e1m, true, (ACT & 1) != 0);
         // stage k: step n + k, one row behind stage k - 1, from its registers
         const int qf = t - NS - 1;              // the last stage's E1, B1, phi row
         const bool full = qf >= c0 && qf < c1;
@@ -1614,9 +1636,11 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
             const Stage<T>& pv = sg[k - 1];
             const T e1in[3] = {pv.e1h_3[0], pv.e1h_3[1], pv.e1h_3[2]};
             const T e0in[2] = {pv.e0h_2[0], pv.e0h_2[1]};
-            sg[k].advance(r, bext0, bext1, bext2, pv.b0p_1, pv.b1n, pv.pb_2, pv.pn, e0in, e1in, k < NS - 1 || full);
+            sg[k].advance(r, bext0, bext1, bext2, pv.b0p_1, pv.b1n, pv.pb_2, pv.pn, e0in, e1in, k < NS - 1 || full,
+                          ((ACT >> k) & 1) != 0);
         }
-        if (own_x) {
+        // (no warm-up iteration stores: its rows are all below c0)
+        if (ACT == (1 << NS) - 1 && own_x) {
             // intermediate steps n + k + 1 (k < NS - 1): E0, B0z at row
             // t - 1 - k; E1, B1 and the axion level n + k + 2 at row t - 2 - k
 #pragma unroll
@@ -1664,6 +1688,20 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
                 stp(phi_slot(step + NS + 1), o, sl.pn);
             }
         }
+    };
+    // the warm-up iterations t_first + h, h < kHead
+    static_for<kHead>([&](auto hc) __attribute__((always_inline)) {
+        constexpr int h = decltype(hc)::value, t_rel = kLoad0 + h;
+        constexpr int act = (t_rel >= kFirst0 ? 1 : 0) | (t_rel >= kFirst1 ? 2 : 0) | (NS == 3 && t_rel >= kFirst2 ? 4 : 0);
+        iter(std::integral_constant<int, act>{}, t_first + h, buf[h % PD]);
+    });
+    constexpr int U = PD == 1 ? 1 : 6;
+    for (int t0 = t_first + kHead; t0 <= t_last; t0 += U)
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int t = t0 + u;
+        if (t > t_last) break;
+        iter(std::integral_constant<int, (1 << NS) - 1>{}, t, buf[(u + kHead) % PD]);
     }
 }
 
