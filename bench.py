@@ -40,7 +40,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # built-in shape of the 2D wavefront step: (steps per pass, rows per interior
 # wavefront, prefetch distance, rows per frame wavefront)
-DEFAULT_WAVE_SHAPE = {"f32": (3, 12, 2, 6), "f64": (3, 12, 1, 6)}
+DEFAULT_WAVE_SHAPE = {"f32": (4, 16, 2, 8), "f64": (4, 16, 1, 8)}
 COPY_BYTES = 1 << 30
 CSRC = "paper_2406_16796_amd/csrc/"
 COMMON_SOURCES = [CSRC + "axf_stencil.h", CSRC + "axf_internal.h", "paper_2406_16796_amd/build.py"]
@@ -348,7 +348,7 @@ def pmc_rows(path):
     return out
 
 
-PROFILE_WARMUP = 3     # steps of the profile-only run before the timed ones (one three-step pass)
+PROFILE_WARMUP = 4     # steps of the profile-only run before the timed ones (one four-step pass)
 
 
 def pmc_summary(args):

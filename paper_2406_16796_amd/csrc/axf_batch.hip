@@ -44,7 +44,7 @@ static bool run_pairs(const Run *R)
 {
     if (!run_wave2d(R) || !R->multi) return false;
     int ci = 0, cf = 0;
-    run_pass_shape(R, &ci, &cf);
+    run_pass_shape(R, 2, &ci, &cf);
     return R->cfg.precision == AXF_F64 ? wave2d_pass_available(R->hk<double>(), 2, ci, cf)
                                        : wave2d_pass_available(R->hk<float>(), 2, ci, cf);
 }
@@ -70,7 +70,7 @@ static void run_blocks(const Run *R, bool wave, bool pair, long blk[kNumKinds])
     blk[kPair] = blk[kFrameA] = blk[kFrameB] = 0;
     if (pair) {
         int ci = 0, cf = 0;
-        run_pass_shape(R, &ci, &cf);
+        run_pass_shape(R, 2, &ci, &cf);
         if (R->cfg.precision == AXF_F64) wave2d_pair_blocks(R->hk<double>(), ci, cf, &blk[kPair], &blk[kFrameA], &blk[kFrameB]);
         else wave2d_pair_blocks(R->hk<float>(), ci, cf, &blk[kPair], &blk[kFrameA], &blk[kFrameB]);
     }
@@ -218,7 +218,7 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
             b.step0 = R->step;
             b.rec0 = R->rec_written;
             b.chunk = run_wave_chunk(R);
-            run_pass_shape(R, &b.pass_ci, &b.pass_cf);
+            run_pass_shape(R, 2, &b.pass_ci, &b.pass_cf);
             long nb[kNumKinds];
             run_blocks(R, g.wave, g.pair, nb);
             for (int q = 0; q < kNumKinds; q++) acc[q] += nb[q];

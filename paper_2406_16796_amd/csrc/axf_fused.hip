@@ -1609,9 +1609,9 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
     // formulas over the rows, relative to c0); before those, the stage only
     // takes its inputs.  Peeled at compile time, so the main loop has no
     // per-row branch.
-    constexpr int kLoad0 = NS == 3 ? -5 : -4;
-    constexpr int kFirst0 = NS == 3 ? -4 : -3, kFirst1 = NS == 3 ? -2 : 0, kFirst2 = 1;
-    constexpr int kHead = (NS == 3 ? kFirst2 : kFirst1) - kLoad0;
+    constexpr int kLoad0 = -2 - NS;
+    constexpr int kFirstTab[3][4] = {{-3, 0, 0, 0}, {-4, -2, 1, 0}, {-5, -3, -1, 2}};
+    constexpr int kHead = kFirstTab[NS - 2][NS - 1] - kLoad0;
     const int t_first = c0 + kLoad0, t_last = c1 + NS;
     (void)cs;
 #pragma unroll
@@ -1639,13 +1639,15 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
             sg[k].advance(r, bext0, bext1, bext2, pv.b0p_1, pv.b1n, pv.pb_2, pv.pn, e0in, e1in, k < NS - 1 || full,
                           ((ACT >> k) & 1) != 0);
         }
-        // (no warm-up iteration stores: its rows are all below c0)
-        if (ACT == (1 << NS) - 1 && own_x) {
+        // a stage stores only where it computes (a warm-up iteration may
+        // already hold a stored row of an early stage: four steps, row c0)
+        if (own_x) {
             // intermediate steps n + k + 1 (k < NS - 1): E0, B0z at row
             // t - 1 - k; E1, B1 and the axion level n + k + 2 at row t - 2 - k
 #pragma unroll
             for (int k = 0; k < NS - 1; k++) {
                 const int q = t - 2 - k;
+                if (((ACT >> k) & 1) == 0) continue;
                 const bool rows = q >= c0 && q < c1;
                 if (MODE == kCores && rows && q >= core_y0[k] && q < core_y1[k] && core_x[k])
                     stp(phi_slot(step + 2 + k), off(q), sg[k].pn);
@@ -1673,13 +1675,14 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
             // the axion level n + NS + 1 at row t - NS - 1
             const Stage<T>& sl = sg[NS - 1];
             const int qe = t - NS;
-            if (qe >= c0 && qe < c1) {
+            constexpr bool last_on = ((ACT >> (NS - 1)) & 1) != 0;
+            if (last_on && qe >= c0 && qe < c1) {
                 const unsigned o = off(qe);
                 ste(0, 0, o, sl.e0h_1[0]);
                 ste(0, 1, o, sl.e0h_1[1]);
                 ste(1, 2, o, sl.b0p_1);
             }
-            if (full) {
+            if (last_on && full) {
                 const unsigned o = off(qf);
 #pragma unroll
                 for (int c = 0; c < 3; c++) ste(2, c, o, sl.e1h_2[c]);
@@ -1692,7 +1695,9 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
     // the warm-up iterations t_first + h, h < kHead
     static_for<kHead>([&](auto hc) __attribute__((always_inline)) {
         constexpr int h = decltype(hc)::value, t_rel = kLoad0 + h;
-        constexpr int act = (t_rel >= kFirst0 ? 1 : 0) | (t_rel >= kFirst1 ? 2 : 0) | (NS == 3 && t_rel >= kFirst2 ? 4 : 0);
+        constexpr int act = (t_rel >= kFirstTab[NS - 2][0] ? 1 : 0) | (t_rel >= kFirstTab[NS - 2][1] ? 2 : 0) |
+                            (NS >= 3 && t_rel >= kFirstTab[NS - 2][2] ? 4 : 0) |
+                            (NS >= 4 && t_rel >= kFirstTab[NS - 2][3] ? 8 : 0);
         iter(std::integral_constant<int, act>{}, t_first + h, buf[h % PD]);
     });
     constexpr int U = PD == 1 ? 1 : 6;
@@ -1961,6 +1966,7 @@ bool wave2d_pass_available(const RunK<T>& h, int ns, int ci, int cf)
     if (ci <= 0 || cf <= 0 || ci % cf != 0) return false;
     if (ns == 2) return wave2d_split_pass<2>(h, ci, cf).in.interior() > 0;
     if (ns == 3) return wave2d_split_pass<3>(h, ci, cf).in.interior() > 0;
+    if (ns == 4) return wave2d_split_pass<4>(h, ci, cf).in.interior() > 0;
     return false;
 }
 
@@ -1970,6 +1976,7 @@ hipError_t launch_wave2d_pass(const RunK<T> *rk, const RunK<T>& h, long step, in
 {
     if (ns == 2) return launch_pass_ns<T, 2>(rk, h, step, ci, cf, pd, st, ws);
     if (ns == 3) return launch_pass_ns<T, 3>(rk, h, step, ci, cf, pd, st, ws);
+    if (ns == 4) return launch_pass_ns<T, 4>(rk, h, step, ci, cf, pd, st, ws);
     return hipErrorInvalidValue;
 }
 

@@ -30,17 +30,17 @@ template <int D> __host__ __device__ constexpr bool actE1(int c) { return D >= 2
 template <int D> __host__ __device__ constexpr bool actB1(int c) { return D >= 2 ? true : c != 0; }
 
 // Time levels rotate through slots: the E/B buffers and the Mur ghosts through
-// four (step n reads slot n mod 4, writes slot (n + 1) mod 4), the axion levels
-// and their ghosts through five (level L, the field at t = (L - 1/2) dt, in
-// slot L mod 5).  A pass of up to three steps reads the slots of step n while
-// its launches write those of steps n + 1 .. n + 3, all distinct.
-constexpr int kEmSlots = 4, kPhiSlots = 5;
+// five (step n reads slot n mod 5, writes slot (n + 1) mod 5), the axion levels
+// and their ghosts through six (level L, the field at t = (L - 1/2) dt, in
+// slot L mod 6).  A pass of up to four steps reads the slots of step n while
+// its launches write those of steps n + 1 .. n + 4, all distinct.
+constexpr int kEmSlots = 5, kPhiSlots = 6;
 __host__ __device__ constexpr int em_slot(long step) { return (int)(step % kEmSlots); }
 __host__ __device__ constexpr int phi_slot(long level) { return (int)(level % kPhiSlots); }
 
-// Uniform layout of a run's device buffer: 56 field arrays of equal size at
+// Uniform layout of a run's device buffer: 69 field arrays of equal size at
 // state_base + q * arr_stride (the 12 EM components of one slot together, then
-// the axion levels and the current scratch), and 174 boundary planes of equal
+// the axion levels and the current scratch), and 216 boundary planes of equal
 // size at face_base + q * face_stride (some unused for a given configuration).
 constexpr int kEmPerSlot = 12;
 __host__ __device__ constexpr int q_em(int kind, int slot, int comp) { return slot * kEmPerSlot + kind * 3 + comp; }  // kind 0 E0, 1 B0, 2 E1, 3 B1

@@ -81,7 +81,7 @@ bool run_wave2d(const Run *R);
 int run_wave_chunk(const Run *R);
 // rows per interior and frame wavefront of a pass of several steps, and the
 // most steps per pass
-void run_pass_shape(const Run *R, int *ci, int *cf);
+void run_pass_shape(const Run *R, int ns, int *ci, int *cf);
 int run_pass_steps(const Run *R);
 // the most steps per pass this run's grid and shape give (1: one step per pass)
 int run_pass_steps_taken(const Run *R);

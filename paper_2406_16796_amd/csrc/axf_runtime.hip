@@ -421,12 +421,14 @@ static int steps_fused(Run *R, int64_t nsteps)
         }
         // several steps per pass (2D) unless a diagnostic record falls on one of
         // them but the last: a pass stores no complete state of the steps inside it
-        // (three, else two, else one)
-        int ci = 0, cf = 0;
-        run_pass_shape(R, &ci, &cf);
+        // (four, else three, else two, else one)
+        int ci[5] = {0, 0, 0, 0, 0}, cf[5] = {0, 0, 0, 0, 0};
         const int nmax = run_pass_steps(R);
-        bool avail[4] = {false, false, false, false};
-        for (int k = 2; k <= nmax; k++) avail[k] = wave2d && R->multi && wave2d_pass_available<T>(h, k, ci, cf);
+        bool avail[5] = {false, false, false, false, false};
+        for (int k = 2; k <= nmax; k++) {
+            run_pass_shape(R, k, &ci[k], &cf[k]);
+            avail[k] = wave2d && R->multi && wave2d_pass_available<T>(h, k, ci[k], cf[k]);
+        }
         auto due = [&](long s) { return R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0; };
         auto clear = [&](long s, int k) {
             for (int q = 0; q < k; q++)
@@ -441,7 +443,7 @@ static int steps_fused(Run *R, int64_t nsteps)
             const bool multi = ns > 1;
             ensure_incident<D, T>(R, s, ns);
             const WaveStreams *wsp = ws.side ? &ws : nullptr;
-            hipError_t e = multi ? launch_wave2d_pass<T>(rk, h, s, ns, ci, cf, R->pass_pd, R->stream, wsp)
+            hipError_t e = multi ? launch_wave2d_pass<T>(rk, h, s, ns, ci[ns], cf[ns], R->pass_pd, R->stream, wsp)
                            : wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->pd, R->stream, wsp)
                                     : F::launch(rk, h, s, chunk, R->stream);
             if (e != hipSuccess) return hip_fail(e, "fused step launch");
@@ -537,7 +539,7 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     if (const char *pc = getenv("AXF_PASS_CHUNK")) R->pass_ci = atoi(pc);
     if (const char *pf = getenv("AXF_PASS_FRAME")) R->pass_cf = atoi(pf);
     if (const char *pp = getenv("AXF_PASS_PD")) R->pass_pd = atoi(pp);
-    if (const char *ps = getenv("AXF_PASS_STEPS")) R->pass_steps = atoi(ps) >= 3 ? 3 : 2;
+    if (const char *ps = getenv("AXF_PASS_STEPS")) R->pass_steps = atoi(ps) >= 4 ? 4 : (atoi(ps) == 3 ? 3 : 2);
     if (const char *pr = getenv("AXF_PASS_RING")) R->pass_ring = pr[0] != '0';
     R->use_fused = cfg->path == AXF_PATH_FUSED || (cfg->path == AXF_PATH_AUTO && fused_supported(cfg) && auto_fused_enabled(cfg));
     choose_scales(cfg, &R->s_phi, &R->s_1);
@@ -585,9 +587,9 @@ int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 8; }
 int run_pass_steps_taken(const Run *R)
 {
     if (!run_wave2d(R) || !R->multi) return 1;
-    int ci = 0, cf = 0;
-    run_pass_shape(R, &ci, &cf);
     for (int k = run_pass_steps(R); k >= 2; k--) {
+        int ci = 0, cf = 0;
+        run_pass_shape(R, k, &ci, &cf);
         const bool ok = R->cfg.precision == AXF_F64 ? wave2d_pass_available<double>(R->hd, k, ci, cf)
                                                     : wave2d_pass_available<float>(R->hf, k, ci, cf);
         if (ok) return k;
@@ -597,15 +599,17 @@ int run_pass_steps_taken(const Run *R)
 
 int run_pass_steps(const Run *R)
 {
-    // measured on 4096^2 (Gcell/s, two / three steps per pass at the best
-    // shapes): FP32 72.0 / 86.3, FP64 41.7 / 50.8
-    return R->pass_steps > 0 ? R->pass_steps : 3;
+    // measured on 4096^2 (Gcell/s, two / three / four steps per pass at the
+    // best shapes): FP32 72.0 / 93.4 / 107.4, FP64 41.7 / 55.2 / 56.1
+    return R->pass_steps > 0 ? R->pass_steps : 4;
 }
 
-void run_pass_shape(const Run *R, int *ci, int *cf)
+void run_pass_shape(const Run *R, int ns, int *ci, int *cf)
 {
-    *cf = R->pass_cf > 0 ? R->pass_cf : 6;
-    *ci = R->pass_ci > 0 ? R->pass_ci : 12;
+    // rows per interior / frame wavefront: 16 / 8 for four steps per pass
+    // (FP32 107.4 against 105.5 at 12 / 6), 12 / 6 for fewer
+    *cf = R->pass_cf > 0 ? R->pass_cf : (ns >= 4 ? 8 : 6);
+    *ci = R->pass_ci > 0 ? R->pass_ci : (ns >= 4 ? 16 : 12);
 }
 
 int run_step(Run *R, int64_t nsteps)
@@ -894,8 +898,8 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
     // several steps per pass: steps, rows per interior wavefront, per frame
     // wavefront, prefetch distance
     // (prefetch 0: the built-in one for the precision and steps)
-    const int passes[][4] = {{2, 8, 8, 0}, {2, 12, 6, 0}, {3, 12, 6, 0}, {3, 12, 6, 1},
-                            {3, 12, 6, 2}, {3, 8, 8, 0}, {3, 14, 7, 0}, {3, 16, 8, 0}};
+    const int passes[][4] = {{2, 8, 8, 0},  {2, 12, 6, 0}, {3, 12, 6, 0}, {3, 12, 6, 1}, {3, 16, 8, 0},
+                            {4, 16, 8, 0}, {4, 16, 8, 1}, {4, 12, 6, 0}, {4, 24, 8, 0}, {4, 16, 4, 0}};
     // dflt: the built-in shape; *taken: the most steps per pass the shape
     // gives on this grid (1: one step per pass)
     auto time_shape = [&](const TunedShape& sh, bool dflt, double *ms, int *taken) -> int {
@@ -983,19 +987,25 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
         best.chunk = 8;
         best.pd = wave2d_default_pd(f64, 1);
         best.multi = dflt_taken > 1;
-        best.pass_steps = 3;
-        best.pass_ci = 12;
-        best.pass_cf = 6;
-        best.pass_pd = 0;
+        best.pass_steps = 0;
+        best.pass_ci = best.pass_cf = best.pass_pd = 0;
         best_multi = best_single = dflt;
         best_taken = dflt_taken;
     }
     out->path = AXF_PATH_FUSED;
     out->steps_per_pass = best.multi ? best_taken : 1;
-    out->chunk = best.multi ? best.pass_ci : best.chunk;
+    // the shape the runs take (the built-in rows for the pass length when 0)
+    int eff_ci = best.pass_ci, eff_cf = best.pass_cf;
+    if (best.multi && (eff_ci <= 0 || eff_cf <= 0)) {
+        axf_run P;
+        P.pass_ci = best.pass_ci;
+        P.pass_cf = best.pass_cf;
+        run_pass_shape(&P, best_taken, &eff_ci, &eff_cf);
+    }
+    out->chunk = best.multi ? eff_ci : best.chunk;
     out->prefetch = best.multi ? (best.pass_pd > 0 ? best.pass_pd : wave2d_default_pd(c.precision == AXF_F64, best_taken))
                               : best.pd;
-    out->frame_chunk = best.multi ? best.pass_cf : 0;
+    out->frame_chunk = best.multi ? eff_cf : 0;
     out->ms_per_step = best.multi ? best_multi : best_single;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[tune_key(cfg)] = best;

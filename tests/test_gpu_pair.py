@@ -1,7 +1,7 @@
 """Passes of several steps of the 2D wavefront step (temporal blocking) against
 the one-step pass, through the C ABI.
 
-A pass advances the interior two or three steps with the same point formulas
+A pass advances the interior two, three or four steps with the same point formulas
 in the same order as one-step passes, and the boundary frame with one-step
 launches, so fields, diagnostic records and probabilities must be the same
 bits.  The one-step pass is itself tied to the oracle by the parity tests; one
@@ -45,14 +45,18 @@ def grid_2d(nx, ny, ax_bc, pml_n=8, seed=5):
     return cfg
 
 
-CI, CF = 12, 6          # the built-in rows per interior / frame wavefront
+def default_shape(ns):
+    """The built-in rows per interior / frame wavefront of an ns-step pass."""
+    return (16, 8) if ns >= 4 else (12, 6)
 
 
-def pass_available(cfg, ns, ci=CI, cf=CF):
+def pass_available(cfg, ns, ci=None, cf=None):
     """Whether the grid (Mur EM on x and y) has an interior for an ns-step pass:
     columns x0 - lo .. x0 - lo + 63 and rows c0 - 3 ns - 1 .. c0 + ci + ns clear
     of the margin, and a core of one segment and one frame chunk inside
     ns - 1 rings."""
+    if ci is None or cf is None:
+        ci, cf = default_shape(ns)
     n0, n1 = int(cfg["n"][0]), int(cfg["n"][1])
     nn1 = n1 + 1
     pml = int(cfg.get("pml_n", 20))
@@ -74,7 +78,7 @@ def pass_available(cfg, ns, ci=CI, cf=CF):
     return sx1 - sx0 >= need and (cy1 - cy0) * k >= need
 
 
-def model_launches(cfg, counts, nmax, diag_every, ci=CI, cf=CF):
+def model_launches(cfg, counts, nmax, diag_every, ci=None, cf=None):
     avail = {k: pass_available(cfg, k, ci=ci, cf=cf) for k in range(2, nmax + 1)}
     due = lambda s: diag_every > 0 and s % diag_every == 0
     step, launches = 0, 0
@@ -93,7 +97,7 @@ def model_launches(cfg, counts, nmax, diag_every, ci=CI, cf=CF):
 
 
 def run_steps(axf, monkeypatch, cfg, prec, counts, ns, diag_every=0, ci=None, cf=None):
-    """ns = 1: one step per pass; 2 or 3: passes of up to ns steps."""
+    """ns = 1: one step per pass; 2, 3 or 4: passes of up to ns steps."""
     monkeypatch.setenv("AXF_WAVE_PASS", "1" if ns > 1 else "0")
     monkeypatch.setenv("AXF_PASS_STEPS", str(max(ns, 2)))
     for name, v in (("AXF_PASS_CHUNK", ci), ("AXF_PASS_FRAME", cf)):
@@ -119,7 +123,7 @@ def assert_same(a, b, label):
     assert a.diag_now() == b.diag_now(), label
 
 
-@pytest.mark.parametrize("ns", [2, 3])
+@pytest.mark.parametrize("ns", [2, 3, 4])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("bc", ["periodic", "outflow", "pml", "reflect"])
 def test_pass_equals_single_bitwise(axf, monkeypatch, ns, prec, bc):
@@ -136,10 +140,11 @@ def test_pass_equals_single_bitwise(axf, monkeypatch, ns, prec, bc):
     assert_same(multi, one, "%d steps %s %s" % (ns, prec, bc))
 
 
-@pytest.mark.parametrize("ns", [2, 3])
+@pytest.mark.parametrize("ns", [2, 3, 4])
 @pytest.mark.parametrize("ci,cf", [(8, 8), (24, 8), (36, 6), (16, 4)])
 def test_pass_interior_chunks_bitwise(axf, monkeypatch, ns, ci, cf):
-    cfg = grid_2d(420, 331, W.AX_PML, pml_n=20, seed=11)
+    cfg = grid_2d(420 if ns < 4 else 520, 331, W.AX_PML, pml_n=20, seed=11)
+    assert pass_available(cfg, ns, ci=ci, cf=cf)
     multi, nm = run_steps(axf, monkeypatch, cfg, axf.F32, [60], ns, ci=ci, cf=cf)
     one, _ = run_steps(axf, monkeypatch, cfg, axf.F32, [60], 1)
     assert nm == model_launches(cfg, [60], ns, 0, ci=ci, cf=cf), nm
@@ -158,7 +163,7 @@ def test_pass_small_grid_falls_back(axf, monkeypatch):
         assert_same(multi, one, "small %dx%d" % (nx, ny))
 
 
-@pytest.mark.parametrize("ns", [2, 3])
+@pytest.mark.parametrize("ns", [2, 3, 4])
 def test_pass_matches_oracle(axf, monkeypatch, ns):
     cfg = grid_2d(420, 331, W.AX_PML)
     run, n = run_steps(axf, monkeypatch, cfg, axf.F64, [120], ns)
@@ -206,7 +211,7 @@ def smallest_grid(ns):
     return nx, ny
 
 
-@pytest.mark.parametrize("ns", [2, 3])
+@pytest.mark.parametrize("ns", [2, 3, 4])
 @pytest.mark.parametrize("dx,dy", [(0, 0), (1, 7), (59, 1)])
 def test_pass_smallest_interiors_bitwise(axf, monkeypatch, ns, dx, dy):
     """Grids at the edge of having an interior for the pass (one column or
