@@ -70,7 +70,7 @@ def full_2d():
 def oracle_2d():
     cfg = full_2d()
     ora = Oracle(cfg)
-    ora.step(6)
+    ora.step(8)
     return cfg, ora
 
 
@@ -80,7 +80,9 @@ def test_full_size_2d_fused_matches_oracle(axf, oracle_2d, prec):
     p = axf.F64 if prec == "f64" else axf.F32
     run = axf.Run(cfg, precision=p)
     assert run.uses_fused()
-    run.step(6)
+    run.step(8)
+    # the default the benchmark times: two four-step passes
+    assert run.last_step_timing()[1] == 2
     compare(run, ora, 1e-10 if prec == "f64" else 2e-5, "full 2d " + prec)
 
 
