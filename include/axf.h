@@ -182,7 +182,7 @@ int axf_last_step_timing(const axf_run *run, double *ms, int64_t *launches);
 /* ------------------------------------------------------------ tuning
  * Launch shape of the fused 2D step, chosen by timing every candidate on a
  * scratch run: one step per pass (rows per wavefront march, prefetch
- * distance) or passes of two or three steps (temporal blocking: steps per
+ * distance) or passes of two, three or four steps (temporal blocking: steps per
  * pass, rows per interior wavefront, rows per frame wavefront, prefetch
  * distance).  The best shape of each kind is kept in a process-wide table
  * keyed by dimensionality, precision, boundary kinds, PML width and the
@@ -198,7 +198,7 @@ typedef struct {
                                     interior of a pass of several steps) */
     int32_t prefetch;            /* rows prefetched ahead (fused 2D) */
     int32_t candidates;          /* shapes timed */
-    int32_t steps_per_pass;      /* most steps per pass (2 or 3), or 1 */
+    int32_t steps_per_pass;      /* most steps per pass (2, 3 or 4), or 1 */
     int32_t frame_chunk;         /* rows per frame wavefront of a pass of several steps (0 if 1) */
     double  ms_per_step;         /* best */
     double  default_ms_per_step; /* the built-in default shape */
