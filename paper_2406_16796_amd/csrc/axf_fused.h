@@ -12,7 +12,7 @@ namespace axf {
 struct WaveStreams {
     hipStream_t side;
     hipEvent_t fork, join;
-    // three-step passes: the stream of the interior's ring launch (null: the
+    // three- and four-step passes: the stream of the interior's ring launch (null: the
     // interior in one launch, the frame launches covering the ring instead)
     hipStream_t ring = nullptr;
     hipEvent_t ring_done = nullptr;
@@ -36,7 +36,7 @@ hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chu
 template <typename T>
 hipError_t launch_wave2d_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st,
                                const WaveStreams *ws);
-// NS steps per pass (NS = 2 or 3): the interior advanced NS steps in one
+// NS steps per pass (NS = 2, 3 or 4): the interior advanced NS steps in one
 // launch, the frame in NS one-step launches beside it
 template <typename T>
 bool wave2d_pass_available(const RunK<T>& h, int ns, int ci, int cf);

@@ -1215,7 +1215,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
 // ------------------------------------------------------ several steps per pass
 //
 // Temporal blocking of the interior march: a wavefront advances its rows NS
-// (2 or 3) time steps per pass.  Stage 0 is the one-step pipeline on the
+// (2, 3 or 4) time steps per pass.  Stage 0 is the one-step pipeline on the
 // loaded rows; stage k is the same pipeline one row behind stage k - 1, fed
 // from its registers (E, B and the axion level of step n + k) instead of from
 // memory, so each row of the state is read once and written once per NS
@@ -1470,7 +1470,8 @@ __global__ void __launch_bounds__(256, 3) k_wave2d(const RunK<T> *__restrict__ r
 
 // The pass.  Stage k is valid on lanes 2k + 1 .. 62 - 2k (each stage's
 // stencils lose a lane on either side twice), so the pass owns lanes
-// 2 NS - 1 .. 64 - 2 NS: 58 columns per wavefront for two steps, 54 for three.
+// 2 NS - 1 .. 64 - 2 NS: 58 columns per wavefront for two steps, 54 for three,
+// 50 for four.
 // The boundary frame is NS one-step launches in order on the side stream:
 // frame k advances step n + k everywhere but core k, the interior shrunk by
 // NS - 1 - k rings (a ring is one segment and one frame chunk), so frame k + 1
@@ -1887,7 +1888,7 @@ hipError_t launch_wave2d(const RunK<T> *rk, const RunK<T>& h, long step, int chu
 int wave2d_default_pd(bool f64, int ns)
 {
     // measured on 4096^2: one step per pass FP32 3, FP64 2; two steps FP32 2,
-    // FP64 3; three steps FP32 2, FP64 1
+    // FP64 3; three and four steps FP32 2, FP64 1
     if (ns <= 1) return f64 ? 2 : 3;
     if (ns == 2) return f64 ? 3 : 2;
     return f64 ? 1 : 2;
@@ -1915,7 +1916,8 @@ static hipError_t launch_pass_ns(const RunK<T> *rk, const RunK<T>& h, long step,
     WaveSplit rc{nis, nic, 1, nis - 1, 1, nic - 1, wp.in.wid};
     if (nis < 3 || nic < 3) rc.sx0 = rc.sx1 = rc.cy0 = rc.cy1 = 0;
     // (measured on 4096^2 FP32: three steps 93.6 Gcell/s split against 86.1;
-    // two steps 70.0 against 72.0, where the frames were cheap already)
+    // two steps 70.0 against 72.0, where the frames were cheap already; four
+    // steps are taken split)
     const bool split = NS >= 3 && ws && ws->side && ws->ring;
     if (!split) {
         // one interior launch; frame k leaves out core k

@@ -53,8 +53,8 @@ struct Run {
     bool multi = true;               // 2D fused: advance several steps per pass where possible
     int pass_ci = 0, pass_cf = 0;    // ... rows per interior / frame wavefront (0: default)
     int pass_pd = 0;                 // ... prefetch distance of the interior (0: default)
-    int pass_steps = 0;              // ... most steps per pass (2 or 3; 0: default)
-    bool pass_ring = true;           // ... three-step interior as core and ring launches
+    int pass_steps = 0;              // ... most steps per pass (2, 3 or 4; 0: default)
+    bool pass_ring = true;           // ... three- and four-step interior as core and ring launches
     hipStream_t side = nullptr;      // 2D fused: stream of the boundary-frame launch (created on use)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipStream_t ring = nullptr;      // 2D fused: stream of the interior's ring (passes of several steps)
