@@ -247,3 +247,36 @@ def test_pass_one_interior_launch_bitwise(axf, monkeypatch, prec):
     assert nw == ns == model_launches(cfg, counts, 3, 0), (nw, ns)
     assert_same(whole, one, "three steps, one interior launch")
     assert_same(split, one, "three steps, core and ring")
+
+
+def random_cases(count=16, seed=2406):
+    """Seeded random grids, boundaries, chunk shapes, pass lengths and step
+    sequences (with the pass model's availability, so every case takes
+    passes of the length it asks for)."""
+    rng = np.random.default_rng(seed)
+    bcs = [W.AX_PERIODIC, W.AX_OUTFLOW, W.AX_PML, W.AX_REFLECT]
+    shapes = [(8, 8), (12, 6), (16, 8), (16, 4), (20, 10), (24, 8)]
+    out = []
+    while len(out) < count:
+        ns = int(rng.integers(2, 5))
+        ci, cf = shapes[int(rng.integers(len(shapes)))]
+        nx, ny = int(rng.integers(300, 720)), int(rng.integers(120, 520))
+        bc = bcs[int(rng.integers(len(bcs)))]
+        pml = int(rng.integers(4, 24))
+        cfg = grid_2d(nx, ny, bc, pml_n=pml, seed=int(rng.integers(1, 1000)))
+        if not pass_available(cfg, ns, ci=ci, cf=cf):
+            continue
+        counts = [int(v) for v in rng.integers(1, 23, size=3)]
+        de = int(rng.choice([0, 5, 7, 11]))
+        out.append((ns, ci, cf, cfg, counts, de))
+    return out
+
+
+@pytest.mark.parametrize("case", range(16))
+def test_pass_random_grids_bitwise(axf, monkeypatch, case):
+    ns, ci, cf, cfg, counts, de = random_cases()[case]
+    multi, nm = run_steps(axf, monkeypatch, cfg, axf.F32, counts, ns, diag_every=de, ci=ci, cf=cf)
+    one, _ = run_steps(axf, monkeypatch, cfg, axf.F32, counts, 1, diag_every=de)
+    assert nm == model_launches(cfg, counts, ns, de, ci=ci, cf=cf), nm
+    assert_same(multi, one, "case %d: %d steps, %s rows, grid %s, counts %s, diag %d"
+                % (case, ns, (ci, cf), cfg["n"][:2], counts, de))
