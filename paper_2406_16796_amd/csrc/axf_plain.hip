@@ -645,8 +645,15 @@ __global__ void __launch_bounds__(256) k_e0c(const RunK<T> *__restrict__ rp, lon
 constexpr int kTX = 64, kTY = 4, kTZ = 4;
 enum TilePhase { kTE0C = 0, kTE1, kTB, kTPhi };
 
+// Occupancy in FP32 (measured on 512^3, Gcell/s of the whole step): E0 + the
+// axion current held at 96 VGPRs, 5 wavefronts per SIMD instead of 4, no
+// spills (16.0 -> 16.3); B at 8 instead of 7, some scalar registers spilled
+// to vector lanes (-> 17.2).  The axion update at 7 spills vector registers
+// and was slower.
 template <int D, typename T, int PH>
-__global__ void __launch_bounds__(256) k3_tile(const RunK<T> *__restrict__ rp, long step, int tz)
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && PH == kTE0C ? 5 : (sizeof(T) == 4 && PH == kTB ? 8 : 1))))
+k3_tile(const RunK<T> *__restrict__ rp, long step, int tz)
 {
     const RunK<T>& r = *rp;
     const int i = blockIdx.x * kTX + (threadIdx.x & (kTX - 1));
