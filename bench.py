@@ -480,7 +480,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--steps-scale", type=float, default=0.1,
                     help="step counts of the scan and serving legs relative to the workload's 1000-5000")
-    ap.add_argument("--serve-rates", default="8,16,32")
+    ap.add_argument("--serve-rates", default="8,32,128")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-slice", type=int, default=256,
                     help="server work slice per run and round, in units of 2^20 cell-updates")
