@@ -42,7 +42,7 @@ template <typename T>
 bool wave2d_pass_available(const RunK<T>& h, int ns, int ci, int cf);
 template <typename T>
 hipError_t launch_wave2d_pass(const RunK<T> *rk, const RunK<T>& h, long step, int ns, int ci, int cf, int pd,
-                              hipStream_t st, const WaveStreams *ws);
+                              hipStream_t st, const WaveStreams *ws, bool store_e = false);
 // built-in prefetch distance of the interior march for ns steps per pass
 int wave2d_default_pd(bool f64, int ns);
 // the two-step pass over the first n runs of a batch table: steps s and

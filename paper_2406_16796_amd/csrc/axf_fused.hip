@@ -1498,6 +1498,7 @@ struct WavePass {
     WaveSplit in;                 // the interior, in pass_width columns and ci-row chunks
     WaveSplit fr[NS];             // frame k (cf-row chunks); its rectangle is core k
     int ci;
+    int store_e;                  // also store E of step n + 1 (a record of step n follows)
 };
 
 template <int NS, typename R>
@@ -1505,6 +1506,7 @@ __host__ __device__ inline WavePass<NS> wave2d_split_pass(const R& h, int ci, in
 {
     WavePass<NS> p;
     p.ci = ci;
+    p.store_e = 0;
     WaveSplit& w = p.in;
     const int W = pass_width(NS), lo = pass_lane0(NS);
     w.wid = W;
@@ -1551,6 +1553,7 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
     const int e_rd = em_slot(step), e_wr = em_slot(step + NS);
     const int la = phi_slot(step), lb = phi_slot(step + 1);
     const int ci = wp.ci;
+    const bool store_e = __builtin_amdgcn_readfirstlane(wp.store_e) != 0;
     const int x0 = seg * W, gx = x0 - lo + lane;
     const bool own_x = lane >= lo && lane < lo + W;
     const int c0 = ch * ci, c1 = c0 + ci, cs = c0 - 3 * (NS - 1);   // stage 0 starts as if its chunk began at cs
@@ -1654,6 +1657,23 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
                     stp(phi_slot(step + 2 + k), off(q), sg[k].pn);
                 if (MODE == kCore && k == NS - 2 && rows)
                     stp(phi_slot(step + 2 + k), off(q), sg[k].pn);
+                // E of step n + 1, which the record of step n averages with
+                // E of step n (the ring stores it anyway; in one launch, only
+                // core 0 is the interior's alone)
+                if (MODE != kRing && k == 0 && store_e) {
+                    const int qe = t - 1;
+                    const bool in0 = MODE == kCore || core_x[0];
+                    if (in0 && qe >= c0 && qe < c1 && (MODE == kCore || (qe >= core_y0[0] && qe < core_y1[0]))) {
+                        const unsigned o = off(qe);
+                        stm(0, 0, 0, o, sg[0].e0h_1[0]);
+                        stm(0, 0, 1, o, sg[0].e0h_1[1]);
+                    }
+                    if (in0 && rows && (MODE == kCore || (q >= core_y0[0] && q < core_y1[0]))) {
+                        const unsigned o = off(q);
+#pragma unroll
+                        for (int c = 0; c < 3; c++) stm(0, 2, c, o, sg[0].e1h_2[c]);
+                    }
+                }
                 if (MODE == kRing) {
                     const int qe = t - 1 - k;
                     if (qe >= c0 && qe < c1) {
@@ -1905,9 +1925,10 @@ static void launch_interior(const RunK<T> *rk, long step, const WavePass<NS>& wp
 
 template <typename T, int NS>
 static hipError_t launch_pass_ns(const RunK<T> *rk, const RunK<T>& h, long step, int ci, int cf, int pd, hipStream_t st,
-                                 const WaveStreams *ws)
+                                 const WaveStreams *ws, bool store_e)
 {
-    const WavePass<NS> wp = wave2d_split_pass<NS>(h, ci, cf);
+    WavePass<NS> wp = wave2d_split_pass<NS>(h, ci, cf);
+    wp.store_e = store_e ? 1 : 0;
     if (wp.in.interior() == 0) return hipErrorInvalidValue;
     if (pd <= 0) pd = wave2d_default_pd(sizeof(T) == 8, NS);
     // ring and core of the interior (the core empty when the interior is
@@ -1974,18 +1995,18 @@ bool wave2d_pass_available(const RunK<T>& h, int ns, int ci, int cf)
 
 template <typename T>
 hipError_t launch_wave2d_pass(const RunK<T> *rk, const RunK<T>& h, long step, int ns, int ci, int cf, int pd,
-                              hipStream_t st, const WaveStreams *ws)
+                              hipStream_t st, const WaveStreams *ws, bool store_e)
 {
-    if (ns == 2) return launch_pass_ns<T, 2>(rk, h, step, ci, cf, pd, st, ws);
-    if (ns == 3) return launch_pass_ns<T, 3>(rk, h, step, ci, cf, pd, st, ws);
-    if (ns == 4) return launch_pass_ns<T, 4>(rk, h, step, ci, cf, pd, st, ws);
+    if (ns == 2) return launch_pass_ns<T, 2>(rk, h, step, ci, cf, pd, st, ws, store_e);
+    if (ns == 3) return launch_pass_ns<T, 3>(rk, h, step, ci, cf, pd, st, ws, store_e);
+    if (ns == 4) return launch_pass_ns<T, 4>(rk, h, step, ci, cf, pd, st, ws, store_e);
     return hipErrorInvalidValue;
 }
 
 template bool wave2d_pass_available<float>(const RunK<float>&, int, int, int);
 template bool wave2d_pass_available<double>(const RunK<double>&, int, int, int);
-template hipError_t launch_wave2d_pass<float>(const RunK<float> *, const RunK<float>&, long, int, int, int, int, hipStream_t, const WaveStreams *);
-template hipError_t launch_wave2d_pass<double>(const RunK<double> *, const RunK<double>&, long, int, int, int, int, hipStream_t, const WaveStreams *);
+template hipError_t launch_wave2d_pass<float>(const RunK<float> *, const RunK<float>&, long, int, int, int, int, hipStream_t, const WaveStreams *, bool);
+template hipError_t launch_wave2d_pass<double>(const RunK<double> *, const RunK<double>&, long, int, int, int, int, hipStream_t, const WaveStreams *, bool);
 template hipError_t launch_wave2d<float>(const RunK<float> *, const RunK<float>&, long, int, int, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d<double>(const RunK<double> *, const RunK<double>&, long, int, int, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d_batch<float>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);

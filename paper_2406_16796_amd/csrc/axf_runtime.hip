@@ -420,8 +420,10 @@ static int steps_fused(Run *R, int64_t nsteps)
             ws = WaveStreams{R->side, R->ev_fork, R->ev_join, R->pass_ring ? R->ring : nullptr, R->ev_ring};
         }
         // several steps per pass (2D) unless a diagnostic record falls on one of
-        // them but the last: a pass stores no complete state of the steps inside it
-        // (four, else three, else two, else one)
+        // its steps but the first: a pass stores no complete state of the steps
+        // inside it.  A record of its first step n reads the state of step n
+        // (untouched by the pass) and E of step n + 1, which the pass then
+        // also stores everywhere (four, else three, else two, else one)
         int ci[5] = {0, 0, 0, 0, 0}, cf[5] = {0, 0, 0, 0, 0};
         const int nmax = run_pass_steps(R);
         bool avail[5] = {false, false, false, false, false};
@@ -431,7 +433,7 @@ static int steps_fused(Run *R, int64_t nsteps)
         }
         auto due = [&](long s) { return R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0; };
         auto clear = [&](long s, int k) {
-            for (int q = 0; q < k; q++)
+            for (int q = 1; q < k; q++)
                 if (due(s + q)) return false;
             return true;
         };
@@ -443,11 +445,11 @@ static int steps_fused(Run *R, int64_t nsteps)
             const bool multi = ns > 1;
             ensure_incident<D, T>(R, s, ns);
             const WaveStreams *wsp = ws.side ? &ws : nullptr;
-            hipError_t e = multi ? launch_wave2d_pass<T>(rk, h, s, ns, ci[ns], cf[ns], R->pass_pd, R->stream, wsp)
+            hipError_t e = multi ? launch_wave2d_pass<T>(rk, h, s, ns, ci[ns], cf[ns], R->pass_pd, R->stream, wsp, due(s))
                            : wave2d ? launch_wave2d<T>(rk, h, s, chunk, R->pd, R->stream, wsp)
                                     : F::launch(rk, h, s, chunk, R->stream);
             if (e != hipSuccess) return hip_fail(e, "fused step launch");
-            if (!multi && due(s)) {
+            if (due(s)) {
                 Plain<D, T>::diag(rk, h, s, R->rec_written % h.rec_cap, R->stream);
                 R->rec_written++;
             }
