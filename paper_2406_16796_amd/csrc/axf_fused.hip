@@ -1179,7 +1179,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                     T lap = T(0);
                     lap += ((up_pb - T(2) * pb) + dn_pb) * r.inv_dx2[0];
                     lap += ((pb_1 - T(2) * pb) + pb_3) * r.inv_dx2[1];
-                    T sdt = (!INTERIOR && (r.axbc[0] == AXF_AX_PML || r.axbc[1] == AXF_AX_PML)) ? pml_sdt<2>(*rp, gi, gj, 0) : T(0);
+                    T sdt = (r.axbc[0] == AXF_AX_PML || r.axbc[1] == AXF_AX_PML) ? pml_sdt<2>(*rp, gi, gj, 0) : T(0);
                     T x = r.dt2 * ((sax - r.m2 * pb) + lap) - sdt * sdt * pb;
                     T num = ((x + sdt * pa) + T(2) * pb) - pa;
                     T pn = num;
@@ -1252,7 +1252,8 @@ struct Stage {
     // phi at t - 2) only when full
     template <typename K>
     __device__ __forceinline__ void advance(const K& r, T bext0, T bext1, T bext2, T in_b0z, const T in_b1[3], T in_pa,
-                                            T in_pb, const T e0m[2], const T e1m[3], bool full, bool compute = true)
+                                            T in_pb, const T e0m[2], const T e1m[3], bool full, bool compute = true,
+                                            T sdt = T(0))
     {
         b0z_2 = b0z_1; b0z_1 = b0z_0; b0z_0 = in_b0z;
         pa_3 = pa_2; pa_2 = pa_1; pa_1 = in_pa;
@@ -1383,9 +1384,9 @@ struct Stage {
             T lap = T(0);
             lap += ((up_pb - T(2) * pb) + dn_pb) * r.inv_dx2[0];
             lap += ((pb_1 - T(2) * pb) + pb_3) * r.inv_dx2[1];
-            T sdt = T(0);
             T x = r.dt2 * ((sax - r.m2 * pb) + lap) - sdt * sdt * pb;
             pn = ((x + sdt * pa) + T(2) * pb) - pa;
+            if (sdt != T(0)) pn = pn / (T(1) + sdt);
         }
     }
 };
@@ -1413,8 +1414,8 @@ __host__ __device__ inline WaveSplit wave2d_split(const R& h, int chunk)
     w.wid = kWaveOut;
     w.nseg = (h.nn[0] + kWaveOut - 1) / kWaveOut;
     w.nch = (h.nn[1] + chunk - 1) / chunk;
-    const int mxg = 1 + (h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
-    const int myg = 1 + (h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
+    // (the damping layer of a PML axis is interior: the marches apply it)
+    const int mxg = 1, myg = 1;
     // x0 = seg * kWaveOut: need x0 - 3 >= mxg and x0 + 60 <= n0 - 1 - mxg
     w.sx0 = (mxg + 3 + kWaveOut - 1) / kWaveOut;
     w.sx1 = (h.n[0] - 1 - mxg - 60) >= 0 ? (h.n[0] - 1 - mxg - 60) / kWaveOut + 1 : 0;
@@ -1512,8 +1513,8 @@ __host__ __device__ inline WavePass<NS> wave2d_split_pass(const R& h, int ci, in
     w.wid = W;
     w.nseg = (h.nn[0] + W - 1) / W;
     w.nch = (h.nn[1] + ci - 1) / ci;
-    const int mxg = 1 + (h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
-    const int myg = 1 + (h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
+    // (the damping layer of a PML axis is interior: the marches apply it)
+    const int mxg = 1, myg = 1;
     // columns x0 - lo .. x0 - lo + 63 and rows c0 - 3 NS - 1 .. c0 + ci + NS
     // (everything the pass loads or computes) stay at least the margin inside
     w.sx0 = (mxg + lo + W - 1) / W;
@@ -1596,6 +1597,34 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
     };
 
     const T bext0 = bext_at(*rp, 0, gx), bext1 = bext_at(*rp, 1, gx), bext2 = bext_at(*rp, 2, gx);
+    // sigma dt of the axion damping layer (Sec. II.D) at this column, combined
+    // per row with the row's as the unfused kernel combines the axes
+    const bool pmlx = rp->axbc[0] == AXF_AX_PML, pmly = rp->axbc[1] == AXF_AX_PML;
+    const int pml_n = rp->pml_n, n0c = rp->n[0], n1c = rp->n[1];
+    const T sdt_max = rp->pml_sdt_max;
+    bool lx = false;
+    T sdx = T(0);
+    if (pmlx) {
+        const int dist = gx < n0c - 1 - gx ? gx : n0c - 1 - gx;
+        if (dist < pml_n) {
+            const T q = T(1) - T(dist) / T(pml_n);
+            sdx = sdt_max * q * q * q;
+            lx = true;
+        }
+    }
+    auto sdt_at = [&](int row) __attribute__((always_inline)) -> T {
+        T s = T(0);
+        if (lx) s = sdx > s ? sdx : s;
+        if (pmly) {
+            const int dist = row < n1c - 1 - row ? row : n1c - 1 - row;
+            if (dist < pml_n) {
+                const T q = T(1) - T(dist) / T(pml_n);
+                const T sd = sdt_max * q * q * q;
+                s = sd > s ? sd : s;
+            }
+        }
+        return s;
+    };
     // core k of an intermediate level: segments and rows of frame k's rectangle
     bool core_x[NS];
     int core_y0[NS], core_y1[NS];
@@ -1631,7 +1660,7 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
         const T e1m[3] = {P.e1m[0], P.e1m[1], P.e1m[2]};
         if (t + PD <= t_last) prefetch(t + PD, P);
         // stage 0: step n on the loaded rows
-        sg[0].advance(r, bext0, bext1, bext2, b0z, b1, pa, pb, e0m, e1m, true, (ACT & 1) != 0);
+        sg[0].advance(r, bext0, bext1, bext2, b0z, b1, pa, pb, e0m, e1m, true, (ACT & 1) != 0, sdt_at(t - 2));
         // stage k: step n + k, one row behind stage k - 1, from its registers
         const int qf = t - NS - 1;              // the last stage's E1, B1, phi row
         const bool full = qf >= c0 && qf < c1;
@@ -1641,7 +1670,7 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
             const T e1in[3] = {pv.e1h_3[0], pv.e1h_3[1], pv.e1h_3[2]};
             const T e0in[2] = {pv.e0h_2[0], pv.e0h_2[1]};
             sg[k].advance(r, bext0, bext1, bext2, pv.b0p_1, pv.b1n, pv.pb_2, pv.pn, e0in, e1in, k < NS - 1 || full,
-                          ((ACT >> k) & 1) != 0);
+                          ((ACT >> k) & 1) != 0, sdt_at(t - k - 2));
         }
         // a stage stores only where it computes (a warm-up iteration may
         // already hold a stored row of an early stage: four steps, row c0)

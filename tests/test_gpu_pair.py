@@ -55,15 +55,14 @@ def default_shape(ns):
 def pass_available(cfg, ns, ci=None, cf=None):
     """Whether the grid (Mur EM on x and y) has an interior for an ns-step pass:
     columns x0 - lo .. x0 - lo + 63 and rows c0 - 3 ns - 1 .. c0 + ci + ns clear
-    of the margin, and a core of one segment and one frame chunk inside
-    ns - 1 rings."""
+    of the face ghost ring, and a core of one segment and one frame chunk
+    inside ns - 1 rings."""
     if ci is None or cf is None:
         ci, cf = default_shape(ns)
     n0, n1 = int(cfg["n"][0]), int(cfg["n"][1])
     nn1 = n1 + 1
-    pml = int(cfg.get("pml_n", 20))
-    mxg = 1 + (pml if cfg["ax_bc"][0] == W.AX_PML else 0)
-    myg = 1 + (pml if cfg["ax_bc"][1] == W.AX_PML else 0)
+    # the margin is the face ghost ring: a damping layer is interior
+    mxg = myg = 1
     wid, lo = 66 - 4 * ns, 2 * ns - 1
     sx0 = -(-(mxg + lo) // wid)
     r = n0 - 1 - mxg - (63 - lo)
