@@ -1179,7 +1179,9 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
                     T lap = T(0);
                     lap += ((up_pb - T(2) * pb) + dn_pb) * r.inv_dx2[0];
                     lap += ((pb_1 - T(2) * pb) + pb_3) * r.inv_dx2[1];
-                    T sdt = (r.axbc[0] == AXF_AX_PML || r.axbc[1] == AXF_AX_PML) ? pml_sdt<2>(*rp, gi, gj, 0) : T(0);
+                    // (an FP64 interior keeps clear of a damping layer)
+                    T sdt = ((!INTERIOR || sizeof(T) == 4) && (r.axbc[0] == AXF_AX_PML || r.axbc[1] == AXF_AX_PML))
+                                ? pml_sdt<2>(*rp, gi, gj, 0) : T(0);
                     T x = r.dt2 * ((sax - r.m2 * pb) + lap) - sdt * sdt * pb;
                     T num = ((x + sdt * pa) + T(2) * pb) - pa;
                     T pn = num;
@@ -1414,8 +1416,13 @@ __host__ __device__ inline WaveSplit wave2d_split(const R& h, int chunk)
     w.wid = kWaveOut;
     w.nseg = (h.nn[0] + kWaveOut - 1) / kWaveOut;
     w.nch = (h.nn[1] + chunk - 1) / chunk;
-    // (the damping layer of a PML axis is interior: the marches apply it)
-    const int mxg = 1, myg = 1;
+    // the damping layer of a PML axis is interior in FP32, where the marches
+    // apply it (4096^2: 106.5 -> 110.9 Gcell/s); in FP64 its divisions cost
+    // the interior more than the smaller frame saves (58.0 -> 53.7), so there
+    // the layer stays in the frame
+    using TT = decltype(h.half);
+    const int mxg = 1 + (sizeof(TT) == 8 && h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
+    const int myg = 1 + (sizeof(TT) == 8 && h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
     // x0 = seg * kWaveOut: need x0 - 3 >= mxg and x0 + 60 <= n0 - 1 - mxg
     w.sx0 = (mxg + 3 + kWaveOut - 1) / kWaveOut;
     w.sx1 = (h.n[0] - 1 - mxg - 60) >= 0 ? (h.n[0] - 1 - mxg - 60) / kWaveOut + 1 : 0;
@@ -1513,8 +1520,13 @@ __host__ __device__ inline WavePass<NS> wave2d_split_pass(const R& h, int ci, in
     w.wid = W;
     w.nseg = (h.nn[0] + W - 1) / W;
     w.nch = (h.nn[1] + ci - 1) / ci;
-    // (the damping layer of a PML axis is interior: the marches apply it)
-    const int mxg = 1, myg = 1;
+    // the damping layer of a PML axis is interior in FP32, where the marches
+    // apply it (4096^2: 106.5 -> 110.9 Gcell/s); in FP64 its divisions cost
+    // the interior more than the smaller frame saves (58.0 -> 53.7), so there
+    // the layer stays in the frame
+    using TT = decltype(h.half);
+    const int mxg = 1 + (sizeof(TT) == 8 && h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
+    const int myg = 1 + (sizeof(TT) == 8 && h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
     // columns x0 - lo .. x0 - lo + 63 and rows c0 - 3 NS - 1 .. c0 + ci + NS
     // (everything the pass loads or computes) stay at least the margin inside
     w.sx0 = (mxg + lo + W - 1) / W;
@@ -1598,8 +1610,10 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
 
     const T bext0 = bext_at(*rp, 0, gx), bext1 = bext_at(*rp, 1, gx), bext2 = bext_at(*rp, 2, gx);
     // sigma dt of the axion damping layer (Sec. II.D) at this column, combined
-    // per row with the row's as the unfused kernel combines the axes
-    const bool pmlx = rp->axbc[0] == AXF_AX_PML, pmly = rp->axbc[1] == AXF_AX_PML;
+    // per row with the row's as the unfused kernel combines the axes (FP32
+    // only: an FP64 interior keeps clear of the layer)
+    constexpr bool kDamp = sizeof(T) == 4;
+    const bool pmlx = kDamp && rp->axbc[0] == AXF_AX_PML, pmly = kDamp && rp->axbc[1] == AXF_AX_PML;
     const int pml_n = rp->pml_n, n0c = rp->n[0], n1c = rp->n[1];
     const T sdt_max = rp->pml_sdt_max;
     bool lx = false;

@@ -52,17 +52,19 @@ def default_shape(ns):
     return (16, 8) if ns >= 4 else (12, 6)
 
 
-def pass_available(cfg, ns, ci=None, cf=None):
+def pass_available(cfg, ns, ci=None, cf=None, f64=False):
     """Whether the grid (Mur EM on x and y) has an interior for an ns-step pass:
     columns x0 - lo .. x0 - lo + 63 and rows c0 - 3 ns - 1 .. c0 + ci + ns clear
-    of the face ghost ring, and a core of one segment and one frame chunk
-    inside ns - 1 rings."""
+    of the face ghost ring (in FP64 also of a damping layer), and a core of one
+    segment and one frame chunk inside ns - 1 rings."""
     if ci is None or cf is None:
         ci, cf = default_shape(ns)
     n0, n1 = int(cfg["n"][0]), int(cfg["n"][1])
     nn1 = n1 + 1
-    # the margin is the face ghost ring: a damping layer is interior
-    mxg = myg = 1
+    # the margin is the face ghost ring; in FP64 a damping layer too
+    pml = int(cfg.get("pml_n", 20)) if f64 else 0
+    mxg = 1 + (pml if cfg["ax_bc"][0] == W.AX_PML else 0)
+    myg = 1 + (pml if cfg["ax_bc"][1] == W.AX_PML else 0)
     wid, lo = 66 - 4 * ns, 2 * ns - 1
     sx0 = -(-(mxg + lo) // wid)
     r = n0 - 1 - mxg - (63 - lo)
@@ -79,8 +81,8 @@ def pass_available(cfg, ns, ci=None, cf=None):
     return sx1 - sx0 >= need and (cy1 - cy0) * k >= need
 
 
-def model_launches(cfg, counts, nmax, diag_every, ci=None, cf=None):
-    avail = {k: pass_available(cfg, k, ci=ci, cf=cf) for k in range(2, nmax + 1)}
+def model_launches(cfg, counts, nmax, diag_every, ci=None, cf=None, f64=False):
+    avail = {k: pass_available(cfg, k, ci=ci, cf=cf, f64=f64) for k in range(2, nmax + 1)}
     due = lambda s: diag_every > 0 and s % diag_every == 0
     step, launches = 0, 0
     for n in counts:
@@ -131,12 +133,12 @@ def test_pass_equals_single_bitwise(axf, monkeypatch, ns, prec, bc):
     code = {"periodic": W.AX_PERIODIC, "outflow": W.AX_OUTFLOW, "pml": W.AX_PML, "reflect": W.AX_REFLECT}[bc]
     p = axf.F32 if prec == "f32" else axf.F64
     cfg = grid_2d(420, 331, code)
-    assert pass_available(cfg, ns)
+    assert pass_available(cfg, ns, f64=prec == "f64")
     counts = [1, 44, 17, 2]          # odd starts; diagnostics every 10 steps break passes
     multi, nm = run_steps(axf, monkeypatch, cfg, p, counts, ns, diag_every=10)
     one, n1 = run_steps(axf, monkeypatch, cfg, p, counts, 1, diag_every=10)
     assert n1 == sum(counts)
-    assert nm == model_launches(cfg, counts, ns, 10), nm
+    assert nm == model_launches(cfg, counts, ns, 10, f64=prec == "f64"), nm
     assert nm < (0.75 if ns == 2 else 0.6) * sum(counts), nm
     assert_same(multi, one, "%d steps %s %s" % (ns, prec, bc))
 
@@ -245,7 +247,7 @@ def test_pass_one_interior_launch_bitwise(axf, monkeypatch, prec):
     whole, nw = run_steps(axf, monkeypatch, cfg, p, counts, 3)
     monkeypatch.delenv("AXF_PASS_RING")
     one, _ = run_steps(axf, monkeypatch, cfg, p, counts, 1)
-    assert nw == ns == model_launches(cfg, counts, 3, 0), (nw, ns)
+    assert nw == ns == model_launches(cfg, counts, 3, 0, f64=prec == "f64"), (nw, ns)
     assert_same(whole, one, "three steps, one interior launch")
     assert_same(split, one, "three steps, core and ring")
 
