@@ -1417,12 +1417,13 @@ __host__ __device__ inline WaveSplit wave2d_split(const R& h, int chunk)
     w.nseg = (h.nn[0] + kWaveOut - 1) / kWaveOut;
     w.nch = (h.nn[1] + chunk - 1) / chunk;
     // the damping layer of a PML axis is interior in FP32, where the marches
-    // apply it (4096^2: 106.5 -> 110.9 Gcell/s); in FP64 its divisions cost
-    // the interior more than the smaller frame saves (58.0 -> 53.7), so there
-    // the layer stays in the frame
+    // apply it from the run's profile table (4096^2: 106.5 -> 110.9 Gcell/s);
+    // in FP64 the damped points cost the interior more than the smaller frame
+    // saves (58.0 -> 55.6), and a layer wider than the table stays out too
     using TT = decltype(h.half);
-    const int mxg = 1 + (sizeof(TT) == 8 && h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
-    const int myg = 1 + (sizeof(TT) == 8 && h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
+    const bool out = sizeof(TT) == 8 || h.pml_n > kPmlProf;
+    const int mxg = 1 + (out && h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
+    const int myg = 1 + (out && h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
     // x0 = seg * kWaveOut: need x0 - 3 >= mxg and x0 + 60 <= n0 - 1 - mxg
     w.sx0 = (mxg + 3 + kWaveOut - 1) / kWaveOut;
     w.sx1 = (h.n[0] - 1 - mxg - 60) >= 0 ? (h.n[0] - 1 - mxg - 60) / kWaveOut + 1 : 0;
@@ -1521,12 +1522,13 @@ __host__ __device__ inline WavePass<NS> wave2d_split_pass(const R& h, int ci, in
     w.nseg = (h.nn[0] + W - 1) / W;
     w.nch = (h.nn[1] + ci - 1) / ci;
     // the damping layer of a PML axis is interior in FP32, where the marches
-    // apply it (4096^2: 106.5 -> 110.9 Gcell/s); in FP64 its divisions cost
-    // the interior more than the smaller frame saves (58.0 -> 53.7), so there
-    // the layer stays in the frame
+    // apply it from the run's profile table (4096^2: 106.5 -> 110.9 Gcell/s);
+    // in FP64 the damped points cost the interior more than the smaller frame
+    // saves (58.0 -> 55.6), and a layer wider than the table stays out too
     using TT = decltype(h.half);
-    const int mxg = 1 + (sizeof(TT) == 8 && h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
-    const int myg = 1 + (sizeof(TT) == 8 && h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
+    const bool out = sizeof(TT) == 8 || h.pml_n > kPmlProf;
+    const int mxg = 1 + (out && h.axbc[0] == AXF_AX_PML ? h.pml_n : 0);
+    const int myg = 1 + (out && h.axbc[1] == AXF_AX_PML ? h.pml_n : 0);
     // columns x0 - lo .. x0 - lo + 63 and rows c0 - 3 NS - 1 .. c0 + ci + NS
     // (everything the pass loads or computes) stay at least the margin inside
     w.sx0 = (mxg + lo + W - 1) / W;
@@ -1610,30 +1612,28 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
 
     const T bext0 = bext_at(*rp, 0, gx), bext1 = bext_at(*rp, 1, gx), bext2 = bext_at(*rp, 2, gx);
     // sigma dt of the axion damping layer (Sec. II.D) at this column, combined
-    // per row with the row's as the unfused kernel combines the axes (FP32
-    // only: an FP64 interior keeps clear of the layer)
+    // per row with the row's as the unfused kernel combines the axes; the
+    // values come from the run's table of the profile (FP32 only: an FP64
+    // interior, and a layer wider than the table, keep clear of it)
     constexpr bool kDamp = sizeof(T) == 4;
     const bool pmlx = kDamp && rp->axbc[0] == AXF_AX_PML, pmly = kDamp && rp->axbc[1] == AXF_AX_PML;
     const int pml_n = rp->pml_n, n0c = rp->n[0], n1c = rp->n[1];
-    const T sdt_max = rp->pml_sdt_max;
     bool lx = false;
     T sdx = T(0);
-    if (pmlx) {
+    if (pmlx && pml_n <= kPmlProf) {
         const int dist = gx < n0c - 1 - gx ? gx : n0c - 1 - gx;
         if (dist < pml_n) {
-            const T q = T(1) - T(dist) / T(pml_n);
-            sdx = sdt_max * q * q * q;
+            sdx = rp->pml_prof[dist];
             lx = true;
         }
     }
     auto sdt_at = [&](int row) __attribute__((always_inline)) -> T {
         T s = T(0);
         if (lx) s = sdx > s ? sdx : s;
-        if (pmly) {
+        if (pmly && pml_n <= kPmlProf) {
             const int dist = row < n1c - 1 - row ? row : n1c - 1 - row;
             if (dist < pml_n) {
-                const T q = T(1) - T(dist) / T(pml_n);
-                const T sd = sdt_max * q * q * q;
+                const T sd = rp->pml_prof[dist];
                 s = sd > s ? sd : s;
             }
         }

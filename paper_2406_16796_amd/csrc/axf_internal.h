@@ -54,6 +54,7 @@ __host__ __device__ constexpr int q_mur(int o, int d, int side, int comp, int sl
 }
 constexpr int kNumFaces = 6 * kPhiSlots + 36 * kEmSlots;
 constexpr int kIncLevels = 17;   // time levels per laser table fill (16 steps)
+constexpr int kPmlProf = 64;     // damping-layer thicknesses the wavefront interiors tabulate
 
 // Immutable per-run descriptor, stored in device memory once at creation.
 // Time-level slots rotate with the step counter (em_slot, phi_slot).
@@ -71,6 +72,9 @@ struct RunK {
     int slab_lo, slab_hi;
     T pml_sdt_max;            // sigma_max * dt
     int pml_n;
+    // sigma dt at distance d < pml_n from the face (d < kPmlProf), computed with
+    // the point formula's operations, so a table value is the formula's bits
+    T pml_prof[kPmlProf];
     T out_r[3];               // dt / dx for the outflow ghost solve
     // FP64 parameters
     double dt, dx[3], murc[3], m2d;

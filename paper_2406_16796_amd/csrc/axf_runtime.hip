@@ -210,6 +210,10 @@ static void fill_runk(RunK<T>& k, const axf_config *c, const Layout& L, char *ba
     k.slab_lo = c->slab_lo;
     k.slab_hi = c->slab_hi;
     k.pml_sdt_max = (T)c->pml_sigma_dt;
+    for (int d = 0; d < kPmlProf; d++) {
+        T q = T(1) - T(d) / T(c->pml_n > 0 ? c->pml_n : 1);
+        k.pml_prof[d] = k.pml_sdt_max * q * q * q;
+    }
     k.pml_n = c->pml_n > 0 ? c->pml_n : 1;
     k.dt = c->dt;
     k.s_phi = s_phi;

@@ -55,14 +55,16 @@ def default_shape(ns):
 def pass_available(cfg, ns, ci=None, cf=None, f64=False):
     """Whether the grid (Mur EM on x and y) has an interior for an ns-step pass:
     columns x0 - lo .. x0 - lo + 63 and rows c0 - 3 ns - 1 .. c0 + ci + ns clear
-    of the face ghost ring (in FP64 also of a damping layer), and a core of one
+    of the face ghost ring (and of a damping layer in FP64), and a core of one
     segment and one frame chunk inside ns - 1 rings."""
     if ci is None or cf is None:
         ci, cf = default_shape(ns)
     n0, n1 = int(cfg["n"][0]), int(cfg["n"][1])
     nn1 = n1 + 1
-    # the margin is the face ghost ring; in FP64 a damping layer too
-    pml = int(cfg.get("pml_n", 20)) if f64 else 0
+    # the margin is the face ghost ring, and a damping layer in FP64 or when
+    # wider than the run's 64-entry profile table
+    pml = int(cfg.get("pml_n", 20))
+    pml = pml if (f64 or pml > 64) else 0
     mxg = 1 + (pml if cfg["ax_bc"][0] == W.AX_PML else 0)
     myg = 1 + (pml if cfg["ax_bc"][1] == W.AX_PML else 0)
     wid, lo = 66 - 4 * ns, 2 * ns - 1
