@@ -429,9 +429,9 @@ def trace_summary(args):
              "The run times the fused path twice (with and without diagnostics) and the unfused phase "
              "sequence once; the copy kernel is the bandwidth calibration.  In 2D a pass of NS steps is "
              "`k_wave2d_pass<T, PD, NS, MODE>` over the interior with NS `k_wave2d` launches over the "
-             "boundary frame beside it on a second stream.  A three-step pass splits its interior into a "
-             "core launch (MODE 1) and a ring launch (MODE 2, on a third stream, storing the intermediate "
-             "steps the frame launches read); a two-step pass is one launch (MODE 0).", "",
+             "boundary frame beside it on a second stream.  A pass of three or four steps splits its interior "
+             "into a core launch (MODE 1) and a ring launch (MODE 2, on a third stream, storing the "
+             "intermediate steps the frame launches read); a two-step pass is one launch (MODE 0).", "",
              "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in rows:
         name = r["Name"]
