@@ -511,7 +511,7 @@ def main():
     tuned = None
     if not args.no_tune and not args.profile_only:
         axf.tune_reset()
-        tuned = axf.tune(cfg, precision=prec, steps=12)
+        tuned = axf.tune(cfg, precision=prec, steps=40)
     if args.profile_only:
         time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, PROFILE_WARMUP, 0)
         print(json.dumps({"profile_only": tag, "steps": args.steps}), flush=True)

@@ -188,8 +188,9 @@ int axf_last_step_timing(const axf_run *run, double *ms, int64_t *launches);
  * keyed by dimensionality, precision, boundary kinds, PML width and the
  * power-of-two size class of the grid, with the faster kind; runs created
  * afterwards with a matching key use it (batches use the one-step shape, and
- * two-step passes with the multi-step rows).  The built-in shape stays unless
- * a candidate beats it by more than 2%.  Configurations without a fused 2D
+ * two-step passes with the multi-step rows).  The built-in shape is timed
+ * first and again after the candidates (the faster of the two counts) and
+ * stays unless a candidate beats it by more than 2%.  Configurations without a fused 2D
  * path report AXF_PATH_PLAIN and keep their launches.
  */
 typedef struct {
@@ -201,7 +202,7 @@ typedef struct {
     int32_t steps_per_pass;      /* most steps per pass (2, 3 or 4), or 1 */
     int32_t frame_chunk;         /* rows per frame wavefront of a pass of several steps (0 if 1) */
     double  ms_per_step;         /* best */
-    double  default_ms_per_step; /* the built-in default shape */
+    double  default_ms_per_step; /* the built-in default shape (faster of its two timings) */
 } axf_tuning;
 
 /* Time the candidates for `steps` steps each on a run carved from `scratch`
