@@ -216,9 +216,11 @@ int axf_tune_reset(void);
  * Many independent runs (parameter scans over m, g, B0, omega and grid size)
  * carved from one caller device buffer.  Runs are grouped by dimensionality,
  * precision and step path; one batched launch per kernel kind and group
- * advances every active run of the group by one step, each run with its own
- * step counter.  Every run's result is bit-identical to the same run created
- * with axf_create and stepped alone.
+ * advances every active run of the group by one step, or by a pass of two or
+ * four steps (2D wavefront runs whose grid has an interior for it, where no
+ * diagnostic record falls inside the pass), each run with its own step
+ * counter.  Every run's result is bit-identical to the same run created with
+ * axf_create and stepped alone.
  */
 
 /* Device bytes of a batch: a launch table plus each run's footprint, each
@@ -244,7 +246,8 @@ int axf_batch_destroy(axf_batch *b);
  * few rounds blocks later ones from overtaking it), creates them in the pool,
  * and advances every resident run by a work slice of about
  * macro_steps x 2^20 cell-updates (at least one step, at most what remains)
- * through the batched launches.  Finished or cancelled runs are retired and
+ * through the batched launches (passes of at most two steps: four were slower
+ * for its changing mix of runs).  Finished or cancelled runs are retired and
  * their memory returns to the pool.  A result's final record is bit-identical
  * to the same run stepped alone.
  */

@@ -3,11 +3,11 @@
 //
 // Both sit on one stepping engine.  The engine groups runs by the kernels they
 // share: dimensionality, precision, the 2D wavefront kernels (and whether the
-// grid has an interior for the two-step pass) vs the phase sequence.  Each
-// group's runs are sorted by remaining steps, so the runs still active at a
-// step are a prefix of the group's table.  One step (or two-step pass) is then
-// one launch per kernel kind and group, whatever the number of runs: the 2D
-// wavefront launches, the six unfused phases (1D) or five with E0 and the
+// grid has an interior for two- and four-step passes) vs the phase sequence.
+// Each group's runs are sorted by remaining steps, so the runs still active at
+// a step are a prefix of the group's table.  One step (or pass of two or four
+// steps) is then one launch per kernel kind and group, whatever the number of
+// runs: the 2D wavefront launches, the six unfused phases (1D) or five with E0 and the
 // axion current merged (3D); the laser-table fill every 16 steps; the
 // diagnostics at the runs' cadence.  Every block of a batched
 // launch executes its run's own single-run body with the run's own step
@@ -38,19 +38,22 @@ namespace axf {
 static long cdiv(long a, long b) { return (a + b - 1) / b; }
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-// the run takes two-step passes in batched launches (2D wavefront path with
-// an interior for the pass)
-static bool run_pairs(const Run *R)
+// the run takes passes of ns (2 or 4) steps in batched launches (2D wavefront
+// path with an interior for the pass; four only where the run's own passes
+// may take four)
+static bool run_passes(const Run *R, int ns)
 {
-    if (!run_wave2d(R) || !R->multi) return false;
+    if (!run_wave2d(R) || !R->multi || run_pass_steps(R) < ns) return false;
     int ci = 0, cf = 0;
-    run_pass_shape(R, 2, &ci, &cf);
-    return R->cfg.precision == AXF_F64 ? wave2d_pass_available(R->hk<double>(), 2, ci, cf)
-                                       : wave2d_pass_available(R->hk<float>(), 2, ci, cf);
+    run_pass_shape(R, ns, &ci, &cf);
+    return R->cfg.precision == AXF_F64 ? wave2d_pass_available(R->hk<double>(), ns, ci, cf)
+                                       : wave2d_pass_available(R->hk<float>(), ns, ci, cf);
 }
+static bool run_pairs(const Run *R) { return run_passes(R, 2); }
+static bool run_quads(const Run *R) { return run_pairs(R) && run_passes(R, 4); }
 
 // blocks of each launch kind for one run (the single-run launchers' grids)
-static void run_blocks(const Run *R, bool wave, bool pair, long blk[kNumKinds])
+static void run_blocks(const Run *R, bool wave, bool pair, bool quad, long blk[kNumKinds])
 {
     const Layout& L = R->L;
     blk[kVolume] = cdiv(L.npts, 256);
@@ -74,13 +77,20 @@ static void run_blocks(const Run *R, bool wave, bool pair, long blk[kNumKinds])
         if (R->cfg.precision == AXF_F64) wave2d_pair_blocks(R->hk<double>(), ci, cf, &blk[kPair], &blk[kFrameA], &blk[kFrameB]);
         else wave2d_pair_blocks(R->hk<float>(), ci, cf, &blk[kPair], &blk[kFrameA], &blk[kFrameB]);
     }
+    blk[kQuadCore] = blk[kQuadRing] = blk[kQuadFrame] = 0;
+    if (quad) {
+        int ci = 0, cf = 0;
+        run_pass_shape(R, 4, &ci, &cf);
+        if (R->cfg.precision == AXF_F64) wave2d_quad_blocks(R->hk<double>(), ci, cf, &blk[kQuadCore]);
+        else wave2d_quad_blocks(R->hk<float>(), ci, cf, &blk[kQuadCore]);
+    }
 }
 
 // ------------------------------------------------------------------ engine
 
 struct Group {
     int D = 0;
-    bool f64 = false, wave = false, pair = false, any_diag = false;
+    bool f64 = false, wave = false, pair = false, quad = false, any_diag = false;
     std::vector<int> idx;       // runs, sorted by steps this call (descending)
     size_t off = 0;             // first table entry
     int nact = 0;
@@ -98,6 +108,11 @@ public:
             hipEventDestroy(ws_.join);
             hipStreamDestroy(ws_.side);
         }
+        if (ws_.ring) {
+            hipStreamSynchronize(ws_.ring);
+            hipEventDestroy(ws_.ring_done);
+            hipStreamDestroy(ws_.ring);
+        }
     }
 
     // `dev` holds `cap` table entries of device memory owned by the caller
@@ -109,36 +124,47 @@ public:
         BCHK(hipStreamCreateWithFlags(&ws_.side, hipStreamNonBlocking));
         BCHK(hipEventCreateWithFlags(&ws_.fork, hipEventDisableTiming));
         BCHK(hipEventCreateWithFlags(&ws_.join, hipEventDisableTiming));
+        BCHK(hipStreamCreateWithFlags(&ws_.ring, hipStreamNonBlocking));
+        BCHK(hipEventCreateWithFlags(&ws_.ring_done, hipEventDisableTiming));
         return AXF_OK;
     }
 
     static size_t entries_for(size_t runs) { return runs + 16; }
 
+    // four-step passes for runs with an interior for them (batches); the
+    // server keeps two-step passes: with four, its saturated throughput fell
+    // (128 requests/s: 12.2-12.4 against 12.7 Gcell/s) while a 512-run scan
+    // gained (37.2 -> 39.6)
+    bool quads = true;
+
     int step(Run *const *runs, const int64_t *ns, int count, hipStream_t st);
 
 private:
     template <int D, typename T>
-    int group_step(Group& g, long s, bool two, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st);
+    int group_step(Group& g, long s, int ns, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st);
 
     BItem *dev_ = nullptr, *host_ = nullptr;
     size_t cap_ = 0;
-    WaveStreams ws_{nullptr, nullptr, nullptr};   // side stream of the 2D frame launches
+    // side stream of the 2D frame launches, ring stream of four-step passes
+    WaveStreams ws_{nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
-// one step s of the call, or steps s and s + 1 when two (a two-step pass; the
-// caller takes one only where no diagnostic record and no laser-table fill
-// falls on s + 1)
+// one step s of the call, or steps s .. s + ns - 1 as a pass of ns = 2 or 4
+// steps (the caller takes one only where no diagnostic record falls on any
+// of its steps and no laser-table fill on any but the first)
 template <int D, typename T>
-int Engine::group_step(Group& g, long s, bool two, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st)
+int Engine::group_step(Group& g, long s, int ns, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st)
 {
+    const bool two = ns > 1;
     const BItem *dt = dev_ + g.off, *ht = host_ + g.off;
     const int n = g.nact;
     if (s % (kIncLevels - 1) == 0) Plain<D, T>::batch_inc_fill(dt, ht, n, s, kIncLevels, st);
     bool launched = false;
     if constexpr (D == 2) {
         if (g.wave) {
-            hipError_t e = two ? launch_wave2d_pair_batch<T>(dt, ht, n, s, st, &ws_)
-                               : launch_wave2d_batch<T>(dt, ht, n, s, st, &ws_);
+            hipError_t e = ns == 4   ? launch_wave2d_quad_batch<T>(dt, ht, n, s, st, &ws_)
+                           : ns == 2 ? launch_wave2d_pair_batch<T>(dt, ht, n, s, st, &ws_)
+                                     : launch_wave2d_batch<T>(dt, ht, n, s, st, &ws_);
             if (e != hipSuccess) return hip_fail(e, "batched wavefront step");
             launched = true;
         }
@@ -183,9 +209,10 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
         if (rc) return rc;
         const int D = R->cfg.ndim;
         const bool f64 = R->cfg.precision == AXF_F64, wave = run_wave2d(R), pair = run_pairs(R);
+        const bool quad = quads && run_quads(R);
         Group *g = nullptr;
         for (auto& q : groups)
-            if (q.D == D && q.f64 == f64 && q.wave == wave && q.pair == pair) g = &q;
+            if (q.D == D && q.f64 == f64 && q.wave == wave && q.pair == pair && q.quad == quad) g = &q;
         if (!g) {
             groups.emplace_back();
             g = &groups.back();
@@ -193,6 +220,7 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
             g->f64 = f64;
             g->wave = wave;
             g->pair = pair;
+            g->quad = quad;
         }
         g->idx.push_back(i);
         g->any_diag = g->any_diag || R->cfg.diag_every > 0;
@@ -219,8 +247,9 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
             b.rec0 = R->rec_written;
             b.chunk = run_wave_chunk(R);
             run_pass_shape(R, 2, &b.pass_ci, &b.pass_cf);
+            run_pass_shape(R, 4, &b.quad_ci, &b.quad_cf);
             long nb[kNumKinds];
-            run_blocks(R, g.wave, g.pair, nb);
+            run_blocks(R, g.wave, g.pair, g.quad, nb);
             for (int q = 0; q < kNumKinds; q++) acc[q] += nb[q];
         }
         off += g.idx.size() + 1;
@@ -246,21 +275,26 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
             while (g.nact > 0 && ns[g.idx[g.nact - 1]] <= s) g.nact--;
             if (g.nact == 0) continue;
             busy = true;
-            // two steps when every active run takes both, and neither a record
-            // nor a table fill falls on the second
-            const bool two = g.pair && ns[g.idx[g.nact - 1]] > s + 1 && (s + 1) % (kIncLevels - 1) != 0 &&
-                             !diag_at(g, s) && !diag_at(g, s + 1);
+            // a pass of k steps when every active run takes all k, no record
+            // falls on any of them and no table fill on any but the first
+            auto pass_fits = [&](int k) {
+                if (ns[g.idx[g.nact - 1]] < s + k) return false;
+                for (int q = 0; q < k; q++)
+                    if ((q > 0 && (s + q) % (kIncLevels - 1) == 0) || diag_at(g, s + q)) return false;
+                return true;
+            };
+            const int np = g.D != 2 ? 1 : (g.quad && pass_fits(4)) ? 4 : (g.pair && pass_fits(2)) ? 2 : 1;
             int rc;
             switch (g.D * 2 + (g.f64 ? 1 : 0)) {
-            case 2: rc = group_step<1, float>(g, s, false, nrec, runs, st); break;
-            case 3: rc = group_step<1, double>(g, s, false, nrec, runs, st); break;
-            case 4: rc = group_step<2, float>(g, s, two, nrec, runs, st); break;
-            case 5: rc = group_step<2, double>(g, s, two, nrec, runs, st); break;
-            case 6: rc = group_step<3, float>(g, s, false, nrec, runs, st); break;
-            default: rc = group_step<3, double>(g, s, false, nrec, runs, st); break;
+            case 2: rc = group_step<1, float>(g, s, 1, nrec, runs, st); break;
+            case 3: rc = group_step<1, double>(g, s, 1, nrec, runs, st); break;
+            case 4: rc = group_step<2, float>(g, s, np, nrec, runs, st); break;
+            case 5: rc = group_step<2, double>(g, s, np, nrec, runs, st); break;
+            case 6: rc = group_step<3, float>(g, s, 1, nrec, runs, st); break;
+            default: rc = group_step<3, double>(g, s, 1, nrec, runs, st); break;
             }
             if (rc) return rc;
-            g.s += (g.D == 2 && two) ? 2 : 1;
+            g.s += np;
         }
     }
     BCHK(hipGetLastError());
@@ -619,6 +653,7 @@ int axf_server_create(void *pool, size_t pool_bytes, int32_t max_slots, int32_t 
     S->stream = (hipStream_t)stream;
     S->device = device;
     S->alloc.reset(S->pool_bytes);
+    S->eng.quads = false;
     int rc = S->eng.init((BItem *)pool, Engine::entries_for((size_t)max_slots));
     if (rc) {
         delete S;

@@ -53,6 +53,16 @@ hipError_t launch_wave2d_pair_batch(const BItem *it, const BItem *host, int n, l
 // workgroups of one run's three launches of a two-step pass
 template <typename T>
 void wave2d_pair_blocks(const RunK<T>& h, int ci, int cf, long *interior, long *frame_a, long *frame_b);
+// the four-step pass over the first n runs of a batch table: steps s .. s + 3
+// of the call for every run (each run with an interior for the pass), split as
+// a single run's pass is (needs the side and ring streams of `ws`)
+template <typename T>
+hipError_t launch_wave2d_quad_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st,
+                                    const WaveStreams *ws);
+// workgroups of one run's launches of a four-step pass: the interior's core,
+// its ring, and the frame (launched once per step)
+template <typename T>
+void wave2d_quad_blocks(const RunK<T>& h, int ci, int cf, long blk[3]);
 // workgroups (4 wavefronts each) of one run's two wavefront launches: the
 // frame next to the domain boundary and the interior
 template <typename T>

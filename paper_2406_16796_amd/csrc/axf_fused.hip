@@ -1888,6 +1888,95 @@ hipError_t launch_wave2d_pair_batch(const BItem *it, const BItem *host, int n, l
 template hipError_t launch_wave2d_pair_batch<float>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);
 template hipError_t launch_wave2d_pair_batch<double>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);
 
+// batched four-step pass: every active run of the table advances steps s ..
+// s + 3 of the call, each with its own pass shape, in the three launches of a
+// single run's split pass: KIND selects the interior's core (kQuadCore), its
+// ring (kQuadRing, storing the intermediate steps) or the frame around the
+// interior (kQuadFrame, launched once per step with the call's step in s)
+template <typename T>
+__device__ __forceinline__ WaveSplit quad_ring_core(const WavePass<4>& wp)
+{
+    const int nis = wp.in.sx1 - wp.in.sx0, nic = wp.in.cy1 - wp.in.cy0;
+    WaveSplit rc{nis, nic, 1, nis - 1, 1, nic - 1, wp.in.wid};
+    if (nis < 3 || nic < 3) rc.sx0 = rc.sx1 = rc.cy0 = rc.cy1 = 0;
+    return rc;
+}
+
+template <typename T, int KIND>
+__global__ void __launch_bounds__(256, KIND == kQuadFrame ? 3 : 1) kb_wave2d_quad(const BItem *__restrict__ it, int n, long s)
+{
+    const long b = KIND == kQuadFrame ? (long)blockIdx.x : xcd_band(blockIdx.x, gridDim.x);
+    const int i = find_item<KIND>(it, n, b);
+    const RunK<T> *rp = uniform_desc<RunK<T>>(it[i].rk);
+    const int cf = it[i].quad_cf;
+    const WavePass<4> wp = wave2d_split_pass<4>(*rp, it[i].quad_ci, cf);
+    const long gw = (b - it[i].blk[KIND]) * 4L + wave_in_block();
+    const long step = it[i].step0 + s;
+    constexpr int PD = sizeof(T) == 8 ? 1 : 2;
+    if constexpr (KIND == kQuadFrame) {
+        const WaveSplit& w = wp.fr[3];
+        if (gw >= w.edge()) return;
+        int seg, ch;
+        wave2d_edge_item(w, gw, seg, ch);
+        wave2d_body<T, false, 1>(rp, step, seg, ch, w.nch, cf, w.wid);
+    } else {
+        const WaveSplit rc = quad_ring_core<T>(wp);
+        int seg, ch;
+        if (KIND == kQuadCore) {
+            if (gw >= rc.interior()) return;
+            const int ni = rc.sx1 - rc.sx0;
+            seg = wp.in.sx0 + rc.sx0 + (int)(gw % ni);
+            ch = wp.in.cy0 + rc.cy0 + (int)(gw / ni);
+            wave2d_pass_body<T, PD, 4, kCore>(rp, step, wp, seg, ch, cf);
+        } else {
+            if (gw >= rc.edge()) return;
+            wave2d_edge_item(rc, gw, seg, ch);
+            wave2d_pass_body<T, PD, 4, kRing>(rp, step, wp, seg + wp.in.sx0, ch + wp.in.cy0, cf);
+        }
+    }
+}
+
+template <typename T>
+void wave2d_quad_blocks(const RunK<T>& h, int ci, int cf, long blk[3])
+{
+    const WavePass<4> wp = wave2d_split_pass<4>(h, ci, cf);
+    const int nis = wp.in.sx1 - wp.in.sx0, nic = wp.in.cy1 - wp.in.cy0;
+    WaveSplit rc{nis, nic, 1, nis - 1, 1, nic - 1, wp.in.wid};
+    if (nis < 3 || nic < 3) rc.sx0 = rc.sx1 = rc.cy0 = rc.cy1 = 0;
+    blk[0] = (rc.interior() + 3) / 4;
+    blk[1] = (rc.edge() + 3) / 4;
+    blk[2] = (wp.fr[3].edge() + 3) / 4;
+}
+template void wave2d_quad_blocks<float>(const RunK<float>&, int, int, long *);
+template void wave2d_quad_blocks<double>(const RunK<double>&, int, int, long *);
+
+// the streams of a single run's split pass: the core on `st`, the ring on
+// ws->ring, the frame on ws->side (its later steps after the ring has stored
+// them)
+template <typename T>
+hipError_t launch_wave2d_quad_batch(const BItem *it, const BItem *host, int n, long s, hipStream_t st,
+                                    const WaveStreams *ws)
+{
+    if (!ws || !ws->side || !ws->ring || !ws->ring_done) return hipErrorInvalidValue;
+    const unsigned nc = (unsigned)host[n].blk[kQuadCore], nr = (unsigned)host[n].blk[kQuadRing];
+    const unsigned nf = (unsigned)host[n].blk[kQuadFrame];
+    hipEventRecord(ws->fork, st);
+    hipStreamWaitEvent(ws->side, ws->fork, 0);
+    hipStreamWaitEvent(ws->ring, ws->fork, 0);
+    if (nr > 0) hipLaunchKernelGGL((kb_wave2d_quad<T, kQuadRing>), dim3(nr), dim3(256), 0, ws->ring, it, n, s);
+    hipEventRecord(ws->ring_done, ws->ring);
+    if (nf > 0) hipLaunchKernelGGL((kb_wave2d_quad<T, kQuadFrame>), dim3(nf), dim3(256), 0, ws->side, it, n, s);
+    if (nc > 0) hipLaunchKernelGGL((kb_wave2d_quad<T, kQuadCore>), dim3(nc), dim3(256), 0, st, it, n, s);
+    hipStreamWaitEvent(ws->side, ws->ring_done, 0);
+    for (int f = 1; f < 4; f++)
+        if (nf > 0) hipLaunchKernelGGL((kb_wave2d_quad<T, kQuadFrame>), dim3(nf), dim3(256), 0, ws->side, it, n, s + f);
+    hipEventRecord(ws->join, ws->side);
+    hipStreamWaitEvent(st, ws->join, 0);
+    return hipGetLastError();
+}
+template hipError_t launch_wave2d_quad_batch<float>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);
+template hipError_t launch_wave2d_quad_batch<double>(const BItem *, const BItem *, int, long, hipStream_t, const WaveStreams *);
+
 template <typename T>
 void wave2d_blocks(const RunK<T>& h, int chunk, long *edge_blocks, long *interior_blocks)
 {

@@ -110,6 +110,7 @@ __host__ __device__ inline long round_up(long v, long m) { return (v + m - 1) / 
 enum BlockKind {
     kVolume = 0, kFace, kLaser, kWave, kWaveI,
     kPair, kFrameA, kFrameB,           // two-step pass: interior, frames of steps n and n + 1
+    kQuadCore, kQuadRing, kQuadFrame,  // four-step pass: interior core and ring, frame (every step)
     kNumKinds
 };
 struct BItem {
@@ -120,7 +121,8 @@ struct BItem {
     int chunk;          // rows per wavefront march (fused 2D, one step per pass)
     int pass_ci;        // rows per interior / frame wavefront of a two-step pass
     int pass_cf;
-    int pad;
+    int quad_ci;        // ... of a four-step pass
+    int quad_cf;
 };
 
 // the run descriptor of a table entry as a wave-uniform pointer into global

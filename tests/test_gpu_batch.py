@@ -13,6 +13,7 @@ import pytest
 
 from oracle.oracle import Oracle
 from paper_2406_16796_amd import workloads as W
+from test_gpu_pair import pass_available
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +77,41 @@ def test_batch_equals_alone_bitwise(axf, prec):
         batch.step(c)
     for i, cfg in enumerate(cfgs):
         ref = alone(axf, cfg, p, [c[i] for c in counts], diag_every=10)
+        assert batch.runs[i].steps_done == ref.steps_done
+        assert_same(batch.runs[i], ref, "run %d" % i)
+    batch.close()
+
+
+def wide_runs():
+    """2D runs wide enough for four-step passes (the first two) and one that
+    only has an interior for two-step passes."""
+    out = []
+    for (nx, ny), bc in (((470, 150), W.AX_PML), ((520, 170), W.AX_PERIODIC), ((300, 140), W.AX_OUTFLOW)):
+        c = W.gaussian_2d(n=nx, m=0.25, g=0.03, a0=0.5, waist_lam=1.2, fwhm_lam=1.5,
+                          slab=(5, nx - 5), ax_bc=bc, seed=nx)
+        dx = c["dx"][0]
+        c.update(n=[nx, ny, 1], y_c=0.5 * ny * dx, t_center=6.0, pml_n=6, packet_on=1, pk_amp=0.2,
+                 pk_k=1.0, pk_w=2.5, pk_x0=0.6 * nx * dx, pk_y0=0.4 * ny * dx, pk_dir=-1)
+        out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_four_step_passes_equal_alone(axf, prec):
+    """Batched four-step passes (wherever no record and no laser-table fill
+    falls inside one), beside a group of two-step passes, with uneven step
+    counts: every run bit-identical to the run stepped alone."""
+    p = axf.F32 if prec == "f32" else axf.F64
+    cfgs = wide_runs()
+    f64 = prec == "f64"
+    assert [pass_available(c, 4, f64=f64) for c in cfgs] == [True, True, False]
+    assert pass_available(cfgs[2], 2, f64=f64)
+    counts = [[61, 45, 70], [37, 0, 29], [4, 9, 2]]
+    batch = axf.Batch(cfgs, precision=p, diag_every=9)
+    for c in counts:
+        batch.step(c)
+    for i, cfg in enumerate(cfgs):
+        ref = alone(axf, cfg, p, [c[i] for c in counts], diag_every=9)
         assert batch.runs[i].steps_done == ref.steps_done
         assert_same(batch.runs[i], ref, "run %d" % i)
     batch.close()
