@@ -107,6 +107,24 @@ def make_config(cfg):
     return c
 
 
+def laser_centroid(b1z, dx):
+    """Laser centroid along x (Sec. IV, the weak-laser benchmark): the mean
+    of x over the grid weighted by the first-order field squared,
+    x_laser = sum x B1z^2 / sum B1z^2, summed over every B1z point of the
+    grid (the paper's double integral over x and y, a triple one in 3D).  B1z
+    lies on the z edges of the cells, i.e. on the x nodes: the point of
+    column i is at x = i dx.  0 where B1z vanishes everywhere.
+
+    b1z: array (..., nx) of the grid's B1z points, column i last."""
+    b = np.asarray(b1z, dtype=np.float64)
+    w = b * b
+    tot = w.sum()
+    if tot == 0.0:
+        return 0.0
+    x = np.arange(b.shape[-1], dtype=np.float64) * dx
+    return float((w * x).sum() / tot)
+
+
 class Oracle:
     """One FP64 oracle run; arrays are numpy views on the oracle's memory."""
 
@@ -159,6 +177,12 @@ class Oracle:
         out = (ctypes.c_double * 3)()
         lib().ora_energies(self._h, out)
         return tuple(out)
+
+    def laser_centroid(self):
+        """x_laser of B1z at the current integer time (B_z points: every x and
+        y node, the cell centres along z)."""
+        b = self.field("B1Z")[:self.n[2], :self.nn[1], :self.nn[0]]
+        return laser_centroid(b, float(self._cfg.dx[0]))
 
     def threads(self):
         return lib().ora_threads()

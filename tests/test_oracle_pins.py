@@ -12,7 +12,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle.oracle import Oracle
+from oracle.oracle import Oracle, laser_centroid
 
 F = ["E0X", "E0Y", "E0Z", "B0X", "B0Y", "B0Z", "E1X", "E1Y", "E1Z", "B1X", "B1Y", "B1Z"]
 
@@ -494,3 +494,55 @@ def test_brute_force_exact_rationals_both_forms_and_oracle():
         exact = arr.astype(float)
         scale = max(np.abs(exact).max(), 1.0)
         assert np.abs(o.field(name) - exact).max() <= 1e-13 * scale, name
+
+
+# ---------------------------------------------------------------- laser centroid
+
+def test_laser_centroid_closed_forms():
+    """x_laser = sum x B1z^2 / sum B1z^2 with B1z on the x nodes (x = i dx):
+    one point sits at its node; two points weigh by the square (not the
+    value); a profile even about a node has its centroid there; no field
+    gives 0."""
+    b = np.zeros((1, 3, 7))
+    b[0, 1, 4] = 3.0
+    assert laser_centroid(b, 0.5) == 2.0
+    b = np.zeros((2, 4, 9))
+    b[0, 1, 2] = 1.0
+    b[1, 3, 6] = -2.0
+    # (1 * 2 + 4 * 6) / (1 + 4) = 26/5 columns
+    assert laser_centroid(b, 0.5) == pytest.approx(float(Fraction(26, 5) * Fraction(1, 2)), rel=1e-15)
+    x = np.arange(21)
+    prof = np.exp(-0.5 * ((x - 10) / 3.0) ** 2)
+    rows = np.array([0.3, 1.0, 2.5])[:, None]
+    assert laser_centroid((rows * prof)[None], 0.25) == pytest.approx(2.5, rel=1e-14)
+    assert laser_centroid(np.zeros((1, 2, 5)), 1.0) == 0.0
+
+
+def conversion_cfg(x0):
+    # a box long enough in x (48) that the packet and its photons stay far
+    # from its ends: a centroid moves with a shift only while nothing wraps
+    return periodic_cfg([160, 30, 1], [0.3, 0.3, 1.0], 0.2, m=0.2, g=5e-3, bext=[0.0, 1.0, 0.5],
+                        slab_lo=0, slab_hi=160, packet_on=1, pk_amp=1.0, pk_k=1.0, pk_w=2.5,
+                        pk_x0=x0, pk_y0=4.5, pk_dir=1)
+
+
+def test_laser_centroid_of_oracle_run():
+    """The oracle's x_laser of the photons an axion packet generates: the sum
+    written out over every B1z point of the grid, and a whole-cell shift of
+    the packet in a periodic box (uniform field everywhere) shifts it by
+    exactly those cells."""
+    o = Oracle(conversion_cfg(20.0))
+    o.step(20)
+    b = o.field("B1Z")
+    num = den = 0.0
+    for k in range(o.n[2]):
+        for j in range(o.nn[1]):
+            for i in range(o.nn[0]):
+                num += i * 0.3 * b[k, j, i] ** 2
+                den += b[k, j, i] ** 2
+    assert den > 0
+    xc = o.laser_centroid()
+    assert xc == pytest.approx(num / den, rel=1e-13)
+    s = Oracle(conversion_cfg(20.0 + 3 * 0.3))
+    s.step(20)
+    assert s.laser_centroid() - xc == pytest.approx(0.9, abs=1e-9)
