@@ -122,6 +122,8 @@ typedef struct {
     double  p_conv;          /* h_em1 / h_phi (0 if h_phi == 0) */
     int32_t finite;          /* 0 if any field was not finite */
     int32_t pad;
+    double  x_laser;         /* laser centroid (Sec. IV): sum x B1z^2 / sum B1z^2 over the
+                                B1z points, x = i dx on the x nodes (0 if B1z == 0) */
 } axf_diag_record;
 
 typedef struct axf_run axf_run;

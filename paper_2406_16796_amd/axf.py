@@ -60,7 +60,8 @@ class Config(ctypes.Structure):
 class DiagRecord(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("t", ctypes.c_double), ("h_phi", ctypes.c_double),
                 ("h_em0", ctypes.c_double), ("h_em1", ctypes.c_double), ("p_gen", ctypes.c_double),
-                ("p_conv", ctypes.c_double), ("finite", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("p_conv", ctypes.c_double), ("finite", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("x_laser", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}

@@ -54,6 +54,7 @@ __host__ __device__ constexpr int q_mur(int o, int d, int side, int comp, int sl
 }
 constexpr int kNumFaces = 6 * kPhiSlots + 36 * kEmSlots;
 constexpr int kIncLevels = 17;   // time levels per laser table fill (16 steps)
+constexpr int kDiagSums = 6;     // FP64 partial sums per block of a diagnostic record
 constexpr int kPmlProf = 64;     // damping-layer thicknesses the wavefront interiors tabulate
 
 // Immutable per-run descriptor, stored in device memory once at creation.

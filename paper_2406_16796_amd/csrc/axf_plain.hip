@@ -465,29 +465,32 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// block sums of 4 quantities in a fixed order (deterministic), written to part[blk*4 + q]
-__device__ __forceinline__ void block_sum4(double v[4], double *out)
+// block sums of the kDiagSums quantities in a fixed order (deterministic):
+// each wave's sum, then the four waves in turn, written to out[q]
+__device__ __forceinline__ void block_sums(double v[kDiagSums], double *out)
 {
-    __shared__ double red[4][4];
+    __shared__ double red[4][kDiagSums];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
+    for (int q = 0; q < kDiagSums; q++) {
         double s = wave_sum(v[q]);
         if (lane == 0) red[w][q] = s;
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < kDiagSums) {
         int q = threadIdx.x;
         out[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
     }
 }
 
 // energies at t_n: E^n = mean of the two E slots, B^n = old slot, phi^n = mean
-// of the axion levels; H_phi = sum ((D_t phi)^2 + sum_d (D+_d phi)^2 + m^2 phi^2) / 2
+// of the axion levels; H_phi = sum ((D_t phi)^2 + sum_d (D+_d phi)^2 + m^2 phi^2) / 2.
+// Sums 4 and 5: x B1z^2 and B1z^2 over the B1z points (on the x nodes, x = i dx),
+// whose ratio is the laser centroid of Sec. IV
 template <int D, typename T>
 __device__ __forceinline__ void diag_body(const RunK<T>& r, long bx, long step)
 {
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    double v[kDiagSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int i, j, k;
     long p = bx * 256 + threadIdx.x;
     if (decompose(r, p, i, j, k)) {
@@ -536,24 +539,28 @@ __device__ __forceinline__ void diag_body(const RunK<T>& r, long bx, long step)
                     double bv = r.B1[so][c][id];
                     v[2] += 0.5 * bv * bv;
                     fin = fin && finite_val(bv);
+                    if (c == 2) {
+                        v[4] += (double)i * (double)r.dx[0] * (bv * bv);
+                        v[5] += bv * bv;
+                    }
                 }
             }
         }
         v[3] = fin ? 0.0 : 1.0;
     }
-    block_sum4(v, r.part + bx * 4);
+    block_sums(v, r.part + bx * kDiagSums);
 }
 
 // fixed-order sum of the block partials into record slot `slot`
 template <typename T>
 __device__ __forceinline__ void diag_final_body(const RunK<T>& r, long step, int slot)
 {
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    double v[kDiagSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int blk = threadIdx.x; blk < r.diag_blocks; blk += blockDim.x)
 #pragma unroll
-        for (int q = 0; q < 4; q++) v[q] += r.part[blk * 4 + q];
-    __shared__ double tot[4];
-    block_sum4(v, tot);
+        for (int q = 0; q < kDiagSums; q++) v[q] += r.part[blk * kDiagSums + q];
+    __shared__ double tot[kDiagSums];
+    block_sums(v, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
         double dv = 1.0;
@@ -568,6 +575,7 @@ __device__ __forceinline__ void diag_final_body(const RunK<T>& r, long step, int
         rec.p_conv = rec.h_phi > 0.0 ? rec.h_em1 / rec.h_phi : 0.0;
         rec.finite = tot[3] == 0.0 ? 1 : 0;
         rec.pad = 0;
+        rec.x_laser = tot[5] > 0.0 ? tot[4] / tot[5] : 0.0;
         r.rec[slot] = rec;
     }
 }

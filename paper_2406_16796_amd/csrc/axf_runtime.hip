@@ -168,7 +168,7 @@ Layout make_layout(const axf_config *c)
         }
     L.npts = (long)L.nn[0] * L.nn[1] * L.nn[2];
     L.diag_blocks = (int)((L.npts + 255) / 256);
-    L.off_part = take((size_t)L.diag_blocks * 4 * sizeof(double));
+    L.off_part = take((size_t)L.diag_blocks * kDiagSums * sizeof(double));
     L.rec_cap = 4096;
     L.off_rec = take((size_t)(L.rec_cap + 1) * sizeof(axf_diag_record));
     L.inc_face = (long)L.nn[1] * L.nn[2];

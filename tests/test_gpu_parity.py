@@ -66,6 +66,9 @@ def check_energies(rec, ora, tol):
     h = ora.energies()
     for got, want in ((rec["h_phi"], h[0]), (rec["h_em0"], h[1]), (rec["h_em1"], h[2])):
         assert abs(got - want) <= tol * max(abs(want), 1e-300), (got, want)
+    # the laser centroid (a position; 0 where B1z vanishes)
+    xc = ora.laser_centroid()
+    assert abs(rec["x_laser"] - xc) <= tol * max(abs(xc), 1.0), (rec["x_laser"], xc)
 
 
 def small_1d(ax_bc, n=600):
@@ -186,6 +189,11 @@ def test_fp32_tracks_oracle(axf, kind):
     h = ora.energies()
     assert abs(rec["h_phi"] / h[0] - 1) < 1e-3
     assert abs(rec["h_em1"] / h[2] - 1) < 1e-3
+    xc = ora.laser_centroid()
+    assert xc > 0
+    # FP32 fields within 2e-4 of their scale move the weighted mean by a
+    # small fraction of a cell
+    assert abs(rec["x_laser"] - xc) <= 1e-2 * cfg["dx"][0], (rec["x_laser"], xc)
 
 
 def wide_2d(ax_bc, n=(300, 170)):
