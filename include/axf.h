@@ -214,6 +214,46 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
 /* Forget every recorded choice (pure host call). */
 int axf_tune_reset(void);
 
+/* ------------------------------------------------------------ SI inputs
+ * The paper's SI form of the equations (Sec. II.B: the axion field in units of
+ * frequency, g_agg in units of time, as an SI particle-in-cell code takes them)
+ * mapped to the normalised units of axf_config: times in 1/omega0, lengths in
+ * 1/k0 (omega0 = k0 c = 2 pi c / lambda0 of a reference wavelength), fields in
+ * m_e c omega0 / e (E) and m_e omega0 / e (B), masses as m_a c^2 / (hbar omega0).
+ * The single coupling g of axf_config drives both the axion source and the
+ * axion current; it is g = g_agg m_e c^(3/2) / (e sqrt(hbar mu0)) with the
+ * axion field measured in omega0 s, s = m_e c^(3/2) / (e omega0 sqrt(hbar mu0)),
+ * the scale at which the two SI couplings (g / (hbar mu0) and g / c) coincide.
+ * Constants: CODATA 2018.
+ */
+typedef struct {
+    double lambda0;          /* reference wavelength [m] (> 0) */
+    double lambda_laser;     /* laser wavelength [m]; 0: lambda0 */
+    double dx[3];            /* cell sizes [m] (> 0 on the run's axes) */
+    double dt;               /* time step [s] (> 0) */
+    double m_a;              /* axion mass m_a c^2 [eV] (>= 0) */
+    double g_agg;            /* axion-photon coupling [hbar GeV^-1] */
+    double bext[3];          /* static external field [T] */
+    double e_amp;            /* laser peak field [V/m] */
+    double fwhm;             /* laser intensity FWHM duration [s] */
+    double t_center;         /* time the pulse peak crosses x = 0 [s] */
+    double waist;            /* 1/e field radius at focus [m]; 0: plane wave */
+    double x_focus, y_c, z_c;/* focus and transverse centre [m] */
+} axf_si;
+
+/* Fill dx (on the run's ndim axes), dt, m, g, bext, omega, e_amp, fwhm,
+   t_center, waist, x_focus, y_c and z_c of *cfg from *si (every other field
+   of *cfg is left as it is; set ndim first).  Pure host
+   call; EINVAL for a non-positive wavelength, cell size or time step, or a
+   negative mass. */
+int axf_config_from_si(const axf_si *si, axf_config *cfg);
+
+/* The axion-photon coupling of an axion model (Sec. III.B): f_a from
+   m_a = 6.3 eV x 10^6 GeV / f_a, then g_agg = c_gamma 2 alpha / (pi f_a), in
+   hbar GeV^-1 (c_gamma = -0.97 for KSVZ, 0.36 for DFSZ).  Pure host call;
+   EINVAL for m_a <= 0 or a null output. */
+int axf_axion_coupling(double m_a_eV, double c_gamma, double *g_agg);
+
 /* ------------------------------------------------------------ batches
  * Many independent runs (parameter scans over m, g, B0, omega and grid size)
  * carved from one caller device buffer.  Runs are grouped by dimensionality,

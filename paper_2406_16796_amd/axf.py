@@ -26,7 +26,7 @@ EXPORTS = [
     "axf_write_state", "axf_sync", "axf_steps_done", "axf_path_in_use", "axf_destroy", "axf_last_step_timing",
     "axf_tune", "axf_tune_reset", "axf_batch_footprint", "axf_batch_create", "axf_batch_step", "axf_batch_run", "axf_batch_destroy",
     "axf_server_create", "axf_server_submit", "axf_server_cancel", "axf_server_poll", "axf_server_stats",
-    "axf_server_destroy",
+    "axf_server_destroy", "axf_config_from_si", "axf_axion_coupling",
 ]
 
 
@@ -82,6 +82,15 @@ class Result(ctypes.Structure):
 _lib = None
 
 
+class Si(ctypes.Structure):
+    """axf_si: SI inputs of a run."""
+    _fields_ = [("lambda0", ctypes.c_double), ("lambda_laser", ctypes.c_double),
+                ("dx", ctypes.c_double * 3), ("dt", ctypes.c_double), ("m_a", ctypes.c_double),
+                ("g_agg", ctypes.c_double), ("bext", ctypes.c_double * 3), ("e_amp", ctypes.c_double),
+                ("fwhm", ctypes.c_double), ("t_center", ctypes.c_double), ("waist", ctypes.c_double),
+                ("x_focus", ctypes.c_double), ("y_c", ctypes.c_double), ("z_c", ctypes.c_double)]
+
+
 def lib():
     """Load libaxf.so (raises if it has not been built)."""
     global _lib
@@ -127,6 +136,8 @@ def lib():
         "axf_server_poll": ([vp, P(Result), i32, P(i32)], ctypes.c_int),
         "axf_server_stats": ([vp, P(i32), P(i32), P(sz)], ctypes.c_int),
         "axf_server_destroy": ([vp], ctypes.c_int),
+        "axf_config_from_si": ([P(Si), P(Config)], ctypes.c_int),
+        "axf_axion_coupling": ([dp, dp, P(dp)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -168,6 +179,36 @@ def make_config(cfg, precision=F64, diag_every=0, path=PATH_AUTO):
     c.diag_every = int(cfg.get("diag_every", diag_every))
     c.path = int(cfg.get("path", path))
     return c
+
+
+def config_from_si(si, cfg):
+    """`cfg` (a run description dict with at least "n") with dx, dt, m, g,
+    bext, omega, e_amp, fwhm, t_center, waist, x_focus, y_c and z_c converted
+    from the SI inputs `si` (a dict with the keys of axf_si; missing keys 0)
+    by axf_config_from_si."""
+    s = Si()
+    for key, _ in Si._fields_:
+        v = si.get(key, 0.0)
+        if key in ("dx", "bext"):
+            getattr(s, key)[:] = [float(x) for x in (list(v) + [0.0, 0.0, 0.0])[:3]] if v else [0.0] * 3
+        else:
+            setattr(s, key, float(v))
+    c = make_config(dict(cfg, dx=cfg.get("dx", [1.0, 1.0, 1.0]), dt=cfg.get("dt", 1.0)))
+    check(lib().axf_config_from_si(ctypes.byref(s), ctypes.byref(c)))
+    out = dict(cfg)
+    out["ndim"] = c.ndim
+    out["dx"], out["bext"] = list(c.dx), list(c.bext)
+    for key in ("dt", "m", "g", "omega", "e_amp", "fwhm", "t_center", "waist", "x_focus", "y_c", "z_c"):
+        out[key] = getattr(c, key)
+    return out
+
+
+def axion_coupling(m_a_eV, c_gamma):
+    """g_agg [hbar GeV^-1] of an axion model of mass m_a_eV and photon
+    coupling c_gamma (axf_axion_coupling)."""
+    g = ctypes.c_double()
+    check(lib().axf_axion_coupling(float(m_a_eV), float(c_gamma), ctypes.byref(g)))
+    return g.value
 
 
 def footprint(cfg, **kw):
