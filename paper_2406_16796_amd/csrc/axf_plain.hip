@@ -145,6 +145,64 @@ __device__ __forceinline__ void e0c_at(const RunK<T>& r, int i, int j, int k, lo
     r.C[2][id] = dtphi * b[2] - (e[0] * gp[1] - e[1] * gp[0]);
 }
 
+// e0c_at on a walk up the z planes of one column: the z component of
+// E0^{n+1/2} one plane up, which this plane's current needs, is the next
+// plane's own value (the one it stores and averages): kept in `ez_up` (valid
+// when `have`) instead of being computed again.  The same expressions as
+// e0c_at, so the same bits.
+template <int D, typename T>
+__device__ __forceinline__ void e0c_walk_at(const RunK<T>& r, int i, int j, int k, long step, T& ez_up, bool& have)
+{
+    const long id = lin(r, i, j, k);
+    const int so = em_slot(step), sn = em_slot(step + 1), la = phi_slot(step), lb = phi_slot(step + 1);
+    T own[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (!actE0<D>(c) || !in_E<D>(r, c, i, j, k)) continue;
+        own[c] = (D == 3 && c == 2 && have) ? ez_up : e0new_at<D, T>(r, so, c, i, j, k);
+        r.E0[sn][c][id] = own[c];
+    }
+    have = false;
+    // (a point of the current is a face point of every component, so own[]
+    // holds all three below)
+    if (!in_cell(r, i, j, k)) return;
+    T e[3], b[3], gp[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        e[c] = T(0);
+        if (actE0<D>(c)) {
+            const T *m = r.E0[so][c];
+            const long o = c < D ? em_step(r, c, coord(c, i, j, k), 1) : 0;
+            const T p0 = own[c];
+            T p1 = p0;
+            if (c < D) {
+                int i1 = i, j1 = j, k1 = k;
+                coord_up(r, c, i1, j1, k1);
+                p1 = e0new_at<D, T>(r, so, c, i1, j1, k1);
+                if (c == 2) {
+                    ez_up = p1;
+                    have = true;
+                }
+            }
+            T lo = r.half * (m[id] + p0);
+            T hi = r.half * (m[id + o] + p1);
+            e[c] = c < D ? r.half * (lo + hi) : lo;
+        }
+        b[c] = centre_B<D, 0>(r, r.B0[so], c, i, j, k, id) + bext_at(r, c, i);
+    }
+    const T *A = r.phi[la], *Bp = r.phi[lb];
+    T dtphi = (Bp[id] - A[id]) * r.inv_dt;
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        T up = r.half * (phi_nb(r, A, la, d, 1, i, j, k, id) + phi_nb(r, Bp, lb, d, 1, i, j, k, id));
+        T dn = r.half * (phi_nb(r, A, la, d, -1, i, j, k, id) + phi_nb(r, Bp, lb, d, -1, i, j, k, id));
+        gp[d] = (up - dn) * r.inv2dx[d];
+    }
+    r.C[0][id] = dtphi * b[0] - (e[1] * gp[2] - e[2] * gp[1]);
+    r.C[1][id] = dtphi * b[1] - (e[2] * gp[0] - e[0] * gp[2]);
+    r.C[2][id] = dtphi * b[2] - (e[0] * gp[1] - e[1] * gp[0]);
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void e0c_body(const RunK<T>& r, long bx, long step)
 {
@@ -669,8 +727,10 @@ k3_tile(const RunK<T> *__restrict__ rp, long step, int tz)
     if (i >= r.nn[0] || j >= r.nn[1]) return;
     const int so = em_slot(step), sn = em_slot(step + 1);
     const int k0 = blockIdx.z * tz, k1 = min(k0 + tz, r.nn[2]);
+    T ez_up = T(0);
+    bool have = false;
     for (int k = k0; k < k1; k++) {
-        if (PH == kTE0C) e0c_at<D, T>(r, i, j, k, step);
+        if (PH == kTE0C) e0c_walk_at<D, T>(r, i, j, k, step, ez_up, have);
         else if (PH == kTE1) e1_at<D, T>(r, i, j, k, so, so, sn, T(1));
         else if (PH == kTB) b_at<D, T>(r, i, j, k, step);
         else phi_at<D, T>(r, i, j, k, step);
