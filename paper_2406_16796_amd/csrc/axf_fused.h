@@ -68,4 +68,21 @@ void wave2d_quad_blocks(const RunK<T>& h, int ci, int cf, long blk[3]);
 template <typename T>
 void wave2d_blocks(const RunK<T>& h, int chunk, long *edge_blocks, long *interior_blocks);
 
+// One-pass 3D step (a z march of row wavefronts stacked along y, y neighbours
+// through LDS): x segments of `wid` own columns, groups of own rows, chunks
+// of `zc` planes.
+struct M3Geom {
+    int nseg, wid;   // x segments and own columns per segment
+    int nyg;         // row groups
+    int nzc, zc;     // plane chunks and planes per chunk
+};
+// the run fits the march (32-bit offsets within an array)
+template <typename T>
+bool march3d_available(const RunK<T>& h);
+// workgroups of one launch with chunks of zc planes (0: default)
+template <typename T>
+long march3d_blocks(const RunK<T>& h, int zc);
+template <typename T>
+hipError_t launch_march3d(const RunK<T> *rk, const RunK<T>& h, long step, int zc, hipStream_t st);
+
 }  // namespace axf

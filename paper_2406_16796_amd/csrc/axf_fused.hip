@@ -359,24 +359,6 @@ __device__ __forceinline__ T mur_update(const KV<T>& r, int O, int c, int d, int
     return (T)(sg_n + ig_n);
 }
 
-// the same reading the laser table and Mur coefficient from the run descriptor
-template <typename T>
-__device__ __forceinline__ T mur_update_rk(const RunK<T>& r, int O, int c, int d, int side, double e_old, double e_new,
-                                           double g_old, long fidx, long step)
-{
-    double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
-    if (O == 0 && d == 0 && side == 0 && r.las.on && c == r.las.pol) {
-        const long lo = (step % r.inc_k1) * 2 * r.inc_face, ln = ((step + 1) % r.inc_k1) * 2 * r.inc_face;
-        ia_o = r.inc[lo + fidx];
-        ig_o = r.inc[lo + r.inc_face + fidx];
-        ia_n = r.inc[ln + fidx];
-        ig_n = r.inc[ln + r.inc_face + fidx];
-    }
-    double sa_o = e_old - ia_o, sa_n = e_new - ia_n, sg_o = g_old - ig_o;
-    double sg_n = sa_o + r.murc[d] * (sa_n - sg_o);
-    return (T)(sg_n + ig_n);
-}
-
 // ------------------------------------------------------------------ kernel
 
 template <int D, int TX, int TY, typename T>

@@ -60,6 +60,8 @@ struct Run {
     hipStream_t ring = nullptr;      // 2D fused: stream of the interior's ring (passes of several steps)
     hipEvent_t ev_ring = nullptr;
     long inc_lo = -1;               // first time level held by the laser table
+    bool m3_off = false;            // 3D: the tile-walk launches instead of the one-pass march
+    int m3_chunk = 0;               // 3D march: planes per workgroup (0: default)
 
     template <typename T> const RunK<T>& hk() const;
     template <typename T> const RunK<T> *rk() const { return (const RunK<T> *)(base + L.off_rk); }
@@ -79,6 +81,8 @@ int run_prepare(Run *R);
 // the run steps with the 2D wavefront kernel; its rows per march
 bool run_wave2d(const Run *R);
 int run_wave_chunk(const Run *R);
+// the run steps with the one-pass 3D march
+bool run_march3d(const Run *R);
 // rows per interior and frame wavefront of a pass of several steps, and the
 // most steps per pass
 void run_pass_shape(const Run *R, int ns, int *ci, int *cf);

@@ -392,6 +392,27 @@ static void steps_semi(Run *R, int64_t nsteps)
     }
 }
 
+// One-pass 3D step: one launch per step (the z march of axf_march3d.hip)
+template <int D, typename T>
+static int steps_march3d(Run *R, int64_t nsteps)
+{
+    const RunK<T>& h = R->hk<T>();
+    const RunK<T> *rk = R->rk<T>();
+    for (int64_t it = 0; it < nsteps; it++) {
+        long s = R->step;
+        ensure_incident<D, T>(R, s);
+        hipError_t e = launch_march3d<T>(rk, h, s, R->m3_chunk, R->stream);
+        if (e != hipSuccess) return hip_fail(e, "3D march launch");
+        if (R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0) {
+            Plain<D, T>::diag(rk, h, s, R->rec_written % h.rec_cap, R->stream);
+            R->rec_written++;
+        }
+        R->step++;
+        R->launches += 1;
+    }
+    return AXF_OK;
+}
+
 // fused tile shapes per dimensionality and precision
 template <int D, typename T> struct FusedShape;
 template <> struct FusedShape<2, float> { using F = Fused<2, 256, 1, float>; static constexpr int chunk = 64; };
@@ -479,7 +500,8 @@ static int run_steps(Run *R, int64_t nsteps, int *rc)
 {
     if (!R->converted) convert_to_leapfrog<D, T>(R);
     R->ephase_step = -1;
-    if (R->use_fused && D == 3 && !R->lds_march) steps_semi<D, T>(R, nsteps);
+    if (R->use_fused && D == 3 && run_march3d(R)) *rc = steps_march3d<D, T>(R, nsteps);
+    else if (R->use_fused && D == 3 && !R->lds_march) steps_semi<D, T>(R, nsteps);
     else if (R->use_fused) *rc = steps_fused<D, T>(R, nsteps);
     else steps_plain<D, T>(R, nsteps);
     return *rc;
@@ -541,6 +563,8 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     if (const char *ch = getenv("AXF_FUSED_CHUNK")) R->chunk = atoi(ch);
     if (const char *pd = getenv("AXF_WAVE_PD")) R->pd = atoi(pd);
     if (const char *lm = getenv("AXF_LDS_MARCH")) R->lds_march = lm[0] == '1';
+    if (const char *m3 = getenv("AXF_M3")) R->m3_off = m3[0] == '0';
+    if (const char *mc = getenv("AXF_M3_CHUNK")) R->m3_chunk = atoi(mc);
     if (const char *pe = getenv("AXF_WAVE_PASS")) R->multi = pe[0] != '0';
     if (const char *pc = getenv("AXF_PASS_CHUNK")) R->pass_ci = atoi(pc);
     if (const char *pf = getenv("AXF_PASS_FRAME")) R->pass_cf = atoi(pf);
@@ -589,6 +613,18 @@ bool run_wave2d(const Run *R)
 }
 
 int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 8; }
+
+// the one-pass 3D march: the three components of a kind addressed with 32-bit
+// offsets from one base, a plane index wrapped at most once on a periodic z
+// axis, at least one own row per y group
+bool run_march3d(const Run *R)
+{
+    if (!R->use_fused || R->cfg.ndim != 3 || R->lds_march || R->m3_off) return false;
+    if ((uint64_t)R->L.arr_stride * 3 > (1ull << 32)) return false;
+    for (int d = 0; d < 3; d++)
+        if (R->cfg.n[d] < 8) return false;
+    return true;
+}
 
 int run_pass_steps_taken(const Run *R)
 {

@@ -176,6 +176,26 @@ __device__ __forceinline__ auto pml_sdt(const R& r, int i, int j, int k) -> decl
     return s;
 }
 
+// First-order Mur update of one tangential E ghost (FP64) from the adjacent
+// point's E^{n-1/2} and E^{n+1/2} and the ghost's old value, with the laser
+// values of the per-level table on the x_min face (the unfused path's formula)
+template <typename T>
+__device__ __forceinline__ T mur_update_rk(const RunK<T>& r, int O, int c, int d, int side, double e_old, double e_new,
+                                           double g_old, long fidx, long step)
+{
+    double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
+    if (O == 0 && d == 0 && side == 0 && r.las.on && c == r.las.pol) {
+        const long lo = (step % r.inc_k1) * 2 * r.inc_face, ln = ((step + 1) % r.inc_k1) * 2 * r.inc_face;
+        ia_o = r.inc[lo + fidx];
+        ig_o = r.inc[lo + r.inc_face + fidx];
+        ia_n = r.inc[ln + fidx];
+        ig_n = r.inc[ln + r.inc_face + fidx];
+    }
+    double sa_o = e_old - ia_o, sa_n = e_new - ia_n, sg_o = g_old - ig_o;
+    double sg_n = sa_o + r.murc[d] * (sa_n - sg_o);
+    return (T)(sg_n + ig_n);
+}
+
 // ----------------------------------------------------------- analytic inputs
 
 // Laser field component comp (1: y, 2: z) at (x, y, z, t): sin^2-ramped CW or

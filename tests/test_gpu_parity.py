@@ -187,6 +187,7 @@ def test_3d_tiled_periodic_equals_plain_bitwise(axf, prec, monkeypatch):
     to the next plane is the one that plane would compute, wrap or no wrap,
     so the state equals the unfused kernels' bit for bit."""
     monkeypatch.setenv("AXF_TILED", "1")
+    monkeypatch.setenv("AXF_M3", "0")
     rng = np.random.default_rng(33)
     n = [20, 18, 18]
     dx = [0.4, 0.45, 0.5]
@@ -237,12 +238,13 @@ def test_fused_equals_plain_bitwise(axf, kind, prec, monkeypatch):
     the unfused kernels (no FP contraction), so the states agree bit for bit,
     boundaries included: the 2D wavefront kernels (the wide grids run both the
     interior and the boundary-frame kernels), the 3D semi-fused launches, and
-    the LDS-marching kernels (2d_lds, 3d_lds).  The small 3D grid takes one
-    thread per point by default; 3d_tiled forces the tile walks."""
+    the LDS-marching kernels (2d_lds, 3d_lds).  In 3D the fused path is the
+    one-pass march; 3d_tiled forces the tile-walk launches instead."""
     if kind.endswith("_lds"):
         monkeypatch.setenv("AXF_LDS_MARCH", "1")
     if kind == "3d_tiled":
         monkeypatch.setenv("AXF_TILED", "1")
+        monkeypatch.setenv("AXF_M3", "0")
     else:
         monkeypatch.delenv("AXF_TILED", raising=False)
     cfg = {"2d_out": small_2d(W.AX_OUTFLOW), "2d_pml": small_2d(W.AX_PML), "2d_ref": small_2d(W.AX_REFLECT),
