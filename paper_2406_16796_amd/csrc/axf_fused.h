@@ -73,8 +73,12 @@ void wave2d_blocks(const RunK<T>& h, int chunk, long *edge_blocks, long *interio
 // of `zc` planes.
 struct M3Geom {
     int nseg, wid;   // x segments and own columns per segment
+    int sx0, sx1;    // the segments clear of the x faces
     int nyg;         // row groups
-    int nzc, zc;     // plane chunks and planes per chunk
+    int gy0, gy1;    // the row groups clear of the y faces
+    int nzc;         // plane chunks: [0, zf), pieces of zi planes up to zend, [zend, nn2)
+    int zf, zi, zend, nn2;
+    int order;       // interior block order (bit 0: row groups fastest; bit 1: a band per XCD)
 };
 // the run fits the march (32-bit offsets within an array)
 template <typename T>

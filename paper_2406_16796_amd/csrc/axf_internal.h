@@ -56,6 +56,7 @@ constexpr int kNumFaces = 6 * kPhiSlots + 36 * kEmSlots;
 constexpr int kIncLevels = 17;   // time levels per laser table fill (16 steps)
 constexpr int kDiagSums = 6;     // FP64 partial sums per block of a diagnostic record
 constexpr int kPmlProf = 64;     // damping-layer thicknesses the wavefront interiors tabulate
+constexpr long kSinkBytes = 65536;   // per-array store sink of 3D runs (128 wavefronts x 64 lanes x 8 bytes)
 
 // Immutable per-run descriptor, stored in device memory once at creation.
 // Time-level slots rotate with the step counter (em_slot, phi_slot).
@@ -85,6 +86,7 @@ struct RunK {
     // state (uniform layout, see q_em / q_axg; the pointers below point into it)
     char *state_base, *face_base;
     long arr_stride, face_stride;
+    long arr_sink;            // byte offset of each array's store sink (3D; see kSinkBytes)
     T *E0[kEmSlots][3], *B0[kEmSlots][3], *E1[kEmSlots][3], *B1[kEmSlots][3];
     T *phi[kPhiSlots];
     T *C[3];                  // scratch: axion current at centres (plain path)

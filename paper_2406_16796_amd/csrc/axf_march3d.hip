@@ -41,8 +41,12 @@
 #include "axf_fused.h"
 #include "axf_stencil.h"
 
+#include <stdlib.h>
+
+#include <type_traits>
+
 #ifndef AXF_M3_NW
-#define AXF_M3_NW 12
+#define AXF_M3_NW 8
 #endif
 
 namespace axf {
@@ -109,7 +113,7 @@ struct M3Lds {
     enum { B0X, B0Z, PA, PB, B1X, B1Z, E0NY, E0HX, E0HY, E0HZ, CY, B0PX, B0PZ, E1X, E1Z, NQ };
     __host__ __device__ static constexpr int K(int q)
     {
-        return (q == B0X || q == B0Z || q == B0PX || q == B0PZ) ? 3 : ((q == PB || q == E0HY) ? 4 : 2);
+        return (q == B0X || q == B0Z || q == B0PX || q == B0PZ || q == PB || q == E0HY) ? 4 : 2;
     }
     __host__ __device__ static constexpr int R(int q) { return (q == B0X || q == B0Z || q == PA || q == PB) ? NW + 1 : NW; }
     __host__ __device__ static constexpr int roff(int q) { return (q == PA || q == PB) ? 1 : 0; }
@@ -134,8 +138,74 @@ struct M3Lds {
 
 extern __shared__ __align__(16) unsigned char m3_smem[];
 
+// first plane of chunk k: chunk 0 is [0, zf), chunks 1 .. nzc - 2 split
+// [zf, zend) into pieces of zi planes, chunk nzc - 1 is [zend, nn2)
+__host__ __device__ inline int m3_zb(const M3Geom& g, int k)
+{
+    if (k <= 0) return 0;
+    if (k >= g.nzc) return g.nn2;
+    if (k == g.nzc - 1) return g.zend;
+    return min(g.zf + (k - 1) * g.zi, g.zend);
+}
+
+// segment, row group and chunk of block b.  The interior launch covers the
+// box of segments [sx0, sx1), row groups [gy0, gy1) and chunks 1 .. nzc - 2;
+// the frame launch the rest: (A) the first and last chunks of every segment
+// and row group, (B) the inner chunks of the row groups outside [gy0, gy1),
+// (C) the inner chunks of those row groups in the segments outside [sx0, sx1).
+__host__ __device__ inline void m3_block(const M3Geom& g, bool frame, unsigned b, int& seg, int& ygr, int& zch)
+{
+    const unsigned nsx = (unsigned)(g.sx1 - g.sx0), ny = (unsigned)(g.gy1 - g.gy0), nzi = (unsigned)(g.nzc - 2);
+    if (!frame) {
+        // order & 2: the hardware deals blocks to the 8 XCDs in turn; give
+        // each XCD one contiguous band of the block order instead.
+        // order & 1: row groups fastest (the blocks that share halo rows run
+        // together) instead of segments fastest.
+        const unsigned nb = nsx * ny * nzi;
+        if (g.order & 2) b = (unsigned)xcd_band((long)b, (long)nb);
+        if (g.order & 1) {
+            ygr = g.gy0 + (int)(b % ny);
+            const unsigned r = b / ny;
+            seg = g.sx0 + (int)(r % nsx);
+            zch = 1 + (int)(r / nsx);
+        } else {
+            seg = g.sx0 + (int)(b % nsx);
+            const unsigned r = b / nsx;
+            ygr = g.gy0 + (int)(r % ny);
+            zch = 1 + (int)(r / ny);
+        }
+        return;
+    }
+    const unsigned nseg = (unsigned)g.nseg, nyg = (unsigned)g.nyg;
+    const unsigned na = (g.nzc > 1 ? 2u : 1u) * nseg * nyg;
+    if (b < na) {
+        seg = (int)(b % nseg);
+        const unsigned r = b / nseg;
+        ygr = (int)(r % nyg);
+        zch = r < nyg ? 0 : g.nzc - 1;
+        return;
+    }
+    b -= na;
+    const unsigned nfy = nyg - ny, nb = nseg * nfy * nzi;
+    if (b < nb) {
+        seg = (int)(b % nseg);
+        const unsigned r = b / nseg;
+        const int k = (int)(r % nfy);
+        ygr = k < g.gy0 ? k : g.gy1 + (k - g.gy0);
+        zch = 1 + (int)(r / nfy);
+        return;
+    }
+    b -= nb;
+    const unsigned nfx = nseg - nsx;
+    const int k = (int)(b % nfx);
+    seg = k < g.sx0 ? k : g.sx1 + (k - g.sx0);
+    const unsigned r = b / nfx;
+    ygr = g.gy0 + (int)(r % ny);
+    zch = 1 + (int)(r / ny);
+}
+
 // Occupancy (FP32): 12 wavefronts per workgroup, one workgroup per CU (the
-// LDS plan takes about 118 KiB), 3 wavefronts per SIMD.
+// LDS plan takes about 130 KiB), 3 wavefronts per SIMD.
 //
 // Values at positions outside a Mur axis's extents (and the axion values
 // beyond the ghost cells) are never read by a point inside them: the curl
@@ -144,7 +214,18 @@ extern __shared__ __align__(16) unsigned char m3_smem[];
 // on a boundary face averages the one interior centre twice.  So the loads
 // and intermediate values are not masked; loads of such positions read a
 // valid address, and only the stores check the extents.
-template <typename T, int NW>
+//
+// Registers.  The march is unrolled by four, so that every window along z is
+// a ring of two or four registers with a fixed home in each unrolled
+// iteration (no copies), and every LDS slot is a compile-time offset.  A
+// quantity needed for three planes gets a ring of four, whose spare slot is
+// where the loads of the next iteration land.
+//
+// GEN = false is the launch over the segments, row groups and plane chunks
+// whose columns, rows and planes (halos included) keep clear of every face
+// and do not wrap: it has no boundary code.  GEN = true covers the rest (the
+// frame), every boundary included.
+template <typename T, int NW, bool GEN>
 __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__ rp, long step, M3Geom g)
 {
     using LQ = M3Lds<T, NW>;
@@ -156,9 +237,9 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     // ---- the run's geometry and coefficients
     const int n0 = rp->n[0], n1 = rp->n[1], n2 = rp->n[2];
     const int nn0 = rp->nn[0], nn1 = rp->nn[1], nn2 = rp->nn[2];
-    const bool mx = rp->mur[0], my = rp->mur[1], mz = rp->mur[2];
-    const bool apx = rp->axbc[0] == AXF_AX_PERIODIC, apy = rp->axbc[1] == AXF_AX_PERIODIC;
-    const bool apz = rp->axbc[2] == AXF_AX_PERIODIC;
+    const bool mx = GEN && rp->mur[0], my = GEN && rp->mur[1], mz = GEN && rp->mur[2];
+    const bool apx = !GEN || rp->axbc[0] == AXF_AX_PERIODIC, apy = !GEN || rp->axbc[1] == AXF_AX_PERIODIC;
+    const bool apz = !GEN || rp->axbc[2] == AXF_AX_PERIODIC;
     constexpr unsigned es = sizeof(T);
     const unsigned sxb = (unsigned)rp->sx * es, syb = (unsigned)rp->sy * es;
     const T cdt0 = rp->cdt[0], cdt1 = rp->cdt[1], cdt2 = rp->cdt[2], half = rp->half, inv_dt = rp->inv_dt;
@@ -166,92 +247,112 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     const T idx0 = rp->inv_dx2[0], idx1 = rp->inv_dx2[1], idx2 = rp->inv_dx2[2];
     const T dt2 = rp->dt2, m2 = rp->m2, gax = rp->gax, cg1 = rp->cg1;
     const char *const sb = rp->state_base;
-    // array stride in bytes and in units of 256 bytes (arrays are 256-byte
-    // aligned and sized; the three components of a kind span < 4 GiB: host check)
-    const unsigned as32 = (unsigned)rp->arr_stride;
+    // array stride in units of 256 bytes (arrays are 256-byte aligned and sized)
+    const unsigned long long as64 = (unsigned long long)rp->arr_stride;
     unsigned as_l = (unsigned)(rp->arr_stride >> 8);
     const int so = em_slot(step), sn = em_slot(step + 1);
     const int la = phi_slot(step), lb = phi_slot(step + 1), ln = phi_slot(step + 2);
 
     // ---- this workgroup's segment, row group and plane chunk
-    unsigned bq = blockIdx.x;
-    const int seg = (int)(bq % (unsigned)g.nseg);
-    bq /= (unsigned)g.nseg;
-    const int ygr = (int)(bq % (unsigned)g.nyg);
-    const int zch = (int)(bq / (unsigned)g.nyg);
+    int seg, ygr, zch;
+    m3_block(g, GEN, blockIdx.x, seg, ygr, zch);
     const int x0 = seg * g.wid, gx = x0 - 2 + lane;
     const int y0 = ygr * TY, gy = y0 - 1 + w;
-    const int z0 = zch * g.zc, z1 = min(z0 + g.zc, nn2);
+    const int z0 = m3_zb(g, zch), z1 = m3_zb(g, zch + 1);
 
     // ---- this lane's column
-    const int xs_em = mx ? ((gx >= 0 && gx < nn0) ? gx : 0) : m3::imodn(gx, n0);
+    const int xs_em = !GEN ? gx : (mx ? ((gx >= 0 && gx < nn0) ? gx : 0) : m3::imodn(gx, n0));
     // axion column class: 0 a cell (or a periodic axis), 1 / 2 the ghost below / above, 3 none
     const int xcl = apx ? 0 : ((gx >= 0 && gx < n0) ? 0 : (gx == -1 ? 1 : (gx == n0 ? 2 : 3)));
-    const int xs_ph = apx ? m3::imodn(gx, n0) : (xcl == 0 ? gx : 0);
+    const int xs_ph = !GEN ? gx : (apx ? m3::imodn(gx, n0) : (xcl == 0 ? gx : 0));
     const unsigned xo_em = (unsigned)xs_em * es, xo_ph = (unsigned)xs_ph * es;
     // own columns: nodal x components store there, centred ones where also gx < n0
     const bool own_x = lane >= 2 && lane < 2 + g.wid && gx < nn0;
     const bool own_xc = own_x && (!mx || gx < n0);
     auto own_lane = [&](int l) __attribute__((always_inline)) { return l >= 2 && l < 2 + g.wid && x0 - 2 + l < nn0; };
     // the segment holds a ghost column of an x face (Mur or axion)
-    const bool seg_xb = (mx || !apx) && (x0 - 2 <= -1 || x0 + 61 >= n0);
-    const T bext0 = bext_at(*rp, 0, xs_em), bext1 = bext_at(*rp, 1, xs_em), bext2 = bext_at(*rp, 2, xs_em);
+    const bool seg_xb = GEN && (mx || !apx) && (x0 - 2 <= -1 || x0 + 61 >= n0);
+    // B_ext at this lane's cells (slab along x); formed at use from the slab
+    // mask in the interior launch, so that it takes no vector registers
+    const bool in_slab = xs_em >= rp->slab_lo && xs_em < rp->slab_hi;
+    const T bxs0 = rp->bext[0], bxs1 = rp->bext[1], bxs2 = rp->bext[2];
+    T bext0v = T(0), bext1v = T(0), bext2v = T(0);
+    if constexpr (GEN) {
+        bext0v = in_slab ? bxs0 : T(0);
+        bext1v = in_slab ? bxs1 : T(0);
+        bext2v = in_slab ? bxs2 : T(0);
+    }
+    auto bext_c = [&](int c) __attribute__((always_inline)) -> T {
+        if constexpr (GEN) return c == 0 ? bext0v : (c == 1 ? bext1v : bext2v);
+        return in_slab ? (c == 0 ? bxs0 : (c == 1 ? bxs1 : bxs2)) : T(0);
+    };
 
     // ---- rows (wave-uniform)
-    auto ys_em_of = [&](int y) __attribute__((always_inline)) { return my ? ((y >= 0 && y < nn1) ? y : 0) : m3::imodn(y, n1); };
+    auto ys_em_of = [&](int y) __attribute__((always_inline)) {
+        return !GEN ? y : (my ? ((y >= 0 && y < nn1) ? y : 0) : m3::imodn(y, n1));
+    };
     auto ycl_of = [&](int y) __attribute__((always_inline)) {
         return apy ? 0 : ((y >= 0 && y < n1) ? 0 : (y == -1 ? 1 : (y == n1 ? 2 : 3)));
     };
-    auto ys_ph_of = [&](int y) __attribute__((always_inline)) { return apy ? m3::imodn(y, n1) : (ycl_of(y) == 0 ? y : 0); };
+    auto ys_ph_of = [&](int y) __attribute__((always_inline)) {
+        return !GEN ? y : (apy ? m3::imodn(y, n1) : (ycl_of(y) == 0 ? y : 0));
+    };
     const int ys_em = ys_em_of(gy);
     const unsigned yo_em = (unsigned)ys_em * sxb;
     const unsigned yo_em_up = (unsigned)ys_em_of(gy + 1) * sxb;     // the top wavefront's extra row
     const int ycl_w = ycl_of(gy), ycl_dn = ycl_of(gy - 1);          // axion row classes of the row and the one below
     const int ys_ph_w = ys_ph_of(gy), ys_ph_dn = ys_ph_of(gy - 1);
-    const bool own_y = w >= 1 && w <= TY && gy < nn1;
+    const bool own_y = w >= 1 && w <= TY && (!GEN || gy < nn1);
     const bool yc = !my || gy < n1;                     // an own row is a centred-y point too
 
-    // ---- planes (uniform)
-    // a plane index is at most 5 planes outside [0, nn2): one wrap suffices
+    // ---- planes (uniform); a plane index is at most 5 planes outside [0, nn2): one wrap suffices
     auto zs_em = [&](int p) __attribute__((always_inline)) {
-        return mz ? ((p >= 0 && p < nn2) ? p : 0) : (p < 0 ? p + n2 : (p >= n2 ? p - n2 : p));
+        return !GEN ? p : (mz ? ((p >= 0 && p < nn2) ? p : 0) : (p < 0 ? p + n2 : (p >= n2 ? p - n2 : p)));
     };
     auto zcl_of = [&](int p) __attribute__((always_inline)) {
         return apz ? 0 : ((p >= 0 && p < n2) ? 0 : (p == -1 ? 1 : (p == n2 ? 2 : 3)));
     };
     auto zs_ph = [&](int p) __attribute__((always_inline)) {
-        return apz ? (p < 0 ? p + n2 : (p >= n2 ? p - n2 : p)) : (zcl_of(p) == 0 ? p : 0);
+        return !GEN ? p : (apz ? (p < 0 ? p + n2 : (p >= n2 ? p - n2 : p)) : (zcl_of(p) == 0 ? p : 0));
     };
     auto own_p = [&](int p) __attribute__((always_inline)) { return p >= z0 && p < z1; };
     auto zc = [&](int p) __attribute__((always_inline)) { return !mz || p < n2; };   // for an own plane
     auto off_em = [&](int p) __attribute__((always_inline)) -> unsigned { return xo_em + yo_em + (unsigned)zs_em(p) * syb; };
 
-    // ---- arrays: the three components of one kind and slot from one base (the
-    // stride is re-read at each stage, opaque to the compiler, so that the
-    // bases are formed where they are used instead of holding scalar registers)
+    // ---- arrays: component c of a kind and slot has its own base, so that the
+    // three share one 32-bit offset (the stride is re-read at each stage, opaque
+    // to the compiler, so that the bases are formed where they are used)
     auto abase = [&](int q) __attribute__((always_inline)) { return sb + ((unsigned long long)((unsigned)q * as_l) << 8); };
     auto kb_rd = [&](int kind) __attribute__((always_inline)) { return abase(q_em(kind, so, 0)); };
     auto kb_wr = [&](int kind) __attribute__((always_inline)) { return abase(q_em(kind, sn, 0)); };
     auto arr_ph = [&](int L) __attribute__((always_inline)) { return abase(q_phi(L)); };
-    auto ld = [&](const char *kb, int c, unsigned off) __attribute__((always_inline)) -> T { return m3::ldo<T>(kb, (unsigned)c * as32 + off); };
-    auto st = [&](const char *kb, int c, unsigned off, T v) __attribute__((always_inline)) { m3::sto<T>(kb, (unsigned)c * as32 + off, v); };
+    auto ld = [&](const char *kb, int c, unsigned off) __attribute__((always_inline)) -> T { return m3::ldo<T>(kb + c * as64, off); };
+    auto st = [&](const char *kb, int c, unsigned off, T v) __attribute__((always_inline)) { m3::sto<T>(kb + c * as64, off, v); };
 
-    // ---- LDS
-    // slot of the write of iteration i - age for quantities of K slots: kept
-    // per iteration (k2[a], k3[a], k4[a] = (i - a) mod K)
-    int k2[2] = {0, 1}, k3[3] = {0, 2, 1}, k4[4] = {0, 3, 2, 1};
-    auto lslot = [&](int K, int age) __attribute__((always_inline)) { return K == 2 ? k2[age] : (K == 3 ? k3[age] : k4[age]); };
-    auto lidx = [&](int q, int age, int row) __attribute__((always_inline)) {
-        return LQ::base(q) + (lslot(LQ::K(q), age) * LQ::R(q) + row + LQ::roff(q)) * 64;
+    int i = z0 - 2;   // the iteration (first: z0 - 2, last: z1 + 3)
+
+    // ---- LDS: row w + d of quantity q at slot s (a compile-time value in
+    // each unrolled iteration)
+    const int lrow = w * 64 + lane;
+    auto lidx = [&](int q, int s, int d) __attribute__((always_inline)) {
+        return lrow + LQ::base(q) + (s * LQ::R(q) + d + LQ::roff(q)) * 64;
     };
-    auto lw = [&](int q, int age, int row, T v) __attribute__((always_inline)) { lds[lidx(q, age, row) + lane] = v; };
-    auto lr = [&](int q, int age, int row) __attribute__((always_inline)) -> T { return lds[lidx(q, age, row) + lane]; };
-    auto lr1 = [&](int q, int age, int row) __attribute__((always_inline)) -> T { return lds[lidx(q, age, row) + lane + 1]; };
-    const int wlo = w > 0 ? w - 1 : 0;   // the row below (the lowest wavefront reads its own: never used)
+    const int wlo = w > 0 ? -1 : 0;   // the row below (the lowest wavefront reads its own: never used)
+    // Interior launch: every iteration issues the same memory instructions
+    // (loads of clamped planes, all stages, every store), so that the compiler
+    // can count the loads still in flight exactly and never waits for the
+    // stores; a point this wavefront does not own is stored to the array's sink.
+    const unsigned sink_o = (unsigned)rp->arr_sink + (((blockIdx.x * NW + (unsigned)w) & 127u) * 64u + (unsigned)lane) * es;
+    auto act = [&](int lo, int hi) __attribute__((always_inline)) { return !GEN || (i >= lo && i <= hi); };
+    auto clampz = [&](int p, int lo, int hi) __attribute__((always_inline)) { return GEN ? p : (p < lo ? lo : (p > hi ? hi : p)); };
+    // rows read one up / one down by the stages of every wavefront (interior
+    // launch): clamped to the workgroup, where an edge wavefront's value is never used
+    const int dn1 = (!GEN && w == 0) ? 0 : -1;
+    const int up1 = (!GEN && w == NW - 1) ? 0 : 1;
 
-    // ---- axion level L of row y, plane p: the array, or the y / z ghost plane
-    // for a ghost row / plane; in segments with x ghost columns also the x
-    // ghost plane, which phi_take picks for those columns
+    // ---- axion level L of a row of class ycl and storage row ys, plane p: the
+    // array, or the y / z ghost plane for a ghost row / plane; in segments with
+    // x ghost columns also the x ghost plane, which phi_take picks for those columns
     struct PhiRaw { T a, fx; };
     auto phi_load = [&](int L, int ycl, int ys, int p) __attribute__((always_inline)) -> PhiRaw {
         PhiRaw r{T(0), T(0)};
@@ -271,67 +372,84 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
         return (xcl == 1 || xcl == 2) ? r.fx : r.a;
     };
 
-    // ---- register windows along z (suffix k = plane i - k of iteration i)
-    T b0_0[3] = {0, 0, 0}, b0_1[3] = {0, 0, 0}, b0_2[3] = {0, 0, 0};
+    // ---- windows along z.  Rings of four are indexed by (t - i_first) mod 4,
+    // t the iteration that took the value in (loads) or computed it; rings of
+    // two likewise mod 2.
+    //   b0r: B0 of plane t            b1r: B1 of plane t - 2
+    //   e0r: E0^{n-1/2} of plane t - 1 e1r: E1^{n-1/2} of plane t - 3
+    //   e0hr: E0^{n+1/2} of plane t - 1, e0nr: E0^n of plane t - 1
+    //   cxy, cz: C of plane t - 2 (x, y in a ring of two, z in a ring of four)
+    //   bor: B0^n averaged to the centres of plane t - 2 (the current's)
+    //   b0pr: B0^{n+1} of plane t - 2   e1hr: E1^{n+1/2} of plane t - 3
+    T b0r[4][3], b1r[4][3], e0r[2][3], e1r[2][3], e0hr[4][3], e0nr[2][3], cxy[2][2], cz[4], bor[4][3], b0pr[4][3],
+        e1hr[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        cz[k] = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; c++) b0r[k][c] = b1r[k][c] = e0hr[k][c] = bor[k][c] = b0pr[k][c] = e1hr[k][c] = T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        cxy[k][0] = cxy[k][1] = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; c++) e0r[k][c] = e1r[k][c] = e0nr[k][c] = T(0);
+    }
+    // the axion levels (planes i - 1 .. i - 4 and i - 1 .. i - 5) and the
+    // loads of the next iteration's axion levels and extra rows
     T pa_1 = 0, pa_2 = 0, pa_3 = 0, pa_4 = 0;
     T pb_1 = 0, pb_2 = 0, pb_3 = 0, pb_4 = 0, pb_5 = 0;
-    T e0n_1[3] = {0, 0, 0}, e0n_2[3] = {0, 0, 0};
-    T e0h_1[3] = {0, 0, 0}, e0h_2[3] = {0, 0, 0}, e0h_3[3] = {0, 0, 0}, e0h_4[3] = {0, 0, 0};
-    T c_2[3] = {0, 0, 0}, c_3[3] = {0, 0, 0}, c_4z = 0;
-    T bo_2[3] = {0, 0, 0}, bo_3[3] = {0, 0, 0}, bo_4[3] = {0, 0, 0};
-    T b0p_2[3] = {0, 0, 0}, b0p_3[3] = {0, 0, 0}, b0p_4[3] = {0, 0, 0};
-    T b1_2[3] = {0, 0, 0}, b1_3[3] = {0, 0, 0}, b1_4[3] = {0, 0, 0};
-    T e1h_3[3] = {0, 0, 0}, e1h_4[3] = {0, 0, 0}, e1h_5[2] = {0, 0};
+    PhiRaw Ppa{T(0), T(0)}, Ppb{T(0), T(0)};
+    T Pxb0x = T(0), Pxb0z = T(0);      // B0x, B0z of the row above (the highest wavefront)
+    T Pxpa = T(0), Pxpb = T(0);        // both axion levels of the row below (the lowest)
+    T Pxpa_f = T(0), Pxpb_f = T(0);    // ... their x ghost values (frame launch)
 
-    // values loaded one iteration ahead
-    struct Pre {
-        T b0[3], e0[3], b1[3], e1[3], xb0x, xb0z;
-        PhiRaw pa, pb, xpa, xpb;
-    };
-    Pre P;
-#pragma unroll
-    for (int c = 0; c < 3; c++) P.b0[c] = P.e0[c] = P.b1[c] = P.e1[c] = T(0);
-    P.xb0x = P.xb0z = T(0);
-    P.pa = P.pb = P.xpa = P.xpb = PhiRaw{T(0), T(0)};
     // first and last iterations of the march, and the iterations each load
     // group and stage is needed in (no owned value depends on the others)
     const int i_first = z0 - 2, i_last = z1 + 3;
-    auto prefetch = [&](int i) __attribute__((always_inline)) {
+    // the loads taken in by iteration t (ring slots of t)
+    auto prefetch = [&](int t, auto Sc) __attribute__((always_inline)) {
+        constexpr int S4 = decltype(Sc)::value & 3, S2 = decltype(Sc)::value & 1;
         asm volatile("" : "+s"(as_l));
-        if (i <= z1 + 1) {                       // B0 of plane i, axion levels of plane i - 1
+        auto need = [&](int lo, int hi) __attribute__((always_inline)) { return !GEN || (t >= lo && t <= hi); };
+        if (need(-(1 << 30), z1 + 1)) {          // B0 of plane t, axion levels of plane t - 1
             const char *kb = kb_rd(1);
-            const unsigned o = off_em(i);
+            const int pz = clampz(t, z0 - 2, z1 + 1), pp = clampz(t - 1, z0 - 3, z1);
+            const unsigned o = off_em(pz);
 #pragma unroll
-            for (int c = 0; c < 3; c++) P.b0[c] = ld(kb, c, o);
-            P.pa = phi_load(la, ycl_w, ys_ph_w, i - 1);
-            P.pb = phi_load(lb, ycl_w, ys_ph_w, i - 1);
-            if (w == NW - 1) {
-                const unsigned ox = xo_em + yo_em_up + (unsigned)zs_em(i) * syb;
-                P.xb0x = ld(kb, 0, ox);
-                P.xb0z = ld(kb, 2, ox);
+            for (int c = 0; c < 3; c++) b0r[S4][c] = ld(kb, c, o);
+            Ppa = phi_load(la, ycl_w, ys_ph_w, pp);
+            Ppb = phi_load(lb, ycl_w, ys_ph_w, pp);
+            if (!GEN || w == NW - 1) {       // (every wavefront of the interior launch loads the extra rows)
+                const unsigned ox = xo_em + yo_em_up + (unsigned)zs_em(pz) * syb;
+                Pxb0x = ld(kb, 0, ox);
+                Pxb0z = ld(kb, 2, ox);
             }
-            if (w == 0) {
-                P.xpa = phi_load(la, ycl_dn, ys_ph_dn, i - 1);
-                P.xpb = phi_load(lb, ycl_dn, ys_ph_dn, i - 1);
+            if (!GEN || w == 0) {
+                const PhiRaw ra = phi_load(la, ycl_dn, ys_ph_dn, pp), rb = phi_load(lb, ycl_dn, ys_ph_dn, pp);
+                Pxpa = ra.a;
+                Pxpb = rb.a;
+                Pxpa_f = ra.fx;
+                Pxpb_f = rb.fx;
             }
         }
-        if (i >= z0 - 1 && i <= z1 + 1) {       // E0^{n-1/2} of plane i - 1
+        if (need(z0 - 1, z1 + 1)) {              // E0^{n-1/2} of plane t - 1
             const char *kb = kb_rd(0);
-            const unsigned o = off_em(i - 1);
+            const unsigned o = off_em(clampz(t - 1, z0 - 2, z1));
 #pragma unroll
-            for (int c = 0; c < 3; c++) P.e0[c] = ld(kb, c, o);
+            for (int c = 0; c < 3; c++) e0r[S2][c] = ld(kb, c, o);
         }
-        if (i >= z0 + 1 && i <= z1 + 2) {       // B1 of plane i - 2
+        if (need(z0 + 1, z1 + 2)) {              // B1 of plane t - 2
             const char *kb = kb_rd(3);
-            const unsigned o = off_em(i - 2);
+            const unsigned o = off_em(clampz(t - 2, z0 - 1, z1));
 #pragma unroll
-            for (int c = 0; c < 3; c++) P.b1[c] = ld(kb, c, o);
+            for (int c = 0; c < 3; c++) b1r[S4][c] = ld(kb, c, o);
         }
-        if (i >= z0 + 2 && i <= z1 + 2) {       // E1^{n-1/2} of plane i - 3
+        if (need(z0 + 2, z1 + 2)) {              // E1^{n-1/2} of plane t - 3
             const char *kb = kb_rd(2);
-            const unsigned o = off_em(i - 3);
+            const unsigned o = off_em(clampz(t - 3, z0 - 1, z1 - 1));
 #pragma unroll
-            for (int c = 0; c < 3; c++) P.e1[c] = ld(kb, c, o);
+            for (int c = 0; c < 3; c++) e1r[S2][c] = ld(kb, c, o);
         }
     };
 
@@ -342,79 +460,59 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
         return mur_update_rk<T>(*rp, O, c, d, side, (double)e_old, (double)e_new, g_old, fidx, step);
     };
 
-    prefetch(i_first);
-    for (int i = i_first; i <= i_last; i++) {
-        // rotate the LDS slots: slot of iteration i for each K (the first
-        // iteration's slots are the initial ones)
-        if (i > i_first) {
-            k2[1] = k2[0]; k2[0] ^= 1;
-            k3[2] = k3[1]; k3[1] = k3[0]; k3[0] = k3[0] == 2 ? 0 : k3[0] + 1;
-            k4[3] = k4[2]; k4[2] = k4[1]; k4[1] = k4[0]; k4[0] = (k4[0] + 1) & 3;
-        }
-        // ---- rotate the windows and take in the loads of this iteration
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            b0_2[c] = b0_1[c];
-            b0_1[c] = b0_0[c];
-            e0n_2[c] = e0n_1[c];
-            e0h_4[c] = e0h_3[c];
-            e0h_3[c] = e0h_2[c];
-            e0h_2[c] = e0h_1[c];
-            bo_4[c] = bo_3[c];
-            bo_3[c] = bo_2[c];
-            b0p_4[c] = b0p_3[c];
-            b0p_3[c] = b0p_2[c];
-            b1_4[c] = b1_3[c];
-            b1_3[c] = b1_2[c];
-        }
-        c_4z = c_3[2];
-#pragma unroll
-        for (int c = 0; c < 3; c++) c_3[c] = c_2[c];
-        e1h_5[0] = e1h_4[0];
-        e1h_5[1] = e1h_4[1];
-#pragma unroll
-        for (int c = 0; c < 3; c++) e1h_4[c] = e1h_3[c];
-        pa_4 = pa_3; pa_3 = pa_2; pa_2 = pa_1;
-        pb_5 = pb_4; pb_4 = pb_3; pb_3 = pb_2; pb_2 = pb_1;
+    auto iter = [&](auto Jc) __attribute__((always_inline)) {
+        constexpr int J = decltype(Jc)::value;
+        // ring slots of the values taken in / computed k iterations ago
+        constexpr int Q0 = J & 3, Q1 = (J + 3) & 3, Q2 = (J + 2) & 3, Q3 = (J + 1) & 3;
+        constexpr int H0 = J & 1, H1 = (J + 1) & 1;
+        // LDS slot of the write of k iterations ago, K slots
+        constexpr int L20 = J & 1, L21 = (J + 1) & 1;
+        constexpr int L40 = J & 3, L41 = (J + 3) & 3, L42 = (J + 2) & 3, L43 = (J + 1) & 3;
+        auto LW = [&](int q, int s, int d, T v) __attribute__((always_inline)) { lds[lidx(q, s, d)] = v; };
+        auto LR = [&](int q, int s, int d) __attribute__((always_inline)) -> T { return lds[lidx(q, s, d)]; };
+        auto LR1 = [&](int q, int s, int d) __attribute__((always_inline)) -> T { return lds[lidx(q, s, d) + 1]; };
+        auto LRm = [&](int q, int s, int d) __attribute__((always_inline)) -> T { return lds[lidx(q, s, d) - 1]; };
 
+        // ---- take in the axion levels and extra rows, then load for iteration i + 1
+        // the axion levels of this row: the interior launch keeps planes i - 3,
+        // i - 4 of the older level and i - 5 of the newer in registers and reads
+        // the others from its own LDS row (the two reads below take the slots
+        // written two and four iterations ago before this iteration reuses them)
+        if constexpr (!GEN) {
+            pa_4 = pa_3;
+            pa_3 = LR(LQ::PA, L20, 0);
+            pb_5 = LR(LQ::PB, L40, 0);
+        } else {
+            pa_4 = pa_3; pa_3 = pa_2; pa_2 = pa_1;
+            pb_5 = pb_4; pb_4 = pb_3; pb_3 = pb_2; pb_2 = pb_1;
+        }
         const int p1 = i - 1, p2 = i - 2, p3 = i - 3, p4 = i - 4;
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            b0_0[c] = P.b0[c];
-            b1_2[c] = P.b1[c];
-        }
-        pa_1 = phi_take(P.pa, ycl_w, p1);
-        pb_1 = phi_take(P.pb, ycl_w, p1);
-        const T xb0x = P.xb0x, xb0z = P.xb0z;
-        T xpa = T(0), xpb = T(0);
+        pa_1 = phi_take(Ppa, ycl_w, p1);
+        pb_1 = phi_take(Ppb, ycl_w, p1);
         if (w == 0) {
-            xpa = phi_take(P.xpa, ycl_dn, p1);
-            xpb = phi_take(P.xpb, ycl_dn, p1);
+            LW(LQ::PA, L20, -1, phi_take(PhiRaw{Pxpa, Pxpa_f}, ycl_dn, p1));
+            LW(LQ::PB, L40, -1, phi_take(PhiRaw{Pxpb, Pxpb_f}, ycl_dn, p1));
         }
-        const T e0o[3] = {P.e0[0], P.e0[1], P.e0[2]};
-        const T e1o[3] = {P.e1[0], P.e1[1], P.e1[2]};
-        if (i < i_last) prefetch(i + 1);
+        LW(LQ::PA, L20, 0, pa_1);
+        LW(LQ::PB, L40, 0, pb_1);
+        LW(LQ::B0X, L40, 0, b0r[Q0][0]);
+        LW(LQ::B0Z, L40, 0, b0r[Q0][2]);
+        if (w == NW - 1) {
+            LW(LQ::B0X, L40, 1, Pxb0x);
+            LW(LQ::B0Z, L40, 1, Pxb0z);
+        }
+        if (!GEN || i < i_last) prefetch(i + 1, std::integral_constant<int, (J + 1) & 3>{});
 
         // ---- loaded values the neighbouring rows read
-        lw(LQ::B0X, 0, w, b0_0[0]);
-        lw(LQ::B0Z, 0, w, b0_0[2]);
-        lw(LQ::PA, 0, w, pa_1);
-        lw(LQ::PB, 0, w, pb_1);
-        lw(LQ::B1X, 0, w, b1_2[0]);
-        lw(LQ::B1Z, 0, w, b1_2[2]);
-        if (w == NW - 1) {
-            lw(LQ::B0X, 0, NW, xb0x);
-            lw(LQ::B0Z, 0, NW, xb0z);
-        }
-        if (w == 0) {
-            lw(LQ::PA, 0, -1, xpa);
-            lw(LQ::PB, 0, -1, xpb);
-        }
+        LW(LQ::B1X, L20, 0, b1r[Q0][0]);
+        LW(LQ::B1Z, L20, 0, b1r[Q0][2]);
 
         // ================================================ S1: E0 at plane p1
         asm volatile("" : "+s"(as_l));
-        if (i >= z0 - 1 && i <= z1 + 1) {
-            const T b0z_y = lr(LQ::B0Z, 1, w + 1), b0x_y = lr(LQ::B0X, 1, w + 1);
+        if (act(z0 - 1, z1 + 1)) {
+            const T *b0_0 = b0r[Q0], *b0_1 = b0r[Q1];
+            const T *e0o = e0r[H0];
+            const T b0z_y = LR(LQ::B0Z, L41, 1), b0x_y = LR(LQ::B0X, L41, 1);
             const T b0z_x = m3::lane_up(b0_1[2]), b0y_x = m3::lane_up(b0_1[1]);
             T eh[3], en[3];
             {
@@ -434,7 +532,13 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
             }
 #pragma unroll
             for (int c = 0; c < 3; c++) en[c] = half * (e0o[c] + eh[c]);
-            if (own_y && own_p(p1)) {
+            if constexpr (!GEN) {
+                const unsigned o = (own_x && own_y && own_p(p1)) ? off_em(p1) : sink_o;
+                const char *kb = kb_wr(0);
+                st(kb, 0, o, eh[0]);
+                st(kb, 1, o, eh[1]);
+                st(kb, 2, o, eh[2]);
+            } else if (own_y && own_p(p1)) {
                 const char *kb = kb_wr(0);
                 const unsigned o = off_em(p1);
                 if (yc && zc(p1) && own_x) st(kb, 0, o, eh[0]);
@@ -469,10 +573,10 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
 #pragma unroll
                 for (int c = 0; c < 2; c++) {
                     T e_old = side ? ld(kb, c, off_em(n2 - 1)) : e0o[c];
-                    T e_new = side ? e0h_2[c] : eh[c];
+                    T e_new = side ? e0hr[Q1][c] : eh[c];
                     T v = mur(0, c, 2, side, e_old, e_new, f);
                     if (side) eh[c] = v;
-                    else e0h_2[c] = v;
+                    else e0hr[Q1][c] = v;
                     if (owner && (c == 0 ? yc && own_x : own_xc)) m3::fst(rp, q_mur(0, 2, side, c, sn), f, v);
                 }
             }
@@ -487,63 +591,102 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 const T gzv = mur(0, 2, 1, 0, e0o[2], eh[2], f);
                 if (owner && zc(p1) && own_x) m3::fst(rp, q_mur(0, 1, 0, 0, sn), f, gxv);
                 if (owner && own_xc) m3::fst(rp, q_mur(0, 1, 0, 2, sn), f, gzv);
-                lw(LQ::E0HX, 0, w - 1, gxv);
-                lw(LQ::E0HZ, 0, w - 1, gzv);
+                LW(LQ::E0HX, L20, -1, gxv);
+                LW(LQ::E0HZ, L20, -1, gzv);
             }
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                e0h_1[c] = eh[c];
-                e0n_1[c] = en[c];
+                e0hr[Q0][c] = eh[c];
+                e0nr[H0][c] = en[c];
             }
-            lw(LQ::E0NY, 0, w, en[1]);
-            lw(LQ::E0HY, 0, w, eh[1]);
+            LW(LQ::E0NY, L20, 0, en[1]);
+            LW(LQ::E0HY, L40, 0, eh[1]);
             if (!(my && gy == -1)) {
-                lw(LQ::E0HX, 0, w, eh[0]);
-                lw(LQ::E0HZ, 0, w, eh[2]);
+                LW(LQ::E0HX, L20, 0, eh[0]);
+                LW(LQ::E0HZ, L20, 0, eh[2]);
             }
         }
 
         // ================================================ S2: C at the cells of plane p2
-        if (w <= NW - 2 && i >= z0 && i <= z1 + 1) {
+        if ((!GEN || w <= NW - 2) && act(z0, z1 + 1)) {
+            const T *b0_1 = b0r[Q1], *b0_2 = b0r[Q2];
+            const T *e0n_1 = e0nr[H0], *e0n_2 = e0nr[H1];
             T e[3], bb[3], gp[3], bo[3];
             e[0] = half * (e0n_2[0] + m3::lane_up(e0n_2[0]));
-            e[1] = half * (e0n_2[1] + lr(LQ::E0NY, 1, w + 1));
+            e[1] = half * (e0n_2[1] + LR(LQ::E0NY, L21, up1));
             e[2] = half * (e0n_2[2] + e0n_1[2]);
-            const T bxy0 = lr(LQ::B0X, 2, w + 1), bxy1 = lr(LQ::B0X, 1, w + 1);
-            const T bzy = lr(LQ::B0Z, 2, w + 1), bzyx = lr1(LQ::B0Z, 2, w + 1);
+            const T bxy0 = LR(LQ::B0X, L42, 1), bxy1 = LR(LQ::B0X, L41, 1);
+            const T bzy = LR(LQ::B0Z, L42, 1), bzyx = LR1(LQ::B0Z, L42, 1);
             bo[0] = T(0.25) * ((b0_2[0] + bxy0) + (b0_1[0] + bxy1));
             bo[1] = T(0.25) * ((b0_2[1] + m3::lane_up(b0_2[1])) + (b0_1[1] + m3::lane_up(b0_1[1])));
             bo[2] = T(0.25) * ((b0_2[2] + m3::lane_up(b0_2[2])) + (bzy + bzyx));
-            bb[0] = bo[0] + bext0;
-            bb[1] = bo[1] + bext1;
-            bb[2] = bo[2] + bext2;
-            T dtphi = (pb_2 - pa_2) * inv_dt;
+            bb[0] = bo[0] + bext_c(0);
+            bb[1] = bo[1] + bext_c(1);
+            bb[2] = bo[2] + bext_c(2);
+            T qa2, qb2, qb3, upa2, upb2, dna2, dnb2;
+            if constexpr (!GEN) {
+                qa2 = LR(LQ::PA, L21, 0);
+                qb2 = LR(LQ::PB, L41, 0);
+                qb3 = LR(LQ::PB, L42, 0);
+                upa2 = LR1(LQ::PA, L21, 0);
+                upb2 = LR1(LQ::PB, L41, 0);
+                dna2 = LRm(LQ::PA, L21, 0);
+                dnb2 = LRm(LQ::PB, L41, 0);
+            } else {
+                qa2 = pa_2;
+                qb2 = pb_2;
+                qb3 = pb_3;
+                upa2 = m3::lane_up(pa_2);
+                upb2 = m3::lane_up(pb_2);
+                dna2 = m3::lane_dn(pa_2);
+                dnb2 = m3::lane_dn(pb_2);
+            }
+            T dtphi = (qb2 - qa2) * inv_dt;
             {
-                T up = half * (m3::lane_up(pa_2) + m3::lane_up(pb_2)), dn = half * (m3::lane_dn(pa_2) + m3::lane_dn(pb_2));
+                T up = half * (upa2 + upb2), dn = half * (dna2 + dnb2);
                 gp[0] = (up - dn) * i2x0;
             }
             {
-                T up = half * (lr(LQ::PA, 1, w + 1) + lr(LQ::PB, 1, w + 1));
-                T dn = half * (lr(LQ::PA, 1, w - 1) + lr(LQ::PB, 1, w - 1));
+                T up = half * (LR(LQ::PA, L21, up1) + LR(LQ::PB, L41, up1));
+                T dn = half * (LR(LQ::PA, L21, -1) + LR(LQ::PB, L41, -1));
                 gp[1] = (up - dn) * i2x1;
             }
             {
-                T up = half * (pa_1 + pb_1), dn = half * (pa_3 + pb_3);
+                T up = half * (pa_1 + pb_1), dn = half * (pa_3 + qb3);
                 gp[2] = (up - dn) * i2x2;
             }
-            c_2[0] = dtphi * bb[0] - (e[1] * gp[2] - e[2] * gp[1]);
-            c_2[1] = dtphi * bb[1] - (e[2] * gp[0] - e[0] * gp[2]);
-            c_2[2] = dtphi * bb[2] - (e[0] * gp[1] - e[1] * gp[0]);
+            cxy[H0][0] = dtphi * bb[0] - (e[1] * gp[2] - e[2] * gp[1]);
+            cxy[H0][1] = dtphi * bb[1] - (e[2] * gp[0] - e[0] * gp[2]);
+            cz[Q0] = dtphi * bb[2] - (e[0] * gp[1] - e[1] * gp[0]);
 #pragma unroll
-            for (int c = 0; c < 3; c++) bo_2[c] = bo[c];
-            lw(LQ::CY, 0, w, c_2[1]);
+            for (int c = 0; c < 3; c++) bor[Q0][c] = bo[c];
+            LW(LQ::CY, L20, 0, cxy[H0][1]);
         }
 
         // ================================================ S3: B0^{n+1} at plane p2
         asm volatile("" : "+s"(as_l));
-        if (w >= 1 && i >= z0 + 2 && i <= z1 + 2) {
-            const T exm = lr(LQ::E0HX, 1, w - 1), ezm = lr(LQ::E0HZ, 1, w - 1);
-            T ex = e0h_2[0], ez = e0h_2[2];
+        if ((!GEN || w >= 1) && act(z0 + 2, z1 + 2)) {
+            const T *b0_2 = b0r[Q2];
+            const T exm = LR(LQ::E0HX, L21, dn1), ezm = LR(LQ::E0HZ, L21, dn1);
+            // E0^{n+1/2} of this row at planes p2 and p2 - 1 (the interior launch
+            // reads the copies its own row wrote to LDS instead of keeping them)
+            T e2[3], e3x, e3y, dn_ez, dn_e2y;
+            if constexpr (!GEN) {
+                e2[0] = LR(LQ::E0HX, L21, 0);
+                e2[1] = LR(LQ::E0HY, L41, 0);
+                e2[2] = LR(LQ::E0HZ, L21, 0);
+                e3x = e0hr[Q2][0];
+                e3y = LR(LQ::E0HY, L42, 0);
+                dn_ez = LRm(LQ::E0HZ, L21, 0);
+                dn_e2y = LRm(LQ::E0HY, L41, 0);
+            } else {
+                e2[0] = e0hr[Q1][0];
+                e2[1] = e0hr[Q1][1];
+                e2[2] = e0hr[Q1][2];
+                e3x = e0hr[Q2][0];
+                e3y = e0hr[Q2][1];
+            }
+            T ex = e2[0], ez = e2[2];
             const bool ownr = own_y && own_p(p2);
             if (my && gy == n1) {
                 // the Mur ghosts above the top y face, from row n1 - 1's E0x, E0z
@@ -555,20 +698,30 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 if (ownr && zc(p2) && own_x) m3::fst(rp, q_mur(0, 1, 1, 0, sn), f, ex);
                 if (ownr && own_xc) m3::fst(rp, q_mur(0, 1, 1, 2, sn), f, ez);
             }
+            if constexpr (GEN) {
+                dn_ez = m3::lane_dn(ez);
+                dn_e2y = m3::lane_dn(e2[1]);
+            }
             T v[3];
             {
-                T a = cdt1 * (ez - ezm), b = cdt2 * (e0h_2[1] - e0h_3[1]);
+                T a = cdt1 * (ez - ezm), b = cdt2 * (e2[1] - e3y);
                 v[0] = b0_2[0] - (a - b);
             }
             {
-                T a = cdt2 * (ex - e0h_3[0]), b = cdt0 * (ez - m3::lane_dn(ez));
+                T a = cdt2 * (ex - e3x), b = cdt0 * (ez - dn_ez);
                 v[1] = b0_2[1] - (a - b);
             }
             {
-                T a = cdt0 * (e0h_2[1] - m3::lane_dn(e0h_2[1])), b = cdt1 * (ex - exm);
+                T a = cdt0 * (e2[1] - dn_e2y), b = cdt1 * (ex - exm);
                 v[2] = b0_2[2] - (a - b);
             }
-            if (ownr) {
+            if constexpr (!GEN) {
+                const unsigned o = (own_x && ownr) ? off_em(p2) : sink_o;
+                const char *kb = kb_wr(1);
+                st(kb, 0, o, v[0]);
+                st(kb, 1, o, v[1]);
+                st(kb, 2, o, v[2]);
+            } else if (ownr) {
                 const char *kb = kb_wr(1);
                 const unsigned o = off_em(p2);
                 if (own_xc) st(kb, 0, o, v[0]);
@@ -576,16 +729,20 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 if (zc(p2) && own_x) st(kb, 2, o, v[2]);
             }
 #pragma unroll
-            for (int c = 0; c < 3; c++) b0p_2[c] = v[c];
-            lw(LQ::B0PX, 0, w, v[0]);
-            lw(LQ::B0PZ, 0, w, v[2]);
+            for (int c = 0; c < 3; c++) b0pr[Q0][c] = v[c];
+            LW(LQ::B0PX, L40, 0, v[0]);
+            LW(LQ::B0PZ, L40, 0, v[2]);
         }
 
         // ================================================ S4: E1 at plane p3
         asm volatile("" : "+s"(as_l));
-        if (w <= NW - 2 && i >= z0 + 2 && i <= z1 + 2) {
-            const T b1z_y = lr(LQ::B1Z, 1, w + 1), b1x_y = lr(LQ::B1X, 1, w + 1);
-            const T cym = lr(LQ::CY, 1, wlo);
+        if ((!GEN || w <= NW - 2) && act(z0 + 2, z1 + 2)) {
+            const T *b1_2 = b1r[Q0], *b1_3 = b1r[Q1];
+            const T *e1o = e1r[H0];
+            const T *c_3 = cxy[H1];
+            const T c3z = cz[Q1], c_4z = cz[Q2];
+            const T b1z_y = LR(LQ::B1Z, L21, up1), b1x_y = LR(LQ::B1X, L21, up1);
+            const T cym = LR(LQ::CY, L21, wlo);
             const T dn_cx = m3::lane_dn(c_3[0]);
             T eh[3];
             {
@@ -605,14 +762,20 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 eh[1] = e1o[1] + T(1) * rhs;
             }
             {
-                T lo = (mz && p3 - 1 < 0) ? c_3[2] : c_4z;
-                T hi = (mz && p3 > n2 - 1) ? c_4z : c_3[2];
+                T lo = (mz && p3 - 1 < 0) ? c3z : c_4z;
+                T hi = (mz && p3 > n2 - 1) ? c_4z : c3z;
                 T Sc = half * (lo + hi);
                 T a = cdt0 * (m3::lane_up(b1_3[1]) - b1_3[1]), b = cdt1 * (b1x_y - b1_3[0]);
                 T rhs = (a - b) - cg1 * Sc;
                 eh[2] = e1o[2] + T(1) * rhs;
             }
-            if (own_y && own_p(p3)) {
+            if constexpr (!GEN) {
+                const unsigned o = (own_x && own_y && own_p(p3)) ? off_em(p3) : sink_o;
+                const char *kb = kb_wr(2);
+                st(kb, 0, o, eh[0]);
+                st(kb, 1, o, eh[1]);
+                st(kb, 2, o, eh[2]);
+            } else if (own_y && own_p(p3)) {
                 const char *kb = kb_wr(2);
                 const unsigned o = off_em(p3);
                 if (yc && zc(p3) && own_x) st(kb, 0, o, eh[0]);
@@ -643,10 +806,10 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
 #pragma unroll
                 for (int c = 0; c < 2; c++) {
                     T e_old = side ? ld(kb, c, off_em(n2 - 1)) : e1o[c];
-                    T e_new = side ? e1h_4[c] : eh[c];
+                    T e_new = side ? e1hr[Q1][c] : eh[c];
                     T v = mur(1, c, 2, side, e_old, e_new, f);
                     if (side) eh[c] = v;
-                    else e1h_4[c] = v;
+                    else e1hr[Q1][c] = v;
                     if (owner && (c == 0 ? yc && own_x : own_xc)) m3::fst(rp, q_mur(1, 2, side, c, sn), f, v);
                 }
             }
@@ -657,25 +820,34 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 const T gzv = mur(1, 2, 1, 0, e1o[2], eh[2], f);
                 if (owner && zc(p3) && own_x) m3::fst(rp, q_mur(1, 1, 0, 0, sn), f, gxv);
                 if (owner && own_xc) m3::fst(rp, q_mur(1, 1, 0, 2, sn), f, gzv);
-                lw(LQ::E1X, 0, w - 1, gxv);
-                lw(LQ::E1Z, 0, w - 1, gzv);
+                LW(LQ::E1X, L20, -1, gxv);
+                LW(LQ::E1Z, L20, -1, gzv);
             }
 #pragma unroll
-            for (int c = 0; c < 3; c++) e1h_3[c] = eh[c];
+            for (int c = 0; c < 3; c++) e1hr[Q0][c] = eh[c];
             if (!(my && gy == -1)) {
-                lw(LQ::E1X, 0, w, eh[0]);
-                lw(LQ::E1Z, 0, w, eh[2]);
+                LW(LQ::E1X, L20, 0, eh[0]);
+                LW(LQ::E1Z, L20, 0, eh[2]);
             }
         }
 
         // ================================================ S5, S6 at plane p4 (own rows)
         asm volatile("" : "+s"(as_l));
-        if (own_y && i >= z0 + 4 && i <= z1 + 3) {
+        if ((!GEN || own_y) && act(z0 + 4, z1 + 3)) {
             const bool ownp = own_p(p4);
             // ---- S5: B1^{n+1}
             {
-                const T exm = lr(LQ::E1X, 1, w - 1), ezm = lr(LQ::E1Z, 1, w - 1);
-                T ex = e1h_4[0], ez = e1h_4[2];
+                const T *e1h_4 = e1hr[Q1], *e1h_5 = e1hr[Q2], *b1_4 = b1r[Q2];
+                const T exm = LR(LQ::E1X, L21, dn1), ezm = LR(LQ::E1Z, L21, dn1);
+                T ex, ez, dn_ez;
+                if constexpr (!GEN) {
+                    ex = LR(LQ::E1X, L21, 0);
+                    ez = LR(LQ::E1Z, L21, 0);
+                    dn_ez = LRm(LQ::E1Z, L21, 0);
+                } else {
+                    ex = e1h_4[0];
+                    ez = e1h_4[2];
+                }
                 if (my && gy == n1) {
                     const long f = (long)zs_em(p4) * nn0 + xs_em;
                     const unsigned om = xo_em + (unsigned)(n1 - 1) * sxb + (unsigned)zs_em(p4) * syb;
@@ -690,15 +862,22 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                     T a = cdt1 * (ez - ezm), b = cdt2 * (e1h_4[1] - e1h_5[1]);
                     v[0] = b1_4[0] - (a - b);
                 }
+                if constexpr (GEN) dn_ez = m3::lane_dn(ez);
                 {
-                    T a = cdt2 * (ex - e1h_5[0]), b = cdt0 * (ez - m3::lane_dn(ez));
+                    T a = cdt2 * (ex - e1h_5[0]), b = cdt0 * (ez - dn_ez);
                     v[1] = b1_4[1] - (a - b);
                 }
                 {
                     T a = cdt0 * (e1h_4[1] - m3::lane_dn(e1h_4[1])), b = cdt1 * (ex - exm);
                     v[2] = b1_4[2] - (a - b);
                 }
-                if (ownp) {
+                if constexpr (!GEN) {
+                    const unsigned o = (own_x && own_y && ownp) ? off_em(p4) : sink_o;
+                    const char *kb = kb_wr(3);
+                    st(kb, 0, o, v[0]);
+                    st(kb, 1, o, v[1]);
+                    st(kb, 2, o, v[2]);
+                } else if (ownp) {
                     const char *kb = kb_wr(3);
                     const unsigned o = off_em(p4);
                     if (own_xc) st(kb, 0, o, v[0]);
@@ -706,36 +885,68 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                     if (zc(p4) && own_x) st(kb, 2, o, v[2]);
                 }
             }
-            // ---- S6: phi^{n+3/2} at the cells
+                // ---- S6: phi^{n+3/2} at the cells
             {
+                const T *e0h_3 = e0hr[Q2], *e0h_4 = e0hr[Q3], *bo_4 = bor[Q2], *b0p_3 = b0pr[Q1], *b0p_4 = b0pr[Q2];
                 T e[3], bb[3], bn[3];
+                // this row's E0y^{n+1/2} at p4 and B0x, B0z^{n+1} at p4 (and B0x at p4 + 1):
+                // LDS copies in the interior launch, registers in the frame launch
+                T e4y, p4x, p3x, p4z, p4zx;
+                if constexpr (!GEN) {
+                    e4y = LR(LQ::E0HY, L43, 0);
+                    p4x = LR(LQ::B0PX, L42, 0);
+                    p3x = LR(LQ::B0PX, L41, 0);
+                    p4z = LR(LQ::B0PZ, L42, 0);
+                    p4zx = LR1(LQ::B0PZ, L42, 0);
+                } else {
+                    e4y = e0h_4[1];
+                    p4x = b0p_4[0];
+                    p3x = b0p_3[0];
+                    p4z = b0p_4[2];
+                    p4zx = m3::lane_up(b0p_4[2]);
+                }
                 e[0] = half * (e0h_4[0] + m3::lane_up(e0h_4[0]));
-                e[1] = half * (e0h_4[1] + lr(LQ::E0HY, 3, w + 1));
+                e[1] = half * (e4y + LR(LQ::E0HY, L43, up1));
                 e[2] = half * (e0h_4[2] + e0h_3[2]);
-                bn[0] = T(0.25) * ((b0p_4[0] + lr(LQ::B0PX, 2, w + 1)) + (b0p_3[0] + lr(LQ::B0PX, 1, w + 1)));
+                bn[0] = T(0.25) * ((p4x + LR(LQ::B0PX, L42, up1)) + (p3x + LR(LQ::B0PX, L41, up1)));
                 bn[1] = T(0.25) * ((b0p_4[1] + m3::lane_up(b0p_4[1])) + (b0p_3[1] + m3::lane_up(b0p_3[1])));
-                bn[2] = T(0.25) * ((b0p_4[2] + m3::lane_up(b0p_4[2])) + (lr(LQ::B0PZ, 2, w + 1) + lr1(LQ::B0PZ, 2, w + 1)));
-                bb[0] = half * (bo_4[0] + bn[0]) + bext0;
-                bb[1] = half * (bo_4[1] + bn[1]) + bext1;
-                bb[2] = half * (bo_4[2] + bn[2]) + bext2;
+                bn[2] = T(0.25) * ((p4z + p4zx) + (LR(LQ::B0PZ, L42, up1) + LR1(LQ::B0PZ, L42, up1)));
+                bb[0] = half * (bo_4[0] + bn[0]) + bext_c(0);
+                bb[1] = half * (bo_4[1] + bn[1]) + bext_c(1);
+                bb[2] = half * (bo_4[2] + bn[2]) + bext_c(2);
                 T sax = gax * (e[0] * bb[0] + e[1] * bb[1] + e[2] * bb[2]);
-                T pa = pa_4, pb = pb_4;
+                T pb, upb4, dnb4, qb3s;
+                if constexpr (!GEN) {
+                    pb = LR(LQ::PB, L43, 0);
+                    upb4 = LR1(LQ::PB, L43, 0);
+                    dnb4 = LRm(LQ::PB, L43, 0);
+                    qb3s = LR(LQ::PB, L42, 0);
+                } else {
+                    pb = pb_4;
+                    upb4 = m3::lane_up(pb_4);
+                    dnb4 = m3::lane_dn(pb_4);
+                    qb3s = pb_3;
+                }
+                const T pa = pa_4;
                 T lap = T(0);
-                lap += ((m3::lane_up(pb_4) - T(2) * pb) + m3::lane_dn(pb_4)) * idx0;
-                lap += ((lr(LQ::PB, 3, w + 1) - T(2) * pb) + lr(LQ::PB, 3, w - 1)) * idx1;
-                lap += ((pb_3 - T(2) * pb) + pb_5) * idx2;
+                lap += ((upb4 - T(2) * pb) + dnb4) * idx0;
+                lap += ((LR(LQ::PB, L43, up1) - T(2) * pb) + LR(LQ::PB, L43, -1)) * idx1;
+                lap += ((qb3s - T(2) * pb) + pb_5) * idx2;
                 const int gz = zs_em(p4);
-                const bool pml = rp->axbc[0] == AXF_AX_PML || rp->axbc[1] == AXF_AX_PML || rp->axbc[2] == AXF_AX_PML;
+                // (a run with a damping layer has no interior launch)
+                const bool pml = GEN && (rp->axbc[0] == AXF_AX_PML || rp->axbc[1] == AXF_AX_PML || rp->axbc[2] == AXF_AX_PML);
                 T sdt = pml ? pml_sdt<3>(*rp, xs_em, ys_em, gz) : T(0);
                 T xq = dt2 * ((sax - m2 * pb) + lap) - sdt * sdt * pb;
                 T pn = ((xq + sdt * pa) + T(2) * pb) - pa;
                 if (sdt != T(0)) pn = pn / (T(1) + sdt);
-                if (ownp && yc && zc(p4) && own_xc) {
+                if constexpr (!GEN) {
+                    m3::sto<T>(arr_ph(ln), (own_x && own_y && ownp) ? xo_em + yo_em + (unsigned)gz * syb : sink_o, pn);
+                } else if (ownp && yc && zc(p4) && own_xc) {
                     m3::sto<T>(arr_ph(ln), xo_em + yo_em + (unsigned)gz * syb, pn);
                     // axion ghosts of the new level at the boundary cells
 #pragma unroll
                     for (int d = 0; d < 3; d++) {
-                        if (rp->axbc[d] == AXF_AX_PERIODIC) continue;
+                        if (!GEN || rp->axbc[d] == AXF_AX_PERIODIC) continue;
                         const int gv = d == 0 ? xs_em : (d == 1 ? ys_em : gz);
 #pragma unroll
                         for (int side = 0; side < 2; side++) {
@@ -758,56 +969,120 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
             }
         }
         __syncthreads();
+    };
+
+    prefetch(i_first, std::integral_constant<int, 0>{});
+    for (;;) {
+        iter(std::integral_constant<int, 0>{});
+        if (++i > i_last) break;
+        iter(std::integral_constant<int, 1>{});
+        if (++i > i_last) break;
+        iter(std::integral_constant<int, 2>{});
+        if (++i > i_last) break;
+        iter(std::integral_constant<int, 3>{});
+        if (++i > i_last) break;
     }
 }
 
 // ------------------------------------------------------------------ host side
 
-template <typename T> struct March3 { static constexpr int NW = sizeof(T) == 4 ? AXF_M3_NW : 8; };
+template <typename T> struct March3 { static constexpr int NW = sizeof(T) == 4 ? AXF_M3_NW : 6; };
 
-
+// Decomposition: x segments of at most 60 own columns; row groups of NW - 2
+// rows; plane chunks of about zc planes between two boundary chunks of 3
+// planes.  A row group is interior when its rows y0 - 2 .. y0 + NW - 1 (the
+// extra rows included) are inside [0, n1); a chunk is interior when its loads
+// (planes z0 - 3 .. z1 + 1) are inside [0, n2) and it holds neither ghost
+// plane nor boundary cell of a z face.
 template <typename T>
 static M3Geom march3d_geom(const RunK<T>& h, int zc)
 {
-    constexpr int TY = March3<T>::NW - 2;
+    constexpr int NW = March3<T>::NW, TY = NW - 2;
     M3Geom g;
     g.nseg = (h.nn[0] + 59) / 60;
     g.wid = (h.nn[0] + g.nseg - 1) / g.nseg;
     g.nyg = (h.nn[1] + TY - 1) / TY;
-    g.zc = zc > 0 ? zc : 64;
-    g.nzc = (h.nn[2] + g.zc - 1) / g.zc;
+    // interior segments: columns x0 - 2 .. x0 + 61 inside [0, n0)
+    g.sx0 = 1;
+    g.sx1 = 1;
+    while (g.sx1 < g.nseg && g.sx1 * g.wid + 61 <= h.n[0] - 1) g.sx1++;
+    g.gy0 = 1;
+    g.gy1 = 1;
+    while (g.gy1 < g.nyg && g.gy1 * TY + NW - 1 <= h.n[1] - 1) g.gy1++;
+    // a damping layer reaches into the interior: such runs take the frame
+    // launch everywhere
+    const bool pml = h.axbc[0] == AXF_AX_PML || h.axbc[1] == AXF_AX_PML || h.axbc[2] == AXF_AX_PML;
+    if (pml || g.gy1 <= g.gy0 || g.sx1 <= g.sx0) g.gy0 = g.gy1 = g.sx0 = g.sx1 = 0;
+    const int zcv = zc > 0 ? zc : 64;
+    const char *oe = getenv("AXF_M3_ORDER");
+    g.order = oe ? atoi(oe) : 0;
+    g.nn2 = h.nn[2];
+    g.zf = 3;
+    g.zend = h.n[2] - 2;
+    if (g.zend - g.zf < 1) {            // no interior chunk: one chunk and an empty one
+        g.zf = g.zend = h.nn[2];
+        g.nzc = 2;
+        g.zi = 1;
+        g.gy0 = g.gy1 = g.sx0 = g.sx1 = 0;
+        return g;
+    }
+    const int nzi = (g.zend - g.zf + zcv - 1) / zcv;
+    g.zi = (g.zend - g.zf + nzi - 1) / nzi;
+    g.nzc = nzi + 2;
     return g;
 }
 
 template <typename T>
 bool march3d_available(const RunK<T>& h)
 {
-    // 32-bit byte offsets within one array
-    return h.D == 3 && (unsigned long long)h.arr_stride < (1ull << 32);
+    // 32-bit byte offsets within the three components of a kind
+    return h.D == 3 && (unsigned long long)h.arr_stride * 3 <= (1ull << 32);
+}
+
+template <typename T>
+static void march3d_counts(const M3Geom& g, long *interior, long *frame)
+{
+    *interior = (long)(g.sx1 - g.sx0) * (g.gy1 - g.gy0) * (g.nzc - 2);
+    *frame = (long)g.nseg * g.nyg * g.nzc - *interior;
 }
 
 template <typename T>
 long march3d_blocks(const RunK<T>& h, int zc)
 {
-    M3Geom g = march3d_geom(h, zc);
-    return (long)g.nseg * g.nyg * g.nzc;
+    long a, b;
+    march3d_counts<T>(march3d_geom(h, zc), &a, &b);
+    return a + b;
 }
 
+template <typename T, bool GEN>
+static hipError_t march3d_attr()
+{
+    constexpr int NW = March3<T>::NW;
+    static bool done = false;
+    if (!done) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_march3d<T, NW, GEN>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)M3Lds<T, NW>::BYTES);
+        if (e != hipSuccess) return e;
+        done = true;
+    }
+    return hipSuccess;
+}
+
+// the interior launch, then the frame launch, on the run's stream (both read
+// only the state of step n and write disjoint owned points)
 template <typename T>
 hipError_t launch_march3d(const RunK<T> *rk, const RunK<T>& h, long step, int zc, hipStream_t st)
 {
     constexpr int NW = March3<T>::NW;
     using LQ = M3Lds<T, NW>;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_march3d<T, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)LQ::BYTES);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    hipError_t e = march3d_attr<T, false>();
+    if (e == hipSuccess) e = march3d_attr<T, true>();
+    if (e != hipSuccess) return e;
     const M3Geom g = march3d_geom(h, zc);
-    const long nb = (long)g.nseg * g.nyg * g.nzc;
-    hipLaunchKernelGGL((k_march3d<T, NW>), dim3((unsigned)nb), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
+    long ni, nf;
+    march3d_counts<T>(g, &ni, &nf);
+    if (ni > 0) hipLaunchKernelGGL((k_march3d<T, NW, false>), dim3((unsigned)ni), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
+    if (nf > 0) hipLaunchKernelGGL((k_march3d<T, NW, true>), dim3((unsigned)nf), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
     return hipGetLastError();
 }
 

@@ -136,7 +136,11 @@ Layout make_layout(const axf_config *c)
     };
     // every array and every boundary plane is reserved, used or not, so that
     // the kernels address them as base + index * stride
-    L.arr_stride = (size_t)round_up((long)L.arr_bytes, 256);
+    // 3D: each array is followed by a sink of kSinkBytes that nothing reads,
+    // where the one-pass march sends the stores of points it does not own (so
+    // that every iteration issues the same memory instructions)
+    L.arr_sink = (size_t)round_up((long)L.arr_bytes, 256);
+    L.arr_stride = L.arr_sink + (D == 3 ? kSinkBytes : 0);
     L.off_arrays = off;
     off += L.arr_stride * kNumArrays;
     for (int kind = 0; kind < 4; kind++)
@@ -245,6 +249,7 @@ static void fill_runk(RunK<T>& k, const axf_config *c, const Layout& L, char *ba
     k.state_base = base + L.off_arrays;
     k.face_base = base + L.off_faces;
     k.arr_stride = (long)L.arr_stride;
+    k.arr_sink = (long)L.arr_sink;
     k.face_stride = (long)L.face_stride;
     for (int s = 0; s < kEmSlots; s++)
         for (int comp = 0; comp < 3; comp++) {
