@@ -162,6 +162,19 @@ int axf_read_field(axf_run *run, int32_t field_id, void *dst, size_t dst_bytes, 
 /* Compute a diagnostic record at the current time now (synchronises). */
 int axf_diag_now(axf_run *run, axf_diag_record *out);
 
+/* For callers that cannot allocate device memory at the call (code under HIP
+   graph capture, serving loops, harnesses that forbid hipMalloc): the record of
+   axf_diag_now, computed by `rows` workgroups (1..1024, 0 = 1024, capped at one
+   per 256 grid points) whose FP64 partials and record sit in a static device
+   workspace of the library (1024 x 6 doubles + one record, 49.4 KB per device,
+   held until the process ends).  Allocates nothing and uses nothing of the
+   run's buffer beyond its state.  The sums are folded in another order than
+   axf_diag_now's, so the two records agree to FP64 rounding, not bit for bit.
+   Every call on one device shares that workspace and the call returns only
+   once its record is copied out, so calls made at the same time from several
+   host threads on one device race.  rows outside 0..1024 -> AXF_EINVAL. */
+int axf_diag_now_static(axf_run *run, int32_t rows, axf_diag_record *out);
+
 /* Copy up to `max` recorded diagnostics (oldest first) and clear them; *n = count. */
 int axf_read_diag(axf_run *run, axf_diag_record *out, int32_t max, int32_t *n);
 

@@ -22,7 +22,7 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 
 EXPORTS = [
     "axf_last_error", "axf_version", "axf_footprint", "axf_extents", "axf_create", "axf_write_field",
-    "axf_step", "axf_read_field", "axf_diag_now", "axf_read_diag", "axf_state_bytes", "axf_read_state",
+    "axf_step", "axf_read_field", "axf_diag_now", "axf_diag_now_static", "axf_read_diag", "axf_state_bytes", "axf_read_state",
     "axf_write_state", "axf_sync", "axf_steps_done", "axf_path_in_use", "axf_destroy", "axf_last_step_timing",
     "axf_tune", "axf_tune_reset", "axf_batch_footprint", "axf_batch_create", "axf_batch_step", "axf_batch_run", "axf_batch_destroy",
     "axf_server_create", "axf_server_submit", "axf_server_cancel", "axf_server_poll", "axf_server_stats",
@@ -114,6 +114,7 @@ def lib():
         "axf_step": ([vp, i64], ctypes.c_int),
         "axf_read_field": ([vp, i32, vp, sz, i32], ctypes.c_int),
         "axf_diag_now": ([vp, P(DiagRecord)], ctypes.c_int),
+        "axf_diag_now_static": ([vp, i32, P(DiagRecord)], ctypes.c_int),
         "axf_read_diag": ([vp, P(DiagRecord), i32, P(i32)], ctypes.c_int),
         "axf_state_bytes": ([vp, P(sz)], ctypes.c_int),
         "axf_read_state": ([vp, vp, sz], ctypes.c_int),
@@ -323,6 +324,11 @@ class Run:
     def diag_now(self):
         rec = DiagRecord()
         check(lib().axf_diag_now(self._h, ctypes.byref(rec)))
+        return rec.as_dict()
+
+    def diag_now_static(self, rows=0):
+        rec = DiagRecord()
+        check(lib().axf_diag_now_static(self._h, int(rows), ctypes.byref(rec)))
         return rec.as_dict()
 
     def read_diag(self, max_records=4096):

@@ -55,6 +55,10 @@ __host__ __device__ constexpr int q_mur(int o, int d, int side, int comp, int sl
 constexpr int kNumFaces = 6 * kPhiSlots + 36 * kEmSlots;
 constexpr int kIncLevels = 17;   // time levels per laser table fill (16 steps)
 constexpr int kDiagSums = 6;     // FP64 partial sums per block of a diagnostic record
+// static diagnostic workspace (axf_diag_now_static): at most kStaticDiagRows
+// block partials, then one record
+constexpr int kStaticDiagRows = 1024;
+constexpr int kStaticRecDoubles = 32;
 constexpr int kPmlProf = 64;     // damping-layer thicknesses the wavefront interiors tabulate
 constexpr long kSinkBytes = 65536;   // per-array store sink of 3D runs (128 wavefronts x 64 lanes x 8 bytes)
 

@@ -19,6 +19,10 @@ struct Plain {
     static void init_phi(const RunK<T> *rk, const RunK<T>& h, hipStream_t st);
     static void copy_ghosts(const RunK<T> *rk, const RunK<T>& h, int s0, int s1, hipStream_t st);
     static void diag(const RunK<T> *rk, const RunK<T>& h, long step, int slot, hipStream_t st);
+    // the same record from `rows` workgroups folding the point blocks in a
+    // fixed order, partials and record in the workspace `ws` (device address
+    // of the static array, see static_workspace)
+    static void diag_rows(const RunK<T> *rk, const RunK<T>& h, long step, double *ws, int rows, hipStream_t st);
     // semi-fused step: E0 with the axion current, B with the axion update
     static void e0c(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
     // the semi-fused step's launches (E0+C, E1, Mur, B, axion) on 3D tile walks
@@ -30,5 +34,9 @@ struct Plain {
     static void batch_inc_fill(const BItem *it, const BItem *host, int n, long s, int nlev, hipStream_t st);
     static void batch_diag(const BItem *it, const BItem *host, int n, long s, long ev, hipStream_t st);
 };
+
+// device address of the static diagnostic workspace on device `dev` (looked up
+// once per device and kept); hipSuccess or the lookup's error
+hipError_t static_workspace(int dev, double **ptr);
 
 }  // namespace axf

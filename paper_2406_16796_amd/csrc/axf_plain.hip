@@ -6,6 +6,8 @@
 #include "axf_stencil.h"
 #include "axf_kernels.h"
 
+#include <mutex>
+
 namespace axf {
 
 template <typename T>
@@ -546,11 +548,9 @@ __device__ __forceinline__ void block_sums(double v[kDiagSums], double *out)
 // Sums 4 and 5: x B1z^2 and B1z^2 over the B1z points (on the x nodes, x = i dx),
 // whose ratio is the laser centroid of Sec. IV
 template <int D, typename T>
-__device__ __forceinline__ void diag_body(const RunK<T>& r, long bx, long step)
+__device__ __forceinline__ void diag_point(const RunK<T>& r, long p, long step, double v[kDiagSums])
 {
-    double v[kDiagSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int i, j, k;
-    long p = bx * 256 + threadIdx.x;
     if (decompose(r, p, i, j, k)) {
         long id = lin(r, i, j, k);
         const int so = em_slot(step), sn = em_slot(step + 1);
@@ -570,7 +570,7 @@ __device__ __forceinline__ void diag_body(const RunK<T>& r, long bx, long step)
                 double gr = (pn - pm) / r.dx[d];
                 e += gr * gr;
             }
-            v[0] = 0.5 * e;
+            v[0] += 0.5 * e;
             fin = fin && finite_val(pa) && finite_val(pb);
         }
 #pragma unroll
@@ -604,19 +604,27 @@ __device__ __forceinline__ void diag_body(const RunK<T>& r, long bx, long step)
                 }
             }
         }
-        v[3] = fin ? 0.0 : 1.0;
+        v[3] += fin ? 0.0 : 1.0;
     }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void diag_body(const RunK<T>& r, long bx, long step)
+{
+    double v[kDiagSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    diag_point<D, T>(r, bx * 256 + threadIdx.x, step, v);
     block_sums(v, r.part + bx * kDiagSums);
 }
 
 // fixed-order sum of the block partials into record slot `slot`
 template <typename T>
-__device__ __forceinline__ void diag_final_body(const RunK<T>& r, long step, int slot)
+__device__ __forceinline__ void diag_fold(const RunK<T>& r, long step, const double *part, int nparts,
+                                          axf_diag_record *dst)
 {
     double v[kDiagSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int blk = threadIdx.x; blk < r.diag_blocks; blk += blockDim.x)
+    for (int blk = threadIdx.x; blk < nparts; blk += blockDim.x)
 #pragma unroll
-        for (int q = 0; q < kDiagSums; q++) v[q] += r.part[blk * kDiagSums + q];
+        for (int q = 0; q < kDiagSums; q++) v[q] += part[blk * kDiagSums + q];
     __shared__ double tot[kDiagSums];
     block_sums(v, tot);
     __syncthreads();
@@ -634,8 +642,14 @@ __device__ __forceinline__ void diag_final_body(const RunK<T>& r, long step, int
         rec.finite = tot[3] == 0.0 ? 1 : 0;
         rec.pad = 0;
         rec.x_laser = tot[5] > 0.0 ? tot[4] / tot[5] : 0.0;
-        r.rec[slot] = rec;
+        *dst = rec;
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void diag_final_body(const RunK<T>& r, long step, int slot)
+{
+    diag_fold<T>(r, step, r.part, r.diag_blocks, &r.rec[slot]);
 }
 
 // ------------------------------------------------------ single-run kernels
@@ -692,6 +706,32 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_diag_final(const RunK<T> *__restrict__ rp, long step, int slot)
 {
     diag_final_body<T>(*rp, step, slot);
+}
+
+// ------------------------------------------ static diagnostic workspace
+// The partials and the record of axf_diag_now_static: kStaticDiagRows rows of
+// kDiagSums FP64 sums, then one record.  Every device holds its own copy until
+// the process ends; host code reaches it only through the device address that
+// static_workspace looks up, never through this name.
+static __device__ __align__(256) double scratch[kStaticDiagRows * kDiagSums + kStaticRecDoubles];
+static_assert(sizeof(axf_diag_record) <= kStaticRecDoubles * sizeof(double), "record slot too small");
+static_assert((kStaticDiagRows * kDiagSums * sizeof(double)) % 256 == 0, "record slot alignment");
+
+// workgroup b folds the 256-point blocks b, b + rows, b + 2 rows, ... in turn
+template <int D, typename T>
+__global__ void __launch_bounds__(256) k_diag_rows(const RunK<T> *__restrict__ rp, long step, double *part, int rows)
+{
+    const RunK<T>& r = *rp;
+    double v[kDiagSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (long bx = blockIdx.x; bx < r.diag_blocks; bx += rows) diag_point<D, T>(r, bx * 256 + threadIdx.x, step, v);
+    block_sums(v, part + (long)blockIdx.x * kDiagSums);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag_rows_final(const RunK<T> *__restrict__ rp, long step,
+                                                         const double *part, int rows, axf_diag_record *dst)
+{
+    diag_fold<T>(*rp, step, part, rows, dst);
 }
 
 // merged phase of the semi-fused step: E0 with the axion current
@@ -887,6 +927,40 @@ void Plain<D, T>::diag(const RunK<T> *rk, const RunK<T>& h, long step, int slot,
 {
     hipLaunchKernelGGL((k_diag<D, T>), dim3(nblocks(h.npts, 256)), dim3(256), 0, st, rk, step);
     hipLaunchKernelGGL((k_diag_final<T>), dim3(1), dim3(256), 0, st, rk, step, slot);
+}
+
+template <int D, typename T>
+void Plain<D, T>::diag_rows(const RunK<T> *rk, const RunK<T>& h, long step, double *ws, int rows, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_diag_rows<D, T>), dim3(rows), dim3(256), 0, st, rk, step, ws, rows);
+    hipLaunchKernelGGL((k_diag_rows_final<T>), dim3(1), dim3(256), 0, st, rk, step, (const double *)ws, rows,
+                       (axf_diag_record *)(ws + kStaticDiagRows * kDiagSums));
+}
+
+static std::mutex g_ws_mu;
+static double *g_ws_ptr[64];
+
+hipError_t static_workspace(int dev, double **ptr)
+{
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    if (!g_ws_ptr[dev]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) {
+            hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_ws_ptr[dev] = (double *)p;
+    }
+    *ptr = g_ws_ptr[dev];
+    return hipSuccess;
 }
 
 template <int D, typename T>

@@ -100,6 +100,7 @@ struct TunedShape {
 };
 bool tuned_shape(const axf_config *c, TunedShape *out);
 int run_diag_now(Run *R, axf_diag_record *out);
+int run_diag_now_static(Run *R, int rows, axf_diag_record *out);
 void run_release(Run *R);
 bool fused_supported(const axf_config *c);
 

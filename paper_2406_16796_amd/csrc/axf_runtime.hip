@@ -793,6 +793,38 @@ int run_diag_now(Run *R, axf_diag_record *out)
     return AXF_OK;
 }
 
+template <int D, typename T>
+static void diag_static_impl(Run *R, double *ws, int rows)
+{
+    if (!R->converted) convert_to_leapfrog<D, T>(R);
+    e_phase<D, T>(R);
+    Plain<D, T>::diag_rows(R->rk<T>(), R->hk<T>(), R->step, ws, rows, R->stream);
+}
+
+// the record of run_diag_now with its partials in the static workspace of the
+// stream's device: nothing is allocated and nothing of the run's buffer beyond
+// the state is touched
+int run_diag_now_static(Run *R, int rows, axf_diag_record *out)
+{
+    if (rows < 0 || rows > kStaticDiagRows)
+        return fail(AXF_EINVAL, "rows = %d: the static diagnostic workspace holds 1..%d workgroup partials "
+                    "(0 picks %d)", rows, kStaticDiagRows, kStaticDiagRows);
+    int dev = 0;
+    HIPCHK(hipStreamGetDevice(R->stream, &dev));
+    double *ws = nullptr;
+    HIPCHK(static_workspace(dev, &ws));
+    const int blocks = R->L.diag_blocks;
+    if (rows == 0) rows = kStaticDiagRows;
+    rows = std::min(rows, blocks);
+    AXF_DISPATCH(R, diag_static_impl, R, ws, rows);
+    R->ephase_step = R->step;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, ws + kStaticDiagRows * kDiagSums, sizeof(axf_diag_record), hipMemcpyDeviceToHost,
+                          R->stream));
+    HIPCHK(hipStreamSynchronize(R->stream));
+    return AXF_OK;
+}
+
 int run_read_diag(Run *R, axf_diag_record *out, int max, int *n)
 {
     HIPCHK(hipStreamSynchronize(R->stream));
@@ -1126,6 +1158,12 @@ int axf_diag_now(axf_run *run, axf_diag_record *out)
 {
     if (!run || !out) return fail(AXF_EINVAL, "null argument");
     return run_diag_now(run, out);
+}
+
+int axf_diag_now_static(axf_run *run, int32_t rows, axf_diag_record *out)
+{
+    if (!run || !out) return fail(AXF_EINVAL, "null argument");
+    return run_diag_now_static(run, rows, out);
 }
 
 int axf_read_diag(axf_run *run, axf_diag_record *out, int32_t max, int32_t *n)
