@@ -1,19 +1,24 @@
 """Benchmark of the axion-coupled Yee step on one MI355X.
 
-Default workload: the 2D Gaussian-pulse run (4096 x 4096 cells, lambda/16,
-dt = 0.95 dx / sqrt(2), Gaussian laser of waist 8 lambda and FWHM 10 lambda
-entering through the x_min Mur face, static B slab over cells 1024-3071, PML
-axion layers), FP32 fields, advanced by the fused wavefront kernel.  One step
-is one full leapfrog step of every active field (zero-order E/B, axion,
-first-order E/B, Mur and axion boundaries, laser injection); the energy and
-probability diagnostics are recorded every 100 steps inside the timed region.
+Default workload: the 3D focused-pulse run (512^3 cells at lambda/12, dt =
+0.95 dx / sqrt(3)): a focused Gaussian laser (waist 6 lambda, FWHM 10
+lambda, E along z) entering through the x_min Mur face and a counter-
+propagating Gaussian axion packet (k = 1, width 5 lambda, amplitude 1e-3),
+m = 0.3, g = 1e-4, uniform B0 along z, Mur EM and outflow axion boundaries,
+FP32 fields, advanced by the one-pass march (one interior launch and one
+boundary-frame launch per step).  One step is one full leapfrog step of
+every field (zero-order E/B, axion, first-order E/B, Mur and axion
+boundaries, laser injection); the energy and probability diagnostics are
+recorded every 100 steps inside the timed region.
 
 Printed: one JSON line with the whole-path throughput (Gcell-updates/s), the
-HBM roofline of the dominant kernel (algorithmic bytes per launch over the mean
-launch time from HIP events on the run's stream; measured HBM traffic from the
-committed rocprofv3 counter summary when it matches the kernel source), the
-unfused path for comparison, a device copy for the achievable bandwidth, and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+HBM roofline of the step (algorithmic bytes per step over the mean step time
+from HIP events on the run's stream; measured HBM traffic from the committed
+rocprofv3 counter summary when it matches the kernel source), the unfused
+path for comparison, the 2D 4096^2 Gaussian-pulse run in FP32 and FP64 (its
+fraction from counted HBM bytes: a pass advances four steps), a device copy
+for the achievable bandwidth, and the FP64 CPU oracle timed on a bounded
+sample of the same workload on one host thread and on all of them.
 
 Other modes:
   --profile-only          the device copy and the fused steps only (the command
@@ -45,14 +50,13 @@ COPY_BYTES = 1 << 30
 CSRC = "paper_2406_16796_amd/csrc/"
 COMMON_SOURCES = [CSRC + "axf_stencil.h", CSRC + "axf_internal.h", "paper_2406_16796_amd/build.py"]
 # workload -> (generator, file tag of the step kernels, kernel-name patterns of
-# one step's launches ({T} = float or double), sources those kernels are built
-# from)
+# one step's launches ({T} = float or double, {NW} = row wavefronts per march
+# workgroup), sources those kernels are built from)
 WORKLOADS = {
     "2d": ("gaussian_2d", "k_wave2d", ["k_wave2d_pass<{T}", "k_wave2d_int<{T}", "k_wave2d<{T}"],
            [CSRC + "axf_fused.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
-    "3d": ("focused_3d", "k3_tile", ["k3_tile<3,{T},0>", "k3_tile<3,{T},1>", "k_mur<3,{T}>",
-                                     "k3_tile<3,{T},2>", "k3_tile<3,{T},3>"],
-           [CSRC + "axf_plain.hip", CSRC + "axf_kernels.h"] + COMMON_SOURCES),
+    "3d": ("focused_3d", "k_march3d", ["k_march3d<{T},{NW},false>", "k_march3d<{T},{NW},true>"],
+           [CSRC + "axf_march3d.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
     "1d": ("plane_wave_1d", "plain_step", ["k_e0<1,{T}>", "k_c<1,{T}>", "k_e1<1,{T}>", "k_mur<1,{T}>",
                                            "k_b<1,{T}>", "k_phi<1,{T}>"],
            [CSRC + "axf_plain.hip", CSRC + "axf_kernels.h"] + COMMON_SOURCES),
@@ -63,10 +67,14 @@ def pattern_label(p):
     return p if p.endswith(">") else p + ",...>"
 
 
+# row wavefronts per workgroup of the 3D march by storage precision
+MARCH_NW = {"f32": 8, "f64": 6}
+
+
 def step_patterns(name, precision):
     """Kernel-name patterns (spaces removed) of one step's launches."""
     t = "float" if precision == "f32" else "double"
-    return [p.replace("{T}", t) for p in WORKLOADS[name][2]]
+    return [p.replace("{T}", t).replace("{NW}", str(MARCH_NW[precision])) for p in WORKLOADS[name][2]]
 
 
 def words_per_cell(ndim):
@@ -154,9 +162,21 @@ def time_path(axf, torch, cfg, precision, path, steps, warmup, diag_every):
     return wall, ev_ms, launches, rec, fused
 
 
-def cpu_baseline(cfg, target_s=15.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, target_s=12.0):
     """The FP64 oracle on a bounded sample: the same workload on a grid cut
-    down to a few 10^5 cells, timed over whole steps."""
+    down to a few 10^5 cells, timed over whole steps, on every thread the
+    OpenMP runtime gives it (OMP_NUM_THREADS) and on one thread."""
     from oracle.oracle import Oracle
     sample = dict(cfg)
     ndim = sum(1 for v in cfg["n"] if v > 1)
@@ -165,54 +185,62 @@ def cpu_baseline(cfg, target_s=15.0):
     sample["n"] = n
     sample["slab_hi"] = min(int(cfg.get("slab_hi", n[0])), n[0])
     sample["slab_lo"] = min(int(cfg.get("slab_lo", 0)), n[0])
-    o = Oracle(sample)
-    o.step(1)
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < target_s and steps < 1000:
-        o.step(1)
-        steps += 1
-    dt = time.perf_counter() - t0
     nc = n[0] * n[1] * n[2]
-    threads = o.threads()
-    return {"value": nc * steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": "%s cells of the same workload (FP64, same boundaries and sources), %d whole steps in %.1f s"
-                      % ("x".join(map(str, n)), steps, dt)}
+    out = {}
+    for label, threads in (("all", None), ("one", 1)):
+        if threads is None:
+            Oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1))
+        else:
+            Oracle.set_threads(threads)
+        o = Oracle(sample)
+        o.step(1)
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < target_s and steps < 1000:
+            o.step(1)
+            steps += 1
+        dt = time.perf_counter() - t0
+        out[label] = (nc * steps / dt / 1e9, o.threads(), steps, dt)
+        o.close()
+    v, th, steps, dt = out["all"]
+    v1, _, steps1, dt1 = out["one"]
+    return {"value": round(v, 5), "unit": "Gcell-updates/s", "cores": th, "kind": "oracle",
+            "sample": "%s cells of the same workload (FP64, same boundaries and sources), %d whole steps in %.1f s "
+                      "on %d threads" % ("x".join(map(str, n)), steps, dt, th),
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": round(v1, 5), "cores": 1,
+                           "sample": "the same sample, %d whole steps in %.1f s" % (steps1, dt1)}}
 
 
-def leg_3d(axf, torch, steps=10):
-    """The 512^3 focused-pulse run (FP32): the fused path (E0 and the axion
-    current merged, then E1, Mur, B, axion) against the unfused phases, with
-    its HBM roofline (27 words per cell-update)."""
-    cfg = workload("3d")
-    nc = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
-    out = {"workload": workload_tag(cfg, "f32")}
-    for name, path in (("fused", axf.PATH_AUTO), ("plain", axf.PATH_PLAIN)):
-        _, ms, _, _, fused = time_path(axf, torch, cfg, axf.F32, path, steps, 2, 0)
-        step_s = ms / 1e3 / steps
-        out[name] = {"Gcell_s": round(nc / step_s / 1e9, 3), "ms_per_step": round(step_s * 1e3, 4)}
-        if name == "fused":
-            achieved = words_per_cell(3) * 4 * nc / step_s / 1e9
-            out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": round(achieved / HBM_PEAK_GBS, 4), "path_fused": fused}
-    return out
-
-
-def leg_other_precision(axf, torch, name, precision, steps=200):
-    """The same 2D workload in the other storage precision (the FP32 vs FP64
-    comparison of the 4096^2 configuration): the fused step alone."""
-    cfg = workload(name)
+def leg_2d(axf, torch, precision, steps=200):
+    """The 2D Gaussian-pulse run (4096^2, lambda/16) through the fused 2D
+    wavefront kernel in one storage precision (the FP32 vs FP64 comparison of
+    that configuration).  A pass of that kernel advances several steps per
+    read of the state, so its HBM fraction is taken from the counted bytes of
+    the committed counter summary over the measured step time; the
+    algorithmic-equivalent rate (one full read and write of the state per
+    step) is given beside it and may exceed the peak."""
+    cfg = workload("2d")
     prec = axf.F64 if precision == "f64" else axf.F32
     esize = 8 if precision == "f64" else 4
     nc = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
-    ndim = sum(1 for v in cfg["n"] if v > 1)
-    _, ms, _, _, fused = time_path(axf, torch, cfg, prec, axf.PATH_AUTO, steps, 2, 0)
+    _, ms, launches, _, fused = time_path(axf, torch, cfg, prec, axf.PATH_AUTO, steps, 4, 0)
     step_s = ms / 1e3 / steps
-    achieved = words_per_cell(ndim) * esize * nc / step_s / 1e9
-    return {"workload": workload_tag(cfg, precision), "Gcell_s": round(nc / step_s / 1e9, 3),
-            "ms_per_step": round(step_s * 1e3, 4),
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "path_fused": fused}}
+    equiv = words_per_cell(2) * esize * nc / step_s / 1e9
+    tag = workload_tag(cfg, precision)
+    traffic = read_traffic("2d", tag, WORKLOADS["2d"][1]) if fused else None
+    roof = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "path_fused": fused,
+            "algorithmic_equivalent_GBs": round(equiv, 1), "traffic": round(traffic) if traffic else None}
+    if traffic:
+        roof["achieved"] = round(traffic / step_s / 1e9, 1)
+        roof["frac"] = round(traffic / step_s / 1e9 / HBM_PEAK_GBS, 4)
+        roof["basis"] = "counted HBM bytes per step (FETCH_SIZE + WRITE_SIZE) over the mean step time"
+    else:
+        roof["achieved"] = None
+        roof["frac"] = None
+        roof["basis"] = "no counter summary for this kernel source: fraction not reported"
+    return {"workload": tag, "Gcell_s": round(nc / step_s / 1e9, 3), "ms_per_step": round(step_s * 1e3, 4),
+            "launches_per_step": round(launches / steps, 3), "roofline": roof}
 
 
 def scan_leg(axf, torch, steps_scale, count=512, tune=True):
@@ -418,7 +446,7 @@ def trace_summary(args):
     kernel, pats = WORKLOADS[args.workload][1], step_patterns(args.workload, args.precision)
     rows = list(csv.DictReader(open(args.trace_summary)))
     cmd = ("python3 $REPO/bench.py --workload %s --precision %s --steps %d --warmup %d --plain-steps %d "
-           "--no-cpu-baseline --no-scan --no-serve --no-3d --no-tune"
+           "--no-cpu-baseline --no-scan --no-serve --no-2d --no-tune"
            % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps))
     lines = ["# Kernel trace of bench.py, workload %s" % tag, "",
              "    cd /tmp && export TMPDIR=/tmp",
@@ -427,11 +455,16 @@ def trace_summary(args):
              "--trace-summary $OUT/kt/kt_kernel_stats.csv"
              % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps), "",
              "The run times the fused path twice (with and without diagnostics) and the unfused phase "
-             "sequence once; the copy kernel is the bandwidth calibration.  In 2D a pass of NS steps is "
-             "`k_wave2d_pass<T, PD, NS, MODE>` over the interior with NS `k_wave2d` launches over the "
-             "boundary frame beside it on a second stream.  A pass of three or four steps splits its interior "
-             "into a core launch (MODE 1) and a ring launch (MODE 2, on a third stream, storing the "
-             "intermediate steps the frame launches read); a two-step pass is one launch (MODE 0).", "",
+             "sequence once; the copy kernel is the bandwidth calibration.  " + (
+                 "In 3D one step is `k_march3d<T, NW, false>` over the interior box (every workgroup clear "
+                 "of the faces) followed by `k_march3d<T, NW, true>` over the boundary frame, on the run's "
+                 "stream; the step time is the sum of their mean durations."
+                 if args.workload == "3d" else
+                 "In 2D a pass of NS steps is `k_wave2d_pass<T, PD, NS, MODE>` over the interior with NS "
+                 "`k_wave2d` launches over the boundary frame beside it on a second stream.  A pass of three "
+                 "or four steps splits its interior into a core launch (MODE 1) and a ring launch (MODE 2, on "
+                 "a third stream, storing the intermediate steps the frame launches read); a two-step pass is "
+                 "one launch (MODE 0)."), "",
              "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in rows:
         name = r["Name"]
@@ -454,6 +487,10 @@ def trace_summary(args):
                 lines.append("- `%s_mean_us_per_step = %.2f` (%s calls, a launch of the%s interior advances "
                              "%d steps)" % (pattern_label(pat), float(r["AverageNs"]) / 1e3 / ns, r["Calls"],
                                             modes.get(m.group(2), ""), ns))
+    if args.workload == "3d":
+        means = [float(r["AverageNs"]) / 1e3 for pat in pats for r in rows if pat in r["Name"].replace(" ", "")]
+        if len(means) == len(pats):
+            lines.append("- `step_mean_us = %.2f` (the interior and frame launches of one step)" % sum(means))
     lines.append("- `kernel_source_sha256 = %s`" % kernel_source_hash(args.workload))
     path = os.path.join(ROOT, "profiles", "%s_%s_kernel_trace.md" % (kernel, tag))
     with open(path, "w") as f:
@@ -466,7 +503,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="3d", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--plain-steps", type=int, default=200)
@@ -475,7 +512,7 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV")
     ap.add_argument("--no-scan", action="store_true")
-    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D 4096^2 leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shapes")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--steps-scale", type=float, default=0.1,
@@ -509,7 +546,7 @@ def main():
 
     copy_gbs = device_copy(torch)
     tuned = None
-    if not args.no_tune and not args.profile_only:
+    if args.workload == "2d" and not args.no_tune and not args.profile_only:
         axf.tune_reset()
         tuned = axf.tune(cfg, precision=prec, steps=40)
     if args.profile_only:
@@ -522,12 +559,13 @@ def main():
                                        args.diag_every)
     value = nc * args.steps / wall / 1e9
     # the step kernels alone (no diagnostics): HIP events on the run's stream
-    # around the timed steps; one fused 2D step is the interior launch plus the
-    # boundary-frame launch running beside it on a second stream
+    # around the timed steps (in 3D one step is the interior launch followed by
+    # the boundary-frame launch; in 2D a pass of several steps is the interior
+    # launch with the frame launches beside it on a second stream)
     _, k_ms, k_launches, _, _ = time_path(axf, torch, cfg, prec, axf.PATH_AUTO, args.steps, 2, 0)
-    per_launch_s = k_ms / 1e3 / args.steps
+    per_step_s = k_ms / 1e3 / args.steps
     algo_bytes = words_per_cell(ndim) * esize * nc
-    achieved = algo_bytes / per_launch_s / 1e9
+    achieved = algo_bytes / per_step_s / 1e9
     # the counter summary was taken with the built-in launch shape
     default_shape = DEFAULT_WAVE_SHAPE[args.precision]
     same_shape = tuned is None or (tuned["steps_per_pass"], tuned["chunk"], tuned["prefetch"],
@@ -560,8 +598,11 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": round(traffic) if traffic is not None else None,
             "kernel": " + ".join(pattern_label(p) for p in pats) if fused else "plain phase sequence",
-            "unit_of_work": "one fused step of the whole grid", "bytes_per_step": algo_bytes,
-            "mean_step_ms": round(per_launch_s * 1e3, 5), "steps_timed": args.steps,
+            "unit_of_work": "one step of the whole grid (%s)" % (
+                "interior launch then boundary-frame launch" if args.workload == "3d" else "fused launches"),
+            "bytes_per_step": algo_bytes, "launches_per_step": round(k_launches / args.steps, 3),
+            "mean_step_ms": round(per_step_s * 1e3, 5), "steps_timed": args.steps,
+            "traffic_over_algorithmic": round(traffic / algo_bytes, 3) if traffic is not None else None,
             "copy_kernel_GBs": round(copy_gbs, 1),
             "tuned": None if tuned is None else {"steps_per_pass": tuned["steps_per_pass"],
                                                  "chunk": tuned["chunk"], "prefetch": tuned["prefetch"],
@@ -576,11 +617,12 @@ def main():
                   "fused_speedup": round(value / plain_value, 3) if plain_value > 0 else None},
         "diag": {"step": rec["step"], "p_gen": rec["p_gen"], "p_conv": rec["p_conv"], "finite": rec["finite"]},
     }
-    if args.workload == "2d":
-        other = "f64" if args.precision == "f32" else "f32"
-        line[other] = leg_other_precision(axf, torch, "2d", other)
-    if not args.no_3d and args.workload != "3d":
-        line["3d"] = leg_3d(axf, torch)
+    if not args.no_2d:
+        if args.workload == "2d":
+            other = "f64" if args.precision == "f32" else "f32"
+            line[other] = leg_2d(axf, torch, other)
+        else:
+            line["2d"] = {p: leg_2d(axf, torch, p) for p in ("f32", "f64")}
     if not args.no_scan:
         line["scan"] = scan_leg(axf, torch, args.steps_scale, tune=not args.no_tune)
     if not args.no_serve:

@@ -55,6 +55,17 @@ int ora_threads(void)
 #endif
 }
 
+/* threads of the following loops (timing only: every sum has a fixed order,
+   so the results do not depend on the count) */
+void ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 struct ora_state {
     ora_config c;
     int    n[3], nn[3];

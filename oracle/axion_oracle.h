@@ -98,6 +98,7 @@ void   ora_energies(const ora_state *s, double out[3]);
 /* incident laser E component comp (1 = y, 2 = z) at (x, y, z, t); exposed for tests */
 /* OpenMP threads the step loops use (1 without OpenMP) */
 int    ora_threads(void);
+void   ora_set_threads(int n);
 
 double ora_incident(const ora_state *s, int comp, double x, double y, double z, double t);
 

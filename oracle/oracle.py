@@ -79,6 +79,8 @@ def lib():
         L.ora_incident.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_double] * 4
         L.ora_incident.restype = ctypes.c_double
         L.ora_threads.restype = ctypes.c_int
+        L.ora_set_threads.argtypes = [ctypes.c_int]
+        L.ora_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -186,6 +188,11 @@ class Oracle:
 
     def threads(self):
         return lib().ora_threads()
+
+    @staticmethod
+    def set_threads(n):
+        """Threads of the oracle's loops from now on (timing only)."""
+        lib().ora_set_threads(int(n))
 
     def incident(self, comp, x, y, z, t):
         return lib().ora_incident(self._h, comp, x, y, z, t)
