@@ -79,6 +79,7 @@ struct M3Geom {
     int nzc;         // plane chunks: [0, zf), pieces of zi planes up to zend, [zend, nn2)
     int zf, zi, zend, nn2;
     int order;       // interior block order (bit 0: row groups fastest; bit 1: a band per XCD)
+    int xb;          // the segments outside [sx0, sx1) have a launch of their own (Mur x, outflow or reflecting axion x)
 };
 // the run fits the march (32-bit offsets within an array)
 template <typename T>

@@ -89,6 +89,13 @@ __device__ __forceinline__ void sto(const char *base, unsigned boff, T v)
 {
     *(__attribute__((address_space(1))) T *)((__attribute__((address_space(1))) char *)base + boff) = v;
 }
+// element i of a wave-uniform address through the scalar cache (data the
+// launch does not write: old ghost levels, the laser table)
+template <typename T>
+__device__ __forceinline__ T sld(const char *base, long i)
+{
+    return ((const __attribute__((address_space(4))) T *)base)[i];
+}
 // element i of a boundary plane (boundary code only)
 template <typename T>
 __device__ __forceinline__ T fld(const RunK<T> *rp, int q, long i)
@@ -148,15 +155,26 @@ __host__ __device__ inline int m3_zb(const M3Geom& g, int k)
     return min(g.zf + (k - 1) * g.zi, g.zend);
 }
 
-// segment, row group and chunk of block b.  The interior launch covers the
-// box of segments [sx0, sx1), row groups [gy0, gy1) and chunks 1 .. nzc - 2;
-// the frame launch the rest: (A) the first and last chunks of every segment
-// and row group, (B) the inner chunks of the row groups outside [gy0, gy1),
-// (C) the inner chunks of those row groups in the segments outside [sx0, sx1).
-__host__ __device__ inline void m3_block(const M3Geom& g, bool frame, unsigned b, int& seg, int& ygr, int& zch)
+// segment, row group and chunk of block b.  The interior launch (mode 0)
+// covers the box of segments [sx0, sx1), row groups [gy0, gy1) and chunks
+// 1 .. nzc - 2.  (C) the inner chunks of those row groups in the segments
+// outside [sx0, sx1) are the x-face launch (mode 1) when g.xb is set.  The
+// frame launch (mode 2) takes the rest: (A) the first and last chunks of
+// every segment and row group, (B) the inner chunks of the row groups outside
+// [gy0, gy1), and (C) when there is no x-face launch.
+__host__ __device__ inline void m3_block(const M3Geom& g, int mode, unsigned b, int& seg, int& ygr, int& zch)
 {
     const unsigned nsx = (unsigned)(g.sx1 - g.sx0), ny = (unsigned)(g.gy1 - g.gy0), nzi = (unsigned)(g.nzc - 2);
-    if (!frame) {
+    if (mode == 1) {
+        const unsigned nfx = (unsigned)g.nseg - nsx;
+        const int k = (int)(b % nfx);
+        seg = k < g.sx0 ? k : g.sx1 + (k - g.sx0);
+        const unsigned r = b / nfx;
+        ygr = g.gy0 + (int)(r % ny);
+        zch = 1 + (int)(r / ny);
+        return;
+    }
+    if (mode == 0) {
         // order & 2: the hardware deals blocks to the 8 XCDs in turn; give
         // each XCD one contiguous band of the block order instead.
         // order & 1: row groups fastest (the blocks that share halo rows run
@@ -204,8 +222,9 @@ __host__ __device__ inline void m3_block(const M3Geom& g, bool frame, unsigned b
     zch = 1 + (int)(r / ny);
 }
 
-// Occupancy (FP32): 12 wavefronts per workgroup, one workgroup per CU (the
-// LDS plan takes about 130 KiB), 3 wavefronts per SIMD.
+// Occupancy (FP32): 8 wavefronts per workgroup of up to 256 VGPRs each, two
+// wavefronts per SIMD, one workgroup per CU (the LDS plan takes 88 KiB);
+// 12 wavefronts (3 per SIMD, 168 VGPRs) spill and were slower.
 //
 // Values at positions outside a Mur axis's extents (and the axion values
 // beyond the ghost cells) are never read by a point inside them: the curl
@@ -221,13 +240,20 @@ __host__ __device__ inline void m3_block(const M3Geom& g, bool frame, unsigned b
 // quantity needed for three planes gets a ring of four, whose spare slot is
 // where the loads of the next iteration land.
 //
-// GEN = false is the launch over the segments, row groups and plane chunks
-// whose columns, rows and planes (halos included) keep clear of every face
-// and do not wrap: it has no boundary code.  GEN = true covers the rest (the
-// frame), every boundary included.
-template <typename T, int NW, bool GEN>
+// MODE 0 is the launch over the segments, row groups and plane chunks whose
+// columns, rows and planes (halos included) keep clear of every face and do
+// not wrap: it has no boundary code.  MODE 1 takes the segments that hold an
+// x face of a run with Mur x faces and an outflow or reflecting axion x
+// boundary, in the row groups and plane chunks of the interior: the code of
+// mode 0 plus that face, whose ghosts every lane computes and stores (lanes
+// other than the ghost's to the sink), the uniform face values read through
+// the scalar cache, so that it too issues the same vector memory
+// instructions in every iteration.  MODE 2 covers the rest (the frame),
+// every boundary included.
+template <typename T, int NW, int MODE>
 __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__ rp, long step, M3Geom g)
 {
+    constexpr bool GEN = MODE == 2, XB = MODE == 1;
     using LQ = M3Lds<T, NW>;
     constexpr int TY = NW - 2;
     T *const lds = reinterpret_cast<T *>(m3_smem);
@@ -237,8 +263,8 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     // ---- the run's geometry and coefficients
     const int n0 = rp->n[0], n1 = rp->n[1], n2 = rp->n[2];
     const int nn0 = rp->nn[0], nn1 = rp->nn[1], nn2 = rp->nn[2];
-    const bool mx = GEN && rp->mur[0], my = GEN && rp->mur[1], mz = GEN && rp->mur[2];
-    const bool apx = !GEN || rp->axbc[0] == AXF_AX_PERIODIC, apy = !GEN || rp->axbc[1] == AXF_AX_PERIODIC;
+    const bool mx = XB || (GEN && rp->mur[0]), my = GEN && rp->mur[1], mz = GEN && rp->mur[2];
+    const bool apx = XB ? false : (!GEN || rp->axbc[0] == AXF_AX_PERIODIC), apy = !GEN || rp->axbc[1] == AXF_AX_PERIODIC;
     const bool apz = !GEN || rp->axbc[2] == AXF_AX_PERIODIC;
     constexpr unsigned es = sizeof(T);
     const unsigned sxb = (unsigned)rp->sx * es, syb = (unsigned)rp->sy * es;
@@ -255,23 +281,26 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
 
     // ---- this workgroup's segment, row group and plane chunk
     int seg, ygr, zch;
-    m3_block(g, GEN, blockIdx.x, seg, ygr, zch);
+    m3_block(g, MODE, blockIdx.x, seg, ygr, zch);
     const int x0 = seg * g.wid, gx = x0 - 2 + lane;
     const int y0 = ygr * TY, gy = y0 - 1 + w;
     const int z0 = m3_zb(g, zch), z1 = m3_zb(g, zch + 1);
 
     // ---- this lane's column
-    const int xs_em = !GEN ? gx : (mx ? ((gx >= 0 && gx < nn0) ? gx : 0) : m3::imodn(gx, n0));
+    const int xs_em = MODE == 0 ? gx : (mx ? ((gx >= 0 && gx < nn0) ? gx : 0) : m3::imodn(gx, n0));
     // axion column class: 0 a cell (or a periodic axis), 1 / 2 the ghost below / above, 3 none
     const int xcl = apx ? 0 : ((gx >= 0 && gx < n0) ? 0 : (gx == -1 ? 1 : (gx == n0 ? 2 : 3)));
-    const int xs_ph = !GEN ? gx : (apx ? m3::imodn(gx, n0) : (xcl == 0 ? gx : 0));
+    const int xs_ph = MODE == 0 ? gx : (apx ? m3::imodn(gx, n0) : (xcl == 0 ? gx : 0));
     const unsigned xo_em = (unsigned)xs_em * es, xo_ph = (unsigned)xs_ph * es;
     // own columns: nodal x components store there, centred ones where also gx < n0
     const bool own_x = lane >= 2 && lane < 2 + g.wid && gx < nn0;
     const bool own_xc = own_x && (!mx || gx < n0);
     auto own_lane = [&](int l) __attribute__((always_inline)) { return l >= 2 && l < 2 + g.wid && x0 - 2 + l < nn0; };
     // the segment holds a ghost column of an x face (Mur or axion)
-    const bool seg_xb = GEN && (mx || !apx) && (x0 - 2 <= -1 || x0 + 61 >= n0);
+    const bool seg_xb = XB || (GEN && (mx || !apx) && (x0 - 2 <= -1 || x0 + 61 >= n0));
+    // the x face of a mode-1 segment (0: x_min, 1: x_max) and the column of its ghost
+    const int xside = seg < g.sx0 ? 0 : 1;
+    const int gx_ghost = xside ? n0 : -1;
     // B_ext at this lane's cells (slab along x); formed at use from the slab
     // mask in the interior launch, so that it takes no vector registers
     const bool in_slab = xs_em >= rp->slab_lo && xs_em < rp->slab_hi;
@@ -363,7 +392,8 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
             r.a = m3::fld(rp, q_axg(1, ycl - 1, L), (long)zs * nn0 + xs_ph);
         } else {
             r.a = m3::ldo<T>(arr_ph(L), xo_ph + (unsigned)ys * sxb + (unsigned)zs * syb);
-            if (seg_xb && !apx) r.fx = m3::fld(rp, q_axg(0, xcl == 2 ? 1 : 0, L), (long)zs * nn1 + ys);
+            if constexpr (XB) r.fx = m3::sld<T>(rp->face_base + q_axg(0, xside, L) * rp->face_stride, (long)zs * nn1 + ys);
+            else if (seg_xb && !apx) r.fx = m3::fld(rp, q_axg(0, xcl == 2 ? 1 : 0, L), (long)zs * nn1 + ys);
         }
         return r;
     };
@@ -459,6 +489,35 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
         const double g_old = (double)m3::fld(rp, q_mur(O, d, side, c, so), fidx);
         return mur_update_rk<T>(*rp, O, c, d, side, (double)e_old, (double)e_new, g_old, fidx, step);
     };
+    // mode 1: face plane q; a store of element f of it by the lanes that own
+    // it, to the sink by the others
+    auto face = [&](int q) __attribute__((always_inline)) { return rp->face_base + (size_t)q * rp->face_stride; };
+    auto fstx = [&](bool owner, int q, long f, T v) __attribute__((always_inline)) {
+        T *const p = owner ? (T *)face(q) + f : (T *)(abase(0) + sink_o);
+        *(__attribute__((address_space(1))) T *)p = v;
+    };
+    // mode 1: the Mur ghost of order O, component c on this segment's x face
+    // at face point f (uniform), from the adjacent point's E^{n-1/2}, E^{n+1/2};
+    // the old ghost and the laser values come through the scalar cache, the
+    // laser's from a valid address also where they are not used
+    auto mur_x = [&](int O, int c, T e_old, T e_new, long f) __attribute__((always_inline)) -> T {
+        const double g_old = (double)m3::sld<T>(face(q_mur(O, 0, xside, c, so)), f);
+        double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
+        if (O == 0) {
+            const bool use = xside == 0 && rp->las.on && c == rp->las.pol;
+            const char *tb = use ? (const char *)rp->inc : rp->face_base;
+            const long k1 = rp->inc_k1, fc = rp->inc_face;
+            const long lo = use ? (step % k1) * 2 * fc + f : 0, ln = use ? ((step + 1) % k1) * 2 * fc + f : 0;
+            const long fo = use ? fc : 0;
+            const double a0 = m3::sld<double>(tb, lo), a1 = m3::sld<double>(tb, lo + fo);
+            const double a2 = m3::sld<double>(tb, ln), a3 = m3::sld<double>(tb, ln + fo);
+            ia_o = use ? a0 : 0.0;
+            ig_o = use ? a1 : 0.0;
+            ia_n = use ? a2 : 0.0;
+            ig_n = use ? a3 : 0.0;
+        }
+        return (T)mur_core(rp->murc[0], (double)e_old, (double)e_new, g_old, ia_o, ia_n, ig_o, ig_n);
+    };
 
     auto iter = [&](auto Jc) __attribute__((always_inline)) {
         constexpr int J = decltype(Jc)::value;
@@ -532,12 +591,29 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
             }
 #pragma unroll
             for (int c = 0; c < 3; c++) en[c] = half * (e0o[c] + eh[c]);
+            if constexpr (XB) {
+                // the Mur ghosts across x of E0y and E0z
+                const T up_y = m3::lane_up(eh[1]), dn_y = m3::lane_dn(eh[1]), up_z = m3::lane_up(eh[2]), dn_z = m3::lane_dn(eh[2]);
+                const T oup_y = m3::lane_up(e0o[1]), odn_y = m3::lane_dn(e0o[1]);
+                const T oup_z = m3::lane_up(e0o[2]), odn_z = m3::lane_dn(e0o[2]);
+                const long f = (long)zs_em(p1) * nn1 + ys_em;
+                const T vy = mur_x(0, 1, xside ? odn_y : oup_y, xside ? dn_y : up_y, f);
+                const T vz = mur_x(0, 2, xside ? odn_z : oup_z, xside ? dn_z : up_z, f);
+                const bool isg = gx == gx_ghost;
+                const bool owner = isg && own_lane(xside ? lane - 1 : lane + 1) && own_y && own_p(p1);
+                eh[1] = isg ? vy : eh[1];
+                eh[2] = isg ? vz : eh[2];
+                fstx(owner, q_mur(0, 0, xside, 1, sn), f, vy);
+                fstx(owner, q_mur(0, 0, xside, 2, sn), f, vz);
+            }
             if constexpr (!GEN) {
-                const unsigned o = (own_x && own_y && own_p(p1)) ? off_em(p1) : sink_o;
+                const bool ow = own_y && own_p(p1);
+                const unsigned on = (own_x && ow) ? off_em(p1) : sink_o;
+                const unsigned oc = XB ? ((own_xc && ow) ? off_em(p1) : sink_o) : on;
                 const char *kb = kb_wr(0);
-                st(kb, 0, o, eh[0]);
-                st(kb, 1, o, eh[1]);
-                st(kb, 2, o, eh[2]);
+                st(kb, 0, on, eh[0]);
+                st(kb, 1, oc, eh[1]);
+                st(kb, 2, oc, eh[2]);
             } else if (own_y && own_p(p1)) {
                 const char *kb = kb_wr(0);
                 const unsigned o = off_em(p1);
@@ -546,7 +622,7 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 if (yc && own_xc) st(kb, 2, o, eh[2]);
             }
             // Mur ghosts across x of E0y (nodal y, centred z) and E0z (centred y, nodal z)
-            if (mx && seg_xb) {
+            if (GEN && mx && seg_xb) {
                 const T up_y = m3::lane_up(eh[1]), dn_y = m3::lane_dn(eh[1]), up_z = m3::lane_up(eh[2]), dn_z = m3::lane_dn(eh[2]);
                 const T oup_y = m3::lane_up(e0o[1]), odn_y = m3::lane_dn(e0o[1]);
                 const T oup_z = m3::lane_up(e0o[2]), odn_z = m3::lane_dn(e0o[2]);
@@ -716,11 +792,12 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 v[2] = b0_2[2] - (a - b);
             }
             if constexpr (!GEN) {
-                const unsigned o = (own_x && ownr) ? off_em(p2) : sink_o;
+                const unsigned on = (own_x && ownr) ? off_em(p2) : sink_o;
+                const unsigned oc = XB ? ((own_xc && ownr) ? off_em(p2) : sink_o) : on;
                 const char *kb = kb_wr(1);
-                st(kb, 0, o, v[0]);
-                st(kb, 1, o, v[1]);
-                st(kb, 2, o, v[2]);
+                st(kb, 0, oc, v[0]);
+                st(kb, 1, on, v[1]);
+                st(kb, 2, on, v[2]);
             } else if (ownr) {
                 const char *kb = kb_wr(1);
                 const unsigned o = off_em(p2);
@@ -769,12 +846,28 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 T rhs = (a - b) - cg1 * Sc;
                 eh[2] = e1o[2] + T(1) * rhs;
             }
+            if constexpr (XB) {
+                const T up_y = m3::lane_up(eh[1]), dn_y = m3::lane_dn(eh[1]), up_z = m3::lane_up(eh[2]), dn_z = m3::lane_dn(eh[2]);
+                const T oup_y = m3::lane_up(e1o[1]), odn_y = m3::lane_dn(e1o[1]);
+                const T oup_z = m3::lane_up(e1o[2]), odn_z = m3::lane_dn(e1o[2]);
+                const long f = (long)zs_em(p3) * nn1 + ys_em;
+                const T vy = mur_x(1, 1, xside ? odn_y : oup_y, xside ? dn_y : up_y, f);
+                const T vz = mur_x(1, 2, xside ? odn_z : oup_z, xside ? dn_z : up_z, f);
+                const bool isg = gx == gx_ghost;
+                const bool owner = isg && own_lane(xside ? lane - 1 : lane + 1) && own_y && own_p(p3);
+                eh[1] = isg ? vy : eh[1];
+                eh[2] = isg ? vz : eh[2];
+                fstx(owner, q_mur(1, 0, xside, 1, sn), f, vy);
+                fstx(owner, q_mur(1, 0, xside, 2, sn), f, vz);
+            }
             if constexpr (!GEN) {
-                const unsigned o = (own_x && own_y && own_p(p3)) ? off_em(p3) : sink_o;
+                const bool ow = own_y && own_p(p3);
+                const unsigned on = (own_x && ow) ? off_em(p3) : sink_o;
+                const unsigned oc = XB ? ((own_xc && ow) ? off_em(p3) : sink_o) : on;
                 const char *kb = kb_wr(2);
-                st(kb, 0, o, eh[0]);
-                st(kb, 1, o, eh[1]);
-                st(kb, 2, o, eh[2]);
+                st(kb, 0, on, eh[0]);
+                st(kb, 1, oc, eh[1]);
+                st(kb, 2, oc, eh[2]);
             } else if (own_y && own_p(p3)) {
                 const char *kb = kb_wr(2);
                 const unsigned o = off_em(p3);
@@ -782,7 +875,7 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 if (zc(p3) && own_xc) st(kb, 1, o, eh[1]);
                 if (yc && own_xc) st(kb, 2, o, eh[2]);
             }
-            if (mx && seg_xb) {
+            if (GEN && mx && seg_xb) {
                 const T up_y = m3::lane_up(eh[1]), dn_y = m3::lane_dn(eh[1]), up_z = m3::lane_up(eh[2]), dn_z = m3::lane_dn(eh[2]);
                 const T oup_y = m3::lane_up(e1o[1]), odn_y = m3::lane_dn(e1o[1]);
                 const T oup_z = m3::lane_up(e1o[2]), odn_z = m3::lane_dn(e1o[2]);
@@ -872,11 +965,12 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                     v[2] = b1_4[2] - (a - b);
                 }
                 if constexpr (!GEN) {
-                    const unsigned o = (own_x && own_y && ownp) ? off_em(p4) : sink_o;
+                    const unsigned on = (own_x && own_y && ownp) ? off_em(p4) : sink_o;
+                    const unsigned oc = XB ? ((own_xc && own_y && ownp) ? off_em(p4) : sink_o) : on;
                     const char *kb = kb_wr(3);
-                    st(kb, 0, o, v[0]);
-                    st(kb, 1, o, v[1]);
-                    st(kb, 2, o, v[2]);
+                    st(kb, 0, oc, v[0]);
+                    st(kb, 1, on, v[1]);
+                    st(kb, 2, on, v[2]);
                 } else if (ownp) {
                     const char *kb = kb_wr(3);
                     const unsigned o = off_em(p4);
@@ -939,8 +1033,20 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 T xq = dt2 * ((sax - m2 * pb) + lap) - sdt * sdt * pb;
                 T pn = ((xq + sdt * pa) + T(2) * pb) - pa;
                 if (sdt != T(0)) pn = pn / (T(1) + sdt);
+                if constexpr (XB) {
+                    // the axion ghost beyond the boundary cell of this segment's x face
+                    const long f = (long)gz * nn1 + ys_em;
+                    const T gbv = m3::sld<T>(face(q_axg(0, xside, lb)), f), gav = m3::sld<T>(face(q_axg(0, xside, la)), f);
+                    const T rr = rp->out_r[0];
+                    T xx = (((T(-2) * gbv + T(2) * gav) - dt2 * (sax - m2 * gbv)) + rr * pb - rr * rr * (pb - T(2) * gbv))
+                           / (rr + rr * rr);
+                    const T gval = rp->axbc[0] == AXF_AX_OUTFLOW ? gav + rr * (pb - xx) : pn;
+                    const bool owner = own_xc && own_y && ownp && xs_em == (xside ? n0 - 1 : 0);
+                    fstx(owner, q_axg(0, xside, ln), f, gval);
+                }
                 if constexpr (!GEN) {
-                    m3::sto<T>(arr_ph(ln), (own_x && own_y && ownp) ? xo_em + yo_em + (unsigned)gz * syb : sink_o, pn);
+                    const bool ownc = (XB ? own_xc : own_x) && own_y && ownp;
+                    m3::sto<T>(arr_ph(ln), ownc ? xo_em + yo_em + (unsigned)gz * syb : sink_o, pn);
                 } else if (ownp && yc && zc(p4) && own_xc) {
                     m3::sto<T>(arr_ph(ln), xo_em + yo_em + (unsigned)gz * syb, pn);
                     // axion ghosts of the new level at the boundary cells
@@ -1013,6 +1119,10 @@ static M3Geom march3d_geom(const RunK<T>& h, int zc)
     // launch everywhere
     const bool pml = h.axbc[0] == AXF_AX_PML || h.axbc[1] == AXF_AX_PML || h.axbc[2] == AXF_AX_PML;
     if (pml || g.gy1 <= g.gy0 || g.sx1 <= g.sx0) g.gy0 = g.gy1 = g.sx0 = g.sx1 = 0;
+    // the x-face launch: Mur x faces with an outflow or reflecting axion
+    g.xb = g.sx1 > g.sx0 && h.mur[0] && (h.axbc[0] == AXF_AX_OUTFLOW || h.axbc[0] == AXF_AX_REFLECT) ? 1 : 0;
+    const char *xe = getenv("AXF_M3_XB");
+    if (xe && atoi(xe) == 0) g.xb = 0;
     const int zcv = zc > 0 ? zc : 64;
     const char *oe = getenv("AXF_M3_ORDER");
     g.order = oe ? atoi(oe) : 0;
@@ -1024,6 +1134,7 @@ static M3Geom march3d_geom(const RunK<T>& h, int zc)
         g.nzc = 2;
         g.zi = 1;
         g.gy0 = g.gy1 = g.sx0 = g.sx1 = 0;
+        g.xb = 0;
         return g;
     }
     const int nzi = (g.zend - g.zf + zcv - 1) / zcv;
@@ -1035,32 +1146,36 @@ static M3Geom march3d_geom(const RunK<T>& h, int zc)
 template <typename T>
 bool march3d_available(const RunK<T>& h)
 {
-    // 32-bit byte offsets within the three components of a kind
-    return h.D == 3 && (unsigned long long)h.arr_stride * 3 <= (1ull << 32);
+    // 32-bit byte offsets within the three components of a kind, within the
+    // boundary planes and within the laser table
+    return h.D == 3 && (unsigned long long)h.arr_stride * 3 <= (1ull << 32) &&
+           (unsigned long long)h.face_stride * kNumFaces < (1ull << 32) &&
+           (unsigned long long)h.inc_k1 * 2 * h.inc_face * 8 < (1ull << 32);
 }
 
 template <typename T>
-static void march3d_counts(const M3Geom& g, long *interior, long *frame)
+static void march3d_counts(const M3Geom& g, long *interior, long *xface, long *frame)
 {
     *interior = (long)(g.sx1 - g.sx0) * (g.gy1 - g.gy0) * (g.nzc - 2);
-    *frame = (long)g.nseg * g.nyg * g.nzc - *interior;
+    *xface = g.xb ? (long)(g.nseg - (g.sx1 - g.sx0)) * (g.gy1 - g.gy0) * (g.nzc - 2) : 0;
+    *frame = (long)g.nseg * g.nyg * g.nzc - *interior - *xface;
 }
 
 template <typename T>
 long march3d_blocks(const RunK<T>& h, int zc)
 {
-    long a, b;
-    march3d_counts<T>(march3d_geom(h, zc), &a, &b);
-    return a + b;
+    long a, b, c;
+    march3d_counts<T>(march3d_geom(h, zc), &a, &b, &c);
+    return a + b + c;
 }
 
-template <typename T, bool GEN>
+template <typename T, int MODE>
 static hipError_t march3d_attr()
 {
     constexpr int NW = March3<T>::NW;
     static bool done = false;
     if (!done) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_march3d<T, NW, GEN>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        hipError_t e = hipFuncSetAttribute((const void *)k_march3d<T, NW, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)M3Lds<T, NW>::BYTES);
         if (e != hipSuccess) return e;
         done = true;
@@ -1068,21 +1183,24 @@ static hipError_t march3d_attr()
     return hipSuccess;
 }
 
-// the interior launch, then the frame launch, on the run's stream (both read
-// only the state of step n and write disjoint owned points)
+// the interior launch, the x-face launch, then the frame launch, on the
+// run's stream (all read only the state of step n and write disjoint owned
+// points)
 template <typename T>
 hipError_t launch_march3d(const RunK<T> *rk, const RunK<T>& h, long step, int zc, hipStream_t st)
 {
     constexpr int NW = March3<T>::NW;
     using LQ = M3Lds<T, NW>;
-    hipError_t e = march3d_attr<T, false>();
-    if (e == hipSuccess) e = march3d_attr<T, true>();
+    hipError_t e = march3d_attr<T, 0>();
+    if (e == hipSuccess) e = march3d_attr<T, 1>();
+    if (e == hipSuccess) e = march3d_attr<T, 2>();
     if (e != hipSuccess) return e;
     const M3Geom g = march3d_geom(h, zc);
-    long ni, nf;
-    march3d_counts<T>(g, &ni, &nf);
-    if (ni > 0) hipLaunchKernelGGL((k_march3d<T, NW, false>), dim3((unsigned)ni), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
-    if (nf > 0) hipLaunchKernelGGL((k_march3d<T, NW, true>), dim3((unsigned)nf), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
+    long ni, nx, nf;
+    march3d_counts<T>(g, &ni, &nx, &nf);
+    if (ni > 0) hipLaunchKernelGGL((k_march3d<T, NW, 0>), dim3((unsigned)ni), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
+    if (nx > 0) hipLaunchKernelGGL((k_march3d<T, NW, 1>), dim3((unsigned)nx), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
+    if (nf > 0) hipLaunchKernelGGL((k_march3d<T, NW, 2>), dim3((unsigned)nf), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
     return hipGetLastError();
 }
 

@@ -179,6 +179,16 @@ __device__ __forceinline__ auto pml_sdt(const R& r, int i, int j, int k) -> decl
 // First-order Mur update of one tangential E ghost (FP64) from the adjacent
 // point's E^{n-1/2} and E^{n+1/2} and the ghost's old value, with the laser
 // values of the per-level table on the x_min face (the unfused path's formula)
+// The Mur formula itself on the scattered parts (E minus the laser's value
+// at the adjacent point (ia) and at the ghost (ig), old and new levels)
+__device__ __forceinline__ double mur_core(double murc, double e_old, double e_new, double g_old, double ia_o,
+                                           double ia_n, double ig_o, double ig_n)
+{
+    double sa_o = e_old - ia_o, sa_n = e_new - ia_n, sg_o = g_old - ig_o;
+    double sg_n = sa_o + murc * (sa_n - sg_o);
+    return sg_n + ig_n;
+}
+
 template <typename T>
 __device__ __forceinline__ T mur_update_rk(const RunK<T>& r, int O, int c, int d, int side, double e_old, double e_new,
                                            double g_old, long fidx, long step)
@@ -191,9 +201,7 @@ __device__ __forceinline__ T mur_update_rk(const RunK<T>& r, int O, int c, int d
         ia_n = r.inc[ln + fidx];
         ig_n = r.inc[ln + r.inc_face + fidx];
     }
-    double sa_o = e_old - ia_o, sa_n = e_new - ia_n, sg_o = g_old - ig_o;
-    double sg_n = sa_o + r.murc[d] * (sa_n - sg_o);
-    return (T)(sg_n + ig_n);
+    return (T)mur_core(r.murc[d], e_old, e_new, g_old, ia_o, ia_n, ig_o, ig_n);
 }
 
 // ----------------------------------------------------------- analytic inputs
