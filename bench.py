@@ -55,7 +55,7 @@ COMMON_SOURCES = [CSRC + "axf_stencil.h", CSRC + "axf_internal.h", "paper_2406_1
 WORKLOADS = {
     "2d": ("gaussian_2d", "k_wave2d", ["k_wave2d_pass<{T}", "k_wave2d_int<{T}", "k_wave2d<{T}"],
            [CSRC + "axf_fused.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
-    "3d": ("focused_3d", "k_march3d", ["k_march3d<{T},{NW},false>", "k_march3d<{T},{NW},true>"],
+    "3d": ("focused_3d", "k_march3d", ["k_march3d<{T},{NW},0>", "k_march3d<{T},{NW},1>", "k_march3d<{T},{NW},2>"],
            [CSRC + "axf_march3d.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
     "1d": ("plane_wave_1d", "plain_step", ["k_e0<1,{T}>", "k_c<1,{T}>", "k_e1<1,{T}>", "k_mur<1,{T}>",
                                            "k_b<1,{T}>", "k_phi<1,{T}>"],
@@ -456,8 +456,9 @@ def trace_summary(args):
              % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps), "",
              "The run times the fused path twice (with and without diagnostics) and the unfused phase "
              "sequence once; the copy kernel is the bandwidth calibration.  " + (
-                 "In 3D one step is `k_march3d<T, NW, false>` over the interior box (every workgroup clear "
-                 "of the faces) followed by `k_march3d<T, NW, true>` over the boundary frame, on the run's "
+                 "In 3D one step is `k_march3d<T, NW, 0>` over the interior box (every workgroup clear "
+                 "of the faces), `k_march3d<T, NW, 1>` over the two x-face segment columns and "
+                 "`k_march3d<T, NW, 2>` over the rest of the boundary frame, in turn on the run's "
                  "stream; the step time is the sum of their mean durations."
                  if args.workload == "3d" else
                  "In 2D a pass of NS steps is `k_wave2d_pass<T, PD, NS, MODE>` over the interior with NS "
@@ -490,7 +491,7 @@ def trace_summary(args):
     if args.workload == "3d":
         means = [float(r["AverageNs"]) / 1e3 for pat in pats for r in rows if pat in r["Name"].replace(" ", "")]
         if len(means) == len(pats):
-            lines.append("- `step_mean_us = %.2f` (the interior and frame launches of one step)" % sum(means))
+            lines.append("- `step_mean_us = %.2f` (the three launches of one step)" % sum(means))
     lines.append("- `kernel_source_sha256 = %s`" % kernel_source_hash(args.workload))
     path = os.path.join(ROOT, "profiles", "%s_%s_kernel_trace.md" % (kernel, tag))
     with open(path, "w") as f:
@@ -599,7 +600,7 @@ def main():
             "traffic": round(traffic) if traffic is not None else None,
             "kernel": " + ".join(pattern_label(p) for p in pats) if fused else "plain phase sequence",
             "unit_of_work": "one step of the whole grid (%s)" % (
-                "interior launch then boundary-frame launch" if args.workload == "3d" else "fused launches"),
+                "interior, x-face and frame launches" if args.workload == "3d" else "fused launches"),
             "bytes_per_step": algo_bytes, "launches_per_step": round(k_launches / args.steps, 3),
             "mean_step_ms": round(per_step_s * 1e3, 5), "steps_timed": args.steps,
             "traffic_over_algorithmic": round(traffic / algo_bytes, 3) if traffic is not None else None,
