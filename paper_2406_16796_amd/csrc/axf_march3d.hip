@@ -166,12 +166,15 @@ __host__ __device__ inline void m3_block(const M3Geom& g, int mode, unsigned b, 
 {
     const unsigned nsx = (unsigned)(g.sx1 - g.sx0), ny = (unsigned)(g.gy1 - g.gy0), nzi = (unsigned)(g.nzc - 2);
     if (mode == 1) {
+        // row groups fastest (a segment's only neighbours here are along y),
+        // with a band of the order per XCD as in the interior launch
         const unsigned nfx = (unsigned)g.nseg - nsx;
-        const int k = (int)(b % nfx);
+        if (g.order & 2) b = (unsigned)xcd_band((long)b, (long)(nfx * ny * nzi));
+        ygr = g.gy0 + (int)(b % ny);
+        const unsigned r = b / ny;
+        const int k = (int)(r % nfx);
         seg = k < g.sx0 ? k : g.sx1 + (k - g.sx0);
-        const unsigned r = b / nfx;
-        ygr = g.gy0 + (int)(r % ny);
-        zch = 1 + (int)(r / ny);
+        zch = 1 + (int)(r / nfx);
         return;
     }
     if (mode == 0) {
@@ -1124,8 +1127,10 @@ static M3Geom march3d_geom(const RunK<T>& h, int zc)
     const char *xe = getenv("AXF_M3_XB");
     if (xe && atoi(xe) == 0) g.xb = 0;
     const int zcv = zc > 0 ? zc : 64;
+    // interior block order: a band per XCD, segments fastest (measured on
+    // 512^3 FP32: 39% fewer HBM reads than the plain order, 6.5 against 6.8 ms)
     const char *oe = getenv("AXF_M3_ORDER");
-    g.order = oe ? atoi(oe) : 0;
+    g.order = oe ? atoi(oe) : 2;
     g.nn2 = h.nn[2];
     g.zf = 3;
     g.zend = h.n[2] - 2;
