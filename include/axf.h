@@ -122,7 +122,7 @@ typedef struct {
     double  p_conv;          /* h_em1 / h_phi (0 if h_phi == 0) */
     int32_t finite;          /* 0 if any field was not finite */
     int32_t pad;
-    double  x_laser;         /* laser centroid (Sec. IV): sum x B1z^2 / sum B1z^2 over the
+    double  x_laser;         /* laser centroid (Sec. III.D): sum x B1z^2 / sum B1z^2 over the
                                 B1z points, x = i dx on the x nodes (0 if B1z == 0) */
 } axf_diag_record;
 
@@ -137,29 +137,61 @@ const char *axf_version(void);
 
 /* ------------------------------------------------------------ single run */
 
-/* Device bytes a run needs (all state, ghosts and scratch).  Pure host call. */
+/* Device bytes one run of `cfg` needs: the state of the leapfrog form of
+   Sec. II.C (E^{n-1/2} and B^n of both orders, the axion levels), the
+   boundary planes (axion ghosts of Sec. II.D, Mur ghosts), the laser table
+   and the diagnostic partials and records.  Pure host call, no GPU.
+   Errors: EINVAL (bad config), EUNSTABLE (dt beyond the stability limit). */
 int axf_footprint(const axf_config *cfg, size_t *bytes);
 
-/* Storage extents of the arrays crossing the ABI for this configuration. */
+/* Storage extents nn[3] of the arrays crossing the ABI for `cfg` (the
+   staggered layout of Sec. II.C: n + 1 along Mur axes, n otherwise).
+   Pure host call.  Errors: EINVAL. */
 int axf_extents(const axf_config *cfg, int32_t nn[3]);
 
-/* Create a run carved from caller-owned device memory `dev_buf` of `bytes`
-   (>= axf_footprint), enqueue the analytic initial state on `stream`.
-   Errors: EINVAL (bad config), EUNSTABLE (dt), ENOMEM (buffer too small), EHIP. */
+/* Create a run: the problem statement of Sec. II.C (grid n, dx and time step
+   dt), the axion mass m and coupling g of eq. wave_axion (Sec. II.A), the
+   static field B0 = B_ext over the slab (Sec. III.B), the laser source
+   (Sec. III.B), the initial axion at two time levels (Sec. III.A) and the
+   boundary kinds (Sec. II.D).
+   dev_buf: caller-owned device memory of `bytes` >= axf_footprint(cfg),
+   256-byte aligned, holding the run until axf_destroy; never freed by the
+   library.  stream: the hipStream_t every GPU operation of the run goes to
+   (NULL: the default stream).  The analytic initial state (fields zero, the
+   packet's two levels at t = -dt/2 and +dt/2, the laser table) is enqueued
+   on the stream; the call returns before it runs.  *out receives the run.
+   Errors: EINVAL (bad config or null argument), EUNSTABLE (dt), ENOMEM
+   (buffer smaller than the footprint), EHIP (a HIP call failed). */
 int axf_create(const axf_config *cfg, void *dev_buf, size_t bytes, void *stream, axf_run **out);
 
-/* Overwrite field `field_id` of the initial state (only before the first step).
-   `src` holds the dense array in FP64 (true, unscaled values); host or device. */
+/* Overwrite field `field_id` (AXF_E0X .. AXF_PHI_NEW) of the initial state
+   before the first step: the initial conditions of Sec. III.A, e.g. both
+   axion levels of a packet, or any field of a synthetic test state.
+   src: dense FP64 array of the true (unscaled) values with the extents of
+   axf_extents, x fastest, src_bytes >= nn[0] nn[1] nn[2] * 8; in host memory
+   (src_is_device = 0) or device memory (1), read before the call returns.
+   Errors: EINVAL (bad id, size or pointer), ESTATE (the run has stepped), EHIP. */
 int axf_write_field(axf_run *run, int32_t field_id, const void *src, size_t src_bytes, int32_t src_is_device);
 
-/* Advance `nsteps` steps (asynchronous on the run's stream). */
+/* Advance nsteps >= 0 full steps of Sec. II.C (eqs. update_E, update_B and
+   update_axion, in the leapfrog form) with the axion boundaries of Sec. II.D
+   and the Mur faces, recording the diagnostics every diag_every steps.
+   Asynchronous on the run's stream.  Errors: EINVAL (nsteps < 0), EHIP. */
 int axf_step(axf_run *run, int64_t nsteps);
 
-/* Read field `field_id` at the current integer time into `dst` as FP64 true
-   values (E fields co-timed at t_n; phi at t_n -+ dt/2).  Synchronises the stream. */
+/* Read field `field_id` at the current integer time t_n: phi, E1 and B1 (the
+   perturbed fields of Sec. II.B, "perturbed laser field" of Sec. III.C) or
+   E0 and B0, as dense FP64 true values (descaled), x fastest, the extents of
+   axf_extents.  E fields are co-timed at t_n (mean of E^{n-1/2}, E^{n+1/2}),
+   B at t_n, phi at t_n - dt/2 (AXF_PHI_OLD) and t_n + dt/2 (AXF_PHI_NEW).
+   dst: host (dst_is_device = 0) or device memory of dst_bytes >= nn[0] nn[1]
+   nn[2] * 8.  Synchronises the run's stream.  Errors: EINVAL, EHIP. */
 int axf_read_field(axf_run *run, int32_t field_id, void *dst, size_t dst_bytes, int32_t dst_is_device);
 
-/* Compute a diagnostic record at the current time now (synchronises). */
+/* The diagnostic record of Sec. III.B/C at the current time t_n: H_phi,
+   H_gamma0, H_gamma1 in FP64, P_gamma->phi = H_phi / H_gamma0,
+   P_phi->gamma = H_gamma1 / H_phi, and x_laser (Sec. III.D).  *out is host
+   memory.  Synchronises the run's stream.  Errors: EINVAL, EHIP. */
 int axf_diag_now(axf_run *run, axf_diag_record *out);
 
 /* For callers that cannot allocate device memory at the call (code under HIP
@@ -175,15 +207,26 @@ int axf_diag_now(axf_run *run, axf_diag_record *out);
    host threads on one device race.  rows outside 0..1024 -> AXF_EINVAL. */
 int axf_diag_now_static(axf_run *run, int32_t rows, axf_diag_record *out);
 
-/* Copy up to `max` recorded diagnostics (oldest first) and clear them; *n = count. */
+/* Copy up to `max` of the records taken every diag_every steps (the
+   probabilities of Sec. III.B/C over time, oldest first) into host memory
+   `out` and clear them; *n = the number copied.  The run keeps the last 4096.
+   Synchronises the run's stream.  Errors: EINVAL, EHIP. */
 int axf_read_diag(axf_run *run, axf_diag_record *out, int32_t max, int32_t *n);
 
-/* Checkpoint: raw state (fields, ghosts, counters) into / from a host buffer. */
+/* Checkpoint and resume (a project facility; no passage of the paper): the
+   raw state (fields, ghosts, the laser table, step counter) into or from a
+   host buffer of axf_state_bytes bytes.  A state written back into a run of
+   the same configuration continues bit for bit as the run it was read from.
+   Both synchronise the stream and copy before they return; write also has
+   the next step refill the laser table.  Errors: ENOMEM (buffer smaller than
+   axf_state_bytes), EINVAL (a state of another configuration), EHIP. */
 int axf_state_bytes(const axf_run *run, size_t *bytes);
 int axf_read_state(axf_run *run, void *buf, size_t bytes);
 int axf_write_state(axf_run *run, const void *buf, size_t bytes);
 
+/* Wait for the run's stream.  Errors: EINVAL, EHIP. */
 int axf_sync(axf_run *run);
+/* Steps taken so far (host counter, no synchronisation). */
 int axf_steps_done(const axf_run *run, int64_t *steps);
 /* the step path this run takes: AXF_PATH_PLAIN or AXF_PATH_FUSED (AUTO resolved) */
 int axf_path_in_use(const axf_run *run, int32_t *path);
@@ -228,7 +271,7 @@ int axf_tune(const axf_config *cfg, void *scratch, size_t bytes, void *stream, i
 int axf_tune_reset(void);
 
 /* ------------------------------------------------------------ SI inputs
- * The paper's SI form of the equations (Sec. II.B: the axion field in units of
+ * The paper's SI form of the equations (Sec. II.A: the axion field in units of
  * frequency, g_agg in units of time, as an SI particle-in-cell code takes them)
  * mapped to the normalised units of axf_config: times in 1/omega0, lengths in
  * 1/k0 (omega0 = k0 c = 2 pi c / lambda0 of a reference wavelength), fields in

@@ -28,14 +28,19 @@
  * centred everywhere.  Entries a component does not use stay zero.
  *
  * Pins (tests/test_oracle_*.py): Yee and Klein-Gordon discrete dispersion
- * relations (exact normal modes), the discrete EM energy invariant, div B,
- * Gauss-law convergence with the axion charge, bit-exact linearity in g,
- * exact-rational brute force of the half-step and leapfrog forms, reflect
- * boundary by the method of images, periodic translation invariance,
- * outflow/PML reflectivity against the 1% of Sec. III.A, and the conversion
- * probability of Sec. III.B.  The laser injection profile and Mur details
- * are pinned only by the plane-wave transmission and Mur reflection tests
- * (they have no formula in the paper).
+ * relations (exact normal modes), the discrete EM and KG energy invariants,
+ * div B, Gauss's law with the axion charge (kept exactly with E0 = 0, and
+ * converging at second order with a laser wave on, which pins E0 x grad phi;
+ * copies of this file with a planted sign or component slip fail it),
+ * bit-exact linearity in g, exact-rational brute force of the half-step and
+ * leapfrog forms, reflect boundary by the method of images, periodic
+ * translation invariance, outflow/PML reflectivity against the 1% of
+ * Sec. III.A, the conversion probability of Sec. III.B, the Mur faces
+ * (plane-wave transmission of the injected laser; a normal pulse leaving
+ * through x_max and y_max), and the first-order effect of the literal
+ * reading of the time derivative (ORA_DTPHI_LITERAL).  The Gaussian
+ * envelope and focused profile of the injected laser have no formula in the
+ * paper and no pin (parity unpinned).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -280,11 +285,23 @@ static double phi_mid(const ora_state *s, int La, int Lb, int i, int j, int k)
     return 0.5 * (phi_at(s, Lb, i, j, k) + phi_at(s, La, i, j, k));
 }
 
+/* Reading of the time derivative in the second E1 half step (Sec. II.C,
+   eq. update_E at t_{n+1}): the paper writes it at n + 1/2 beside fields at
+   n + 1.  The default takes (D_t phi)^{n+1} = (phi^{n+3/2} - phi^{n+1/2}) / dt,
+   which makes the two half steps one leapfrog step; ORA_DTPHI_LITERAL = 1 (a
+   separate test build only) takes the literal centred derivative at n + 1/2,
+   (phi^{n+3/2} - phi^{n-1/2}) / (2 dt). */
+#ifndef ORA_DTPHI_LITERAL
+#define ORA_DTPHI_LITERAL 0
+#endif
+
 /* C = (D_t phi) B0 - E0 x D phi at every centre, for the integer time between
-   axion slots La (earlier) and Lb (later), with the E0, B0 arrays as they are */
-static void compute_C(ora_state *s, int La, int Lb)
+   axion slots La (earlier) and Lb (later), with the E0, B0 arrays as they are;
+   Lo: the slot before La (the literal reading's level), -1 for none */
+static void compute_C(ora_state *s, int La, int Lb, int Lo)
 {
     const double dt = s->c.dt, *h = s->c.dx;
+    const int literal = ORA_DTPHI_LITERAL && Lo >= 0;
     #pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < s->n[2]; k++)
         for (int j = 0; j < s->n[1]; j++)
@@ -292,7 +309,8 @@ static void compute_C(ora_state *s, int La, int Lb)
                 double e[3], b[3], gp[3];
                 centre_E0(s, i, j, k, e);
                 centre_B0(s, i, j, k, b);
-                double dtphi = (phi_at(s, Lb, i, j, k) - phi_at(s, La, i, j, k)) / dt;
+                double dtphi = literal ? (phi_at(s, Lb, i, j, k) - phi_at(s, Lo, i, j, k)) / (2.0 * dt)
+                                       : (phi_at(s, Lb, i, j, k) - phi_at(s, La, i, j, k)) / dt;
                 gp[0] = (phi_mid(s, La, Lb, i + 1, j, k) - phi_mid(s, La, Lb, i - 1, j, k)) / (2.0 * h[0]);
                 gp[1] = (phi_mid(s, La, Lb, i, j + 1, k) - phi_mid(s, La, Lb, i, j - 1, k)) / (2.0 * h[1]);
                 gp[2] = (phi_mid(s, La, Lb, i, j, k + 1) - phi_mid(s, La, Lb, i, j, k - 1)) / (2.0 * h[2]);
@@ -492,7 +510,7 @@ static void one_step(ora_state *s)
     const double h = 0.5 * s->c.dt, g = s->c.g;
     int La = s->la, Lb = s->lb, Ln = 3 - La - Lb;
 
-    compute_C(s, La, Lb);          /* axion current at t_n (uses E0^n, B0^n) */
+    compute_C(s, La, Lb, -1);      /* axion current at t_n (uses E0^n, B0^n) */
     update_E(s, 0, h, 0.0);        /* E0^{n+1/2} */
     update_E(s, 1, h, g);          /* E1^{n+1/2}, eq. update_E */
     mur_ghosts(s);                 /* tangential E ghosts at t_{n+1/2} */
@@ -502,7 +520,7 @@ static void one_step(ora_state *s)
     axion_ghosts(s, La, Lb, Ln);
     update_B(s, h);                /* B^{n+1} */
     update_E(s, 0, h, 0.0);        /* E0^{n+1} */
-    compute_C(s, Lb, Ln);          /* axion current at t_{n+1} (E0^{n+1}, B0^{n+1}) */
+    compute_C(s, Lb, Ln, La);      /* axion current at t_{n+1} (E0^{n+1}, B0^{n+1}) */
     update_E(s, 1, h, g);          /* E1^{n+1} */
 
     s->la = Lb;
@@ -578,7 +596,7 @@ static double *zalloc(long n)
 static void init_mur_history(ora_state *s)
 {
     const double dt = s->c.dt, h = 0.5 * dt, g = s->c.g, t_old = -0.5 * dt;
-    compute_C(s, s->la, s->lb);
+    compute_C(s, s->la, s->lb, -1);
     for (int d = 0; d < 3; d++) {
         if (em_periodic(s, d)) continue;
         int a, b;

@@ -43,16 +43,20 @@ class OraConfig(ctypes.Structure):
     ]
 
 
-def build(force=False):
-    """Compile liboracle.so with gcc (plain -O2, no FP contraction)."""
-    src = os.path.join(HERE, "axion_oracle.c")
-    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(src):
-        return LIB_PATH
+def build(force=False, src=None, out=None, defines=()):
+    """Compile liboracle.so with gcc (plain -O2, no FP contraction).  `src`,
+    `out` and `defines` build another copy of the source (the tests'
+    planted-mistake variants, the literal reading of Sec. II.C) into another
+    library."""
+    src = src or os.path.join(HERE, "axion_oracle.c")
+    out = out or LIB_PATH
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
+        return out
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
-           "-std=gnu99", "-Wall", "-o", LIB_PATH + ".tmp", src, "-lm"]
+           "-std=gnu99", "-Wall", "-I", HERE] + ["-D" + d for d in defines] + ["-o", out + ".tmp", src, "-lm"]
     subprocess.check_call(cmd)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(out + ".tmp", out)
+    return out
 
 
 _lib = None
@@ -62,27 +66,32 @@ def lib():
     global _lib
     if _lib is None:
         build()
-        L = ctypes.CDLL(LIB_PATH)
-        L.ora_create.argtypes = [ctypes.POINTER(OraConfig), ctypes.POINTER(ctypes.c_void_p)]
-        L.ora_create.restype = ctypes.c_int
-        L.ora_destroy.argtypes = [ctypes.c_void_p]
-        L.ora_extents.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
-        L.ora_field.argtypes = [ctypes.c_void_p, ctypes.c_int]
-        L.ora_field.restype = ctypes.POINTER(ctypes.c_double)
-        L.ora_axion_ghost.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
-        L.ora_axion_ghost.restype = ctypes.POINTER(ctypes.c_double)
-        L.ora_refresh_initial.argtypes = [ctypes.c_void_p]
-        L.ora_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
-        L.ora_step_count.argtypes = [ctypes.c_void_p]
-        L.ora_step_count.restype = ctypes.c_long
-        L.ora_energies.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
-        L.ora_incident.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_double] * 4
-        L.ora_incident.restype = ctypes.c_double
-        L.ora_threads.restype = ctypes.c_int
-        L.ora_set_threads.argtypes = [ctypes.c_int]
-        L.ora_set_threads.restype = None
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
+
+
+def load(path):
+    """A built oracle library with its call signatures declared."""
+    L = ctypes.CDLL(path)
+    L.ora_create.argtypes = [ctypes.POINTER(OraConfig), ctypes.POINTER(ctypes.c_void_p)]
+    L.ora_create.restype = ctypes.c_int
+    L.ora_destroy.argtypes = [ctypes.c_void_p]
+    L.ora_extents.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
+    L.ora_field.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.ora_field.restype = ctypes.POINTER(ctypes.c_double)
+    L.ora_axion_ghost.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.ora_axion_ghost.restype = ctypes.POINTER(ctypes.c_double)
+    L.ora_refresh_initial.argtypes = [ctypes.c_void_p]
+    L.ora_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+    L.ora_step_count.argtypes = [ctypes.c_void_p]
+    L.ora_step_count.restype = ctypes.c_long
+    L.ora_energies.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    L.ora_incident.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_double] * 4
+    L.ora_incident.restype = ctypes.c_double
+    L.ora_threads.restype = ctypes.c_int
+    L.ora_set_threads.argtypes = [ctypes.c_int]
+    L.ora_set_threads.restype = None
+    return L
 
 
 def make_config(cfg):
@@ -110,7 +119,7 @@ def make_config(cfg):
 
 
 def laser_centroid(b1z, dx):
-    """Laser centroid along x (Sec. IV, the weak-laser benchmark): the mean
+    """Laser centroid along x (Sec. III.D, the weak-laser benchmark): the mean
     of x over the grid weighted by the first-order field squared,
     x_laser = sum x B1z^2 / sum B1z^2, summed over every B1z point of the
     grid (the paper's double integral over x and y, a triple one in 3D).  B1z
@@ -130,20 +139,22 @@ def laser_centroid(b1z, dx):
 class Oracle:
     """One FP64 oracle run; arrays are numpy views on the oracle's memory."""
 
-    def __init__(self, cfg):
+    def __init__(self, cfg, library=None):
+        """`library`: another build of the oracle (load()); the default one otherwise."""
+        self._L = library or lib()
         self._cfg = make_config(cfg)
         h = ctypes.c_void_p()
-        if lib().ora_create(ctypes.byref(self._cfg), ctypes.byref(h)) != 0:
+        if self._L.ora_create(ctypes.byref(self._cfg), ctypes.byref(h)) != 0:
             raise ValueError("oracle rejected the configuration")
         self._h = h
         nn = (ctypes.c_int * 3)()
-        lib().ora_extents(h, nn)
+        self._L.ora_extents(h, nn)
         self.nn = tuple(nn)
         self.n = tuple(self._cfg.n)
 
     def close(self):
         if self._h:
-            lib().ora_destroy(self._h)
+            self._L.ora_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -154,30 +165,30 @@ class Oracle:
 
     def field(self, name):
         """Array of field `name` with shape (nn_z, nn_y, nn_x): a live view."""
-        p = lib().ora_field(self._h, FIELD_IDS[name])
+        p = self._L.ora_field(self._h, FIELD_IDS[name])
         nz, ny, nx = self.nn[2], self.nn[1], self.nn[0]
         return np.ctypeslib.as_array(p, shape=(nz * ny * nx,)).reshape(nz, ny, nx)
 
     def axion_ghost(self, d, side, level):
-        p = lib().ora_axion_ghost(self._h, d, side, level)
+        p = self._L.ora_axion_ghost(self._h, d, side, level)
         if not p:
             return None
         a, b = [e for e in range(3) if e != d]
         return np.ctypeslib.as_array(p, shape=(self.nn[a] * self.nn[b],)).reshape(self.nn[b], self.nn[a])
 
     def refresh_initial(self):
-        lib().ora_refresh_initial(self._h)
+        self._L.ora_refresh_initial(self._h)
 
     def step(self, nsteps=1):
-        lib().ora_step(self._h, int(nsteps))
+        self._L.ora_step(self._h, int(nsteps))
 
     @property
     def step_count(self):
-        return lib().ora_step_count(self._h)
+        return self._L.ora_step_count(self._h)
 
     def energies(self):
         out = (ctypes.c_double * 3)()
-        lib().ora_energies(self._h, out)
+        self._L.ora_energies(self._h, out)
         return tuple(out)
 
     def laser_centroid(self):
@@ -187,7 +198,7 @@ class Oracle:
         return laser_centroid(b, float(self._cfg.dx[0]))
 
     def threads(self):
-        return lib().ora_threads()
+        return self._L.ora_threads()
 
     @staticmethod
     def set_threads(n):
@@ -195,4 +206,4 @@ class Oracle:
         lib().ora_set_threads(int(n))
 
     def incident(self, comp, x, y, z, t):
-        return lib().ora_incident(self._h, comp, x, y, z, t)
+        return self._L.ora_incident(self._h, comp, x, y, z, t)

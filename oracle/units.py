@@ -9,7 +9,7 @@ Normalised units: times in 1/omega0, lengths in 1/k0 with k0 = 2 pi / lambda0
 and omega0 = c k0; fields in m_e c omega0 / e (E) and m_e omega0 / e (B);
 masses as m_a c^2 / (hbar omega0).  The axion field is measured so that one
 coupling drives both the axion source and the axion current of the SI
-equations (Sec. II.B); in natural (Heaviside-Lorentz) units that coupling is
+equations (Sec. II.A); in natural (Heaviside-Lorentz) units that coupling is
 g_agg m_e c^2 / sqrt(4 pi alpha), g_agg in GeV^-1.
 """
 import math

@@ -546,7 +546,7 @@ __device__ __forceinline__ void block_sums(double v[kDiagSums], double *out)
 // energies at t_n: E^n = mean of the two E slots, B^n = old slot, phi^n = mean
 // of the axion levels; H_phi = sum ((D_t phi)^2 + sum_d (D+_d phi)^2 + m^2 phi^2) / 2.
 // Sums 4 and 5: x B1z^2 and B1z^2 over the B1z points (on the x nodes, x = i dx),
-// whose ratio is the laser centroid of Sec. IV
+// whose ratio is the laser centroid of Sec. III.D
 template <int D, typename T>
 __device__ __forceinline__ void diag_point(const RunK<T>& r, long p, long step, double v[kDiagSums])
 {

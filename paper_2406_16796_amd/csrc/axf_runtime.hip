@@ -885,6 +885,9 @@ int run_write_state(Run *R, const void *buf, size_t bytes)
     R->rec_written = h.rec_written;
     R->converted = h.converted != 0;
     R->ephase_step = -1;
+    // the laser table came with the state: which levels it holds is unknown
+    // here, so the next step refills it
+    R->inc_lo = -1;
     return AXF_OK;
 }
 

@@ -1,7 +1,7 @@
 // axf_units.hip -- SI inputs to the normalised units of a run (host only).
 //
 // The derivation follows the SI form of the axion-Maxwell equations (Sec.
-// II.B).  With t = t'/omega0, x = x'/k0, E = (m_e c omega0 / e) E',
+// II.A).  With t = t'/omega0, x = x'/k0, E = (m_e c omega0 / e) E',
 // B = (m_e omega0 / e) B' and the axion field phi = s omega0 phi':
 //   - the Klein-Gordon equation, divided by omega0^3 s / c^2, has the source
 //     g m_e^2 c^3 / (hbar mu0 e^2 omega0 s) E'.B' and the mass term

@@ -288,6 +288,26 @@ def test_checkpoint_resume_is_bit_exact(axf):
         assert np.array_equal(a.read(nm), c.read(nm)), nm
 
 
+@pytest.mark.parametrize("kind", ["2d", "3d"])
+def test_checkpoint_restored_into_the_same_run(axf, kind):
+    """A laser run checkpointed at step 32, stepped 20 more (which refills
+    the laser table) and restored into the same run continues as a fresh
+    run restored from the same checkpoint: the restored table's levels are
+    not taken for those the run held before."""
+    cfg = small_2d(W.AX_OUTFLOW) if kind == "2d" else small_3d((130, 40, 32))
+    a = axf.Run(cfg, precision=axf.F32)
+    a.step(32)
+    blob = a.state()
+    a.step(20)
+    a.load_state(blob)
+    a.step(45)
+    b = axf.Run(cfg, precision=axf.F32)
+    b.load_state(blob)
+    b.step(45)
+    for nm in FIELDS:
+        assert np.array_equal(a.read(nm), b.read(nm)), nm
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_coupling_scaled_out_bit_exact(axf, prec):
     """g -> 4 g: phi x 4, E1/B1 x 16 exactly, because the stored fields are the
