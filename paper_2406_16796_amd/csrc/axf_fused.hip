@@ -58,6 +58,7 @@ struct KV {
     const double *inc;          // laser table on the x_min face (see RunK::inc)
     long inc_face;
     int inc_k1, las_on, las_pol;
+    int nem, nph;
     double murc[3];
 
     __device__ __forceinline__ const T *arr(int q) const { return (const T *)(sb + q * as); }
@@ -103,6 +104,8 @@ __device__ __forceinline__ KV<T> make_kv(const RunK<T> *__restrict__ rp)
     v.inc_k1 = rp->inc_k1;
     v.las_on = rp->las.on;
     v.las_pol = rp->las.pol;
+    v.nem = rp->nem;
+    v.nph = rp->nph;
 #pragma unroll
     for (int d = 0; d < 3; d++) v.murc[d] = rp->murc[d];
     return v;
@@ -298,7 +301,7 @@ __device__ __forceinline__ T load_phi(const KV<T>& r, int L, int x, int y, int z
     if (o0) return gld(r.face(q_axg(0, o0 < 0 ? 0 : 1, L)), face_index(r, 0, v0, v1, v2));
     if (D >= 2 && o1) return gld(r.face(q_axg(1, o1 < 0 ? 0 : 1, L)), face_index(r, 1, v0, v1, v2));
     if (D >= 3 && o2) return gld(r.face(q_axg(2, o2 < 0 ? 0 : 1, L)), face_index(r, 2, v0, v1, v2));
-    return gld(r.arr(q_phi(L)), lin3<D>(r, v0, v1, v2));
+    return gld(r.arr(q_phi(r.nem, L)), lin3<D>(r, v0, v1, v2));
 }
 
 // Address of a B / E / phi point for an unconditional load: the element
@@ -332,7 +335,7 @@ __device__ __forceinline__ const T *addr_phi(const KV<T>& r, int L, int x, int y
     if (D >= 3) chk(2, v2, o2);
     const int nout = (o0 != 0) + (o1 != 0) + (o2 != 0);
     ok = !(nout > 1 || o0 == 2 || o1 == 2 || o2 == 2);
-    const T *base = r.arr(q_phi(L));
+    const T *base = r.arr(q_phi(r.nem, L));
     if (!ok) return base;
     if (o0) return r.face(q_axg(0, o0 < 0 ? 0 : 1, L)) + face_index(r, 0, v0, v1, v2);
     if (D >= 2 && o1) return r.face(q_axg(1, o1 < 0 ? 0 : 1, L)) + face_index(r, 1, v0, v1, v2);
@@ -376,8 +379,8 @@ k_fused(const RunK<T> *__restrict__ rp, long step, int ntx, int nty, int nch, in
     const int L = (int)xcd_band(blockIdx.x, (long)ntx * nty * nch);
     const int tx = L % ntx, ty = (L / ntx) % nty, ch = L / (ntx * nty);
 
-    const int so = em_slot(step), sn = em_slot(step + 1);
-    const int la = phi_slot(step), lb = phi_slot(step + 1), ln = phi_slot(step + 2);
+    const int so = em_slot(step, r.nem), sn = em_slot(step + 1, r.nem);
+    const int la = phi_slot(step, r.nph), lb = phi_slot(step + 1, r.nph), ln = phi_slot(step + 2, r.nph);
 
     // in-plane tile and ownership ranges (the last tile also owns the nodal plane n)
     const int x0 = tx * TX, y0 = ty * TY;
@@ -704,7 +707,7 @@ k_fused(const RunK<T> *__restrict__ rp, long step, int ntx, int nty, int nch, in
                 // outside the damping layer the divisor is exactly 1: skip the division
     T pn = ((x + sdt * pa) + T(2) * pb) - pa;
     if (sdt != T(0)) pn = pn / (T(1) + sdt);
-                gst(r.warr(q_phi(ln)), gi2, pn);
+                gst(r.warr(q_phi(r.nem, ln)), gi2, pn);
                 const int gv[3] = {gi, gj, gk};
 #pragma unroll
                 for (int d = 0; d < D; d++) {
@@ -836,8 +839,10 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
 {
     KW<T> r = make_kw(rp);
     const int lane = threadIdx.x & 63;
-    const int so = em_slot(step), sn = em_slot(step + 1);
-    const int la = phi_slot(step), lb = phi_slot(step + 1), ln = phi_slot(step + 2);
+    // (the wavefront kernels advance 2D runs only, which keep kEmSlots E/B
+    // slots and kPhiSlots axion slots)
+    const int so = em_slot(step, kEmSlots), sn = em_slot(step + 1, kEmSlots);
+    const int la = phi_slot(step, kPhiSlots), lb = phi_slot(step + 1, kPhiSlots), ln = phi_slot(step + 2, kPhiSlots);
 
     const int x0 = seg * wid, gx = x0 - 3 + lane;
     const int own_x_hi = min(x0 + wid, r.nn[0]);
@@ -871,7 +876,7 @@ __device__ __forceinline__ void wave2d_body(const RunK<T> *__restrict__ rp, long
     unsigned as_l = r.as;
     const char *const b_rd = r.sb + (size_t)q_em(0, so, 0) * r.as;
     const char *const b_wr = r.sb + (size_t)q_em(0, sn, 0) * r.as;
-    const char *const b_ph = r.sb + (size_t)q_phi(0) * r.as;
+    const char *const b_ph = r.sb + (size_t)q_phi(kEmSlots, 0) * r.as;
     auto lde = [&](int kind, int c, unsigned o) __attribute__((always_inline)) -> T {
         return ldo((const T *)b_rd, (unsigned)(kind * 3 + c) * as_l + o);
     };
@@ -1547,8 +1552,8 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
     KW<T> r = make_kw(rp);
     constexpr int lo = pass_lane0(NS), W = pass_width(NS);
     const int lane = threadIdx.x & 63;
-    const int e_rd = em_slot(step), e_wr = em_slot(step + NS);
-    const int la = phi_slot(step), lb = phi_slot(step + 1);
+    const int e_rd = em_slot(step, kEmSlots), e_wr = em_slot(step + NS, kEmSlots);
+    const int la = phi_slot(step, kPhiSlots), lb = phi_slot(step + 1, kPhiSlots);
     const int ci = wp.ci;
     const bool store_e = __builtin_amdgcn_readfirstlane(wp.store_e) != 0;
     const int x0 = seg * W, gx = x0 - lo + lane;
@@ -1559,7 +1564,7 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
     unsigned as_l = r.as;
     const char *const b_rd = r.sb + (size_t)q_em(0, e_rd, 0) * r.as;
     const char *const b_wr = r.sb + (size_t)q_em(0, e_wr, 0) * r.as;
-    const char *const b_ph = r.sb + (size_t)q_phi(0) * r.as;
+    const char *const b_ph = r.sb + (size_t)q_phi(kEmSlots, 0) * r.as;
     auto lde = [&](int kind, int c, unsigned o) __attribute__((always_inline)) -> T {
         return ldo((const T *)b_rd, (unsigned)(kind * 3 + c) * as_l + o);
     };
@@ -1571,7 +1576,7 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
     auto off = [&](int p) __attribute__((always_inline)) -> unsigned { return bx + (unsigned)p * sxb; };
     // E/B of the intermediate steps n + 1 .. n + NS - 1 (ring wavefronts)
     auto stm = [&](int k, int kind, int c, unsigned o, T v) __attribute__((always_inline)) {
-        const char *b = r.sb + (size_t)q_em(0, em_slot(step + k + 1), 0) * r.as;
+        const char *b = r.sb + (size_t)q_em(0, em_slot(step + k + 1, kEmSlots), 0) * r.as;
         sto((T *)b, (unsigned)(kind * 3 + c) * as_l + o, v);
     };
 
@@ -1679,9 +1684,9 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
                 if (((ACT >> k) & 1) == 0) continue;
                 const bool rows = q >= c0 && q < c1;
                 if (MODE == kCores && rows && q >= core_y0[k] && q < core_y1[k] && core_x[k])
-                    stp(phi_slot(step + 2 + k), off(q), sg[k].pn);
+                    stp(phi_slot(step + 2 + k, kPhiSlots), off(q), sg[k].pn);
                 if (MODE == kCore && k == NS - 2 && rows)
-                    stp(phi_slot(step + 2 + k), off(q), sg[k].pn);
+                    stp(phi_slot(step + 2 + k, kPhiSlots), off(q), sg[k].pn);
                 // E of step n + 1, which the record of step n averages with
                 // E of step n (the ring stores it anyway; in one launch, only
                 // core 0 is the interior's alone)
@@ -1713,7 +1718,7 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
                         for (int c = 0; c < 3; c++) stm(k, 2, c, o, sg[k].e1h_2[c]);
 #pragma unroll
                         for (int c = 0; c < 3; c++) stm(k, 3, c, o, sg[k].b1n[c]);
-                        stp(phi_slot(step + 2 + k), o, sg[k].pn);
+                        stp(phi_slot(step + 2 + k, kPhiSlots), o, sg[k].pn);
                     }
                 }
             }
@@ -1734,7 +1739,7 @@ __device__ __forceinline__ void wave2d_pass_body(const RunK<T> *__restrict__ rp,
                 for (int c = 0; c < 3; c++) ste(2, c, o, sl.e1h_2[c]);
 #pragma unroll
                 for (int c = 0; c < 3; c++) ste(3, c, o, sl.b1n[c]);
-                stp(phi_slot(step + NS + 1), o, sl.pn);
+                stp(phi_slot(step + NS + 1, kPhiSlots), o, sl.pn);
             }
         }
     };

@@ -29,24 +29,30 @@ template <int D> __host__ __device__ constexpr bool actB0(int c) { return D == 3
 template <int D> __host__ __device__ constexpr bool actE1(int c) { return D >= 2 ? true : c != 0; }
 template <int D> __host__ __device__ constexpr bool actB1(int c) { return D >= 2 ? true : c != 0; }
 
-// Time levels rotate through slots: the E/B buffers and the Mur ghosts through
-// five (step n reads slot n mod 5, writes slot (n + 1) mod 5), the axion levels
-// and their ghosts through six (level L, the field at t = (L - 1/2) dt, in
-// slot L mod 6).  A pass of up to four steps reads the slots of step n while
-// its launches write those of steps n + 1 .. n + 4, all distinct.
-constexpr int kEmSlots = 5, kPhiSlots = 6;
-__host__ __device__ constexpr int em_slot(long step) { return (int)(step % kEmSlots); }
-__host__ __device__ constexpr int phi_slot(long level) { return (int)(level % kPhiSlots); }
+// Time levels rotate through slots: the E/B buffers and the Mur ghosts
+// through nem (step n reads slot n mod nem, writes slot (n + 1) mod nem), the
+// axion levels and their ghosts through nph (level L, the field at
+// t = (L - 1/2) dt, in slot L mod nph).  2D runs keep five and six: a pass of
+// up to four steps reads the slots of step n while its launches write those
+// of steps n + 1 .. n + 4, all distinct.  1D and 3D runs advance one step per
+// launch and keep two and three (the old and new E/B; the two axion levels a
+// step reads and the one it writes).
+constexpr int kEmSlots = 5, kPhiSlots = 6;      // the most a run keeps
+__host__ __device__ constexpr int em_slots_of(int D) { return D == 2 ? kEmSlots : 2; }
+__host__ __device__ constexpr int phi_slots_of(int D) { return D == 2 ? kPhiSlots : 3; }
+__host__ __device__ constexpr int em_slot(long step, int nem) { return (int)(step % nem); }
+__host__ __device__ constexpr int phi_slot(long level, int nph) { return (int)(level % nph); }
 
-// Uniform layout of a run's device buffer: 69 field arrays of equal size at
-// state_base + q * arr_stride (the 12 EM components of one slot together, then
-// the axion levels and the current scratch), and 216 boundary planes of equal
-// size at face_base + q * face_stride (some unused for a given configuration).
+// Uniform layout of a run's device buffer: 12 nem + nph + 3 field arrays of
+// equal size at state_base + q * arr_stride (the 12 EM components of one slot
+// together, slot after slot, then the axion levels and the current scratch),
+// and 216 boundary planes of equal size at face_base + q * face_stride (some
+// unused for a given configuration).
 constexpr int kEmPerSlot = 12;
 __host__ __device__ constexpr int q_em(int kind, int slot, int comp) { return slot * kEmPerSlot + kind * 3 + comp; }  // kind 0 E0, 1 B0, 2 E1, 3 B1
-__host__ __device__ constexpr int q_phi(int slot) { return kEmSlots * kEmPerSlot + slot; }
-__host__ __device__ constexpr int q_c(int comp) { return q_phi(kPhiSlots) + comp; }
-constexpr int kNumArrays = q_c(3);
+__host__ __device__ constexpr int q_phi(int nem, int slot) { return nem * kEmPerSlot + slot; }
+__host__ __device__ constexpr int q_c(int nem, int nph, int comp) { return q_phi(nem, nph) + comp; }
+__host__ __device__ constexpr int num_arrays(int nem, int nph) { return q_c(nem, nph, 3); }
 __host__ __device__ constexpr int q_axg(int d, int side, int slot) { return (d * 2 + side) * kPhiSlots + slot; }
 __host__ __device__ constexpr int q_mur(int o, int d, int side, int comp, int slot)
 {
@@ -67,6 +73,7 @@ constexpr long kSinkBytes = 65536;   // per-array store sink of 3D runs (128 wav
 template <typename T>
 struct RunK {
     int D;
+    int nem, nph;             // E/B and axion time-level slots (em_slots_of, phi_slots_of)
     int n[3], nn[3];          // cells, storage extents (n + 1 on Mur axes)
     int mur[3], axbc[3];
     long sx, sy;              // element strides of j and k

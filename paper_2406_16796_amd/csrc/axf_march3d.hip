@@ -279,8 +279,9 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     // array stride in units of 256 bytes (arrays are 256-byte aligned and sized)
     const unsigned long long as64 = (unsigned long long)rp->arr_stride;
     unsigned as_l = (unsigned)(rp->arr_stride >> 8);
-    const int so = em_slot(step), sn = em_slot(step + 1);
-    const int la = phi_slot(step), lb = phi_slot(step + 1), ln = phi_slot(step + 2);
+    const int nem = rp->nem, nph = rp->nph;
+    const int so = em_slot(step, nem), sn = em_slot(step + 1, nem);
+    const int la = phi_slot(step, nph), lb = phi_slot(step + 1, nph), ln = phi_slot(step + 2, nph);
 
     // ---- this workgroup's segment, row group and plane chunk
     int seg, ygr, zch;
@@ -357,7 +358,7 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     auto abase = [&](int q) __attribute__((always_inline)) { return sb + ((unsigned long long)((unsigned)q * as_l) << 8); };
     auto kb_rd = [&](int kind) __attribute__((always_inline)) { return abase(q_em(kind, so, 0)); };
     auto kb_wr = [&](int kind) __attribute__((always_inline)) { return abase(q_em(kind, sn, 0)); };
-    auto arr_ph = [&](int L) __attribute__((always_inline)) { return abase(q_phi(L)); };
+    auto arr_ph = [&](int L) __attribute__((always_inline)) { return abase(q_phi(nem, L)); };
     auto ld = [&](const char *kb, int c, unsigned off) __attribute__((always_inline)) -> T { return m3::ldo<T>(kb + c * as64, off); };
     auto st = [&](const char *kb, int c, unsigned off, T v) __attribute__((always_inline)) { m3::sto<T>(kb + c * as64, off, v); };
 

@@ -107,7 +107,7 @@ template <int D, typename T>
 __device__ __forceinline__ void e0c_at(const RunK<T>& r, int i, int j, int k, long step)
 {
     const long id = lin(r, i, j, k);
-    const int so = em_slot(step), sn = em_slot(step + 1), la = phi_slot(step), lb = phi_slot(step + 1);
+    const int so = em_slot(step, r.nem), sn = em_slot(step + 1, r.nem), la = phi_slot(step, r.nph), lb = phi_slot(step + 1, r.nph);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         if (!actE0<D>(c) || !in_E<D>(r, c, i, j, k)) continue;
@@ -156,7 +156,7 @@ template <int D, typename T>
 __device__ __forceinline__ void e0c_walk_at(const RunK<T>& r, int i, int j, int k, long step, T& ez_up, bool& have)
 {
     const long id = lin(r, i, j, k);
-    const int so = em_slot(step), sn = em_slot(step + 1), la = phi_slot(step), lb = phi_slot(step + 1);
+    const int so = em_slot(step, r.nem), sn = em_slot(step + 1, r.nem), la = phi_slot(step, r.nph), lb = phi_slot(step + 1, r.nph);
     T own[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -271,7 +271,7 @@ __device__ __forceinline__ void mur_point(const RunK<T>& r, long step, int d, in
         int ext = (e == c) ? r.nn[e] : r.n[e];
         if (id3[e] >= ext) return;
     }
-    const int s_old = em_slot(step), s_new = em_slot(step + 1);
+    const int s_old = em_slot(step, r.nem), s_new = em_slot(step + 1, r.nem);
     long id = lin(r, id3[0], id3[1], id3[2]);
     long f = face_index(r, d, id3[0], id3[1], id3[2]);
     T *const *Eo = O == 0 ? r.E0[s_old] : r.E1[s_old];
@@ -364,7 +364,7 @@ template <int D, typename T>
 __device__ __forceinline__ void b_at(const RunK<T>& r, int i, int j, int k, long step)
 {
     long id = lin(r, i, j, k);
-    const int so = em_slot(step), sn = em_slot(step + 1);
+    const int so = em_slot(step, r.nem), sn = em_slot(step + 1, r.nem);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         if (!in_B<D>(r, c, i, j, k)) continue;
@@ -408,8 +408,8 @@ __device__ __forceinline__ void phi_at(const RunK<T>& r, int i, int j, int k, lo
 {
     if (!in_cell(r, i, j, k)) return;
     long id = lin(r, i, j, k);
-    const int so = em_slot(step), sn = em_slot(step + 1);
-    const int la = phi_slot(step), lb = phi_slot(step + 1), ln = phi_slot(step + 2);
+    const int so = em_slot(step, r.nem), sn = em_slot(step + 1, r.nem);
+    const int la = phi_slot(step, r.nph), lb = phi_slot(step + 1, r.nph), ln = phi_slot(step + 2, r.nph);
     T e[3], b[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -553,8 +553,8 @@ __device__ __forceinline__ void diag_point(const RunK<T>& r, long p, long step, 
     int i, j, k;
     if (decompose(r, p, i, j, k)) {
         long id = lin(r, i, j, k);
-        const int so = em_slot(step), sn = em_slot(step + 1);
-        const int la = phi_slot(step), lb = phi_slot(step + 1);
+        const int so = em_slot(step, r.nem), sn = em_slot(step + 1, r.nem);
+        const int la = phi_slot(step, r.nph), lb = phi_slot(step + 1, r.nph);
         bool fin = true;
         if (in_cell(r, i, j, k)) {
             const T *A = r.phi[la], *Bp = r.phi[lb];
@@ -765,7 +765,7 @@ k3_tile(const RunK<T> *__restrict__ rp, long step, int tz)
     const int i = blockIdx.x * kTX + (threadIdx.x & (kTX - 1));
     const int j = blockIdx.y * kTY + (threadIdx.x / kTX);
     if (i >= r.nn[0] || j >= r.nn[1]) return;
-    const int so = em_slot(step), sn = em_slot(step + 1);
+    const int so = em_slot(step, r.nem), sn = em_slot(step + 1, r.nem);
     const int k0 = blockIdx.z * tz, k1 = min(k0 + tz, r.nn[2]);
     T ez_up = T(0);
     bool have = false;
@@ -790,7 +790,7 @@ template <int D, typename T, int PH>
 __device__ __forceinline__ void kb_volume_run(const RunK<T> *__restrict__ rp, long bx, long step)
 {
     const RunK<T>& r = *rp;
-    const int so = em_slot(step), sn = em_slot(step + 1), la = phi_slot(step), lb = phi_slot(step + 1);
+    const int so = em_slot(step, r.nem), sn = em_slot(step + 1, r.nem), la = phi_slot(step, r.nph), lb = phi_slot(step + 1, r.nph);
     if (PH == kPhE0) e0_body<D, T>(r, bx, so, so, sn, T(1));
     else if (PH == kPhC) c_body<D, T>(r, bx, la, lb, so, sn, so, 0);
     else if (PH == kPhE0C) e0c_body<D, T>(r, bx, step);

@@ -18,6 +18,7 @@ struct Layout {
     size_t off_state;            // start of the checkpointed region
     size_t off_arrays, arr_stride, off_faces, face_stride;
     size_t arr_sink;             // start of an array's store sink (3D), from the array's start
+    int nem, nph;                // time-level slots of the E/B arrays and of the axion levels
     long off_em[4][kEmSlots][3];        // [E0,B0,E1,B1][slot][component]
     long off_phi[kPhiSlots];
     long off_c[3];

@@ -141,14 +141,17 @@ Layout make_layout(const axf_config *c)
     // that every iteration issues the same memory instructions)
     L.arr_sink = (size_t)round_up((long)L.arr_bytes, 256);
     L.arr_stride = L.arr_sink + (D == 3 ? kSinkBytes : 0);
+    L.nem = em_slots_of(D);
+    L.nph = phi_slots_of(D);
     L.off_arrays = off;
-    off += L.arr_stride * kNumArrays;
+    off += L.arr_stride * num_arrays(L.nem, L.nph);
+    // (entries of slots a run does not keep alias the slots it does; nothing reads them)
     for (int kind = 0; kind < 4; kind++)
         for (int s = 0; s < kEmSlots; s++)
             for (int comp = 0; comp < 3; comp++)
-                L.off_em[kind][s][comp] = act(kind, comp) ? (long)(L.off_arrays + L.arr_stride * q_em(kind, s, comp)) : -1;
-    for (int s = 0; s < kPhiSlots; s++) L.off_phi[s] = (long)(L.off_arrays + L.arr_stride * q_phi(s));
-    for (int comp = 0; comp < 3; comp++) L.off_c[comp] = (long)(L.off_arrays + L.arr_stride * q_c(comp));
+                L.off_em[kind][s][comp] = act(kind, comp) ? (long)(L.off_arrays + L.arr_stride * q_em(kind, s % L.nem, comp)) : -1;
+    for (int s = 0; s < kPhiSlots; s++) L.off_phi[s] = (long)(L.off_arrays + L.arr_stride * q_phi(L.nem, s % L.nph));
+    for (int comp = 0; comp < 3; comp++) L.off_c[comp] = (long)(L.off_arrays + L.arr_stride * q_c(L.nem, L.nph, comp));
     // boundary planes exist only normal to the active axes
     size_t fmax = 0;
     for (int d = 0; d < D; d++) {
@@ -187,6 +190,8 @@ static void fill_runk(RunK<T>& k, const axf_config *c, const Layout& L, char *ba
     memset((void *)&k, 0, sizeof k);
     const int D = c->ndim;
     k.D = D;
+    k.nem = L.nem;
+    k.nph = L.nph;
     for (int d = 0; d < 3; d++) {
         k.n[d] = L.n[d];
         k.nn[d] = L.nn[d];
@@ -312,7 +317,7 @@ static void e_phase(Run *R)
     const RunK<T>& h = R->hk<T>();
     const RunK<T> *rk = R->rk<T>();
     long s = R->step;
-    int so = em_slot(s), sn = em_slot(s + 1), la = phi_slot(s), lb = phi_slot(s + 1);
+    int so = em_slot(s, h.nem), sn = em_slot(s + 1, h.nem), la = phi_slot(s, h.nph), lb = phi_slot(s + 1, h.nph);
     P::e0(rk, h, so, so, sn, T(1), R->stream);
     P::c(rk, h, la, lb, so, sn, so, 0, R->stream);
     P::e1(rk, h, so, so, sn, T(1), R->stream);
@@ -337,7 +342,7 @@ static void steps_plain(Run *R, int64_t nsteps)
     hipStream_t st = R->stream;
     for (int64_t it = 0; it < nsteps; it++) {
         long s = R->step;
-        int so = em_slot(s), sn = em_slot(s + 1), la = phi_slot(s), lb = phi_slot(s + 1);
+        int so = em_slot(s, h.nem), sn = em_slot(s + 1, h.nem), la = phi_slot(s, h.nph), lb = phi_slot(s + 1, h.nph);
         ensure_incident<D, T>(R, s);
         P::e0(rk, h, so, so, sn, T(1), st);
         P::c(rk, h, la, lb, so, sn, so, 0, st);
@@ -377,7 +382,7 @@ static void steps_semi(Run *R, int64_t nsteps)
     const bool tiled = D == 3 && (te ? te[0] == '1' : waste_ok);
     for (int64_t it = 0; it < nsteps; it++) {
         long s = R->step;
-        int so = em_slot(s), sn = em_slot(s + 1);
+        int so = em_slot(s, h.nem), sn = em_slot(s + 1, h.nem);
         ensure_incident<D, T>(R, s);
         if (tiled) {
             P::tiled_step(rk, h, s, R->chunk, st);
@@ -733,12 +738,12 @@ int run_read_field(Run *R, int id, void *dst, size_t dst_bytes, int dst_is_devic
     std::vector<double> out(cnt, 0.0), tmp;
     long s = R->step;
     if (kind == 4) {
-        int slot = phi_slot(s + comp);
+        int slot = phi_slot(s + comp, R->L.nph);
         HIPCHK(hipStreamSynchronize(R->stream));
         if ((rc = fetch(R, array_ptr(R, 4, 0, slot), out))) return rc;
     } else if (array_ptr(R, kind, comp, 0)) {
         bool is_e = (kind == 0 || kind == 2);
-        int so = em_slot(s), sn = em_slot(s + 1);
+        int so = em_slot(s, R->L.nem), sn = em_slot(s + 1, R->L.nem);
         if (is_e && R->converted && R->ephase_step != s) {
             AXF_DISPATCH(R, e_phase, R);
             R->ephase_step = s;

@@ -32,14 +32,27 @@ def test_footprint_and_extents_follow_the_layout():
     assert nn == (65, 65, 65)               # Mur axes carry the extra node plane
     f32 = axf.footprint(cfg, precision=axf.F32)
     f64 = axf.footprint(cfg, precision=axf.F64)
-    # 12 EM arrays x 5 time slots + 6 axion levels + 3 scratch, rows padded to
-    # whole 128-byte lines: 96 floats, 80 doubles; in 3D each array is followed
-    # by a 64 KiB sink for the stores of points a march wavefront does not own
+    # 3D keeps 2 time slots of the 12 EM arrays + 3 axion levels + 3 scratch,
+    # rows padded to whole 128-byte lines: 96 floats, 80 doubles; each array
+    # is followed by a 64 KiB sink for the stores of points a march wavefront
+    # does not own
     arr32, arr64 = 96 * 65 * 65 * 4 + 65536, 80 * 65 * 65 * 8 + 65536
-    assert 69 * arr32 <= f32 < 74 * arr32      # + 216 boundary planes, diagnostics
-    assert 69 * arr64 <= f64 < 74 * arr64
+    assert 30 * arr32 <= f32 < 35 * arr32      # + 216 boundary planes, diagnostics
+    assert 30 * arr64 <= f64 < 35 * arr64
     one_d = W.plane_wave_1d(nx=1000)
     assert axf.extents(one_d) == (1001, 1, 1)
+    # 2D keeps 5 slots and 6 levels (its passes write up to four steps ahead)
+    two_d = W.gaussian_2d(n=256)
+    arr2 = 272 * 256 * 4
+    assert 69 * arr2 <= axf.footprint(two_d, precision=axf.F32) < 80 * arr2
+
+
+def test_512_cubed_fp32_footprint():
+    """The 512^3 FP32 run: 30 arrays of 544 x 513 x 513 floats (17.2 GB) and
+    the boundary planes; 1D and 3D runs keep two E/B slots and three axion
+    levels, 2D runs five and six."""
+    b = axf.footprint(W.focused_3d(), precision=axf.F32)
+    assert 30 * 544 * 513 * 513 * 4 < b < 17.6e9, b
 
 
 @pytest.mark.parametrize("mutate,code", [
