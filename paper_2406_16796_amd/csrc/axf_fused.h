@@ -88,6 +88,7 @@ bool march3d_available(const RunK<T>& h);
 template <typename T>
 long march3d_blocks(const RunK<T>& h, int zc);
 template <typename T>
-hipError_t launch_march3d(const RunK<T> *rk, const RunK<T>& h, long step, int zc, hipStream_t st);
+hipError_t launch_march3d(const RunK<T> *rk, const RunK<T>& h, long step, int zc, hipStream_t st,
+                          const WaveStreams *ws);
 
 }  // namespace axf

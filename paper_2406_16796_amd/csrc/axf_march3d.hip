@@ -437,13 +437,46 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     T Pxb0x = T(0), Pxb0z = T(0);      // B0x, B0z of the row above (the highest wavefront)
     T Pxpa = T(0), Pxpb = T(0);        // both axion levels of the row below (the lowest)
     T Pxpa_f = T(0), Pxpb_f = T(0);    // ... their x ghost values (frame launch)
+    // FP32 issues the loads of iteration t two iterations ahead, into one of
+    // two staging sets (by the parity of t), and moves them into the windows
+    // when t begins: an iteration then waits only for the loads, and the
+    // stores before them, issued two iterations earlier.  FP64 has no
+    // registers to spare and loads one iteration ahead straight into the
+    // windows.
+    constexpr int PD = sizeof(T) == 4 ? 2 : 1;
+    struct Stage {
+        T b0[3], e0[3], b1[3], e1[3];
+        PhiRaw pa, pb;
+        T xb0x, xb0z, xpa, xpb, xpa_f, xpb_f;
+    };
+    Stage stg[PD];
+#pragma unroll
+    for (int k = 0; k < PD; k++) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) stg[k].b0[c] = stg[k].e0[c] = stg[k].b1[c] = stg[k].e1[c] = T(0);
+        stg[k].pa = stg[k].pb = PhiRaw{T(0), T(0)};
+        stg[k].xb0x = stg[k].xb0z = stg[k].xpa = stg[k].xpb = stg[k].xpa_f = stg[k].xpb_f = T(0);
+    }
 
     // first and last iterations of the march, and the iterations each load
     // group and stage is needed in (no owned value depends on the others)
     const int i_first = z0 - 2, i_last = z1 + 3;
-    // the loads taken in by iteration t (ring slots of t)
+    // the loads taken in by iteration t: into its ring slots (Sc = the slot
+    // of t mod 4) or, two iterations ahead, into staging set Sc mod 2
     auto prefetch = [&](int t, auto Sc) __attribute__((always_inline)) {
         constexpr int S4 = decltype(Sc)::value & 3, S2 = decltype(Sc)::value & 1;
+        T (&db0)[3] = PD == 2 ? stg[S2 % PD].b0 : b0r[S4];
+        T (&de0)[3] = PD == 2 ? stg[S2 % PD].e0 : e0r[S2];
+        T (&db1)[3] = PD == 2 ? stg[S2 % PD].b1 : b1r[S4];
+        T (&de1)[3] = PD == 2 ? stg[S2 % PD].e1 : e1r[S2];
+        PhiRaw &dpa = PD == 2 ? stg[S2 % PD].pa : Ppa;
+        PhiRaw &dpb = PD == 2 ? stg[S2 % PD].pb : Ppb;
+        T &dxb0x = PD == 2 ? stg[S2 % PD].xb0x : Pxb0x;
+        T &dxb0z = PD == 2 ? stg[S2 % PD].xb0z : Pxb0z;
+        T &dxpa = PD == 2 ? stg[S2 % PD].xpa : Pxpa;
+        T &dxpb = PD == 2 ? stg[S2 % PD].xpb : Pxpb;
+        T &dxpa_f = PD == 2 ? stg[S2 % PD].xpa_f : Pxpa_f;
+        T &dxpb_f = PD == 2 ? stg[S2 % PD].xpb_f : Pxpb_f;
         asm volatile("" : "+s"(as_l));
         auto need = [&](int lo, int hi) __attribute__((always_inline)) { return !GEN || (t >= lo && t <= hi); };
         if (need(-(1 << 30), z1 + 1)) {          // B0 of plane t, axion levels of plane t - 1
@@ -451,39 +484,39 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
             const int pz = clampz(t, z0 - 2, z1 + 1), pp = clampz(t - 1, z0 - 3, z1);
             const unsigned o = off_em(pz);
 #pragma unroll
-            for (int c = 0; c < 3; c++) b0r[S4][c] = ld(kb, c, o);
-            Ppa = phi_load(la, ycl_w, ys_ph_w, pp);
-            Ppb = phi_load(lb, ycl_w, ys_ph_w, pp);
+            for (int c = 0; c < 3; c++) db0[c] = ld(kb, c, o);
+            dpa = phi_load(la, ycl_w, ys_ph_w, pp);
+            dpb = phi_load(lb, ycl_w, ys_ph_w, pp);
             if (!GEN || w == NW - 1) {       // (every wavefront of the interior launch loads the extra rows)
                 const unsigned ox = xo_em + yo_em_up + (unsigned)zs_em(pz) * syb;
-                Pxb0x = ld(kb, 0, ox);
-                Pxb0z = ld(kb, 2, ox);
+                dxb0x = ld(kb, 0, ox);
+                dxb0z = ld(kb, 2, ox);
             }
             if (!GEN || w == 0) {
                 const PhiRaw ra = phi_load(la, ycl_dn, ys_ph_dn, pp), rb = phi_load(lb, ycl_dn, ys_ph_dn, pp);
-                Pxpa = ra.a;
-                Pxpb = rb.a;
-                Pxpa_f = ra.fx;
-                Pxpb_f = rb.fx;
+                dxpa = ra.a;
+                dxpb = rb.a;
+                dxpa_f = ra.fx;
+                dxpb_f = rb.fx;
             }
         }
         if (need(z0 - 1, z1 + 1)) {              // E0^{n-1/2} of plane t - 1
             const char *kb = kb_rd(0);
             const unsigned o = off_em(clampz(t - 1, z0 - 2, z1));
 #pragma unroll
-            for (int c = 0; c < 3; c++) e0r[S2][c] = ld(kb, c, o);
+            for (int c = 0; c < 3; c++) de0[c] = ld(kb, c, o);
         }
         if (need(z0 + 1, z1 + 2)) {              // B1 of plane t - 2
             const char *kb = kb_rd(3);
             const unsigned o = off_em(clampz(t - 2, z0 - 1, z1));
 #pragma unroll
-            for (int c = 0; c < 3; c++) b1r[S4][c] = ld(kb, c, o);
+            for (int c = 0; c < 3; c++) db1[c] = ld(kb, c, o);
         }
         if (need(z0 + 2, z1 + 2)) {              // E1^{n-1/2} of plane t - 3
             const char *kb = kb_rd(2);
             const unsigned o = off_em(clampz(t - 3, z0 - 1, z1 - 1));
 #pragma unroll
-            for (int c = 0; c < 3; c++) e1r[S2][c] = ld(kb, c, o);
+            for (int c = 0; c < 3; c++) de1[c] = ld(kb, c, o);
         }
     };
 
@@ -536,7 +569,26 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
         auto LR1 = [&](int q, int s, int d) __attribute__((always_inline)) -> T { return lds[lidx(q, s, d) + 1]; };
         auto LRm = [&](int q, int s, int d) __attribute__((always_inline)) -> T { return lds[lidx(q, s, d) - 1]; };
 
-        // ---- take in the axion levels and extra rows, then load for iteration i + 1
+        // ---- FP32: move this iteration's staged loads into the windows
+        if constexpr (PD == 2) {
+            const Stage &sg = stg[J & 1];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                b0r[Q0][c] = sg.b0[c];
+                e0r[H0][c] = sg.e0[c];
+                b1r[Q0][c] = sg.b1[c];
+                e1r[H0][c] = sg.e1[c];
+            }
+            Ppa = sg.pa;
+            Ppb = sg.pb;
+            Pxb0x = sg.xb0x;
+            Pxb0z = sg.xb0z;
+            Pxpa = sg.xpa;
+            Pxpb = sg.xpb;
+            Pxpa_f = sg.xpa_f;
+            Pxpb_f = sg.xpb_f;
+        }
+        // ---- take in the axion levels and extra rows, then load for iteration i + PD
         // the axion levels of this row: the interior launch keeps planes i - 3,
         // i - 4 of the older level and i - 5 of the newer in registers and reads
         // the others from its own LDS row (the two reads below take the slots
@@ -564,7 +616,7 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
             LW(LQ::B0X, L40, 1, Pxb0x);
             LW(LQ::B0Z, L40, 1, Pxb0z);
         }
-        if (!GEN || i < i_last) prefetch(i + 1, std::integral_constant<int, (J + 1) & 3>{});
+        if (!GEN || i + PD <= i_last) prefetch(i + PD, std::integral_constant<int, (J + PD) & 3>{});
 
         // ---- loaded values the neighbouring rows read
         LW(LQ::B1X, L20, 0, b1r[Q0][0]);
@@ -1082,6 +1134,7 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     };
 
     prefetch(i_first, std::integral_constant<int, 0>{});
+    if (PD == 2 && (!GEN || i_first + 1 <= i_last)) prefetch(i_first + 1, std::integral_constant<int, 1>{});
     for (;;) {
         iter(std::integral_constant<int, 0>{});
         if (++i > i_last) break;
@@ -1189,11 +1242,13 @@ static hipError_t march3d_attr()
     return hipSuccess;
 }
 
-// the interior launch, the x-face launch, then the frame launch, on the
-// run's stream (all read only the state of step n and write disjoint owned
-// points)
+// the interior launch on the run's stream and the x-face and frame launches
+// after it, or beside it on ws->side when given (all three read only the
+// state of step n and write disjoint owned points, so they may run in any
+// order or together; the side launches then fill the interior's last round)
 template <typename T>
-hipError_t launch_march3d(const RunK<T> *rk, const RunK<T>& h, long step, int zc, hipStream_t st)
+hipError_t launch_march3d(const RunK<T> *rk, const RunK<T>& h, long step, int zc, hipStream_t st,
+                          const WaveStreams *ws)
 {
     constexpr int NW = March3<T>::NW;
     using LQ = M3Lds<T, NW>;
@@ -1204,17 +1259,31 @@ hipError_t launch_march3d(const RunK<T> *rk, const RunK<T>& h, long step, int zc
     const M3Geom g = march3d_geom(h, zc);
     long ni, nx, nf;
     march3d_counts<T>(g, &ni, &nx, &nf);
+    const bool fork = ws && ws->side && ni > 0 && nx + nf > 0;
+    hipStream_t se = st;
+    if (fork) {
+        if ((e = hipEventRecord(ws->fork, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ws->side, ws->fork, 0)) != hipSuccess) return e;
+        se = ws->side;
+    }
     if (ni > 0) hipLaunchKernelGGL((k_march3d<T, NW, 0>), dim3((unsigned)ni), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
-    if (nx > 0) hipLaunchKernelGGL((k_march3d<T, NW, 1>), dim3((unsigned)nx), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
-    if (nf > 0) hipLaunchKernelGGL((k_march3d<T, NW, 2>), dim3((unsigned)nf), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
-    return hipGetLastError();
+    if (nx > 0) hipLaunchKernelGGL((k_march3d<T, NW, 1>), dim3((unsigned)nx), dim3(64 * NW), LQ::BYTES, se, rk, step, g);
+    if (nf > 0) hipLaunchKernelGGL((k_march3d<T, NW, 2>), dim3((unsigned)nf), dim3(64 * NW), LQ::BYTES, se, rk, step, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (fork) {
+        if ((e = hipEventRecord(ws->join, ws->side)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(st, ws->join, 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template bool march3d_available<float>(const RunK<float>&);
 template bool march3d_available<double>(const RunK<double>&);
 template long march3d_blocks<float>(const RunK<float>&, int);
 template long march3d_blocks<double>(const RunK<double>&, int);
-template hipError_t launch_march3d<float>(const RunK<float> *, const RunK<float>&, long, int, hipStream_t);
-template hipError_t launch_march3d<double>(const RunK<double> *, const RunK<double>&, long, int, hipStream_t);
+template hipError_t launch_march3d<float>(const RunK<float> *, const RunK<float>&, long, int, hipStream_t,
+                                          const WaveStreams *);
+template hipError_t launch_march3d<double>(const RunK<double> *, const RunK<double>&, long, int, hipStream_t,
+                                           const WaveStreams *);
 
 }  // namespace axf

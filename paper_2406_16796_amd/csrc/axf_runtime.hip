@@ -408,10 +408,24 @@ static int steps_march3d(Run *R, int64_t nsteps)
 {
     const RunK<T>& h = R->hk<T>();
     const RunK<T> *rk = R->rk<T>();
+    // the x-face and frame launches beside the interior one on a second
+    // stream (AXF_M3_SIDE=0: all three on the run's stream)
+    WaveStreams ws{nullptr, nullptr, nullptr};
+    const char *sidee = getenv("AXF_M3_SIDE");
+    if (!(sidee && sidee[0] == '0')) {
+        if (!R->side) {
+            HIPCHK(hipStreamCreateWithFlags(&R->side, hipStreamNonBlocking));
+            HIPCHK(hipStreamCreateWithFlags(&R->ring, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&R->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&R->ev_join, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&R->ev_ring, hipEventDisableTiming));
+        }
+        ws = WaveStreams{R->side, R->ev_fork, R->ev_join};
+    }
     for (int64_t it = 0; it < nsteps; it++) {
         long s = R->step;
         ensure_incident<D, T>(R, s);
-        hipError_t e = launch_march3d<T>(rk, h, s, R->m3_chunk, R->stream);
+        hipError_t e = launch_march3d<T>(rk, h, s, R->m3_chunk, R->stream, ws.side ? &ws : nullptr);
         if (e != hipSuccess) return hip_fail(e, "3D march launch");
         if (R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0) {
             Plain<D, T>::diag(rk, h, s, R->rec_written % h.rec_cap, R->stream);
