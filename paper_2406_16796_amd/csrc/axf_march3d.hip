@@ -363,6 +363,9 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     auto st = [&](const char *kb, int c, unsigned off, T v) __attribute__((always_inline)) { m3::sto<T>(kb + c * as64, off, v); };
 
     int i = z0 - 2;   // the iteration (first: z0 - 2, last: z1 + 3)
+    // mode 1: first elements of the laser table's levels of t_n and t_n+1
+    const long inc_lv0 = (step % rp->inc_k1) * 2 * rp->inc_face;
+    const long inc_lv1 = ((step + 1) % rp->inc_k1) * 2 * rp->inc_face;
 
     // ---- LDS: row w + d of quantity q at slot s (a compile-time value in
     // each unrolled iteration)
@@ -543,9 +546,8 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
         if (O == 0) {
             const bool use = xside == 0 && rp->las.on && c == rp->las.pol;
             const char *tb = use ? (const char *)rp->inc : rp->face_base;
-            const long k1 = rp->inc_k1, fc = rp->inc_face;
-            const long lo = use ? (step % k1) * 2 * fc + f : 0, ln = use ? ((step + 1) % k1) * 2 * fc + f : 0;
-            const long fo = use ? fc : 0;
+            const long lo = use ? inc_lv0 + f : 0, ln = use ? inc_lv1 + f : 0;
+            const long fo = use ? rp->inc_face : 0;
             const double a0 = m3::sld<double>(tb, lo), a1 = m3::sld<double>(tb, lo + fo);
             const double a2 = m3::sld<double>(tb, ln), a3 = m3::sld<double>(tb, ln + fo);
             ia_o = use ? a0 : 0.0;
