@@ -108,6 +108,17 @@ typedef struct {
     /* execution */
     int32_t diag_every;      /* record energies every k steps (0: only on request) */
     int32_t path;            /* AXF_PATH_*: step kernels to use */
+    /* moving window (Sec. III.B: the window follows the laser at c once it is
+       in).  win_cells = 0: a fixed window.  Otherwise, before step n, once
+       n dt >= win_t0, the window has moved win_cells * floor((n dt - win_t0) /
+       (win_cells dx)) columns along +x: every field shifts left, new columns
+       are vacuum, B_ext's slab stays where it is in the lab (it moves left in
+       the window) and the laser is no longer injected; the x_min ghosts take
+       the values that lay there before a move, the x_max ghosts are vacuum.
+       Needs a Mur x axis, 1 <= win_cells <= 64, win_cells < n[0] and
+       win_t0 >= dt; single runs only (not batches or served requests). */
+    double  win_t0;
+    int32_t win_cells;
 } axf_config;
 
 /* one diagnostic record at integer time t = step * dt, all FP64, descaled

@@ -83,8 +83,12 @@ struct ora_state {
     double *mur_a[2][3][2][3];     /* E at the interior centre next to that ghost, t_n - dt/2 */
     double *C[3];                  /* scratch: (D_t phi) B0 - E0 x grad phi at centres */
     double *Sax;                   /* scratch: g E0.B0 at centres */
+    double *Eh[2][3];              /* E at t_n - dt/2 on the first ORA_WIN_KEEP x columns (window moves) */
     long   step;
 };
+
+/* columns of E^{n-1/2} kept for a move of the window (the most one move shifts) */
+#define ORA_WIN_KEEP 64
 
 /* ---------------------------------------------------------------- helpers */
 
@@ -503,6 +507,18 @@ static void axion_ghosts(ora_state *s, int La, int Lb, int Ln)
     }
 }
 
+/* E^{n+1/2} of the first ORA_WIN_KEEP x columns, both orders */
+static void keep_half_columns(ora_state *s)
+{
+    const int kc = s->nn[0] < ORA_WIN_KEEP ? s->nn[0] : ORA_WIN_KEEP;
+    for (int o = 0; o < 2; o++)
+        for (int c = 0; c < 3; c++)
+            for (int k = 0; k < s->nn[2]; k++)
+                for (int j = 0; j < s->nn[1]; j++)
+                    for (int i = 0; i < kc; i++)
+                        s->Eh[o][c][((long)k * s->nn[1] + j) * ORA_WIN_KEEP + i] = s->E[o][c][IX(s, i, j, k)];
+}
+
 /* ------------------------------------------------------------ one step */
 
 static void one_step(ora_state *s)
@@ -513,6 +529,7 @@ static void one_step(ora_state *s)
     compute_C(s, La, Lb, -1);      /* axion current at t_n (uses E0^n, B0^n) */
     update_E(s, 0, h, 0.0);        /* E0^{n+1/2} */
     update_E(s, 1, h, g);          /* E1^{n+1/2}, eq. update_E */
+    keep_half_columns(s);          /* for a move of the window at t_{n+1} */
     mur_ghosts(s);                 /* tangential E ghosts at t_{n+1/2} */
     update_B(s, h);                /* B^{n+1/2} */
     compute_Sax(s);                /* g E0.B0 at t_{n+1/2} */
@@ -534,6 +551,77 @@ void ora_step(ora_state *s, long nsteps)
 }
 
 long ora_step_count(const ora_state *s) { return s->step; }
+
+/* ------------------------------------------------------------ moving window */
+
+/* shift rows of length m (x fastest, `rows` of them) left by `cells`, vacuum after */
+static void shift_rows(double *a, long rows, int m, int cells)
+{
+    if (!a) return;
+    #pragma omp parallel for schedule(static)
+    for (long r = 0; r < rows; r++) {
+        double *row = a + r * m;
+        for (int i = 0; i < m; i++) row[i] = i + cells < m ? row[i + cells] : 0.0;
+    }
+}
+
+/* Sec. III.B: the simulation window moves along +x at c once the laser is
+   in.  One move by `cells` columns at a step boundary: every field array and
+   every plane of the y and z faces shifts left by `cells` columns, the new
+   columns at x_max are vacuum, the B_ext slab and the laser (no longer
+   injected) are taken in window coordinates.  The x_min ghosts become the
+   values that lay there before the move: the Mur ghost and its adjacent
+   history the E^{n-1/2} of columns cells - 1 and cells, the axion ghosts both
+   levels of cell cells - 1; the x_max ghosts are vacuum.
+   Needs a Mur x axis, 1 <= cells <= ORA_WIN_KEEP, cells < n_x, and at least
+   one step taken (E^{n-1/2}).  Returns 0, or -1 for such a bad request. */
+int ora_shift_window(ora_state *s, int cells)
+{
+    if (s->c.em_bc[0] != ORA_EM_MUR || cells < 1 || cells > ORA_WIN_KEEP || cells >= s->n[0] || s->step < 1)
+        return -1;
+    const int m = s->nn[0];
+    const long rows = (long)s->nn[1] * s->nn[2];
+    /* x faces first, from the columns before the move */
+    for (int k = 0; k < s->nn[2]; k++)
+        for (int j = 0; j < s->nn[1]; j++) {
+            const long f = (long)k * s->nn[1] + j;
+            for (int o = 0; o < 2; o++)
+                for (int c = 1; c < 3; c++) {
+                    const double *eh = s->Eh[o][c] + f * ORA_WIN_KEEP;
+                    s->mur_g[o][0][0][c][f] = eh[cells - 1];
+                    s->mur_a[o][0][0][c][f] = eh[cells];
+                    s->mur_g[o][0][1][c][f] = 0.0;
+                    s->mur_a[o][0][1][c][f] = 0.0;
+                }
+            if (!ax_periodic(s, 0) && j < s->n[1] && k < s->n[2])
+                for (int L = 0; L < 3; L++) {
+                    s->axg[0][0][L][f] = s->phi[L][IX(s, cells - 1, j, k)];
+                    s->axg[0][1][L][f] = 0.0;
+                }
+        }
+    for (int o = 0; o < 2; o++)
+        for (int c = 0; c < 3; c++) {
+            shift_rows(s->E[o][c], rows, m, cells);
+            shift_rows(s->B[o][c], rows, m, cells);
+        }
+    for (int L = 0; L < 3; L++) shift_rows(s->phi[L], rows, m, cells);
+    /* the planes of the y and z faces: rows along x */
+    for (int d = 1; d < 3; d++) {
+        const int b = d == 2 ? 1 : 2;
+        for (int side = 0; side < 2; side++) {
+            for (int L = 0; L < 3; L++) shift_rows(s->axg[d][side][L], s->nn[b], m, cells);
+            for (int o = 0; o < 2; o++)
+                for (int c = 0; c < 3; c++) {
+                    shift_rows(s->mur_g[o][d][side][c], s->nn[b], m, cells);
+                    shift_rows(s->mur_a[o][d][side][c], s->nn[b], m, cells);
+                }
+        }
+    }
+    s->c.slab_lo -= cells;
+    s->c.slab_hi -= cells;
+    s->c.laser_on = 0;
+    return 0;
+}
 
 /* ------------------------------------------------------------ energies */
 
@@ -677,6 +765,8 @@ int ora_create(const ora_config *cfg, ora_state **out)
     for (int L = 0; L < 3; L++) s->phi[L] = zalloc(s->ncell);
     for (int c = 0; c < 3; c++) s->C[c] = zalloc(s->ncell);
     s->Sax = zalloc(s->ncell);
+    for (int o = 0; o < 2; o++)
+        for (int c = 0; c < 3; c++) s->Eh[o][c] = zalloc((long)s->nn[1] * s->nn[2] * ORA_WIN_KEEP);
     for (int d = 0; d < 3; d++) {
         int a, b;
         other_axes(d, &a, &b);
@@ -746,6 +836,8 @@ void ora_destroy(ora_state *s)
     for (int L = 0; L < 3; L++) free(s->phi[L]);
     for (int c = 0; c < 3; c++) free(s->C[c]);
     free(s->Sax);
+    for (int o = 0; o < 2; o++)
+        for (int c = 0; c < 3; c++) free(s->Eh[o][c]);
     for (int d = 0; d < 3; d++)
         for (int side = 0; side < 2; side++) {
             for (int L = 0; L < 3; L++) free(s->axg[d][side][L]);

@@ -92,6 +92,7 @@ double *ora_axion_ghost(ora_state *s, int d, int side, int level);
 /* after editing the initial arrays in place: recompute derived boundary history */
 void   ora_refresh_initial(ora_state *s);
 void   ora_step(ora_state *s, long nsteps);
+int    ora_shift_window(ora_state *s, int cells);
 long   ora_step_count(const ora_state *s);
 /* energies at the current integer time: out[0] = H_phi, out[1] = H_gamma(E0,B0), out[2] = H_gamma(E1,B1) */
 void   ora_energies(const ora_state *s, double out[3]);

@@ -83,6 +83,8 @@ def load(path):
     L.ora_axion_ghost.restype = ctypes.POINTER(ctypes.c_double)
     L.ora_refresh_initial.argtypes = [ctypes.c_void_p]
     L.ora_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+    L.ora_shift_window.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.ora_shift_window.restype = ctypes.c_int
     L.ora_step_count.argtypes = [ctypes.c_void_p]
     L.ora_step_count.restype = ctypes.c_long
     L.ora_energies.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
@@ -181,6 +183,11 @@ class Oracle:
 
     def step(self, nsteps=1):
         self._L.ora_step(self._h, int(nsteps))
+
+    def shift_window(self, cells):
+        """Move the window `cells` columns along +x (Sec. III.B)."""
+        if self._L.ora_shift_window(self._h, int(cells)) != 0:
+            raise ValueError("window move rejected")
 
     @property
     def step_count(self):

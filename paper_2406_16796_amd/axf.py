@@ -54,6 +54,7 @@ class Config(ctypes.Structure):
         ("pk_x0", ctypes.c_double), ("pk_y0", ctypes.c_double), ("pk_z0", ctypes.c_double),
         ("pk_dir", ctypes.c_int32),
         ("diag_every", ctypes.c_int32), ("path", ctypes.c_int32),
+        ("win_t0", ctypes.c_double), ("win_cells", ctypes.c_int32),
     ]
 
 
@@ -179,6 +180,8 @@ def make_config(cfg, precision=F64, diag_every=0, path=PATH_AUTO):
         setattr(c, key, float(cfg.get(key, 0.0)))
     c.diag_every = int(cfg.get("diag_every", diag_every))
     c.path = int(cfg.get("path", path))
+    c.win_t0 = float(cfg.get("win_t0", 0.0))
+    c.win_cells = int(cfg.get("win_cells", 0))
     return c
 
 

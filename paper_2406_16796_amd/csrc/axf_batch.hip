@@ -326,6 +326,7 @@ static int batch_layout(const axf_config *cfgs, int32_t count, std::vector<size_
     size_t off = align256(Engine::entries_for(count) * sizeof(BItem));
     for (int32_t i = 0; i < count; i++) {
         int rc = validate(&cfgs[i]);
+        if (rc == AXF_OK && cfgs[i].win_cells != 0) rc = fail(AXF_EINVAL, "batches take fixed windows only");
         if (rc) return fail(rc, "run %d: %s", i, axf_last_error());
         if (offs) offs->push_back(off);
         off += align256(make_layout(&cfgs[i]).total);
@@ -669,6 +670,7 @@ int axf_server_submit(axf_server *s, const axf_config *cfg, int64_t nsteps, uint
     if (!s || !cfg || !id) return fail(AXF_EINVAL, "null argument");
     if (nsteps <= 0) return fail(AXF_EINVAL, "nsteps must be positive");
     int rc = validate(cfg);
+    if (rc == AXF_OK && cfg->win_cells != 0) rc = fail(AXF_EINVAL, "served requests take fixed windows only");
     if (rc) return rc;
     const size_t bytes = align256(make_layout(cfg).total);
     if (bytes > s->pool_bytes) return fail(AXF_ENOMEM, "request of %zu bytes exceeds the pool of %zu", bytes, s->pool_bytes);

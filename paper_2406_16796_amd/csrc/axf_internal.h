@@ -60,6 +60,7 @@ __host__ __device__ constexpr int q_mur(int o, int d, int side, int comp, int sl
 }
 constexpr int kNumFaces = 6 * kPhiSlots + 36 * kEmSlots;
 constexpr int kIncLevels = 17;   // time levels per laser table fill (16 steps)
+constexpr int kWinMaxCells = 64; // the most columns one move of a moving window shifts
 constexpr int kDiagSums = 6;     // FP64 partial sums per block of a diagnostic record
 // static diagnostic workspace (axf_diag_now_static): at most kStaticDiagRows
 // block partials, then one record

@@ -64,6 +64,7 @@ struct Run {
     long inc_lo = -1;               // first time level held by the laser table
     bool m3_off = false;            // 3D: the tile-walk launches instead of the one-pass march
     int m3_chunk = 0;               // 3D march: planes per workgroup (0: default)
+    long win_shifted = 0;           // columns the moving window has moved so far
 
     template <typename T> const RunK<T>& hk() const;
     template <typename T> const RunK<T> *rk() const { return (const RunK<T> *)(base + L.off_rk); }
@@ -75,6 +76,12 @@ template <> inline const RunK<double>& Run::hk<double>() const { return hd; }
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int validate(const axf_config *c);
+// the moving window: columns moved by the start of step n; one move of the
+// state by `cells` columns; the descriptor's slab and laser switch for the
+// columns moved so far
+long window_target(const axf_config& c, long n);
+int run_window_move(Run *R, int cells);
+int run_window_desc(Run *R);
 Layout make_layout(const axf_config *c);
 int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStream_t stream);
 int run_step(Run *R, int64_t nsteps);

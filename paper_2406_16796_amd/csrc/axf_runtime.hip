@@ -101,6 +101,13 @@ int validate(const axf_config *c)
         return fail(AXF_EINVAL, "packet needs w > 0 and dir = +-1");
     if (c->diag_every < 0) return fail(AXF_EINVAL, "diag_every must be >= 0");
     if (c->path < AXF_PATH_AUTO || c->path > AXF_PATH_FUSED) return fail(AXF_EINVAL, "bad path");
+    if (c->win_cells < 0 || c->win_cells > kWinMaxCells)
+        return fail(AXF_EINVAL, "win_cells must be 0 (fixed window) .. %d", kWinMaxCells);
+    if (c->win_cells > 0) {
+        if (c->em_bc[0] != AXF_EM_MUR) return fail(AXF_EINVAL, "a moving window needs Mur x faces");
+        if (c->win_cells >= c->n[0]) return fail(AXF_EINVAL, "win_cells must be below n[0]");
+        if (!(c->win_t0 >= c->dt)) return fail(AXF_EINVAL, "the window starts moving at win_t0 >= dt");
+    }
     return AXF_OK;
 }
 
@@ -327,7 +334,7 @@ static void e_phase(Run *R)
 template <int D, typename T>
 static void ensure_incident(Run *R, long s, int nst = 1)
 {
-    if (!R->cfg.laser_on) return;
+    if (!R->cfg.laser_on || R->win_shifted > 0) return;
     if (R->inc_lo >= 0 && s >= R->inc_lo && s + nst < R->inc_lo + kIncLevels) return;
     Plain<D, T>::inc_fill(R->rk<T>(), R->hk<T>(), s, kIncLevels, R->stream);
     R->inc_lo = s;
@@ -524,10 +531,23 @@ static int run_steps(Run *R, int64_t nsteps, int *rc)
 {
     if (!R->converted) convert_to_leapfrog<D, T>(R);
     R->ephase_step = -1;
-    if (R->use_fused && D == 3 && run_march3d(R)) *rc = steps_march3d<D, T>(R, nsteps);
-    else if (R->use_fused && D == 3 && !R->lds_march) steps_semi<D, T>(R, nsteps);
-    else if (R->use_fused) *rc = steps_fused<D, T>(R, nsteps);
-    else steps_plain<D, T>(R, nsteps);
+    while (nsteps > 0 && *rc == AXF_OK) {
+        // a moving window moves at the step boundaries where it is due and
+        // the steps in between go as one call of the path
+        int64_t k = nsteps;
+        if (R->cfg.win_cells > 0) {
+            const long want = window_target(R->cfg, R->step);
+            while (R->win_shifted < want)
+                if ((*rc = run_window_move(R, R->cfg.win_cells)) != AXF_OK) return *rc;
+            k = 1;
+            while (k < nsteps && window_target(R->cfg, R->step + k) == want) k++;
+        }
+        if (R->use_fused && D == 3 && run_march3d(R)) *rc = steps_march3d<D, T>(R, k);
+        else if (R->use_fused && D == 3 && !R->lds_march) steps_semi<D, T>(R, k);
+        else if (R->use_fused) *rc = steps_fused<D, T>(R, k);
+        else steps_plain<D, T>(R, k);
+        nsteps -= k;
+    }
     return *rc;
 }
 
@@ -865,7 +885,7 @@ struct StateHeader {
     int64_t step;
     int64_t rec_written;
     int32_t converted;
-    int32_t pad;
+    int32_t win_shifted;   // columns a moving window has moved
     uint64_t region;
 };
 
@@ -883,7 +903,8 @@ int run_read_state(Run *R, void *buf, size_t bytes)
     run_state_bytes(R, &need);
     if (bytes < need) return fail(AXF_ENOMEM, "state buffer of %zu bytes < %zu", bytes, need);
     HIPCHK(hipStreamSynchronize(R->stream));
-    StateHeader h = {kMagic, R->step, R->rec_written, R->converted ? 1 : 0, 0, R->L.total - R->L.off_state};
+    StateHeader h = {kMagic, R->step, R->rec_written, R->converted ? 1 : 0, (int32_t)R->win_shifted,
+                     R->L.total - R->L.off_state};
     memcpy(buf, &h, sizeof h);
     HIPCHK(hipMemcpy((char *)buf + sizeof h, R->base + R->L.off_state, h.region, hipMemcpyDeviceToHost));
     return AXF_OK;
@@ -907,7 +928,9 @@ int run_write_state(Run *R, const void *buf, size_t bytes)
     // the laser table came with the state: which levels it holds is unknown
     // here, so the next step refills it
     R->inc_lo = -1;
-    return AXF_OK;
+    // the window's place in the lab (the descriptor is outside the state)
+    R->win_shifted = h.win_shifted;
+    return run_window_desc(R);
 }
 
 // ------------------------------------------------------------ tuning table

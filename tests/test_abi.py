@@ -90,3 +90,26 @@ def test_batch_footprint_is_the_sum_of_run_footprints():
     bad = dict(cfgs[1], dt=10.0)
     with pytest.raises(axf.AxfError):
         axf.batch_footprint([cfgs[0], bad], precision=axf.F32)
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda c: c.update(win_cells=65),
+    lambda c: c.update(win_cells=-1),
+    lambda c: c.update(win_t0=0.0),                      # the window moves after the first step
+    lambda c: c.update(em_bc=[0, 1, 0], laser_on=0),     # a moving window needs Mur x faces
+])
+def test_moving_window_settings_are_checked(mutate):
+    cfg = W.gaussian_2d(n=256)
+    cfg.update(win_cells=8, win_t0=10.0)
+    axf.footprint(cfg)
+    mutate(cfg)
+    with pytest.raises(axf.AxfError) as e:
+        axf.footprint(cfg)
+    assert e.value.code == axf.EINVAL
+
+
+def test_batches_take_fixed_windows_only():
+    cfg = W.gaussian_2d(n=64)
+    cfg.update(win_cells=8, win_t0=10.0)
+    with pytest.raises(axf.AxfError):
+        axf.batch_footprint([W.plane_wave_1d(nx=1000), cfg], precision=axf.F32)
