@@ -53,7 +53,7 @@ static bool run_pairs(const Run *R) { return run_passes(R, 2); }
 static bool run_quads(const Run *R) { return run_pairs(R) && run_passes(R, 4); }
 
 // blocks of each launch kind for one run (the single-run launchers' grids)
-static void run_blocks(const Run *R, bool wave, bool pair, bool quad, long blk[kNumKinds])
+static void run_blocks(const Run *R, bool wave, bool pair, bool quad, bool w1, long blk[kNumKinds])
 {
     const Layout& L = R->L;
     blk[kVolume] = cdiv(L.npts, 256);
@@ -84,17 +84,20 @@ static void run_blocks(const Run *R, bool wave, bool pair, bool quad, long blk[k
         if (R->cfg.precision == AXF_F64) wave2d_quad_blocks(R->hk<double>(), ci, cf, &blk[kQuadCore]);
         else wave2d_quad_blocks(R->hk<float>(), ci, cf, &blk[kQuadCore]);
     }
+    blk[kWave1] = 0;
+    if (w1) blk[kWave1] = R->cfg.precision == AXF_F64 ? wave1d_tiles(R->hd) : wave1d_tiles(R->hf);
 }
 
 // ------------------------------------------------------------------ engine
 
 struct Group {
     int D = 0;
-    bool f64 = false, wave = false, pair = false, quad = false, any_diag = false;
+    bool f64 = false, wave = false, pair = false, quad = false, w1 = false, any_diag = false;
     std::vector<int> idx;       // runs, sorted by steps this call (descending)
     size_t off = 0;             // first table entry
     int nact = 0;
     int64_t s = 0;              // steps of this call done
+    int64_t inc_lo = -1;        // first level (call step) of the active runs' laser tables
 };
 
 class Engine {
@@ -141,7 +144,8 @@ public:
 
 private:
     template <int D, typename T>
-    int group_step(Group& g, long s, int ns, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st);
+    int group_step(Group& g, long s, int ns, std::vector<int64_t>& nrec, std::vector<int64_t>& inc_at,
+                   Run *const *runs, hipStream_t st);
 
     BItem *dev_ = nullptr, *host_ = nullptr;
     size_t cap_ = 0;
@@ -153,12 +157,19 @@ private:
 // steps (the caller takes one only where no diagnostic record falls on any
 // of its steps and no laser-table fill on any but the first)
 template <int D, typename T>
-int Engine::group_step(Group& g, long s, int ns, std::vector<int64_t>& nrec, Run *const *runs, hipStream_t st)
+int Engine::group_step(Group& g, long s, int ns, std::vector<int64_t>& nrec, std::vector<int64_t>& inc_at,
+                       Run *const *runs, hipStream_t st)
 {
     const bool two = ns > 1;
     const BItem *dt = dev_ + g.off, *ht = host_ + g.off;
     const int n = g.nact;
-    if (s % (kIncLevels - 1) == 0) Plain<D, T>::batch_inc_fill(dt, ht, n, s, kIncLevels, st);
+    // the laser tables hold the levels s .. s + ns of these steps (a fill
+    // every 16 steps while the group steps through the unfused kernels)
+    if (!(g.inc_lo >= 0 && s >= g.inc_lo && s + ns < g.inc_lo + kIncLevels)) {
+        Plain<D, T>::batch_inc_fill(dt, ht, n, s, kIncLevels, st);
+        g.inc_lo = s;
+        for (int k = 0; k < n; k++) inc_at[g.idx[k]] = s;
+    }
     bool launched = false;
     if constexpr (D == 2) {
         if (g.wave) {
@@ -210,9 +221,10 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
         const int D = R->cfg.ndim;
         const bool f64 = R->cfg.precision == AXF_F64, wave = run_wave2d(R), pair = run_pairs(R);
         const bool quad = quads && run_quads(R);
+        const bool w1 = D == 1 && R->use_fused;
         Group *g = nullptr;
         for (auto& q : groups)
-            if (q.D == D && q.f64 == f64 && q.wave == wave && q.pair == pair && q.quad == quad) g = &q;
+            if (q.D == D && q.f64 == f64 && q.wave == wave && q.pair == pair && q.quad == quad && q.w1 == w1) g = &q;
         if (!g) {
             groups.emplace_back();
             g = &groups.back();
@@ -221,6 +233,7 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
             g->wave = wave;
             g->pair = pair;
             g->quad = quad;
+            g->w1 = w1;
         }
         g->idx.push_back(i);
         g->any_diag = g->any_diag || R->cfg.diag_every > 0;
@@ -249,7 +262,7 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
             run_pass_shape(R, 2, &b.pass_ci, &b.pass_cf);
             run_pass_shape(R, 4, &b.quad_ci, &b.quad_cf);
             long nb[kNumKinds];
-            run_blocks(R, g.wave, g.pair, g.quad, nb);
+            run_blocks(R, g.wave, g.pair, g.quad, g.w1, nb);
             for (int q = 0; q < kNumKinds; q++) acc[q] += nb[q];
         }
         off += g.idx.size() + 1;
@@ -258,7 +271,7 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
     // the staging buffer is rewritten by the next call: finish the copy now
     BCHK(hipStreamSynchronize(st));
 
-    std::vector<int64_t> nrec(count, 0);
+    std::vector<int64_t> nrec(count, 0), inc_at(count, -1);
     // a diagnostic record of some active run of the group falls on step s
     auto diag_at = [&](const Group& g, int64_t s) {
         if (!g.any_diag) return false;
@@ -283,15 +296,36 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
                     if ((q > 0 && (s + q) % (kIncLevels - 1) == 0) || diag_at(g, s + q)) return false;
                 return true;
             };
+            if (g.w1) {
+                // a fused 1D pass over the steps before the next record of any
+                // active run (the record's step takes the unfused kernels)
+                int64_t free = ns[g.idx[g.nact - 1]] - s;
+                for (int k = 0; k < g.nact; k++) {
+                    const Run *R = runs[g.idx[k]];
+                    const int64_t de = R->cfg.diag_every, at = R->step + s;
+                    if (de > 0) free = std::min<int64_t>(free, (at + de - 1) / de * de - at);
+                }
+                const Run *R0 = runs[g.idx[0]];
+                const int kmax = g.f64 ? wave1d_kmax<double>() : wave1d_kmax<float>();
+                const int k = free >= 2 ? wave1d_pick(free, kmax, R0->L.nem, R0->L.nph) : 0;
+                if (k >= 2) {
+                    const BItem *dt = dev_ + g.off, *ht = host_ + g.off;
+                    hipError_t e = g.f64 ? launch_wave1d_batch<double>(dt, ht, g.nact, s, k, st)
+                                         : launch_wave1d_batch<float>(dt, ht, g.nact, s, k, st);
+                    if (e != hipSuccess) return hip_fail(e, "batched fused 1D pass");
+                    g.s += k;
+                    continue;
+                }
+            }
             const int np = g.D != 2 ? 1 : (g.quad && pass_fits(4)) ? 4 : (g.pair && pass_fits(2)) ? 2 : 1;
             int rc;
             switch (g.D * 2 + (g.f64 ? 1 : 0)) {
-            case 2: rc = group_step<1, float>(g, s, 1, nrec, runs, st); break;
-            case 3: rc = group_step<1, double>(g, s, 1, nrec, runs, st); break;
-            case 4: rc = group_step<2, float>(g, s, np, nrec, runs, st); break;
-            case 5: rc = group_step<2, double>(g, s, np, nrec, runs, st); break;
-            case 6: rc = group_step<3, float>(g, s, 1, nrec, runs, st); break;
-            default: rc = group_step<3, double>(g, s, 1, nrec, runs, st); break;
+            case 2: rc = group_step<1, float>(g, s, 1, nrec, inc_at, runs, st); break;
+            case 3: rc = group_step<1, double>(g, s, 1, nrec, inc_at, runs, st); break;
+            case 4: rc = group_step<2, float>(g, s, np, nrec, inc_at, runs, st); break;
+            case 5: rc = group_step<2, double>(g, s, np, nrec, inc_at, runs, st); break;
+            case 6: rc = group_step<3, float>(g, s, 1, nrec, inc_at, runs, st); break;
+            default: rc = group_step<3, double>(g, s, 1, nrec, inc_at, runs, st); break;
             }
             if (rc) return rc;
             g.s += np;
@@ -301,7 +335,7 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
     for (int i = 0; i < count; i++) {
         if (ns[i] == 0) continue;
         Run *R = runs[i];
-        if (R->cfg.laser_on) R->inc_lo = R->step + (ns[i] - 1) / (kIncLevels - 1) * (kIncLevels - 1);
+        if (R->cfg.laser_on) R->inc_lo = inc_at[i] >= 0 ? R->step + inc_at[i] : -1;
         R->step += ns[i];
         R->rec_written += nrec[i];
     }

@@ -68,6 +68,25 @@ void wave2d_quad_blocks(const RunK<T>& h, int ci, int cf, long blk[3]);
 template <typename T>
 void wave2d_blocks(const RunK<T>& h, int chunk, long *edge_blocks, long *interior_blocks);
 
+// Fused 1D step: K steps per launch on windows of cells held in LDS, halos
+// of K + 1 cells (temporal blocking); the grid in one window when it fits.
+// A pass reads the slots of step s and writes those of step s + K: K must
+// keep them apart (wave1d_k_ok) and be at most wave1d_kmax.
+bool wave1d_k_ok(int k, int nem, int nph);
+template <typename T>
+int wave1d_kmax();
+// the longest pass of at most min(free, kmax) steps that wave1d_k_ok allows,
+// preferring one that does not leave exactly one step; 0 if there is none
+int wave1d_pick(long free, int kmax, int nem, int nph);
+// workgroups (tiles) of one run's pass
+template <typename T>
+long wave1d_tiles(const RunK<T>& h);
+template <typename T>
+hipError_t launch_wave1d(const RunK<T> *rk, const RunK<T>& h, long step, int K, hipStream_t st);
+// the same pass over the first n runs of a batch table at step s of the call
+template <typename T>
+hipError_t launch_wave1d_batch(const BItem *it, const BItem *host, int n, long s, int K, hipStream_t st);
+
 // One-pass 3D step (a z march of row wavefronts stacked along y, y neighbours
 // through LDS): x segments of `wid` own columns, groups of own rows, chunks
 // of `zc` planes.

@@ -34,12 +34,14 @@ template <int D> __host__ __device__ constexpr bool actB1(int c) { return D >= 2
 // axion levels and their ghosts through nph (level L, the field at
 // t = (L - 1/2) dt, in slot L mod nph).  2D runs keep five and six: a pass of
 // up to four steps reads the slots of step n while its launches write those
-// of steps n + 1 .. n + 4, all distinct.  1D and 3D runs advance one step per
-// launch and keep two and three (the old and new E/B; the two axion levels a
-// step reads and the one it writes).
+// of steps n + 1 .. n + 4, all distinct.  1D runs keep as many: a pass of K
+// steps reads the slots of step n and writes those of step n + K, which five
+// and six keep apart for K = 2, 3, 4, 8, 9, 14, 16, ... (tiny arrays).  3D
+// runs advance one step per launch and keep two and three (the old and new
+// E/B; the two axion levels a step reads and the one it writes).
 constexpr int kEmSlots = 5, kPhiSlots = 6;      // the most a run keeps
-__host__ __device__ constexpr int em_slots_of(int D) { return D == 2 ? kEmSlots : 2; }
-__host__ __device__ constexpr int phi_slots_of(int D) { return D == 2 ? kPhiSlots : 3; }
+__host__ __device__ constexpr int em_slots_of(int D) { return D == 3 ? 2 : kEmSlots; }
+__host__ __device__ constexpr int phi_slots_of(int D) { return D == 3 ? 3 : kPhiSlots; }
 __host__ __device__ constexpr int em_slot(long step, int nem) { return (int)(step % nem); }
 __host__ __device__ constexpr int phi_slot(long level, int nph) { return (int)(level % nph); }
 
@@ -126,6 +128,7 @@ enum BlockKind {
     kVolume = 0, kFace, kLaser, kWave, kWaveI,
     kPair, kFrameA, kFrameB,           // two-step pass: interior, frames of steps n and n + 1
     kQuadCore, kQuadRing, kQuadFrame,  // four-step pass: interior core and ring, frame (every step)
+    kWave1,                            // fused 1D pass: one workgroup per window
     kNumKinds
 };
 struct BItem {

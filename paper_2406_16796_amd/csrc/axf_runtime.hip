@@ -57,7 +57,7 @@ static bool auto_fused_enabled(const axf_config *c)
 {
     const char *e = getenv("AXF_AUTO_FUSED");
     if (e) return e[0] == '1';
-    return c->ndim >= 2;
+    return true;
 }
 
 static double pow2_near(double v) { return ldexp(1.0, (int)lround(log2(v))); }
@@ -517,10 +517,37 @@ static int steps_fused(Run *R, int64_t nsteps)
     }
 }
 
-// the fused kernel needs the axion to be periodic wherever the EM field is
+// Fused 1D step: passes of several steps (one launch each) between the steps
+// that carry a diagnostic record, which take the unfused kernels (the record
+// reads the time levels a pass does not keep), as does a single step left over
+template <typename T>
+static int steps_wave1d(Run *R, int64_t nsteps)
+{
+    const RunK<T>& h = R->hk<T>();
+    const int kmax = wave1d_kmax<T>();
+    while (nsteps > 0) {
+        const long s = R->step;
+        int64_t free = nsteps;
+        const int64_t de = R->cfg.diag_every;
+        if (de > 0) free = std::min<int64_t>(free, (s + de - 1) / de * de - s);
+        const int k = free >= 2 ? wave1d_pick(free, kmax, h.nem, h.nph) : 0;
+        if (k < 2) {
+            steps_plain<1, T>(R, 1);
+            nsteps -= 1;
+            continue;
+        }
+        hipError_t e = launch_wave1d<T>(R->rk<T>(), h, s, k, R->stream);
+        if (e != hipSuccess) return hip_fail(e, "fused 1D pass");
+        R->step += k;
+        R->launches += 1;
+        nsteps -= k;
+    }
+    return AXF_OK;
+}
+
+// the fused kernels need the axion to be periodic wherever the EM field is
 bool fused_supported(const axf_config *c)
 {
-    if (c->ndim < 2) return false;
     for (int d = 0; d < c->ndim; d++)
         if (c->em_bc[d] == AXF_EM_PERIODIC && c->ax_bc[d] != AXF_AX_PERIODIC) return false;
     return true;
@@ -541,6 +568,12 @@ static int run_steps(Run *R, int64_t nsteps, int *rc)
                 if ((*rc = run_window_move(R, R->cfg.win_cells)) != AXF_OK) return *rc;
             k = 1;
             while (k < nsteps && window_target(R->cfg, R->step + k) == want) k++;
+        }
+        if constexpr (D == 1) {
+            if (R->use_fused) *rc = steps_wave1d<T>(R, k);
+            else steps_plain<D, T>(R, k);
+            nsteps -= k;
+            continue;
         }
         if (R->use_fused && D == 3 && run_march3d(R)) *rc = steps_march3d<D, T>(R, k);
         else if (R->use_fused && D == 3 && !R->lds_march) steps_semi<D, T>(R, k);
@@ -593,7 +626,7 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     R->base = (char *)dev_buf;
     R->stream = stream;
     if (cfg->path == AXF_PATH_FUSED && !fused_supported(cfg))
-        return fail(AXF_EINVAL, "the fused path needs ndim >= 2 and a periodic axion on every periodic EM axis");
+        return fail(AXF_EINVAL, "the fused path needs a periodic axion on every periodic EM axis");
     TunedShape ts;
     if (tuned_shape(cfg, &ts)) {
         R->chunk = ts.chunk;

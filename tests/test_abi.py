@@ -49,8 +49,8 @@ def test_footprint_and_extents_follow_the_layout():
 
 def test_512_cubed_fp32_footprint():
     """The 512^3 FP32 run: 30 arrays of 544 x 513 x 513 floats (17.2 GB) and
-    the boundary planes; 1D and 3D runs keep two E/B slots and three axion
-    levels, 2D runs five and six."""
+    the boundary planes; 3D runs keep two E/B slots and three axion levels,
+    1D and 2D runs five and six."""
     b = axf.footprint(W.focused_3d(), precision=axf.F32)
     assert 30 * 544 * 513 * 513 * 4 < b < 17.6e9, b
 
