@@ -85,7 +85,10 @@ static void run_blocks(const Run *R, bool wave, bool pair, bool quad, bool w1, l
         else wave2d_quad_blocks(R->hk<float>(), ci, cf, &blk[kQuadCore]);
     }
     blk[kWave1] = 0;
-    if (w1) blk[kWave1] = R->cfg.precision == AXF_F64 ? wave1d_tiles(R->hd) : wave1d_tiles(R->hf);
+    if (w1) {
+        const int win = wave1d_window(true);
+        blk[kWave1] = R->cfg.precision == AXF_F64 ? wave1d_tiles(R->hd, win) : wave1d_tiles(R->hf, win);
+    }
 }
 
 // ------------------------------------------------------------------ engine
@@ -310,8 +313,9 @@ int Engine::step(Run *const *runs, const int64_t *ns, int count, hipStream_t st)
                 const int k = free >= 2 ? wave1d_pick(free, kmax, R0->L.nem, R0->L.nph) : 0;
                 if (k >= 2) {
                     const BItem *dt = dev_ + g.off, *ht = host_ + g.off;
-                    hipError_t e = g.f64 ? launch_wave1d_batch<double>(dt, ht, g.nact, s, k, st)
-                                         : launch_wave1d_batch<float>(dt, ht, g.nact, s, k, st);
+                    const int win = wave1d_window(true);
+                    hipError_t e = g.f64 ? launch_wave1d_batch<double>(dt, ht, g.nact, s, k, win, st)
+                                         : launch_wave1d_batch<float>(dt, ht, g.nact, s, k, win, st);
                     if (e != hipSuccess) return hip_fail(e, "batched fused 1D pass");
                     g.s += k;
                     continue;

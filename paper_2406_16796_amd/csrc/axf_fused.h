@@ -78,14 +78,16 @@ int wave1d_kmax();
 // the longest pass of at most min(free, kmax) steps that wave1d_k_ok allows,
 // preferring one that does not leave exactly one step; 0 if there is none
 int wave1d_pick(long free, int kmax, int nem, int nph);
-// workgroups (tiles) of one run's pass
+// cells per window (256, 512 or 1024) of a single run's passes or a batch's
+int wave1d_window(bool batched);
+// workgroups (tiles) of one run's pass with windows of `win` cells
 template <typename T>
-long wave1d_tiles(const RunK<T>& h);
+long wave1d_tiles(const RunK<T>& h, int win);
 template <typename T>
-hipError_t launch_wave1d(const RunK<T> *rk, const RunK<T>& h, long step, int K, hipStream_t st);
+hipError_t launch_wave1d(const RunK<T> *rk, const RunK<T>& h, long step, int K, int win, hipStream_t st);
 // the same pass over the first n runs of a batch table at step s of the call
 template <typename T>
-hipError_t launch_wave1d_batch(const BItem *it, const BItem *host, int n, long s, int K, hipStream_t st);
+hipError_t launch_wave1d_batch(const BItem *it, const BItem *host, int n, long s, int K, int win, hipStream_t st);
 
 // One-pass 3D step (a z march of row wavefronts stacked along y, y neighbours
 // through LDS): x segments of `wid` own columns, groups of own rows, chunks

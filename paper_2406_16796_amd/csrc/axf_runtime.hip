@@ -536,7 +536,7 @@ static int steps_wave1d(Run *R, int64_t nsteps)
             nsteps -= 1;
             continue;
         }
-        hipError_t e = launch_wave1d<T>(R->rk<T>(), h, s, k, R->stream);
+        hipError_t e = launch_wave1d<T>(R->rk<T>(), h, s, k, wave1d_window(false), R->stream);
         if (e != hipSuccess) return hip_fail(e, "fused 1D pass");
         R->step += k;
         R->launches += 1;

@@ -26,28 +26,27 @@
 #include "axf_fused.h"
 #include "axf_stencil.h"
 
+#include <stdlib.h>
+
 #include <algorithm>
 
 namespace axf {
 
 namespace {
 
-template <typename T> struct W1Cfg;
-// window slots per workgroup and the most steps per pass
-template <> struct W1Cfg<float> { static constexpr int W = 1024, KMAX = 32; };
-template <> struct W1Cfg<double> { static constexpr int W = 512, KMAX = 16; };
-constexpr int kW1Threads = 256;
+// the most steps per pass; threads per workgroup
+constexpr int kW1Kmax = 16, kW1Threads = 256;
 
-template <typename T>
+// LDS of a window of W cells
+template <typename T, int W>
 struct W1Lds {
-    static constexpr int W = W1Cfg<T>::W;
     T e0y[W], e0z[W], e1y[W], e1z[W];   // E^{n-1/2}, E^{n+1/2} after phase A
     T b[2][4][W];                        // B0y B0z B1y B1z: B^n in [n & 1]
     T ph[3][W];                          // axion level L in [L % 3]
     T bn[2][4];                          // the same at node n (Mur x_max face)
     T mg[2][2][2];                       // Mur ghosts [side][order][component - 1]
     T ag[2][3];                          // axion ghosts [side][level % 3]
-    double inc[2][W1Cfg<T>::KMAX + 1];   // laser at the first centre [0] and at the ghost [1], levels s0 ..
+    double inc[2][kW1Kmax + 1];          // laser at the first centre [0] and at the ghost [1], levels s0 ..
 };
 
 // the window of tile t: cells gs .. gs + wn - 1 (mod n when it wraps), own
@@ -94,17 +93,46 @@ __device__ inline W1Tile w1_tile(int n, bool axp, int W, int kmax, int t)
     return g;
 }
 
-template <typename T>
-__device__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T>& sm)
+// (inlined into its kernels, so that `sm` is known to be LDS)
+template <typename T, int W>
+__device__ __forceinline__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T, W>& sm)
 {
-    constexpr int W = W1Cfg<T>::W, KM = W1Cfg<T>::KMAX;
+    constexpr int KM = kW1Kmax;
     const int n = r.n[0];
     const bool mur = r.mur[0] != 0, axp = r.axbc[0] == AXF_AX_PERIODIC, outflow = r.axbc[0] == AXF_AX_OUTFLOW;
     const W1Tile tg = w1_tile(n, axp, W, KM, t);
     const int tid = threadIdx.x;
-    auto gcell = [&](int w) { return tg.wrap ? ((tg.gs + w) % n + n) % n : tg.gs + w; };
-    auto nbr = [&](int w, int d) { return tg.ring ? (w + d + tg.wn) % tg.wn : min(max(w + d, 0), tg.wn - 1); };
-    const T half = r.half, cdt = r.cdt[0];
+    // (gs > -n and gs + w < 2n: one correction wraps a cell index)
+    auto gcell = [&](int w) {
+        const int g = tg.gs + w;
+        return !tg.wrap ? g : (g < 0 ? g + n : (g >= n ? g - n : g));
+    };
+    auto nbr = [&](int w, int d) {
+        const int v = w + d;
+        return tg.ring ? (v < 0 ? v + tg.wn : (v >= tg.wn ? v - tg.wn : v)) : min(max(v, 0), tg.wn - 1);
+    };
+    // the descriptor's coefficients in registers (the loop's stores to device
+    // memory would otherwise have them read again every iteration)
+    const T half = r.half, cdt = r.cdt[0], inv_dt = r.inv_dt, inv2dx = r.inv2dx[0], inv_dx2 = r.inv_dx2[0];
+    const T cg1 = r.cg1, gax = r.gax, m2 = r.m2, dt2 = r.dt2, out_r = r.out_r[0], sdt_max = r.pml_sdt_max;
+    const T bx[3] = {r.bext[0], r.bext[1], r.bext[2]};
+    const int slab_lo = r.slab_lo, slab_hi = r.slab_hi, pml_n = r.pml_n, las_on = r.las.on, las_pol = r.las.pol;
+    const bool pml = r.axbc[0] == AXF_AX_PML;
+    const double murc = r.murc[0];
+    // bext_at and pml_sdt with those registers (the same operations)
+    auto bext = [&](int c, int g) { return (g >= slab_lo && g < slab_hi) ? bx[c] : T(0); };
+    auto sdt_at = [&](int g) {
+        T sv = T(0);
+        if (pml) {
+            const int dist = g < n - 1 - g ? g : n - 1 - g;
+            if (dist < pml_n) {
+                const T q = T(1) - T(dist) / T(pml_n);
+                const T sd = sdt_max * q * q * q;
+                sv = sd > sv ? sd : sv;
+            }
+        }
+        return sv;
+    };
 
     // the state of step s0
     {
@@ -140,9 +168,9 @@ __device__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T>& sm)
         }
         // the laser on the x_min face at levels s0 .. s0 + K, as the unfused
         // path tabulates it
-        const int w0 = tg.wrap ? ((-tg.gs) % n + n) % n : -tg.gs;
-        if (mur && r.las.on && w0 >= 0 && w0 < tg.wn && tid <= K) {
-            const int c = r.las.pol, j = 0, k = 0;
+        const int w0 = tg.wrap && tg.gs > 0 ? n - tg.gs : -tg.gs;
+        if (mur && las_on && w0 >= 0 && w0 < tg.wn && tid <= K) {
+            const int c = las_pol, j = 0, k = 0;
             const double y = (c == 1) ? j * r.dx[1] : (j + 0.5) * r.dx[1];
             const double z = (c == 2) ? k * r.dx[2] : (k + 0.5) * r.dx[2];
             const long L = s0 + tid;
@@ -154,6 +182,17 @@ __device__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T>& sm)
     __syncthreads();
 
     const int so2 = em_slot(s0 + K, r.nem), lo2 = phi_slot(s0 + K, r.nph), ln2 = phi_slot(s0 + K + 1, r.nph);
+    // where the pass leaves the state of step s0 + K
+    T *const oE[4] = {r.E0[so2][1], r.E0[so2][2], r.E1[so2][1], r.E1[so2][2]};
+    T *const oB[4] = {r.B0[so2][1], r.B0[so2][2], r.B1[so2][1], r.B1[so2][2]};
+    T *const oP0 = r.phi[lo2], *const oP1 = r.phi[ln2];
+    T *oM[2][2][2], *oA[2][2];
+    for (int side = 0; side < 2; side++) {
+        for (int o = 0; o < 2; o++)
+            for (int c = 1; c < 3; c++) oM[side][o][c - 1] = mur ? r.murg[o][0][side][c][so2] : nullptr;
+        oA[side][0] = axp ? nullptr : r.axg[0][side][lo2];
+        oA[side][1] = axp ? nullptr : r.axg[0][side][ln2];
+    }
     for (int k = 0; k < K; k++) {
         const int pb = k & 1, qa = k % 3, qb = (k + 1) % 3, qn = (k + 2) % 3;
         const bool last = k == K - 1;
@@ -174,7 +213,7 @@ __device__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T>& sm)
             // mean of its two levels, B0 the mean of the two nodes, phi^n the mean
             // of the two axion levels
             const T e0 = T(0), e1 = half * (ey0 + ny0), e2 = half * (ez0 + nz0);
-            const T b1 = half * (by0 + rb[0]) + bext_at(r, 1, g), b2 = half * (bz0 + rb[1]) + bext_at(r, 2, g);
+            const T b1 = half * (by0 + rb[0]) + bext(1, g), b2 = half * (bz0 + rb[1]) + bext(2, g);
             const T pa = sm.ph[qa][w], pbv = sm.ph[qb][w];
             T pal, pbl, par, pbr;
             if (!axp && g == 0) {
@@ -191,14 +230,14 @@ __device__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T>& sm)
                 par = sm.ph[qa][wr];
                 pbr = sm.ph[qb][wr];
             }
-            const T dtphi = (pbv - pa) * r.inv_dt;
+            const T dtphi = (pbv - pa) * inv_dt;
             const T up = half * (par + pbr), dn = half * (pal + pbl);
-            const T gp0 = (up - dn) * r.inv2dx[0], gp1 = T(0), gp2 = T(0);
+            const T gp0 = (up - dn) * inv2dx, gp1 = T(0), gp2 = T(0);
             const T c1 = dtphi * b1 - (e2 * gp0 - e0 * gp2);
             const T c2 = dtphi * b2 - (e0 * gp1 - e1 * gp0);
             // E1^{n+1/2} with the current on the face (the centre itself in 1D)
-            const T ny1 = ey1 + T(1) * ((T(0) - cdt * (rb[3] - bz1)) - r.cg1 * c1);
-            const T nz1 = ez1 + T(1) * ((cdt * (rb[2] - by1) - T(0)) - r.cg1 * c2);
+            const T ny1 = ey1 + T(1) * ((T(0) - cdt * (rb[3] - bz1)) - cg1 * c1);
+            const T nz1 = ez1 + T(1) * ((cdt * (rb[2] - by1) - T(0)) - cg1 * c2);
             sm.e0y[w] = ny0;
             sm.e0z[w] = nz0;
             sm.e1y[w] = ny1;
@@ -210,24 +249,24 @@ __device__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T>& sm)
                     for (int o = 0; o < 2; o++)
                         for (int c = 1; c < 3; c++) {
                             double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
-                            if (o == 0 && side == 0 && r.las.on && c == r.las.pol) {
+                            if (o == 0 && side == 0 && las_on && c == las_pol) {
                                 ia_o = sm.inc[0][k];
                                 ig_o = sm.inc[1][k];
                                 ia_n = sm.inc[0][k + 1];
                                 ig_n = sm.inc[1][k + 1];
                             }
                             T& gh = sm.mg[side][o][c - 1];
-                            gh = (T)mur_core(r.murc[0], (double)eo[o][c - 1], (double)en[o][c - 1], (double)gh, ia_o,
-                                             ia_n, ig_o, ig_n);
-                            if (last && w >= tg.own0 && w < tg.own1) r.murg[o][0][side][c][so2][0] = gh;
+                            gh = (T)mur_core(murc, (double)eo[o][c - 1], (double)en[o][c - 1], (double)gh, ia_o, ia_n,
+                                             ig_o, ig_n);
+                            if (last && w >= tg.own0 && w < tg.own1) oM[side][o][c - 1][0] = gh;
                         }
                 }
             }
             if (last && w >= tg.own0 && w < tg.own1) {
-                r.E0[so2][1][g] = ny0;
-                r.E0[so2][2][g] = nz0;
-                r.E1[so2][1][g] = ny1;
-                r.E1[so2][2][g] = nz1;
+                oE[0][g] = ny0;
+                oE[1][g] = nz0;
+                oE[2][g] = ny1;
+                oE[3][g] = nz1;
             }
         }
         __syncthreads();
@@ -273,10 +312,10 @@ __device__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T>& sm)
                 sm.bn[pb ^ 1][2] = ry1n;
                 sm.bn[pb ^ 1][3] = rz1n;
                 if (last && w >= tg.own0 && w < tg.own1) {
-                    r.B0[so2][1][n] = ry0n;
-                    r.B0[so2][2][n] = rz0n;
-                    r.B1[so2][1][n] = ry1n;
-                    r.B1[so2][2][n] = rz1n;
+                    oB[0][n] = ry0n;
+                    oB[1][n] = rz0n;
+                    oB[2][n] = ry1n;
+                    oB[3][n] = rz1n;
                 }
             } else {
                 ry0o = sm.b[pb][0][wr];
@@ -286,17 +325,17 @@ __device__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T>& sm)
             }
             // phi^{n+3/2}: source g E0^{n+1/2}.B0^{n+1/2} at the centre
             const T eb0 = T(0), eb1 = ey0, eb2 = ez0;
-            const T bb0 = half * (T(0) + T(0)) + bext_at(r, 0, g);
-            const T bb1 = half * (half * (by0 + ry0o) + half * (nby0 + ry0n)) + bext_at(r, 1, g);
-            const T bb2 = half * (half * (bz0 + rz0o) + half * (nbz0 + rz0n)) + bext_at(r, 2, g);
-            const T sax = r.gax * (eb0 * bb0 + eb1 * bb1 + eb2 * bb2);
+            const T bb0 = half * (T(0) + T(0)) + bext(0, g);
+            const T bb1 = half * (half * (by0 + ry0o) + half * (nby0 + ry0n)) + bext(1, g);
+            const T bb2 = half * (half * (bz0 + rz0o) + half * (nbz0 + rz0n)) + bext(2, g);
+            const T sax = gax * (eb0 * bb0 + eb1 * bb1 + eb2 * bb2);
             const T pa = sm.ph[qa][w], pbv = sm.ph[qb][w];
             const T pl = (!axp && g == 0) ? sm.ag[0][qb] : sm.ph[qb][wl];
             const T pr = (!axp && g == n - 1) ? sm.ag[1][qb] : sm.ph[qb][wr];
             T lap = T(0);
-            lap += ((pr - T(2) * pbv) + pl) * r.inv_dx2[0];
-            const T sdt = pml_sdt<1>(r, g, 0, 0);
-            const T x = r.dt2 * ((sax - r.m2 * pbv) + lap) - sdt * sdt * pbv;
+            lap += ((pr - T(2) * pbv) + pl) * inv_dx2;
+            const T sdt = sdt_at(g);
+            const T x = dt2 * ((sax - m2 * pbv) + lap) - sdt * sdt * pbv;
             T pn = ((x + sdt * pa) + T(2) * pbv) - pa;
             if (sdt != T(0)) pn = pn / (T(1) + sdt);
             sm.ph[qn][w] = pn;
@@ -307,8 +346,8 @@ __device__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T>& sm)
                     T gv;
                     if (outflow) {
                         // one-way wave and Klein-Gordon at the ghost (Sec. II.D, outflow)
-                        const T gb = sm.ag[side][qb], ga = sm.ag[side][qa], rr = r.out_r[0];
-                        const T xx = (((T(-2) * gb + T(2) * ga) - r.dt2 * (sax - r.m2 * gb)) + rr * pbv -
+                        const T gb = sm.ag[side][qb], ga = sm.ag[side][qa], rr = out_r;
+                        const T xx = (((T(-2) * gb + T(2) * ga) - dt2 * (sax - m2 * gb)) + rr * pbv -
                                       rr * rr * (pbv - T(2) * gb)) / (rr + rr * rr);
                         gv = ga + rr * (pbv - xx);
                     } else {
@@ -316,42 +355,57 @@ __device__ void w1_pass(const RunK<T>& r, int t, long s0, int K, W1Lds<T>& sm)
                     }
                     sm.ag[side][qn] = gv;
                     if (own) {
-                        r.axg[0][side][lo2][0] = sm.ag[side][qb];
-                        r.axg[0][side][ln2][0] = gv;
+                        oA[side][0][0] = sm.ag[side][qb];
+                        oA[side][1][0] = gv;
                     }
                 }
             }
             if (own) {
-                r.B0[so2][1][g] = nby0;
-                r.B0[so2][2][g] = nbz0;
-                r.B1[so2][1][g] = nby1;
-                r.B1[so2][2][g] = nbz1;
-                r.phi[lo2][g] = pbv;
-                r.phi[ln2][g] = pn;
+                oB[0][g] = nby0;
+                oB[1][g] = nbz0;
+                oB[2][g] = nby1;
+                oB[3][g] = nbz1;
+                oP0[g] = pbv;
+                oP1[g] = pn;
             }
         }
         __syncthreads();
     }
 }
 
-template <typename T>
+template <typename T, int W>
 __global__ void __launch_bounds__(kW1Threads) k_wave1d(const RunK<T> *__restrict__ rp, long s0, int K)
 {
-    __shared__ W1Lds<T> sm;
-    w1_pass<T>(*rp, blockIdx.x, s0, K, sm);
+    __shared__ W1Lds<T, W> sm;
+    w1_pass<T, W>(*rp, blockIdx.x, s0, K, sm);
 }
 
-template <typename T>
+template <typename T, int W>
 __global__ void __launch_bounds__(kW1Threads) kb_wave1d(const BItem *__restrict__ it, int nrun, long s, int K)
 {
-    __shared__ W1Lds<T> sm;
+    __shared__ W1Lds<T, W> sm;
     const long b = blockIdx.x;
     const int q = find_item<kWave1>(it, nrun, b);
     const RunK<T>& r = *uniform_desc<RunK<T>>(it[q].rk);
-    w1_pass<T>(r, (int)(b - it[q].blk[kWave1]), it[q].step0 + s, K, sm);
+    w1_pass<T, W>(r, (int)(b - it[q].blk[kWave1]), it[q].step0 + s, K, sm);
 }
 
 }  // namespace
+
+int wave1d_window(bool batched)
+{
+    // measured (3000 steps; one run of 4096 or 65536 cells, and the 256 1D runs of
+    // the 512-run scan in one batch): windows of 256 / 512 / 1024 cells take
+    // 7.3 / 10.0 / 16.4 ms for the single FP32 runs (one wavefront per SIMD
+    // works through a cell's chain of updates: a step costs the same whatever
+    // the grid) and give 91.9 / 110.0 / 65.0 Gcell/s over the batch
+    static const int env = [] {
+        const char *e = getenv("AXF_W1_WIN");
+        const int v = e ? atoi(e) : 0;
+        return v == 256 || v == 512 || v == 1024 ? v : 0;
+    }();
+    return env ? env : (batched ? 512 : 256);
+}
 
 bool wave1d_k_ok(int k, int nem, int nph)
 {
@@ -360,7 +414,7 @@ bool wave1d_k_ok(int k, int nem, int nph)
 }
 
 template <typename T>
-int wave1d_kmax() { return W1Cfg<T>::KMAX; }
+int wave1d_kmax() { return kW1Kmax; }
 
 int wave1d_pick(long free, int kmax, int nem, int nph)
 {
@@ -375,33 +429,43 @@ int wave1d_pick(long free, int kmax, int nem, int nph)
 }
 
 template <typename T>
-long wave1d_tiles(const RunK<T>& h) { return w1_ntiles(h.n[0], W1Cfg<T>::W, W1Cfg<T>::KMAX); }
+long wave1d_tiles(const RunK<T>& h, int win) { return w1_ntiles(h.n[0], win, kW1Kmax); }
 
 template <typename T>
-hipError_t launch_wave1d(const RunK<T> *rk, const RunK<T>& h, long step, int K, hipStream_t st)
+hipError_t launch_wave1d(const RunK<T> *rk, const RunK<T>& h, long step, int K, int win, hipStream_t st)
 {
-    if (h.D != 1 || K < 2 || K > W1Cfg<T>::KMAX || !wave1d_k_ok(K, h.nem, h.nph)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_wave1d<T>), dim3((unsigned)wave1d_tiles(h)), dim3(kW1Threads), 0, st, rk, step, K);
+    if (h.D != 1 || K < 2 || K > kW1Kmax || !wave1d_k_ok(K, h.nem, h.nph)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)wave1d_tiles(h, win));
+    switch (win) {
+    case 256: hipLaunchKernelGGL((k_wave1d<T, 256>), grid, dim3(kW1Threads), 0, st, rk, step, K); break;
+    case 512: hipLaunchKernelGGL((k_wave1d<T, 512>), grid, dim3(kW1Threads), 0, st, rk, step, K); break;
+    default: hipLaunchKernelGGL((k_wave1d<T, 1024>), grid, dim3(kW1Threads), 0, st, rk, step, K); break;
+    }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_wave1d_batch(const BItem *it, const BItem *host, int n, long s, int K, hipStream_t st)
+hipError_t launch_wave1d_batch(const BItem *it, const BItem *host, int n, long s, int K, int win, hipStream_t st)
 {
-    if (K < 2 || K > W1Cfg<T>::KMAX) return hipErrorInvalidValue;
+    if (K < 2 || K > kW1Kmax) return hipErrorInvalidValue;
     const long blocks = host[n].blk[kWave1];
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((kb_wave1d<T>), dim3((unsigned)blocks), dim3(kW1Threads), 0, st, it, n, s, K);
+    const dim3 grid((unsigned)blocks);
+    switch (win) {
+    case 256: hipLaunchKernelGGL((kb_wave1d<T, 256>), grid, dim3(kW1Threads), 0, st, it, n, s, K); break;
+    case 512: hipLaunchKernelGGL((kb_wave1d<T, 512>), grid, dim3(kW1Threads), 0, st, it, n, s, K); break;
+    default: hipLaunchKernelGGL((kb_wave1d<T, 1024>), grid, dim3(kW1Threads), 0, st, it, n, s, K); break;
+    }
     return hipGetLastError();
 }
 
 template int wave1d_kmax<float>();
 template int wave1d_kmax<double>();
-template long wave1d_tiles<float>(const RunK<float>&);
-template long wave1d_tiles<double>(const RunK<double>&);
-template hipError_t launch_wave1d<float>(const RunK<float> *, const RunK<float>&, long, int, hipStream_t);
-template hipError_t launch_wave1d<double>(const RunK<double> *, const RunK<double>&, long, int, hipStream_t);
-template hipError_t launch_wave1d_batch<float>(const BItem *, const BItem *, int, long, int, hipStream_t);
-template hipError_t launch_wave1d_batch<double>(const BItem *, const BItem *, int, long, int, hipStream_t);
+template long wave1d_tiles<float>(const RunK<float>&, int);
+template long wave1d_tiles<double>(const RunK<double>&, int);
+template hipError_t launch_wave1d<float>(const RunK<float> *, const RunK<float>&, long, int, int, hipStream_t);
+template hipError_t launch_wave1d<double>(const RunK<double> *, const RunK<double>&, long, int, int, hipStream_t);
+template hipError_t launch_wave1d_batch<float>(const BItem *, const BItem *, int, long, int, int, hipStream_t);
+template hipError_t launch_wave1d_batch<double>(const BItem *, const BItem *, int, long, int, int, hipStream_t);
 
 }  // namespace axf

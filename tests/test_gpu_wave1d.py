@@ -22,8 +22,9 @@ from paper_2406_16796_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FIELDS = ["E0Y", "E0Z", "B0Y", "B0Z", "E1Y", "E1Z", "B1Y", "B1Z", "PHI_OLD", "PHI_NEW"]
-# cells of a window and the most steps per pass (FP32, FP64)
-WIN = {"f32": (1024, 32), "f64": (512, 16)}
+# cells of a single run's window and the most steps per pass (FP32, FP64);
+# batches take windows of 512
+WIN = {"f32": (256, 16), "f64": (256, 16)}
 
 
 @pytest.fixture(scope="module")
@@ -112,7 +113,7 @@ def assert_same(runs, records=None):
 @pytest.mark.parametrize("ax_bc", [W.AX_PERIODIC, W.AX_REFLECT, W.AX_OUTFLOW, W.AX_PML])
 @pytest.mark.parametrize("size", ["one_window", "tiles"])
 def test_fused_1d_equals_plain_bitwise(axf, prec, ax_bc, size):
-    n = 300 if size == "one_window" else 2500
+    n = 200 if size == "one_window" else 2500
     runs = both(axf, cfg_1d(n, ax_bc), prec, 301)
     assert runs[1].uses_fused() and not runs[0].uses_fused()
     assert_same(runs)
@@ -128,7 +129,7 @@ def test_fused_1d_shapes_equal_plain_bitwise(axf, prec, case):
     own = w - 2 * (kmax + 1)
     cfg = {
         "gauss_pol_z": lambda: cfg_1d(2000, W.AX_OUTFLOW, env=W.ENV_GAUSS, pol=2),
-        "periodic_em_one_window": lambda: cfg_1d(400, W.AX_PERIODIC, em=W.EM_PERIODIC),
+        "periodic_em_one_window": lambda: cfg_1d(200, W.AX_PERIODIC, em=W.EM_PERIODIC),
         "periodic_em_tiles": lambda: cfg_1d(3 * own + 17, W.AX_PERIODIC, em=W.EM_PERIODIC),
         "exact_window": lambda: cfg_1d(w, W.AX_PERIODIC),
         "window_plus_one": lambda: cfg_1d(w + 1, W.AX_PML),
