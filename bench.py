@@ -57,9 +57,8 @@ WORKLOADS = {
            [CSRC + "axf_fused.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
     "3d": ("focused_3d", "k_march3d", ["k_march3d<{T},{NW},0>", "k_march3d<{T},{NW},1>", "k_march3d<{T},{NW},2>"],
            [CSRC + "axf_march3d.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
-    "1d": ("plane_wave_1d", "plain_step", ["k_e0<1,{T}>", "k_c<1,{T}>", "k_e1<1,{T}>", "k_mur<1,{T}>",
-                                           "k_b<1,{T}>", "k_phi<1,{T}>"],
-           [CSRC + "axf_plain.hip", CSRC + "axf_kernels.h"] + COMMON_SOURCES),
+    "1d": ("plane_wave_1d", "k_wave1d", ["k_wave1d<{T},256>"],
+           [CSRC + "axf_wave1d.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
 }
 
 
@@ -210,6 +209,23 @@ def cpu_baseline(cfg, target_s=12.0):
             "cpu_model": cpu_model(),
             "one_thread": {"value": round(v1, 5), "cores": 1,
                            "sample": "the same sample, %d whole steps in %.1f s" % (steps1, dt1)}}
+
+
+def leg_1d(axf, torch):
+    """The 4096-cell 1D conversion run (FP64, 3000 steps, CW laser, periodic
+    axion, Mur EM), fused passes against the unfused phase sequence, both
+    timed whole with HIP events on the run's stream."""
+    from paper_2406_16796_amd import workloads as W
+    cfg = W.plane_wave_1d()
+    steps = int(cfg["steps"])
+    out = {"workload": workload_tag(cfg, "f64"), "steps": steps}
+    for label, path in (("fused", axf.PATH_FUSED), ("plain", axf.PATH_PLAIN)):
+        _, ms, launches, rec, _ = time_path(axf, torch, cfg, axf.F64, path, steps, 2, 0)
+        out[label] = {"ms": round(ms, 3), "launches": launches,
+                      "Gcell_s": round(int(cfg["n"][0]) * steps / (ms * 1e-3) / 1e9, 3), "p_gen": rec["p_gen"]}
+    out["fused_speedup"] = round(out["plain"]["ms"] / out["fused"]["ms"], 2)
+    out["p_bitwise_equal"] = out["fused"]["p_gen"] == out["plain"]["p_gen"]
+    return out
 
 
 def leg_2d(axf, torch, precision, steps=200):
@@ -537,6 +553,7 @@ def main():
     ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV")
     ap.add_argument("--no-scan", action="store_true")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D 4096^2 leg")
+    ap.add_argument("--no-1d", action="store_true", help="skip the 1D 4096-cell leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shapes")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--steps-scale", type=float, default=0.1,
@@ -647,6 +664,8 @@ def main():
             line[other] = leg_2d(axf, torch, other)
         else:
             line["2d"] = {p: leg_2d(axf, torch, p) for p in ("f32", "f64")}
+    if not args.no_1d and args.workload != "1d":
+        line["1d"] = leg_1d(axf, torch)
     if not args.no_scan:
         line["scan"] = scan_leg(axf, torch, args.steps_scale, tune=not args.no_tune)
     if not args.no_serve:
