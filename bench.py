@@ -329,12 +329,20 @@ def serve_leg(axf, torch, rates, count, steps_scale, pool_gb, max_slots=64, macr
 
     def stats(lat, kinds, span, work):
         small = [v for v, k in zip(lat, kinds) if k < 3]
-        big = [v for v, k in zip(lat, kinds) if k == 3]
         r4 = lambda v: None if v is None else round(v, 4)
-        return {"Gcell_s": round(work / span / 1e9, 3), "req_s": round(len(lat) / span, 2),
-                "p50_s": r4(percentile(lat, 50)), "p99_s": r4(percentile(lat, 99)),
-                "small_p50_s": r4(percentile(small, 50)), "small_p99_s": r4(percentile(small, 99)),
-                "3d_p50_s": r4(percentile(big, 50)), "3d_p99_s": r4(percentile(big, 99))}
+        out = {"Gcell_s": round(work / span / 1e9, 3), "req_s": round(len(lat) / span, 2),
+               "p50_s": r4(percentile(lat, 50)), "p99_s": r4(percentile(lat, 99)),
+               "small_p50_s": r4(percentile(small, 50)), "small_p99_s": r4(percentile(small, 99))}
+        for d in (1, 2, 3):
+            cls = [v for v, k in zip(lat, kinds) if k == d]
+            out["%dd_p50_s" % d] = r4(percentile(cls, 50))
+            out["%dd_p99_s" % d] = r4(percentile(cls, 99))
+        return out
+
+    def progress(label, done, total, t0):
+        if done % 200 == 0 or done == total:
+            print("serving %s: %d/%d done at %.1f s" % (label, done, total, time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
 
     out = []
     for rate in rates:
@@ -356,6 +364,7 @@ def serve_leg(axf, torch, rates, count, steps_scale, pool_gb, max_slots=64, macr
                     raise SystemExit("served request failed with status %d" % r["status"])
                 lat.append(r["t_done"] - r["t_submit"])
                 kinds.append(ndim[ids[r["id"]]])
+                progress("server %g req/s" % rate, len(lat), len(reqs), t0)
             time.sleep(0.0005)
         span = time.perf_counter() - t0
         srv.close()
@@ -372,6 +381,7 @@ def serve_leg(axf, torch, rates, count, steps_scale, pool_gb, max_slots=64, macr
             run.step(n)
             run.diag_now()
             fifo.append(time.perf_counter() - t0 - t_arr)
+            progress("per-request %g req/s" % rate, len(fifo), len(reqs), t0)
             run.close()
             del run
         fifo_span = time.perf_counter() - t0

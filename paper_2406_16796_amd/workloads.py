@@ -49,7 +49,10 @@ def plane_wave_1d(nx=4096, steps=3000, m=0.1, g=1e-4, a0=1e-3, b0=1.0, ppw=20, o
     3000-step FP64 conversion run (lambda/20, dt = 0.95 dx)."""
     lam = TWO_PI / omega
     dx = lam / ppw
-    cfg = _base([nx, 1, 1], [dx, 1.0, 1.0], 0.95 * dx)
+    # dt = 0.95 dx unless that passes the Klein-Gordon limit of the leapfrog,
+    # dx / sqrt(1 + (m dx / 2)^2) (heavy axions on coarse grids): then 0.95 of it
+    limit = dx / math.sqrt(1.0 + (m * dx / 2.0) ** 2)
+    cfg = _base([nx, 1, 1], [dx, 1.0, 1.0], 0.95 * dx if 0.95 * dx <= limit else 0.95 * limit)
     cfg.update(em_bc=[EM_MUR, 0, 0], ax_bc=[ax_bc, 0, 0], m=m, g=g, bext=[0.0, b0, 0.0],
                laser_on=1, laser_pol=1, laser_env=ENV_CW, omega=omega, e_amp=a0 * omega,
                ramp_periods=4.0, steps=steps, name="1d_cw_%d" % nx)
