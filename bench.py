@@ -319,7 +319,7 @@ def percentile(v, q):
     return v[k]
 
 
-def serve_leg(axf, torch, rates, count, steps_scale, pool_gb, max_slots=64, macro=16):
+def serve_leg(axf, torch, rates, count, steps_scale, pool_gb, max_slots=64, macro=16, with_fifo=True):
     """Poisson arrivals of conversion requests (90% like the scan, 10% 3D
     128^3-256^3), served by the continuous-batching server and, for the same
     trace, one request at a time in arrival order (per-request launches).
@@ -370,6 +370,12 @@ def serve_leg(axf, torch, rates, count, steps_scale, pool_gb, max_slots=64, macr
         srv.close()
         del srv
         torch.cuda.empty_cache()
+        point = {"offered_req_s": rate, "requests": len(reqs), "cell_updates": work,
+                 "server": stats(lat, kinds, span, work)}
+        print("serving %g req/s, server: %s" % (rate, json.dumps(point["server"])), file=sys.stderr, flush=True)
+        if not with_fifo:
+            out.append(point)
+            continue
         # the same trace, one request at a time in arrival order
         fifo = []
         t0 = time.perf_counter()
@@ -386,9 +392,8 @@ def serve_leg(axf, torch, rates, count, steps_scale, pool_gb, max_slots=64, macr
             del run
         fifo_span = time.perf_counter() - t0
         torch.cuda.empty_cache()
-        out.append({"offered_req_s": rate, "requests": len(reqs), "cell_updates": work,
-                    "server": stats(lat, kinds, span, work),
-                    "fifo_per_request": stats(fifo, ndim, fifo_span, work)})
+        point["fifo_per_request"] = stats(fifo, ndim, fifo_span, work)
+        out.append(point)
     return {"steps_scale": steps_scale, "pool_GB": pool_gb, "max_slots": max_slots,
             "slice_cell_updates": macro * (1 << 20), "points": out}
 
@@ -570,6 +575,8 @@ def main():
                     help="step counts of the scan and serving legs relative to the workload's 1000-5000")
     ap.add_argument("--serve-rates", default="8,32,128")
     ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-no-fifo", action="store_true",
+                    help="serve only (no one-request-at-a-time pass over the same trace)")
     ap.add_argument("--serve-slice", type=int, default=256,
                     help="server work slice per run and round, in units of 2^20 cell-updates")
     args = ap.parse_args()
@@ -681,7 +688,7 @@ def main():
     if not args.no_serve:
         rates = [float(v) for v in args.serve_rates.split(",") if v]
         line["serving"] = serve_leg(axf, torch, rates, args.serve_requests, args.steps_scale, pool_gb=64,
-                                    macro=args.serve_slice)
+                                    macro=args.serve_slice, with_fifo=not args.serve_no_fifo)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)
