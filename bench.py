@@ -339,10 +339,13 @@ def serve_leg(axf, torch, rates, count, steps_scale, pool_gb, max_slots=64, macr
             out["%dd_p99_s" % d] = r4(percentile(cls, 99))
         return out
 
+    last = [0.0]
+
     def progress(label, done, total, t0):
-        if done % 200 == 0 or done == total:
-            print("serving %s: %d/%d done at %.1f s" % (label, done, total, time.perf_counter() - t0),
-                  file=sys.stderr, flush=True)
+        t = time.perf_counter() - t0
+        if done % 50 == 0 or done == total or t - last[0] > 15.0:
+            last[0] = t
+            print("serving %s: %d/%d done at %.1f s" % (label, done, total, t), file=sys.stderr, flush=True)
 
     out = []
     for rate in rates:

@@ -455,12 +455,17 @@ int axf_batch_destroy(axf_batch *b)
 // join the batched launches of the runs already on the device and small runs
 // are not held behind large ones.  Runs that reach their step count (or are cancelled) are retired:
 // their final diagnostic record becomes the result and their memory returns to
-// the pool.  A request passed over for more than kStarveRounds rounds stops
-// later requests from overtaking it.
+// the pool.  Queued requests are considered in the order of a deadline: the
+// arrival time plus the request's work (cells x steps) at kRefRate, so a
+// burst is admitted shortest first while a large request overtakes every
+// request that arrives more than its own service time after it.  A request
+// passed over for more than kStarveRounds rounds for want of memory stops the
+// requests after it in that order from overtaking it.
 
 namespace {
 
 constexpr int kStarveRounds = 4;
+constexpr double kRefRate = 1e10;   // cell-updates per second of the deadline
 
 struct Request {
     uint64_t id;
@@ -469,6 +474,7 @@ struct Request {
     size_t bytes;
     double t_submit;
     int skipped = 0;
+    double deadline() const { return t_submit + (double)cfg.n[0] * cfg.n[1] * cfg.n[2] * (double)nsteps / kRefRate; }
 };
 
 struct Resident {
@@ -603,6 +609,9 @@ struct axf_server {
                     if (cancels.erase(r.id)) r.cancel = true;
                 int slots = max_slots - (int)res.size();
                 bool blocked = false;
+                // earliest deadline first (ties: arrival order)
+                std::stable_sort(queue.begin(), queue.end(),
+                                 [](const Request& a, const Request& b) { return a.deadline() < b.deadline(); });
                 for (auto it = queue.begin(); it != queue.end() && slots > 0;) {
                     size_t off;
                     if (!blocked && alloc.take(it->bytes, &off)) {
