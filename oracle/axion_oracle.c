@@ -85,6 +85,12 @@ struct ora_state {
     double *Sax;                   /* scratch: g E0.B0 at centres */
     double *Eh[2][3];              /* E at t_n - dt/2 on the first ORA_WIN_KEEP x columns (window moves) */
     long   step;
+    /* particles (Sec. II.B): zero-order position x^n and momentum u^n = p/(mc),
+       first-order ones, density carried (0: absorbed); current at t_n on the E
+       points of both orders */
+    long   np;
+    double *px[3], *pu[3], *px1[3], *pu1[3], *pw;
+    double *J[2][3];
 };
 
 /* columns of E^{n-1/2} kept for a move of the window (the most one move shifts) */
@@ -341,17 +347,20 @@ static double face_S(const ora_state *s, int c, int i, int j, int k)
     return 0.5 * (s->C[c][IX(s, lo[0], lo[1], lo[2])] + s->C[c][IX(s, hi[0], hi[1], hi[2])]);
 }
 
-/* E_o += h (curl B_o - g S) over every E point; g S only for order 1 */
+/* E_o += h (curl B_o - j_o - g S) over every E point; g S only for order 1,
+   j only with particles (the current at the time of the half step) */
 static void update_E(ora_state *s, int o, double h, double g)
 {
     for (int c = 0; c < 3; c++) {
         int e0 = extent(s, 0, c == 0), e1 = extent(s, 1, c == 1), e2 = extent(s, 2, c == 2);
         double *E = s->E[o][c];
+        const double *J = s->J[o][c];
         #pragma omp parallel for collapse(2) schedule(static)
         for (int k = 0; k < e2; k++)
             for (int j = 0; j < e1; j++)
                 for (int i = 0; i < e0; i++) {
                     double rhs = curl_B(s, o, c, i, j, k);
+                    if (J) rhs = rhs - J[IX(s, i, j, k)];
                     if (o == 1) rhs = rhs - g * face_S(s, c, i, j, k);
                     E[IX(s, i, j, k)] += h * rhs;
                 }
@@ -401,7 +410,7 @@ static void mur_ghosts(ora_state *s)
                         }
                         pg[d] = coord(s, d, igh, 0);
                         for (int o = 0; o < 2; o++) {
-                            int inj = (o == 0 && d == 0 && side == 0);
+                            int inj = (o == s->c.laser_order && d == 0 && side == 0);
                             double ia_new = inj ? ora_incident(s, c, pa[0], pa[1], pa[2], t_new) : 0.0;
                             double ia_old = inj ? ora_incident(s, c, pa[0], pa[1], pa[2], t_old) : 0.0;
                             double ig_new = inj ? ora_incident(s, c, pg[0], pg[1], pg[2], t_new) : 0.0;
@@ -519,6 +528,269 @@ static void keep_half_columns(ora_state *s)
                         s->Eh[o][c][((long)k * s->nn[1] + j) * ORA_WIN_KEEP + i] = s->E[o][c][IX(s, i, j, k)];
 }
 
+/* ------------------------------------------------------------ particles */
+
+/* Sec. II.B.  Zero order: cold electrons (q = -1, m = 1) pushed by E0 and
+   B0 + B_ext (Boris); first order: the perturbations x1, u1 of the same push,
+   driven by the fields a particle feels to first order,
+     F_p = sum S(r - x0) F1 + sum (grad S(r - x0) . x1) F0,
+   i.e. the push's derivative: dp1/dt = q (E_p + v0 x B_p + v1 x B_nop) with
+   v1 = (gamma0^2 u1 - u0 (u0.u1)) / gamma0^3.  Currents, deposited at the E
+   points with the same shape:
+     j0 = q w S(r - x0) v0,   j1 = q w [(grad S(r - x0) . x1) v0 + S(r - x0) v1].
+   The shape S is linear (one cell wide) along every active axis, on each
+   component's own staggered points.  Time levels: x^n, u^n at integer times;
+   a step drifts x half a step with v^n, kicks u with E^{n+1/2}, B^{n+1/2} at
+   that midpoint, drifts again with v^{n+1}, and deposits j^{n+1} at x^{n+1}
+   for the second E half step (and the first one of the next step). */
+
+typedef struct {
+    int i[2];            /* the two points */
+    double w[2], dw[2];  /* weights and their d/dx */
+    int m;               /* points used: 1 on a degenerate axis */
+} ora_shape;
+
+static void shape1(const ora_state *s, int d, int nodal, double x, ora_shape *sh)
+{
+    if (s->n[d] == 1) {
+        sh->m = 1;
+        sh->i[0] = sh->i[1] = 0;
+        sh->w[0] = 1.0; sh->w[1] = 0.0;
+        sh->dw[0] = sh->dw[1] = 0.0;
+        return;
+    }
+    double u = x / s->c.dx[d] - (nodal ? 0.0 : 0.5);
+    double f0 = floor(u), f = u - f0;
+    int i0 = (int)f0, i1 = i0 + 1;
+    if (em_periodic(s, d)) {
+        i0 = wrapn(i0, s->n[d]);
+        i1 = wrapn(i1, s->n[d]);
+    } else if (i0 < 0 || i1 >= extent(s, d, nodal)) {
+        die("particle shape");
+    }
+    sh->m = 2;
+    sh->i[0] = i0; sh->i[1] = i1;
+    sh->w[0] = 1.0 - f; sh->w[1] = f;
+    sh->dw[0] = -1.0 / s->c.dx[d]; sh->dw[1] = 1.0 / s->c.dx[d];
+}
+
+static void shapes(const ora_state *s, int c, int isB, const double X[3], ora_shape sh[3])
+{
+    for (int d = 0; d < 3; d++) shape1(s, d, isB ? d != c : d == c, X[d], &sh[d]);
+}
+
+/* F(X) = sum S F and sum (grad S . dX) F for component c of F, on the E
+   points or the B points (isB), the zero-order B with B_ext added (bext) */
+static void gather(const ora_state *s, const double *F, int c, int isB, int bext, const double X[3],
+                   const double dX[3], double *val, double *grad)
+{
+    ora_shape sh[3];
+    shapes(s, c, isB, X, sh);
+    double v = 0.0, g = 0.0;
+    for (int a2 = 0; a2 < sh[2].m; a2++)
+        for (int a1 = 0; a1 < sh[1].m; a1++)
+            for (int a0 = 0; a0 < sh[0].m; a0++) {
+                double f = F[IX(s, sh[0].i[a0], sh[1].i[a1], sh[2].i[a2])];
+                if (bext) f += bext_at(s, c, sh[0].i[a0]);
+                double w = sh[0].w[a0] * sh[1].w[a1] * sh[2].w[a2];
+                double gw = sh[0].dw[a0] * sh[1].w[a1] * sh[2].w[a2] * dX[0]
+                          + sh[0].w[a0] * sh[1].dw[a1] * sh[2].w[a2] * dX[1]
+                          + sh[0].w[a0] * sh[1].w[a1] * sh[2].dw[a2] * dX[2];
+                v += w * f;
+                g += gw * f;
+            }
+    *val = v;
+    *grad = g;
+}
+
+/* J_c += a S(r - X) + b (grad S(r - X) . dX) at the E_c points */
+static void deposit(ora_state *s, double *J, int c, const double X[3], const double dX[3], double a, double b)
+{
+    ora_shape sh[3];
+    shapes(s, c, 0, X, sh);
+    for (int a2 = 0; a2 < sh[2].m; a2++)
+        for (int a1 = 0; a1 < sh[1].m; a1++)
+            for (int a0 = 0; a0 < sh[0].m; a0++) {
+                double w = sh[0].w[a0] * sh[1].w[a1] * sh[2].w[a2];
+                double gw = sh[0].dw[a0] * sh[1].w[a1] * sh[2].w[a2] * dX[0]
+                          + sh[0].w[a0] * sh[1].dw[a1] * sh[2].w[a2] * dX[1]
+                          + sh[0].w[a0] * sh[1].w[a1] * sh[2].dw[a2] * dX[2];
+                J[IX(s, sh[0].i[a0], sh[1].i[a1], sh[2].i[a2])] += a * w + b * gw;
+            }
+}
+
+/* on a Mur axis a particle counts while it stays 1.5 cells inside the
+   faces (its shape then reaches interior points only); periodic axes wrap */
+static int place(const ora_state *s, double X[3])
+{
+    for (int d = 0; d < 3; d++) {
+        if (s->n[d] == 1) continue;
+        double L = s->n[d] * s->c.dx[d];
+        if (em_periodic(s, d)) {
+            if (X[d] < 0.0) X[d] += L;
+            if (X[d] >= L) X[d] -= L;
+        } else if (X[d] < 1.5 * s->c.dx[d] || X[d] > L - 1.5 * s->c.dx[d]) {
+            return 0;
+        }
+    }
+    return 1;
+}
+
+static void cross(const double a[3], const double b[3], double out[3])
+{
+    out[0] = a[1] * b[2] - a[2] * b[1];
+    out[1] = a[2] * b[0] - a[0] * b[2];
+    out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Boris rotation (J. P. Boris 1970) of u by the fields E, B with
+   hq = q dt / (2 m), and its derivative along (du, dE, dB) */
+static void boris(const double u[3], const double du[3], const double E[3], const double dE[3], const double B[3],
+                  const double dB[3], double hq, double un[3], double dun[3])
+{
+    double um[3], dum[3], t[3], dtv[3], up[3], dup[3], sv[3], ds[3], c1[3], c2[3];
+    for (int q = 0; q < 3; q++) {
+        um[q] = u[q] + hq * E[q];
+        dum[q] = du[q] + hq * dE[q];
+    }
+    double g = sqrt(1.0 + dot(um, um)), dg = dot(um, dum) / g;
+    for (int q = 0; q < 3; q++) {
+        t[q] = hq * B[q] / g;
+        dtv[q] = hq * dB[q] / g - hq * B[q] * dg / (g * g);
+    }
+    double tt = dot(t, t), dtt = 2.0 * dot(t, dtv), den = 1.0 + tt;
+    for (int q = 0; q < 3; q++) {
+        sv[q] = 2.0 * t[q] / den;
+        ds[q] = 2.0 * dtv[q] / den - 2.0 * t[q] * dtt / (den * den);
+    }
+    cross(um, t, c1);
+    for (int q = 0; q < 3; q++) up[q] = um[q] + c1[q];
+    cross(dum, t, c1);
+    cross(um, dtv, c2);
+    for (int q = 0; q < 3; q++) dup[q] = dum[q] + c1[q] + c2[q];
+    cross(up, sv, c1);
+    double upl[3], dupl[3];
+    for (int q = 0; q < 3; q++) upl[q] = um[q] + c1[q];
+    cross(dup, sv, c1);
+    cross(up, ds, c2);
+    for (int q = 0; q < 3; q++) dupl[q] = dum[q] + c1[q] + c2[q];
+    for (int q = 0; q < 3; q++) {
+        un[q] = upl[q] + hq * E[q];
+        dun[q] = dupl[q] + hq * dE[q];
+    }
+}
+
+/* velocity v = u / gamma and its derivative (gamma^2 du - u (u.du)) / gamma^3 */
+static void velocity(const double u[3], const double du[3], double v[3], double dv[3])
+{
+    double g = sqrt(1.0 + dot(u, u)), ud = dot(u, du);
+    for (int q = 0; q < 3; q++) {
+        v[q] = u[q] / g;
+        dv[q] = (g * g * du[q] - u[q] * ud) / (g * g * g);
+    }
+}
+
+static void zero_currents(ora_state *s)
+{
+    for (int o = 0; o < 2; o++)
+        for (int c = 0; c < 3; c++)
+            if (s->J[o][c]) memset(s->J[o][c], 0, sizeof(double) * s->ncell);
+}
+
+/* j0 and j1 of one particle at X, dX with velocity v, dv */
+static void deposit_particle(ora_state *s, long p, const double X[3], const double dX[3], const double v[3],
+                             const double dv[3])
+{
+    const double qw = -1.0 * s->pw[p];
+    for (int c = 0; c < 3; c++) {
+        deposit(s, s->J[0][c], c, X, dX, qw * v[c], 0.0);
+        deposit(s, s->J[1][c], c, X, dX, qw * dv[c], qw * v[c]);
+    }
+}
+
+void ora_redeposit(ora_state *s)
+{
+    if (!s->np) return;
+    zero_currents(s);
+    for (long p = 0; p < s->np; p++) {
+        if (s->pw[p] == 0.0) continue;
+        double X[3], dX[3], u[3], du[3], v[3], dv[3];
+        for (int q = 0; q < 3; q++) {
+            X[q] = s->px[q][p]; dX[q] = s->px1[q][p]; u[q] = s->pu[q][p]; du[q] = s->pu1[q][p];
+        }
+        velocity(u, du, v, dv);
+        deposit_particle(s, p, X, dX, v, dv);
+    }
+}
+
+/* one step of every particle with the fields as they are (E^{n+1/2},
+   B^{n+1/2}), then j^{n+1}; particles in index order, so every sum has a
+   fixed order */
+static void push_particles(ora_state *s)
+{
+    if (!s->np) return;
+    const double dt = s->c.dt, hq = -0.5 * dt;
+    zero_currents(s);
+    for (long p = 0; p < s->np; p++) {
+        if (s->pw[p] == 0.0) continue;
+        double X[3], dX[3], u[3], du[3], v[3], dv[3];
+        for (int q = 0; q < 3; q++) {
+            X[q] = s->px[q][p]; dX[q] = s->px1[q][p]; u[q] = s->pu[q][p]; du[q] = s->pu1[q][p];
+        }
+        velocity(u, du, v, dv);
+        for (int q = 0; q < 3; q++) {
+            X[q] += 0.5 * dt * v[q];
+            dX[q] += 0.5 * dt * dv[q];
+        }
+        if (!place(s, X)) { s->pw[p] = 0.0; continue; }
+        double E0[3], Ep[3], B0[3], Bp[3];
+        for (int c = 0; c < 3; c++) {
+            double f, gf, f1, g1;
+            gather(s, s->E[0][c], c, 0, 0, X, dX, &f, &gf);
+            gather(s, s->E[1][c], c, 0, 0, X, dX, &f1, &g1);
+            E0[c] = f;
+            Ep[c] = f1 + gf;
+            gather(s, s->B[0][c], c, 1, 1, X, dX, &f, &gf);
+            gather(s, s->B[1][c], c, 1, 0, X, dX, &f1, &g1);
+            B0[c] = f;
+            Bp[c] = f1 + gf;
+        }
+        double un[3], dun[3];
+        boris(u, du, E0, Ep, B0, Bp, hq, un, dun);
+        velocity(un, dun, v, dv);
+        for (int q = 0; q < 3; q++) {
+            X[q] += 0.5 * dt * v[q];
+            dX[q] += 0.5 * dt * dv[q];
+        }
+        int in = place(s, X);
+        for (int q = 0; q < 3; q++) {
+            s->px[q][p] = X[q]; s->px1[q][p] = dX[q]; s->pu[q][p] = un[q]; s->pu1[q][p] = dun[q];
+        }
+        if (!in) { s->pw[p] = 0.0; continue; }
+        deposit_particle(s, p, X, dX, v, dv);
+    }
+}
+
+long ora_particles(const ora_state *s) { return s->np; }
+
+double *ora_particle_array(ora_state *s, int id)
+{
+    if (!s->np || id < 0 || id > 12) return NULL;
+    if (id < 3) return s->px[id];
+    if (id < 6) return s->pu[id - 3];
+    if (id < 9) return s->px1[id - 6];
+    if (id < 12) return s->pu1[id - 9];
+    return s->pw;
+}
+
+double *ora_current(ora_state *s, int o, int c)
+{
+    if (o < 0 || o > 1 || c < 0 || c > 2) return NULL;
+    return s->J[o][c];
+}
+
 /* ------------------------------------------------------------ one step */
 
 static void one_step(ora_state *s)
@@ -535,6 +807,7 @@ static void one_step(ora_state *s)
     compute_Sax(s);                /* g E0.B0 at t_{n+1/2} */
     update_phi(s, La, Lb, Ln);     /* phi^{n+3/2}, eq. update_axion (PML form in the layer) */
     axion_ghosts(s, La, Lb, Ln);
+    push_particles(s);             /* x, u to t_{n+1} with E, B at t_{n+1/2}; j^{n+1} (Sec. II.B) */
     update_B(s, h);                /* B^{n+1} */
     update_E(s, 0, h, 0.0);        /* E0^{n+1} */
     compute_C(s, Lb, Ln, La);      /* axion current at t_{n+1} (E0^{n+1}, B0^{n+1}) */
@@ -705,9 +978,10 @@ static void init_mur_history(ora_state *s)
                         pg[d] = coord(s, d, igh, 0);
                         for (int o = 0; o < 2; o++) {
                             double rhs = curl_B(s, o, c, id[0], id[1], id[2]);
+                            if (s->J[o][c]) rhs = rhs - s->J[o][c][IX(s, id[0], id[1], id[2])];
                             if (o == 1) rhs = rhs - g * face_S(s, c, id[0], id[1], id[2]);
                             s->mur_a[o][d][side][c][f] = s->E[o][c][IX(s, id[0], id[1], id[2])] - h * rhs;
-                            int inj = (o == 0 && d == 0 && side == 0);
+                            int inj = (o == s->c.laser_order && d == 0 && side == 0);
                             s->mur_g[o][d][side][c][f] = inj ? ora_incident(s, c, pg[0], pg[1], pg[2], t_old) : 0.0;
                         }
                     }
@@ -748,6 +1022,16 @@ int ora_create(const ora_config *cfg, ora_state **out)
     }
     if (!(cfg->dt > 0.0) || cfg->dt * cfg->dt * inv2 >= 1.0) return -1;
     if (cfg->laser_on && (cfg->em_bc[0] != ORA_EM_MUR || (cfg->laser_pol != 1 && cfg->laser_pol != 2))) return -1;
+    if (cfg->laser_order != 0 && cfg->laser_order != 1) return -1;
+    if (cfg->ppc[0] > 0) {
+        /* particles: 1D or 2D, periodic transverse axes, the plasma two cells
+           inside a Mur x axis */
+        if (cfg->n[2] > 1 || cfg->ppc[1] < 1 || cfg->plasma_lo < 0 || cfg->plasma_hi > cfg->n[0] ||
+            cfg->plasma_lo >= cfg->plasma_hi || !(cfg->plasma_n > 0.0))
+            return -1;
+        if (cfg->n[1] > 1 && cfg->em_bc[1] != ORA_EM_PERIODIC) return -1;
+        if (cfg->em_bc[0] == ORA_EM_MUR && (cfg->plasma_lo < 2 || cfg->plasma_hi > cfg->n[0] - 2)) return -1;
+    }
 
     ora_state *s = (ora_state *)calloc(1, sizeof(ora_state));
     if (!s) return -1;
@@ -786,6 +1070,31 @@ int ora_create(const ora_config *cfg, ora_state **out)
     s->la = 0;
     s->lb = 1;
     s->step = 0;
+
+    /* the plasma: a lattice of ppc[0] x ppc[1] particles per cell */
+    if (cfg->ppc[0] > 0) {
+        const int px = cfg->ppc[0], py = s->n[1] > 1 ? cfg->ppc[1] : 1;
+        s->np = (long)(cfg->plasma_hi - cfg->plasma_lo) * s->n[1] * px * py;
+        for (int q = 0; q < 3; q++) {
+            s->px[q] = zalloc(s->np); s->pu[q] = zalloc(s->np);
+            s->px1[q] = zalloc(s->np); s->pu1[q] = zalloc(s->np);
+        }
+        s->pw = zalloc(s->np);
+        for (int o = 0; o < 2; o++)
+            for (int c = 0; c < 3; c++) s->J[o][c] = zalloc(s->ncell);
+        long p = 0;
+        for (int j = 0; j < s->n[1]; j++)
+            for (int i = cfg->plasma_lo; i < cfg->plasma_hi; i++)
+                for (int b = 0; b < py; b++)
+                    for (int a = 0; a < px; a++, p++) {
+                        s->px[0][p] = (i + (a + 0.5) / px) * cfg->dx[0];
+                        s->px[1][p] = s->n[1] > 1 ? (j + (b + 0.5) / py) * cfg->dx[1] : 0.0;
+                        s->px[2][p] = 0.0;
+                        for (int q = 0; q < 3; q++) s->pu[q][p] = cfg->plasma_u[q];
+                        s->pw[p] = cfg->plasma_n / (px * py);
+                    }
+        ora_redeposit(s);          /* j^0 */
+    }
 
     /* axion levels at t = -dt/2 and +dt/2 (the two-level start of Sec. III.A) */
     const double dt = cfg->dt;
@@ -837,7 +1146,9 @@ void ora_destroy(ora_state *s)
     for (int c = 0; c < 3; c++) free(s->C[c]);
     free(s->Sax);
     for (int o = 0; o < 2; o++)
-        for (int c = 0; c < 3; c++) free(s->Eh[o][c]);
+        for (int c = 0; c < 3; c++) { free(s->Eh[o][c]); free(s->J[o][c]); }
+    for (int q = 0; q < 3; q++) { free(s->px[q]); free(s->pu[q]); free(s->px1[q]); free(s->pu1[q]); }
+    free(s->pw);
     for (int d = 0; d < 3; d++)
         for (int side = 0; side < 2; side++) {
             for (int L = 0; L < 3; L++) free(s->axg[d][side][L]);

@@ -67,6 +67,18 @@ typedef struct {
     int    packet_on;
     double pk_amp, pk_k, pk_w, pk_x0, pk_y0, pk_z0;
     int    pk_dir;        /* +1 moves to +x, -1 moves to -x */
+    /* which order carries the injected laser: 0 (E0/B0) or 1 (E1/B1, the weak
+       laser of Sec. III.D riding on a strong background) */
+    int    laser_order;
+    /* cold plasma electrons (charge -1, mass 1; immobile neutralising ions),
+       Sec. II.B: ppc[0] x ppc[1] particles per cell on a regular lattice in the
+       cells plasma_lo <= i < plasma_hi along x and every cell along y; density
+       plasma_n in critical densities (omega_p^2 = plasma_n), momentum u = p/(mc)
+       plasma_u at t = 0.  ppc[0] = 0: no particles. */
+    int    ppc[2];
+    double plasma_n;
+    int    plasma_lo, plasma_hi;
+    double plasma_u[3];
 } ora_config;
 
 typedef struct ora_state ora_state;
@@ -94,6 +106,15 @@ void   ora_refresh_initial(ora_state *s);
 void   ora_step(ora_state *s, long nsteps);
 int    ora_shift_window(ora_state *s, int cells);
 long   ora_step_count(const ora_state *s);
+/* particles: count, and their arrays (id 0-2 position x^n, 3-5 momentum u^n,
+   6-8 first-order position, 9-11 first-order momentum, 12 weight (density
+   carried; 0 once absorbed)); current at the E points of order o, component c
+   (j at t_n, the value the next E half step uses), laid out as the fields */
+long   ora_particles(const ora_state *s);
+double *ora_particle_array(ora_state *s, int id);
+double *ora_current(ora_state *s, int o, int c);
+/* recompute j at t_n from the particle arrays as they are (after editing them) */
+void   ora_redeposit(ora_state *s);
 /* energies at the current integer time: out[0] = H_phi, out[1] = H_gamma(E0,B0), out[2] = H_gamma(E1,B1) */
 void   ora_energies(const ora_state *s, double out[3]);
 /* incident laser E component comp (1 = y, 2 = z) at (x, y, z, t); exposed for tests */

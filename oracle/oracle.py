@@ -40,6 +40,8 @@ class OraConfig(ctypes.Structure):
         ("pk_amp", ctypes.c_double), ("pk_k", ctypes.c_double), ("pk_w", ctypes.c_double),
         ("pk_x0", ctypes.c_double), ("pk_y0", ctypes.c_double), ("pk_z0", ctypes.c_double),
         ("pk_dir", ctypes.c_int),
+        ("laser_order", ctypes.c_int), ("ppc", ctypes.c_int * 2), ("plasma_n", ctypes.c_double),
+        ("plasma_lo", ctypes.c_int), ("plasma_hi", ctypes.c_int), ("plasma_u", ctypes.c_double * 3),
     ]
 
 
@@ -90,6 +92,14 @@ def load(path):
     L.ora_energies.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     L.ora_incident.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_double] * 4
     L.ora_incident.restype = ctypes.c_double
+    L.ora_particles.argtypes = [ctypes.c_void_p]
+    L.ora_particles.restype = ctypes.c_long
+    L.ora_particle_array.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.ora_particle_array.restype = ctypes.POINTER(ctypes.c_double)
+    L.ora_current.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    L.ora_current.restype = ctypes.POINTER(ctypes.c_double)
+    L.ora_redeposit.argtypes = [ctypes.c_void_p]
+    L.ora_redeposit.restype = None
     L.ora_threads.restype = ctypes.c_int
     L.ora_set_threads.argtypes = [ctypes.c_int]
     L.ora_set_threads.restype = None
@@ -115,6 +125,12 @@ def make_config(cfg):
     for key in ("omega", "e_amp", "ramp_periods", "fwhm", "t_center", "waist", "x_focus",
                 "y_c", "z_c", "cep", "pk_amp", "pk_k", "pk_w", "pk_x0", "pk_y0", "pk_z0"):
         setattr(c, key, float(cfg.get(key, 0.0)))
+    c.laser_order = int(cfg.get("laser_order", 0))
+    c.ppc[:] = [int(v) for v in cfg.get("ppc", [0, 1])]
+    c.plasma_n = float(cfg.get("plasma_n", 0.0))
+    c.plasma_lo = int(cfg.get("plasma_lo", 0))
+    c.plasma_hi = int(cfg.get("plasma_hi", c.n[0]))
+    c.plasma_u[:] = [float(v) for v in cfg.get("plasma_u", [0.0, 0.0, 0.0])]
     if c.laser_on and c.omega == 0.0:
         raise ValueError("laser needs omega > 0")
     return c
@@ -211,6 +227,33 @@ class Oracle:
     def set_threads(n):
         """Threads of the oracle's loops from now on (timing only)."""
         lib().ora_set_threads(int(n))
+
+    PARTICLE_IDS = {"x": 0, "y": 1, "z": 2, "ux": 3, "uy": 4, "uz": 5, "x1": 6, "y1": 7, "z1": 8,
+                    "u1x": 9, "u1y": 10, "u1z": 11, "w": 12}
+
+    @property
+    def n_particles(self):
+        return self._L.ora_particles(self._h)
+
+    def particles(self, name):
+        """Particle array `name` (x, y, z, ux, uy, uz, their first-order
+        x1 ... u1z, w): a live view."""
+        p = self._L.ora_particle_array(self._h, self.PARTICLE_IDS[name])
+        if not p:
+            return None
+        return np.ctypeslib.as_array(p, shape=(self.n_particles,))
+
+    def current(self, order, comp):
+        """j of order 0/1, component 0-2 at the E points (t_n): a live view."""
+        p = self._L.ora_current(self._h, int(order), int(comp))
+        if not p:
+            return None
+        nz, ny, nx = self.nn[2], self.nn[1], self.nn[0]
+        return np.ctypeslib.as_array(p, shape=(nz * ny * nx,)).reshape(nz, ny, nx)
+
+    def redeposit(self):
+        """j at t_n again from the particle arrays (after editing them)."""
+        self._L.ora_redeposit(self._h)
 
     def incident(self, comp, x, y, z, t):
         return self._L.ora_incident(self._h, comp, x, y, z, t)
