@@ -119,6 +119,22 @@ typedef struct {
        win_t0 >= dt; single runs only (not batches or served requests). */
     double  win_t0;
     int32_t win_cells;
+    /* which order carries the injected laser: 0 (E0/B0) or 1 (E1/B1: the weak
+       laser of Sec. III.D on a strong background).  1 needs the unfused path. */
+    int32_t laser_order;
+    /* Cold plasma electrons, the particle side of the first-order expansion
+       (Sec. II.B): charge -1, mass 1, immobile neutralising ions; ppc[0] x
+       ppc[1] particles per cell on a regular lattice in the cells
+       plasma_lo <= i < plasma_hi along x and every cell along y, density
+       plasma_n in critical densities (omega_p^2 = plasma_n), momentum
+       u = p/(m c) = plasma_u at t = 0.  ppc[0] = 0: no particles.  Particles
+       need ndim 1 or 2, a periodic y axis, the plasma at least two cells
+       inside a Mur x axis and the unfused path (single runs only).  A
+       particle that comes within 1.5 cells of a Mur face stops depositing. */
+    int32_t ppc[2];
+    double  plasma_n;
+    int32_t plasma_lo, plasma_hi;
+    double  plasma_u[3];
 } axf_config;
 
 /* one diagnostic record at integer time t = step * dt, all FP64, descaled
@@ -198,6 +214,17 @@ int axf_step(axf_run *run, int64_t nsteps);
    dst: host (dst_is_device = 0) or device memory of dst_bytes >= nn[0] nn[1]
    nn[2] * 8.  Synchronises the run's stream.  Errors: EINVAL, EHIP. */
 int axf_read_field(axf_run *run, int32_t field_id, void *dst, size_t dst_bytes, int32_t dst_is_device);
+
+/* Particle arrays of a run with a plasma (Sec. II.B), as dense FP64 true
+   values (descaled) into host memory: id 0-2 position x^n, 3-5 momentum
+   u^n = p/(mc), 6-8 the first-order position x1, 9-11 the first-order
+   momentum u1, 12 the density each particle carries (0 once absorbed), at
+   the current integer time t_n; `max` >= the particle count (*n on return).
+   The currents are deposited with atomic additions, so a run is
+   reproducible to their rounding order, not bit for bit.  Synchronises the
+   run's stream.  Errors: EINVAL (no particles, bad id), ENOMEM (max too
+   small), EHIP. */
+int axf_read_particles(axf_run *run, int32_t id, double *dst, int64_t max, int64_t *n);
 
 /* The diagnostic record of Sec. III.B/C at the current time t_n: H_phi,
    H_gamma0, H_gamma1 in FP64, P_gamma->phi = H_phi / H_gamma0,

@@ -22,7 +22,7 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 
 EXPORTS = [
     "axf_last_error", "axf_version", "axf_footprint", "axf_extents", "axf_create", "axf_write_field",
-    "axf_step", "axf_read_field", "axf_diag_now", "axf_diag_now_static", "axf_read_diag", "axf_state_bytes", "axf_read_state",
+    "axf_step", "axf_read_field", "axf_read_particles", "axf_diag_now", "axf_diag_now_static", "axf_read_diag", "axf_state_bytes", "axf_read_state",
     "axf_write_state", "axf_sync", "axf_steps_done", "axf_path_in_use", "axf_destroy", "axf_last_step_timing",
     "axf_tune", "axf_tune_reset", "axf_batch_footprint", "axf_batch_create", "axf_batch_step", "axf_batch_run", "axf_batch_destroy",
     "axf_server_create", "axf_server_submit", "axf_server_cancel", "axf_server_poll", "axf_server_stats",
@@ -55,6 +55,8 @@ class Config(ctypes.Structure):
         ("pk_dir", ctypes.c_int32),
         ("diag_every", ctypes.c_int32), ("path", ctypes.c_int32),
         ("win_t0", ctypes.c_double), ("win_cells", ctypes.c_int32),
+        ("laser_order", ctypes.c_int32), ("ppc", ctypes.c_int32 * 2), ("plasma_n", ctypes.c_double),
+        ("plasma_lo", ctypes.c_int32), ("plasma_hi", ctypes.c_int32), ("plasma_u", ctypes.c_double * 3),
     ]
 
 
@@ -114,6 +116,7 @@ def lib():
         "axf_write_field": ([vp, i32, vp, sz, i32], ctypes.c_int),
         "axf_step": ([vp, i64], ctypes.c_int),
         "axf_read_field": ([vp, i32, vp, sz, i32], ctypes.c_int),
+        "axf_read_particles": ([vp, i32, P(dp), i64, P(i64)], ctypes.c_int),
         "axf_diag_now": ([vp, P(DiagRecord)], ctypes.c_int),
         "axf_diag_now_static": ([vp, i32, P(DiagRecord)], ctypes.c_int),
         "axf_read_diag": ([vp, P(DiagRecord), i32, P(i32)], ctypes.c_int),
@@ -182,6 +185,12 @@ def make_config(cfg, precision=F64, diag_every=0, path=PATH_AUTO):
     c.path = int(cfg.get("path", path))
     c.win_t0 = float(cfg.get("win_t0", 0.0))
     c.win_cells = int(cfg.get("win_cells", 0))
+    c.laser_order = int(cfg.get("laser_order", 0))
+    c.ppc[:] = [int(v) for v in cfg.get("ppc", [0, 1])]
+    c.plasma_n = float(cfg.get("plasma_n", 0.0))
+    c.plasma_lo = int(cfg.get("plasma_lo", 0))
+    c.plasma_hi = int(cfg.get("plasma_hi", n[0]))
+    c.plasma_u[:] = [float(v) for v in cfg.get("plasma_u", [0.0, 0.0, 0.0])]
     return c
 
 
@@ -318,6 +327,21 @@ class Run:
         check(lib().axf_read_field(self._h, FIELD_ID[name], out.ctypes.data_as(ctypes.c_void_p),
                                    out.nbytes, 0))
         return out.reshape(self.nn[2], self.nn[1], self.nn[0])
+
+    PARTICLE_ID = {"x": 0, "y": 1, "z": 2, "ux": 3, "uy": 4, "uz": 5, "x1": 6, "y1": 7, "z1": 8,
+                   "u1x": 9, "u1y": 10, "u1z": 11, "w": 12}
+
+    def read_particles(self, name):
+        """Particle array `name` (x, y, z, ux, uy, uz, the first-order x1 ...
+        u1z, w) at the current time as float64 (axf_read_particles)."""
+        cnt = int(self.cfg.ppc[0]) * max(1, int(self.cfg.ppc[1]) if self.cfg.n[1] > 1 else 1) * \
+            (int(self.cfg.plasma_hi) - int(self.cfg.plasma_lo)) * int(self.cfg.n[1])
+        out = np.empty(max(cnt, 1), dtype=np.float64)
+        n = ctypes.c_int64()
+        check(lib().axf_read_particles(self._h, self.PARTICLE_ID[name],
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size,
+                                       ctypes.byref(n)))
+        return out[:n.value]
 
     def write(self, name, arr):
         a = np.ascontiguousarray(np.broadcast_to(np.asarray(arr, dtype=np.float64),

@@ -365,6 +365,8 @@ static int batch_layout(const axf_config *cfgs, int32_t count, std::vector<size_
     for (int32_t i = 0; i < count; i++) {
         int rc = validate(&cfgs[i]);
         if (rc == AXF_OK && cfgs[i].win_cells != 0) rc = fail(AXF_EINVAL, "batches take fixed windows only");
+        if (rc == AXF_OK && (cfgs[i].ppc[0] > 0 || cfgs[i].laser_order != 0))
+            rc = fail(AXF_EINVAL, "batches take runs without particles and with a zero-order laser");
         if (rc) return fail(rc, "run %d: %s", i, axf_last_error());
         if (offs) offs->push_back(off);
         off += align256(make_layout(&cfgs[i]).total);
@@ -718,6 +720,8 @@ int axf_server_submit(axf_server *s, const axf_config *cfg, int64_t nsteps, uint
     if (nsteps <= 0) return fail(AXF_EINVAL, "nsteps must be positive");
     int rc = validate(cfg);
     if (rc == AXF_OK && cfg->win_cells != 0) rc = fail(AXF_EINVAL, "served requests take fixed windows only");
+    if (rc == AXF_OK && (cfg->ppc[0] > 0 || cfg->laser_order != 0))
+        rc = fail(AXF_EINVAL, "served requests take runs without particles and with a zero-order laser");
     if (rc) return rc;
     const size_t bytes = align256(make_layout(cfg).total);
     if (bytes > s->pool_bytes) return fail(AXF_ENOMEM, "request of %zu bytes exceeds the pool of %zu", bytes, s->pool_bytes);

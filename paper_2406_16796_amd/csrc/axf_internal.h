@@ -12,6 +12,7 @@ namespace axf {
 // Laser injected through x_min (parameters in FP64).
 struct Laser {
     int on, pol, env, q;          // q = number of transverse axes of the beam profile
+    int order;                    // the field order the laser is injected into (0 or 1)
     double omega, e_amp, ramp_t, tau0, t_center, waist, x_focus, y_c, z_c, cep, zr;
 };
 
@@ -116,6 +117,16 @@ struct RunK {
     int diag_blocks;
     axf_diag_record *rec;     // device ring of records (slot chosen by the host)
     int rec_cap;
+    // particles (Sec. II.B): count; arrays x y z, ux uy uz (zero order), the
+    // same of first order (stored scaled by 1/s_1 like E1), density carried;
+    // currents j0, j1 (j1 scaled) at the E points, t_n (null without particles)
+    long np;
+    T *pa[13];
+    T *J[2][3];
+    // the initial lattice: particles per cell, first plasma cell, density per
+    // particle, initial momentum
+    int ppc[2], plasma_lo, plasma_cells;
+    T pw0, pu0[3];
 };
 
 __host__ __device__ inline long round_up(long v, long m) { return (v + m - 1) / m * m; }

@@ -35,6 +35,17 @@ struct Plain {
     static void batch_diag(const BItem *it, const BItem *host, int n, long s, long ev, hipStream_t st);
 };
 
+// The particle side of the first-order expansion (2D runs with a plasma):
+// the initial lattice and its current j^0, the current of the particles as
+// they are, and one step of every particle (after the step's B and axion
+// updates; it leaves dt j^{n+1} for the next E updates).
+template <typename T>
+struct Particles {
+    static void init(const RunK<T> *rk, const RunK<T>& h, hipStream_t st);
+    static void deposit(const RunK<T> *rk, const RunK<T>& h, hipStream_t st);
+    static void push(const RunK<T> *rk, const RunK<T>& h, long step, hipStream_t st);
+};
+
 // device address of the static diagnostic workspace on device `dev` (looked up
 // once per device and kept); hipSuccess or the lookup's error
 hipError_t static_workspace(int dev, double **ptr);

@@ -39,7 +39,8 @@ __device__ __forceinline__ bool in_cell(const RunK<T>& r, int i, int j, int k)
     return i < r.n[0] && j < r.n[1] && k < r.n[2];
 }
 
-// E0_out = E0_in + scale * dt curl B0   (scale 1: step; -1/2: backward half step)
+// E0_out = E0_in + scale * dt (curl B0 - j0)   (scale 1: step; -1/2: backward
+// half step; j0 only with particles, stored as dt j0)
 template <int D, typename T>
 __device__ __forceinline__ void e0_at(const RunK<T>& r, int i, int j, int k, int s_in, int s_b, int s_out, T scale)
 {
@@ -48,6 +49,7 @@ __device__ __forceinline__ void e0_at(const RunK<T>& r, int i, int j, int k, int
     for (int c = 0; c < 3; c++) {
         if (!actE0<D>(c) || !in_E<D>(r, c, i, j, k)) continue;
         T rhs = curl_B<D, 0>(r, r.B0[s_b], c, i, j, k, id);
+        if (r.J[0][c]) rhs = rhs - r.J[0][c][id];
         r.E0[s_out][c][id] = r.E0[s_in][c][id] + scale * rhs;
     }
 }
@@ -231,7 +233,7 @@ __device__ __forceinline__ T face_S(const RunK<T>& r, int c, int i, int j, int k
     return r.half * (C[id + (long)(lo - v) * st] + C[id + (long)(hi - v) * st]);
 }
 
-// E1_out = E1_in + scale * dt (curl B1 - g1 S)
+// E1_out = E1_in + scale * dt (curl B1 - j1 - g1 S)   (j1 only with particles)
 template <int D, typename T>
 __device__ __forceinline__ void e1_at(const RunK<T>& r, int i, int j, int k, int s_in, int s_b, int s_out, T scale)
 {
@@ -239,7 +241,11 @@ __device__ __forceinline__ void e1_at(const RunK<T>& r, int i, int j, int k, int
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         if (!actE1<D>(c) || !in_E<D>(r, c, i, j, k)) continue;
-        T rhs = curl_B<D, 1>(r, r.B1[s_b], c, i, j, k, id) - r.cg1 * face_S<D>(r, c, i, j, k, id);
+        T rhs;
+        if (r.J[1][c])
+            rhs = (curl_B<D, 1>(r, r.B1[s_b], c, i, j, k, id) - r.J[1][c][id]) - r.cg1 * face_S<D>(r, c, i, j, k, id);
+        else
+            rhs = curl_B<D, 1>(r, r.B1[s_b], c, i, j, k, id) - r.cg1 * face_S<D>(r, c, i, j, k, id);
         r.E1[s_out][c][id] = r.E1[s_in][c][id] + scale * rhs;
     }
 }
@@ -279,12 +285,20 @@ __device__ __forceinline__ void mur_point(const RunK<T>& r, long step, int d, in
     double e_old = (double)Eo[c][id], e_new = (double)En[c][id];
     double g_old = (double)r.murg[O][d][side][c][s_old][f];
     double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
-    if (O == 0 && d == 0 && side == 0 && r.las.on && c == r.las.pol) {
+    if (O == r.las.order && d == 0 && side == 0 && r.las.on && c == r.las.pol) {
         const long lo = (step % r.inc_k1) * 2 * r.inc_face, ln = ((step + 1) % r.inc_k1) * 2 * r.inc_face;
         ia_o = r.inc[lo + f];
         ig_o = r.inc[lo + r.inc_face + f];
         ia_n = r.inc[ln + f];
         ig_n = r.inc[ln + r.inc_face + f];
+        if (O == 1) {
+            // the first-order fields are stored divided by s_1
+            const double is1 = 1.0 / r.s_1;
+            ia_o *= is1;
+            ig_o *= is1;
+            ia_n *= is1;
+            ig_n *= is1;
+        }
     }
     double sa_o = e_old - ia_o, sa_n = e_new - ia_n, sg_o = g_old - ig_o;
     double sg_n = sa_o + r.murc[d] * (sa_n - sg_o);
@@ -347,12 +361,12 @@ __global__ void k_mur_init(const RunK<T> *__restrict__ rp)
             T *g = r.murg[o][d][side][c][0];
             if (!g) continue;
             double v = 0.0;
-            if (o == 0 && d == 0 && side == 0 && r.las.on) {
+            if (o == r.las.order && d == 0 && side == 0 && r.las.on) {
                 int id3[3];
                 id3[0] = 0; id3[a] = ia; id3[b] = ib;
                 double y = (c == 1) ? id3[1] * r.dx[1] : (id3[1] + 0.5) * r.dx[1];
                 double z = (c == 2) ? id3[2] * r.dx[2] : (id3[2] + 0.5) * r.dx[2];
-                v = incident(r.las, c, -0.5 * r.dx[0], y, z, -0.5 * r.dt);
+                v = incident(r.las, c, -0.5 * r.dx[0], y, z, -0.5 * r.dt) / (o == 1 ? r.s_1 : 1.0);
             }
             g[p] = (T)v;
         }

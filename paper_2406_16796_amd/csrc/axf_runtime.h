@@ -29,6 +29,9 @@ struct Layout {
     int rec_cap;
     size_t off_rec;
     long inc_face, off_inc;
+    long np;                     // particles (Sec. II.B; 0: none)
+    long off_pa[13];             // their arrays (-1 = absent)
+    long off_j[2][3];            // currents of both orders at the E points (-1 = absent)
     size_t total;
 };
 

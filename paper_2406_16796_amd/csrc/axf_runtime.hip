@@ -101,6 +101,23 @@ int validate(const axf_config *c)
         return fail(AXF_EINVAL, "packet needs w > 0 and dir = +-1");
     if (c->diag_every < 0) return fail(AXF_EINVAL, "diag_every must be >= 0");
     if (c->path < AXF_PATH_AUTO || c->path > AXF_PATH_FUSED) return fail(AXF_EINVAL, "bad path");
+    if (c->laser_order != 0 && c->laser_order != 1) return fail(AXF_EINVAL, "laser_order must be 0 or 1");
+    if (c->ppc[0] < 0) return fail(AXF_EINVAL, "ppc[0] must be >= 0");
+    if (c->ppc[0] > 0) {
+        if (D != 2) return fail(AXF_EINVAL, "particles need ndim 2");
+        if (c->ppc[1] < 1) return fail(AXF_EINVAL, "ppc[1] must be >= 1");
+        if (c->em_bc[1] != AXF_EM_PERIODIC) return fail(AXF_EINVAL, "particles need a periodic y axis");
+        if (c->plasma_lo < 0 || c->plasma_hi > c->n[0] || c->plasma_lo >= c->plasma_hi)
+            return fail(AXF_EINVAL, "plasma cells [%d, %d) outside the grid", c->plasma_lo, c->plasma_hi);
+        if (c->em_bc[0] == AXF_EM_MUR && (c->plasma_lo < 2 || c->plasma_hi > c->n[0] - 2))
+            return fail(AXF_EINVAL, "the plasma must stay two cells inside the Mur x faces");
+        if (!(c->plasma_n > 0.0)) return fail(AXF_EINVAL, "plasma_n must be positive");
+        if (c->plasma_u[2] != 0.0 || c->bext[0] != 0.0 || c->bext[1] != 0.0)
+            return fail(AXF_EINVAL, "2D particles keep the zero-order motion in the plane: plasma_u[2] = 0, B_ext along z");
+        if (c->path == AXF_PATH_FUSED) return fail(AXF_EINVAL, "particle runs take the unfused path");
+        if (c->win_cells != 0) return fail(AXF_EINVAL, "particle runs take a fixed window");
+    }
+    if (c->laser_order == 1 && c->path == AXF_PATH_FUSED) return fail(AXF_EINVAL, "a first-order laser takes the unfused path");
     if (c->win_cells < 0 || c->win_cells > kWinMaxCells)
         return fail(AXF_EINVAL, "win_cells must be 0 (fixed window) .. %d", kWinMaxCells);
     if (c->win_cells > 0) {
@@ -187,6 +204,12 @@ Layout make_layout(const axf_config *c)
     L.off_rec = take((size_t)(L.rec_cap + 1) * sizeof(axf_diag_record));
     L.inc_face = (long)L.nn[1] * L.nn[2];
     L.off_inc = c->laser_on ? (long)take((size_t)kIncLevels * 2 * L.inc_face * sizeof(double)) : -1;
+    // particles and the currents they deposit
+    L.np = c->ppc[0] > 0 ? (long)(c->plasma_hi - c->plasma_lo) * c->n[1] * c->ppc[0] * (c->n[1] > 1 ? c->ppc[1] : 1) : 0;
+    for (int q = 0; q < 13; q++) L.off_pa[q] = L.np ? (long)take((size_t)L.np * es) : -1;
+    for (int o = 0; o < 2; o++)
+        for (int comp = 0; comp < 3; comp++)
+            L.off_j[o][comp] = (L.np && act(o == 0 ? 0 : 2, comp)) ? (long)take(L.arr_bytes) : -1;
     L.total = off;
     return L;
 }
@@ -249,6 +272,7 @@ static void fill_runk(RunK<T>& k, const axf_config *c, const Layout& L, char *ba
     k.las.z_c = c->z_c;
     k.las.cep = c->cep;
     k.las.zr = 0.5 * c->omega * c->waist * c->waist;
+    k.las.order = c->laser_order;
     k.pk.on = c->packet_on;
     k.pk.dir = c->pk_dir;
     k.pk.amp = c->pk_amp;
@@ -286,6 +310,18 @@ static void fill_runk(RunK<T>& k, const axf_config *c, const Layout& L, char *ba
     k.inc = L.off_inc < 0 ? nullptr : (double *)(base + L.off_inc);
     k.inc_k1 = kIncLevels;
     k.inc_face = L.inc_face;
+    k.np = L.np;
+    for (int q = 0; q < 13; q++) k.pa[q] = P(L.off_pa[q]);
+    for (int o = 0; o < 2; o++)
+        for (int comp = 0; comp < 3; comp++) k.J[o][comp] = P(L.off_j[o][comp]);
+    k.ppc[0] = c->ppc[0];
+    k.ppc[1] = c->ppc[1];
+    k.plasma_lo = c->plasma_lo;
+    k.plasma_cells = c->plasma_hi - c->plasma_lo;
+    if (L.np) {
+        k.pw0 = (T)(c->plasma_n / ((double)c->ppc[0] * (c->n[1] > 1 ? c->ppc[1] : 1)));
+        for (int q = 0; q < 3; q++) k.pu0[q] = (T)c->plasma_u[q];
+    }
 }
 
 // Power-of-two scales of the stored first-order quantities: phi / s_phi and
@@ -293,6 +329,12 @@ static void fill_runk(RunK<T>& k, const axf_config *c, const Layout& L, char *ba
 // is exact and keeps the stored values of order one whatever g is.
 static void choose_scales(const axf_config *c, double *s_phi, double *s_1)
 {
+    if (c->laser_order == 1 && c->laser_on && c->e_amp != 0.0) {
+        // a laser of the first order (Sec. III.D) sets the first-order scale
+        *s_phi = 1.0;
+        *s_1 = pow2_near(fabs(c->e_amp));
+        return;
+    }
     double g = fabs(c->g);
     if (!(g > 0.0)) { *s_phi = 1.0; *s_1 = 1.0; return; }
     double pg = pow2_near(g);
@@ -357,6 +399,10 @@ static void steps_plain(Run *R, int64_t nsteps)
         P::mur(rk, h, s, st);
         P::b(rk, h, s, st);
         P::phi(rk, h, s, st);
+        if (h.np) {
+            Particles<T>::push(rk, h, s, st);
+            R->launches += 2;
+        }
         if (R->cfg.diag_every > 0 && s % R->cfg.diag_every == 0) {
             P::diag(rk, h, s, R->rec_written % h.rec_cap, st);
             R->rec_written++;
@@ -548,6 +594,8 @@ static int steps_wave1d(Run *R, int64_t nsteps)
 // the fused kernels need the axion to be periodic wherever the EM field is
 bool fused_supported(const axf_config *c)
 {
+    // particles and a first-order laser take the unfused kernels
+    if (c->ppc[0] > 0 || c->laser_order != 0) return false;
     for (int d = 0; d < c->ndim; d++)
         if (c->em_bc[d] == AXF_EM_PERIODIC && c->ax_bc[d] != AXF_AX_PERIODIC) return false;
     return true;
@@ -614,6 +662,7 @@ static void init_state(Run *R)
 {
     Plain<D, T>::init_phi(R->rk<T>(), R->hk<T>(), R->stream);
     Plain<D, T>::mur_init(R->rk<T>(), R->hk<T>(), R->stream);
+    Particles<T>::init(R->rk<T>(), R->hk<T>(), R->stream);
 }
 
 int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStream_t stream)
@@ -825,6 +874,24 @@ int run_read_field(Run *R, int id, void *dst, size_t dst_bytes, int dst_is_devic
     for (size_t q = 0; q < cnt; q++) out[q] *= scale;
     if (dst_is_device) HIPCHK(hipMemcpy(dst, out.data(), cnt * 8, hipMemcpyHostToDevice));
     else memcpy(dst, out.data(), cnt * 8);
+    return AXF_OK;
+}
+
+// particle array `id` (0-12, see axf_read_particles) as FP64 true values
+static int read_particles(Run *R, int id, double *dst, int64_t max, int64_t *n)
+{
+    if (R->L.np == 0) return fail(AXF_EINVAL, "the run has no particles");
+    if (id < 0 || id > 12) return fail(AXF_EINVAL, "particle array id %d outside 0..12", id);
+    if (max < R->L.np) return fail(AXF_ENOMEM, "destination holds %lld values, need %ld", (long long)max, R->L.np);
+    const size_t es = elem_size(&R->cfg);
+    std::vector<char> tmp((size_t)R->L.np * es);
+    HIPCHK(hipStreamSynchronize(R->stream));
+    HIPCHK(hipMemcpy(tmp.data(), R->base + R->L.off_pa[id], tmp.size(), hipMemcpyDeviceToHost));
+    // the first-order arrays are stored divided by s_1
+    const double scale = (id >= 6 && id < 12) ? R->s_1 : 1.0;
+    for (long p = 0; p < R->L.np; p++)
+        dst[p] = (es == 4 ? (double)((const float *)tmp.data())[p] : ((const double *)tmp.data())[p]) * scale;
+    *n = R->L.np;
     return AXF_OK;
 }
 
@@ -1230,6 +1297,12 @@ int axf_read_field(axf_run *run, int32_t field_id, void *dst, size_t dst_bytes, 
 {
     if (!run || !dst) return fail(AXF_EINVAL, "null argument");
     return run_read_field(run, field_id, dst, dst_bytes, dst_is_device);
+}
+
+int axf_read_particles(axf_run *run, int32_t id, double *dst, int64_t max, int64_t *n)
+{
+    if (!run || !dst || !n) return fail(AXF_EINVAL, "null argument");
+    return read_particles(run, id, dst, max, n);
 }
 
 int axf_diag_now(axf_run *run, axf_diag_record *out)
