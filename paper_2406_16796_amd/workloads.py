@@ -99,6 +99,51 @@ def focused_3d(n=512, steps=2000, m=0.3, g=1e-4, a0=1e-2, ppw=12, waist_lam=6.0,
     return cfg
 
 
+def weak_laser_plasma_2d(nx=12000, ny=100, n0=3e-3, pulse_fwhm_periods=2.0, plasma_from_lam=2.0,
+                         b_over_bc=1e-20, plasma=True):
+    """The FPS check of Sec. III.D: a laser so weak (its magnetic field 1e-20
+    B_c) that it is carried by the first-order fields alone, propagating
+    along x through a plasma of density n0 (critical densities) magnetised
+    along z by B_c = m_e omega_p / e (normalised: B_c = omega_p =
+    sqrt(n0), so omega_c = omega_p), polarised along y (perpendicular to
+    B_c: the extraordinary wave).  Box 40 x 100 lambda0 on 12000 x 100
+    cells (lambda0/300 along x), Mur x faces, periodic y; cold electrons,
+    one per cell, at rest in the cells from plasma_from_lam to 2 cells before
+    x_max; a Gaussian plane-wave pulse of pulse_fwhm_periods periods (FWHM).
+    plasma=False: the same run in vacuum."""
+    lam = TWO_PI
+    dx, dy = 40.0 * lam / nx, 100.0 * lam / ny
+    cfg = _base([nx, ny, 1], [dx, dy, 1.0], yee_dt([dx, dy], 2))
+    bc = math.sqrt(n0)
+    fwhm = pulse_fwhm_periods * lam
+    tau0 = fwhm / math.sqrt(2.0 * math.log(2.0))
+    cfg.update(ndim=2, em_bc=[EM_MUR, EM_PERIODIC, 0], ax_bc=[AX_OUTFLOW, AX_PERIODIC, 0], m=0.0, g=0.0,
+               bext=[0.0, 0.0, bc], slab_lo=0, slab_hi=nx, laser_on=1, laser_pol=1, laser_env=ENV_GAUSS,
+               laser_order=1, omega=1.0, e_amp=b_over_bc * bc, fwhm=fwhm, t_center=3.0 * tau0, waist=0.0,
+               name="fps_weak_laser_%dx%d" % (nx, ny))
+    if plasma:
+        cfg.update(ppc=[1, 1], plasma_n=n0, plasma_lo=int(round(plasma_from_lam * lam / dx)), plasma_hi=nx - 2,
+                   plasma_u=[0.0, 0.0, 0.0])
+    return cfg
+
+
+def xmode_group_velocity(n0, omega=1.0, omega_c=None):
+    """Group velocity of the extraordinary wave in a cold magnetised plasma
+    (Sec. III.D): eta^2 = 1 - (wp^2/w^2)(w^2 - wp^2)/(w^2 - wp^2 - wc^2) and
+    v_g = c eta / (eta^2 + w^2 d(eta^2)/d(w^2)), the derivative in closed
+    form; wc = wp when omega_c is None."""
+    a = n0
+    c2 = a if omega_c is None else omega_c ** 2
+    w = omega * omega
+    eta2 = 1.0 - (a / w) * (w - a) / (w - a - c2)
+    # d/dw of (a/w)(w - a)/(w - a - c2)
+    f = (w - a) / (w * (w - a - c2))
+    df = ((w * (w - a - c2)) - (w - a) * (2.0 * w - a - c2)) / (w * (w - a - c2)) ** 2
+    deta2 = -a * df
+    eta = math.sqrt(eta2)
+    return eta / (eta2 + w * deta2), eta
+
+
 def packet_2d(n=400, ppw=10, m=None, w_lam=5.0, ax_bc=AX_OUTFLOW, steps=None):
     """Left-moving Gaussian axion packet of the boundary check of Sec. III.A:
     box [-20, 20] lambda squared on 400x400 cells, w = 5 lambda, k = k_0,
