@@ -59,7 +59,11 @@ WORKLOADS = {
            [CSRC + "axf_march3d.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
     "1d": ("plane_wave_1d", "k_wave1d", ["k_wave1d<{T},256>"],
            [CSRC + "axf_wave1d.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
+    "fps": ("weak_laser_plasma_2d", "k_push", ["k_push<{T}>", "k_jzero<{T}>"],
+            [CSRC + "axf_particles.hip", CSRC + "axf_kernels.h"] + COMMON_SOURCES),
 }
+# particle state words a push reads (x, y, u, x1, y1, u1, w) and writes (all but w)
+PARTICLE_WORDS = 11 + 10
 
 
 def pattern_label(p):
@@ -225,6 +229,33 @@ def leg_1d(axf, torch):
                       "Gcell_s": round(int(cfg["n"][0]) * steps / (ms * 1e-3) / 1e9, 3), "p_gen": rec["p_gen"]}
     out["fused_speedup"] = round(out["plain"]["ms"] / out["fused"]["ms"], 2)
     out["p_bitwise_equal"] = out["fused"]["p_gen"] == out["plain"]["p_gen"]
+    return out
+
+
+def leg_fps(axf, torch, steps=1000):
+    """The weak-laser plasma of Sec. III.D (12000 x 100 cells, one cold
+    electron per cell, FP32): the step with the particles against the same
+    grid in vacuum, both timed with HIP events on the run's stream.  The
+    difference is the particle kernels' share of a step (the push and the
+    zeroing of the current arrays); the push moves PARTICLE_WORDS words of
+    particle state per particle."""
+    from paper_2406_16796_amd import workloads as W
+    out = {}
+    for label, plasma in (("plasma", True), ("vacuum", False)):
+        cfg = W.weak_laser_plasma_2d(plasma=plasma)
+        _, ms, launches, rec, _ = time_path(axf, torch, cfg, axf.F32, axf.PATH_AUTO, steps, 2, 0)
+        out[label] = {"ms_per_step": round(ms / steps, 5), "launches_per_step": round(launches / steps, 2)}
+        if plasma:
+            npart = (cfg["plasma_hi"] - cfg["plasma_lo"]) * cfg["n"][1] * cfg["ppc"][0] * cfg["ppc"][1]
+            out["workload"] = workload_tag(cfg, "f32")
+            out["particles"] = npart
+    dt_s = (out["plasma"]["ms_per_step"] - out["vacuum"]["ms_per_step"]) * 1e-3
+    out["particle_ms_per_step"] = round(dt_s * 1e3, 5)
+    out["particle_pushes_per_s"] = round(out["particles"] / dt_s, 1) if dt_s > 0 else None
+    gbs = out["particles"] * PARTICLE_WORDS * 4 / dt_s / 1e9 if dt_s > 0 else None
+    out["particle_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None,
+                                "bytes_per_particle": PARTICLE_WORDS * 4}
     return out
 
 
@@ -496,6 +527,10 @@ def trace_summary(args):
                  "the first on a second stream, so their durations overlap and the step time is the "
                  "span of the three."
                  if args.workload == "3d" else
+                 "With particles a step is the unfused field phases (`k_e0`, `k_c`, `k_e1`, `k_mur`, `k_b`, "
+                 "`k_phi`), then `k_jzero<T>` clearing the current arrays and `k_push<T>` (one thread per "
+                 "particle: the push, its first-order derivative, the atomic deposit of both currents)."
+                 if args.workload == "fps" else
                  "In 2D a pass of NS steps is `k_wave2d_pass<T, PD, NS, MODE>` over the interior with NS "
                  "`k_wave2d` launches over the boundary frame beside it on a second stream.  A pass of three "
                  "or four steps splits its interior into a core launch (MODE 1) and a ring launch (MODE 2, on "
@@ -572,6 +607,7 @@ def main():
     ap.add_argument("--no-scan", action="store_true")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D 4096^2 leg")
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D 4096-cell leg")
+    ap.add_argument("--no-fps", action="store_true", help="skip the weak-laser plasma (particles) leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shapes")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--steps-scale", type=float, default=0.1,
@@ -686,6 +722,8 @@ def main():
             line["2d"] = {p: leg_2d(axf, torch, p) for p in ("f32", "f64")}
     if not args.no_1d and args.workload != "1d":
         line["1d"] = leg_1d(axf, torch)
+    if not args.no_fps and args.workload != "fps":
+        line["fps"] = leg_fps(axf, torch)
     if not args.no_scan:
         line["scan"] = scan_leg(axf, torch, args.steps_scale, tune=not args.no_tune)
     if not args.no_serve:

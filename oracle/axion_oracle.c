@@ -38,7 +38,10 @@
  * Sec. III.A, the conversion probability of Sec. III.B, the Mur faces
  * (plane-wave transmission of the injected laser; a normal pulse leaving
  * through x_max and y_max), and the first-order effect of the literal
- * reading of the time derivative (ORA_DTPHI_LITERAL).  The Gaussian
+ * reading of the time derivative (ORA_DTPHI_LITERAL).  Particles (Sec.
+ * II.B): Boris gyration in closed form, the k = 0 Langmuir recurrence, and
+ * the first-order particles and fields against a central difference of two
+ * zero-order runs (copies with a planted slip fail it).  The Gaussian
  * envelope and focused profile of the injected laser have no formula in the
  * paper and no pin (parity unpinned).
  */
