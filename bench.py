@@ -511,16 +511,18 @@ def trace_summary(args):
     kernel, pats = WORKLOADS[args.workload][1], step_patterns(args.workload, args.precision)
     rows = list(csv.DictReader(open(args.trace_summary)))
     cmd = ("python3 $REPO/bench.py --workload %s --precision %s --steps %d --warmup %d --plain-steps %d "
-           "--no-cpu-baseline --no-scan --no-serve --no-2d --no-tune"
-           % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps))
+           % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps)) + (
+        "--profile-only" if args.workload == "fps" else "--no-cpu-baseline --no-scan --no-serve --no-2d --no-tune")
     lines = ["# Kernel trace of bench.py, workload %s" % tag, "",
              "    cd /tmp && export TMPDIR=/tmp",
              "    timeout -k 10 300 rocprofv3 --kernel-trace --stats -d $OUT/kt -o kt --output-format csv -- " + cmd,
              "    python3 $REPO/bench.py --workload %s --precision %s --steps %d --warmup %d --plain-steps %d "
              "--trace-summary $OUT/kt/kt_kernel_stats.csv"
              % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps), "",
-             "The run times the fused path twice (with and without diagnostics) and the unfused phase "
-             "sequence once; the copy kernel is the bandwidth calibration.  " + (
+             ("The run steps the workload once (the particle path: unfused field phases and the particle "
+              "kernels); the copy kernel is the bandwidth calibration.  " if args.workload == "fps" else
+              "The run times the fused path twice (with and without diagnostics) and the unfused phase "
+              "sequence once; the copy kernel is the bandwidth calibration.  ") + (
                  "In 3D one step is `k_march3d<T, NW, 0>` over the interior box (every workgroup clear "
                  "of the faces), `k_march3d<T, NW, 1>` over the two x-face segment columns and "
                  "`k_march3d<T, NW, 2>` over the rest of the boundary frame; the last two run beside "
@@ -538,7 +540,7 @@ def trace_summary(args):
                  "one launch (MODE 0)."), "",
              "| kernel | calls | mean us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in rows:
-        name = r["Name"]
+        name = r["Name"].replace("(anonymous namespace)::", "")
         short = name.split("(")[0].replace("void ", "")
         if len(short) > 70:
             short = short[:67] + "..."

@@ -29,26 +29,18 @@ namespace axf {
 
 namespace {
 
-// the two points along axis d of a component nodal (or centred) along d,
-// their weights and the weights' derivatives
+// the two points along axis d (0 or 1: particles move in 2D runs) of a
+// component nodal (or centred) along d, their weights and the weights'
+// derivatives
 template <typename T>
 struct Sh1 {
     int i[2];
     T w[2], dw[2];
-    int m;
 };
 
 template <typename T>
 __device__ __forceinline__ void shape1(const RunK<T>& r, int d, bool nodal, T x, Sh1<T>& s)
 {
-    if (d >= r.D) {
-        s.m = 1;
-        s.i[0] = s.i[1] = 0;
-        s.w[0] = T(1);
-        s.w[1] = T(0);
-        s.dw[0] = s.dw[1] = T(0);
-        return;
-    }
     const T idx = T(2) * r.inv2dx[d];
     const T u = x * idx - (nodal ? T(0) : T(0.5));
     const T f0 = floor(u), f = u - f0;
@@ -57,7 +49,6 @@ __device__ __forceinline__ void shape1(const RunK<T>& r, int d, bool nodal, T x,
         i0 = wrapi(i0, r.n[d]);
         i1 = wrapi(i1, r.n[d]);
     }
-    s.m = 2;
     s.i[0] = i0;
     s.i[1] = i1;
     s.w[0] = T(1) - f;
@@ -80,8 +71,10 @@ __device__ __forceinline__ void gather(const RunK<T>& r, const T *a, const T *b,
     Sh1<T> sx, sy;
     shape1(r, 0, isB ? c != 0 : c == 0, X[0], sx);
     shape1(r, 1, isB ? c != 1 : c == 1, X[1], sy);
-    for (int q = 0; q < sy.m; q++)
-        for (int p = 0; p < sx.m; p++) {
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
             const long id = lin(r, sx.i[p], sy.i[q], 0);
             T f = a ? (b ? r.half * (a[id] + b[id]) : a[id]) : T(0);
             if (bx) f += bext_at(r, c, sx.i[p]);
@@ -100,8 +93,10 @@ __device__ __forceinline__ void deposit(const RunK<T>& r, T *J, int c, const T X
     Sh1<T> sx, sy;
     shape1(r, 0, c == 0, X[0], sx);
     shape1(r, 1, c == 1, X[1], sy);
-    for (int q = 0; q < sy.m; q++)
-        for (int p = 0; p < sx.m; p++) {
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
             const T w = sx.w[p] * sy.w[q];
             const T gw = sx.dw[p] * sy.w[q] * dX[0] + sx.w[p] * sy.dw[q] * dX[1];
             atomicAdd(&J[lin(r, sx.i[p], sy.i[q], 0)], a * w + b * gw);
@@ -189,6 +184,7 @@ __device__ __forceinline__ void deposit_particle(const RunK<T>& r, T w, const T 
                                                  const T dv[3])
 {
     const T qw = T(-r.dt) * w;
+#pragma unroll
     for (int c = 0; c < 3; c++) {
         deposit(r, r.J[0][c], c, X, dX, qw * v[c], T(0));
         deposit(r, r.J[1][c], c, X, dX, qw * dv[c], qw * v[c]);
@@ -278,6 +274,7 @@ __global__ void __launch_bounds__(256) k_push(const RunK<T> *__restrict__ rp, lo
         return;
     }
     T E0[3], Ep[3], B0[3], Bp[3];
+#pragma unroll
     for (int c = 0; c < 3; c++) {
         T f, gf, f1, g1;
         gather(r, r.E0[sn][c], (const T *)nullptr, c, false, false, X, dX, f, gf);
