@@ -17,7 +17,10 @@
 // at that midpoint, drifts again with v^{n+1}, and deposits dt j^{n+1} at
 // x^{n+1}; the E updates of the next step subtract it.  One thread per
 // particle; the deposit is an atomic addition, so the sums' order (and
-// their last bits) vary from run to run.
+// their last bits) vary from run to run.  Lanes of a wavefront hold
+// consecutive particles, in consecutive cells of a row at the start: a lane
+// adds its lower neighbour's value at the point they share, which halves
+// the atomics of a row of particles.
 //
 // The 2D field set keeps E0x, E0y, B0z and all first-order components, so
 // the zero-order motion stays in the plane (B_ext along z, in-plane initial
@@ -246,16 +249,51 @@ __global__ void __launch_bounds__(256) k_deposit(const RunK<T> *__restrict__ rp)
     deposit_particle(r, w, X, dX, v, dv);
 }
 
+// J_c += a S + b (grad S . dX) at the E_c points, every lane of the wavefront
+// taking part (live: this lane has a particle to deposit).  Along x a lane's
+// upper point is often the next lane's lower point (consecutive particles sit
+// in consecutive cells of a row): the next lane then adds both values with one
+// atomic and this lane leaves that point out.
+template <typename T>
+__device__ __forceinline__ void deposit_w(const RunK<T>& r, T *J, int c, const T X[2], const T dX[2], T a, T b,
+                                          bool live)
+{
+    if (!J) return;
+    Sh1<T> sx, sy;
+    shape1(r, 0, c == 0, X[0], sx);
+    shape1(r, 1, c == 1, X[1], sy);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const long i0 = lin(r, sx.i[0], sy.i[q], 0), i1 = lin(r, sx.i[1], sy.i[q], 0);
+        const T v0 = a * (sx.w[0] * sy.w[q]) + b * (sx.dw[0] * sy.w[q] * dX[0] + sx.w[0] * sy.dw[q] * dX[1]);
+        const T v1 = a * (sx.w[1] * sy.w[q]) + b * (sx.dw[1] * sy.w[q] * dX[0] + sx.w[1] * sy.dw[q] * dX[1]);
+        const long pi1 = __shfl_up(i1, 1), ni0 = __shfl_down(i0, 1);
+        const T pv1 = __shfl_up(v1, 1);
+        const int plive = __shfl_up((int)live, 1), nlive = __shfl_down((int)live, 1);
+        const bool absorb = lane > 0 && plive && pi1 == i0;
+        const bool given = lane < 63 && nlive && ni0 == i1;
+        // a zero term changes no sum (the arrays start at +0), and a plasma at
+        // rest deposits nothing but zeros to zero order
+        const T s0 = absorb ? v0 + pv1 : v0;
+        if (live && s0 != T(0)) atomicAdd(&J[i0], s0);
+        if (live && !given && v1 != T(0)) atomicAdd(&J[i1], v1);
+    }
+}
+
 // one step of every particle with E^{n+1/2} (slot sn) and B^{n+1/2} (mean of
-// slots so and sn), then dt j^{n+1}
+// slots so and sn), then dt j^{n+1}.  Every lane runs to the end (lanes
+// without a live particle take the last particle's values and store nothing),
+// so that the deposit's lane exchanges see the whole wavefront.
 template <typename T>
 __global__ void __launch_bounds__(256) k_push(const RunK<T> *__restrict__ rp, long step)
 {
     const RunK<T>& r = *rp;
-    const long p = blockIdx.x * 256L + threadIdx.x;
-    if (p >= r.np) return;
+    const long p0 = blockIdx.x * 256L + threadIdx.x;
+    const bool valid = p0 < r.np;
+    const long p = valid ? p0 : r.np - 1;
     T w = r.pa[12][p];
-    if (w == T(0)) return;
+    bool live = valid && w != T(0);
     const int so = em_slot(step, r.nem), sn = em_slot(step + 1, r.nem);
     const T hdt = T(0.5 * r.dt), hq = T(-0.5 * r.dt);
     T X[2] = {r.pa[0][p], r.pa[1][p]}, dX[2] = {r.pa[6][p], r.pa[7][p]};
@@ -269,9 +307,14 @@ __global__ void __launch_bounds__(256) k_push(const RunK<T> *__restrict__ rp, lo
         X[d] += hdt * v[d];
         dX[d] += hdt * dv[d];
     }
-    if (!place(r, X)) {
+    if (live && !place(r, X)) {
         r.pa[12][p] = T(0);
-        return;
+        live = false;
+    }
+    if (__ballot(live) == 0) return;   // uniform: the wavefront has nothing left to do
+    if (!live) {
+        X[0] = T(0.5 * r.n[0] * r.dx[0]);
+        X[1] = T(0.5 * r.n[1] * r.dx[1]);
     }
     T E0[3], Ep[3], B0[3], Bp[3];
 #pragma unroll
@@ -294,19 +337,25 @@ __global__ void __launch_bounds__(256) k_push(const RunK<T> *__restrict__ rp, lo
         dX[d] += hdt * dv[d];
     }
     const bool in = place(r, X);
-    r.pa[0][p] = X[0];
-    r.pa[1][p] = X[1];
-    r.pa[6][p] = dX[0];
-    r.pa[7][p] = dX[1];
+    if (live) {
+        r.pa[0][p] = X[0];
+        r.pa[1][p] = X[1];
+        r.pa[6][p] = dX[0];
+        r.pa[7][p] = dX[1];
+        for (int c = 0; c < 3; c++) {
+            r.pa[3 + c][p] = un[c];
+            r.pa[9 + c][p] = dun[c];
+        }
+        if (!in) r.pa[12][p] = T(0);
+    }
+    live = live && in;
+    if (!live) X[0] = T(0.5 * r.n[0] * r.dx[0]), X[1] = T(0.5 * r.n[1] * r.dx[1]);
+    const T qw = T(-r.dt) * w;
+#pragma unroll
     for (int c = 0; c < 3; c++) {
-        r.pa[3 + c][p] = un[c];
-        r.pa[9 + c][p] = dun[c];
+        deposit_w(r, r.J[0][c], c, X, dX, qw * v[c], T(0), live);
+        deposit_w(r, r.J[1][c], c, X, dX, qw * dv[c], qw * v[c], live);
     }
-    if (!in) {
-        r.pa[12][p] = T(0);
-        return;
-    }
-    deposit_particle(r, w, X, dX, v, dv);
 }
 
 unsigned blocks_of(long n) { return (unsigned)((n + 255) / 256); }

@@ -819,18 +819,23 @@ static int field_info(const Run *R, int id, int *kind, int *comp, double *scale)
 
 static size_t dense_count(const Run *R) { return (size_t)R->L.nn[0] * R->L.nn[1] * R->L.nn[2]; }
 
-// device array (padded rows) -> dense host doubles
+// device array (padded rows) -> dense host doubles.  The padded block is
+// copied whole with one linear copy and the rows are unpacked on the host.
 static int fetch(const Run *R, const char *dev, std::vector<double>& out)
 {
-    const size_t es = elem_size(&R->cfg), nx = R->L.nn[0], rows = (size_t)R->L.nn[1] * R->L.nn[2];
-    std::vector<char> tmp(nx * rows * es);
-    HIPCHK(hipMemcpy2D(tmp.data(), nx * es, dev, R->L.px * es, nx * es, rows, hipMemcpyDeviceToHost));
+    const size_t es = elem_size(&R->cfg), nx = R->L.nn[0], px = R->L.px, rows = (size_t)R->L.nn[1] * R->L.nn[2];
+    std::vector<char> tmp(px * rows * es);
+    HIPCHK(hipMemcpy(tmp.data(), dev, tmp.size(), hipMemcpyDeviceToHost));
     out.resize(nx * rows);
-    if (es == 4) {
-        const float *f = (const float *)tmp.data();
-        for (size_t q = 0; q < out.size(); q++) out[q] = f[q];
-    } else {
-        memcpy(out.data(), tmp.data(), out.size() * 8);
+    for (size_t y = 0; y < rows; y++) {
+        const char *row = tmp.data() + y * px * es;
+        double *o = out.data() + y * nx;
+        if (es == 4) {
+            const float *f = (const float *)row;
+            for (size_t x = 0; x < nx; x++) o[x] = f[x];
+        } else {
+            memcpy(o, row, nx * 8);
+        }
     }
     return AXF_OK;
 }
@@ -909,15 +914,21 @@ int run_write_field(Run *R, int id, const void *src, size_t src_bytes, int src_i
     std::vector<double> in(cnt);
     if (src_is_device) HIPCHK(hipMemcpy(in.data(), src, cnt * 8, hipMemcpyDeviceToHost));
     else memcpy(in.data(), src, cnt * 8);
-    const size_t es = elem_size(&R->cfg), nx = R->L.nn[0], rows = cnt / nx;
-    std::vector<char> tmp(cnt * es);
-    for (size_t q = 0; q < cnt; q++) {
-        double v = in[q] / scale;
-        if (es == 4) ((float *)tmp.data())[q] = (float)v;
-        else ((double *)tmp.data())[q] = v;
-    }
+    // the padded block goes down whole (its padding columns as they were),
+    // with linear copies both ways
+    const size_t es = elem_size(&R->cfg), nx = R->L.nn[0], px = R->L.px, rows = cnt / nx;
+    std::vector<char> tmp(px * rows * es);
     HIPCHK(hipStreamSynchronize(R->stream));
-    HIPCHK(hipMemcpy2D((void *)dev, R->L.px * es, tmp.data(), nx * es, nx * es, rows, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(tmp.data(), dev, tmp.size(), hipMemcpyDeviceToHost));
+    for (size_t y = 0; y < rows; y++) {
+        char *row = tmp.data() + y * px * es;
+        for (size_t x = 0; x < nx; x++) {
+            const double v = in[y * nx + x] / scale;
+            if (es == 4) ((float *)row)[x] = (float)v;
+            else ((double *)row)[x] = v;
+        }
+    }
+    HIPCHK(hipMemcpy((void *)dev, tmp.data(), tmp.size(), hipMemcpyHostToDevice));
     return AXF_OK;
 }
 
