@@ -118,6 +118,21 @@ def test_first_order_laser_over_plasma_matches_oracle(axf, prec, plasma, steps):
     assert max(worst.values()) <= (1e-10 if prec == "f64" else 2e-4), worst
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_one_particle_per_cell_matches_oracle(axf, prec):
+    """One particle per cell, as in the weak-laser plasma: consecutive lanes
+    hold particles in consecutive cells of a row, so nearly every lane adds
+    its neighbour's value at the x point they share (the wavefront's first
+    lane and the row ends do not).  The grid's 61 plasma cells per row make
+    wavefronts start mid-row and span two rows."""
+    cfg = coupled_case(nx=77, ny=5)
+    cfg.update(ppc=[1, 1], plasma_lo=8, plasma_hi=69)
+    worst, p99, run, ora = compare(axf, cfg, prec, 100)
+    assert ora.n_particles == 61 * 5
+    assert np.abs(ora.field("E1Z")).max() > 0 and np.abs(ora.particles("u1z")).max() > 0
+    assert max(worst.values()) <= (1e-10 if prec == "f64" else 2e-4), worst
+
+
 def test_fp64_runs_agree_to_rounding(axf):
     cfg = coupled_case()
     runs = []
