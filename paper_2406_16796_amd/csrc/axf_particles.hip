@@ -282,9 +282,11 @@ __device__ __forceinline__ void deposit_w(const RunK<T>& r, T *J, int c, const T
 }
 
 // one step of every particle with E^{n+1/2} (slot sn) and B^{n+1/2} (mean of
-// slots so and sn), then dt j^{n+1}.  Every lane runs to the end (lanes
-// without a live particle take the last particle's values and store nothing),
-// so that the deposit's lane exchanges see the whole wavefront.
+// slots so and sn), then dt j^{n+1}.  Every lane of a wavefront with a live
+// particle runs to the end, so that the deposit's lane exchanges see the
+// whole wavefront: a lane past the last particle reads the last one's state,
+// a lane without a live particle gathers at the grid's centre, and neither
+// stores or deposits anything.
 template <typename T>
 __global__ void __launch_bounds__(256) k_push(const RunK<T> *__restrict__ rp, long step)
 {
