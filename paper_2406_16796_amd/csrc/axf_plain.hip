@@ -10,10 +10,20 @@
 
 namespace axf {
 
+// storage index p -> (i, j, k); 32-bit divisions (a few instructions, not
+// the long 64-bit expansion) whenever the grid's point count fits in them
 template <typename T>
 __device__ __forceinline__ bool decompose(const RunK<T>& r, long p, int& i, int& j, int& k)
 {
     if (p >= r.npts) return false;
+    if (r.npts <= 0xffffffffL) {
+        const unsigned up = (unsigned)p, n0 = (unsigned)r.nn[0], n1 = (unsigned)r.nn[1];
+        const unsigned q = up / n0;
+        i = (int)(up - q * n0);
+        k = (int)(q / n1);
+        j = (int)(q - (unsigned)k * n1);
+        return true;
+    }
     long q = p / r.nn[0];
     i = (int)(p - q * r.nn[0]);
     k = (int)(q / r.nn[1]);
