@@ -133,6 +133,27 @@ def test_one_particle_per_cell_matches_oracle(axf, prec):
     assert max(worst.values()) <= (1e-10 if prec == "f64" else 2e-4), worst
 
 
+def test_checkpoint_resume_of_a_plasma_run(axf):
+    """The state blob holds the particle arrays and the currents the last
+    push deposited: a plasma run resumed from step 40 continues as the run
+    that went on.  The deposits are atomic sums, so the two agree to FP64
+    rounding, not bit for bit."""
+    cfg = coupled_case()
+    a = axf.Run(cfg, precision=axf.F64)
+    a.step(40)
+    blob = a.state()
+    a.step(50)
+    b = axf.Run(cfg, precision=axf.F64)
+    b.load_state(blob)
+    b.step(50)
+    for n in FIELDS:
+        x, y = a.read(n), b.read(n)
+        assert np.abs(x - y).max() <= 1e-12 * max(np.abs(x).max(), 1e-300), n
+    for g_name, _ in PARTS:
+        x, y = a.read_particles(g_name), b.read_particles(g_name)
+        assert np.abs(x - y).max() <= 1e-12 * max(np.abs(x).max(), 1e-300), g_name
+
+
 def test_fp64_runs_agree_to_rounding(axf):
     cfg = coupled_case()
     runs = []
