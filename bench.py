@@ -661,7 +661,7 @@ def main():
                     help="server work slice per run and round, in units of 2^20 cell-updates")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only (--gpus %d requested): the step is a single-GPU kernel; "
+        print("the benchmark runs on one GPU only (--gpus %d requested): the step is a single-GPU kernel; "
               "slab sharding across GPUs is a design, not code" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.pmc_summary:

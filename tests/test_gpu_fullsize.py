@@ -222,7 +222,7 @@ def test_128_crossing_march_matches_oracle(axf, oracle_128, prec):
 
 def test_fp32_probabilities_512_full_run(axf):
     """The 512^3 run's 2000 steps in FP32 and FP64 through the march, records
-    every 100 steps.  Each probability is judged over the records where its
+    every 100 steps.  Each probability is compared over the records where its
     denominator is at least 1% of its peak over the run: P_conv = H_g1 / H_phi
     while the packet is in the box, P_gen = H_phi / H_g0 while the laser is.
     There the FP32 error is within 1e-5 of the window's largest FP64 value,
