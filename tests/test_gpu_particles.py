@@ -133,6 +133,21 @@ def test_one_particle_per_cell_matches_oracle(axf, prec):
     assert max(worst.values()) <= (1e-10 if prec == "f64" else 2e-4), worst
 
 
+def test_particles_absorbed_at_the_mur_faces_match_oracle(axf):
+    """A plasma from 2 cells inside x_min to 2 cells inside x_max, drifting
+    and gyrating: particles that come within 1.5 cells of a Mur face leave
+    the run (weight 0) in the half drift before the gathers or in the one
+    after the kick, on both faces.  FP64, so that both sides take each
+    decision on the same value."""
+    cfg = coupled_case()
+    cfg.update(plasma_lo=2, plasma_hi=62, plasma_u=[0.4, 0.1, 0.0])
+    worst, p99, run, ora = compare(axf, cfg, "f64", 120)
+    w = ora.particles("w")
+    assert (w == 0).sum() > 50 and (w > 0).sum() > 1000
+    assert np.array_equal(run.read_particles("w") == 0, w == 0)
+    assert max(worst.values()) <= 1e-10, worst
+
+
 def test_checkpoint_resume_of_a_plasma_run(axf):
     """The state blob holds the particle arrays and the currents the last
     push deposited: a plasma run resumed from step 40 continues as the run
