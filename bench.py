@@ -61,7 +61,12 @@ WORKLOADS = {
            [CSRC + "axf_wave1d.hip", CSRC + "axf_fused.h"] + COMMON_SOURCES),
     "fps": ("weak_laser_plasma_2d", "k_push", ["k_push<{T}>", "k_jzero<{T}>"],
             [CSRC + "axf_particles.hip", CSRC + "axf_kernels.h"] + COMMON_SOURCES),
+    "window": ("gaussian_2d_window", "k_win_rows", ["k_win_rows<{T}", "k_win_xghosts<{T}>"],
+               [CSRC + "axf_window.hip"] + COMMON_SOURCES),
 }
+# words of each cell a window move reads and writes in 2D (E0x, E0y, B0z, E1,
+# B1, phi at two levels); the boundary planes that move with them are left out
+WINDOW_WORDS_2D = 11
 # particle state words a push reads (x, y, u, x1, y1, u1, w) and writes (all but w)
 PARTICLE_WORDS = 11 + 10
 
@@ -276,6 +281,50 @@ def leg_fps(axf, torch, steps=1000):
     out["particle_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None,
                                 "bytes_per_particle": PARTICLE_WORDS * 4, "window": "late"}
+    return out
+
+
+def window_moves(cfg, n0, n1):
+    """Window moves between steps n0 and n1 (the library's schedule: the
+    window stands win_cells * floor((t - win_t0) / (win_cells dx)) columns
+    along at t = n dt, and has not moved before win_t0)."""
+    def target(n):
+        t = n * cfg["dt"]
+        if n < 1 or t < cfg["win_t0"]:
+            return 0
+        return int(math.floor((t - cfg["win_t0"]) / (cfg["win_cells"] * cfg["dx"][0])))
+    return target(n1) - target(n0)
+
+
+def window_points(cfg):
+    """Storage points of a 2D grid (node counts: n + 1 along a Mur axis)."""
+    from paper_2406_16796_amd import workloads as W
+    return math.prod(int(cfg["n"][d]) + (1 if cfg["em_bc"][d] == W.EM_MUR else 0) for d in range(2))
+
+
+def leg_window(axf, torch, steps=600):
+    """The moving window of Sec. III.B on the 4096^2 FP32 Gaussian-pulse run:
+    the run with a move every 8 columns against the same run standing, both
+    timed with HIP events on the run's stream.  The difference over the
+    moves in the timed steps is the cost of one move; a move reads and
+    writes WINDOW_WORDS_2D words of every cell."""
+    from paper_2406_16796_amd import workloads as W
+    out = {}
+    warm = 8
+    for label, cfg in (("static", W.gaussian_2d()), ("window", W.gaussian_2d_window(8))):
+        _, ms, launches, _, _ = time_path(axf, torch, cfg, axf.F32, axf.PATH_AUTO, steps, warm, 0)
+        out[label] = {"ms_per_step": round(ms / steps, 5)}
+        if label == "window":
+            out["workload"] = workload_tag(cfg, "f32")
+            moves = window_moves(cfg, warm, warm + steps)
+            nn = window_points(cfg)
+            out["moves"] = moves
+            per_move = (out["window"]["ms_per_step"] - out["static"]["ms_per_step"]) * steps / moves
+            out["ms_per_move"] = round(per_move, 4)
+            gbs = 2 * WINDOW_WORDS_2D * 4 * nn / (per_move * 1e-3) / 1e9 if per_move > 0 else None
+            out["move_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": HBM_PEAK_GBS,
+                                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None,
+                                    "bytes_per_move": 2 * WINDOW_WORDS_2D * 4 * nn}
     return out
 
 
@@ -532,14 +581,20 @@ def trace_summary(args):
     rows = list(csv.DictReader(open(args.trace_summary)))
     cmd = ("python3 $REPO/bench.py --workload %s --precision %s --steps %d --warmup %d --plain-steps %d "
            % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps)) + (
-        "--profile-only" if args.workload == "fps" else "--no-cpu-baseline --no-scan --no-serve --no-2d --no-tune")
+        "--profile-only" if args.workload in ("fps", "window") else
+        "--no-cpu-baseline --no-scan --no-serve --no-2d --no-tune")
     lines = ["# Kernel trace of bench.py, workload %s" % tag, "",
              "    cd /tmp && export TMPDIR=/tmp",
              "    timeout -k 10 300 rocprofv3 --kernel-trace --stats -d $OUT/kt -o kt --output-format csv -- " + cmd,
              "    python3 $REPO/bench.py --workload %s --precision %s --steps %d --warmup %d --plain-steps %d "
              "--trace-summary $OUT/kt/kt_kernel_stats.csv"
              % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps), "",
-             ("The run steps the workload once (the particle path: unfused field phases and the particle "
+             ("The run steps the workload once: the fused 2D passes, broken at every move of the window "
+              "(every 8 columns the light crosses).  A move is `k_win_xghosts<T>` (the x-face ghosts after "
+              "the move, one thread per face point) and `k_win_rows<T, R>` (every array's rows shifted left "
+              "in place, a row per workgroup of 256 threads through R registers each).  The copy kernel is "
+              "the bandwidth calibration.  " if args.workload == "window" else
+              "The run steps the workload once (the particle path: unfused field phases and the particle "
               "kernels), first to the late window (the pulse centre three quarters of the way across the "
               "grid, %d steps) and then the profiled steps; the table covers every call, the figures "
               "below it the last %d calls of each kernel (the late window).  The copy kernel is the "
@@ -601,6 +656,15 @@ def trace_summary(args):
                 lines.append("- `%s_mean_us_per_step = %.2f` (%s calls, a launch of the%s interior advances "
                              "%d steps)" % (pattern_label(pat), float(r["AverageNs"]) / 1e3 / ns, r["Calls"],
                                             modes.get(m.group(2), ""), ns))
+    if args.workload == "window":
+        dom = [r for r in rows if pats[0] in r["Name"].replace(" ", "")]
+        if dom:
+            nbytes = 2 * WINDOW_WORDS_2D * 4 * window_points(cfg)
+            us = float(dom[0]["AverageNs"]) / 1e3
+            lines.append("- `bytes_per_move = %d` (%d words of each of %d points, read and written)"
+                         % (nbytes, WINDOW_WORDS_2D, window_points(cfg)))
+            gbs = nbytes / us / 1e3
+            lines.append("- `move_GBs = %.1f` = %.1f%% of %.0f GB/s" % (gbs, 100.0 * gbs / HBM_PEAK_GBS, HBM_PEAK_GBS))
     if args.workload == "3d":
         # the x-face and frame launches run beside the interior one, so their
         # durations overlap: a step is the span from the first start to the
@@ -649,6 +713,7 @@ def main():
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D 4096^2 leg")
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D 4096-cell leg")
     ap.add_argument("--no-fps", action="store_true", help="skip the weak-laser plasma (particles) leg")
+    ap.add_argument("--no-window", action="store_true", help="skip the moving-window leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shapes")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--steps-scale", type=float, default=0.1,
@@ -767,6 +832,8 @@ def main():
         line["1d"] = leg_1d(axf, torch)
     if not args.no_fps and args.workload != "fps":
         line["fps"] = leg_fps(axf, torch)
+    if not args.no_window and args.workload != "window":
+        line["window"] = leg_window(axf, torch)
     if not args.no_scan:
         line["scan"] = scan_leg(axf, torch, args.steps_scale, tune=not args.no_tune)
     if not args.no_serve:

@@ -56,23 +56,54 @@ __global__ void __launch_bounds__(256) k_win_xghosts(const RunK<T> *__restrict__
     }
 }
 
-// One workgroup per row: the row moves left by `cells` in chunks of the
-// workgroup's width.  Every read of a chunk lands before its writes (the
-// barrier), and no later chunk reads what an earlier one wrote: a chunk
-// writes [c0, c0 + w) and reads [c0 + cells, c0 + w + cells).
-template <typename T>
+// One workgroup of 256 threads per row: the row moves left by `cells`.
+// With R > 0 (rows of at most 256 R elements) the whole row passes through
+// registers: every read, one barrier, every write, so that a thread has R
+// loads in flight.  With R = 0 the row goes in chunks of 256: every read of
+// a chunk lands before its writes (the barrier), and no later chunk reads
+// what an earlier one wrote (a chunk writes [c0, c0 + 256) and reads
+// [c0 + cells, c0 + 256 + cells)).
+template <typename T, int R>
 __global__ void __launch_bounds__(256) k_win_rows(WinRows<T> w)
 {
     const long b = blockIdx.x;
     int a = 0;
     while (a + 1 < w.n && w.first[a + 1] <= b) a++;
     T *row = w.base[a] + (b - w.first[a]) * w.pitch[a];
-    for (int c0 = 0; c0 < w.len; c0 += blockDim.x) {
-        const int i = c0 + (int)threadIdx.x;
-        const T v = (i + w.cells < w.len) ? row[i + w.cells] : T(0);
+    const int t = (int)threadIdx.x;
+    if constexpr (R > 0) {
+        T v[R];
+#pragma unroll
+        for (int q = 0; q < R; q++) {
+            const int i = q * 256 + t;
+            v[q] = (i + w.cells < w.len) ? row[i + w.cells] : T(0);
+        }
         __syncthreads();
-        if (i < w.len) row[i] = v;
+#pragma unroll
+        for (int q = 0; q < R; q++) {
+            const int i = q * 256 + t;
+            if (i < w.len) row[i] = v[q];
+        }
+    } else {
+        for (int c0 = 0; c0 < w.len; c0 += 256) {
+            const int i = c0 + t;
+            const T v = (i + w.cells < w.len) ? row[i + w.cells] : T(0);
+            __syncthreads();
+            if (i < w.len) row[i] = v;
+        }
     }
+}
+
+// the row-shift launch for rows of w.len elements
+template <typename T>
+void launch_win_rows(const WinRows<T>& w, long rows, hipStream_t st)
+{
+    const dim3 g((unsigned)rows), b(256);
+    if (w.len <= 4 * 256) hipLaunchKernelGGL((k_win_rows<T, 4>), g, b, 0, st, w);
+    else if (w.len <= 8 * 256) hipLaunchKernelGGL((k_win_rows<T, 8>), g, b, 0, st, w);
+    else if (w.len <= 16 * 256) hipLaunchKernelGGL((k_win_rows<T, 16>), g, b, 0, st, w);
+    else if (w.len <= 32 * 256) hipLaunchKernelGGL((k_win_rows<T, 32>), g, b, 0, st, w);
+    else hipLaunchKernelGGL((k_win_rows<T, 0>), g, b, 0, st, w);
 }
 
 // the run descriptor's slab (window coordinates) and laser switch
@@ -149,7 +180,7 @@ int window_move(Run *R, int cells)
             tot += arrs[a0 + q].rows;
         }
         w.first[w.n] = tot;
-        hipLaunchKernelGGL((k_win_rows<T>), dim3((unsigned)tot), dim3(256), 0, R->stream, w);
+        launch_win_rows<T>(w, tot, R->stream);
     }
     if (hipGetLastError() != hipSuccess) return fail(AXF_EHIP, "window move launch");
     R->win_shifted += cells;

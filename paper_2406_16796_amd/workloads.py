@@ -78,6 +78,15 @@ def gaussian_2d(n=4096, steps=6000, m=0.0, g=1e-5, a0=1e-2, ppw=16, waist_lam=8.
     return cfg
 
 
+def gaussian_2d_window(win_cells=8, **kw):
+    """The 2D Gaussian-pulse run (gaussian_2d) with a moving window from the
+    first step on (Sec. III.B): each time the light has crossed win_cells
+    columns, the window moves by as many."""
+    cfg = gaussian_2d(**kw)
+    cfg.update(win_cells=win_cells, win_t0=cfg["dt"], name="%s_window%d" % (cfg["name"], win_cells))
+    return cfg
+
+
 def focused_3d(n=512, steps=2000, m=0.3, g=1e-4, a0=1e-2, ppw=12, waist_lam=6.0,
                fwhm_lam=10.0, pk_amp=1e-3, pk_w_lam=5.0, seed=2):
     """3D focused Gaussian pulse (E along z) from x_min plus a counter-
