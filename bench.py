@@ -582,7 +582,7 @@ def trace_summary(args):
     cmd = ("python3 $REPO/bench.py --workload %s --precision %s --steps %d --warmup %d --plain-steps %d "
            % (args.workload, args.precision, args.steps, args.warmup, args.plain_steps)) + (
         "--profile-only" if args.workload in ("fps", "window") else
-        "--no-cpu-baseline --no-scan --no-serve --no-2d --no-tune")
+        "--no-cpu-baseline --no-scan --no-serve --no-2d --no-1d --no-fps --no-window --no-tune")
     lines = ["# Kernel trace of bench.py, workload %s" % tag, "",
              "    cd /tmp && export TMPDIR=/tmp",
              "    timeout -k 10 300 rocprofv3 --kernel-trace --stats -d $OUT/kt -o kt --output-format csv -- " + cmd,

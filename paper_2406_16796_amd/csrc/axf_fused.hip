@@ -1791,7 +1791,7 @@ __global__ void __launch_bounds__(256) k_wave2d_pass(const RunK<T> *__restrict__
 
 // batched: every active run of the table, each with its own step and chunk
 template <typename T, bool INTERIOR>
-__global__ void __launch_bounds__(256, INTERIOR ? 1 : 3) kb_wave2d(const BItem *__restrict__ it, int n, long s)
+__global__ void __launch_bounds__(256, INTERIOR ? 1 : (sizeof(T) == 4 ? 5 : 3)) kb_wave2d(const BItem *__restrict__ it, int n, long s)
 {
     constexpr int K = INTERIOR ? kWaveI : kWave;
     const long b = INTERIOR ? xcd_band(blockIdx.x, gridDim.x) : (long)blockIdx.x;
@@ -1816,7 +1816,7 @@ __global__ void __launch_bounds__(256, INTERIOR ? 1 : 3) kb_wave2d(const BItem *
 // s + 1 of the call, each with its own pass shape; KIND selects the interior
 // (kPair) or one of the two frame launches (kFrameA: step s, kFrameB: s + 1)
 template <typename T, int KIND>
-__global__ void __launch_bounds__(256, KIND == kPair ? 1 : 3) kb_wave2d_pair(const BItem *__restrict__ it, int n, long s)
+__global__ void __launch_bounds__(256, KIND == kPair ? 1 : (sizeof(T) == 4 ? 5 : 3)) kb_wave2d_pair(const BItem *__restrict__ it, int n, long s)
 {
     const long b = KIND == kPair ? xcd_band(blockIdx.x, gridDim.x) : (long)blockIdx.x;
     const int i = find_item<KIND>(it, n, b);
@@ -1890,7 +1890,7 @@ __device__ __forceinline__ WaveSplit quad_ring_core(const WavePass<4>& wp)
 }
 
 template <typename T, int KIND>
-__global__ void __launch_bounds__(256, KIND == kQuadFrame ? 3 : 1) kb_wave2d_quad(const BItem *__restrict__ it, int n, long s)
+__global__ void __launch_bounds__(256, KIND == kQuadFrame ? (sizeof(T) == 4 ? 5 : 3) : 1) kb_wave2d_quad(const BItem *__restrict__ it, int n, long s)
 {
     const long b = KIND == kQuadFrame ? (long)blockIdx.x : xcd_band(blockIdx.x, gridDim.x);
     const int i = find_item<KIND>(it, n, b);
