@@ -646,9 +646,25 @@ __device__ __forceinline__ void diag_fold(const RunK<T>& r, long step, const dou
                                           axf_diag_record *dst)
 {
     double v[kDiagSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int blk = threadIdx.x; blk < nparts; blk += blockDim.x)
+    // thread t adds partials t, t + 256, t + 512, ... in that order; the
+    // loads of eight of them are issued before their additions
+    constexpr int kU = 8;
+    const int nt = (int)blockDim.x;
+    int blk = threadIdx.x;
+    for (; blk + (kU - 1) * nt < nparts; blk += kU * nt) {
+        double w[kU][kDiagSums];
 #pragma unroll
-        for (int q = 0; q < kDiagSums; q++) v[q] += part[blk * kDiagSums + q];
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int q = 0; q < kDiagSums; q++) w[u][q] = part[(long)(blk + u * nt) * kDiagSums + q];
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int q = 0; q < kDiagSums; q++) v[q] += w[u][q];
+    }
+    for (; blk < nparts; blk += nt)
+#pragma unroll
+        for (int q = 0; q < kDiagSums; q++) v[q] += part[(long)blk * kDiagSums + q];
     __shared__ double tot[kDiagSums];
     block_sums(v, tot);
     __syncthreads();
