@@ -128,9 +128,11 @@ typedef struct {
        plasma_lo <= i < plasma_hi along x and every cell along y, density
        plasma_n in critical densities (omega_p^2 = plasma_n), momentum
        u = p/(m c) = plasma_u at t = 0.  ppc[0] = 0: no particles.  Particles
-       need ndim 1 or 2, a periodic y axis, the plasma at least two cells
-       inside a Mur x axis and the unfused path (single runs only).  A
-       particle that comes within 1.5 cells of a Mur face stops depositing. */
+       need ndim 2, a periodic y axis, the plasma at least two cells inside a
+       Mur x axis, zero-order motion in the plane (plasma_u[2] = 0, B_ext
+       along z), a fixed window and the unfused path (single runs only);
+       otherwise axf_create fails with EINVAL.  A particle that comes within
+       1.5 cells of a Mur face leaves the run (its density becomes 0). */
     int32_t ppc[2];
     double  plasma_n;
     int32_t plasma_lo, plasma_hi;
