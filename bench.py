@@ -602,7 +602,8 @@ def trace_summary(args):
               "The run times the fused path twice (with and without diagnostics) and the unfused phase "
               "sequence once; the copy kernel is the bandwidth calibration.  ") + (
                  "In 3D one step is `k_march3d<T, NW, 0>` over the interior box (every workgroup clear "
-                 "of the faces), `k_march3d<T, NW, 1>` over the two x-face segment columns and "
+                 "of the faces), `k_march3d<T, NW, 1>` over the columns at both x faces (one wavefront "
+                 "per row holds both faces) and "
                  "`k_march3d<T, NW, 2>` over the rest of the boundary frame; the last two run beside "
                  "the first on a second stream, so their durations overlap and the step time is the "
                  "span of the three."

@@ -93,14 +93,16 @@ hipError_t launch_wave1d_batch(const BItem *it, const BItem *host, int n, long s
 // through LDS): x segments of `wid` own columns, groups of own rows, chunks
 // of `zc` planes.
 struct M3Geom {
-    int nseg, wid;   // x segments and own columns per segment
-    int sx0, sx1;    // the segments clear of the x faces
+    int nseg, wid;   // x segments and own columns per segment (frame launch)
+    int sx0, sx1;    // the interior launch's segments
+    int xi0, wi;     // first own column of interior segment sx0, own columns per interior segment
+    int xa, xc1;     // x-face launch: own columns 0 .. xa - 1 (lanes 2 ..), and xc1 .. nn0 - 1 (lanes 34 ..)
     int nyg;         // row groups
     int gy0, gy1;    // the row groups clear of the y faces
     int nzc;         // plane chunks: [0, zf), pieces of zi planes up to zend, [zend, nn2)
     int zf, zi, zend, nn2;
     int order;       // interior block order (bit 0: row groups fastest; bit 1: a band per XCD)
-    int xb;          // the segments outside [sx0, sx1) have a launch of their own (Mur x, outflow or reflecting axion x)
+    int xb;          // the columns outside the interior segments have a launch of their own (Mur x, outflow or reflecting axion x)
 };
 // the run fits the march (32-bit offsets within an array)
 template <typename T>

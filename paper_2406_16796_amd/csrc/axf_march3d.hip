@@ -157,24 +157,24 @@ __host__ __device__ inline int m3_zb(const M3Geom& g, int k)
 
 // segment, row group and chunk of block b.  The interior launch (mode 0)
 // covers the box of segments [sx0, sx1), row groups [gy0, gy1) and chunks
-// 1 .. nzc - 2.  (C) the inner chunks of those row groups in the segments
-// outside [sx0, sx1) are the x-face launch (mode 1) when g.xb is set.  The
-// frame launch (mode 2) takes the rest: (A) the first and last chunks of
-// every segment and row group, (B) the inner chunks of the row groups outside
-// [gy0, gy1), and (C) when there is no x-face launch.
+// 1 .. nzc - 2.  (C) the inner chunks of those row groups in the columns
+// outside the interior segments are the x-face launch (mode 1) when g.xb is
+// set: one block per row group and chunk, whose wavefronts hold the columns
+// of both x faces.  The frame launch (mode 2) takes the rest in segments of
+// wid columns: (A) the first and last chunks of every segment and row group,
+// (B) the inner chunks of the row groups outside [gy0, gy1), and (C) when
+// there is no x-face launch, in which case the interior segments are those of
+// the frame's split.
 __host__ __device__ inline void m3_block(const M3Geom& g, int mode, unsigned b, int& seg, int& ygr, int& zch)
 {
     const unsigned nsx = (unsigned)(g.sx1 - g.sx0), ny = (unsigned)(g.gy1 - g.gy0), nzi = (unsigned)(g.nzc - 2);
     if (mode == 1) {
-        // row groups fastest (a segment's only neighbours here are along y),
+        // row groups fastest (a block's only neighbours here are along y),
         // with a band of the order per XCD as in the interior launch
-        const unsigned nfx = (unsigned)g.nseg - nsx;
-        if (g.order & 2) b = (unsigned)xcd_band((long)b, (long)(nfx * ny * nzi));
+        if (g.order & 2) b = (unsigned)xcd_band((long)b, (long)(ny * nzi));
         ygr = g.gy0 + (int)(b % ny);
-        const unsigned r = b / ny;
-        const int k = (int)(r % nfx);
-        seg = k < g.sx0 ? k : g.sx1 + (k - g.sx0);
-        zch = 1 + (int)(r / nfx);
+        seg = 0;
+        zch = 1 + (int)(b / ny);
         return;
     }
     if (mode == 0) {
@@ -245,14 +245,17 @@ __host__ __device__ inline void m3_block(const M3Geom& g, int mode, unsigned b, 
 //
 // MODE 0 is the launch over the segments, row groups and plane chunks whose
 // columns, rows and planes (halos included) keep clear of every face and do
-// not wrap: it has no boundary code.  MODE 1 takes the segments that hold an
-// x face of a run with Mur x faces and an outflow or reflecting axion x
-// boundary, in the row groups and plane chunks of the interior: the code of
-// mode 0 plus that face, whose ghosts every lane computes and stores (lanes
-// other than the ghost's to the sink), the uniform face values read through
-// the scalar cache, so that it too issues the same vector memory
-// instructions in every iteration.  MODE 2 covers the rest (the frame),
-// every boundary included.
+// not wrap: it has no boundary code.  MODE 1 takes the columns at both x
+// faces of a run with Mur x faces and an outflow or reflecting axion x
+// boundary, in the row groups and plane chunks of the interior, each
+// wavefront holding both faces (lanes 0 .. 31 x_min, 32 .. 63 x_max, each
+// half with two halo lanes on its inner side): the code of mode 0 plus the
+// faces, whose ghosts every lane computes from its half's face values and
+// stores (lanes other than a ghost's to the sink), the uniform face values
+// of both faces read through the scalar cache, so that it too issues the
+// same vector memory instructions in every iteration.  A lane shift across
+// lanes 31 / 32 reaches only halo lanes, as lane 0's and lane 63's reach
+// nothing.  MODE 2 covers the rest (the frame), every boundary included.
 template <typename T, int NW, int MODE>
 __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__ rp, long step, M3Geom g)
 {
@@ -286,7 +289,13 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     // ---- this workgroup's segment, row group and plane chunk
     int seg, ygr, zch;
     m3_block(g, MODE, blockIdx.x, seg, ygr, zch);
-    const int x0 = seg * g.wid, gx = x0 - 2 + lane;
+    // an interior segment (mode 0) starts at column xi0 + (seg - sx0) wi, a
+    // frame segment at seg * wid; an x-face wavefront (mode 1) holds columns
+    // -2 .. 29 in lanes 0 .. 31 and xc1 - 2 .. xc1 + 29 in lanes 32 .. 63 (own
+    // columns 0 .. xa - 1 in lanes 2 .., xc1 .. nn0 - 1 in lanes 34 .. 61)
+    const int x0 = MODE == 0 ? g.xi0 + (seg - g.sx0) * g.wi : seg * g.wid;
+    const int wseg = MODE == 0 ? g.wi : g.wid;
+    const int gx = XB ? (lane < 32 ? lane - 2 : g.xc1 - 34 + lane) : x0 - 2 + lane;
     const int y0 = ygr * TY, gy = y0 - 1 + w;
     const int z0 = m3_zb(g, zch), z1 = m3_zb(g, zch + 1);
 
@@ -297,13 +306,17 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     const int xs_ph = MODE == 0 ? gx : (apx ? m3::imodn(gx, n0) : (xcl == 0 ? gx : 0));
     const unsigned xo_em = (unsigned)xs_em * es, xo_ph = (unsigned)xs_ph * es;
     // own columns: nodal x components store there, centred ones where also gx < n0
-    const bool own_x = lane >= 2 && lane < 2 + g.wid && gx < nn0;
+    auto own_lane = [&](int l) __attribute__((always_inline)) {
+        if constexpr (XB) return l < 32 ? (l >= 2 && l < 2 + g.xa) : (l >= 34 && g.xc1 - 34 + l < nn0);
+        return l >= 2 && l < 2 + wseg && x0 - 2 + l < nn0;
+    };
+    const bool own_x = own_lane(lane);
     const bool own_xc = own_x && (!mx || gx < n0);
-    auto own_lane = [&](int l) __attribute__((always_inline)) { return l >= 2 && l < 2 + g.wid && x0 - 2 + l < nn0; };
     // the segment holds a ghost column of an x face (Mur or axion)
     const bool seg_xb = XB || (GEN && (mx || !apx) && (x0 - 2 <= -1 || x0 + 61 >= n0));
-    // the x face of a mode-1 segment (0: x_min, 1: x_max) and the column of its ghost
-    const int xside = seg < g.sx0 ? 0 : 1;
+    // the x face of this lane's half of a mode-1 wavefront (0: x_min, 1:
+    // x_max) and the column of its ghost
+    const int xside = (XB && lane >= 32) ? 1 : 0;
     const int gx_ghost = xside ? n0 : -1;
     // B_ext at this lane's cells (slab along x); formed at use from the slab
     // mask in the interior launch, so that it takes no vector registers
@@ -399,7 +412,12 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
             r.a = m3::fld(rp, q_axg(1, ycl - 1, L), (long)zs * nn0 + xs_ph);
         } else {
             r.a = m3::ldo<T>(arr_ph(L), xo_ph + (unsigned)ys * sxb + (unsigned)zs * syb);
-            if constexpr (XB) r.fx = m3::sld<T>(rp->face_base + q_axg(0, xside, L) * rp->face_stride, (long)zs * nn1 + ys);
+            if constexpr (XB) {
+                const long fi = (long)zs * nn1 + ys;
+                const T f0 = m3::sld<T>(rp->face_base + q_axg(0, 0, L) * rp->face_stride, fi);
+                const T f1 = m3::sld<T>(rp->face_base + q_axg(0, 1, L) * rp->face_stride, fi);
+                r.fx = xside ? f1 : f0;
+            }
             else if (seg_xb && !apx) r.fx = m3::fld(rp, q_axg(0, xcl == 2 ? 1 : 0, L), (long)zs * nn1 + ys);
         }
         return r;
@@ -536,18 +554,22 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
         T *const p = owner ? (T *)face(q) + f : (T *)(abase(0) + sink_o);
         *(__attribute__((address_space(1))) T *)p = v;
     };
-    // mode 1: the Mur ghost of order O, component c on this segment's x face
-    // at face point f (uniform), from the adjacent point's E^{n-1/2}, E^{n+1/2};
-    // the old ghost and the laser values come through the scalar cache, the
-    // laser's from a valid address also where they are not used
+    // mode 1: the Mur ghost of order O, component c on the x face of this
+    // lane's half at face point f (uniform), from the adjacent point's
+    // E^{n-1/2}, E^{n+1/2}; the old ghosts of both faces and the laser values
+    // come through the scalar cache, the laser's from a valid address also
+    // where they are not used, and the x_max half takes no laser
     auto mur_x = [&](int O, int c, T e_old, T e_new, long f) __attribute__((always_inline)) -> T {
-        const double g_old = (double)m3::sld<T>(face(q_mur(O, 0, xside, c, so)), f);
+        const double g_lo = (double)m3::sld<T>(face(q_mur(O, 0, 0, c, so)), f);
+        const double g_hi = (double)m3::sld<T>(face(q_mur(O, 0, 1, c, so)), f);
+        const double g_old = xside ? g_hi : g_lo;
         double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
         if (O == 0) {
-            const bool use = xside == 0 && rp->las.on && c == rp->las.pol;
-            const char *tb = use ? (const char *)rp->inc : rp->face_base;
-            const long lo = use ? inc_lv0 + f : 0, ln = use ? inc_lv1 + f : 0;
-            const long fo = use ? rp->inc_face : 0;
+            const bool tab = rp->las.on && c == rp->las.pol;
+            const bool use = tab && xside == 0;
+            const char *tb = tab ? (const char *)rp->inc : rp->face_base;
+            const long lo = tab ? inc_lv0 + f : 0, ln = tab ? inc_lv1 + f : 0;
+            const long fo = tab ? rp->inc_face : 0;
             const double a0 = m3::sld<double>(tb, lo), a1 = m3::sld<double>(tb, lo + fo);
             const double a2 = m3::sld<double>(tb, ln), a3 = m3::sld<double>(tb, ln + fo);
             ia_o = use ? a0 : 0.0;
@@ -1092,9 +1114,11 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 T pn = ((xq + sdt * pa) + T(2) * pb) - pa;
                 if (sdt != T(0)) pn = pn / (T(1) + sdt);
                 if constexpr (XB) {
-                    // the axion ghost beyond the boundary cell of this segment's x face
+                    // the axion ghost beyond the boundary cell of the x face of this lane's half
                     const long f = (long)gz * nn1 + ys_em;
-                    const T gbv = m3::sld<T>(face(q_axg(0, xside, lb)), f), gav = m3::sld<T>(face(q_axg(0, xside, la)), f);
+                    const T gb0 = m3::sld<T>(face(q_axg(0, 0, lb)), f), ga0 = m3::sld<T>(face(q_axg(0, 0, la)), f);
+                    const T gb1 = m3::sld<T>(face(q_axg(0, 1, lb)), f), ga1 = m3::sld<T>(face(q_axg(0, 1, la)), f);
+                    const T gbv = xside ? gb1 : gb0, gav = xside ? ga1 : ga0;
                     const T rr = rp->out_r[0];
                     T xx = (((T(-2) * gbv + T(2) * gav) - dt2 * (sax - m2 * gbv)) + rr * pb - rr * rr * (pb - T(2) * gbv))
                            / (rr + rr * rr);
@@ -1158,7 +1182,11 @@ template <typename T> struct March3 { static constexpr int NW = sizeof(T) == 4 ?
 // planes.  A row group is interior when its rows y0 - 2 .. y0 + NW - 1 (the
 // extra rows included) are inside [0, n1); a chunk is interior when its loads
 // (planes z0 - 3 .. z1 + 1) are inside [0, n2) and it holds neither ghost
-// plane nor boundary cell of a z face.
+// plane nor boundary cell of a z face.  With an x-face launch the columns
+// split differently in the interior row groups and chunks: 28 own columns at
+// x_min and 1 .. 28 at x_max go to one x-face wavefront per row, and the
+// columns between them to the fewest interior segments of equal width whose
+// 64 loaded columns stay inside [0, n0).
 template <typename T>
 static M3Geom march3d_geom(const RunK<T>& h, int zc)
 {
@@ -1178,10 +1206,33 @@ static M3Geom march3d_geom(const RunK<T>& h, int zc)
     // launch everywhere
     const bool pml = h.axbc[0] == AXF_AX_PML || h.axbc[1] == AXF_AX_PML || h.axbc[2] == AXF_AX_PML;
     if (pml || g.gy1 <= g.gy0 || g.sx1 <= g.sx0) g.gy0 = g.gy1 = g.sx0 = g.sx1 = 0;
+    g.xi0 = g.sx0 * g.wid;
+    g.wi = g.wid;
+    g.xa = g.xc1 = 0;
     // the x-face launch: Mur x faces with an outflow or reflecting axion
-    g.xb = g.sx1 > g.sx0 && h.mur[0] && (h.axbc[0] == AXF_AX_OUTFLOW || h.axbc[0] == AXF_AX_REFLECT) ? 1 : 0;
+    g.xb = 0;
     const char *xe = getenv("AXF_M3_XB");
-    if (xe && atoi(xe) == 0) g.xb = 0;
+    if (g.sx1 > g.sx0 && h.mur[0] && (h.axbc[0] == AXF_AX_OUTFLOW || h.axbc[0] == AXF_AX_REFLECT) && !(xe && atoi(xe) == 0)) {
+        // ns interior segments of w columns between the two halves: x_max
+        // keeps nb = rem - ns w in [1, 28] columns (lanes 34 .. 61, so that
+        // its own lanes stay two lanes clear of lane 63, as in a segment),
+        // and the last segment's loads (to column 28 + (ns - 1) w + 61) stay
+        // below n0
+        const int xa = 28, rem = h.nn[0] - xa;
+        for (int ns = 1; ns * 33 <= rem && !g.xb; ns++) {
+            for (int w = 60; w >= 33; w--) {
+                const int nb = rem - ns * w;
+                if (nb < 1 || nb > 28 || xa + (ns - 1) * w + 61 > h.n[0] - 1) continue;
+                g.xb = 1;
+                g.sx0 = 0;
+                g.sx1 = ns;
+                g.xi0 = g.xa = xa;
+                g.wi = w;
+                g.xc1 = xa + ns * w;
+                break;
+            }
+        }
+    }
     const int zcv = zc > 0 ? zc : 64;
     // interior block order: a band per XCD, segments fastest (measured on
     // 512^3 FP32: 39% fewer HBM reads than the plain order, 6.5 against 6.8 ms)
@@ -1217,9 +1268,13 @@ bool march3d_available(const RunK<T>& h)
 template <typename T>
 static void march3d_counts(const M3Geom& g, long *interior, long *xface, long *frame)
 {
-    *interior = (long)(g.sx1 - g.sx0) * (g.gy1 - g.gy0) * (g.nzc - 2);
-    *xface = g.xb ? (long)(g.nseg - (g.sx1 - g.sx0)) * (g.gy1 - g.gy0) * (g.nzc - 2) : 0;
-    *frame = (long)g.nseg * g.nyg * g.nzc - *interior - *xface;
+    const long nsx = g.sx1 - g.sx0, ny = g.gy1 - g.gy0, nzi = g.nzc - 2;
+    *interior = nsx * ny * nzi;
+    *xface = g.xb ? ny * nzi : 0;
+    // (A) the first and last chunks, (B) the inner chunks of the row groups
+    // outside [gy0, gy1), (C) the x-face columns when they have no launch
+    *frame = (long)(g.nzc > 1 ? 2 : 1) * g.nseg * g.nyg + (long)g.nseg * (g.nyg - ny) * nzi +
+             (g.xb ? 0 : (long)(g.nseg - nsx) * ny * nzi);
 }
 
 template <typename T>

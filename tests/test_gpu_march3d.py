@@ -81,6 +81,27 @@ def test_march_equals_plain_mur_outflow(axf, prec, chunk, monkeypatch):
     assert_same(plain, march)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_march_equals_plain_reflect_x_faces(axf, prec, monkeypatch):
+    """Mur x faces with a reflecting axion on the ragged grid: the x-face
+    launch (both x faces in one wavefront per row, lanes 0-31 and 32-63) takes
+    the reflecting ghost, two interior segments lie between the halves."""
+    cfg = box_3d(RAGGED, W.AX_REFLECT)
+    plain, march, _ = pair(axf, cfg, prec, 45, 16, monkeypatch)
+    assert_same(plain, march)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_march_equals_plain_wide_x(axf, prec, monkeypatch):
+    """257 nodal columns: 28 at x_min and 9 at x_max in the x-face wavefronts,
+    four interior segments of 55 between them; the axion packet starts 8
+    cells from the x_max face, so that it reaches that face's ghosts."""
+    cfg = box_3d((256, 26, 22))
+    cfg.update(pk_x0=(256 - 8) * cfg["dx"][0])
+    plain, march, _ = pair(axf, cfg, prec, 40, 8, monkeypatch)
+    assert_same(plain, march)
+
+
 @pytest.mark.parametrize("ax_bc", [W.AX_PML, W.AX_REFLECT, W.AX_PERIODIC])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_march_equals_plain_axion_boundaries(axf, ax_bc, prec, monkeypatch):
