@@ -66,6 +66,7 @@ struct Run {
     hipEvent_t ev_ring = nullptr;
     long inc_lo = -1;               // first time level held by the laser table
     bool m3_off = false;            // 3D: the tile-walk launches instead of the one-pass march
+    bool m3_on = false;             // 3D FP64: the one-pass march instead of the tile walks
     int m3_chunk = 0;               // 3D march: planes per workgroup (0: default)
     long win_shifted = 0;           // columns the moving window has moved so far
 

@@ -689,7 +689,10 @@ int run_init(Run *R, const axf_config *cfg, void *dev_buf, size_t bytes, hipStre
     if (const char *ch = getenv("AXF_FUSED_CHUNK")) R->chunk = atoi(ch);
     if (const char *pd = getenv("AXF_WAVE_PD")) R->pd = atoi(pd);
     if (const char *lm = getenv("AXF_LDS_MARCH")) R->lds_march = lm[0] == '1';
-    if (const char *m3 = getenv("AXF_M3")) R->m3_off = m3[0] == '0';
+    if (const char *m3 = getenv("AXF_M3")) {
+        R->m3_off = m3[0] == '0';
+        R->m3_on = m3[0] == '1';
+    }
     if (const char *mc = getenv("AXF_M3_CHUNK")) R->m3_chunk = atoi(mc);
     if (const char *pe = getenv("AXF_WAVE_PASS")) R->multi = pe[0] != '0';
     if (const char *pc = getenv("AXF_PASS_CHUNK")) R->pass_ci = atoi(pc);
@@ -742,10 +745,14 @@ int run_wave_chunk(const Run *R) { return R->chunk > 0 ? R->chunk : 8; }
 
 // the one-pass 3D march: the three components of a kind addressed with 32-bit
 // offsets from one base, a plane index wrapped at most once on a periodic z
-// axis, at least one own row per y group
+// axis, at least one own row per y group.  FP64 runs take the tile walks
+// unless AXF_M3=1: with six row wavefronts per workgroup and spilled
+// registers the FP64 march is the slower one (512^3: 21.0 ms per step
+// against 17.2 ms for the tile walks and 18.3 ms for the unfused phases).
 bool run_march3d(const Run *R)
 {
     if (!R->use_fused || R->cfg.ndim != 3 || R->lds_march || R->m3_off) return false;
+    if (R->cfg.precision == AXF_F64 && !R->m3_on) return false;
     if ((uint64_t)R->L.arr_stride * 3 > (1ull << 32)) return false;
     for (int d = 0; d < 3; d++)
         if (R->cfg.n[d] < 8) return false;

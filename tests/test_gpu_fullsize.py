@@ -1,6 +1,7 @@
 """GPU parity at the workloads' full sizes, in the launch configuration the
 benchmark times (AUTO path: the fused wavefront kernel in 2D, the one-pass
-march in 3D, the unfused phases in 1D), and the FP32 accuracy budget on the
+march in 3D FP32 and the tile walks in 3D FP64, the unfused phases in 1D),
+and the FP32 accuracy budget on the
 conversion probabilities.
 
 - Full-size 2D: the oracle advances the whole 4096^2 grid for a few steps;
@@ -185,13 +186,17 @@ def oracle_128():
     return cfg, mid, h_mid, ora
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_128_crossing_march_matches_oracle(axf, oracle_128, prec):
+@pytest.mark.parametrize("prec,m3", [("f64", "1"), ("f64", None), ("f32", None)])
+def test_128_crossing_march_matches_oracle(axf, oracle_128, prec, m3, monkeypatch):
+    """FP32 and FP64 through the march (AXF_M3=1 for FP64) and FP64 through
+    its default 3D path, the tile walks."""
+    if m3 is not None:
+        monkeypatch.setenv("AXF_M3", m3)
     cfg, mid, h_mid, ora = oracle_128
     cfg = {k: v for k, v in cfg.items() if k != "mid"}
     run = axf.Run(cfg, precision=axf.F64 if prec == "f64" else axf.F32)
     assert run.uses_fused()
-    print("128^3 crossing", prec, cfg["steps"], "steps", flush=True)
+    print("128^3 crossing", prec, "AXF_M3", m3, cfg["steps"], "steps", flush=True)
     tol_f = 1e-10 if prec == "f64" else 1e-4
     tol_p = 1e-10 if prec == "f64" else P_TOL_FP32
     # mid-crossing: every field on its order's scale, both probabilities
@@ -221,7 +226,8 @@ def test_128_crossing_march_matches_oracle(axf, oracle_128, prec):
 
 
 def test_fp32_probabilities_512_full_run(axf):
-    """The 512^3 run's 2000 steps in FP32 and FP64 through the march, records
+    """The 512^3 run's 2000 steps in FP32 (the march) and FP64 (its default
+    3D path, the tile walks), records
     every 100 steps.  Each probability is compared over the records where its
     denominator is at least 1% of its peak over the run: P_conv = H_g1 / H_phi
     while the packet is in the box, P_gen = H_phi / H_g0 while the laser is.

@@ -32,6 +32,12 @@ def axf():
     return A
 
 
+@pytest.fixture(autouse=True)
+def march_in_both_precisions(monkeypatch):
+    """FP64 runs take the tile walks by default; this file tests the march."""
+    monkeypatch.setenv("AXF_M3", "1")
+
+
 def box_3d(n, ax_bc=W.AX_OUTFLOW):
     """A focused pulse from x_min and a counter-propagating axion packet in a
     uniform B_ext along z, with all couplings strong enough to move every
