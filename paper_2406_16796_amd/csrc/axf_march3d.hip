@@ -143,6 +143,25 @@ struct M3Lds {
     static constexpr size_t BYTES = (size_t)ELEMS * sizeof(T);
 };
 
+// x-face launch: the face values its rows and planes read, staged in LDS
+// behind the quantities' slots when a block starts.  Per plane p in
+// [z0 - 6, z1 + 2] and row y in [y0 - 2, y0 + NW - 2] one record of NT values
+// of T (the axion ghosts of levels la and lb, the Mur ghosts of E0y, E0z,
+// E1y, E1z, each for x_min then x_max) and, in a second array, four doubles
+// (the laser table's values at that face point for t_n and t_n+1).  FP32 only:
+// beside the FP64 slots the records of a chunk do not fit.
+template <typename T, int NW>
+struct M3Face {
+    static constexpr int NT = 12, ROWS = NW + 1, LAG_LO = 6, LAG_HI = 2;
+    static constexpr size_t PLANE = (size_t)ROWS * (NT * sizeof(T) + 4 * sizeof(double));
+    static constexpr size_t LDS_MAX = 160 * 1024;
+    static constexpr int NP_MAX = M3Lds<T, NW>::BYTES < LDS_MAX ? (int)((LDS_MAX - M3Lds<T, NW>::BYTES) / PLANE) : 0;
+    static constexpr bool ON = sizeof(T) == 4;
+    // planes staged by a block of chunk [z0, z1)
+    __host__ __device__ static constexpr int planes(int z0, int z1) { return z1 - z0 + LAG_LO + LAG_HI + 1; }
+    static constexpr size_t bytes(int np) { return M3Lds<T, NW>::BYTES + (size_t)np * PLANE; }
+};
+
 extern __shared__ __align__(16) unsigned char m3_smem[];
 
 // first plane of chunk k: chunk 0 is [0, zf), chunks 1 .. nzc - 2 split
@@ -380,6 +399,41 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
     const long inc_lv0 = (step % rp->inc_k1) * 2 * rp->inc_face;
     const long inc_lv1 = ((step + 1) % rp->inc_k1) * 2 * rp->inc_face;
 
+    // ---- mode 1: the face values of this block's planes and rows into LDS
+    // (planes outside the grid, read only by warm-up iterations whose values
+    // no owned point takes, are clamped to it; the rows are inside it)
+    using FQ = M3Face<T, NW>;
+    const int fz0 = z0 - FQ::LAG_LO, fnp = FQ::planes(z0, z1);
+    T *const fst_t = reinterpret_cast<T *>(m3_smem + LQ::BYTES);
+    double *const fst_d = reinterpret_cast<double *>(m3_smem + LQ::BYTES + (size_t)fnp * FQ::ROWS * FQ::NT * sizeof(T));
+    if constexpr (XB) {
+        const bool las = rp->las.on;
+        for (int k = (int)threadIdx.x; k < fnp * FQ::ROWS; k += 64 * NW) {
+            const int pl = k / FQ::ROWS, r = k - pl * FQ::ROWS;
+            int p = fz0 + pl;
+            p = p < 0 ? 0 : (p > nn2 - 1 ? nn2 - 1 : p);
+            const long f = (long)p * nn1 + (y0 - 2 + r);
+            T *const d = fst_t + k * FQ::NT;
+#pragma unroll
+            for (int sd = 0; sd < 2; sd++) {
+                d[0 + sd] = m3::fld(rp, q_axg(0, sd, la), f);
+                d[2 + sd] = m3::fld(rp, q_axg(0, sd, lb), f);
+                d[4 + sd] = m3::fld(rp, q_mur(0, 0, sd, 1, so), f);
+                d[6 + sd] = m3::fld(rp, q_mur(0, 0, sd, 2, so), f);
+                d[8 + sd] = m3::fld(rp, q_mur(1, 0, sd, 1, so), f);
+                d[10 + sd] = m3::fld(rp, q_mur(1, 0, sd, 2, so), f);
+            }
+            double *const e = fst_d + k * 4;
+            e[0] = las ? rp->inc[inc_lv0 + f] : 0.0;
+            e[1] = las ? rp->inc[inc_lv0 + rp->inc_face + f] : 0.0;
+            e[2] = las ? rp->inc[inc_lv1 + f] : 0.0;
+            e[3] = las ? rp->inc[inc_lv1 + rp->inc_face + f] : 0.0;
+        }
+        __syncthreads();
+    }
+    // record of plane p, row y - (y0 - 2)
+    auto frec = [&](int p, int r) __attribute__((always_inline)) { return (p - fz0) * FQ::ROWS + r; };
+
     // ---- LDS: row w + d of quantity q at slot s (a compile-time value in
     // each unrolled iteration)
     const int lrow = w * 64 + lane;
@@ -412,12 +466,7 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
             r.a = m3::fld(rp, q_axg(1, ycl - 1, L), (long)zs * nn0 + xs_ph);
         } else {
             r.a = m3::ldo<T>(arr_ph(L), xo_ph + (unsigned)ys * sxb + (unsigned)zs * syb);
-            if constexpr (XB) {
-                const long fi = (long)zs * nn1 + ys;
-                const T f0 = m3::sld<T>(rp->face_base + q_axg(0, 0, L) * rp->face_stride, fi);
-                const T f1 = m3::sld<T>(rp->face_base + q_axg(0, 1, L) * rp->face_stride, fi);
-                r.fx = xside ? f1 : f0;
-            }
+            if constexpr (XB) r.fx = fst_t[frec(zs, ys - (y0 - 2)) * FQ::NT + (L == lb ? 2 : 0) + xside];
             else if (seg_xb && !apx) r.fx = m3::fld(rp, q_axg(0, xcl == 2 ? 1 : 0, L), (long)zs * nn1 + ys);
         }
         return r;
@@ -555,23 +604,18 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
         *(__attribute__((address_space(1))) T *)p = v;
     };
     // mode 1: the Mur ghost of order O, component c on the x face of this
-    // lane's half at face point f (uniform), from the adjacent point's
-    // E^{n-1/2}, E^{n+1/2}; the old ghosts of both faces and the laser values
-    // come through the scalar cache, the laser's from a valid address also
-    // where they are not used, and the x_max half takes no laser
-    auto mur_x = [&](int O, int c, T e_old, T e_new, long f) __attribute__((always_inline)) -> T {
-        const double g_lo = (double)m3::sld<T>(face(q_mur(O, 0, 0, c, so)), f);
-        const double g_hi = (double)m3::sld<T>(face(q_mur(O, 0, 1, c, so)), f);
-        const double g_old = xside ? g_hi : g_lo;
+    // lane's half in this wavefront's row of plane p, from the adjacent
+    // point's E^{n-1/2}, E^{n+1/2}; the old ghost and the laser values come
+    // from the block's staged face records, and the x_max half takes no laser
+    auto mur_x = [&](int O, int c, T e_old, T e_new, int p) __attribute__((always_inline)) -> T {
+        const int k = frec(p, w + 1);
+        const double g_old = (double)fst_t[k * FQ::NT + 4 + 4 * O + 2 * (c - 1) + xside];
         double ia_o = 0.0, ia_n = 0.0, ig_o = 0.0, ig_n = 0.0;
         if (O == 0) {
             const bool tab = rp->las.on && c == rp->las.pol;
             const bool use = tab && xside == 0;
-            const char *tb = tab ? (const char *)rp->inc : rp->face_base;
-            const long lo = tab ? inc_lv0 + f : 0, ln = tab ? inc_lv1 + f : 0;
-            const long fo = tab ? rp->inc_face : 0;
-            const double a0 = m3::sld<double>(tb, lo), a1 = m3::sld<double>(tb, lo + fo);
-            const double a2 = m3::sld<double>(tb, ln), a3 = m3::sld<double>(tb, ln + fo);
+            const double a0 = fst_d[k * 4 + 0], a1 = fst_d[k * 4 + 1];
+            const double a2 = fst_d[k * 4 + 2], a3 = fst_d[k * 4 + 3];
             ia_o = use ? a0 : 0.0;
             ig_o = use ? a1 : 0.0;
             ia_n = use ? a2 : 0.0;
@@ -677,8 +721,8 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 const T oup_y = m3::lane_up(e0o[1]), odn_y = m3::lane_dn(e0o[1]);
                 const T oup_z = m3::lane_up(e0o[2]), odn_z = m3::lane_dn(e0o[2]);
                 const long f = (long)zs_em(p1) * nn1 + ys_em;
-                const T vy = mur_x(0, 1, xside ? odn_y : oup_y, xside ? dn_y : up_y, f);
-                const T vz = mur_x(0, 2, xside ? odn_z : oup_z, xside ? dn_z : up_z, f);
+                const T vy = mur_x(0, 1, xside ? odn_y : oup_y, xside ? dn_y : up_y, p1);
+                const T vz = mur_x(0, 2, xside ? odn_z : oup_z, xside ? dn_z : up_z, p1);
                 const bool isg = gx == gx_ghost;
                 const bool owner = isg && own_lane(xside ? lane - 1 : lane + 1) && own_y && own_p(p1);
                 eh[1] = isg ? vy : eh[1];
@@ -931,8 +975,8 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 const T oup_y = m3::lane_up(e1o[1]), odn_y = m3::lane_dn(e1o[1]);
                 const T oup_z = m3::lane_up(e1o[2]), odn_z = m3::lane_dn(e1o[2]);
                 const long f = (long)zs_em(p3) * nn1 + ys_em;
-                const T vy = mur_x(1, 1, xside ? odn_y : oup_y, xside ? dn_y : up_y, f);
-                const T vz = mur_x(1, 2, xside ? odn_z : oup_z, xside ? dn_z : up_z, f);
+                const T vy = mur_x(1, 1, xside ? odn_y : oup_y, xside ? dn_y : up_y, p3);
+                const T vz = mur_x(1, 2, xside ? odn_z : oup_z, xside ? dn_z : up_z, p3);
                 const bool isg = gx == gx_ghost;
                 const bool owner = isg && own_lane(xside ? lane - 1 : lane + 1) && own_y && own_p(p3);
                 eh[1] = isg ? vy : eh[1];
@@ -1116,9 +1160,8 @@ __global__ void __launch_bounds__(64 * NW) k_march3d(const RunK<T> *__restrict__
                 if constexpr (XB) {
                     // the axion ghost beyond the boundary cell of the x face of this lane's half
                     const long f = (long)gz * nn1 + ys_em;
-                    const T gb0 = m3::sld<T>(face(q_axg(0, 0, lb)), f), ga0 = m3::sld<T>(face(q_axg(0, 0, la)), f);
-                    const T gb1 = m3::sld<T>(face(q_axg(0, 1, lb)), f), ga1 = m3::sld<T>(face(q_axg(0, 1, la)), f);
-                    const T gbv = xside ? gb1 : gb0, gav = xside ? ga1 : ga0;
+                    const int fk = frec(gz, w + 1) * FQ::NT;
+                    const T gbv = fst_t[fk + 2 + xside], gav = fst_t[fk + 0 + xside];
                     const T rr = rp->out_r[0];
                     T xx = (((T(-2) * gbv + T(2) * gav) - dt2 * (sax - m2 * gbv)) + rr * pb - rr * rr * (pb - T(2) * gbv))
                            / (rr + rr * rr);
@@ -1191,6 +1234,7 @@ template <typename T>
 static M3Geom march3d_geom(const RunK<T>& h, int zc)
 {
     constexpr int NW = March3<T>::NW, TY = NW - 2;
+    using FQ = M3Face<T, NW>;
     M3Geom g;
     g.nseg = (h.nn[0] + 59) / 60;
     g.wid = (h.nn[0] + g.nseg - 1) / g.nseg;
@@ -1209,10 +1253,30 @@ static M3Geom march3d_geom(const RunK<T>& h, int zc)
     g.xi0 = g.sx0 * g.wid;
     g.wi = g.wid;
     g.xa = g.xc1 = 0;
-    // the x-face launch: Mur x faces with an outflow or reflecting axion
     g.xb = 0;
+    const int zcv = zc > 0 ? zc : 64;
+    // interior block order: a band per XCD, segments fastest (measured on
+    // 512^3 FP32: 39% fewer HBM reads than the plain order, 6.5 against 6.8 ms)
+    const char *oe = getenv("AXF_M3_ORDER");
+    g.order = oe ? atoi(oe) : 2;
+    g.nn2 = h.nn[2];
+    g.zf = 3;
+    g.zend = h.n[2] - 2;
+    if (g.zend - g.zf < 1) {            // no interior chunk: one chunk and an empty one
+        g.zf = g.zend = h.nn[2];
+        g.nzc = 2;
+        g.zi = 1;
+        g.gy0 = g.gy1 = g.sx0 = g.sx1 = 0;
+        return g;
+    }
+    const int nzi = (g.zend - g.zf + zcv - 1) / zcv;
+    g.zi = (g.zend - g.zf + nzi - 1) / nzi;
+    g.nzc = nzi + 2;
+    // the x-face launch: Mur x faces with an outflow or reflecting axion, in
+    // FP32 with chunks whose face records fit in LDS beside the slots
     const char *xe = getenv("AXF_M3_XB");
-    if (g.sx1 > g.sx0 && h.mur[0] && (h.axbc[0] == AXF_AX_OUTFLOW || h.axbc[0] == AXF_AX_REFLECT) && !(xe && atoi(xe) == 0)) {
+    if (g.sx1 > g.sx0 && h.mur[0] && (h.axbc[0] == AXF_AX_OUTFLOW || h.axbc[0] == AXF_AX_REFLECT) &&
+        FQ::ON && FQ::planes(0, g.zi) <= FQ::NP_MAX && !(xe && atoi(xe) == 0)) {
         // ns interior segments of w columns between the two halves: x_max
         // keeps nb = rem - ns w in [1, 28] columns (lanes 34 .. 61, so that
         // its own lanes stay two lanes clear of lane 63, as in a segment),
@@ -1233,25 +1297,6 @@ static M3Geom march3d_geom(const RunK<T>& h, int zc)
             }
         }
     }
-    const int zcv = zc > 0 ? zc : 64;
-    // interior block order: a band per XCD, segments fastest (measured on
-    // 512^3 FP32: 39% fewer HBM reads than the plain order, 6.5 against 6.8 ms)
-    const char *oe = getenv("AXF_M3_ORDER");
-    g.order = oe ? atoi(oe) : 2;
-    g.nn2 = h.nn[2];
-    g.zf = 3;
-    g.zend = h.n[2] - 2;
-    if (g.zend - g.zf < 1) {            // no interior chunk: one chunk and an empty one
-        g.zf = g.zend = h.nn[2];
-        g.nzc = 2;
-        g.zi = 1;
-        g.gy0 = g.gy1 = g.sx0 = g.sx1 = 0;
-        g.xb = 0;
-        return g;
-    }
-    const int nzi = (g.zend - g.zf + zcv - 1) / zcv;
-    g.zi = (g.zend - g.zf + nzi - 1) / nzi;
-    g.nzc = nzi + 2;
     return g;
 }
 
@@ -1289,10 +1334,12 @@ template <typename T, int MODE>
 static hipError_t march3d_attr()
 {
     constexpr int NW = March3<T>::NW;
+    using FQ = M3Face<T, NW>;
     static bool done = false;
     if (!done) {
+        const size_t bytes = MODE == 1 ? FQ::bytes(FQ::NP_MAX) : M3Lds<T, NW>::BYTES;
         hipError_t e = hipFuncSetAttribute((const void *)k_march3d<T, NW, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)M3Lds<T, NW>::BYTES);
+                                           (int)bytes);
         if (e != hipSuccess) return e;
         done = true;
     }
@@ -1309,8 +1356,11 @@ hipError_t launch_march3d(const RunK<T> *rk, const RunK<T>& h, long step, int zc
 {
     constexpr int NW = March3<T>::NW;
     using LQ = M3Lds<T, NW>;
+    using FQ = M3Face<T, NW>;
     hipError_t e = march3d_attr<T, 0>();
-    if (e == hipSuccess) e = march3d_attr<T, 1>();
+    if constexpr (FQ::ON) {
+        if (e == hipSuccess) e = march3d_attr<T, 1>();
+    }
     if (e == hipSuccess) e = march3d_attr<T, 2>();
     if (e != hipSuccess) return e;
     const M3Geom g = march3d_geom(h, zc);
@@ -1324,7 +1374,12 @@ hipError_t launch_march3d(const RunK<T> *rk, const RunK<T>& h, long step, int zc
         se = ws->side;
     }
     if (ni > 0) hipLaunchKernelGGL((k_march3d<T, NW, 0>), dim3((unsigned)ni), dim3(64 * NW), LQ::BYTES, st, rk, step, g);
-    if (nx > 0) hipLaunchKernelGGL((k_march3d<T, NW, 1>), dim3((unsigned)nx), dim3(64 * NW), LQ::BYTES, se, rk, step, g);
+    if constexpr (FQ::ON) {
+        // every chunk of the x-face launch stages at most planes(0, zi) planes
+        if (nx > 0)
+            hipLaunchKernelGGL((k_march3d<T, NW, 1>), dim3((unsigned)nx), dim3(64 * NW), FQ::bytes(FQ::planes(0, g.zi)), se,
+                               rk, step, g);
+    }
     if (nf > 0) hipLaunchKernelGGL((k_march3d<T, NW, 2>), dim3((unsigned)nf), dim3(64 * NW), LQ::BYTES, se, rk, step, g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (fork) {

@@ -6,7 +6,8 @@ each row one wavefront for both x faces: lanes 0-31 hold columns -2 .. 29
 (28 own at x_min, lanes 2-29, two halo lanes above), lanes 32-63 hold columns
 xc1 - 2 .. xc1 + 29 (two halo lanes below, then the last nb columns up to the
 nodal top column n0).  The rule below is the one the library applies when it
-lays out a run: the fewest interior segments of equal width w <= 60 between
+lays out an FP32 run whose plane chunks' face records fit in LDS (FP64 runs
+and longer chunks leave the face columns to the frame launch): the fewest interior segments of equal width w <= 60 between
 the halves, nb in [1, 28] (so that an x_max own lane stays two lanes clear of
 lane 63, as in a segment), and the last segment's loads below n0, tried
 where the frame's split into segments has an interior one.  The model
