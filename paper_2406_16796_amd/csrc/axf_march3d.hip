@@ -270,9 +270,9 @@ __host__ __device__ inline void m3_block(const M3Geom& g, int mode, unsigned b, 
 // wavefront holding both faces (lanes 0 .. 31 x_min, 32 .. 63 x_max, each
 // half with two halo lanes on its inner side): the code of mode 0 plus the
 // faces, whose ghosts every lane computes from its half's face values and
-// stores (lanes other than a ghost's to the sink), the uniform face values
-// of both faces read through the scalar cache, so that it too issues the
-// same vector memory instructions in every iteration.  A lane shift across
+// stores (lanes other than a ghost's to the sink), the face values of both
+// faces staged in LDS when the block starts (M3Face), so that it too issues
+// the same vector memory instructions in every iteration.  A lane shift across
 // lanes 31 / 32 reaches only halo lanes, as lane 0's and lane 63's reach
 // nothing.  MODE 2 covers the rest (the frame), every boundary included.
 template <typename T, int NW, int MODE>

@@ -10,9 +10,12 @@ Tolerances (derived from the arithmetic, stated per test):
   1e-11 relative.  The GPU stores the leapfrog form and multiplies by
   precomputed reciprocals, so the two differ by rounding only (a few ulp per
   step, growing linearly).
-- FP32 storage: the per-field error is reported and bounded by 2e-4 of the
-  field's maximum; the conversion probabilities by 1e-3 relative on these
-  short runs (the long-run FP32 budget is checked by the probability tests).
+- FP32 storage: the per-field error is reported and bounded by 1e-4 of the
+  order's maximum (a few FP32 roundings of 6e-8 per step over these runs'
+  110-700 steps; measured at most 1.4e-5); the energies H_phi and H_gamma1
+  by 2e-4 relative (twice the fields' relative error, squared sums
+  accumulated in FP64) on these short runs (the long-run FP32 budget is
+  checked by the probability tests).
 """
 import math
 
@@ -234,14 +237,16 @@ def test_3d_tiled_periodic_equals_plain_bitwise(axf, prec, monkeypatch):
 def test_fp32_tracks_oracle(axf, kind):
     cfg = {"1d": small_1d(W.AX_OUTFLOW), "2d": small_2d(W.AX_PML), "3d": small_3d()}[kind]
     run, ora = run_both(axf, cfg, axf.F32, cfg["steps"])
-    check_fields(run, ora, 2e-4, "fp32 " + kind)
+    check_fields(run, ora, 1e-4, "fp32 " + kind)
     rec = run.diag_now()
     h = ora.energies()
-    assert abs(rec["h_phi"] / h[0] - 1) < 1e-3
-    assert abs(rec["h_em1"] / h[2] - 1) < 1e-3
+    print("fp32", kind, "H_phi rel %.2e H_em1 rel %.2e" % (abs(rec["h_phi"] / h[0] - 1), abs(rec["h_em1"] / h[2] - 1)),
+          flush=True)
+    assert abs(rec["h_phi"] / h[0] - 1) < 2e-4
+    assert abs(rec["h_em1"] / h[2] - 1) < 2e-4
     xc = ora.laser_centroid()
     assert xc > 0
-    # FP32 fields within 2e-4 of their scale move the weighted mean by a
+    # FP32 fields within 1e-4 of their scale move the weighted mean by a
     # small fraction of a cell
     assert abs(rec["x_laser"] - xc) <= 1e-2 * cfg["dx"][0], (rec["x_laser"], xc)
 
