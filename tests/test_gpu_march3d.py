@@ -143,11 +143,13 @@ def test_march_equals_plain_periodic_random_state(axf, prec, monkeypatch):
     assert_same(*runs)
 
 
-def test_march_equals_plain_mixed_axes(axf, monkeypatch):
-    """Mur EM and an outflow axion along x only, periodic y and z."""
-    cfg = box_3d((75, 26, 22))
+@pytest.mark.parametrize("n,prec", [((75, 26, 22), "f64"), ((130, 26, 22), "f32")])
+def test_march_equals_plain_mixed_axes(axf, n, prec, monkeypatch):
+    """Mur EM and an outflow axion along x only, periodic y and z (the 130
+    cell FP32 grid takes the x-face launch, the narrow FP64 one the frame)."""
+    cfg = box_3d(n)
     cfg.update(em_bc=[W.EM_MUR, W.EM_PERIODIC, W.EM_PERIODIC], ax_bc=[W.AX_OUTFLOW, W.AX_PERIODIC, W.AX_PERIODIC])
-    plain, march, _ = pair(axf, cfg, "f64", 40, 9, monkeypatch)
+    plain, march, _ = pair(axf, cfg, prec, 40, 9, monkeypatch)
     assert_same(plain, march)
 
 
