@@ -51,10 +51,10 @@ def test_window_matches_oracle(axf, prec):
     run.close()
 
 
-def window_3d():
+def window_3d(nx=96):
     cfg = W.focused_3d(n=96, steps=0, m=0.3, g=0.03, a0=0.5, waist_lam=0.8, fwhm_lam=1.0, pk_amp=0.0,
                        pk_w_lam=0.5)
-    n = [96, 30, 26]
+    n = [nx, 30, 26]
     dx = cfg["dx"][0]
     tau0 = cfg["fwhm"] / math.sqrt(2.0 * math.log(2.0))
     cfg.update(n=n, y_c=0.5 * n[1] * dx, z_c=0.5 * n[2] * dx, x_focus=20 * dx, t_center=3.0 * tau0, packet_on=0,
@@ -62,10 +62,12 @@ def window_3d():
     return cfg
 
 
-@pytest.mark.parametrize("kind", ["2d", "3d"])
+@pytest.mark.parametrize("kind", ["2d", "3d", "3d_wide"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_window_fused_equals_plain_bitwise(axf, kind, prec):
-    cfg = pulse_2d(240) if kind == "2d" else window_3d()
+    """3d_wide: 131 nodal columns, wide enough for the march's x-face launch
+    in FP32 (face values staged per block) while the window moves."""
+    cfg = pulse_2d(240) if kind == "2d" else (window_3d() if kind == "3d" else window_3d(130))
     steps = 400 if kind == "2d" else 200
     p = axf.F64 if prec == "f64" else axf.F32
     runs = []
