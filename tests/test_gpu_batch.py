@@ -82,6 +82,29 @@ def test_batch_equals_alone_bitwise(axf, prec):
     batch.close()
 
 
+def test_large_3d_run_in_a_batch_equals_alone(axf):
+    """A 200^3 FP32 run, alone in its group (the batched unfused phases),
+    beside a 1D run: both equal the runs stepped alone (the 3D one through
+    the one-pass march), diagnostic records included, through two calls
+    that start on different steps."""
+    big = W.focused_3d(n=200, m=0.3, g=0.03, a0=0.5, waist_lam=0.8, fwhm_lam=1.5, pk_amp=0.2, pk_w_lam=0.5)
+    dx = big["dx"][0]
+    big.update(pk_x0=0.5 * 200 * dx, t_center=3.0)
+    one = mixed_runs()[1]
+    cfgs = [big, one]
+    counts = [[23, 40], [14, 9]]
+    batch = axf.Batch(cfgs, precision=axf.F32, diag_every=7)
+    print("batch 200^3 + 1d", flush=True)
+    for c in counts:
+        batch.step(c)
+    for i, cfg in enumerate(cfgs):
+        ref = alone(axf, cfg, axf.F32, [c[i] for c in counts], diag_every=7)
+        assert batch.runs[i].steps_done == ref.steps_done
+        assert_same(batch.runs[i], ref, "run %d" % i)
+        ref.close()
+    batch.close()
+
+
 def wide_runs():
     """2D runs wide enough for four-step passes (the first two) and one that
     only has an interior for two-step passes."""
