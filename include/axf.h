@@ -55,6 +55,11 @@ enum { AXF_F32 = 0, AXF_F64 = 1 };                       /* field storage precis
 enum { AXF_EM_PERIODIC = 0, AXF_EM_MUR = 1 };
 enum { AXF_AX_PERIODIC = 0, AXF_AX_REFLECT = 1, AXF_AX_OUTFLOW = 2, AXF_AX_PML = 3 };
 enum { AXF_ENV_CW = 0, AXF_ENV_GAUSS = 1 };
+/* step kernels: PLAIN the unfused phases (one launch per phase of Sec. II.C);
+   FUSED the fused step of the dimensionality (1D: multi-step LDS passes; 2D:
+   the wavefront march, up to four steps per pass; 3D FP32: the one-pass z
+   march; 3D FP64: the merged tile walks); AUTO takes FUSED wherever the run
+   supports it.  Every path gives the same bits. */
 enum { AXF_PATH_AUTO = 0, AXF_PATH_PLAIN = 1, AXF_PATH_FUSED = 2 };
 
 /* field ids for axf_read_field / axf_write_field */
