@@ -777,6 +777,8 @@ def main():
     same_shape = tuned is None or (tuned["steps_per_pass"], tuned["chunk"], tuned["prefetch"],
                                    tuned["frame_chunk"]) == default_shape
     traffic = read_traffic(args.workload, tag, kernel) if fused and same_shape else None
+    # 3D FP64 runs step through the merged tile walks, not the march
+    tiles = args.workload == "3d" and args.precision == "f64"
     # the unfused phase sequence for comparison
     p_wall, _, p_launches, _, _ = time_path(axf, torch, cfg, prec, axf.PATH_PLAIN, args.plain_steps, 2, 0)
     plain_value = nc * args.plain_steps / p_wall / 1e9
@@ -803,8 +805,10 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": round(traffic) if traffic is not None else None,
-            "kernel": " + ".join(pattern_label(p) for p in pats) if fused else "plain phase sequence",
+            "kernel": ("merged tile-walk launches (k3_tile<3,double,...>, k_mur<3,double>)" if tiles else
+                       " + ".join(pattern_label(p) for p in pats)) if fused else "plain phase sequence",
             "unit_of_work": "one step of the whole grid (%s)" % (
+                "the tile-walk launches" if tiles else
                 "interior, x-face and frame launches" if args.workload == "3d" else "fused launches"),
             "bytes_per_step": algo_bytes, "launches_per_step": round(k_launches / args.steps, 3),
             "mean_step_ms": round(per_step_s * 1e3, 5), "steps_timed": args.steps,
